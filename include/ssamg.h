@@ -1,0 +1,221 @@
+/*
+ * ssamg.h - C ABI of a semi-structured algebraic multigrid (SSAMG) solver for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Magri, Falgout and Yang, "A New Semi-Structured
+ * Algebraic Multigrid Method" (arXiv 2205.14273):
+ *   - the problem is A x = b with A = S + U on a semi-structured grid
+ *     (Section 2): n_p parts, each a box of cells with its own index space,
+ *     a per-part stencil S with per-cell coefficients, and a sparse matrix U
+ *     holding the couplings between parts;
+ *   - setup (Section 3): grid-spacing metric W and Algorithm 1 (semicoarsening
+ *     direction per level and part), two-point operator-collapse interpolation
+ *     (Section 3.2, eq:prolEx), Galerkin coarse operators
+ *     A_c = P^T S P + P^T U P (Section 3.3, eq:galerkin);
+ *   - solve: PCG preconditioned by one V(1,1) cycle of weighted Jacobi with the
+ *     per-part weights of eq:relax1 / eq:alpha-beta (Sections 3.4 and 4).
+ *
+ * Conventions shared by every call:
+ *   - every function returns ssamg_status; nothing throws across the ABI; the
+ *     text of the last error of the calling thread is ssamg_last_error();
+ *   - cells are numbered part-major and, inside a part, lexicographically with
+ *     x fastest: id = offset[p] + i + nx*(j + ny*k); every box has lower corner
+ *     (0,0,0) in its part's own index space (other lower corners are
+ *     SSAMG_ERR_UNSUPPORTED: only the parity of the index matters to the
+ *     method, and a shifted box is the same problem);
+ *   - pointers tagged "device" are HIP device pointers on the current device;
+ *     "host" pointers are ordinary memory; the library copies what it keeps
+ *     and never frees caller memory;
+ *   - all device work is ordered on the HIP stream given at creation (NULL =
+ *     the null stream); calls that return results to the host synchronize it;
+ *   - total cells of a problem must stay below 2^31.
+ */
+#ifndef SSAMG_H
+#define SSAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSAMG_OK = 0,
+  SSAMG_NOT_CONVERGED = 1,     /* max_iter reached; x and info are filled */
+  SSAMG_ERR_ARG = -1,          /* bad argument (index, size, NULL, layout) */
+  SSAMG_ERR_STATE = -2,        /* call out of order (e.g. solve before setup) */
+  SSAMG_ERR_UNSUPPORTED = -3,  /* valid request outside this implementation */
+  SSAMG_ERR_NUMERIC = -4,      /* nonpositive diagonal or collapse denominator,
+                                  NaN/Inf, PCG breakdown (p^T A p <= 0) */
+  SSAMG_ERR_DEVICE = -5,       /* a HIP runtime call failed */
+  SSAMG_ERR_ALLOC = -6         /* device or host allocation failed */
+} ssamg_status;
+
+enum { SSAMG_FACE_PHYSICAL = 0, SSAMG_FACE_PART = 1 };
+enum { SSAMG_MEM_HOST = 0, SSAMG_MEM_DEVICE = 1 };
+enum { SSAMG_RELAX_JACOBI = 0, SSAMG_RELAX_L1_JACOBI = 1 };
+enum { SSAMG_COARSE_SWEEP = 0, SSAMG_COARSE_DIRECT = 1 };
+enum { SSAMG_FP64 = 0, SSAMG_FP32 = 1 };
+
+typedef struct ssamg_problem_s *ssamg_problem;
+typedef struct ssamg_solver_s *ssamg_solver;
+
+/* ---------------------------------------------------------------- problem */
+
+/* Create an empty problem of n_p = nparts parts in ndim (2 or 3) dimensions.
+ * In 2D every box has nz = 1 and stencil offsets have dz = 0 (Section 2). */
+ssamg_status ssamg_problem_create(int ndim, int nparts, ssamg_problem *out);
+ssamg_status ssamg_problem_destroy(ssamg_problem prob);
+
+/* Box of part `part`: cells lo[d] .. hi[d] inclusive, lo must be {0,0,0}.
+ * One box per part (Section 2 allows several; bounding boxes of Algorithm 1
+ * then coincide with the box). */
+ssamg_status ssamg_problem_set_box(ssamg_problem prob, int part, const int lo[3],
+                                   const int hi[3]);
+
+/* Placement of part `part` in a shared global index space.  Used only by
+ * ssamg_problem_fv_assemble (neighbour lookup across parts) and to derive
+ * face kinds; not needed for problems given through set_coeffs/set_coupling. */
+ssamg_status ssamg_problem_set_origin(ssamg_problem prob, int part, const int origin[3]);
+
+/* Kind of face `face` (0..5 = -x,+x,-y,+y,-z,+z) of part `part`:
+ * SSAMG_FACE_PART marks a part boundary that is not a physical boundary, where
+ * the interpolation rule of Section 3.2 (crossing weight 0, opposite weight 1)
+ * applies.  Default SSAMG_FACE_PHYSICAL. */
+ssamg_status ssamg_problem_set_face(ssamg_problem prob, int part, int face, int kind);
+
+/* Stencil of part `part` (Section 2): nent offsets off[nent][3] in
+ * {-1,0,1}^3 (the 27-point neighbourhood, Section 3.1), distinct, including
+ * (0,0,0).  Offsets outside the neighbourhood are SSAMG_ERR_UNSUPPORTED. */
+ssamg_status ssamg_problem_set_stencil(ssamg_problem prob, int part, int nent,
+                                       const int *off);
+
+/* Coefficients of part `part` for its stencil: vals[nent][nz][ny][nx] (x
+ * fastest), or vals[nent] when constant = 1 (one value per stencil entry for
+ * the whole part, Section 2).  `where` = SSAMG_MEM_HOST or SSAMG_MEM_DEVICE.
+ * Copied.  Entries whose neighbour lies outside the box are discarded
+ * (Dirichlet elimination).  Requires set_box and set_stencil first. */
+ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double *vals,
+                                      int where, int constant);
+
+/* Inter-part couplings U (Section 2): nnz entries (row[k], col[k], val[k]) with
+ * global cell ids; host arrays; copied; duplicates are summed, explicit zeros
+ * kept as structure.  An entry inside one part is SSAMG_ERR_ARG (assumption of
+ * the theorem of Section 3.3).  May be called once; nnz = 0 means none. */
+ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const int64_t *row,
+                                        const int64_t *col, const double *val);
+
+/* Finite-volume diffusion operator from per-cell conductivity (the synthetic
+ * workloads): kappa (device, N doubles, copied), aniso (host, [nparts][3]
+ * directional factors), stencil 7 or 27 (5 or 9 in 2D).  For neighbour offset
+ * s the conductance is t = g_s * H(a_{p(i),s} kappa_i, a_{p(j),s} kappa_j),
+ * H(x,y) = 2xy/(x+y), g_s = 1, 1/2, 1/4 for faces, edges, corners, a_{p,s} the
+ * mean of the part's factors over the nonzero components of s; neighbours
+ * outside every part are zero-Dirichlet ghosts with kappa_j = kappa_i.
+ * A_ii = sum of t, A_ij = -t; same-part entries go to S, the rest to U.  Needs
+ * boxes and origins of every part; sets the stencils, the face kinds and U. */
+ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa,
+                                       const double *aniso, int stencil, void *hip_stream);
+
+/* Gradient of L(x(kappa)) for the operator of the last fv_assemble:
+ * grad[c] = -lambda^T (dA/dkappa_c) x, where lambda solves A lambda = dL/dx.
+ * lambda, x, grad: device, N doubles each. */
+ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, const double *lambda, const double *x,
+                                   double *grad, void *hip_stream);
+
+/* Number of cells N of the problem. */
+ssamg_status ssamg_problem_num_cells(ssamg_problem prob, int64_t *n);
+
+/* ---------------------------------------------------------------- solver */
+
+typedef struct {
+  int max_levels;            /* l_max of Section 3.1 (default 64) */
+  int64_t min_coarse_size;   /* s_max of Section 3.1: stop at the first level with
+                                fewer cells (default 0: coarsen to one cell/part) */
+  int relax;                 /* SSAMG_RELAX_JACOBI (default) */
+  double omega;              /* > 0: fixed weight; <= 0: per-part omega_p (default) */
+  int coarse;                /* SSAMG_COARSE_SWEEP (default, Section 3.5) */
+  int cycle_precision;       /* SSAMG_FP64 (default) or SSAMG_FP32: V-cycle in FP32
+                                inside FP64 PCG, coarsest level in FP64 */
+  double tol;                /* ||r||_2 < tol ||b||_2 (default 1e-8) */
+  int max_iter;              /* default 100 */
+  int max_nrhs;              /* right-hand sides per solve, power of two <= 32 (default 1) */
+  int use_graph;             /* capture the V-cycle in a HIP graph (default 1) */
+} ssamg_params;
+
+typedef struct {
+  int nrhs;
+  int iters[32];             /* per right-hand side */
+  double relres[32];         /* ||r_k||/||b|| of the recursive residual at exit */
+  double true_relres[32];    /* ||b - A x||/||b|| recomputed at exit */
+  int converged[32];
+  double t_solve;            /* seconds, host wall clock around the solve */
+} ssamg_info;
+
+typedef struct {
+  int dims[3];               /* box extents at this level */
+  int64_t offset;            /* first cell of the part in the level vector */
+  int dstar;                 /* semicoarsening direction 0,1,2; -1: not coarsened */
+  double omega;              /* relaxation weight of the part at this level */
+  int nent;                  /* stencil entries */
+  int pattern[27][3];        /* stencil offsets (level 0: as given; coarser: sorted
+                                by (dz, dy, dx)) */
+  int fdims[3];              /* F-box (cells odd along dstar) extents */
+} ssamg_level_desc;
+
+ssamg_status ssamg_params_default(ssamg_params *params);
+
+/* Create a solver for `prob` (which must outlive it) on `hip_stream`. */
+ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
+                                 void *hip_stream, ssamg_solver *out);
+ssamg_status ssamg_solver_destroy(ssamg_solver s);
+
+/* Symbolic setup: the metric reduction (device, one small copy back), W,
+ * Algorithm 1, omega_p, symbolic coarse stencils and Galerkin tables, and the
+ * structure of every coarse coupling matrix U_c (host, integer work). */
+ssamg_status ssamg_setup_symbolic(ssamg_solver s);
+
+/* Device bytes the numeric setup needs (hierarchy + work vectors). */
+ssamg_status ssamg_workspace_bytes(ssamg_solver s, size_t *bytes);
+
+/* Numeric setup (device kernels only): interpolation weights, structured and
+ * unstructured Galerkin products per level, FP32 copies when cycle_precision =
+ * SSAMG_FP32.  ws: caller-owned device buffer of at least workspace_bytes
+ * (kept until the solver is destroyed), or NULL to let the library allocate. */
+ssamg_status ssamg_setup_numeric(ssamg_solver s, void *ws, size_t bytes);
+
+/* Solve A X = B for nrhs right-hand sides (1 <= nrhs <= max_nrhs, power of two).
+ * b, x: device, [N][nrhs] doubles (right-hand side index fastest; for nrhs = 1
+ * a plain vector).  x0 = 0.  Returns SSAMG_NOT_CONVERGED when some right-hand
+ * side did not meet tol within max_iter.  info may be NULL. */
+ssamg_status ssamg_solve(ssamg_solver s, int nrhs, const double *b, double *x, ssamg_info *info);
+
+/* y = A_l x at level `level` in FP64 (device vectors of that level's size). */
+ssamg_status ssamg_apply_A(ssamg_solver s, int level, const double *x, double *y);
+
+/* z = B r: one V(1,1) cycle in the configured precision (device, N doubles). */
+ssamg_status ssamg_apply_precond(ssamg_solver s, const double *r, double *z);
+
+ssamg_status ssamg_num_levels(ssamg_solver s, int *nlevels);
+ssamg_status ssamg_level_info(ssamg_solver s, int level, int part, ssamg_level_desc *info);
+
+/* c[p][d] of Section 3.1 as reduced on the device (host out, nparts*3). */
+ssamg_status ssamg_direction_sums(ssamg_solver s, double *c_out);
+
+/* Copies to host memory, for inspection and tests (after numeric setup). */
+ssamg_status ssamg_copy_stencil(ssamg_solver s, int level, int part, double *vals /*[nent][ncell]*/);
+ssamg_status ssamg_copy_interp(ssamg_solver s, int level, int part, double *wm, double *wp /*F-box*/);
+ssamg_status ssamg_coupling_nnz(ssamg_solver s, int level, int64_t *nnz);
+/* CSR over all cells of the level: rowptr[N_l+1], col[nnz], val[nnz] (columns
+ * ascending in each row; structure is symbolic, numeric zeros kept). */
+ssamg_status ssamg_copy_coupling(ssamg_solver s, int level, int64_t *rowptr, int64_t *col,
+                                 double *val);
+
+const char *ssamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSAMG_H */

@@ -1,0 +1,128 @@
+"""ctypes declarations of the SSAMG C ABI (include/ssamg.h).
+
+Loads ``libssamg.so`` from this package directory and fails loudly when it is
+missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssamg.so")
+
+OK = 0
+NOT_CONVERGED = 1
+ERR_ARG = -1
+ERR_STATE = -2
+ERR_UNSUPPORTED = -3
+ERR_NUMERIC = -4
+ERR_DEVICE = -5
+ERR_ALLOC = -6
+
+FACE_PHYSICAL = 0
+FACE_PART = 1
+MEM_HOST = 0
+MEM_DEVICE = 1
+RELAX_JACOBI = 0
+RELAX_L1_JACOBI = 1
+COARSE_SWEEP = 0
+COARSE_DIRECT = 1
+FP64 = 0
+FP32 = 1
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_STATE",
+                -3: "ERR_UNSUPPORTED", -4: "ERR_NUMERIC", -5: "ERR_DEVICE", -6: "ERR_ALLOC"}
+
+
+class ssamg_params(C.Structure):
+    _fields_ = [("max_levels", C.c_int), ("min_coarse_size", C.c_int64), ("relax", C.c_int),
+                ("omega", C.c_double), ("coarse", C.c_int), ("cycle_precision", C.c_int),
+                ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
+                ("use_graph", C.c_int)]
+
+
+class ssamg_info(C.Structure):
+    _fields_ = [("nrhs", C.c_int), ("iters", C.c_int * 32), ("relres", C.c_double * 32),
+                ("true_relres", C.c_double * 32), ("converged", C.c_int * 32),
+                ("t_solve", C.c_double)]
+
+
+class ssamg_level_desc(C.Structure):
+    _fields_ = [("dims", C.c_int * 3), ("offset", C.c_int64), ("dstar", C.c_int),
+                ("omega", C.c_double), ("nent", C.c_int), ("pattern", (C.c_int * 3) * 27),
+                ("fdims", C.c_int * 3)]
+
+
+P = C.c_void_p
+I = C.c_int
+I64 = C.c_int64
+D = C.c_double
+PI = C.POINTER(C.c_int)
+PI64 = C.POINTER(C.c_int64)
+PD = C.POINTER(C.c_double)
+PP = C.POINTER(C.c_void_p)
+
+# name: argtypes  (every function returns ssamg_status, except ssamg_last_error)
+SIGNATURES = {
+    "ssamg_problem_create": [I, I, PP],
+    "ssamg_problem_destroy": [P],
+    "ssamg_problem_set_box": [P, I, PI, PI],
+    "ssamg_problem_set_origin": [P, I, PI],
+    "ssamg_problem_set_face": [P, I, I, I],
+    "ssamg_problem_set_stencil": [P, I, I, PI],
+    "ssamg_problem_set_coeffs": [P, I, P, I, I],
+    "ssamg_problem_set_coupling": [P, I64, PI64, PI64, PD],
+    "ssamg_problem_fv_assemble": [P, P, PD, I, P],
+    "ssamg_problem_fv_grad": [P, P, P, P, P],
+    "ssamg_problem_num_cells": [P, PI64],
+    "ssamg_params_default": [C.POINTER(ssamg_params)],
+    "ssamg_solver_create": [P, C.POINTER(ssamg_params), P, PP],
+    "ssamg_solver_destroy": [P],
+    "ssamg_setup_symbolic": [P],
+    "ssamg_workspace_bytes": [P, C.POINTER(C.c_size_t)],
+    "ssamg_setup_numeric": [P, P, C.c_size_t],
+    "ssamg_solve": [P, I, P, P, C.POINTER(ssamg_info)],
+    "ssamg_apply_A": [P, I, P, P],
+    "ssamg_apply_precond": [P, P, P],
+    "ssamg_num_levels": [P, PI],
+    "ssamg_level_info": [P, I, I, C.POINTER(ssamg_level_desc)],
+    "ssamg_direction_sums": [P, PD],
+    "ssamg_copy_stencil": [P, I, I, PD],
+    "ssamg_copy_interp": [P, I, I, PD, PD],
+    "ssamg_coupling_nnz": [P, I, PI64],
+    "ssamg_copy_coupling": [P, I, PI64, PI64, PD],
+    "ssamg_last_error": [],
+}
+
+
+class SSAMGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"SSAMG HIP library not built: {LIB_PATH} is missing "
+                              "(run __graft_entry__.build() or python -m paper_2205_14273_amd._build)")
+        h = C.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(h, name)
+            f.argtypes = args
+            f.restype = C.c_char_p if name == "ssamg_last_error" else C.c_int
+        _lib = h
+    return _lib
+
+
+def check(status, allow_not_converged=False):
+    if status == OK or (allow_not_converged and status == NOT_CONVERGED):
+        return status
+    msg = lib().ssamg_last_error().decode()
+    raise SSAMGError(status, msg)

@@ -1,0 +1,262 @@
+// C ABI of the solver object (include/ssamg.h).
+#include <cmath>
+#include <cstring>
+
+#include "capi_common.h"
+#include "ssamg_impl.h"
+
+using namespace ssamg;
+
+namespace ssamg {
+extern thread_local std::string g_last_error;
+}
+
+namespace {
+
+Solver *S(ssamg_solver h) {
+  if (!h) throw Error(SSAMG_ERR_ARG, "NULL solver");
+  return reinterpret_cast<Solver *>(h);
+}
+
+void need(const Solver *s, int state, const char *what) {
+  if (s->state < state) throw Error(SSAMG_ERR_STATE, what);
+}
+
+void check_level(const Solver *s, int level) {
+  if (level < 0 || level >= (int)s->lv.size()) throw Error(SSAMG_ERR_ARG, "level out of range");
+}
+
+void check_part(const Solver *s, int level, int part) {
+  check_level(s, level);
+  if (part < 0 || part >= (int)s->lv[level].parts.size()) throw Error(SSAMG_ERR_ARG, "part out of range");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ssamg_last_error(void) { return ssamg::g_last_error.c_str(); }
+
+ssamg_status ssamg_params_default(ssamg_params *p) {
+  API_BEGIN
+  if (!p) throw Error(SSAMG_ERR_ARG, "NULL params");
+  std::memset(p, 0, sizeof(*p));
+  p->max_levels = 64;
+  p->min_coarse_size = 0;
+  p->relax = SSAMG_RELAX_JACOBI;
+  p->omega = 0.0;
+  p->coarse = SSAMG_COARSE_SWEEP;
+  p->cycle_precision = SSAMG_FP64;
+  p->tol = 1e-8;
+  p->max_iter = 100;
+  p->max_nrhs = 1;
+  p->use_graph = 1;
+  API_END
+}
+
+ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params, void *hip_stream,
+                                 ssamg_solver *out) {
+  API_BEGIN
+  if (!prob || !out) throw Error(SSAMG_ERR_ARG, "NULL problem or output");
+  ssamg_params p;
+  if (params)
+    p = *params;
+  else
+    ssamg_params_default(&p);
+  if (p.max_levels < 1) throw Error(SSAMG_ERR_ARG, "max_levels must be >= 1");
+  if (p.min_coarse_size < 0) throw Error(SSAMG_ERR_ARG, "min_coarse_size must be >= 0");
+  if (p.relax != SSAMG_RELAX_JACOBI) throw Error(SSAMG_ERR_UNSUPPORTED, "only weighted Jacobi relaxation");
+  if (p.coarse != SSAMG_COARSE_SWEEP) throw Error(SSAMG_ERR_UNSUPPORTED, "only the one-sweep coarsest level");
+  if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
+    throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
+  if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw Error(SSAMG_ERR_ARG, "tol must be positive");
+  if (p.max_iter < 1) throw Error(SSAMG_ERR_ARG, "max_iter must be >= 1");
+  if (p.max_nrhs < 1 || p.max_nrhs > kMaxRhs || (p.max_nrhs & (p.max_nrhs - 1)))
+    throw Error(SSAMG_ERR_ARG, "max_nrhs must be a power of two <= 32");
+  if (!std::isfinite(p.omega) || p.omega >= 2.0) throw Error(SSAMG_ERR_ARG, "omega must be < 2");
+  auto *s = new Solver();
+  s->prob = reinterpret_cast<Problem *>(prob);
+  s->prm = p;
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&s->stream) != hipSuccess) {
+      delete s;
+      throw Error(SSAMG_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    s->own_stream = true;
+  }
+  void *pin = nullptr;
+  if (hipHostMalloc(&pin, kScalSlots * kMaxRhs * sizeof(double)) != hipSuccess) {
+    delete s;
+    throw Error(SSAMG_ERR_ALLOC, "hipHostMalloc failed");
+  }
+  s->h_pin = (double *)pin;
+  *out = reinterpret_cast<ssamg_solver>(s);
+  API_END
+}
+
+ssamg_status ssamg_solver_destroy(ssamg_solver s) {
+  API_BEGIN
+  delete reinterpret_cast<Solver *>(s);
+  API_END
+}
+
+ssamg_status ssamg_setup_symbolic(ssamg_solver h) {
+  API_BEGIN
+  setup_symbolic(*S(h));
+  API_END
+}
+
+ssamg_status ssamg_workspace_bytes(ssamg_solver h, size_t *bytes) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  if (!bytes) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *bytes = s->ws_bytes;
+  API_END
+}
+
+ssamg_status ssamg_setup_numeric(ssamg_solver h, void *ws, size_t bytes) {
+  API_BEGIN
+  setup_numeric(*S(h), ws, bytes);
+  API_END
+}
+
+ssamg_status ssamg_solve(ssamg_solver h, int nrhs, const double *b, double *x, ssamg_info *info) {
+  Solver *s = nullptr;
+  try {
+    s = S(h);
+    need(s, 2, "setup_numeric must come first");
+    if (!b || !x) throw Error(SSAMG_ERR_ARG, "NULL vector");
+    if (nrhs < 1 || nrhs > s->prm.max_nrhs || (nrhs & (nrhs - 1)))
+      throw Error(SSAMG_ERR_ARG, "nrhs must be a power of two <= max_nrhs");
+    const ssamg_status st = pcg_solve(*s, nrhs, b, x, info);
+    set_last_error(st == SSAMG_OK ? "" : "not converged within max_iter");
+    return st;
+  } catch (const Error &e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception &e) {
+    set_last_error(e.what());
+    return SSAMG_ERR_ARG;
+  }
+}
+
+ssamg_status ssamg_apply_A(ssamg_solver h, int level, const double *x, double *y) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 2, "setup_numeric must come first");
+  check_level(s, level);
+  if (!x || !y) throw Error(SSAMG_ERR_ARG, "NULL vector");
+  apply_level(*s, level, x, y);
+  API_END
+}
+
+ssamg_status ssamg_apply_precond(ssamg_solver h, const double *r, double *z) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 2, "setup_numeric must come first");
+  if (!r || !z) throw Error(SSAMG_ERR_ARG, "NULL vector");
+  apply_precond(*s, r, z);
+  API_END
+}
+
+ssamg_status ssamg_num_levels(ssamg_solver h, int *nlevels) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  if (!nlevels) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *nlevels = (int)s->lv.size();
+  API_END
+}
+
+ssamg_status ssamg_level_info(ssamg_solver h, int level, int part, ssamg_level_desc *info) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  check_part(s, level, part);
+  if (!info) throw Error(SSAMG_ERR_ARG, "NULL output");
+  const PartLevel &q = s->lv[level].parts[part];
+  std::memset(info, 0, sizeof(*info));
+  for (int d = 0; d < 3; ++d) {
+    info->dims[d] = q.n[d];
+    info->fdims[d] = q.fn[d];
+  }
+  info->offset = q.off;
+  info->dstar = q.dstar;
+  info->omega = q.omega;
+  info->nent = (int)q.pat.size();
+  for (size_t e = 0; e < q.pat.size(); ++e)
+    for (int d = 0; d < 3; ++d) info->pattern[e][d] = q.pat[e][d];
+  API_END
+}
+
+ssamg_status ssamg_direction_sums(ssamg_solver h, double *c_out) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  if (!c_out) throw Error(SSAMG_ERR_ARG, "NULL output");
+  std::memcpy(c_out, s->cd.data(), s->cd.size() * sizeof(double));
+  API_END
+}
+
+ssamg_status ssamg_copy_stencil(ssamg_solver h, int level, int part, double *vals) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 2, "setup_numeric must come first");
+  check_part(s, level, part);
+  if (!vals) throw Error(SSAMG_ERR_ARG, "NULL output");
+  const PartLevel &q = s->lv[level].parts[part];
+  SSAMG_HIP(hipStreamSynchronize(s->stream));
+  SSAMG_HIP(hipMemcpy(vals, q.coef64, q.pat.size() * q.ncell * sizeof(double), hipMemcpyDeviceToHost));
+  API_END
+}
+
+ssamg_status ssamg_copy_interp(ssamg_solver h, int level, int part, double *wm, double *wp) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 2, "setup_numeric must come first");
+  check_part(s, level, part);
+  if (!wm || !wp) throw Error(SSAMG_ERR_ARG, "NULL output");
+  const Level &V = s->lv[level];
+  const PartLevel &q = V.parts[part];
+  if (q.nf == 0) return SSAMG_OK;
+  SSAMG_HIP(hipStreamSynchronize(s->stream));
+  SSAMG_HIP(hipMemcpy(wm, V.d_w64 + q.wofs, q.nf * sizeof(double), hipMemcpyDeviceToHost));
+  SSAMG_HIP(hipMemcpy(wp, V.d_w64 + q.wofs + q.nf, q.nf * sizeof(double), hipMemcpyDeviceToHost));
+  API_END
+}
+
+ssamg_status ssamg_coupling_nnz(ssamg_solver h, int level, int64_t *nnz) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  check_level(s, level);
+  if (!nnz) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *nnz = (int64_t)s->lv[level].ucol.size();
+  API_END
+}
+
+ssamg_status ssamg_copy_coupling(ssamg_solver h, int level, int64_t *rowptr, int64_t *col, double *val) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 2, "setup_numeric must come first");
+  check_level(s, level);
+  if (!rowptr || !col || !val) throw Error(SSAMG_ERR_ARG, "NULL output");
+  const Level &V = s->lv[level];
+  const size_t nnz = V.ucol.size();
+  std::vector<double> hv(nnz);
+  SSAMG_HIP(hipStreamSynchronize(s->stream));
+  if (nnz) SSAMG_HIP(hipMemcpy(hv.data(), V.d_uval64, nnz * sizeof(double), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i <= V.N; ++i) rowptr[i] = 0;
+  for (size_t r = 0; r < V.urow.size(); ++r) rowptr[V.urow[r] + 1] = V.uptr[r + 1] - V.uptr[r];
+  for (int64_t i = 0; i < V.N; ++i) rowptr[i + 1] += rowptr[i];
+  for (size_t k = 0; k < nnz; ++k) {
+    col[k] = V.ucol[k];
+    val[k] = hv[k];
+  }
+  API_END
+}
+
+}  // extern "C"

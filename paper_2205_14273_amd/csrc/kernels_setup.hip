@@ -1,0 +1,269 @@
+// Setup kernels (gfx950): Dirichlet elimination, the grid-spacing metric
+// reduction (Section 3.1), operator-collapse interpolation weights (Section
+// 3.2, eq:prolEx), the structured Galerkin product P^T S P as a stencil triple
+// product (Section 3.3), the numeric part of P^T U P, and the relaxation
+// scale of the coupling rows.
+#include "ssamg_impl.h"
+
+namespace ssamg {
+
+namespace {
+
+__device__ __forceinline__ void cell_ijk(int c, int nx, int ny, int &i, int &j, int &k) {
+  i = c % nx;
+  int t = c / nx;
+  j = t % ny;
+  k = t / ny;
+}
+
+__device__ __forceinline__ int off_comp(int code, int d) { return ((code >> (2 * d)) & 3) - 1; }
+
+// Zero every coefficient whose neighbour lies outside the box; flag a
+// nonpositive or non-finite diagonal or a non-finite coefficient.
+__global__ __launch_bounds__(kBlock) void k_normalise(BoxStencil bs, int *__restrict__ flag) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= bs.ncell) return;
+  int i, j, k;
+  cell_ijk((int)c, bs.n[0], bs.n[1], i, j, k);
+  const int p[3] = {i, j, k};
+  int bad = 0;
+  for (int s = 0; s < bs.nent; ++s) {
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+      const int q = p[d] + off_comp(bs.code[s], d);
+      in = in && q >= 0 && q < bs.n[d];
+    }
+    double *a = bs.coef + (long long)s * bs.ncell + c;
+    if (!in) *a = 0.0;
+    const double v = *a;
+    if (!isfinite(v)) bad = 1;
+    if (s == bs.center && !(v > 0.0)) bad = 1;
+  }
+  if (bad) flag[0] = 1;
+}
+
+// c_d of Section 3.1 for each part: sum over cells of minus the off-diagonal
+// coefficients with a nonzero d component, sign-adjusted by the center.
+__global__ __launch_bounds__(kBlock) void k_wsum_partial(const PartDesc<double> *__restrict__ desc,
+                                                         double *__restrict__ partial) {
+  __shared__ double sh[3][kBlock];
+  const PartDesc<double> &d = desc[blockIdx.y];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < d.ncell;
+       c += (long long)gridDim.x * kBlock) {
+    const double ac = d.coef[(long long)d.center * d.ncell + c];
+    const double sg = ac < 0.0 ? 1.0 : -1.0;
+    for (int s = 0; s < d.nent; ++s) {
+      if (s == d.center) continue;
+      const double v = sg * d.coef[(long long)s * d.ncell + c];
+      for (int q = 0; q < 3; ++q)
+        if (off_comp(d.code[s], q) != 0) acc[q] += v;
+    }
+  }
+  for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = acc[q];
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3)
+    partial[((long long)blockIdx.y * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_wsum_final(const double *__restrict__ partial, int nblk,
+                                                       double *__restrict__ out) {
+  __shared__ double sh[3][kBlock];
+  const int p = blockIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock)
+    for (int q = 0; q < 3; ++q) acc[q] += partial[((long long)p * nblk + b) * 3 + q];
+  for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = acc[q];
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) out[p * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Two-point collapse along d* for every F cell (odd index along d*):
+//   den = sum of the coefficients with zero d* component,
+//   wm = -(sum of those at -1)/den, wp = -(sum of those at +1)/den;
+// a coarse neighbour outside the box is absent (weight 0); if it lies across a
+// part face the opposite weight becomes 1 (Section 3.2).
+__global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double> *__restrict__ desc,
+                                                           int *__restrict__ flag) {
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const long long fidx = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (d.dstar < 0 || fidx >= d.nf) return;
+  const int ds = d.dstar;
+  int g[3];
+  cell_ijk((int)fidx, d.fn[0], d.fn[1], g[0], g[1], g[2]);
+  int f[3] = {g[0], g[1], g[2]};
+  f[ds] = 2 * g[ds] + 1;
+  const long long c = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
+  double den = 0.0, sm = 0.0, sp = 0.0;
+  for (int s = 0; s < d.nent; ++s) {
+    const double v = d.coef[(long long)s * d.ncell + c];
+    const int o = off_comp(d.code[s], ds);
+    if (o == 0)
+      den += v;
+    else if (o < 0)
+      sm += v;
+    else
+      sp += v;
+  }
+  double wm = -sm / den, wp = -sp / den;
+  if (!(den > 0.0) || !isfinite(wm) || !isfinite(wp)) flag[0] = 1;
+  const bool hi_out = f[ds] + 1 > d.n[ds] - 1;   // lower corner 0: f-1 >= 0 always
+  if (hi_out) {
+    wp = 0.0;
+    if ((d.faces >> (2 * ds + 1)) & 1) wm = 1.0;
+  }
+  const_cast<double *>(d.wm)[fidx] = wm;
+  const_cast<double *>(d.wp)[fidx] = wp;
+}
+
+// Structured Galerkin product for one coarse cell I of a part coarsened along
+// d*: fine rows f = 2I + r (r = -1, 0, 1) carry the restriction weights
+// rho_{-1} = wp(2I-1), rho_0 = 1, rho_{+1} = wm(2I+1); each fine coefficient
+// a_s(f) reaches fine cell g = f + s, which is coarse (weight 1) when
+// q = r + s_d* is even and an F cell (weights wm(g), wp(g) toward its two
+// coarse neighbours) when q is odd.  The host table lists, for each coarse
+// entry, the (r, s, which-weight-of-g) triples that land on it.
+__global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restrict__ desc,
+                                                const RapDesc *__restrict__ rd) {
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const RapDesc &t = rd[blockIdx.y];
+  const long long cidx = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (cidx >= d.cncell) return;
+  if (d.dstar < 0) {
+    // identity transfer: same operator, entries permuted into the sorted pattern
+    for (int e = 0; e < t.nent; ++e)
+      t.out[(long long)e * d.cncell + cidx] = d.coef[(long long)t.code[e] * d.ncell + cidx];
+    return;
+  }
+  const int ds = d.dstar;
+  int ci[3];
+  cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
+  const int nd = d.n[ds];
+  const int fb = 2 * ci[ds];
+  double rho[3];
+  bool row_ok[3];
+  {
+    int g[3] = {ci[0], ci[1], ci[2]};
+    row_ok[0] = fb - 1 >= 0;
+    row_ok[1] = true;
+    row_ok[2] = fb + 1 <= nd - 1;
+    g[ds] = ci[ds] - 1;
+    rho[0] = row_ok[0] ? d.wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
+    rho[1] = 1.0;
+    g[ds] = ci[ds];
+    rho[2] = row_ok[2] ? d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
+  }
+  for (int e = 0; e < t.nent; ++e) {
+    double acc = 0.0;
+    for (int q = t.start[e]; q < t.start[e + 1]; ++q) {
+      const int w = t.code[q];
+      const int r = (w & 3) - 1;
+      const int s = (w >> 2) & 31;
+      const int gsel = (w >> 7) & 3;
+      if (!row_ok[r + 1]) continue;
+      int f[3] = {ci[0], ci[1], ci[2]};
+      f[ds] = fb + r;
+      int g[3];
+      bool in = true;
+      for (int a = 0; a < 3; ++a) {
+        g[a] = f[a] + off_comp(d.code[s], a);
+        in = in && g[a] >= 0 && g[a] < d.n[a];
+      }
+      if (!in) continue;
+      const long long fl = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
+      const double a = d.coef[(long long)s * d.ncell + fl];
+      double wg = 1.0;
+      if (gsel != 0) {
+        int h[3] = {g[0], g[1], g[2]};
+        h[ds] = (g[ds] - 1) >> 1;
+        const long long hl = h[0] + (long long)d.fn[0] * (h[1] + (long long)d.fn[1] * h[2]);
+        wg = gsel == 1 ? d.wm[hl] : d.wp[hl];
+      }
+      acc = fma(rho[r + 1] * a, wg, acc);
+    }
+    t.out[(long long)e * d.cncell + cidx] = acc;
+  }
+}
+
+// U_c = P^T U P on the host-built structure: each coarse entry sums, in a
+// fixed order, w(a) * U[k] * w(b) over its contributions (w(-1) = 1).
+__global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int *__restrict__ start,
+                                                       const int *__restrict__ kk,
+                                                       const int *__restrict__ ia,
+                                                       const int *__restrict__ ib,
+                                                       const double *__restrict__ uprev,
+                                                       const double *__restrict__ w,
+                                                       double *__restrict__ uval) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nnz) return;
+  double acc = 0.0;
+  for (int q = start[e]; q < start[e + 1]; ++q) {
+    const double wa = ia[q] < 0 ? 1.0 : w[ia[q]];
+    const double wb = ib[q] < 0 ? 1.0 : w[ib[q]];
+    acc = fma(wa * uprev[kk[q]], wb, acc);
+  }
+  uval[e] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_uscale(int nrow, const int *__restrict__ row,
+                                                   const int *__restrict__ row_part,
+                                                   const PartDesc<double> *__restrict__ desc,
+                                                   double *__restrict__ scale) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrow) return;
+  const PartDesc<double> &d = desc[row_part[r]];
+  const long long c = row[r] - d.off;
+  scale[r] = d.omega / d.coef[(long long)d.center * d.ncell + c];
+}
+
+inline unsigned nblk(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+}  // namespace
+
+void launch_normalise(const BoxStencil &bs, int *flag, hipStream_t st) {
+  if (bs.ncell > 0) k_normalise<<<nblk(bs.ncell), kBlock, 0, st>>>(bs, flag);
+}
+
+void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *partial, double *out,
+                 hipStream_t st) {
+  long long nb = (maxcell + kBlock - 1) / kBlock;
+  if (nb > 256) nb = 256;
+  if (nb < 1) nb = 1;
+  k_wsum_partial<<<dim3((unsigned)nb, nparts), kBlock, 0, st>>>(desc, partial);
+  k_wsum_final<<<nparts, kBlock, 0, st>>>(partial, (int)nb, out);
+}
+
+void launch_interp_weights(const PartDesc<double> *desc, int nparts, int maxf, int *flag,
+                           hipStream_t st) {
+  k_interp_weights<<<dim3(nblk(maxf), nparts), kBlock, 0, st>>>(desc, flag);
+}
+
+void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
+                hipStream_t st) {
+  k_rap<<<dim3(nblk(maxcoarse), nparts), kBlock, 0, st>>>(desc, rd);
+}
+
+void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
+                       const double *uprev, const double *w, double *uval, hipStream_t st) {
+  if (nnz > 0) k_uc_numeric<<<nblk(nnz), kBlock, 0, st>>>(nnz, start, k, a, b, uprev, w, uval);
+}
+
+void launch_uscale(int nrow, const int *row, const int *row_part, const PartDesc<double> *desc,
+                   double *scale, hipStream_t st) {
+  if (nrow > 0) k_uscale<<<nblk(nrow), kBlock, 0, st>>>(nrow, row, row_part, desc, scale);
+}
+
+}  // namespace ssamg

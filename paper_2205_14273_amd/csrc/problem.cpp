@@ -1,0 +1,491 @@
+// Problem description (Section 2: grid of boxes, per-part stencils, inter-part
+// couplings U, per-cell coefficients) and the C ABI calls that fill it.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "capi_common.h"
+#include "ssamg_impl.h"
+
+namespace ssamg {
+
+int64_t Problem::ncell_total() const {
+  int64_t n = 0;
+  for (auto &d : dims) n += (int64_t)d[0] * d[1] * d[2];
+  return n;
+}
+
+std::vector<int64_t> Problem::offsets() const {
+  std::vector<int64_t> off(nparts + 1, 0);
+  for (int p = 0; p < nparts; ++p) off[p + 1] = off[p] + (int64_t)dims[p][0] * dims[p][1] * dims[p][2];
+  return off;
+}
+
+void Problem::free_device() {
+  for (auto &c : coef) {
+    if (c) (void)hipFree(c);
+    c = nullptr;
+  }
+  for (void *p : {(void *)d_urow, (void *)d_uptr, (void *)d_ucol, (void *)d_uval, (void *)d_kappa,
+                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom})
+    if (p) (void)hipFree(p);
+  d_urow = d_uptr = d_ucol = d_ucode = d_geom = nullptr;
+  d_uval = d_kappa = d_aniso = nullptr;
+}
+
+namespace {
+
+Problem *P(ssamg_problem h) {
+  if (!h) throw Error(SSAMG_ERR_ARG, "NULL problem");
+  return reinterpret_cast<Problem *>(h);
+}
+
+void check_part(const Problem *pr, int part) {
+  if (part < 0 || part >= pr->nparts) throw Error(SSAMG_ERR_ARG, "part index out of range");
+}
+
+void check_box(const Problem *pr, int part) {
+  auto &d = pr->dims[part];
+  if (d[0] <= 0 || d[1] <= 0 || d[2] <= 0) throw Error(SSAMG_ERR_STATE, "box of part not set");
+}
+
+int center_of(const std::vector<std::array<int, 3>> &st) {
+  for (size_t e = 0; e < st.size(); ++e)
+    if (st[e][0] == 0 && st[e][1] == 0 && st[e][2] == 0) return (int)e;
+  return -1;
+}
+
+// Build the canonical compressed-row CSR from COO (sorted by row, then col;
+// duplicates summed).
+void canonical_csr(int64_t nnz, const int64_t *row, const int64_t *col, const double *val,
+                   std::vector<int> &urow, std::vector<int> &uptr, std::vector<int> &ucol,
+                   std::vector<double> &uval) {
+  std::vector<int64_t> idx(nnz);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return row[a] != row[b] ? row[a] < row[b] : col[a] < col[b];
+  });
+  urow.clear();
+  uptr.assign(1, 0);
+  ucol.clear();
+  uval.clear();
+  int64_t pr = -1, pc = -1;
+  for (int64_t t = 0; t < nnz; ++t) {
+    const int64_t k = idx[t];
+    if (row[k] == pr && col[k] == pc) {
+      uval.back() += val[k];
+      continue;
+    }
+    if (row[k] != pr) {
+      if (!urow.empty()) uptr.push_back((int)ucol.size());
+      urow.push_back((int)row[k]);
+    }
+    ucol.push_back((int)col[k]);
+    uval.push_back(val[k]);
+    pr = row[k];
+    pc = col[k];
+  }
+  if (!urow.empty()) uptr.push_back((int)ucol.size());
+}
+
+}  // namespace
+
+// face kind from placement: PART when the layer of cells just across the face
+// overlaps another part's box
+void derive_faces(Problem *pr) {
+  for (int p = 0; p < pr->nparts; ++p) {
+    for (int f = 0; f < 6; ++f) {
+      const int ax = f / 2, sg = (f & 1) ? 1 : -1;
+      if (ax >= pr->ndim) {
+        pr->faces[p][f] = SSAMG_FACE_PHYSICAL;
+        continue;
+      }
+      int lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = pr->origin[p][d];
+        hi[d] = pr->origin[p][d] + pr->dims[p][d] - 1;
+      }
+      if (sg < 0)
+        lo[ax] = hi[ax] = pr->origin[p][ax] - 1;
+      else
+        lo[ax] = hi[ax] = pr->origin[p][ax] + pr->dims[p][ax];
+      int kind = SSAMG_FACE_PHYSICAL;
+      for (int q = 0; q < pr->nparts && kind == SSAMG_FACE_PHYSICAL; ++q) {
+        if (q == p) continue;
+        bool over = true;
+        for (int d = 0; d < 3; ++d) {
+          const int qlo = pr->origin[q][d], qhi = pr->origin[q][d] + pr->dims[q][d] - 1;
+          over = over && lo[d] <= qhi && qlo <= hi[d];
+        }
+        if (over) kind = SSAMG_FACE_PART;
+      }
+      pr->faces[p][f] = kind;
+    }
+  }
+}
+
+// canonical finite-volume stencil: center first, then (dz, dy, dx) ascending
+std::vector<std::array<int, 3>> fv_offsets(int kind, int ndim) {
+  std::vector<std::array<int, 3>> out = {{0, 0, 0}};
+  const int zl = ndim == 3 ? -1 : 0, zh = ndim == 3 ? 1 : 0;
+  for (int dz = zl; dz <= zh; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nnz == 0) continue;
+        if ((kind == 7 || kind == 5) && nnz > 1) continue;
+        out.push_back({dx, dy, dz});
+      }
+  return out;
+}
+
+}  // namespace ssamg
+
+using namespace ssamg;
+
+extern "C" {
+
+ssamg_status ssamg_problem_create(int ndim, int nparts, ssamg_problem *out) {
+  API_BEGIN
+  if (!out) throw Error(SSAMG_ERR_ARG, "NULL output");
+  if (ndim != 2 && ndim != 3) throw Error(SSAMG_ERR_ARG, "ndim must be 2 or 3");
+  if (nparts <= 0 || nparts > 8191) throw Error(SSAMG_ERR_ARG, "nparts must be in 1..8191");
+  auto *pr = new Problem();
+  pr->ndim = ndim;
+  pr->nparts = nparts;
+  pr->dims.assign(nparts, {0, 0, 0});
+  pr->origin.assign(nparts, {0, 0, 0});
+  pr->has_origin.assign(nparts, 0);
+  pr->faces.assign(nparts, {0, 0, 0, 0, 0, 0});
+  pr->stencil.assign(nparts, {});
+  pr->center.assign(nparts, -1);
+  pr->coef.assign(nparts, nullptr);
+  pr->coef_set.assign(nparts, 0);
+  *out = reinterpret_cast<ssamg_problem>(pr);
+  API_END
+}
+
+ssamg_status ssamg_problem_destroy(ssamg_problem prob) {
+  API_BEGIN
+  delete reinterpret_cast<Problem *>(prob);
+  API_END
+}
+
+ssamg_status ssamg_problem_set_box(ssamg_problem prob, int part, const int lo[3], const int hi[3]) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  if (!lo || !hi) throw Error(SSAMG_ERR_ARG, "NULL corner");
+  if (lo[0] != 0 || lo[1] != 0 || lo[2] != 0)
+    throw Error(SSAMG_ERR_UNSUPPORTED, "box lower corner must be (0,0,0)");
+  for (int d = 0; d < 3; ++d)
+    if (hi[d] < lo[d]) throw Error(SSAMG_ERR_ARG, "empty box");
+  if (pr->ndim == 2 && hi[2] != 0) throw Error(SSAMG_ERR_ARG, "2D box must have nz = 1");
+  std::array<int, 3> n = {hi[0] + 1, hi[1] + 1, hi[2] + 1};
+  if ((int64_t)n[0] * n[1] * n[2] >= (int64_t(1) << 31)) throw Error(SSAMG_ERR_UNSUPPORTED, "box too large");
+  if (pr->dims[part] != n) {
+    pr->dims[part] = n;
+    if (pr->coef[part]) (void)hipFree(pr->coef[part]);
+    pr->coef[part] = nullptr;
+    pr->coef_set[part] = 0;
+  }
+  API_END
+}
+
+ssamg_status ssamg_problem_set_origin(ssamg_problem prob, int part, const int origin[3]) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  if (!origin) throw Error(SSAMG_ERR_ARG, "NULL origin");
+  pr->origin[part] = {origin[0], origin[1], pr->ndim == 2 ? 0 : origin[2]};
+  pr->has_origin[part] = 1;
+  API_END
+}
+
+ssamg_status ssamg_problem_set_face(ssamg_problem prob, int part, int face, int kind) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  if (face < 0 || face > 5) throw Error(SSAMG_ERR_ARG, "face must be 0..5");
+  if (kind != SSAMG_FACE_PHYSICAL && kind != SSAMG_FACE_PART) throw Error(SSAMG_ERR_ARG, "bad face kind");
+  pr->faces[part][face] = kind;
+  API_END
+}
+
+ssamg_status ssamg_problem_set_stencil(ssamg_problem prob, int part, int nent, const int *off) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  if (!off || nent <= 0) throw Error(SSAMG_ERR_ARG, "empty stencil");
+  if (nent > kMaxEnt) throw Error(SSAMG_ERR_UNSUPPORTED, "more than 27 stencil entries");
+  std::vector<std::array<int, 3>> st;
+  for (int e = 0; e < nent; ++e) {
+    std::array<int, 3> o = {off[3 * e], off[3 * e + 1], off[3 * e + 2]};
+    for (int d = 0; d < 3; ++d)
+      if (o[d] < -1 || o[d] > 1)
+        throw Error(SSAMG_ERR_UNSUPPORTED, "stencil offsets must lie in {-1,0,1}^3");
+    if (pr->ndim == 2 && o[2] != 0) throw Error(SSAMG_ERR_ARG, "2D stencil with dz != 0");
+    if (std::find(st.begin(), st.end(), o) != st.end()) throw Error(SSAMG_ERR_ARG, "repeated stencil offset");
+    st.push_back(o);
+  }
+  const int c = center_of(st);
+  if (c < 0) throw Error(SSAMG_ERR_ARG, "stencil lacks the (0,0,0) entry");
+  if (pr->stencil[part] != st) {
+    pr->stencil[part] = st;
+    pr->center[part] = c;
+    if (pr->coef[part]) (void)hipFree(pr->coef[part]);
+    pr->coef[part] = nullptr;
+    pr->coef_set[part] = 0;
+  }
+  API_END
+}
+
+ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double *vals, int where,
+                                      int constant) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  check_box(pr, part);
+  if (pr->stencil[part].empty()) throw Error(SSAMG_ERR_STATE, "stencil of part not set");
+  if (!vals) throw Error(SSAMG_ERR_ARG, "NULL coefficients");
+  if (where != SSAMG_MEM_HOST && where != SSAMG_MEM_DEVICE) throw Error(SSAMG_ERR_ARG, "bad memory kind");
+  const int nent = (int)pr->stencil[part].size();
+  const int64_t ncell = (int64_t)pr->dims[part][0] * pr->dims[part][1] * pr->dims[part][2];
+  if (!pr->coef[part]) pr->coef[part] = dev_alloc<double>((size_t)nent * ncell);
+  double *dst = pr->coef[part];
+  if (constant) {
+    std::vector<double> host(nent);
+    if (where == SSAMG_MEM_HOST)
+      std::memcpy(host.data(), vals, nent * sizeof(double));
+    else
+      SSAMG_HIP(hipMemcpy(host.data(), vals, nent * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> full((size_t)nent * ncell);
+    for (int e = 0; e < nent; ++e) std::fill(full.begin() + e * ncell, full.begin() + (e + 1) * ncell, host[e]);
+    SSAMG_HIP(hipMemcpy(dst, full.data(), full.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    SSAMG_HIP(hipMemcpy(dst, vals, (size_t)nent * ncell * sizeof(double),
+                        where == SSAMG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice));
+  }
+  BoxStencil bs{};
+  for (int d = 0; d < 3; ++d) bs.n[d] = pr->dims[part][d];
+  bs.nent = nent;
+  bs.center = pr->center[part];
+  bs.ncell = ncell;
+  for (int e = 0; e < nent; ++e)
+    bs.code[e] = pack_off(pr->stencil[part][e][0], pr->stencil[part][e][1], pr->stencil[part][e][2]);
+  bs.coef = dst;
+  int *flag = dev_alloc<int>(1);
+  SSAMG_HIP(hipMemset(flag, 0, sizeof(int)));
+  launch_normalise(bs, flag, nullptr);
+  int hflag = 0;
+  SSAMG_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+  (void)hipFree(flag);
+  SSAMG_HIP(hipGetLastError());
+  pr->coef_set[part] = 1;
+  if (hflag) throw Error(SSAMG_ERR_NUMERIC, "nonpositive diagonal or non-finite coefficient");
+  API_END
+}
+
+ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const int64_t *row,
+                                        const int64_t *col, const double *val) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  if (nnz < 0) throw Error(SSAMG_ERR_ARG, "negative nnz");
+  if (nnz > 0 && (!row || !col || !val)) throw Error(SSAMG_ERR_ARG, "NULL coupling arrays");
+  for (int p = 0; p < pr->nparts; ++p) check_box(pr, p);
+  const auto off = pr->offsets();
+  const int64_t N = off.back();
+  auto part_of = [&](int64_t id) {
+    return (int)(std::upper_bound(off.begin(), off.end(), id) - off.begin()) - 1;
+  };
+  for (int64_t k = 0; k < nnz; ++k) {
+    if (row[k] < 0 || row[k] >= N || col[k] < 0 || col[k] >= N)
+      throw Error(SSAMG_ERR_ARG, "coupling index out of range");
+    if (part_of(row[k]) == part_of(col[k]))
+      throw Error(SSAMG_ERR_ARG, "coupling inside one part (U must couple different parts)");
+    if (!std::isfinite(val[k])) throw Error(SSAMG_ERR_NUMERIC, "non-finite coupling value");
+  }
+  canonical_csr(nnz, row, col, val, pr->urow, pr->uptr, pr->ucol, pr->uval_host);
+  dev_upload(pr->d_urow, pr->urow);
+  dev_upload(pr->d_uptr, pr->uptr);
+  dev_upload(pr->d_ucol, pr->ucol);
+  dev_upload(pr->d_uval, pr->uval_host);
+  pr->coupling_set = true;
+  API_END
+}
+
+ssamg_status ssamg_problem_num_cells(ssamg_problem prob, int64_t *n) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  if (!n) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *n = pr->ncell_total();
+  API_END
+}
+
+ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, const double *aniso,
+                                       int stencil, void *hip_stream) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!kappa || !aniso) throw Error(SSAMG_ERR_ARG, "NULL kappa or aniso");
+  const bool ok3 = pr->ndim == 3 && (stencil == 7 || stencil == 27);
+  const bool ok2 = pr->ndim == 2 && (stencil == 5 || stencil == 9);
+  if (!ok3 && !ok2) throw Error(SSAMG_ERR_ARG, "stencil must be 7|27 (3D) or 5|9 (2D)");
+  for (int p = 0; p < pr->nparts; ++p) {
+    check_box(pr, p);
+    if (!pr->has_origin[p]) throw Error(SSAMG_ERR_STATE, "origin of every part is needed");
+    for (int d = 0; d < 3; ++d)
+      if (!(aniso[3 * p + d] > 0.0) || !std::isfinite(aniso[3 * p + d]))
+        throw Error(SSAMG_ERR_ARG, "aniso factors must be positive");
+  }
+  // parts must not overlap in the global index space
+  for (int p = 0; p < pr->nparts; ++p)
+    for (int q = p + 1; q < pr->nparts; ++q) {
+      bool over = true;
+      for (int d = 0; d < 3; ++d)
+        over = over && pr->origin[p][d] < pr->origin[q][d] + pr->dims[q][d] &&
+               pr->origin[q][d] < pr->origin[p][d] + pr->dims[p][d];
+      if (over) throw Error(SSAMG_ERR_ARG, "parts overlap in the global index space");
+    }
+  const auto st_off = fv_offsets(stencil, pr->ndim);
+  const int nent = (int)st_off.size();
+  const auto off = pr->offsets();
+  const int64_t N = off.back();
+  int maxcell = 0;
+  for (int p = 0; p < pr->nparts; ++p) {
+    const int64_t nc = off[p + 1] - off[p];
+    maxcell = std::max<int64_t>(maxcell, nc);
+    if (pr->stencil[p] != st_off || !pr->coef[p]) {
+      if (pr->coef[p]) (void)hipFree(pr->coef[p]);
+      pr->coef[p] = dev_alloc<double>((size_t)nent * nc);
+    }
+    pr->stencil[p] = st_off;
+    pr->center[p] = 0;
+    pr->coef_set[p] = 1;
+  }
+  derive_faces(pr);
+  // geometry table
+  std::vector<int> geom(7 * pr->nparts);
+  for (int p = 0; p < pr->nparts; ++p) {
+    for (int d = 0; d < 3; ++d) {
+      geom[7 * p + d] = pr->origin[p][d];
+      geom[7 * p + 3 + d] = pr->dims[p][d];
+    }
+    geom[7 * p + 6] = (int)off[p];
+  }
+  dev_upload(pr->d_geom, geom);
+  // coupling structure from placement: boundary cells whose neighbour lies in
+  // another part
+  std::vector<int64_t> crow, ccol;
+  std::vector<int> ccode_raw;
+  for (int p = 0; p < pr->nparts; ++p) {
+    const auto &n = pr->dims[p];
+    const auto &o = pr->origin[p];
+    for (int k = 0; k < n[2]; ++k)
+      for (int j = 0; j < n[1]; ++j) {
+        const bool edge_jk = (j == 0 || j == n[1] - 1 || k == 0 || k == n[2] - 1);
+        for (int i = 0; i < n[0]; ++i) {
+          if (!edge_jk && i != 0 && i != n[0] - 1) {
+            i = n[0] - 2;   // skip to the last cell of the row
+            continue;
+          }
+          for (int e = 1; e < nent; ++e) {
+            const int lc[3] = {i + st_off[e][0], j + st_off[e][1], k + st_off[e][2]};
+            if (lc[0] >= 0 && lc[0] < n[0] && lc[1] >= 0 && lc[1] < n[1] && lc[2] >= 0 && lc[2] < n[2])
+              continue;
+            const int G[3] = {o[0] + lc[0], o[1] + lc[1], o[2] + lc[2]};
+            for (int q = 0; q < pr->nparts; ++q) {
+              if (q == p) continue;
+              const auto &h = pr->origin[q];
+              const auto &m = pr->dims[q];
+              if (G[0] >= h[0] && G[0] < h[0] + m[0] && G[1] >= h[1] && G[1] < h[1] + m[1] &&
+                  G[2] >= h[2] && G[2] < h[2] + m[2]) {
+                const int64_t jid = off[q] + (G[0] - h[0]) + (int64_t)m[0] * ((G[1] - h[1]) + (int64_t)m[1] * (G[2] - h[2]));
+                crow.push_back(off[p] + i + (int64_t)n[0] * (j + (int64_t)n[1] * k));
+                ccol.push_back(jid);
+                ccode_raw.push_back(pack_off(st_off[e][0], st_off[e][1], st_off[e][2]) | (p << 5) | (q << 18));
+                break;
+              }
+            }
+          }
+        }
+      }
+  }
+  // canonical order (rows ascending already; sort entries inside each row)
+  std::vector<int64_t> idx(crow.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return crow[a] != crow[b] ? crow[a] < crow[b] : ccol[a] < ccol[b];
+  });
+  pr->urow.clear();
+  pr->uptr.assign(1, 0);
+  pr->ucol.clear();
+  std::vector<int> ucode;
+  for (int64_t t = 0; t < (int64_t)idx.size(); ++t) {
+    const int64_t k = idx[t];
+    if (pr->urow.empty() || pr->urow.back() != (int)crow[k]) {
+      if (!pr->urow.empty()) pr->uptr.push_back((int)pr->ucol.size());
+      pr->urow.push_back((int)crow[k]);
+    }
+    pr->ucol.push_back((int)ccol[k]);
+    ucode.push_back(ccode_raw[k]);
+  }
+  if (!pr->urow.empty()) pr->uptr.push_back((int)pr->ucol.size());
+  pr->uval_host.assign(pr->ucol.size(), 0.0);
+  dev_upload(pr->d_urow, pr->urow);
+  dev_upload(pr->d_uptr, pr->uptr);
+  dev_upload(pr->d_ucol, pr->ucol);
+  dev_upload(pr->d_ucode, ucode);
+  if (pr->d_uval) (void)hipFree(pr->d_uval);
+  pr->d_uval = dev_alloc<double>(pr->ucol.size());
+  pr->coupling_set = true;
+  // conductivity and anisotropy copies
+  if (pr->d_kappa) (void)hipFree(pr->d_kappa);
+  pr->d_kappa = dev_alloc<double>(N);
+  SSAMG_HIP(hipMemcpyAsync(pr->d_kappa, kappa, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<double> an(aniso, aniso + 3 * pr->nparts);
+  dev_upload(pr->d_aniso, an);
+  pr->fv_stencil = stencil;
+  // kernels
+  FvArgs fa{};
+  fa.geom = pr->d_geom;
+  fa.nparts = pr->nparts;
+  fa.nent = nent;
+  for (int e = 0; e < nent; ++e) fa.code[e] = pack_off(st_off[e][0], st_off[e][1], st_off[e][2]);
+  std::vector<double *> cptr(pr->coef.begin(), pr->coef.end());
+  double **d_cptr = dev_alloc<double *>(cptr.size());
+  SSAMG_HIP(hipMemcpy(d_cptr, cptr.data(), cptr.size() * sizeof(double *), hipMemcpyHostToDevice));
+  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, d_cptr, st);
+  launch_fv_coupling((int)pr->urow.size(), pr->d_urow, pr->d_uptr, pr->d_ucol, pr->d_ucode,
+                     pr->d_kappa, pr->d_aniso, pr->d_uval, st);
+  SSAMG_HIP(hipGetLastError());
+  SSAMG_HIP(hipStreamSynchronize(st));
+  (void)hipFree(d_cptr);
+  API_END
+}
+
+ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, const double *lambda, const double *x,
+                                   double *grad, void *hip_stream) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  if (!pr->fv_stencil) throw Error(SSAMG_ERR_STATE, "fv_assemble has not been called");
+  if (!lambda || !x || !grad) throw Error(SSAMG_ERR_ARG, "NULL vector");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const auto st_off = fv_offsets(pr->fv_stencil, pr->ndim);
+  FvArgs fa{};
+  fa.geom = pr->d_geom;
+  fa.nparts = pr->nparts;
+  fa.nent = (int)st_off.size();
+  for (int e = 0; e < fa.nent; ++e) fa.code[e] = pack_off(st_off[e][0], st_off[e][1], st_off[e][2]);
+  const auto off = pr->offsets();
+  int64_t maxcell = 0;
+  for (int p = 0; p < pr->nparts; ++p) maxcell = std::max(maxcell, off[p + 1] - off[p]);
+  launch_fv_grad(fa, (int)maxcell, pr->d_kappa, pr->d_aniso, lambda, x, grad, (int)pr->urow.size(),
+                 pr->d_urow, pr->d_uptr, pr->d_ucol, pr->d_ucode, st);
+  SSAMG_HIP(hipGetLastError());
+  SSAMG_HIP(hipStreamSynchronize(st));
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,813 @@
+// SSAMG solver: symbolic setup (Section 3.1 metric and Algorithm 1, symbolic
+// coarse stencils and Galerkin tables, structure of every coarse coupling
+// matrix), numeric setup (device kernels), the V(1,1) cycle and PCG.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "capi_common.h"
+#include "ssamg_impl.h"
+
+namespace ssamg {
+
+thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+constexpr double kTieRtol = 1e-10;
+constexpr double kInf = std::numeric_limits<double>::infinity();
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Bump allocator over the workspace; run once with base = nullptr to size it.
+struct Carver {
+  char *base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t n) {
+    off = align_up(off);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+int64_t vol(const std::array<int, 3> &n) { return (int64_t)n[0] * n[1] * n[2]; }
+
+void carve(Solver &s, Carver &cv);
+
+int argmin_tied(const std::array<double, 3> &w, const std::vector<int> &cand) {
+  double wmin = kInf;
+  for (int d : cand) wmin = std::min(wmin, w[d]);
+  for (int d : cand)
+    if (w[d] == wmin || w[d] <= wmin * (1.0 + kTieRtol)) return d;
+  return cand.front();
+}
+
+// eq:relax1 / eq:alpha-beta: omega_p = 2 / (3 - beta_p / alpha_p)
+double relax_weight(const std::array<double, 3> &w, int dstar, int ndim) {
+  double alpha = 0.0, beta = 0.0;
+  for (int d = 0; d < ndim; ++d) {
+    const double inv = std::isfinite(w[d]) ? 1.0 / (w[d] * w[d]) : 0.0;
+    alpha += inv;
+    if (d != dstar) beta += inv;
+  }
+  const double ratio = alpha > 0.0 ? beta / alpha : 0.0;
+  return 2.0 / (3.0 - ratio);
+}
+
+// symbolic coarse stencil: along d*, 0 -> {-1,0,1} and +-1 -> {0,+-1}; sorted (dz,dy,dx)
+std::vector<std::array<int, 3>> coarse_pattern(const std::vector<std::array<int, 3>> &fine, int ds) {
+  std::vector<std::array<int, 3>> out;
+  auto add = [&](std::array<int, 3> t) {
+    if (std::find(out.begin(), out.end(), t) == out.end()) out.push_back(t);
+  };
+  for (auto s : fine) {
+    if (ds < 0) {
+      add(s);
+    } else if (s[ds] == 0) {
+      for (int t = -1; t <= 1; ++t) {
+        auto u = s;
+        u[ds] = t;
+        add(u);
+      }
+    } else {
+      auto u = s;
+      u[ds] = 0;
+      add(u);
+      add(s);
+    }
+  }
+  std::sort(out.begin(), out.end(), [](const std::array<int, 3> &a, const std::array<int, 3> &b) {
+    return std::make_tuple(a[2], a[1], a[0]) < std::make_tuple(b[2], b[1], b[0]);
+  });
+  return out;
+}
+
+int index_of(const std::vector<std::array<int, 3>> &pat, const std::array<int, 3> &t) {
+  for (size_t e = 0; e < pat.size(); ++e)
+    if (pat[e] == t) return (int)e;
+  return -1;
+}
+
+// Galerkin table of one part (see k_rap)
+void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) {
+  f.rap_start.assign(1, 0);
+  f.rap_code.clear();
+  if (f.dstar < 0) {
+    for (size_t e = 0; e < cpat.size(); ++e) {
+      f.rap_code.push_back(index_of(f.pat, cpat[e]));
+      f.rap_start.push_back((int)f.rap_code.size());
+    }
+    return;
+  }
+  const int ds = f.dstar;
+  std::vector<std::vector<int>> lists(cpat.size());
+  for (int r = -1; r <= 1; ++r)
+    for (size_t si = 0; si < f.pat.size(); ++si) {
+      const auto s = f.pat[si];
+      const int q = r + s[ds];
+      auto push = [&](int td, int gsel) {
+        auto t = s;
+        t[ds] = td;
+        const int e = index_of(cpat, t);
+        if (e < 0) throw Error(SSAMG_ERR_STATE, "internal: Galerkin target outside coarse pattern");
+        lists[e].push_back((r + 1) | ((int)si << 2) | (gsel << 7));
+      };
+      if ((q & 1) == 0) {
+        push(q / 2, 0);
+      } else {
+        push((q - 1) / 2, 1);
+        push((q + 1) / 2, 2);
+      }
+    }
+  for (auto &l : lists) {
+    f.rap_code.insert(f.rap_code.end(), l.begin(), l.end());
+    f.rap_start.push_back((int)f.rap_code.size());
+  }
+}
+
+int part_of(const Level &L, int64_t cell) {
+  int lo = 0, hi = (int)L.parts.size() - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (L.parts[mid].off <= cell)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// nonzeros of row `cell` of P_l: coarse ids and weight sources (-1 = 1.0,
+// else an index into the level weight buffer)
+int prow(const Level &L, int64_t cell, int col[2], int src[2]) {
+  const int p = part_of(L, cell);
+  const PartLevel &q = L.parts[p];
+  const int64_t loc = cell - q.off;
+  if (q.dstar < 0) {
+    col[0] = (int)(q.coff + loc);
+    src[0] = -1;
+    return 1;
+  }
+  int f[3];
+  f[0] = (int)(loc % q.n[0]);
+  f[1] = (int)((loc / q.n[0]) % q.n[1]);
+  f[2] = (int)(loc / ((int64_t)q.n[0] * q.n[1]));
+  const int ds = q.dstar;
+  auto clin = [&](const int c[3]) { return q.coff + c[0] + (int64_t)q.cn[0] * (c[1] + (int64_t)q.cn[1] * c[2]); };
+  int c[3] = {f[0], f[1], f[2]};
+  if ((f[ds] & 1) == 0) {
+    c[ds] = f[ds] / 2;
+    col[0] = (int)clin(c);
+    src[0] = -1;
+    return 1;
+  }
+  int g[3] = {f[0], f[1], f[2]};
+  g[ds] = (f[ds] - 1) / 2;
+  const int64_t fl = g[0] + (int64_t)q.fn[0] * (g[1] + (int64_t)q.fn[1] * g[2]);
+  c[ds] = (f[ds] - 1) / 2;
+  col[0] = (int)clin(c);
+  src[0] = (int)(q.wofs + fl);
+  if (f[ds] + 1 <= q.n[ds] - 1) {
+    c[ds] = (f[ds] + 1) / 2;
+    col[1] = (int)clin(c);
+    src[1] = (int)(q.wofs + q.nf + fl);
+    return 2;
+  }
+  return 1;
+}
+
+// Structure of U_{l+1} = P^T U_l P and, for every coarse entry, the ordered
+// list of (U_l entry, weight source of P(f, I), weight source of P(g, J)).
+void build_coarse_coupling(const Level &f, Level &c) {
+  const int nrow = (int)f.urow.size();
+  std::vector<int> cnt(c.N + 1, 0);
+  int colf[2], srcf[2], colg[2], srcg[2];
+  for (int r = 0; r < nrow; ++r) {
+    const int nf = prow(f, f.urow[r], colf, srcf);
+    for (int k = f.uptr[r]; k < f.uptr[r + 1]; ++k) {
+      const int ng = prow(f, f.ucol[k], colg, srcg);
+      for (int a = 0; a < nf; ++a) cnt[colf[a] + 1] += ng;
+    }
+  }
+  for (int64_t i = 0; i < c.N; ++i) cnt[i + 1] += cnt[i];
+  const int64_t ntot = cnt[c.N];
+  std::vector<int> J(ntot), K(ntot), A(ntot), B(ntot);
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+  for (int r = 0; r < nrow; ++r) {
+    const int nf = prow(f, f.urow[r], colf, srcf);
+    for (int k = f.uptr[r]; k < f.uptr[r + 1]; ++k) {
+      const int ng = prow(f, f.ucol[k], colg, srcg);
+      for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < ng; ++b) {
+          const int t = pos[colf[a]]++;
+          J[t] = colg[b];
+          K[t] = k;
+          A[t] = srcf[a];
+          B[t] = srcg[b];
+        }
+    }
+  }
+  c.urow.clear();
+  c.uptr.assign(1, 0);
+  c.ucol.clear();
+  c.uc_start.assign(1, 0);
+  c.uc_k.clear();
+  c.uc_a.clear();
+  c.uc_b.clear();
+  c.uc_k.reserve(ntot);
+  c.uc_a.reserve(ntot);
+  c.uc_b.reserve(ntot);
+  std::vector<int> idx;
+  for (int64_t I = 0; I < c.N; ++I) {
+    const int s0 = cnt[I], s1 = cnt[I + 1];
+    if (s0 == s1) continue;
+    idx.resize(s1 - s0);
+    std::iota(idx.begin(), idx.end(), s0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return J[a] < J[b]; });
+    c.urow.push_back((int)I);
+    int prevJ = -1;
+    for (int t : idx) {
+      if (J[t] != prevJ) {
+        if (prevJ >= 0) c.uc_start.push_back((int)c.uc_k.size());
+        c.ucol.push_back(J[t]);
+        prevJ = J[t];
+      }
+      c.uc_k.push_back(K[t]);
+      c.uc_a.push_back(A[t]);
+      c.uc_b.push_back(B[t]);
+    }
+    c.uc_start.push_back((int)c.uc_k.size());
+    c.uptr.push_back((int)c.ucol.size());
+  }
+}
+
+void fill_urow_part(Level &L) {
+  L.urow_part.resize(L.urow.size());
+  for (size_t r = 0; r < L.urow.size(); ++r) L.urow_part[r] = part_of(L, L.urow[r]);
+}
+
+template <typename T>
+PartDesc<T> make_desc(const PartLevel &q, const T *coef, const T *w) {
+  PartDesc<T> d{};
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = q.n[a];
+    d.fn[a] = q.fn[a];
+    d.cn[a] = q.cn[a];
+  }
+  d.nent = (int)q.pat.size();
+  d.center = q.center;
+  d.dstar = q.dstar;
+  d.faces = q.faces;
+  d.off = q.off;
+  d.ncell = q.ncell;
+  d.coff = q.coff;
+  d.cncell = q.cncell;
+  d.nf = q.nf;
+  d.omega = (T)q.omega;
+  d.coef = coef;
+  d.wm = w ? w + q.wofs : nullptr;
+  d.wp = w ? w + q.wofs + q.nf : nullptr;
+  for (size_t e = 0; e < q.pat.size(); ++e) {
+    const auto &o = q.pat[e];
+    d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
+    d.code[e] = pack_off(o[0], o[1], o[2]);
+  }
+  return d;
+}
+
+template <typename T>
+void upload(T *dst, const std::vector<T> &src, hipStream_t st) {
+  if (!src.empty())
+    SSAMG_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+}  // namespace
+
+Solver::~Solver() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ws_owned && ws) (void)hipFree(ws);
+  if (h_pin) (void)hipHostFree(h_pin);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// ---------------------------------------------------------------- symbolic
+
+void setup_symbolic(Solver &s) {
+  Problem &pr = *s.prob;
+  const int np = pr.nparts;
+  for (int p = 0; p < np; ++p) {
+    if (vol(pr.dims[p]) <= 0) throw Error(SSAMG_ERR_STATE, "box of part " + std::to_string(p) + " not set");
+    if (pr.stencil[p].empty() || !pr.coef_set[p] || !pr.coef[p])
+      throw Error(SSAMG_ERR_STATE, "coefficients of part " + std::to_string(p) + " not set");
+  }
+  if (pr.ncell_total() >= (int64_t(1) << 31)) throw Error(SSAMG_ERR_UNSUPPORTED, "more than 2^31 cells");
+  if (s.graph_exec) {
+    (void)hipGraphExecDestroy(s.graph_exec);
+    s.graph_exec = nullptr;
+  }
+  if (s.graph) {
+    (void)hipGraphDestroy(s.graph);
+    s.graph = nullptr;
+  }
+  if (s.ws_owned && s.ws) (void)hipFree(s.ws);
+  s.ws = nullptr;
+  s.ws_owned = false;
+  s.lv.clear();
+  s.state = 0;
+
+  // level 0 from the problem
+  Level L0;
+  int64_t off = 0;
+  for (int p = 0; p < np; ++p) {
+    PartLevel q;
+    q.n = pr.dims[p];
+    q.off = off;
+    q.ncell = vol(q.n);
+    off += q.ncell;
+    q.pat = pr.stencil[p];
+    q.center = pr.center[p];
+    q.coef64 = pr.coef[p];
+    for (int f = 0; f < 6; ++f)
+      if (pr.faces[p][f] == SSAMG_FACE_PART) q.faces |= 1 << f;
+    L0.parts.push_back(q);
+  }
+  L0.N = off;
+  L0.urow = pr.urow;
+  L0.uptr = pr.uptr.empty() ? std::vector<int>{0} : pr.uptr;
+  L0.ucol = pr.ucol;
+
+  // direction sums c_d on the device (the only round trip of the symbolic setup)
+  {
+    std::vector<PartDesc<double>> hd;
+    int maxcell = 0;
+    for (auto &q : L0.parts) {
+      hd.push_back(make_desc<double>(q, q.coef64, nullptr));
+      maxcell = std::max<int64_t>(maxcell, q.ncell);
+    }
+    PartDesc<double> *dd = dev_alloc<PartDesc<double>>(np);
+    double *part = dev_alloc<double>((size_t)np * 256 * 3);
+    double *out = dev_alloc<double>((size_t)np * 3);
+    SSAMG_HIP(hipMemcpyAsync(dd, hd.data(), np * sizeof(PartDesc<double>), hipMemcpyHostToDevice, s.stream));
+    launch_wsum(dd, np, maxcell, part, out, s.stream);
+    SSAMG_HIP(hipGetLastError());
+    s.cd.assign((size_t)np * 3, 0.0);
+    SSAMG_HIP(hipMemcpyAsync(s.cd.data(), out, np * 3 * sizeof(double), hipMemcpyDeviceToHost, s.stream));
+    SSAMG_HIP(hipStreamSynchronize(s.stream));
+    (void)hipFree(dd);
+    (void)hipFree(part);
+    (void)hipFree(out);
+  }
+
+  // W (Section 3.1) and Algorithm 1
+  const int ndim = pr.ndim;
+  std::vector<std::array<double, 3>> W(np);
+  for (int p = 0; p < np; ++p) {
+    double cmax = -kInf;
+    for (int d = 0; d < ndim; ++d) cmax = std::max(cmax, s.cd[3 * p + d]);
+    for (int d = 0; d < 3; ++d) {
+      const double c = s.cd[3 * p + d];
+      W[p][d] = (d < ndim && c > 0.0 && cmax > 0.0) ? std::sqrt(cmax / c) : kInf;
+    }
+  }
+  std::vector<int> all_d(ndim);
+  std::iota(all_d.begin(), all_d.end(), 0);
+  s.lv.push_back(std::move(L0));
+  while (true) {
+    Level &L = s.lv.back();
+    const int l = (int)s.lv.size() - 1;
+    bool all_one = true;
+    for (auto &q : L.parts) all_one = all_one && q.ncell == 1;
+    const bool last = all_one || l >= s.prm.max_levels - 1 ||
+                      (s.prm.min_coarse_size > 0 && L.N < s.prm.min_coarse_size);
+    Level C;
+    int64_t coff = 0;
+    for (int p = 0; p < np; ++p) {
+      PartLevel &q = L.parts[p];
+      std::vector<int> cand;
+      for (int d = 0; d < ndim; ++d)
+        if (q.n[d] > 1) cand.push_back(d);
+      int ds = -1;
+      if (last || cand.empty()) {
+        q.omega = relax_weight(W[p], argmin_tied(W[p], all_d), ndim);
+      } else {
+        ds = argmin_tied(W[p], cand);
+        q.omega = relax_weight(W[p], ds, ndim);
+        W[p][ds] *= 2.0;
+      }
+      if (s.prm.omega > 0.0) q.omega = s.prm.omega;
+      q.dstar = ds;
+      q.cn = q.n;
+      q.fn = {0, 0, 0};
+      q.nf = 0;
+      if (ds >= 0) {
+        q.cn[ds] = (q.n[ds] + 1) / 2;
+        q.fn = q.n;
+        q.fn[ds] = q.n[ds] / 2;
+        q.nf = vol(q.fn);
+      }
+      q.cncell = vol(q.cn);
+      q.coff = coff;
+      coff += q.cncell;
+      if (!last) {
+        PartLevel c;
+        c.n = q.cn;
+        c.off = q.coff;
+        c.ncell = q.cncell;
+        c.faces = q.faces;
+        c.pat = coarse_pattern(q.pat, ds);
+        c.center = index_of(c.pat, {0, 0, 0});
+        build_rap_table(q, c.pat);
+        C.parts.push_back(std::move(c));
+      }
+    }
+    // weight buffer layout of this level
+    int64_t w = 0;
+    for (auto &q : L.parts) {
+      q.wofs = w;
+      w += 2 * q.nf;
+    }
+    L.nw = w;
+    L.maxcell = L.maxcoarse = L.maxf = 0;
+    for (auto &q : L.parts) {
+      L.maxcell = std::max<int64_t>(L.maxcell, q.ncell);
+      L.maxcoarse = std::max<int64_t>(L.maxcoarse, q.cncell);
+      L.maxf = std::max<int64_t>(L.maxf, q.nf);
+    }
+    fill_urow_part(L);
+    if (last) break;
+    C.N = coff;
+    build_coarse_coupling(L, C);
+    s.lv.push_back(std::move(C));
+  }
+  // sizing pass of the workspace
+  Carver cv;
+  carve(s, cv);
+  s.ws_bytes = cv.off + 256;
+  s.state = 1;
+}
+
+namespace {
+
+// Assign every device buffer of the hierarchy from one workspace (base =
+// nullptr: sizing only).  The order of takes must not depend on base.
+void carve(Solver &s, Carver &cv) {
+  const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
+  const int L = (int)s.lv.size();
+  const int nr = s.prm.max_nrhs;
+  const int64_t N0 = s.lv[0].N;
+  s.r = cv.take<double>((size_t)N0 * nr);
+  s.z = cv.take<double>((size_t)N0 * nr);
+  s.p = cv.take<double>((size_t)N0 * nr);
+  s.q = cv.take<double>((size_t)N0 * nr);
+  s.partial = cv.take<double>((size_t)kRedBlocks * kMaxRhs);
+  s.scal = cv.take<double>((size_t)kScalSlots * kMaxRhs);
+  s.active = cv.take<int>(kMaxRhs);
+  s.flag = cv.take<int>(1);
+  for (int l = 0; l < L; ++l) {
+    Level &V = s.lv[l];
+    const bool cyc32 = mixed && l < L - 1;
+    V.cycle32 = mixed;   // the coarsest level of a mixed cycle keeps FP32 vectors
+    for (auto &q : V.parts) {
+      if (l > 0) q.coef64 = cv.take<double>((size_t)q.pat.size() * q.ncell);
+      q.coef32 = cyc32 ? cv.take<float>((size_t)q.pat.size() * q.ncell) : nullptr;
+      q.d_rap_start = l < L - 1 ? cv.take<int>(q.rap_start.size()) : nullptr;
+      q.d_rap_code = l < L - 1 ? cv.take<int>(q.rap_code.size()) : nullptr;
+    }
+    V.d_desc64 = cv.take<PartDesc<double>>(V.parts.size());
+    V.d_desc32 = mixed ? cv.take<PartDesc<float>>(V.parts.size()) : nullptr;
+    V.d_rapdesc = l < L - 1 ? cv.take<RapDesc>(V.parts.size()) : nullptr;
+    V.d_w64 = l < L - 1 ? cv.take<double>(V.nw) : nullptr;
+    V.d_w32 = (cyc32 && l < L - 1) ? cv.take<float>(V.nw) : nullptr;
+    const size_t nnz = V.ucol.size(), nrow = V.urow.size();
+    if (l == 0) {
+      V.d_urow = s.prob->d_urow;
+      V.d_uptr = s.prob->d_uptr;
+      V.d_ucol = s.prob->d_ucol;
+      V.d_uval64 = s.prob->d_uval;
+    } else {
+      V.d_urow = cv.take<int>(nrow);
+      V.d_uptr = cv.take<int>(nrow + 1);
+      V.d_ucol = cv.take<int>(nnz);
+      V.d_uval64 = cv.take<double>(nnz);
+      V.d_uc_start = cv.take<int>(V.uc_start.size());
+      V.d_uc_k = cv.take<int>(V.uc_k.size());
+      V.d_uc_a = cv.take<int>(V.uc_a.size());
+      V.d_uc_b = cv.take<int>(V.uc_b.size());
+    }
+    V.d_urow_part = cv.take<int>(nrow);
+    V.d_uscale64 = cv.take<double>(nrow);
+    V.d_uval32 = cyc32 ? cv.take<float>(nnz) : nullptr;
+    V.d_uscale32 = cyc32 ? cv.take<float>(nrow) : nullptr;
+    const size_t nv = (size_t)V.N * nr;
+    if (mixed) {
+      V.vb = cv.take<float>(nv);
+      V.vx = cv.take<float>(nv);
+      V.vt = cv.take<float>(nv);
+    } else {
+      V.vb = l == 0 ? (void *)s.r : (void *)cv.take<double>(nv);
+      V.vx = cv.take<double>(nv);
+      V.vt = l == 0 ? (void *)s.z : (void *)cv.take<double>(nv);
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- numeric
+
+void setup_numeric(Solver &s, void *ws, size_t bytes) {
+  if (s.state < 1) throw Error(SSAMG_ERR_STATE, "setup_symbolic must come first");
+  hipStream_t st = s.stream;
+  if (ws) {
+    if (bytes < s.ws_bytes) throw Error(SSAMG_ERR_ARG, "workspace smaller than ssamg_workspace_bytes");
+    if (s.ws_owned && s.ws) (void)hipFree(s.ws);
+    s.ws = ws;
+    s.ws_owned = false;
+  } else if (!s.ws || !s.ws_owned) {
+    s.ws = dev_alloc<char>(s.ws_bytes);
+    s.ws_owned = true;
+  }
+  if (s.graph_exec) {
+    (void)hipGraphExecDestroy(s.graph_exec);
+    s.graph_exec = nullptr;
+  }
+  if (s.graph) {
+    (void)hipGraphDestroy(s.graph);
+    s.graph = nullptr;
+  }
+  Carver cv;
+  cv.base = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(s.ws) + 255) & ~uintptr_t(255));
+  carve(s, cv);
+  const int L = (int)s.lv.size();
+  const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
+  // descriptors and host-built tables
+  for (int l = 0; l < L; ++l) {
+    Level &V = s.lv[l];
+    std::vector<PartDesc<double>> h64;
+    std::vector<PartDesc<float>> h32;
+    std::vector<RapDesc> hr;
+    for (auto &q : V.parts) {
+      h64.push_back(make_desc<double>(q, q.coef64, V.d_w64));
+      if (mixed) h32.push_back(make_desc<float>(q, q.coef32, V.d_w32));
+      if (l < L - 1) {
+        upload(q.d_rap_start, q.rap_start, st);
+        upload(q.d_rap_code, q.rap_code, st);
+        RapDesc r{};
+        r.out = nullptr;   // filled below once the coarse part is known
+        r.start = q.d_rap_start;
+        r.code = q.d_rap_code;
+        r.nent = (int)q.rap_start.size() - 1;
+        hr.push_back(r);
+      }
+    }
+    if (l < L - 1)
+      for (size_t p = 0; p < V.parts.size(); ++p) hr[p].out = s.lv[l + 1].parts[p].coef64;
+    upload(V.d_desc64, h64, st);
+    if (mixed) upload(V.d_desc32, h32, st);
+    if (l < L - 1) upload(V.d_rapdesc, hr, st);
+    if (l > 0) {
+      upload(V.d_urow, V.urow, st);
+      upload(V.d_uptr, V.uptr, st);
+      upload(V.d_ucol, V.ucol, st);
+      upload(V.d_uc_start, V.uc_start, st);
+      upload(V.d_uc_k, V.uc_k, st);
+      upload(V.d_uc_a, V.uc_a, st);
+      upload(V.d_uc_b, V.uc_b, st);
+    }
+    upload(V.d_urow_part, V.urow_part, st);
+  }
+  SSAMG_HIP(hipMemsetAsync(s.flag, 0, sizeof(int), st));
+  // level by level: weights, structured and unstructured Galerkin products
+  for (int l = 0; l + 1 < L; ++l) {
+    Level &V = s.lv[l], &C = s.lv[l + 1];
+    const int np = (int)V.parts.size();
+    launch_interp_weights(V.d_desc64, np, V.maxf, s.flag, st);
+    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, st);
+    launch_uc_numeric((int64_t)C.ucol.size(), C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
+                      V.d_w64, C.d_uval64, st);
+  }
+  for (int l = 0; l < L; ++l) {
+    Level &V = s.lv[l];
+    launch_uscale((int)V.urow.size(), V.d_urow, V.d_urow_part, V.d_desc64, V.d_uscale64, st);
+  }
+  if (mixed) {
+    for (int l = 0; l + 1 < L; ++l) {
+      Level &V = s.lv[l];
+      for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
+      launch_cast_d2f(V.d_w64, V.d_w32, V.nw, st);
+      launch_cast_d2f(V.d_uval64, V.d_uval32, (int64_t)V.ucol.size(), st);
+      launch_cast_d2f(V.d_uscale64, V.d_uscale32, (int64_t)V.urow.size(), st);
+    }
+  }
+  SSAMG_HIP(hipGetLastError());
+  int hflag = 0;
+  SSAMG_HIP(hipMemcpyAsync(&hflag, s.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipStreamSynchronize(st));
+  if (hflag) throw Error(SSAMG_ERR_NUMERIC, "nonpositive or non-finite interpolation denominator");
+  s.state = 2;
+}
+
+// ---------------------------------------------------------------- cycle
+
+namespace {
+
+template <typename T>
+const PartDesc<T> *desc_of(const Level &V);
+template <>
+const PartDesc<double> *desc_of<double>(const Level &V) { return V.d_desc64; }
+template <>
+const PartDesc<float> *desc_of<float>(const Level &V) { return V.d_desc32; }
+
+template <typename T>
+CouplingDev<T> coupling_of(const Level &V);
+template <>
+CouplingDev<double> coupling_of<double>(const Level &V) {
+  return {(int)V.urow.size(), (int64_t)V.ucol.size(), V.d_urow, V.d_uptr, V.d_ucol, V.d_uval64, V.d_uscale64};
+}
+template <>
+CouplingDev<float> coupling_of<float>(const Level &V) {
+  return {(int)V.urow.size(), (int64_t)V.ucol.size(), V.d_urow, V.d_uptr, V.d_ucol, V.d_uval32, V.d_uscale32};
+}
+
+// One V(1,1) cycle from level 0's vb into level 0's vt (all levels in T; the
+// coarsest level runs in FP64).
+template <typename T>
+void run_cycle_t(Solver &s, int lg) {
+  hipStream_t st = s.stream;
+  const int L = (int)s.lv.size();
+  const int np = (int)s.lv[0].parts.size();
+  for (int l = 0; l + 1 < L; ++l) {
+    Level &V = s.lv[l];
+    const PartDesc<T> *d = desc_of<T>(V);
+    T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
+    launch_smooth_zero<T>(d, np, V.maxcell, lg, b, x, st);
+    launch_stencil<T>(MODE_RESID, d, np, V.maxcell, lg, x, b, t, st);
+    launch_ufix<T>(MODE_RESID, coupling_of<T>(V), lg, x, t, st);
+    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
+  }
+  Level &C = s.lv[L - 1];
+  if (sizeof(T) == sizeof(float))
+    launch_coarse_mixed(C.d_desc64, np, C.maxcell, lg, (const float *)C.vb, (float *)C.vt, st);
+  else
+    launch_smooth_zero<double>(C.d_desc64, np, C.maxcell, lg, (const double *)C.vb, (double *)C.vt, st);
+  for (int l = L - 2; l >= 0; --l) {
+    Level &V = s.lv[l];
+    const PartDesc<T> *d = desc_of<T>(V);
+    T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
+    launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[l + 1].vt, x, st);
+    launch_stencil<T>(MODE_JACOBI, d, np, V.maxcell, lg, x, b, t, st);
+    launch_ufix<T>(MODE_JACOBI, coupling_of<T>(V), lg, x, t, st);
+  }
+}
+
+// z = B r on the solver's PCG buffers s.r -> s.z
+void run_precond(Solver &s, int lg) {
+  const int64_t nel = s.lv[0].N << lg;
+  if (s.prm.cycle_precision == SSAMG_FP32) {
+    launch_cast_d2f(s.r, (float *)s.lv[0].vb, nel, s.stream);
+    run_cycle_t<float>(s, lg);
+    launch_cast_f2d((const float *)s.lv[0].vt, s.z, nel, s.stream);
+  } else {
+    run_cycle_t<double>(s, lg);
+  }
+}
+
+void precond(Solver &s, int lg) {
+  if (!s.prm.use_graph) {
+    run_precond(s, lg);
+    return;
+  }
+  if (!s.graph_exec || s.graph_nrhs != (1 << lg)) {
+    if (s.graph_exec) (void)hipGraphExecDestroy(s.graph_exec);
+    if (s.graph) (void)hipGraphDestroy(s.graph);
+    s.graph_exec = nullptr;
+    s.graph = nullptr;
+    SSAMG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
+    run_precond(s, lg);
+    hipGraph_t g = nullptr;
+    SSAMG_HIP(hipStreamEndCapture(s.stream, &g));
+    s.graph = g;
+    SSAMG_HIP(hipGraphInstantiate(&s.graph_exec, g, nullptr, nullptr, 0));
+    s.graph_nrhs = 1 << lg;
+  }
+  SSAMG_HIP(hipGraphLaunch(s.graph_exec, s.stream));
+}
+
+void apply_A0(Solver &s, int lg, const double *x, double *y) {
+  Level &V = s.lv[0];
+  launch_stencil<double>(MODE_APPLY, V.d_desc64, (int)V.parts.size(), V.maxcell, lg, x, nullptr, y, s.stream);
+  launch_ufix<double>(MODE_APPLY, coupling_of<double>(V), lg, x, y, s.stream);
+}
+
+}  // namespace
+
+void apply_level(Solver &s, int level, const double *x, double *y) {
+  Level &V = s.lv[level];
+  launch_stencil<double>(MODE_APPLY, V.d_desc64, (int)V.parts.size(), V.maxcell, 0, x, nullptr, y, s.stream);
+  launch_ufix<double>(MODE_APPLY, coupling_of<double>(V), 0, x, y, s.stream);
+  SSAMG_HIP(hipGetLastError());
+  SSAMG_HIP(hipStreamSynchronize(s.stream));
+}
+
+void apply_precond(Solver &s, const double *r, double *z) {
+  const int64_t N = s.lv[0].N;
+  launch_copy(r, s.r, N, s.stream);
+  precond(s, 0);
+  launch_copy(s.z, z, N, s.stream);
+  SSAMG_HIP(hipGetLastError());
+  SSAMG_HIP(hipStreamSynchronize(s.stream));
+}
+
+// ---------------------------------------------------------------- PCG
+
+ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_info *info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = s.stream;
+  int lg = 0;
+  while ((1 << lg) < nrhs) ++lg;
+  const int64_t nel = s.lv[0].N << lg;
+  const bool flexible = s.prm.cycle_precision == SSAMG_FP32;
+  double *h = s.h_pin;   // [kScalSlots][kMaxRhs] mirror
+  std::vector<int> act(kMaxRhs, 0), iters(nrhs, 0), conv(nrhs, 0);
+  std::vector<double> bb(nrhs), relres(nrhs, 0.0);
+
+  launch_fill(x, 0.0, nel, st);
+  launch_copy(b, s.r, nel, st);
+  launch_dot(b, b, nel, lg, s.partial, s.scal, S_BB, 0, st);
+  SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipStreamSynchronize(st));
+  int nact = 0;
+  for (int k = 0; k < nrhs; ++k) {
+    bb[k] = h[S_BB * kMaxRhs + k];
+    if (!std::isfinite(bb[k])) throw Error(SSAMG_ERR_NUMERIC, "non-finite right-hand side");
+    act[k] = bb[k] > 0.0;
+    conv[k] = !act[k];
+    nact += act[k];
+  }
+  SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
+  if (nact > 0) {
+    precond(s, lg);
+    launch_copy(s.z, s.p, nel, st);
+    launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 0, st);
+  }
+  const double tol = s.prm.tol;
+  for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
+    apply_A0(s, lg, s.p, s.q);
+    launch_dot(s.p, s.q, nel, lg, s.partial, s.scal, S_PQ, 0, st);
+    launch_pcg_xr(nel, lg, s.scal, s.active, x, s.r, s.p, s.q, s.partial, s.scal, st);
+    SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    SSAMG_HIP(hipStreamSynchronize(st));
+    bool changed = false;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!act[k]) continue;
+      const double pq = h[S_PQ * kMaxRhs + k], rr = h[S_RR * kMaxRhs + k];
+      if (!(pq > 0.0) || !std::isfinite(pq)) throw Error(SSAMG_ERR_NUMERIC, "PCG breakdown: p^T A p <= 0");
+      if (!std::isfinite(rr)) throw Error(SSAMG_ERR_NUMERIC, "non-finite residual");
+      iters[k] = it;
+      relres[k] = std::sqrt(rr / bb[k]);
+      if (relres[k] < tol) {
+        act[k] = 0;
+        conv[k] = 1;
+        --nact;
+        changed = true;
+      }
+    }
+    if (changed)
+      SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
+    if (nact == 0 || it == s.prm.max_iter) break;
+    precond(s, lg);
+    launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 1, st);
+    if (flexible) launch_dot(s.z, s.q, nel, lg, s.partial, s.scal, S_ZQ, 0, st);
+    launch_pcg_p(nel, lg, s.scal, s.active, flexible ? 1 : 0, s.z, s.p, st);
+  }
+  // true residual
+  apply_A0(s, lg, x, s.q);
+  launch_resid_norm(b, s.q, nel, lg, s.partial, s.scal, S_TR, st);
+  SSAMG_HIP(hipGetLastError());
+  SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipStreamSynchronize(st));
+  const auto t1 = std::chrono::steady_clock::now();
+  bool all = true;
+  for (int k = 0; k < nrhs; ++k) all = all && conv[k];
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->nrhs = nrhs;
+    for (int k = 0; k < nrhs; ++k) {
+      info->iters[k] = iters[k];
+      info->relres[k] = relres[k];
+      info->true_relres[k] = bb[k] > 0.0 ? std::sqrt(h[S_TR * kMaxRhs + k] / bb[k]) : 0.0;
+      info->converged[k] = conv[k];
+    }
+    info->t_solve = std::chrono::duration<double>(t1 - t0).count();
+  }
+  return all ? SSAMG_OK : SSAMG_NOT_CONVERGED;
+}
+
+}  // namespace ssamg

@@ -1,0 +1,267 @@
+// Internal declarations of the SSAMG library: host-side hierarchy objects,
+// the device-side per-part descriptors read by every kernel, and the kernel
+// launchers.  Not part of the ABI (include/ssamg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ssamg.h"
+
+namespace ssamg {
+
+struct Error : std::runtime_error {
+  ssamg_status code;
+  Error(ssamg_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define SSAMG_HIP(call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::ssamg::Error(SSAMG_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxEnt = 27;      // stencils live in the 27-point neighbourhood
+constexpr int kBlock = 256;      // threads per block of every grid-over-cells kernel
+constexpr int kRedBlocks = 512;  // fixed grid of the deterministic reductions
+constexpr int kMaxRhs = 32;
+
+// Packed stencil offset: (dx+1) | (dy+1) << 2 | (dz+1) << 4.
+inline int pack_off(int dx, int dy, int dz) { return (dx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4); }
+
+// One part at one level, as seen by the kernels (lives in device memory; every
+// kernel indexes it with blockIdx.y, so its fields are wave-uniform).
+template <typename T>
+struct PartDesc {
+  int n[3];            // box extents
+  int nent;            // stencil entries
+  int center;          // index of (0,0,0) in the stencil
+  int dstar;           // semicoarsening direction to the next level, -1: identity
+  int faces;           // bit f set: face f (-x,+x,-y,+y,-z,+z) is a part boundary
+  int fn[3];           // F-box extents (cells odd along dstar)
+  int cn[3];           // coarse box extents
+  int pad0;
+  long long off;       // first cell of the part in the level vector
+  long long ncell;
+  long long coff;      // first cell of the part in the next level vector
+  long long cncell;
+  long long nf;        // cells of the F-box
+  T omega;             // relaxation weight
+  const T *coef;       // [nent][ncell]
+  const T *wm;         // [nf] weight toward the -dstar coarse neighbour
+  const T *wp;         // [nf] weight toward the +dstar coarse neighbour
+  int lin[kMaxEnt];    // dx + nx*(dy + ny*dz)
+  int code[kMaxEnt];   // pack_off(dx, dy, dz)
+};
+
+// Coupling matrix U of one level, compressed rows (only rows with entries).
+template <typename T>
+struct CouplingDev {
+  int nrow = 0;
+  int64_t nnz = 0;
+  const int *row = nullptr;     // cell id of each stored row
+  const int *ptr = nullptr;     // [nrow + 1]
+  const int *col = nullptr;     // [nnz] cell ids
+  const T *val = nullptr;       // [nnz]
+  const T *scale = nullptr;     // [nrow] omega_p / a_ii of the row's cell
+};
+
+// ------------------------------------------------------------------ problem
+
+struct Problem {
+  int ndim = 3, nparts = 0;
+  std::vector<std::array<int, 3>> dims;
+  std::vector<std::array<int, 3>> origin;
+  std::vector<int> has_origin;
+  std::vector<std::array<int, 6>> faces;
+  std::vector<std::vector<std::array<int, 3>>> stencil;
+  std::vector<int> center;
+  std::vector<double *> coef;        // device [nent][ncell] per part, problem-owned
+  std::vector<int> coef_set;
+  // couplings, canonical compressed-row CSR (host copy + device copy)
+  std::vector<int> urow, uptr, ucol;
+  std::vector<double> uval_host;
+  int *d_urow = nullptr, *d_uptr = nullptr, *d_ucol = nullptr;
+  double *d_uval = nullptr;
+  bool coupling_set = false;
+  // finite-volume description of the last fv_assemble
+  int fv_stencil = 0;
+  double *d_kappa = nullptr;
+  double *d_aniso = nullptr;
+  int *d_ucode = nullptr;            // per coupling entry: offset code | p_i << 5 | p_j << 18
+  int *d_geom = nullptr;             // per part: origin[3], dims[3], offset
+  int64_t ncell_total() const;
+  std::vector<int64_t> offsets() const;
+  void free_device();
+  ~Problem() { free_device(); }
+};
+
+// ------------------------------------------------------------------ hierarchy
+
+struct PartLevel {
+  std::array<int, 3> n{}, fn{}, cn{};
+  int64_t off = 0, ncell = 0, coff = 0, cncell = 0, nf = 0;
+  int dstar = -1;
+  double omega = 0.0;
+  int faces = 0;
+  std::vector<std::array<int, 3>> pat;
+  int center = 0;
+  double *coef64 = nullptr;
+  float *coef32 = nullptr;
+  int64_t wofs = 0;                  // offset of wm in the level weight buffer (wp at +nf)
+  // Galerkin table toward the next level (host + device)
+  std::vector<int> rap_start, rap_code;
+  int *d_rap_start = nullptr, *d_rap_code = nullptr;
+};
+
+struct Level {
+  std::vector<PartLevel> parts;
+  int64_t N = 0;
+  int maxcell = 0, maxcoarse = 0, maxf = 0;
+  // couplings (compressed rows), host structure
+  std::vector<int> urow, uptr, ucol, urow_part;
+  int *d_urow = nullptr, *d_uptr = nullptr, *d_ucol = nullptr, *d_urow_part = nullptr;
+  double *d_uval64 = nullptr, *d_uscale64 = nullptr;
+  float *d_uval32 = nullptr, *d_uscale32 = nullptr;
+  // recipe of this level's U as P^T U P from the previous level
+  std::vector<int> uc_start, uc_k, uc_a, uc_b;
+  int *d_uc_start = nullptr, *d_uc_k = nullptr, *d_uc_a = nullptr, *d_uc_b = nullptr;
+  // interpolation weights of all parts toward the next level
+  int64_t nw = 0;
+  double *d_w64 = nullptr;
+  float *d_w32 = nullptr;
+  PartDesc<double> *d_desc64 = nullptr;
+  PartDesc<float> *d_desc32 = nullptr;
+  struct RapDesc *d_rapdesc = nullptr;
+  // V-cycle vectors in the cycle precision: [N][max_nrhs]
+  void *vb = nullptr, *vx = nullptr, *vt = nullptr;
+  bool cycle32 = false;              // this level's cycle runs in FP32
+};
+
+struct Solver {
+  Problem *prob = nullptr;
+  ssamg_params prm{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
+  std::vector<Level> lv;
+  std::vector<double> cd;            // direction sums c[p][d]
+  // workspace
+  size_t ws_bytes = 0;
+  void *ws = nullptr;
+  bool ws_owned = false;
+  // PCG vectors (FP64, [N0][max_nrhs])
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *partial = nullptr;         // [kRedBlocks][kMaxRhs]
+  double *scal = nullptr;            // [kScalSlots][kMaxRhs]
+  int *active = nullptr;             // [kMaxRhs]
+  int *flag = nullptr;               // device error flag
+  double *h_pin = nullptr;           // pinned host mirror of a few scalar slots
+  // graph of one V-cycle
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_nrhs = 0;
+  ~Solver();
+};
+
+void setup_symbolic(Solver &s);
+void setup_numeric(Solver &s, void *ws, size_t bytes);
+void apply_level(Solver &s, int level, const double *x, double *y);
+void apply_precond(Solver &s, const double *r, double *z);
+ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_info *info);
+
+enum ScalSlot { S_RZ = 0, S_RZN, S_PQ, S_RR, S_ZQ, S_BB, S_TR, kScalSlots };
+
+// ------------------------------------------------------------------ launchers
+
+// one part's box + stencil, passed by value to the per-part setup kernels
+struct BoxStencil {
+  int n[3];
+  int nent;
+  int center;
+  int pad;
+  long long ncell;
+  int code[kMaxEnt];
+  double *coef;
+};
+
+// per-part Galerkin table of one level (device array indexed by part)
+struct RapDesc {
+  double *out;         // coarse coefficients [nent_c][cncell]
+  const int *start;    // [nent_c + 1] into code
+  const int *code;     // (r+1) | s << 2 | gsel << 7; identity parts: fine entry per coarse entry
+  int nent;            // coarse entries
+  int pad;
+};
+
+// finite-volume assembly arguments
+struct FvArgs {
+  const int *geom;     // per part: origin[3], dims[3], cell offset
+  int nparts;
+  int nent;
+  int code[kMaxEnt];   // stencil offsets, entry 0 = center
+};
+
+enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
+
+// kernels_cycle.hip
+template <typename T>
+void launch_stencil(int mode, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
+                    const T *x, const T *b, T *y, hipStream_t st);
+template <typename T>
+void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, T *y, hipStream_t st);
+template <typename T>
+void launch_smooth_zero(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *b, T *x,
+                        hipStream_t st);
+template <typename T>
+void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
+                     hipStream_t st);
+template <typename T>
+void launch_interp_add(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *xc, T *x,
+                       hipStream_t st);
+void launch_coarse_mixed(const PartDesc<double> *desc, int nparts, int maxcell, int lg, const float *b,
+                         float *x, hipStream_t st);
+void launch_cast_d2f(const double *in, float *out, int64_t n, hipStream_t st);
+void launch_cast_f2d(const float *in, double *out, int64_t n, hipStream_t st);
+void launch_fill(double *x, double v, int64_t n, hipStream_t st);
+void launch_copy(const double *in, double *out, int64_t n, hipStream_t st);
+void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *partial, double *scal,
+                int slot, int shift_rz, hipStream_t st);
+void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
+                   const double *p, const double *q, double *partial, double *scal_out,
+                   hipStream_t st);
+void launch_pcg_p(int64_t nel, int lg, const double *scal, const int *active, int flexible,
+                  const double *z, double *p, hipStream_t st);
+void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, double *partial,
+                       double *scal, int slot, hipStream_t st);
+
+// kernels_setup.hip
+void launch_normalise(const BoxStencil &bs, int *flag, hipStream_t st);
+void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *partial, double *out,
+                 hipStream_t st);
+void launch_interp_weights(const PartDesc<double> *desc, int nparts, int maxf, int *flag,
+                           hipStream_t st);
+void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
+                hipStream_t st);
+void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
+                       const double *uprev, const double *w, double *uval, hipStream_t st);
+void launch_uscale(int nrow, const int *row, const int *row_part, const PartDesc<double> *desc,
+                   double *scale, hipStream_t st);
+
+// kernels_fv.hip
+void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
+                       double *const *coef, hipStream_t st);
+void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *ucol,
+                        const int *ucode, const double *kappa, const double *aniso, double *uval,
+                        hipStream_t st);
+void launch_fv_grad(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
+                    const double *lam, const double *x, double *grad, int nrow, const int *urow,
+                    const int *uptr, const int *ucol, const int *ucode, hipStream_t st);
+
+}  // namespace ssamg

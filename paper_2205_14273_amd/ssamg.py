@@ -1,0 +1,330 @@
+"""Python binding of the SSAMG C ABI.
+
+The ``ssamg_*`` functions mirror include/ssamg.h one to one (argument
+marshalling only).  ``Problem`` and ``Solver`` wrap the handles; PyTorch
+tensors provide device memory and ``torch.cuda.current_stream()`` the HIP
+stream.  Every step of setup and solve runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import SSAMGError, check, lib  # noqa: F401
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ints(v):
+    a = (C.c_int * len(v))(*[int(x) for x in v])
+    return a
+
+
+# ---------------------------------------------------------------- raw ABI
+
+
+def ssamg_problem_create(ndim, nparts):
+    h = C.c_void_p()
+    check(lib().ssamg_problem_create(ndim, nparts, C.byref(h)))
+    return h
+
+
+def ssamg_problem_destroy(h):
+    check(lib().ssamg_problem_destroy(h))
+
+
+def ssamg_problem_set_box(h, part, lo, hi):
+    check(lib().ssamg_problem_set_box(h, part, _ints(lo), _ints(hi)))
+
+
+def ssamg_problem_set_origin(h, part, origin):
+    check(lib().ssamg_problem_set_origin(h, part, _ints(origin)))
+
+
+def ssamg_problem_set_face(h, part, face, kind):
+    check(lib().ssamg_problem_set_face(h, part, face, kind))
+
+
+def ssamg_problem_set_stencil(h, part, offsets):
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1))
+    check(lib().ssamg_problem_set_stencil(h, part, len(off) // 3, _ints(off)))
+
+
+def ssamg_problem_set_coeffs(h, part, vals, constant=0):
+    """vals: a CUDA float64 tensor (device) or a numpy float64 array (host)."""
+    if isinstance(vals, torch.Tensor):
+        t = vals.contiguous()
+        where = L.MEM_DEVICE if t.is_cuda else L.MEM_HOST
+        check(lib().ssamg_problem_set_coeffs(h, part, _ptr(t), where, constant))
+    else:
+        a = np.ascontiguousarray(vals, dtype=np.float64)
+        check(lib().ssamg_problem_set_coeffs(h, part, a.ctypes.data_as(C.c_void_p), L.MEM_HOST,
+                                             constant))
+
+
+def ssamg_problem_set_coupling(h, rows, cols, vals):
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    check(lib().ssamg_problem_set_coupling(h, len(r), r.ctypes.data_as(L.PI64),
+                                           c.ctypes.data_as(L.PI64), v.ctypes.data_as(L.PD)))
+
+
+def ssamg_problem_fv_assemble(h, kappa, aniso, stencil):
+    a = np.ascontiguousarray(aniso, dtype=np.float64)
+    check(lib().ssamg_problem_fv_assemble(h, _ptr(kappa), a.ctypes.data_as(L.PD), stencil, _stream()))
+
+
+def ssamg_problem_fv_grad(h, lam, x, grad):
+    check(lib().ssamg_problem_fv_grad(h, _ptr(lam), _ptr(x), _ptr(grad), _stream()))
+
+
+def ssamg_problem_num_cells(h):
+    n = C.c_int64()
+    check(lib().ssamg_problem_num_cells(h, C.byref(n)))
+    return n.value
+
+
+def ssamg_params_default():
+    p = L.ssamg_params()
+    check(lib().ssamg_params_default(C.byref(p)))
+    return p
+
+
+def ssamg_solver_create(prob, params, stream=None):
+    h = C.c_void_p()
+    check(lib().ssamg_solver_create(prob, C.byref(params), stream if stream is not None else _stream(),
+                                    C.byref(h)))
+    return h
+
+
+def ssamg_solver_destroy(h):
+    check(lib().ssamg_solver_destroy(h))
+
+
+def ssamg_setup_symbolic(h):
+    check(lib().ssamg_setup_symbolic(h))
+
+
+def ssamg_workspace_bytes(h):
+    n = C.c_size_t()
+    check(lib().ssamg_workspace_bytes(h, C.byref(n)))
+    return n.value
+
+
+def ssamg_setup_numeric(h, ws=None):
+    if ws is None:
+        check(lib().ssamg_setup_numeric(h, None, 0))
+    else:
+        check(lib().ssamg_setup_numeric(h, _ptr(ws), ws.numel() * ws.element_size()))
+
+
+def ssamg_solve(h, nrhs, b, x):
+    info = L.ssamg_info()
+    st = lib().ssamg_solve(h, nrhs, _ptr(b), _ptr(x), C.byref(info))
+    check(st, allow_not_converged=True)
+    return st, info
+
+
+def ssamg_apply_A(h, level, x, y):
+    check(lib().ssamg_apply_A(h, level, _ptr(x), _ptr(y)))
+
+
+def ssamg_apply_precond(h, r, z):
+    check(lib().ssamg_apply_precond(h, _ptr(r), _ptr(z)))
+
+
+def ssamg_num_levels(h):
+    n = C.c_int()
+    check(lib().ssamg_num_levels(h, C.byref(n)))
+    return n.value
+
+
+def ssamg_level_info(h, level, part):
+    d = L.ssamg_level_desc()
+    check(lib().ssamg_level_info(h, level, part, C.byref(d)))
+    return d
+
+
+def ssamg_direction_sums(h, nparts):
+    out = np.zeros(nparts * 3)
+    check(lib().ssamg_direction_sums(h, out.ctypes.data_as(L.PD)))
+    return out.reshape(nparts, 3)
+
+
+def ssamg_copy_stencil(h, level, part, nent, ncell):
+    out = np.zeros((nent, ncell))
+    check(lib().ssamg_copy_stencil(h, level, part, out.ctypes.data_as(L.PD)))
+    return out
+
+
+def ssamg_copy_interp(h, level, part, nf):
+    wm = np.zeros(max(nf, 1))
+    wp = np.zeros(max(nf, 1))
+    check(lib().ssamg_copy_interp(h, level, part, wm.ctypes.data_as(L.PD), wp.ctypes.data_as(L.PD)))
+    return wm[:nf], wp[:nf]
+
+
+def ssamg_coupling_nnz(h, level):
+    n = C.c_int64()
+    check(lib().ssamg_coupling_nnz(h, level, C.byref(n)))
+    return n.value
+
+
+def ssamg_copy_coupling(h, level, nrows):
+    nnz = ssamg_coupling_nnz(h, level)
+    rp = np.zeros(nrows + 1, dtype=np.int64)
+    col = np.zeros(max(nnz, 1), dtype=np.int64)
+    val = np.zeros(max(nnz, 1))
+    check(lib().ssamg_copy_coupling(h, level, rp.ctypes.data_as(L.PI64), col.ctypes.data_as(L.PI64),
+                                    val.ctypes.data_as(L.PD)))
+    return rp, col[:nnz], val[:nnz]
+
+
+# ---------------------------------------------------------------- objects
+
+
+class Problem:
+    """A semi-structured problem: one box per part (lower corner 0)."""
+
+    def __init__(self, ndim, dims, origins=None):
+        self.ndim = ndim
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.nparts = len(self.dims)
+        self.h = ssamg_problem_create(ndim, self.nparts)
+        for p, d in enumerate(self.dims):
+            ssamg_problem_set_box(self.h, p, (0, 0, 0), (d[0] - 1, d[1] - 1, d[2] - 1))
+            if origins is not None:
+                ssamg_problem_set_origin(self.h, p, origins[p])
+        self.n = ssamg_problem_num_cells(self.h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and L._lib is not None:
+            L._lib.ssamg_problem_destroy(h)
+            self.h = None
+
+    @classmethod
+    def from_fv(cls, geometry, stencil, kappa, aniso):
+        """Finite-volume problem assembled on the device from per-cell kappa."""
+        pr = cls(geometry.ndim, geometry.dims, geometry.origins)
+        pr.fv_assemble(kappa, aniso, stencil)
+        return pr
+
+    @classmethod
+    def from_raw(cls, case):
+        """Problem given as stencil arrays + inter-part couplings (host arrays)."""
+        g = case.geometry
+        pr = cls(g.ndim, g.dims)
+        for p in range(pr.nparts):
+            for f in range(6):
+                ssamg_problem_set_face(pr.h, p, f, int(case.faces[p][f]))
+            ssamg_problem_set_stencil(pr.h, p, case.stencils[p])
+            ssamg_problem_set_coeffs(pr.h, p, np.asarray(case.coeffs[p]).reshape(-1))
+        ssamg_problem_set_coupling(pr.h, case.urow, case.ucol, case.uval)
+        return pr
+
+    def fv_assemble(self, kappa, aniso, stencil):
+        if not isinstance(kappa, torch.Tensor):
+            kappa = torch.as_tensor(np.asarray(kappa, dtype=np.float64), device="cuda")
+        self._kappa = kappa.to(device="cuda", dtype=torch.float64).contiguous()
+        ssamg_problem_fv_assemble(self.h, self._kappa, aniso, stencil)
+
+    def fv_grad(self, lam, x):
+        g = torch.empty_like(x)
+        ssamg_problem_fv_grad(self.h, lam.contiguous(), x.contiguous(), g)
+        return g
+
+
+class Solver:
+    """SSAMG-preconditioned PCG on a Problem (which must outlive the solver)."""
+
+    def __init__(self, problem, **params):
+        self.problem = problem
+        self.params = ssamg_params_default()
+        for k, v in params.items():
+            if not hasattr(self.params, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(self.params, k, v)
+        self.h = ssamg_solver_create(problem.h, self.params)
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and L._lib is not None:
+            L._lib.ssamg_solver_destroy(h)
+            self.h = None
+
+    def setup(self):
+        """Symbolic + numeric setup; the workspace is a torch uint8 tensor."""
+        ssamg_setup_symbolic(self.h)
+        nbytes = ssamg_workspace_bytes(self.h)
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        ssamg_setup_numeric(self.h, self.ws)
+        self.nlevels = ssamg_num_levels(self.h)
+        return self
+
+    def setup_symbolic(self):
+        ssamg_setup_symbolic(self.h)
+        self.nlevels = ssamg_num_levels(self.h)
+
+    def setup_numeric(self):
+        nbytes = ssamg_workspace_bytes(self.h)
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        ssamg_setup_numeric(self.h, self.ws)
+
+    def solve(self, b, x=None):
+        """b: CUDA float64 [N] or [N, nrhs] (rhs fastest).  Returns (x, status, info)."""
+        b = b.contiguous()
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        if x is None:
+            x = torch.empty_like(b)
+        st, info = ssamg_solve(self.h, nrhs, b, x)
+        return x, st, info
+
+    def apply_A(self, level, x):
+        y = torch.empty_like(x)
+        ssamg_apply_A(self.h, level, x.contiguous(), y)
+        return y
+
+    def apply_precond(self, r):
+        z = torch.empty_like(r)
+        ssamg_apply_precond(self.h, r.contiguous(), z)
+        return z
+
+    def level_info(self, level, part):
+        d = ssamg_level_info(self.h, level, part)
+        return {"dims": tuple(d.dims), "offset": d.offset, "dstar": d.dstar, "omega": d.omega,
+                "nent": d.nent, "pattern": np.array([[d.pattern[e][a] for a in range(3)]
+                                                      for e in range(d.nent)], dtype=np.int32),
+                "fdims": tuple(d.fdims)}
+
+    def level_cells(self, level):
+        return sum(int(np.prod(self.level_info(level, p)["dims"])) for p in range(self.problem.nparts))
+
+    def direction_sums(self):
+        return ssamg_direction_sums(self.h, self.problem.nparts)
+
+    def copy_stencil(self, level, part):
+        li = self.level_info(level, part)
+        return ssamg_copy_stencil(self.h, level, part, li["nent"], int(np.prod(li["dims"])))
+
+    def copy_interp(self, level, part):
+        li = self.level_info(level, part)
+        return ssamg_copy_interp(self.h, level, part, int(np.prod(li["fdims"])) if li["dstar"] >= 0 else 0)
+
+    def copy_coupling(self, level):
+        return ssamg_copy_coupling(self.h, level, self.level_cells(level))

@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Integer results (levels, d*, boxes, stencil patterns, coupling structure) must
+match bit for bit; coarse operators, weights and couplings to a row-relative
+1e-12; solves to a relative residual of 1e-8 with the oracle's iteration count
++-1.  Sizes span several 256-cell tiles with ragged tails and odd extents.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import assemble, ssamg as O
+from tests.parity_util import (compare_hierarchy, gpu_fv, gpu_raw, oracle_fv, oracle_raw,
+                               row_rel_err)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "c1_16": lambda: W.c1(16),
+    "c2_13": lambda: W.c2(13),
+    "c2_20": lambda: W.c2(20),
+    "c3_9": lambda: W.c3(9),
+    "c4_12": lambda: W.c4(12, nrhs=1),
+    "c5_11": lambda: W.c5(11),
+}
+
+
+def _cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
+
+
+def _print_case(name):
+    print(f"[gpu parity] case {name}", flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_parity(name):
+    _print_case(name)
+    case = CASES[name]()
+    h = oracle_fv(case)
+    pr, s = gpu_fv(case)
+    # direction sums of Section 3.1 (device reduction vs correctly rounded sums)
+    cd = s.direction_sums()
+    assert np.allclose(cd, h.cd, rtol=1e-12, atol=0)
+    compare_hierarchy(h, s, case.geometry.nparts)
+
+
+@pytest.mark.parametrize("name", ["c1_16", "c2_20", "c3_9", "c5_11"])
+def test_matvec_parity_every_level(name):
+    _print_case(name)
+    case = CASES[name]()
+    h = oracle_fv(case)
+    pr, s = gpu_fv(case)
+    rng = np.random.default_rng(7)
+    for l, lev in enumerate(h.levels):
+        x = rng.standard_normal(lev.n)
+        y = s.apply_A(l, _cuda(x)).cpu().numpy()
+        want = lev.A @ x
+        scale = np.abs(lev.A) @ np.abs(x)
+        assert np.max(np.abs(y - want) / np.maximum(scale, 1e-300)) <= 1e-13, l
+
+
+@pytest.mark.parametrize("name", ["c1_16", "c2_20", "c3_9", "c5_11"])
+def test_vcycle_parity(name):
+    _print_case(name)
+    case = CASES[name]()
+    h = oracle_fv(case)
+    pr, s = gpu_fv(case)
+    r = np.random.default_rng(3).uniform(-1, 1, h.levels[0].n)
+    z = s.apply_precond(_cuda(r)).cpu().numpy()
+    want = O.vcycle(h, r)
+    assert np.linalg.norm(z - want) <= 1e-11 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_parity(name):
+    _print_case(name)
+    case = CASES[name]()
+    h = oracle_fv(case)
+    b = case.b if case.b.ndim == 1 else case.b[0]
+    ref = O.solve(h, b, tol=1e-8)
+    pr, s = gpu_fv(case)
+    x, st, info = s.solve(_cuda(b))
+    assert st == 0
+    assert abs(info.iters[0] - ref.iters) <= 1, (info.iters[0], ref.iters)
+    assert info.relres[0] < 1e-8 and info.true_relres[0] < 1e-8
+    xn = x.cpu().numpy()
+    tr = np.linalg.norm(b - h.levels[0].A @ xn) / np.linalg.norm(b)
+    assert tr < 1e-8
+    assert np.linalg.norm(xn - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_solve_matches_dense_direct():
+    case = W.c3(5)
+    A, _ = assemble.assemble_fv(case.geometry, 27, case.kappa, case.aniso)
+    pr, s = gpu_fv(case, tol=1e-12)
+    x, st, info = s.solve(_cuda(case.b))
+    xd = sla.solve(A.toarray(), case.b, assume_a="pos")
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("seed,kind", [(1, 7), (2, 27), (3, 27)])
+def test_raw_problem_parity(seed, kind):
+    g = W.Geometry(3, [(9, 7, 5), (6, 7, 5), (5, 4, 6)], [(0, 0, 0), (9, 0, 0), (9, 7, 0)])
+    case = W.random_link_case(seed, g, kind, junk_outside=True)
+    h = oracle_raw(case)
+    pr, s = gpu_raw(case)
+    compare_hierarchy(h, s, g.nparts)
+    ref = O.solve(h, case.b, tol=1e-8)
+    x, st, info = s.solve(_cuda(case.b))
+    assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
+
+
+def test_raw_2d_problem_parity():
+    g = W.Geometry(2, [(17, 11, 1), (9, 11, 1)], [(0, 0, 0), (17, 0, 0)])
+    case = W.random_link_case(5, g, 9)
+    h = oracle_raw(case)
+    pr, s = gpu_raw(case)
+    compare_hierarchy(h, s, g.nparts)
+    ref = O.solve(h, case.b, tol=1e-8)
+    x, st, info = s.solve(_cuda(case.b))
+    assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
+
+
+def test_max_levels_and_min_coarse_size():
+    case = W.c2(12)
+    for kw in ({"max_levels": 4}, {"min_coarse_size": 300}):
+        h = oracle_fv(case, **kw)
+        pr, s = gpu_fv(case, **kw)
+        compare_hierarchy(h, s, 4)
+        ref = O.solve(h, case.b, tol=1e-8)
+        x, st, info = s.solve(_cuda(case.b))
+        assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
+
+
+def test_single_cell_parts():
+    # degenerate: every part is one cell, the hierarchy has one level
+    g = W.Geometry(3, [(1, 1, 1)] * 3, [(0, 0, 0), (1, 0, 0), (2, 0, 0)])
+    case = W.FVCase("t", g, 7, np.array([1.0, 2.0, 3.0]), np.ones((3, 3)), np.array([1.0, -1.0, 0.5]))
+    h = oracle_fv(case)
+    pr, s = gpu_fv(case)
+    assert s.nlevels == 1 == h.nlevels
+    ref = O.solve(h, case.b, tol=1e-10)
+    x, st, info = s.solve(_cuda(case.b))
+    assert np.allclose(x.cpu().numpy(), ref.x, rtol=1e-12)
+
+
+def test_zero_rhs():
+    pr, s = gpu_fv(W.c1(8))
+    x, st, info = s.solve(torch.zeros(512, dtype=torch.float64, device="cuda"))
+    assert st == 0 and info.iters[0] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_not_converged_status():
+    pr, s = gpu_fv(W.c2(12), max_iter=2)
+    x, st, info = s.solve(_cuda(W.c2(12).b))
+    assert st == 1 and info.iters[0] == 2 and not info.converged[0]
+
+
+def test_errors_are_reported():
+    from paper_2205_14273_amd import ssamg as B
+    from paper_2205_14273_amd._lib import SSAMGError
+    pr = B.Problem(3, [(4, 4, 4)])
+    B.ssamg_problem_set_stencil(pr.h, 0, W.stencil_offsets(7))
+    bad = np.ones((7, 64))
+    bad[0, 5] = -1.0      # nonpositive diagonal
+    with pytest.raises(SSAMGError) as e:
+        B.ssamg_problem_set_coeffs(pr.h, 0, bad)
+    assert e.value.status == -4
+    s = B.Solver(pr)
+    with pytest.raises(SSAMGError) as e:
+        B.ssamg_solve(s.h, 1, torch.zeros(64, dtype=torch.float64, device="cuda"),
+                      torch.zeros(64, dtype=torch.float64, device="cuda"))
+    assert e.value.status == -2
+    with pytest.raises(SSAMGError) as e:
+        B.ssamg_problem_set_coupling(pr.h, [0], [1], [1.0])   # same part
+    assert e.value.status == -1
+
+
+def test_nan_rhs_is_an_error():
+    from paper_2205_14273_amd._lib import SSAMGError
+    pr, s = gpu_fv(W.c1(6))
+    b = torch.ones(216, dtype=torch.float64, device="cuda")
+    b[3] = float("nan")
+    with pytest.raises(SSAMGError) as e:
+        s.solve(b)
+    assert e.value.status == -4
+
+
+def test_repeatable_bitwise():
+    case = W.c3(7)
+    pr, s = gpu_fv(case)
+    x1, _, i1 = s.solve(_cuda(case.b))
+    x2, _, i2 = s.solve(_cuda(case.b))
+    assert torch.equal(x1, x2) and i1.iters[0] == i2.iters[0]
+
+
+def test_graph_and_eager_agree():
+    case = W.c2(14)
+    pr, s1 = gpu_fv(case, use_graph=1)
+    _, s2 = gpu_fv(case, use_graph=0)
+    b = _cuda(case.b)
+    for _ in range(3):   # replay the captured cycle several times with eager work between
+        z1 = s1.apply_precond(b)
+        z2 = s2.apply_precond(b)
+        torch.cuda.synchronize()
+        assert torch.equal(z1, z2)
