@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""SSAMG benchmark on one MI355X: seconds of setup + solve to a 1e-8 relative
+residual, FP32 V-cycle inside FP64 PCG (the timed step) next to the FP64 cycle,
+the roofline of the dominant kernel, and the CPU oracle as baseline.
+
+A step is one pass of the whole hot path over one synthetic input already
+resident in HBM: finite-volume assembly from kappa, symbolic + numeric setup
+(metric, Algorithm 1, interpolation, Galerkin products, FP32 copies) and the
+preconditioned CG solve.  Prints exactly one JSON line on stdout; progress goes
+to stderr.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SSAMG setup+solve sec to 1e-8 rel residual (FP64 vs FP32 V-cycle); HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+DESCR = {
+    "c1": "1 part 16^3, 7-point Laplacian, fixed omega 2/3",
+    "c2": "4 parts of 64^3 along x, 7-point diffusion, anisotropy 100:1:1 strong x,y,z,x",
+    "c3": "8 parts of 128^3 in 2x2x2, 27-point, log-normal kappa (sigma 2), 1e4 part jumps",
+    "c4": "2 parts of 96^3 along x, 7-point, anisotropy 10:1:1, 32 right-hand sides",
+    "c5": "3 parts of 64^3 along x, 7-point, kappa = exp(N(0,1)), adjoint gradient",
+}
+
+# finest-level kernel kinds the library can time with HIP events, and the
+# kernel names rocprofv3 reports for them in a mixed-precision cycle
+PROBES = {
+    "matvec": (0, "k_stencil<double, 0, double, double, 1>"),
+    "smooth0": (1, "k_smooth_zero<float, double, 1>"),
+    "resid0": (2, "k_stencil<float, 1, double, float, 1>"),
+    "restrict0": (3, "k_restrict<float>"),
+    "interp0": (4, "k_interp_add<float>"),
+    "jacobi0": (5, "k_stencil<float, 2, double, double, 1>"),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2205_14273_amd", "csrc"))):
+        if f.endswith(".hip"):
+            with open(os.path.join(ROOT, "paper_2205_14273_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(config, probe):
+    """HBM bytes per launch measured with rocprofv3 --pmc for this kernel, if the
+    stored measurement was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}_{probe}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(DESCR))
+    ap.add_argument("--m", type=int, default=None, help="box size override (smaller runs)")
+    ap.add_argument("--probe", default="jacobi0", choices=sorted(PROBES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2205_14273_amd import ssamg as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    mk = W.CONFIGS[args.config]
+    case = mk(args.m) if args.m else mk()
+    g = case.geometry
+    N = g.n
+    nrhs = case.nrhs
+    log(f"config {args.config} N={N} nrhs={nrhs}")
+    kappa = torch.as_tensor(case.kappa, device=dev)
+    if nrhs == 1:
+        b = torch.as_tensor(case.b, device=dev)
+    else:
+        b = torch.as_tensor(np.ascontiguousarray(case.b.T), device=dev)   # [N][nrhs]
+    aniso = case.aniso
+
+    def make_solver(precision):
+        pr = B.Problem(g.ndim, g.dims, g.origins)
+        params = dict(cycle_precision=precision, max_nrhs=nrhs, tol=case.tol,
+                      max_iter=case.max_iter)
+        if case.omega > 0:
+            params["omega"] = case.omega
+        pr.fv_assemble(kappa, aniso, case.stencil)
+        s = B.Solver(pr, **params)
+        return pr, s
+
+    def step(pr, s, x):
+        t0 = time.perf_counter()
+        pr.fv_assemble(kappa, aniso, case.stencil)
+        t1 = time.perf_counter()
+        s.setup()
+        t2 = time.perf_counter()
+        x, st, info = s.solve(b, x)
+        t3 = time.perf_counter()
+        if st != 0:
+            raise RuntimeError(f"solve did not converge: status {st}")
+        return x, info, (t1 - t0, t2 - t1, t3 - t2)
+
+    def run(precision, steps, warmup, probe_kind=None):
+        pr, s = make_solver(precision)
+        x = torch.empty_like(b)
+        for _ in range(warmup):
+            x, info, _ = step(pr, s, x)
+        if probe_kind is not None:
+            B.ssamg_probe_set(s.h, probe_kind)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phases = []
+        for k in range(steps):
+            x, info, ph = step(pr, s, x)
+            phases.append(ph)
+            log(f"  {'fp32' if precision else 'fp64'} cycle step {k}: assemble {ph[0]*1e3:.2f} ms, "
+                f"setup {ph[1]*1e3:.2f} ms, solve {ph[2]*1e3:.2f} ms, iters {info.iters[0]}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        probe = B.ssamg_probe_read(s.h) if probe_kind is not None else None
+        ph = np.median(np.asarray(phases), axis=0)
+        its = [info.iters[k] for k in range(nrhs)]
+        res = {"ms_per_step": (t1 - t0) / steps * 1e3, "assemble_s": ph[0], "setup_s": ph[1],
+               "solve_s": ph[2], "iters": its if nrhs > 1 else its[0],
+               "true_relres": max(info.true_relres[k] for k in range(nrhs)), "levels": s.nlevels}
+        return res, x, probe, s
+
+    log("timed run: FP32 V-cycle inside FP64 PCG")
+    probe_kind, probe_name = PROBES[args.probe]
+    mixed, x32, probe, s32 = run(B.L.FP32, args.steps, args.warmup, probe_kind)
+    fp64 = None
+    x64 = None
+    if not args.no_fp64:
+        log("comparison run: FP64 V-cycle")
+        fp64, x64, _, _ = run(B.L.FP64, max(1, min(args.steps, 3)), 1)
+
+    roof = None
+    if probe and probe[0] > 0:
+        launches, ms, by = probe
+        avg_s = ms / launches * 1e-3
+        achieved = by / launches / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(args.config, args.probe),
+                "kernel": probe_name, "launches": launches,
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "alg_bytes_per_launch": by / launches}
+
+    cpu = None
+    err = {}
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host cores")
+        from oracle import assemble, ssamg as O
+        t0 = time.perf_counter()
+        scale = 1.0
+        if args.config in ("c3",) and not args.m:
+            sample_case = W.c3(32)
+            sample = "c3 recipe at 8 parts of 32^3 (262,144 cells), time scaled by the cell ratio 64"
+            scale = N / sample_case.geometry.n
+        elif args.config == "c4":
+            sample_case = case
+            sample = "full c4 problem with its first right-hand side, time scaled by 32"
+            scale = float(nrhs)
+        else:
+            sample_case = case
+            sample = f"full {args.config} workload, one step (FV assembly + setup + PCG to 1e-8), FP64"
+        sg = sample_case.geometry
+        A, _ = assemble.assemble_fv(sg, sample_case.stencil, sample_case.kappa, sample_case.aniso)
+        h = O.setup(A, sg.dims, sg.face_kinds(), [W.stencil_offsets(sample_case.stencil, sg.ndim)]
+                    * sg.nparts, sg.ndim, omega=sample_case.omega)
+        bb = sample_case.b if sample_case.b.ndim == 1 else sample_case.b[0]
+        ref = O.solve(h, bb, tol=sample_case.tol, max_iter=sample_case.max_iter)
+        t1 = time.perf_counter()
+        cpu = {"value": round((t1 - t0) * scale, 3), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": sample, "iters": ref.iters, "measured_s": round(t1 - t0, 3)}
+        log(f"  oracle: {t1 - t0:.2f} s, iters {ref.iters}")
+        if sample_case is case:
+            xo = ref.x
+            for name, xg in (("fp32_cycle", x32), ("fp64_cycle", x64)):
+                if xg is None:
+                    continue
+                xv = xg.cpu().numpy()
+                if nrhs > 1:
+                    xv = xv[:, 0]
+                err[name] = float(np.linalg.norm(xv - xo) / np.linalg.norm(xo))
+            cpu["iters_vs_gpu"] = {"oracle": ref.iters,
+                                   "gpu_fp32_cycle": mixed["iters"] if nrhs == 1 else mixed["iters"][0]}
+
+    ms = mixed["ms_per_step"]
+    line = {
+        "metric": METRIC,
+        "value": round(ms / 1e3, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {DESCR[args.config]}; FP32 V(1,1) cycle in FP64 PCG, "
+                               f"tol {case.tol}", "cells": N, "nrhs": nrhs,
+                   "levels": mixed["levels"], "iters": mixed["iters"],
+                   "assemble_s": round(mixed["assemble_s"], 6), "setup_s": round(mixed["setup_s"], 6),
+                   "solve_s": round(mixed["solve_s"], 6), "true_relres": mixed["true_relres"]},
+        "fp64_cycle": None if fp64 is None else {
+            "ms_per_step": round(fp64["ms_per_step"], 4), "setup_s": round(fp64["setup_s"], 6),
+            "solve_s": round(fp64["solve_s"], 6), "iters": fp64["iters"],
+            "true_relres": fp64["true_relres"]},
+        "err_vs_oracle": err or None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -212,6 +212,25 @@ ssamg_status ssamg_coupling_nnz(ssamg_solver s, int level, int64_t *nnz);
 ssamg_status ssamg_copy_coupling(ssamg_solver s, int level, int64_t *rowptr, int64_t *col,
                                  double *val);
 
+/* Measurement hooks: bracket every launch of one finest-level kernel kind with
+ * HIP events on the solver's stream (inside solves and preconditioner
+ * applications) and accumulate its algorithmic bytes (each array element
+ * counted once: coefficients, inputs, outputs).  kind = SSAMG_PROBE_NONE turns
+ * it off.  probe_read synchronizes, returns the launches, summed event time
+ * (ms) and summed algorithmic bytes since the last set/read, and resets them.
+ * At most 2048 launches are recorded between reads. */
+enum {
+  SSAMG_PROBE_NONE = -1,
+  SSAMG_PROBE_MATVEC = 0,     /* PCG product q = A p (FP64) */
+  SSAMG_PROBE_SMOOTH0 = 1,    /* first sweep from zero, finest level */
+  SSAMG_PROBE_RESID0 = 2,     /* residual b - S x, finest level */
+  SSAMG_PROBE_RESTRICT0 = 3,  /* restriction P^T r from the finest level */
+  SSAMG_PROBE_INTERP0 = 4,    /* x += P x_c on the finest level */
+  SSAMG_PROBE_JACOBI0 = 5     /* post-smoothing sweep, finest level */
+};
+ssamg_status ssamg_probe_set(ssamg_solver s, int kind);
+ssamg_status ssamg_probe_read(ssamg_solver s, int64_t *launches, double *total_ms, double *alg_bytes);
+
 const char *ssamg_last_error(void);
 
 #ifdef __cplusplus

@@ -30,6 +30,13 @@ COARSE_SWEEP = 0
 COARSE_DIRECT = 1
 FP64 = 0
 FP32 = 1
+PROBE_NONE = -1
+PROBE_MATVEC = 0
+PROBE_SMOOTH0 = 1
+PROBE_RESID0 = 2
+PROBE_RESTRICT0 = 3
+PROBE_INTERP0 = 4
+PROBE_JACOBI0 = 5
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_STATE",
                 -3: "ERR_UNSUPPORTED", -4: "ERR_NUMERIC", -5: "ERR_DEVICE", -6: "ERR_ALLOC"}
@@ -92,6 +99,8 @@ SIGNATURES = {
     "ssamg_copy_interp": [P, I, I, PD, PD],
     "ssamg_coupling_nnz": [P, I, PI64],
     "ssamg_copy_coupling": [P, I, PI64, PI64, PD],
+    "ssamg_probe_set": [P, I],
+    "ssamg_probe_read": [P, PI64, PD, PD],
     "ssamg_last_error": [],
 }
 

@@ -228,6 +228,22 @@ ssamg_status ssamg_copy_interp(ssamg_solver h, int level, int part, double *wm, 
   API_END
 }
 
+ssamg_status ssamg_probe_set(ssamg_solver h, int kind) {
+  API_BEGIN
+  Solver *s = S(h);
+  if (kind < SSAMG_PROBE_NONE || kind > SSAMG_PROBE_JACOBI0) throw Error(SSAMG_ERR_ARG, "bad probe kind");
+  probe_set(*s, kind);
+  API_END
+}
+
+ssamg_status ssamg_probe_read(ssamg_solver h, int64_t *launches, double *total_ms, double *alg_bytes) {
+  API_BEGIN
+  Solver *s = S(h);
+  if (!launches || !total_ms || !alg_bytes) throw Error(SSAMG_ERR_ARG, "NULL output");
+  probe_read(*s, launches, total_ms, alg_bytes);
+  API_END
+}
+
 ssamg_status ssamg_coupling_nnz(ssamg_solver h, int level, int64_t *nnz) {
   API_BEGIN
   Solver *s = S(h);

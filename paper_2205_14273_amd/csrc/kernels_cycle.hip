@@ -42,10 +42,15 @@ __device__ __forceinline__ int chunk_index() {
   return (b & 7) * (nblk >> 3) + (b >> 3);
 }
 
-template <typename T, int MODE>
+// y = S x (APPLY), r = b - S x (RESID) or x' = x + omega (b - S x) / a_C
+// (JACOBI) over every cell of every part.  T: coefficients and x; TB: b; TO:
+// output.  FINE marks the launches on the finest level (own instantiation: in
+// a mixed-precision cycle they read the FP64 PCG residual and write the FP64
+// correction directly).
+template <typename T, int MODE, typename TB, typename TO, int FINE>
 __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restrict__ desc, int lg,
                                                     const T *__restrict__ x,
-                                                    const T *__restrict__ b, T *__restrict__ y) {
+                                                    const TB *__restrict__ b, TO *__restrict__ y) {
   const PartDesc<T> &d = desc[blockIdx.y];
   const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
   if (e >= (d.ncell << lg)) return;
@@ -64,22 +69,24 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
     acc = fma(a, xv, acc);
   }
   if (MODE == MODE_APPLY) {
-    y[o] = acc;
+    y[o] = (TO)acc;
   } else if (MODE == MODE_RESID) {
-    y[o] = b[o] - acc;
+    y[o] = (TO)((T)b[o] - acc);
   } else {
     const T ac = cf[(long long)d.center * d.ncell];
-    y[o] = xp[0] + d.omega * (b[o] - acc) / ac;
+    y[o] = (TO)(xp[0] + d.omega * ((T)b[o] - acc) / ac);
   }
 }
 
-template <typename T, int MODE>
+// The couplings' share of the same three operations on the rows of U (run
+// after k_stencil; the JACOBI form reads the sweep's input x).
+template <typename T, int MODE, typename TO>
 __global__ __launch_bounds__(kBlock) void k_ufix(int nrow, const int *__restrict__ row,
                                                  const int *__restrict__ ptr,
                                                  const int *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ scale, int lg,
-                                                 const T *__restrict__ x, T *__restrict__ y) {
+                                                 const T *__restrict__ x, TO *__restrict__ y) {
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= ((long long)nrow << lg)) return;
   const int r = (int)(e >> lg);
@@ -88,22 +95,23 @@ __global__ __launch_bounds__(kBlock) void k_ufix(int nrow, const int *__restrict
   for (int q = ptr[r]; q < ptr[r + 1]; ++q) acc = fma(val[q], x[((long long)col[q] << lg) + kr], acc);
   const long long o = ((long long)row[r] << lg) + kr;
   if (MODE == MODE_APPLY)
-    y[o] += acc;
+    y[o] += (TO)acc;
   else if (MODE == MODE_RESID)
-    y[o] -= acc;
+    y[o] -= (TO)acc;
   else
-    y[o] -= scale[r] * acc;
+    y[o] -= (TO)(scale[r] * acc);
 }
 
-template <typename T>
+// x = omega D^{-1} b: the first sweep of eq:relax0 from a zero guess
+template <typename T, typename TB, int FINE>
 __global__ __launch_bounds__(kBlock) void k_smooth_zero(const PartDesc<T> *__restrict__ desc, int lg,
-                                                        const T *__restrict__ b, T *__restrict__ x) {
+                                                        const TB *__restrict__ b, T *__restrict__ x) {
   const PartDesc<T> &d = desc[blockIdx.y];
   const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
   if (e >= (d.ncell << lg)) return;
   const int c = (int)(e >> lg);
   const long long o = ((d.off + c) << lg) + (e & ((1 << lg) - 1));
-  x[o] = d.omega * b[o] / d.coef[(long long)d.center * d.ncell + c];
+  x[o] = d.omega * (T)b[o] / d.coef[(long long)d.center * d.ncell + c];
 }
 
 // Coarsest level of a mixed-precision cycle: one sweep from zero computed in
@@ -353,34 +361,42 @@ inline unsigned red_blocks(long long nel) {
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T>
-void launch_stencil(int mode, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *x,
-                    const T *b, T *y, hipStream_t st) {
+template <typename T, typename TB, typename TO>
+void launch_stencil(int mode, int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
+                    const T *x, const TB *b, TO *y, hipStream_t st) {
   dim3 grid(grid_cells(maxcell, lg), nparts);
-  if (mode == MODE_APPLY)
-    k_stencil<T, MODE_APPLY><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y);
-  else if (mode == MODE_RESID)
-    k_stencil<T, MODE_RESID><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y);
-  else
-    k_stencil<T, MODE_JACOBI><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y);
+#define SSAMG_ST(M, F) k_stencil<T, M, TB, TO, F><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y)
+  if (fine) {
+    if (mode == MODE_APPLY) SSAMG_ST(MODE_APPLY, 1);
+    else if (mode == MODE_RESID) SSAMG_ST(MODE_RESID, 1);
+    else SSAMG_ST(MODE_JACOBI, 1);
+  } else {
+    if (mode == MODE_APPLY) SSAMG_ST(MODE_APPLY, 0);
+    else if (mode == MODE_RESID) SSAMG_ST(MODE_RESID, 0);
+    else SSAMG_ST(MODE_JACOBI, 0);
+  }
+#undef SSAMG_ST
 }
 
-template <typename T>
-void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, T *y, hipStream_t st) {
+template <typename T, typename TO>
+void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, TO *y, hipStream_t st) {
   if (u.nrow == 0) return;
   dim3 grid(grid_cells(u.nrow, lg));
   if (mode == MODE_APPLY)
-    k_ufix<T, MODE_APPLY><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
+    k_ufix<T, MODE_APPLY, TO><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
   else if (mode == MODE_RESID)
-    k_ufix<T, MODE_RESID><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
+    k_ufix<T, MODE_RESID, TO><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
   else
-    k_ufix<T, MODE_JACOBI><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
+    k_ufix<T, MODE_JACOBI, TO><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
 }
 
-template <typename T>
-void launch_smooth_zero(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *b, T *x,
-                        hipStream_t st) {
-  k_smooth_zero<T><<<dim3(grid_cells(maxcell, lg), nparts), kBlock, 0, st>>>(desc, lg, b, x);
+template <typename T, typename TB>
+void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
+                        T *x, hipStream_t st) {
+  if (fine)
+    k_smooth_zero<T, TB, 1><<<dim3(grid_cells(maxcell, lg), nparts), kBlock, 0, st>>>(desc, lg, b, x);
+  else
+    k_smooth_zero<T, TB, 0><<<dim3(grid_cells(maxcell, lg), nparts), kBlock, 0, st>>>(desc, lg, b, x);
 }
 
 template <typename T>
@@ -440,18 +456,33 @@ void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, d
   k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal, slot, 0);
 }
 
-#define SSAMG_INST(T)                                                                            \
-  template void launch_stencil<T>(int, const PartDesc<T> *, int, int, int, const T *, const T *, \
-                                  T *, hipStream_t);                                             \
-  template void launch_ufix<T>(int, const CouplingDev<T> &, int, const T *, T *, hipStream_t);   \
-  template void launch_smooth_zero<T>(const PartDesc<T> *, int, int, int, const T *, T *,        \
-                                      hipStream_t);                                              \
-  template void launch_restrict<T>(const PartDesc<T> *, int, int, int, const T *, T *,           \
-                                   hipStream_t);                                                 \
-  template void launch_interp_add<T>(const PartDesc<T> *, int, int, int, const T *, T *,         \
+template void launch_stencil<double, double, double>(int, int, const PartDesc<double> *, int, int, int,
+                                                     const double *, const double *, double *, hipStream_t);
+template void launch_stencil<float, float, float>(int, int, const PartDesc<float> *, int, int, int,
+                                                  const float *, const float *, float *, hipStream_t);
+template void launch_stencil<float, double, float>(int, int, const PartDesc<float> *, int, int, int,
+                                                   const float *, const double *, float *, hipStream_t);
+template void launch_stencil<float, double, double>(int, int, const PartDesc<float> *, int, int, int,
+                                                    const float *, const double *, double *, hipStream_t);
+template void launch_ufix<double, double>(int, const CouplingDev<double> &, int, const double *, double *,
+                                          hipStream_t);
+template void launch_ufix<float, float>(int, const CouplingDev<float> &, int, const float *, float *,
+                                        hipStream_t);
+template void launch_ufix<float, double>(int, const CouplingDev<float> &, int, const float *, double *,
+                                         hipStream_t);
+template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
+                                                 const double *, double *, hipStream_t);
+template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,
+                                               float *, hipStream_t);
+template void launch_smooth_zero<float, double>(int, const PartDesc<float> *, int, int, int,
+                                                const double *, float *, hipStream_t);
+template void launch_restrict<double>(const PartDesc<double> *, int, int, int, const double *, double *,
+                                      hipStream_t);
+template void launch_restrict<float>(const PartDesc<float> *, int, int, int, const float *, float *,
                                      hipStream_t);
-SSAMG_INST(double)
-SSAMG_INST(float)
-#undef SSAMG_INST
+template void launch_interp_add<double>(const PartDesc<double> *, int, int, int, const double *, double *,
+                                        hipStream_t);
+template void launch_interp_add<float>(const PartDesc<float> *, int, int, int, const float *, float *,
+                                       hipStream_t);
 
 }  // namespace ssamg

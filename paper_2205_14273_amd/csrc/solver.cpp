@@ -294,6 +294,7 @@ Solver::~Solver() {
   if (graph) (void)hipGraphDestroy(graph);
   if (ws_owned && ws) (void)hipFree(ws);
   if (h_pin) (void)hipHostFree(h_pin);
+  for (auto e : pev) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -636,52 +637,79 @@ CouplingDev<float> coupling_of<float>(const Level &V) {
   return {(int)V.urow.size(), (int64_t)V.ucol.size(), V.d_urow, V.d_uptr, V.d_ucol, V.d_uval32, V.d_uscale32};
 }
 
-// One V(1,1) cycle from level 0's vb into level 0's vt (all levels in T; the
-// coarsest level runs in FP64).
+// Algorithmic bytes of one finest-level launch (each array element once).
+double level0_bytes(const Solver &s, int kind, int lg, size_t tc, size_t tx, size_t tb, size_t to) {
+  const Level &V = s.lv[0];
+  const double nr = (double)(1 << lg);
+  double by = 0.0;
+  for (const auto &q : V.parts) {
+    const double n = (double)q.ncell, ne = (double)q.pat.size();
+    switch (kind) {
+      case SSAMG_PROBE_MATVEC: by += n * (ne * tc + nr * (tx + to)); break;
+      case SSAMG_PROBE_SMOOTH0: by += n * (tc + nr * (tb + tx)); break;
+      case SSAMG_PROBE_RESID0:
+      case SSAMG_PROBE_JACOBI0: by += n * (ne * tc + nr * (tx + tb + to)); break;
+      case SSAMG_PROBE_RESTRICT0: by += nr * tx * (n + (double)q.cncell) + 2.0 * tc * (double)q.nf; break;
+      case SSAMG_PROBE_INTERP0: by += nr * tx * (2.0 * n + (double)q.cncell) + 2.0 * tc * (double)q.nf; break;
+      default: break;
+    }
+  }
+  return by;
+}
+
+// HIP-event bracket of one launch of the probed kernel kind
+struct Probe {
+  Solver &s;
+  int slot = -1;
+  Probe(Solver &s_, int kind, double bytes) : s(s_) {
+    if (s.probe_kind != kind || s.pev_next + 2 > s.pev.size()) return;
+    slot = (int)s.pev_next;
+    s.pev_next += 2;
+    s.probe_launches += 1;
+    s.probe_bytes += bytes;
+    SSAMG_HIP(hipEventRecord(s.pev[slot], s.stream));
+  }
+  ~Probe() {
+    if (slot >= 0) (void)hipEventRecord(s.pev[slot + 1], s.stream);
+  }
+};
+
+// Levels l >= 1 of one V(1,1) cycle: from lv[1].vb into lv[1].vt (all in T,
+// the coarsest level in FP64).  Captured in a HIP graph when use_graph is set.
 template <typename T>
-void run_cycle_t(Solver &s, int lg) {
+void run_tail(Solver &s, int lg) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
   const int np = (int)s.lv[0].parts.size();
-  for (int l = 0; l + 1 < L; ++l) {
+  for (int l = 1; l + 1 < L; ++l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
-    launch_smooth_zero<T>(d, np, V.maxcell, lg, b, x, st);
-    launch_stencil<T>(MODE_RESID, d, np, V.maxcell, lg, x, b, t, st);
-    launch_ufix<T>(MODE_RESID, coupling_of<T>(V), lg, x, t, st);
+    launch_smooth_zero<T, T>(0, d, np, V.maxcell, lg, b, x, st);
+    launch_stencil<T, T, T>(MODE_RESID, 0, d, np, V.maxcell, lg, x, b, t, st);
+    launch_ufix<T, T>(MODE_RESID, coupling_of<T>(V), lg, x, t, st);
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   Level &C = s.lv[L - 1];
   if (sizeof(T) == sizeof(float))
     launch_coarse_mixed(C.d_desc64, np, C.maxcell, lg, (const float *)C.vb, (float *)C.vt, st);
   else
-    launch_smooth_zero<double>(C.d_desc64, np, C.maxcell, lg, (const double *)C.vb, (double *)C.vt, st);
-  for (int l = L - 2; l >= 0; --l) {
+    launch_smooth_zero<double, double>(0, C.d_desc64, np, C.maxcell, lg, (const double *)C.vb,
+                                       (double *)C.vt, st);
+  for (int l = L - 2; l >= 1; --l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
     launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[l + 1].vt, x, st);
-    launch_stencil<T>(MODE_JACOBI, d, np, V.maxcell, lg, x, b, t, st);
-    launch_ufix<T>(MODE_JACOBI, coupling_of<T>(V), lg, x, t, st);
+    launch_stencil<T, T, T>(MODE_JACOBI, 0, d, np, V.maxcell, lg, x, b, t, st);
+    launch_ufix<T, T>(MODE_JACOBI, coupling_of<T>(V), lg, x, t, st);
   }
 }
 
-// z = B r on the solver's PCG buffers s.r -> s.z
-void run_precond(Solver &s, int lg) {
-  const int64_t nel = s.lv[0].N << lg;
-  if (s.prm.cycle_precision == SSAMG_FP32) {
-    launch_cast_d2f(s.r, (float *)s.lv[0].vb, nel, s.stream);
-    run_cycle_t<float>(s, lg);
-    launch_cast_f2d((const float *)s.lv[0].vt, s.z, nel, s.stream);
-  } else {
-    run_cycle_t<double>(s, lg);
-  }
-}
-
-void precond(Solver &s, int lg) {
+template <typename T>
+void tail(Solver &s, int lg) {
   if (!s.prm.use_graph) {
-    run_precond(s, lg);
+    run_tail<T>(s, lg);
     return;
   }
   if (!s.graph_exec || s.graph_nrhs != (1 << lg)) {
@@ -690,7 +718,7 @@ void precond(Solver &s, int lg) {
     s.graph_exec = nullptr;
     s.graph = nullptr;
     SSAMG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-    run_precond(s, lg);
+    run_tail<T>(s, lg);
     hipGraph_t g = nullptr;
     SSAMG_HIP(hipStreamEndCapture(s.stream, &g));
     s.graph = g;
@@ -700,20 +728,106 @@ void precond(Solver &s, int lg) {
   SSAMG_HIP(hipGraphLaunch(s.graph_exec, s.stream));
 }
 
+// z = B r: one V(1,1) cycle from s.r into s.z.  Level 0 is launched directly
+// (large kernels; in a mixed-precision cycle they read r and write z in FP64),
+// the coarser levels as one graph.
+template <typename T>
+void precond_t(Solver &s, int lg) {
+  hipStream_t st = s.stream;
+  const int L = (int)s.lv.size();
+  const int np = (int)s.lv[0].parts.size();
+  Level &V = s.lv[0];
+  const PartDesc<T> *d = desc_of<T>(V);
+  const size_t tc = sizeof(T), tx = sizeof(T);
+  T *x = (T *)V.vx, *t = (T *)V.vt;
+  if (L == 1) {
+    if (sizeof(T) == sizeof(float)) {
+      launch_cast_d2f(s.r, (float *)V.vb, V.N << lg, st);
+      launch_coarse_mixed(V.d_desc64, np, V.maxcell, lg, (const float *)V.vb, (float *)V.vt, st);
+      launch_cast_f2d((const float *)V.vt, s.z, V.N << lg, st);
+    } else {
+      launch_smooth_zero<double, double>(1, V.d_desc64, np, V.maxcell, lg, s.r, s.z, st);
+    }
+    return;
+  }
+  {
+    Probe pr(s, SSAMG_PROBE_SMOOTH0, level0_bytes(s, SSAMG_PROBE_SMOOTH0, lg, tc, tx, 8, tx));
+    launch_smooth_zero<T, double>(1, d, np, V.maxcell, lg, s.r, x, st);
+  }
+  {
+    Probe pr(s, SSAMG_PROBE_RESID0, level0_bytes(s, SSAMG_PROBE_RESID0, lg, tc, tx, 8, tx));
+    launch_stencil<T, double, T>(MODE_RESID, 1, d, np, V.maxcell, lg, x, s.r, t, st);
+  }
+  launch_ufix<T, T>(MODE_RESID, coupling_of<T>(V), lg, x, t, st);
+  {
+    Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
+    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[1].vb, st);
+  }
+  tail<T>(s, lg);
+  {
+    Probe pr(s, SSAMG_PROBE_INTERP0, level0_bytes(s, SSAMG_PROBE_INTERP0, lg, tc, tx, tx, tx));
+    launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[1].vt, x, st);
+  }
+  {
+    Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, 8, 8));
+    launch_stencil<T, double, double>(MODE_JACOBI, 1, d, np, V.maxcell, lg, x, s.r, s.z, st);
+  }
+  launch_ufix<T, double>(MODE_JACOBI, coupling_of<T>(V), lg, x, s.z, st);
+}
+
+void precond(Solver &s, int lg) {
+  if (s.prm.cycle_precision == SSAMG_FP32)
+    precond_t<float>(s, lg);
+  else
+    precond_t<double>(s, lg);
+}
+
 void apply_A0(Solver &s, int lg, const double *x, double *y) {
   Level &V = s.lv[0];
-  launch_stencil<double>(MODE_APPLY, V.d_desc64, (int)V.parts.size(), V.maxcell, lg, x, nullptr, y, s.stream);
-  launch_ufix<double>(MODE_APPLY, coupling_of<double>(V), lg, x, y, s.stream);
+  {
+    Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
+    launch_stencil<double, double, double>(MODE_APPLY, 1, V.d_desc64, (int)V.parts.size(), V.maxcell,
+                                           lg, x, nullptr, y, s.stream);
+  }
+  launch_ufix<double, double>(MODE_APPLY, coupling_of<double>(V), lg, x, y, s.stream);
 }
 
 }  // namespace
 
 void apply_level(Solver &s, int level, const double *x, double *y) {
   Level &V = s.lv[level];
-  launch_stencil<double>(MODE_APPLY, V.d_desc64, (int)V.parts.size(), V.maxcell, 0, x, nullptr, y, s.stream);
-  launch_ufix<double>(MODE_APPLY, coupling_of<double>(V), 0, x, y, s.stream);
+  launch_stencil<double, double, double>(MODE_APPLY, level == 0, V.d_desc64, (int)V.parts.size(),
+                                         V.maxcell, 0, x, nullptr, y, s.stream);
+  launch_ufix<double, double>(MODE_APPLY, coupling_of<double>(V), 0, x, y, s.stream);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(s.stream));
+}
+
+void probe_set(Solver &s, int kind) {
+  if (kind >= 0 && s.pev.empty()) {
+    s.pev.resize(4096);
+    for (auto &e : s.pev) SSAMG_HIP(hipEventCreate(&e));
+  }
+  s.probe_kind = kind;
+  s.pev_next = 0;
+  s.probe_launches = 0;
+  s.probe_bytes = 0.0;
+}
+
+void probe_read(Solver &s, int64_t *launches, double *ms, double *bytes) {
+  SSAMG_HIP(hipStreamSynchronize(s.stream));
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < s.pev_next; i += 2) {
+    float t = 0.f;
+    SSAMG_HIP(hipEventElapsedTime(&t, s.pev[i], s.pev[i + 1]));
+    total += t;
+  }
+  *launches = s.probe_launches;
+  *ms = total;
+  *bytes = s.probe_bytes;
+  s.pev_next = 0;
+  s.probe_launches = 0;
+  s.probe_bytes = 0.0;
 }
 
 void apply_precond(Solver &s, const double *r, double *z) {

@@ -167,6 +167,12 @@ struct Solver {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_nrhs = 0;
+  // HIP-event timing of one finest-level kernel kind (SSAMG_PROBE_*)
+  int probe_kind = -1;
+  std::vector<hipEvent_t> pev;
+  size_t pev_next = 0;
+  int64_t probe_launches = 0;
+  double probe_bytes = 0.0;
   ~Solver();
 };
 
@@ -175,6 +181,8 @@ void setup_numeric(Solver &s, void *ws, size_t bytes);
 void apply_level(Solver &s, int level, const double *x, double *y);
 void apply_precond(Solver &s, const double *r, double *z);
 ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_info *info);
+void probe_set(Solver &s, int kind);
+void probe_read(Solver &s, int64_t *launches, double *ms, double *bytes);
 
 enum ScalSlot { S_RZ = 0, S_RZN, S_PQ, S_RR, S_ZQ, S_BB, S_TR, kScalSlots };
 
@@ -211,14 +219,14 @@ struct FvArgs {
 enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
 
 // kernels_cycle.hip
-template <typename T>
-void launch_stencil(int mode, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
-                    const T *x, const T *b, T *y, hipStream_t st);
-template <typename T>
-void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, T *y, hipStream_t st);
-template <typename T>
-void launch_smooth_zero(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *b, T *x,
-                        hipStream_t st);
+template <typename T, typename TB, typename TO>
+void launch_stencil(int mode, int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
+                    const T *x, const TB *b, TO *y, hipStream_t st);
+template <typename T, typename TO>
+void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, TO *y, hipStream_t st);
+template <typename T, typename TB>
+void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
+                        T *x, hipStream_t st);
 template <typename T>
 void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
                      hipStream_t st);

@@ -190,6 +190,18 @@ def ssamg_copy_coupling(h, level, nrows):
     return rp, col[:nnz], val[:nnz]
 
 
+def ssamg_probe_set(h, kind):
+    check(lib().ssamg_probe_set(h, kind))
+
+
+def ssamg_probe_read(h):
+    n = C.c_int64()
+    ms = C.c_double()
+    by = C.c_double()
+    check(lib().ssamg_probe_read(h, C.byref(n), C.byref(ms), C.byref(by)))
+    return n.value, ms.value, by.value
+
+
 # ---------------------------------------------------------------- objects
 
 
