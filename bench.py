@@ -135,13 +135,15 @@ def main():
         t0 = time.perf_counter()
         pr.fv_assemble(kappa, aniso, case.stencil)
         t1 = time.perf_counter()
-        s.setup()
+        s.setup_symbolic()
+        ts = time.perf_counter()
+        s.setup_numeric()
         t2 = time.perf_counter()
         x, st, info = s.solve(b, x)
         t3 = time.perf_counter()
         if st != 0:
             raise RuntimeError(f"solve did not converge: status {st}")
-        return x, info, (t1 - t0, t2 - t1, t3 - t2)
+        return x, info, (t1 - t0, t2 - t1, t3 - t2, ts - t1, t2 - ts)
 
     def run(precision, steps, warmup, probe_kind=None):
         pr, s = make_solver(precision)
@@ -157,14 +159,16 @@ def main():
             x, info, ph = step(pr, s, x)
             phases.append(ph)
             log(f"  {'fp32' if precision else 'fp64'} cycle step {k}: assemble {ph[0]*1e3:.2f} ms, "
-                f"setup {ph[1]*1e3:.2f} ms, solve {ph[2]*1e3:.2f} ms, iters {info.iters[0]}")
+                f"setup {ph[1]*1e3:.2f} ms (symbolic {ph[3]*1e3:.2f}, numeric {ph[4]*1e3:.2f}), "
+                f"solve {ph[2]*1e3:.2f} ms, iters {info.iters[0]}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         probe = B.ssamg_probe_read(s.h) if probe_kind is not None else None
         ph = np.median(np.asarray(phases), axis=0)
         its = [info.iters[k] for k in range(nrhs)]
         res = {"ms_per_step": (t1 - t0) / steps * 1e3, "assemble_s": ph[0], "setup_s": ph[1],
-               "solve_s": ph[2], "iters": its if nrhs > 1 else its[0],
+               "solve_s": ph[2], "symbolic_s": ph[3], "numeric_s": ph[4],
+               "iters": its if nrhs > 1 else its[0],
                "true_relres": max(info.true_relres[k] for k in range(nrhs)), "levels": s.nlevels}
         return res, x, probe, s
 
@@ -247,6 +251,8 @@ def main():
                                f"tol {case.tol}", "cells": N, "nrhs": nrhs,
                    "levels": mixed["levels"], "iters": mixed["iters"],
                    "assemble_s": round(mixed["assemble_s"], 6), "setup_s": round(mixed["setup_s"], 6),
+                   "setup_symbolic_s": round(mixed["symbolic_s"], 6),
+                   "setup_numeric_s": round(mixed["numeric_s"], 6),
                    "solve_s": round(mixed["solve_s"], 6), "true_relres": mixed["true_relres"]},
         "fp64_cycle": None if fp64 is None else {
             "ms_per_step": round(fp64["ms_per_step"], 4), "setup_s": round(fp64["setup_s"], 6),

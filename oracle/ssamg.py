@@ -26,6 +26,13 @@ Readings where the paper is silent or garbled (all are listed in the design note
            are coarse; coarse index i/2; coarse extent ceil(n/2).
   R-pb     part-boundary rule: the weight that would cross a part face is absent
            and the opposite weight is set to 1.
+  R-den    the collapse is undefined where its denominator (the sum of the
+           row's coefficients with zero d* component) is not positive, which
+           happens on Galerkin operators of strongly heterogeneous problems;
+           there the weights are the row's -d* and +d* coefficient sums divided
+           by their total (constants are interpolated), or 1/2 each when that
+           total is not negative.  Rows with a positive denominator are
+           untouched.
   R-omega  omega at level l uses W at level l (before that level's doubling) and
            d*_l; a part that no longer coarsens uses d* = argmin W; the sums in
            eq:alpha-beta run over d = 0 .. n_d - 1.
@@ -218,10 +225,21 @@ def interpolation_weights(level, p, dstar, faces):
     fc[dstar] = 2 * fc[dstar] + 1                     # fine coordinate of each F cell
     lin = fc[0] + nx * (fc[1] + ny * fc[2])
     dd = den[lin]
-    if np.any(dd <= 0):
-        raise FloatingPointError("interpolation denominator <= 0")
-    wm = -sm[lin] / dd
-    wp = -spl[lin] / dd
+    sml, spll = sm[lin], spl[lin]
+    good = dd > 0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        wm = np.where(good, -sml / np.where(good, dd, 1.0), 0.0)
+        wp = np.where(good, -spll / np.where(good, dd, 1.0), 0.0)
+        # R-den: where the collapse denominator is not positive the row's two
+        # off-plane sums alone set the weights, normalised so that constants
+        # are interpolated; with no attracting off-plane coupling, 1/2 each
+        ssum = sml + spll
+        att = ssum < 0
+        safe = np.where(att, ssum, 1.0)
+        wm = np.where(good, wm, np.where(att, sml / safe, 0.5))
+        wp = np.where(good, wp, np.where(att, spll / safe, 0.5))
+    if not (np.all(np.isfinite(wm)) and np.all(np.isfinite(wp))):
+        raise FloatingPointError("non-finite interpolation weight")
     lo_out = fc[dstar] - 1 < 0
     hi_out = fc[dstar] + 1 > n[dstar] - 1
     wm = np.where(lo_out, 0.0, wm)

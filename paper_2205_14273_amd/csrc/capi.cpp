@@ -1,5 +1,6 @@
 // C ABI of the solver object (include/ssamg.h).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "capi_common.h"
@@ -86,6 +87,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
     }
     s->own_stream = true;
   }
+  const char *verbose = std::getenv("SSAMG_VERBOSE");
+  s->verbose = verbose && verbose[0] && verbose[0] != '0';
   void *pin = nullptr;
   if (hipHostMalloc(&pin, kScalSlots * kMaxRhs * sizeof(double)) != hipSuccess) {
     delete s;

@@ -51,10 +51,14 @@ template <typename T, int MODE, typename TB, typename TO, int FINE>
 __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restrict__ desc, int lg,
                                                     const T *__restrict__ x,
                                                     const TB *__restrict__ b, TO *__restrict__ y) {
+  __shared__ int urow_of[kBlock];
   const PartDesc<T> &d = desc[blockIdx.y];
-  const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
-  if (e >= (d.ncell << lg)) return;
-  const int c = (int)(e >> lg);
+  const int chunk = chunk_index();
+  const long long e = (long long)chunk * kBlock + threadIdx.x;
+  const long long nel = d.ncell << lg;
+  if ((long long)chunk * kBlock >= nel) return;      // whole block past the part's end
+  const bool valid = e < nel;
+  const int c = valid ? (int)(e >> lg) : 0;
   const int kr = (int)(e & ((1 << lg) - 1));
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
@@ -63,11 +67,29 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   const T *xp = x + o;
   const T *cf = d.coef + c;
   T acc = T(0);
-  for (int s = 0; s < d.nent; ++s) {
-    const T a = cf[(long long)s * d.ncell];
-    const T xv = nb_ok(mx, my, mz, d.code[s]) ? xp[(long long)d.lin[s] << lg] : T(0);
-    acc = fma(a, xv, acc);
+  if (valid) {
+    for (int s = 0; s < d.nent; ++s) {
+      const T a = cf[(long long)s * d.ncell];
+      const T xv = nb_ok(mx, my, mz, d.code[s]) ? xp[(long long)d.lin[s] << lg] : T(0);
+      acc = fma(a, xv, acc);
+    }
   }
+  // couplings of the cells of this block (part-boundary blocks only): map each
+  // stored row to its cell slot in LDS, then each lane adds its row of U x
+  const int u0 = d.ublk[lg][chunk], u1 = d.ublk[lg][chunk + 1];
+  if (u0 < u1) {
+    const int cpb = kBlock >> lg;
+    const int cell0 = (int)d.off + chunk * cpb;
+    if ((int)threadIdx.x < cpb) urow_of[threadIdx.x] = -1;
+    __syncthreads();
+    for (int t = u0 + (int)threadIdx.x; t < u1; t += kBlock) urow_of[d.urow[t] - cell0] = t;
+    __syncthreads();
+    const int r = urow_of[threadIdx.x >> lg];
+    if (valid && r >= 0)
+      for (int q = d.uptr[r]; q < d.uptr[r + 1]; ++q)
+        acc = fma(d.uval[q], x[((long long)d.ucol[q] << lg) + kr], acc);
+  }
+  if (!valid) return;
   if (MODE == MODE_APPLY) {
     y[o] = (TO)acc;
   } else if (MODE == MODE_RESID) {
@@ -76,30 +98,6 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
     const T ac = cf[(long long)d.center * d.ncell];
     y[o] = (TO)(xp[0] + d.omega * ((T)b[o] - acc) / ac);
   }
-}
-
-// The couplings' share of the same three operations on the rows of U (run
-// after k_stencil; the JACOBI form reads the sweep's input x).
-template <typename T, int MODE, typename TO>
-__global__ __launch_bounds__(kBlock) void k_ufix(int nrow, const int *__restrict__ row,
-                                                 const int *__restrict__ ptr,
-                                                 const int *__restrict__ col,
-                                                 const T *__restrict__ val,
-                                                 const T *__restrict__ scale, int lg,
-                                                 const T *__restrict__ x, TO *__restrict__ y) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= ((long long)nrow << lg)) return;
-  const int r = (int)(e >> lg);
-  const int kr = (int)(e & ((1 << lg) - 1));
-  T acc = T(0);
-  for (int q = ptr[r]; q < ptr[r + 1]; ++q) acc = fma(val[q], x[((long long)col[q] << lg) + kr], acc);
-  const long long o = ((long long)row[r] << lg) + kr;
-  if (MODE == MODE_APPLY)
-    y[o] += (TO)acc;
-  else if (MODE == MODE_RESID)
-    y[o] -= (TO)acc;
-  else
-    y[o] -= (TO)(scale[r] * acc);
 }
 
 // x = omega D^{-1} b: the first sweep of eq:relax0 from a zero guess
@@ -378,18 +376,6 @@ void launch_stencil(int mode, int fine, const PartDesc<T> *desc, int nparts, int
 #undef SSAMG_ST
 }
 
-template <typename T, typename TO>
-void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, TO *y, hipStream_t st) {
-  if (u.nrow == 0) return;
-  dim3 grid(grid_cells(u.nrow, lg));
-  if (mode == MODE_APPLY)
-    k_ufix<T, MODE_APPLY, TO><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
-  else if (mode == MODE_RESID)
-    k_ufix<T, MODE_RESID, TO><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
-  else
-    k_ufix<T, MODE_JACOBI, TO><<<grid, kBlock, 0, st>>>(u.nrow, u.row, u.ptr, u.col, u.val, u.scale, lg, x, y);
-}
-
 template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st) {
@@ -464,12 +450,6 @@ template void launch_stencil<float, double, float>(int, int, const PartDesc<floa
                                                    const float *, const double *, float *, hipStream_t);
 template void launch_stencil<float, double, double>(int, int, const PartDesc<float> *, int, int, int,
                                                     const float *, const double *, double *, hipStream_t);
-template void launch_ufix<double, double>(int, const CouplingDev<double> &, int, const double *, double *,
-                                          hipStream_t);
-template void launch_ufix<float, float>(int, const CouplingDev<float> &, int, const float *, float *,
-                                        hipStream_t);
-template void launch_ufix<float, double>(int, const CouplingDev<float> &, int, const float *, double *,
-                                         hipStream_t);
 template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
                                                  const double *, double *, hipStream_t);
 template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,

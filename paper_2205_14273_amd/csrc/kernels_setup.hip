@@ -92,8 +92,13 @@ __global__ __launch_bounds__(kBlock) void k_wsum_final(const double *__restrict_
 //   den = sum of the coefficients with zero d* component,
 //   wm = -(sum of those at -1)/den, wp = -(sum of those at +1)/den;
 // a coarse neighbour outside the box is absent (weight 0); if it lies across a
-// part face the opposite weight becomes 1 (Section 3.2).
+// part face the opposite weight becomes 1 (Section 3.2).  Where den is not
+// positive (the collapse is undefined; it happens on Galerkin operators of
+// strongly heterogeneous problems) the two off-plane sums are normalised by
+// their total so constants are interpolated, or 1/2 each if that total is not
+// negative.
 __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double> *__restrict__ desc,
+                                                           const PartDesc<float> *__restrict__ desc32,
                                                            int *__restrict__ flag) {
   const PartDesc<double> &d = desc[blockIdx.y];
   const long long fidx = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -115,8 +120,19 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
     else
       sp += v;
   }
-  double wm = -sm / den, wp = -sp / den;
-  if (!(den > 0.0) || !isfinite(wm) || !isfinite(wp)) flag[0] = 1;
+  double wm, wp;
+  if (den > 0.0) {
+    wm = -sm / den;
+    wp = -sp / den;
+  } else if (sm + sp < 0.0) {
+    // non-positive collapse denominator: normalise the two off-plane sums
+    wm = sm / (sm + sp);
+    wp = sp / (sm + sp);
+  } else {
+    wm = 0.5;
+    wp = 0.5;
+  }
+  if (!isfinite(wm) || !isfinite(wp)) flag[0] = 1;
   const bool hi_out = f[ds] + 1 > d.n[ds] - 1;   // lower corner 0: f-1 >= 0 always
   if (hi_out) {
     wp = 0.0;
@@ -124,6 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
   }
   const_cast<double *>(d.wm)[fidx] = wm;
   const_cast<double *>(d.wp)[fidx] = wp;
+  if (desc32) {
+    const PartDesc<float> &d32 = desc32[blockIdx.y];
+    const_cast<float *>(d32.wm)[fidx] = (float)wm;
+    const_cast<float *>(d32.wp)[fidx] = (float)wp;
+  }
 }
 
 // Structured Galerkin product for one coarse cell I of a part coarsened along
@@ -141,8 +162,11 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
   if (cidx >= d.cncell) return;
   if (d.dstar < 0) {
     // identity transfer: same operator, entries permuted into the sorted pattern
-    for (int e = 0; e < t.nent; ++e)
-      t.out[(long long)e * d.cncell + cidx] = d.coef[(long long)t.code[e] * d.ncell + cidx];
+    for (int e = 0; e < t.nent; ++e) {
+      const double v = d.coef[(long long)t.code[e] * d.ncell + cidx];
+      t.out[(long long)e * d.cncell + cidx] = v;
+      if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)v;
+    }
     return;
   }
   const int ds = d.dstar;
@@ -192,6 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
       acc = fma(rho[r + 1] * a, wg, acc);
     }
     t.out[(long long)e * d.cncell + cidx] = acc;
+    if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)acc;
   }
 }
 
@@ -203,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int 
                                                        const int *__restrict__ ib,
                                                        const double *__restrict__ uprev,
                                                        const double *__restrict__ w,
-                                                       double *__restrict__ uval) {
+                                                       double *__restrict__ uval,
+                                                       float *__restrict__ uval32) {
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= nnz) return;
   double acc = 0.0;
@@ -213,17 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int 
     acc = fma(wa * uprev[kk[q]], wb, acc);
   }
   uval[e] = acc;
-}
-
-__global__ __launch_bounds__(kBlock) void k_uscale(int nrow, const int *__restrict__ row,
-                                                   const int *__restrict__ row_part,
-                                                   const PartDesc<double> *__restrict__ desc,
-                                                   double *__restrict__ scale) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= nrow) return;
-  const PartDesc<double> &d = desc[row_part[r]];
-  const long long c = row[r] - d.off;
-  scale[r] = d.omega / d.coef[(long long)d.center * d.ncell + c];
+  if (uval32) uval32[e] = (float)acc;
 }
 
 inline unsigned nblk(long long n) {
@@ -246,9 +262,9 @@ void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *
   k_wsum_final<<<nparts, kBlock, 0, st>>>(partial, (int)nb, out);
 }
 
-void launch_interp_weights(const PartDesc<double> *desc, int nparts, int maxf, int *flag,
-                           hipStream_t st) {
-  k_interp_weights<<<dim3(nblk(maxf), nparts), kBlock, 0, st>>>(desc, flag);
+void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
+                           int maxf, int *flag, hipStream_t st) {
+  k_interp_weights<<<dim3(nblk(maxf), nparts), kBlock, 0, st>>>(desc, desc32, flag);
 }
 
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
@@ -257,13 +273,9 @@ void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int
 }
 
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
-                       const double *uprev, const double *w, double *uval, hipStream_t st) {
-  if (nnz > 0) k_uc_numeric<<<nblk(nnz), kBlock, 0, st>>>(nnz, start, k, a, b, uprev, w, uval);
-}
-
-void launch_uscale(int nrow, const int *row, const int *row_part, const PartDesc<double> *desc,
-                   double *scale, hipStream_t st) {
-  if (nrow > 0) k_uscale<<<nblk(nrow), kBlock, 0, st>>>(nrow, row, row_part, desc, scale);
+                       const double *uprev, const double *w, double *uval, float *uval32,
+                       hipStream_t st) {
+  if (nnz > 0) k_uc_numeric<<<nblk(nnz), kBlock, 0, st>>>(nnz, start, k, a, b, uprev, w, uval, uval32);
 }
 
 }  // namespace ssamg

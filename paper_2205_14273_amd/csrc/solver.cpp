@@ -27,6 +27,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 struct Carver {
   char *base = nullptr;
   size_t off = 0;
+  size_t tab_begin = 0, tab_end = 0;   // host-built tables, uploaded with one copy
   template <typename T>
   T *take(size_t n) {
     off = align_up(off);
@@ -247,13 +248,10 @@ void build_coarse_coupling(const Level &f, Level &c) {
   }
 }
 
-void fill_urow_part(Level &L) {
-  L.urow_part.resize(L.urow.size());
-  for (size_t r = 0; r < L.urow.size(); ++r) L.urow_part[r] = part_of(L, L.urow[r]);
-}
 
 template <typename T>
-PartDesc<T> make_desc(const PartLevel &q, const T *coef, const T *w) {
+PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coef, const T *w,
+                      const T *uval) {
   PartDesc<T> d{};
   for (int a = 0; a < 3; ++a) {
     d.n[a] = q.n[a];
@@ -273,12 +271,40 @@ PartDesc<T> make_desc(const PartLevel &q, const T *coef, const T *w) {
   d.coef = coef;
   d.wm = w ? w + q.wofs : nullptr;
   d.wp = w ? w + q.wofs + q.nf : nullptr;
+  d.urow = V.d_urow;
+  d.uptr = V.d_uptr;
+  d.ucol = V.d_ucol;
+  d.uval = uval;
+  for (int lg = 0; lg <= kMaxLg; ++lg)
+    d.ublk[lg] = V.d_ublk[lg] ? V.d_ublk[lg] + V.ublk_off[lg][p] : nullptr;
   for (size_t e = 0; e < q.pat.size(); ++e) {
     const auto &o = q.pat[e];
     d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
     d.code[e] = pack_off(o[0], o[1], o[2]);
   }
   return d;
+}
+
+// Rows of U falling in each block of a grid-over-cells launch, per part and
+// per right-hand-side count 1 << lg (see k_stencil).
+void build_ublk(Level &V, int lgmax) {
+  for (int lg = 0; lg <= kMaxLg; ++lg) {
+    V.ublk[lg].clear();
+    V.ublk_off[lg].assign(V.parts.size(), 0);
+    if (lg > lgmax) continue;
+    const int64_t cpb = kBlock >> lg;
+    size_t t = 0;
+    for (size_t p = 0; p < V.parts.size(); ++p) {
+      const PartLevel &q = V.parts[p];
+      V.ublk_off[lg][p] = (int64_t)V.ublk[lg].size();
+      const int64_t nchunk = (q.ncell + cpb - 1) / cpb;
+      for (int64_t b = 0; b <= nchunk; ++b) {
+        const int64_t first = q.off + std::min(b * cpb, q.ncell);
+        while (t < V.urow.size() && V.urow[t] < first) ++t;
+        V.ublk[lg].push_back((int)t);
+      }
+    }
+  }
 }
 
 template <typename T>
@@ -301,6 +327,7 @@ Solver::~Solver() {
 // ---------------------------------------------------------------- symbolic
 
 void setup_symbolic(Solver &s) {
+  const auto t0 = std::chrono::steady_clock::now();
   Problem &pr = *s.prob;
   const int np = pr.nparts;
   for (int p = 0; p < np; ++p) {
@@ -348,8 +375,9 @@ void setup_symbolic(Solver &s) {
   {
     std::vector<PartDesc<double>> hd;
     int maxcell = 0;
-    for (auto &q : L0.parts) {
-      hd.push_back(make_desc<double>(q, q.coef64, nullptr));
+    for (size_t p = 0; p < L0.parts.size(); ++p) {
+      const PartLevel &q = L0.parts[p];
+      hd.push_back(make_desc<double>(L0, q, p, q.coef64, nullptr, nullptr));
       maxcell = std::max<int64_t>(maxcell, q.ncell);
     }
     PartDesc<double> *dd = dev_alloc<PartDesc<double>>(np);
@@ -368,6 +396,8 @@ void setup_symbolic(Solver &s) {
 
   // W (Section 3.1) and Algorithm 1
   const int ndim = pr.ndim;
+  int lgmax = 0;
+  while ((1 << lgmax) < s.prm.max_nrhs) ++lgmax;
   std::vector<std::array<double, 3>> W(np);
   for (int p = 0; p < np; ++p) {
     double cmax = -kInf;
@@ -441,7 +471,7 @@ void setup_symbolic(Solver &s) {
       L.maxcoarse = std::max<int64_t>(L.maxcoarse, q.cncell);
       L.maxf = std::max<int64_t>(L.maxf, q.nf);
     }
-    fill_urow_part(L);
+    build_ublk(L, lgmax);
     if (last) break;
     C.N = coff;
     build_coarse_coupling(L, C);
@@ -452,17 +482,59 @@ void setup_symbolic(Solver &s) {
   carve(s, cv);
   s.ws_bytes = cv.off + 256;
   s.state = 1;
+  if (s.verbose) {
+    size_t unnz = 0, contrib = 0;
+    for (auto &L : s.lv) {
+      unnz += L.ucol.size();
+      contrib += L.uc_k.size();
+    }
+    fprintf(stderr, "[ssamg] symbolic setup: %.3f ms, %zu levels, %zu coupling entries, %zu "
+            "Galerkin contributions, workspace %zu bytes\n",
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
+            s.lv.size(), unnz, contrib, s.ws_bytes);
+  }
 }
 
 namespace {
 
 // Assign every device buffer of the hierarchy from one workspace (base =
-// nullptr: sizing only).  The order of takes must not depend on base.
+// nullptr: sizing only).  The order of takes must not depend on base.  The
+// host-built tables come first, in one contiguous segment.
 void carve(Solver &s, Carver &cv) {
   const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
   const int L = (int)s.lv.size();
   const int nr = s.prm.max_nrhs;
   const int64_t N0 = s.lv[0].N;
+  cv.off = align_up(cv.off);
+  cv.tab_begin = cv.off;
+  for (int l = 0; l < L; ++l) {
+    Level &V = s.lv[l];
+    V.d_desc64 = cv.take<PartDesc<double>>(V.parts.size());
+    V.d_desc32 = mixed ? cv.take<PartDesc<float>>(V.parts.size()) : nullptr;
+    V.d_rapdesc = l < L - 1 ? cv.take<RapDesc>(V.parts.size()) : nullptr;
+    for (auto &q : V.parts) {
+      q.d_rap_start = l < L - 1 ? cv.take<int>(q.rap_start.size()) : nullptr;
+      q.d_rap_code = l < L - 1 ? cv.take<int>(q.rap_code.size()) : nullptr;
+    }
+    if (l == 0) {
+      V.d_urow = s.prob->d_urow;
+      V.d_uptr = s.prob->d_uptr;
+      V.d_ucol = s.prob->d_ucol;
+    } else {
+      V.d_urow = cv.take<int>(V.urow.size());
+      V.d_uptr = cv.take<int>(V.uptr.size());
+      V.d_ucol = cv.take<int>(V.ucol.size());
+      V.d_uc_start = cv.take<int>(V.uc_start.size());
+      V.d_uc_k = cv.take<int>(V.uc_k.size());
+      V.d_uc_a = cv.take<int>(V.uc_a.size());
+      V.d_uc_b = cv.take<int>(V.uc_b.size());
+    }
+    for (int lg = 0; lg <= kMaxLg; ++lg)
+      V.d_ublk[lg] = V.ublk[lg].empty() ? nullptr : cv.take<int>(V.ublk[lg].size());
+  }
+  cv.off = align_up(cv.off);
+  cv.tab_end = cv.off;
+  // device-produced data
   s.r = cv.take<double>((size_t)N0 * nr);
   s.z = cv.take<double>((size_t)N0 * nr);
   s.p = cv.take<double>((size_t)N0 * nr);
@@ -478,34 +550,12 @@ void carve(Solver &s, Carver &cv) {
     for (auto &q : V.parts) {
       if (l > 0) q.coef64 = cv.take<double>((size_t)q.pat.size() * q.ncell);
       q.coef32 = cyc32 ? cv.take<float>((size_t)q.pat.size() * q.ncell) : nullptr;
-      q.d_rap_start = l < L - 1 ? cv.take<int>(q.rap_start.size()) : nullptr;
-      q.d_rap_code = l < L - 1 ? cv.take<int>(q.rap_code.size()) : nullptr;
     }
-    V.d_desc64 = cv.take<PartDesc<double>>(V.parts.size());
-    V.d_desc32 = mixed ? cv.take<PartDesc<float>>(V.parts.size()) : nullptr;
-    V.d_rapdesc = l < L - 1 ? cv.take<RapDesc>(V.parts.size()) : nullptr;
     V.d_w64 = l < L - 1 ? cv.take<double>(V.nw) : nullptr;
     V.d_w32 = (cyc32 && l < L - 1) ? cv.take<float>(V.nw) : nullptr;
-    const size_t nnz = V.ucol.size(), nrow = V.urow.size();
-    if (l == 0) {
-      V.d_urow = s.prob->d_urow;
-      V.d_uptr = s.prob->d_uptr;
-      V.d_ucol = s.prob->d_ucol;
-      V.d_uval64 = s.prob->d_uval;
-    } else {
-      V.d_urow = cv.take<int>(nrow);
-      V.d_uptr = cv.take<int>(nrow + 1);
-      V.d_ucol = cv.take<int>(nnz);
-      V.d_uval64 = cv.take<double>(nnz);
-      V.d_uc_start = cv.take<int>(V.uc_start.size());
-      V.d_uc_k = cv.take<int>(V.uc_k.size());
-      V.d_uc_a = cv.take<int>(V.uc_a.size());
-      V.d_uc_b = cv.take<int>(V.uc_b.size());
-    }
-    V.d_urow_part = cv.take<int>(nrow);
-    V.d_uscale64 = cv.take<double>(nrow);
+    const size_t nnz = V.ucol.size();
+    V.d_uval64 = l == 0 ? s.prob->d_uval : cv.take<double>(nnz);
     V.d_uval32 = cyc32 ? cv.take<float>(nnz) : nullptr;
-    V.d_uscale32 = cyc32 ? cv.take<float>(nrow) : nullptr;
     const size_t nv = (size_t)V.N * nr;
     if (mixed) {
       V.vb = cv.take<float>(nv);
@@ -525,6 +575,7 @@ void carve(Solver &s, Carver &cv) {
 
 void setup_numeric(Solver &s, void *ws, size_t bytes) {
   if (s.state < 1) throw Error(SSAMG_ERR_STATE, "setup_symbolic must come first");
+  const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = s.stream;
   if (ws) {
     if (bytes < s.ws_bytes) throw Error(SSAMG_ERR_ARG, "workspace smaller than ssamg_workspace_bytes");
@@ -548,70 +599,80 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   carve(s, cv);
   const int L = (int)s.lv.size();
   const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
-  // descriptors and host-built tables
+  // every host-built table goes up in one copy
+  std::vector<char> stage(cv.tab_end - cv.tab_begin);
+  auto put = [&](const void *dst, const void *src, size_t nbytes) {
+    if (!nbytes) return;
+    const size_t at = (size_t)((const char *)dst - cv.base) - cv.tab_begin;
+    if (at + nbytes > stage.size()) throw Error(SSAMG_ERR_STATE, "internal: table outside its segment");
+    std::memcpy(stage.data() + at, src, nbytes);
+  };
+  auto putv = [&](const void *dst, const auto &v) { put(dst, v.data(), v.size() * sizeof(v[0])); };
   for (int l = 0; l < L; ++l) {
     Level &V = s.lv[l];
     std::vector<PartDesc<double>> h64;
     std::vector<PartDesc<float>> h32;
     std::vector<RapDesc> hr;
-    for (auto &q : V.parts) {
-      h64.push_back(make_desc<double>(q, q.coef64, V.d_w64));
-      if (mixed) h32.push_back(make_desc<float>(q, q.coef32, V.d_w32));
+    for (size_t p = 0; p < V.parts.size(); ++p) {
+      PartLevel &q = V.parts[p];
+      h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64));
+      if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32));
       if (l < L - 1) {
-        upload(q.d_rap_start, q.rap_start, st);
-        upload(q.d_rap_code, q.rap_code, st);
+        putv(q.d_rap_start, q.rap_start);
+        putv(q.d_rap_code, q.rap_code);
         RapDesc r{};
-        r.out = nullptr;   // filled below once the coarse part is known
+        r.out = s.lv[l + 1].parts[p].coef64;
+        r.out32 = mixed && l + 1 < L - 1 ? s.lv[l + 1].parts[p].coef32 : nullptr;
         r.start = q.d_rap_start;
         r.code = q.d_rap_code;
         r.nent = (int)q.rap_start.size() - 1;
         hr.push_back(r);
       }
     }
-    if (l < L - 1)
-      for (size_t p = 0; p < V.parts.size(); ++p) hr[p].out = s.lv[l + 1].parts[p].coef64;
-    upload(V.d_desc64, h64, st);
-    if (mixed) upload(V.d_desc32, h32, st);
-    if (l < L - 1) upload(V.d_rapdesc, hr, st);
+    putv(V.d_desc64, h64);
+    if (mixed) putv(V.d_desc32, h32);
+    if (l < L - 1) putv(V.d_rapdesc, hr);
     if (l > 0) {
-      upload(V.d_urow, V.urow, st);
-      upload(V.d_uptr, V.uptr, st);
-      upload(V.d_ucol, V.ucol, st);
-      upload(V.d_uc_start, V.uc_start, st);
-      upload(V.d_uc_k, V.uc_k, st);
-      upload(V.d_uc_a, V.uc_a, st);
-      upload(V.d_uc_b, V.uc_b, st);
+      putv(V.d_urow, V.urow);
+      putv(V.d_uptr, V.uptr);
+      putv(V.d_ucol, V.ucol);
+      putv(V.d_uc_start, V.uc_start);
+      putv(V.d_uc_k, V.uc_k);
+      putv(V.d_uc_a, V.uc_a);
+      putv(V.d_uc_b, V.uc_b);
     }
-    upload(V.d_urow_part, V.urow_part, st);
+    for (int lg = 0; lg <= kMaxLg; ++lg)
+      if (V.d_ublk[lg]) putv(V.d_ublk[lg], V.ublk[lg]);
   }
+  if (!stage.empty())
+    SSAMG_HIP(hipMemcpyAsync(cv.base + cv.tab_begin, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
   SSAMG_HIP(hipMemsetAsync(s.flag, 0, sizeof(int), st));
+  const auto t1 = std::chrono::steady_clock::now();
+  // finest-level FP32 copies; coarser ones are written by the kernels below
+  if (mixed && L > 1) {
+    Level &V = s.lv[0];
+    for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
+    launch_cast_d2f(V.d_uval64, V.d_uval32, (int64_t)V.ucol.size(), st);
+  }
   // level by level: weights, structured and unstructured Galerkin products
   for (int l = 0; l + 1 < L; ++l) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
-    launch_interp_weights(V.d_desc64, np, V.maxf, s.flag, st);
+    launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
     launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, st);
     launch_uc_numeric((int64_t)C.ucol.size(), C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
-                      V.d_w64, C.d_uval64, st);
-  }
-  for (int l = 0; l < L; ++l) {
-    Level &V = s.lv[l];
-    launch_uscale((int)V.urow.size(), V.d_urow, V.d_urow_part, V.d_desc64, V.d_uscale64, st);
-  }
-  if (mixed) {
-    for (int l = 0; l + 1 < L; ++l) {
-      Level &V = s.lv[l];
-      for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
-      launch_cast_d2f(V.d_w64, V.d_w32, V.nw, st);
-      launch_cast_d2f(V.d_uval64, V.d_uval32, (int64_t)V.ucol.size(), st);
-      launch_cast_d2f(V.d_uscale64, V.d_uscale32, (int64_t)V.urow.size(), st);
-    }
+                      V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
   }
   SSAMG_HIP(hipGetLastError());
   int hflag = 0;
   SSAMG_HIP(hipMemcpyAsync(&hflag, s.flag, sizeof(int), hipMemcpyDeviceToHost, st));
   SSAMG_HIP(hipStreamSynchronize(st));
-  if (hflag) throw Error(SSAMG_ERR_NUMERIC, "nonpositive or non-finite interpolation denominator");
+  const auto t2 = std::chrono::steady_clock::now();
+  if (s.verbose)
+    fprintf(stderr, "[ssamg] numeric setup: tables %.3f ms (%zu bytes), kernels %.3f ms\n",
+            std::chrono::duration<double, std::milli>(t1 - t0).count(), stage.size(),
+            std::chrono::duration<double, std::milli>(t2 - t1).count());
+  if (hflag) throw Error(SSAMG_ERR_NUMERIC, "non-finite interpolation weight");
   s.state = 2;
 }
 
@@ -625,17 +686,6 @@ template <>
 const PartDesc<double> *desc_of<double>(const Level &V) { return V.d_desc64; }
 template <>
 const PartDesc<float> *desc_of<float>(const Level &V) { return V.d_desc32; }
-
-template <typename T>
-CouplingDev<T> coupling_of(const Level &V);
-template <>
-CouplingDev<double> coupling_of<double>(const Level &V) {
-  return {(int)V.urow.size(), (int64_t)V.ucol.size(), V.d_urow, V.d_uptr, V.d_ucol, V.d_uval64, V.d_uscale64};
-}
-template <>
-CouplingDev<float> coupling_of<float>(const Level &V) {
-  return {(int)V.urow.size(), (int64_t)V.ucol.size(), V.d_urow, V.d_uptr, V.d_ucol, V.d_uval32, V.d_uscale32};
-}
 
 // Algorithmic bytes of one finest-level launch (each array element once).
 double level0_bytes(const Solver &s, int kind, int lg, size_t tc, size_t tx, size_t tb, size_t to) {
@@ -687,7 +737,6 @@ void run_tail(Solver &s, int lg) {
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
     launch_smooth_zero<T, T>(0, d, np, V.maxcell, lg, b, x, st);
     launch_stencil<T, T, T>(MODE_RESID, 0, d, np, V.maxcell, lg, x, b, t, st);
-    launch_ufix<T, T>(MODE_RESID, coupling_of<T>(V), lg, x, t, st);
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   Level &C = s.lv[L - 1];
@@ -702,7 +751,6 @@ void run_tail(Solver &s, int lg) {
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
     launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[l + 1].vt, x, st);
     launch_stencil<T, T, T>(MODE_JACOBI, 0, d, np, V.maxcell, lg, x, b, t, st);
-    launch_ufix<T, T>(MODE_JACOBI, coupling_of<T>(V), lg, x, t, st);
   }
 }
 
@@ -758,7 +806,6 @@ void precond_t(Solver &s, int lg) {
     Probe pr(s, SSAMG_PROBE_RESID0, level0_bytes(s, SSAMG_PROBE_RESID0, lg, tc, tx, 8, tx));
     launch_stencil<T, double, T>(MODE_RESID, 1, d, np, V.maxcell, lg, x, s.r, t, st);
   }
-  launch_ufix<T, T>(MODE_RESID, coupling_of<T>(V), lg, x, t, st);
   {
     Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[1].vb, st);
@@ -772,7 +819,6 @@ void precond_t(Solver &s, int lg) {
     Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, 8, 8));
     launch_stencil<T, double, double>(MODE_JACOBI, 1, d, np, V.maxcell, lg, x, s.r, s.z, st);
   }
-  launch_ufix<T, double>(MODE_JACOBI, coupling_of<T>(V), lg, x, s.z, st);
 }
 
 void precond(Solver &s, int lg) {
@@ -789,7 +835,6 @@ void apply_A0(Solver &s, int lg, const double *x, double *y) {
     launch_stencil<double, double, double>(MODE_APPLY, 1, V.d_desc64, (int)V.parts.size(), V.maxcell,
                                            lg, x, nullptr, y, s.stream);
   }
-  launch_ufix<double, double>(MODE_APPLY, coupling_of<double>(V), lg, x, y, s.stream);
 }
 
 }  // namespace
@@ -798,7 +843,6 @@ void apply_level(Solver &s, int level, const double *x, double *y) {
   Level &V = s.lv[level];
   launch_stencil<double, double, double>(MODE_APPLY, level == 0, V.d_desc64, (int)V.parts.size(),
                                          V.maxcell, 0, x, nullptr, y, s.stream);
-  launch_ufix<double, double>(MODE_APPLY, coupling_of<double>(V), 0, x, y, s.stream);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(s.stream));
 }

@@ -31,6 +31,7 @@ constexpr int kMaxEnt = 27;      // stencils live in the 27-point neighbourhood
 constexpr int kBlock = 256;      // threads per block of every grid-over-cells kernel
 constexpr int kRedBlocks = 512;  // fixed grid of the deterministic reductions
 constexpr int kMaxRhs = 32;
+constexpr int kMaxLg = 5;        // log2(kMaxRhs)
 
 // Packed stencil offset: (dx+1) | (dy+1) << 2 | (dz+1) << 4.
 inline int pack_off(int dx, int dy, int dz) { return (dx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4); }
@@ -56,20 +57,16 @@ struct PartDesc {
   const T *coef;       // [nent][ncell]
   const T *wm;         // [nf] weight toward the -dstar coarse neighbour
   const T *wp;         // [nf] weight toward the +dstar coarse neighbour
+  // couplings U of the level (compressed rows, shared by all parts); the rows
+  // of the part's block `b` of a grid-over-cells launch with 1 << lg
+  // right-hand sides are urow[ublk[lg][b] .. ublk[lg][b+1])
+  const int *urow;     // cell id of each stored row (ascending)
+  const int *uptr;
+  const int *ucol;
+  const T *uval;
+  const int *ublk[kMaxLg + 1];
   int lin[kMaxEnt];    // dx + nx*(dy + ny*dz)
   int code[kMaxEnt];   // pack_off(dx, dy, dz)
-};
-
-// Coupling matrix U of one level, compressed rows (only rows with entries).
-template <typename T>
-struct CouplingDev {
-  int nrow = 0;
-  int64_t nnz = 0;
-  const int *row = nullptr;     // cell id of each stored row
-  const int *ptr = nullptr;     // [nrow + 1]
-  const int *col = nullptr;     // [nnz] cell ids
-  const T *val = nullptr;       // [nnz]
-  const T *scale = nullptr;     // [nrow] omega_p / a_ii of the row's cell
 };
 
 // ------------------------------------------------------------------ problem
@@ -125,10 +122,14 @@ struct Level {
   int64_t N = 0;
   int maxcell = 0, maxcoarse = 0, maxf = 0;
   // couplings (compressed rows), host structure
-  std::vector<int> urow, uptr, ucol, urow_part;
-  int *d_urow = nullptr, *d_uptr = nullptr, *d_ucol = nullptr, *d_urow_part = nullptr;
-  double *d_uval64 = nullptr, *d_uscale64 = nullptr;
-  float *d_uval32 = nullptr, *d_uscale32 = nullptr;
+  std::vector<int> urow, uptr, ucol;
+  int *d_urow = nullptr, *d_uptr = nullptr, *d_ucol = nullptr;
+  double *d_uval64 = nullptr;
+  float *d_uval32 = nullptr;
+  // first coupling row of every block of a grid-over-cells launch, per lg
+  std::vector<int> ublk[kMaxLg + 1];
+  std::vector<int64_t> ublk_off[kMaxLg + 1];   // per part
+  int *d_ublk[kMaxLg + 1] = {};
   // recipe of this level's U as P^T U P from the previous level
   std::vector<int> uc_start, uc_k, uc_a, uc_b;
   int *d_uc_start = nullptr, *d_uc_k = nullptr, *d_uc_a = nullptr, *d_uc_b = nullptr;
@@ -149,6 +150,7 @@ struct Solver {
   ssamg_params prm{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool verbose = false;              // SSAMG_VERBOSE: phase timings on stderr
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
   std::vector<Level> lv;
   std::vector<double> cd;            // direction sums c[p][d]
@@ -202,6 +204,7 @@ struct BoxStencil {
 // per-part Galerkin table of one level (device array indexed by part)
 struct RapDesc {
   double *out;         // coarse coefficients [nent_c][cncell]
+  float *out32;        // FP32 copy of them (mixed-precision cycle) or null
   const int *start;    // [nent_c + 1] into code
   const int *code;     // (r+1) | s << 2 | gsel << 7; identity parts: fine entry per coarse entry
   int nent;            // coarse entries
@@ -222,8 +225,6 @@ enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
                     const T *x, const TB *b, TO *y, hipStream_t st);
-template <typename T, typename TO>
-void launch_ufix(int mode, const CouplingDev<T> &u, int lg, const T *x, TO *y, hipStream_t st);
 template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st);
@@ -253,14 +254,13 @@ void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, d
 void launch_normalise(const BoxStencil &bs, int *flag, hipStream_t st);
 void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *partial, double *out,
                  hipStream_t st);
-void launch_interp_weights(const PartDesc<double> *desc, int nparts, int maxf, int *flag,
-                           hipStream_t st);
+void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
+                           int maxf, int *flag, hipStream_t st);
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
                 hipStream_t st);
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
-                       const double *uprev, const double *w, double *uval, hipStream_t st);
-void launch_uscale(int nrow, const int *row, const int *row_part, const PartDesc<double> *desc,
-                   double *scale, hipStream_t st);
+                       const double *uprev, const double *w, double *uval, float *uval32,
+                       hipStream_t st);
 
 // kernels_fv.hip
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,

@@ -116,6 +116,16 @@ def test_raw_problem_parity(seed, kind):
     assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
 
 
+def test_collapse_fallback_parity():
+    from tests.test_oracle_pins import den_fallback_case
+    case = den_fallback_case()
+    h = oracle_raw(case)
+    pr, s = gpu_raw(case)
+    compare_hierarchy(h, s, 1)
+    wm, wp = s.copy_interp(0, 0)
+    assert wm[1] == pytest.approx(0.75, abs=1e-15) and wp[1] == pytest.approx(0.25, abs=1e-15)
+
+
 def test_raw_2d_problem_parity():
     g = W.Geometry(2, [(17, 11, 1), (9, 11, 1)], [(0, 0, 0), (17, 0, 0)])
     case = W.random_link_case(5, g, 9)

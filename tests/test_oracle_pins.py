@@ -417,3 +417,63 @@ def test_fv_gradient_27_point_and_anisotropic():
         km[c] -= h
         fd = (w @ xsol(kp)[0] - w @ xsol(km)[0]) / (2 * h)
         assert grad[c] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# reading R-den: collapse with a non-positive denominator
+
+
+def den_fallback_case():
+    """3 x 5 cells, 5-point, strong y links so d* = y; the F cell (1,1) has
+    diagonal 1 and x links -0.6, -0.6 (collapse denominator 1 - 1.2 < 0) and y
+    links -0.3 (to y=0) and -0.1 (to y=2).  Other rows are strictly dominant."""
+    nx, ny = 3, 5
+    offs = W.stencil_offsets(5, 2)           # center, (0,-1), (-1,0), (1,0), (0,1)
+    key = {tuple(int(v) for v in o): e for e, o in enumerate(offs)}
+    coef = np.zeros((5, 1, ny, nx))
+
+    def link(i0, j0, i1, j1, t):
+        coef[key[(i1 - i0, j1 - j0, 0)], 0, j0, i0] = -t
+        coef[key[(i0 - i1, j0 - j1, 0)], 0, j1, i1] = -t
+
+    for j in range(ny):
+        for i in range(nx):
+            if i + 1 < nx:
+                special = j == 1 and i in (0, 1)
+                link(i, j, i + 1, j, 0.6 if special else 0.1)
+            if j + 1 < ny:
+                t = 4.0
+                if i == 1 and j == 0:
+                    t = 0.3
+                if i == 1 and j == 1:
+                    t = 0.1
+                link(i, j, i, j + 1, t)
+    for j in range(ny):
+        for i in range(nx):
+            coef[0, 0, j, i] = 20.0
+    coef[0, 0, 1, 1] = 1.0
+    g = W.Geometry(2, [(nx, ny, 1)], [(0, 0, 0)])
+    b = np.random.default_rng(11).uniform(-1, 1, nx * ny)
+    return W.RawCase("den", g, np.zeros((1, 6), dtype=np.int32), [offs], [coef],
+                     np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0), b)
+
+
+def test_collapse_fallback_weights():
+    case = den_fallback_case()
+    g = case.geometry
+    A, _ = assemble.assemble_raw(g.dims, case.stencils, case.coeffs, case.urow, case.ucol, case.uval)
+    Ad = A.toarray()
+    np.linalg.cholesky(Ad)                    # the operator is SPD
+    f = 1 + 3 * 1
+    den = Ad[f, f] + Ad[f, f - 1] + Ad[f, f + 1]
+    assert den < 0
+    h = ssamg.setup(A, g.dims, case.faces, case.stencils, 2)
+    lev = h.levels[0]
+    assert lev.dstar[0] == 1
+    # F-box (3 x 2): cell (1,1) -> F (1,0); weights -0.3/-0.4 and -0.1/-0.4
+    assert lev.wm[0][1] == pytest.approx(0.75, abs=1e-15)
+    assert lev.wp[0][1] == pytest.approx(0.25, abs=1e-15)
+    # other F cells keep the plain collapse (positive denominator)
+    assert lev.wm[0][0] == pytest.approx(-Ad[0 + 3, 0] / (Ad[3, 3] + Ad[3, 4]), rel=1e-14)
+    res = ssamg.solve(h, case.b, tol=1e-12)
+    assert np.linalg.norm(res.x - np.linalg.solve(Ad, case.b)) < 1e-10 * np.linalg.norm(res.x)
