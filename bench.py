@@ -37,12 +37,11 @@ DESCR = {
 # finest-level kernel kinds the library can time with HIP events, and the
 # kernel names rocprofv3 reports for them in a mixed-precision cycle
 PROBES = {
-    "matvec": (0, "k_stencil<double, 0, double, double, 1>"),
-    "smooth0": (1, "k_smooth_zero<float, double, 1>"),
-    "resid0": (2, "k_stencil<float, 1, double, float, 1>"),
+    "matvec": (0, "k_stencil<double, 0, double, double, 1, {n}>"),
+    "resid0": (2, "k_smooth_resid<float, double, 1, {n}>"),
     "restrict0": (3, "k_restrict<float>"),
     "interp0": (4, "k_interp_add<float>"),
-    "jacobi0": (5, "k_stencil<float, 2, double, double, 1>"),
+    "jacobi0": (5, "k_stencil<float, 2, double, double, 1, {n}>"),
 }
 
 
@@ -124,7 +123,8 @@ def main():
     def make_solver(precision):
         pr = B.Problem(g.ndim, g.dims, g.origins)
         params = dict(cycle_precision=precision, max_nrhs=nrhs, tol=case.tol,
-                      max_iter=case.max_iter)
+                      max_iter=case.max_iter,
+                      relax=B.L.RELAX_L1_JACOBI if case.relax == "l1" else B.L.RELAX_JACOBI)
         if case.omega > 0:
             params["omega"] = case.omega
         pr.fv_assemble(kappa, aniso, case.stencil)
@@ -174,6 +174,7 @@ def main():
 
     log("timed run: FP32 V-cycle inside FP64 PCG")
     probe_kind, probe_name = PROBES[args.probe]
+    probe_name = probe_name.format(n=7 if case.stencil in (5, 7) else 27)
     mixed, x32, probe, s32 = run(B.L.FP32, args.steps, args.warmup, probe_kind)
     fp64 = None
     x64 = None
@@ -214,7 +215,7 @@ def main():
         sg = sample_case.geometry
         A, _ = assemble.assemble_fv(sg, sample_case.stencil, sample_case.kappa, sample_case.aniso)
         h = O.setup(A, sg.dims, sg.face_kinds(), [W.stencil_offsets(sample_case.stencil, sg.ndim)]
-                    * sg.nparts, sg.ndim, omega=sample_case.omega)
+                    * sg.nparts, sg.ndim, omega=sample_case.omega, relax=sample_case.relax)
         bb = sample_case.b if sample_case.b.ndim == 1 else sample_case.b[0]
         ref = O.solve(h, bb, tol=sample_case.tol, max_iter=sample_case.max_iter)
         t1 = time.perf_counter()

@@ -133,8 +133,12 @@ typedef struct {
   int max_levels;            /* l_max of Section 3.1 (default 64) */
   int64_t min_coarse_size;   /* s_max of Section 3.1: stop at the first level with
                                 fewer cells (default 0: coarsen to one cell/part) */
-  int relax;                 /* SSAMG_RELAX_JACOBI (default) */
-  double omega;              /* > 0: fixed weight; <= 0: per-part omega_p (default) */
+  int relax;                 /* SSAMG_RELAX_JACOBI (default): x += omega D^{-1} (b - Ax);
+                                SSAMG_RELAX_L1_JACOBI: x += factor M^{-1} (b - Ax) with
+                                M_ii = sum_j |a_ij| over S and U (Section 3.4) */
+  double omega;              /* JACOBI: > 0 fixed weight, <= 0 per-part omega_p of
+                                eq:relax1 (default); L1_JACOBI: > 0 the factor, <= 0 3/2
+                                (the paper's SSAMG-base setting) */
   int coarse;                /* SSAMG_COARSE_SWEEP (default, Section 3.5) */
   int cycle_precision;       /* SSAMG_FP64 (default) or SSAMG_FP32: V-cycle in FP32
                                 inside FP64 PCG, coarsest level in FP64 */
@@ -222,8 +226,9 @@ ssamg_status ssamg_copy_coupling(ssamg_solver s, int level, int64_t *rowptr, int
 enum {
   SSAMG_PROBE_NONE = -1,
   SSAMG_PROBE_MATVEC = 0,     /* PCG product q = A p (FP64) */
-  SSAMG_PROBE_SMOOTH0 = 1,    /* first sweep from zero, finest level */
-  SSAMG_PROBE_RESID0 = 2,     /* residual b - S x, finest level */
+  SSAMG_PROBE_SMOOTH0 = 1,    /* reserved: the first sweep is fused into RESID0 */
+  SSAMG_PROBE_RESID0 = 2,     /* first sweep from zero fused with the residual
+                                 b - A x, finest level */
   SSAMG_PROBE_RESTRICT0 = 3,  /* restriction P^T r from the finest level */
   SSAMG_PROBE_INTERP0 = 4,    /* x += P x_c on the finest level */
   SSAMG_PROBE_JACOBI0 = 5     /* post-smoothing sweep, finest level */

@@ -325,6 +325,8 @@ class Hierarchy:
     W0: np.ndarray
     cd: np.ndarray
     coarse: str = "sweep"
+    relax: str = "jacobi"
+    l1_factor: float = 1.5
 
     @property
     def nlevels(self):
@@ -332,7 +334,7 @@ class Hierarchy:
 
 
 def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=64,
-          min_coarse_size=0, coarse="sweep"):
+          min_coarse_size=0, coarse="sweep", relax="jacobi"):
     """Full SSAMG setup.  ``pattern0[p]`` is the input stencil of part p.
 
     ``ustruct0``: 0/1 structure of the input couplings (defaults to A0's
@@ -374,7 +376,11 @@ def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=
         ust.data[:] = 1.0
         ust.sort_indices()
         levels.append(Level(list(cdims), coffs, Ac, pats, ust))
-    return Hierarchy(ndim, levels, np.asarray(faces), W0, cd, coarse)
+    h = Hierarchy(ndim, levels, np.asarray(faces), W0, cd, coarse, relax,
+                  omega if (relax == "l1" and omega > 0) else 1.5)
+    for lev in levels:
+        lev._cache["relax"] = (relax, h.l1_factor)
+    return h
 
 
 # ---------------------------------------------------------------------------
@@ -430,10 +436,16 @@ def coupling_csr(level):
 
 
 def _cell_weights(level):
-    """omega_p / a_ii per cell (the weighted Jacobi smoother M^{-1} = omega D^{-1})."""
+    """Per-cell factor of the smoother x <- x + w (b - A x) (eq:relax0):
+    weighted Jacobi w = omega_p / a_ii (eq:relax1), or weighted L1-Jacobi
+    w = factor / sum_j |a_ij| over the whole row of A = S + U (Section 3.4)."""
     if "wd" not in level._cache:
-        part = np.repeat(np.arange(len(level.dims)), np.diff(level.offsets))
-        level._cache["wd"] = level.omega[part] / level.A.diagonal()
+        relax, factor = level._cache.get("relax", ("jacobi", 1.5))
+        if relax == "l1":
+            level._cache["wd"] = factor / np.asarray(abs(level.A).sum(axis=1)).ravel()
+        else:
+            part = np.repeat(np.arange(len(level.dims)), np.diff(level.offsets))
+            level._cache["wd"] = level.omega[part] / level.A.diagonal()
     return level._cache["wd"]
 
 

@@ -1,5 +1,6 @@
 // C ABI of the solver object (include/ssamg.h).
 #include <cmath>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 
@@ -66,7 +67,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
     ssamg_params_default(&p);
   if (p.max_levels < 1) throw Error(SSAMG_ERR_ARG, "max_levels must be >= 1");
   if (p.min_coarse_size < 0) throw Error(SSAMG_ERR_ARG, "min_coarse_size must be >= 0");
-  if (p.relax != SSAMG_RELAX_JACOBI) throw Error(SSAMG_ERR_UNSUPPORTED, "only weighted Jacobi relaxation");
+  if (p.relax != SSAMG_RELAX_JACOBI && p.relax != SSAMG_RELAX_L1_JACOBI)
+    throw Error(SSAMG_ERR_ARG, "relax must be SSAMG_RELAX_JACOBI or SSAMG_RELAX_L1_JACOBI");
   if (p.coarse != SSAMG_COARSE_SWEEP) throw Error(SSAMG_ERR_UNSUPPORTED, "only the one-sweep coarsest level");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
     throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
@@ -89,6 +91,9 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   }
   const char *verbose = std::getenv("SSAMG_VERBOSE");
   s->verbose = verbose && verbose[0] && verbose[0] != '0';
+  // cycle levels of at most this many elements run in the one-workgroup kernel
+  const char *tail = std::getenv("SSAMG_TAIL_ELEMS");
+  if (tail && tail[0]) s->tail_elems = std::max<int64_t>(0, std::atoll(tail));
   void *pin = nullptr;
   if (hipHostMalloc(&pin, kScalSlots * kMaxRhs * sizeof(double)) != hipSuccess) {
     delete s;
@@ -253,7 +258,7 @@ ssamg_status ssamg_coupling_nnz(ssamg_solver h, int level, int64_t *nnz) {
   need(s, 1, "setup_symbolic must come first");
   check_level(s, level);
   if (!nnz) throw Error(SSAMG_ERR_ARG, "NULL output");
-  *nnz = (int64_t)s->lv[level].ucol.size();
+  *nnz = s->lv[level].nnz;
   API_END
 }
 
@@ -264,15 +269,21 @@ ssamg_status ssamg_copy_coupling(ssamg_solver h, int level, int64_t *rowptr, int
   check_level(s, level);
   if (!rowptr || !col || !val) throw Error(SSAMG_ERR_ARG, "NULL output");
   const Level &V = s->lv[level];
-  const size_t nnz = V.ucol.size();
+  const size_t nnz = (size_t)V.nnz, nrow = (size_t)V.nrow;
   std::vector<double> hv(nnz);
+  std::vector<int> urow(nrow), uptr(nrow + 1, 0), ucol(nnz);
   SSAMG_HIP(hipStreamSynchronize(s->stream));
-  if (nnz) SSAMG_HIP(hipMemcpy(hv.data(), V.d_uval64, nnz * sizeof(double), hipMemcpyDeviceToHost));
+  if (nnz) {
+    SSAMG_HIP(hipMemcpy(hv.data(), V.d_uval64, nnz * sizeof(double), hipMemcpyDeviceToHost));
+    SSAMG_HIP(hipMemcpy(urow.data(), V.d_urow, nrow * sizeof(int), hipMemcpyDeviceToHost));
+    SSAMG_HIP(hipMemcpy(uptr.data(), V.d_uptr, (nrow + 1) * sizeof(int), hipMemcpyDeviceToHost));
+    SSAMG_HIP(hipMemcpy(ucol.data(), V.d_ucol, nnz * sizeof(int), hipMemcpyDeviceToHost));
+  }
   for (int64_t i = 0; i <= V.N; ++i) rowptr[i] = 0;
-  for (size_t r = 0; r < V.urow.size(); ++r) rowptr[V.urow[r] + 1] = V.uptr[r + 1] - V.uptr[r];
+  for (size_t r = 0; r < nrow; ++r) rowptr[urow[r] + 1] = uptr[r + 1] - uptr[r];
   for (int64_t i = 0; i < V.N; ++i) rowptr[i + 1] += rowptr[i];
   for (size_t k = 0; k < nnz; ++k) {
-    col[k] = V.ucol[k];
+    col[k] = ucol[k];
     val[k] = hv[k];
   }
   API_END

@@ -1,0 +1,204 @@
+// Krylov (PCG, Section 4 protocol) and vector kernels (gfx950): deterministic
+// dot products, the fused x/r and p updates, casts, fills and copies.
+// Vectors are [cell][rhs] with nrhs = 1 << lg right-hand sides interleaved.
+#include "ssamg_impl.h"
+
+namespace ssamg {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_cast_d2f(const double *__restrict__ in,
+                                                     float *__restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    out[i] = (float)in[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_f2d(const float *__restrict__ in,
+                                                     double *__restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    out[i] = (double)in[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ x, double v, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    x[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const double *__restrict__ in,
+                                                 double *__restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    out[i] = in[i];
+}
+
+// ---------------------------------------------------------------- reductions
+// Deterministic: a fixed grid of kRedBlocks blocks, each thread accumulating a
+// fixed stride-set of elements, a fixed LDS tree per block, and a single-block
+// final pass in fixed order.  With nrhs interleaved right-hand sides, lanes
+// that share (tid mod nrhs) share a right-hand side, and every tree step keeps
+// that invariant (strides are multiples of nrhs).
+
+__device__ __forceinline__ void block_tree(double *sh, int nr) {
+  for (int s = kBlock / 2; s >= nr; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const double *__restrict__ a,
+                                                        const double *__restrict__ b, long long nel,
+                                                        int lg, double *__restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int nr = 1 << lg;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
+       i += (long long)gridDim.x * kBlock)
+    acc = fma(a[i], b[i], acc);
+  sh[threadIdx.x] = acc;
+  block_tree(sh, nr);
+  if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+}
+
+// slot <- sum of partials; shift_rz: first move S_RZN to S_RZ (PCG bookkeeping)
+__global__ __launch_bounds__(kBlock) void k_dot_final(const double *__restrict__ partial, int nblk,
+                                                      int lg, double *__restrict__ scal, int slot,
+                                                      int shift_rz) {
+  __shared__ double sh[kBlock];
+  const int nr = 1 << lg;
+  const int kr = threadIdx.x & (nr - 1);
+  double acc = 0.0;
+  for (int bidx = threadIdx.x >> lg; bidx < nblk; bidx += kBlock >> lg)
+    acc += partial[bidx * kMaxRhs + kr];
+  sh[threadIdx.x] = acc;
+  block_tree(sh, nr);
+  if ((int)threadIdx.x < nr) {
+    if (shift_rz) scal[S_RZ * kMaxRhs + threadIdx.x] = scal[S_RZN * kMaxRhs + threadIdx.x];
+    scal[slot * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+  }
+}
+
+// x += alpha p, r -= alpha q with alpha = rz/pq per right-hand side (0 when
+// frozen), plus the partial sums of r.r
+__global__ __launch_bounds__(kBlock) void k_pcg_xr(long long nel, int lg,
+                                                   const double *__restrict__ scal,
+                                                   const int *__restrict__ active,
+                                                   double *__restrict__ x, double *__restrict__ r,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ q,
+                                                   double *__restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int nr = 1 << lg;
+  const int kr = threadIdx.x & (nr - 1);
+  const bool act = active[kr] != 0;
+  const double alpha = act ? scal[S_RZN * kMaxRhs + kr] / scal[S_PQ * kMaxRhs + kr] : 0.0;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
+       i += (long long)gridDim.x * kBlock) {
+    double ri = r[i];
+    if (act) {
+      x[i] = fma(alpha, p[i], x[i]);
+      ri = fma(-alpha, q[i], ri);
+      r[i] = ri;
+    }
+    acc = fma(ri, ri, acc);
+  }
+  sh[threadIdx.x] = acc;
+  block_tree(sh, nr);
+  if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+}
+
+// p = z + beta p; beta = rz_new/rz_old, or -(z.q)/(p.q) for flexible CG
+__global__ __launch_bounds__(kBlock) void k_pcg_p(long long nel, int lg,
+                                                  const double *__restrict__ scal,
+                                                  const int *__restrict__ active, int flexible,
+                                                  const double *__restrict__ z,
+                                                  double *__restrict__ p) {
+  const int nr = 1 << lg;
+  const int kr = threadIdx.x & (nr - 1);
+  double beta = flexible ? -scal[S_ZQ * kMaxRhs + kr] / scal[S_PQ * kMaxRhs + kr]
+                         : scal[S_RZN * kMaxRhs + kr] / scal[S_RZ * kMaxRhs + kr];
+  if (!active[kr]) beta = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
+       i += (long long)gridDim.x * kBlock)
+    p[i] = fma(beta, p[i], z[i]);
+}
+
+// partial sums of (b - Ax)^2
+__global__ __launch_bounds__(kBlock) void k_resid_partial(const double *__restrict__ b,
+                                                          const double *__restrict__ ax,
+                                                          long long nel, int lg,
+                                                          double *__restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int nr = 1 << lg;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
+       i += (long long)gridDim.x * kBlock) {
+    const double t = b[i] - ax[i];
+    acc = fma(t, t, acc);
+  }
+  sh[threadIdx.x] = acc;
+  block_tree(sh, nr);
+  if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+}
+
+inline unsigned grid_stream(long long n) {
+  long long nb = (n + kBlock - 1) / kBlock;
+  if (nb > 4096) nb = 4096;
+  return (unsigned)(nb > 0 ? nb : 1);
+}
+
+inline unsigned red_blocks(long long nel) {
+  long long nb = (nel + kBlock - 1) / kBlock;
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  return (unsigned)(nb > 0 ? nb : 1);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+void launch_cast_d2f(const double *in, float *out, int64_t n, hipStream_t st) {
+  if (n > 0) k_cast_d2f<<<grid_stream(n), kBlock, 0, st>>>(in, out, n);
+}
+void launch_cast_f2d(const float *in, double *out, int64_t n, hipStream_t st) {
+  if (n > 0) k_cast_f2d<<<grid_stream(n), kBlock, 0, st>>>(in, out, n);
+}
+void launch_fill(double *x, double v, int64_t n, hipStream_t st) {
+  if (n > 0) k_fill<<<grid_stream(n), kBlock, 0, st>>>(x, v, n);
+}
+void launch_copy(const double *in, double *out, int64_t n, hipStream_t st) {
+  if (n > 0) k_copy<<<grid_stream(n), kBlock, 0, st>>>(in, out, n);
+}
+
+void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *partial, double *scal,
+                int slot, int shift_rz, hipStream_t st) {
+  const unsigned nb = red_blocks(nel);
+  k_dot_partial<<<nb, kBlock, 0, st>>>(a, b, nel, lg, partial);
+  k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal, slot, shift_rz);
+}
+
+void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
+                   const double *p, const double *q, double *partial, double *scal_out,
+                   hipStream_t st) {
+  const unsigned nb = red_blocks(nel);
+  k_pcg_xr<<<nb, kBlock, 0, st>>>(nel, lg, scal, active, x, r, p, q, partial);
+  k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal_out, S_RR, 0);
+}
+
+void launch_pcg_p(int64_t nel, int lg, const double *scal, const int *active, int flexible,
+                  const double *z, double *p, hipStream_t st) {
+  k_pcg_p<<<grid_stream(nel), kBlock, 0, st>>>(nel, lg, scal, active, flexible, z, p);
+}
+
+void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, double *partial,
+                       double *scal, int slot, hipStream_t st) {
+  const unsigned nb = red_blocks(nel);
+  k_resid_partial<<<nb, kBlock, 0, st>>>(b, ax, nel, lg, partial);
+  k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal, slot, 0);
+}
+
+}  // namespace ssamg

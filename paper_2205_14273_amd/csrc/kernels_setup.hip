@@ -242,6 +242,57 @@ __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int 
   if (uval32) uval32[e] = (float)acc;
 }
 
+// Weighted L1-Jacobi (Section 3.4): M_ii = sum_j |a_ij| over the whole row
+// of A = S + U; the smoother factor of cell i is factor / M_ii.
+__global__ __launch_bounds__(kBlock) void k_l1_cells(const PartDesc<double> *__restrict__ desc,
+                                                     double *__restrict__ l1) {
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.ncell) return;
+  double acc = 0.0;
+  for (int s = 0; s < d.nent; ++s) acc += fabs(d.coef[(long long)s * d.ncell + c]);
+  l1[d.off + c] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_l1_urows(int nrow, const int *__restrict__ urow,
+                                                     const int *__restrict__ uptr,
+                                                     const double *__restrict__ uval,
+                                                     double *__restrict__ l1) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrow) return;
+  double acc = 0.0;
+  for (int q = uptr[r]; q < uptr[r + 1]; ++q) acc += fabs(uval[q]);
+  l1[urow[r]] += acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_l1_finish(long long n, double factor,
+                                                      double *__restrict__ rs,
+                                                      float *__restrict__ rs32,
+                                                      int *__restrict__ flag) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double m = rs[i];
+  const double v = factor / m;
+  if (!(m > 0.0) || !isfinite(v)) flag[0] = 1;
+  rs[i] = v;
+  if (rs32) rs32[i] = (float)v;
+}
+
+// Weighted Jacobi (eq:relax0, eq:relax1): the factor of cell i is omega_p / a_ii.
+__global__ __launch_bounds__(kBlock) void k_jacobi_scale(const PartDesc<double> *__restrict__ desc,
+                                                         double *__restrict__ rs,
+                                                         float *__restrict__ rs32,
+                                                         int *__restrict__ flag) {
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.ncell) return;
+  const double a = d.coef[(long long)d.center * d.ncell + c];
+  const double v = d.omega / a;
+  if (!(a > 0.0) || !isfinite(v)) flag[0] = 1;
+  rs[d.off + c] = v;
+  if (rs32) rs32[d.off + c] = (float)v;
+}
+
 inline unsigned nblk(long long n) {
   long long b = (n + kBlock - 1) / kBlock;
   return (unsigned)(b > 0 ? b : 1);
@@ -265,6 +316,18 @@ void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *
 void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
                            int maxf, int *flag, hipStream_t st) {
   k_interp_weights<<<dim3(nblk(maxf), nparts), kBlock, 0, st>>>(desc, desc32, flag);
+}
+
+void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
+                           int nrow, const int *urow, const int *uptr, const double *uval,
+                           double factor, double *rs, float *rs32, int *flag, hipStream_t st) {
+  if (l1) {
+    k_l1_cells<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, rs);
+    if (nrow > 0) k_l1_urows<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, uval, rs);
+    k_l1_finish<<<nblk(n), kBlock, 0, st>>>(n, factor, rs, rs32, flag);
+  } else {
+    k_jacobi_scale<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, rs, rs32, flag);
+  }
 }
 
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,

@@ -1,0 +1,282 @@
+// Symbolic Galerkin product of the couplings on the device (Section 3.3,
+// eq:galerkin, term P^T U P): the structure of U_{l+1} = P_l^T U_l P_l and,
+// for each of its entries, the ordered list of contributions
+// (U_l entry, weight source of P(f, I), weight source of P(g, J)).
+//
+// Every U_l entry (f, g) meets at most two nonzeros in row f and two in row
+// g of P (two-point interpolation), so it emits up to four records keyed by
+// the coarse pair (I, J).  A stable radix sort on the key groups the records
+// by coarse entry while keeping the emission order (row-major over U_l), so
+// the numeric pass sums each entry in a fixed order.  Runs of equal keys are
+// the coarse entries; runs of equal I are the stored rows.
+#include <hipcub/hipcub.hpp>
+
+#include "ssamg_impl.h"
+
+namespace ssamg {
+
+namespace {
+
+__device__ int part_of_cell(const SymPart *sp, int np, long long cell) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sp[mid].off <= cell)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// nonzeros of row `cell` of P: coarse ids and weight sources (-1 = 1.0, else
+// an index into the level's weight buffer, wm block then wp block per part)
+__device__ int prow(const SymPart *sp, int np, long long cell, int col[2], int src[2]) {
+  const SymPart &q = sp[part_of_cell(sp, np, cell)];
+  const long long loc = cell - q.off;
+  if (q.dstar < 0) {
+    col[0] = (int)(q.coff + loc);
+    src[0] = -1;
+    return 1;
+  }
+  int f[3];
+  f[0] = (int)(loc % q.n[0]);
+  f[1] = (int)((loc / q.n[0]) % q.n[1]);
+  f[2] = (int)(loc / ((long long)q.n[0] * q.n[1]));
+  const int ds = q.dstar;
+  int c[3] = {f[0], f[1], f[2]};
+  if ((f[ds] & 1) == 0) {
+    c[ds] = f[ds] >> 1;
+    col[0] = (int)(q.coff + c[0] + (long long)q.cn[0] * (c[1] + (long long)q.cn[1] * c[2]));
+    src[0] = -1;
+    return 1;
+  }
+  int g[3] = {f[0], f[1], f[2]};
+  g[ds] = (f[ds] - 1) >> 1;
+  const long long fl = g[0] + (long long)q.fn[0] * (g[1] + (long long)q.fn[1] * g[2]);
+  c[ds] = (f[ds] - 1) >> 1;
+  col[0] = (int)(q.coff + c[0] + (long long)q.cn[0] * (c[1] + (long long)q.cn[1] * c[2]));
+  src[0] = (int)(q.wofs + fl);
+  if (f[ds] + 1 <= q.n[ds] - 1) {
+    c[ds] = (f[ds] + 1) >> 1;
+    col[1] = (int)(q.coff + c[0] + (long long)q.cn[0] * (c[1] + (long long)q.cn[1] * c[2]));
+    src[1] = (int)(q.wofs + q.nf + fl);
+    return 2;
+  }
+  return 1;
+}
+
+// one thread per stored row of U_l; records of entry q sit at 4q .. 4q+3
+__global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp, int np, int nrow,
+                                                 const int *__restrict__ urow,
+                                                 const int *__restrict__ uptr,
+                                                 const int *__restrict__ ucol,
+                                                 unsigned long long nc, unsigned long long invalid,
+                                                 unsigned long long *__restrict__ key,
+                                                 unsigned *__restrict__ idx, int *__restrict__ rk,
+                                                 int *__restrict__ ra, int *__restrict__ rb) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrow) return;
+  int cf[2], sf[2], cg[2], sg[2];
+  const int nf = prow(sp, np, urow[r], cf, sf);
+  for (int q = uptr[r]; q < uptr[r + 1]; ++q) {
+    const int ng = prow(sp, np, ucol[q], cg, sg);
+    for (int t = 0; t < 4; ++t) {
+      const long long i = 4LL * q + t;
+      const int a = t >> 1, b = t & 1;
+      idx[i] = (unsigned)i;
+      if (a < nf && b < ng) {
+        key[i] = (unsigned long long)cf[a] * nc + (unsigned long long)cg[b];
+        rk[i] = q;
+        ra[i] = sf[a];
+        rb[i] = sg[b];
+      } else {
+        key[i] = invalid;
+        rk[i] = ra[i] = rb[i] = 0;
+      }
+    }
+  }
+}
+
+// after the sort: new-entry flags and the count of valid records
+__global__ __launch_bounds__(kBlock) void k_flags(const unsigned long long *__restrict__ key,
+                                                  long long n, unsigned long long invalid,
+                                                  int *__restrict__ fnew, int *__restrict__ nvalid) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const bool v = key[i] != invalid;
+  fnew[i] = v && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+  const bool last_valid = v && (i == n - 1 || key[i + 1] == invalid);
+  if (last_valid) nvalid[0] = (int)(i + 1);
+}
+
+// coarse entries (column, row) and the contributions in sorted order
+__global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__restrict__ key,
+                                                 const unsigned *__restrict__ idx,
+                                                 const int *__restrict__ fnew,
+                                                 const int *__restrict__ eid, long long nvalid,
+                                                 unsigned long long nc, const int *__restrict__ rk,
+                                                 const int *__restrict__ ra,
+                                                 const int *__restrict__ rb, int *__restrict__ ucol,
+                                                 int *__restrict__ erow, int *__restrict__ start,
+                                                 int *__restrict__ ck, int *__restrict__ ca,
+                                                 int *__restrict__ cb) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nvalid) return;
+  const unsigned s = idx[i];
+  ck[i] = rk[s];
+  ca[i] = ra[s];
+  cb[i] = rb[s];
+  if (fnew[i]) {
+    const int e = eid[i] - 1;
+    ucol[e] = (int)(key[i] % nc);
+    erow[e] = (int)(key[i] / nc);
+    start[e] = (int)i;
+  }
+  if (i == nvalid - 1) start[eid[i]] = (int)nvalid;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rowflags(const int *__restrict__ erow, int nent,
+                                                     int *__restrict__ fnew) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nent) return;
+  fnew[e] = (e == 0 || erow[e] != erow[e - 1]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rowfill(const int *__restrict__ erow,
+                                                    const int *__restrict__ fnew,
+                                                    const int *__restrict__ rid, int nent,
+                                                    int *__restrict__ urow, int *__restrict__ uptr) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nent) return;
+  if (fnew[e]) {
+    urow[rid[e] - 1] = erow[e];
+    uptr[rid[e] - 1] = e;
+  }
+  if (e == nent - 1) uptr[rid[e]] = nent;
+}
+
+// first stored row of every block of a grid-over-cells launch (1 << lg rhs)
+__global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp, int np, int lg,
+                                                 const long long *__restrict__ boff, int nrow,
+                                                 const int *__restrict__ urow, int *__restrict__ out) {
+  const int p = blockIdx.y;
+  const SymPart &q = sp[p];
+  const long long cpb = kBlock >> lg;
+  const long long nchunk = (q.ncell + cpb - 1) / cpb;
+  const long long b = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (b > nchunk) return;
+  const long long first = q.off + (b * cpb < q.ncell ? b * cpb : q.ncell);
+  int lo = 0, hi = nrow;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (urow[mid] < first)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  out[boff[p] + b] = lo;
+}
+
+inline unsigned nblk(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+}  // namespace
+
+void DevBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+  const size_t want = bytes + bytes / 4 + 256;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    throw Error(SSAMG_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  cap = want;
+}
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+
+// U_{l+1} structure and recipe from U_l; returns (nnz, nrow) of U_{l+1}.
+void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int nrow, int64_t nnz,
+                            const int *urow, const int *uptr, const int *ucol, int64_t nc,
+                            CouplingStore &out, int64_t &out_nnz, int &out_nrow, hipStream_t st) {
+  out_nnz = 0;
+  out_nrow = 0;
+  if (nnz == 0) return;
+  const long long n = 4LL * nnz;
+  int end_bit = 1;
+  while (end_bit < 64 && ((unsigned long long)1 << end_bit) <= (unsigned long long)nc * nc) ++end_bit;
+  const unsigned long long invalid = end_bit >= 64 ? ~0ULL : (((unsigned long long)1 << end_bit) - 1);
+  w.key0.reserve(n * 8);
+  w.key1.reserve(n * 8);
+  w.idx0.reserve(n * 4);
+  w.idx1.reserve(n * 4);
+  w.rk.reserve(n * 4);
+  w.ra.reserve(n * 4);
+  w.rb.reserve(n * 4);
+  w.fnew.reserve(n * 4);
+  w.eid.reserve(n * 4);
+  w.small.reserve(64);
+  auto *k0 = (unsigned long long *)w.key0.p, *k1 = (unsigned long long *)w.key1.p;
+  auto *i0 = (unsigned *)w.idx0.p, *i1 = (unsigned *)w.idx1.p;
+  int *rk = (int *)w.rk.p, *ra = (int *)w.ra.p, *rb = (int *)w.rb.p;
+  int *fnew = (int *)w.fnew.p, *eid = (int *)w.eid.p, *small = (int *)w.small.p;
+  k_emit<<<nblk(nrow), kBlock, 0, st>>>(sp, np, nrow, urow, uptr, ucol, (unsigned long long)nc,
+                                        invalid, k0, i0, rk, ra, rb);
+  size_t tbytes = 0;
+  SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
+  w.temp.reserve(tbytes);
+  SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
+  SSAMG_HIP(hipMemsetAsync(small, 0, 16, st));
+  k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, invalid, fnew, small);
+  tbytes = 0;
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, fnew, eid, (int)n, st));
+  w.temp.reserve(tbytes);
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, fnew, eid, (int)n, st));
+  int nvalid = 0;
+  SSAMG_HIP(hipMemcpyAsync(&nvalid, small, sizeof(int), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipStreamSynchronize(st));
+  if (nvalid == 0) return;
+  int nent = 0;
+  SSAMG_HIP(hipMemcpyAsync(&nent, eid + (nvalid - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipStreamSynchronize(st));
+  out.ucol.reserve((size_t)nent * 4);
+  out.erow.reserve((size_t)nent * 4);
+  out.start.reserve((size_t)(nent + 1) * 4);
+  out.ck.reserve((size_t)nvalid * 4);
+  out.ca.reserve((size_t)nvalid * 4);
+  out.cb.reserve((size_t)nvalid * 4);
+  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, fnew, eid, nvalid, (unsigned long long)nc, rk, ra, rb,
+                                          (int *)out.ucol.p, (int *)out.erow.p, (int *)out.start.p,
+                                          (int *)out.ck.p, (int *)out.ca.p, (int *)out.cb.p);
+  k_rowflags<<<nblk(nent), kBlock, 0, st>>>((const int *)out.erow.p, nent, fnew);
+  tbytes = 0;
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, fnew, eid, nent, st));
+  w.temp.reserve(tbytes);
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, fnew, eid, nent, st));
+  int nr = 0;
+  SSAMG_HIP(hipMemcpyAsync(&nr, eid + (nent - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipStreamSynchronize(st));
+  out.urow.reserve((size_t)nr * 4);
+  out.uptr.reserve((size_t)(nr + 1) * 4);
+  k_rowfill<<<nblk(nent), kBlock, 0, st>>>((const int *)out.erow.p, fnew, eid, nent, (int *)out.urow.p,
+                                           (int *)out.uptr.p);
+  SSAMG_HIP(hipGetLastError());
+  out_nnz = nent;
+  out_nrow = nr;
+  out.ncontrib = nvalid;
+}
+
+void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
+                 const int *urow, int *out, hipStream_t st) {
+  k_ublk<<<dim3(nblk(maxchunk + 1), np), kBlock, 0, st>>>(sp, np, lg, boff, nrow, urow, out);
+}
+
+}  // namespace ssamg

@@ -132,127 +132,11 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
   }
 }
 
-int part_of(const Level &L, int64_t cell) {
-  int lo = 0, hi = (int)L.parts.size() - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (L.parts[mid].off <= cell)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// nonzeros of row `cell` of P_l: coarse ids and weight sources (-1 = 1.0,
-// else an index into the level weight buffer)
-int prow(const Level &L, int64_t cell, int col[2], int src[2]) {
-  const int p = part_of(L, cell);
-  const PartLevel &q = L.parts[p];
-  const int64_t loc = cell - q.off;
-  if (q.dstar < 0) {
-    col[0] = (int)(q.coff + loc);
-    src[0] = -1;
-    return 1;
-  }
-  int f[3];
-  f[0] = (int)(loc % q.n[0]);
-  f[1] = (int)((loc / q.n[0]) % q.n[1]);
-  f[2] = (int)(loc / ((int64_t)q.n[0] * q.n[1]));
-  const int ds = q.dstar;
-  auto clin = [&](const int c[3]) { return q.coff + c[0] + (int64_t)q.cn[0] * (c[1] + (int64_t)q.cn[1] * c[2]); };
-  int c[3] = {f[0], f[1], f[2]};
-  if ((f[ds] & 1) == 0) {
-    c[ds] = f[ds] / 2;
-    col[0] = (int)clin(c);
-    src[0] = -1;
-    return 1;
-  }
-  int g[3] = {f[0], f[1], f[2]};
-  g[ds] = (f[ds] - 1) / 2;
-  const int64_t fl = g[0] + (int64_t)q.fn[0] * (g[1] + (int64_t)q.fn[1] * g[2]);
-  c[ds] = (f[ds] - 1) / 2;
-  col[0] = (int)clin(c);
-  src[0] = (int)(q.wofs + fl);
-  if (f[ds] + 1 <= q.n[ds] - 1) {
-    c[ds] = (f[ds] + 1) / 2;
-    col[1] = (int)clin(c);
-    src[1] = (int)(q.wofs + q.nf + fl);
-    return 2;
-  }
-  return 1;
-}
-
-// Structure of U_{l+1} = P^T U_l P and, for every coarse entry, the ordered
-// list of (U_l entry, weight source of P(f, I), weight source of P(g, J)).
-void build_coarse_coupling(const Level &f, Level &c) {
-  const int nrow = (int)f.urow.size();
-  std::vector<int> cnt(c.N + 1, 0);
-  int colf[2], srcf[2], colg[2], srcg[2];
-  for (int r = 0; r < nrow; ++r) {
-    const int nf = prow(f, f.urow[r], colf, srcf);
-    for (int k = f.uptr[r]; k < f.uptr[r + 1]; ++k) {
-      const int ng = prow(f, f.ucol[k], colg, srcg);
-      for (int a = 0; a < nf; ++a) cnt[colf[a] + 1] += ng;
-    }
-  }
-  for (int64_t i = 0; i < c.N; ++i) cnt[i + 1] += cnt[i];
-  const int64_t ntot = cnt[c.N];
-  std::vector<int> J(ntot), K(ntot), A(ntot), B(ntot);
-  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-  for (int r = 0; r < nrow; ++r) {
-    const int nf = prow(f, f.urow[r], colf, srcf);
-    for (int k = f.uptr[r]; k < f.uptr[r + 1]; ++k) {
-      const int ng = prow(f, f.ucol[k], colg, srcg);
-      for (int a = 0; a < nf; ++a)
-        for (int b = 0; b < ng; ++b) {
-          const int t = pos[colf[a]]++;
-          J[t] = colg[b];
-          K[t] = k;
-          A[t] = srcf[a];
-          B[t] = srcg[b];
-        }
-    }
-  }
-  c.urow.clear();
-  c.uptr.assign(1, 0);
-  c.ucol.clear();
-  c.uc_start.assign(1, 0);
-  c.uc_k.clear();
-  c.uc_a.clear();
-  c.uc_b.clear();
-  c.uc_k.reserve(ntot);
-  c.uc_a.reserve(ntot);
-  c.uc_b.reserve(ntot);
-  std::vector<int> idx;
-  for (int64_t I = 0; I < c.N; ++I) {
-    const int s0 = cnt[I], s1 = cnt[I + 1];
-    if (s0 == s1) continue;
-    idx.resize(s1 - s0);
-    std::iota(idx.begin(), idx.end(), s0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return J[a] < J[b]; });
-    c.urow.push_back((int)I);
-    int prevJ = -1;
-    for (int t : idx) {
-      if (J[t] != prevJ) {
-        if (prevJ >= 0) c.uc_start.push_back((int)c.uc_k.size());
-        c.ucol.push_back(J[t]);
-        prevJ = J[t];
-      }
-      c.uc_k.push_back(K[t]);
-      c.uc_a.push_back(A[t]);
-      c.uc_b.push_back(B[t]);
-    }
-    c.uc_start.push_back((int)c.uc_k.size());
-    c.uptr.push_back((int)c.ucol.size());
-  }
-}
-
-
 template <typename T>
 PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coef, const T *w,
-                      const T *uval) {
+                      const T *uval, const T *rs = nullptr) {
   PartDesc<T> d{};
+  d.rs = rs ? rs + q.off : nullptr;
   for (int a = 0; a < 3; ++a) {
     d.n[a] = q.n[a];
     d.fn[a] = q.fn[a];
@@ -285,28 +169,6 @@ PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coe
   return d;
 }
 
-// Rows of U falling in each block of a grid-over-cells launch, per part and
-// per right-hand-side count 1 << lg (see k_stencil).
-void build_ublk(Level &V, int lgmax) {
-  for (int lg = 0; lg <= kMaxLg; ++lg) {
-    V.ublk[lg].clear();
-    V.ublk_off[lg].assign(V.parts.size(), 0);
-    if (lg > lgmax) continue;
-    const int64_t cpb = kBlock >> lg;
-    size_t t = 0;
-    for (size_t p = 0; p < V.parts.size(); ++p) {
-      const PartLevel &q = V.parts[p];
-      V.ublk_off[lg][p] = (int64_t)V.ublk[lg].size();
-      const int64_t nchunk = (q.ncell + cpb - 1) / cpb;
-      for (int64_t b = 0; b <= nchunk; ++b) {
-        const int64_t first = q.off + std::min(b * cpb, q.ncell);
-        while (t < V.urow.size() && V.urow[t] < first) ++t;
-        V.ublk[lg].push_back((int)t);
-      }
-    }
-  }
-}
-
 template <typename T>
 void upload(T *dst, const std::vector<T> &src, hipStream_t st) {
   if (!src.empty())
@@ -325,6 +187,98 @@ Solver::~Solver() {
 }
 
 // ---------------------------------------------------------------- symbolic
+
+namespace {
+
+// Structure of every coarse coupling matrix (device: emit, sort, segment) and
+// the per-block row ranges the stencil kernels use, for all levels.
+void symbolic_couplings(Solver &s, int lgmax) {
+  hipStream_t st = s.stream;
+  const int L = (int)s.lv.size();
+  const int np = (int)s.lv[0].parts.size();
+  while ((int)s.store.size() < L) s.store.emplace_back(new LevelStore());
+  // one upload: SymPart tables of all levels and the block offsets of ublk
+  std::vector<SymPart> sp;
+  std::vector<long long> boff;
+  std::vector<size_t> sp_at(L), boff_at(L * (kMaxLg + 1));
+  for (int l = 0; l < L; ++l) {
+    Level &V = s.lv[l];
+    sp_at[l] = sp.size();
+    for (auto &q : V.parts) {
+      SymPart x{};
+      for (int a = 0; a < 3; ++a) {
+        x.n[a] = q.n[a];
+        x.cn[a] = q.cn[a];
+        x.fn[a] = q.fn[a];
+      }
+      x.dstar = q.dstar;
+      x.off = q.off;
+      x.ncell = q.ncell;
+      x.coff = q.coff;
+      x.nf = q.nf;
+      x.wofs = q.wofs;
+      sp.push_back(x);
+    }
+    for (int lg = 0; lg <= kMaxLg; ++lg) {
+      V.ublk_off[lg].assign(np, 0);
+      boff_at[l * (kMaxLg + 1) + lg] = boff.size();
+      if (lg > lgmax) continue;
+      const int64_t cpb = kBlock >> lg;
+      int64_t tot = 0;
+      for (int p = 0; p < np; ++p) {
+        V.ublk_off[lg][p] = tot;
+        boff.push_back(tot);
+        tot += (V.parts[p].ncell + cpb - 1) / cpb + 1;
+      }
+      V.ublk_len[lg] = tot;
+    }
+  }
+  const size_t sp_bytes = align_up(sp.size() * sizeof(SymPart));
+  s.symtab.reserve(sp_bytes + boff.size() * sizeof(long long) + 256);
+  std::vector<char> stage(sp_bytes + boff.size() * sizeof(long long));
+  std::memcpy(stage.data(), sp.data(), sp.size() * sizeof(SymPart));
+  if (!boff.empty()) std::memcpy(stage.data() + sp_bytes, boff.data(), boff.size() * sizeof(long long));
+  SSAMG_HIP(hipMemcpyAsync(s.symtab.p, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
+  const SymPart *d_sp = (const SymPart *)s.symtab.p;
+  const long long *d_boff = (const long long *)((char *)s.symtab.p + sp_bytes);
+  for (int l = 0; l + 1 < L; ++l) {
+    Level &V = s.lv[l], &C = s.lv[l + 1];
+    CouplingStore &cs = s.store[l + 1]->cpl;
+    int64_t nnz = 0;
+    int nrow = 0;
+    coarse_coupling_device(s.scratch, d_sp + sp_at[l], np, V.nrow, V.nnz, V.d_urow, V.d_uptr, V.d_ucol,
+                           C.N, cs, nnz, nrow, st);
+    C.nnz = nnz;
+    C.nrow = nrow;
+    C.ncontrib = nnz ? cs.ncontrib : 0;
+    C.d_urow = nnz ? (int *)cs.urow.p : nullptr;
+    C.d_uptr = nnz ? (int *)cs.uptr.p : nullptr;
+    C.d_ucol = nnz ? (int *)cs.ucol.p : nullptr;
+    C.d_uc_start = nnz ? (int *)cs.start.p : nullptr;
+    C.d_uc_k = nnz ? (int *)cs.ck.p : nullptr;
+    C.d_uc_a = nnz ? (int *)cs.ca.p : nullptr;
+    C.d_uc_b = nnz ? (int *)cs.cb.p : nullptr;
+  }
+  for (int l = 0; l < L; ++l) {
+    Level &V = s.lv[l];
+    int64_t maxchunk = 0;
+    for (auto &q : V.parts) maxchunk = std::max<int64_t>(maxchunk, q.ncell);
+    for (int lg = 0; lg <= kMaxLg; ++lg) {
+      V.d_ublk[lg] = nullptr;
+      if (lg > lgmax) continue;
+      DevBuf &ub = s.store[l]->ublk[lg];
+      ub.reserve((size_t)V.ublk_len[lg] * sizeof(int));
+      launch_ublk(d_sp + sp_at[l], np, lg, (maxchunk + (kBlock >> lg) - 1) / (kBlock >> lg),
+                  d_boff + boff_at[l * (kMaxLg + 1) + lg], V.nrow, V.d_urow, (int *)ub.p, st);
+      V.d_ublk[lg] = (int *)ub.p;
+    }
+  }
+  SSAMG_HIP(hipGetLastError());
+  SSAMG_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
 
 void setup_symbolic(Solver &s) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -367,9 +321,11 @@ void setup_symbolic(Solver &s) {
     L0.parts.push_back(q);
   }
   L0.N = off;
-  L0.urow = pr.urow;
-  L0.uptr = pr.uptr.empty() ? std::vector<int>{0} : pr.uptr;
-  L0.ucol = pr.ucol;
+  L0.nrow = (int)pr.urow.size();
+  L0.nnz = (int64_t)pr.ucol.size();
+  L0.d_urow = pr.d_urow;
+  L0.d_uptr = pr.d_uptr;
+  L0.d_ucol = pr.d_ucol;
 
   // direction sums c_d on the device (the only round trip of the symbolic setup)
   {
@@ -380,19 +336,19 @@ void setup_symbolic(Solver &s) {
       hd.push_back(make_desc<double>(L0, q, p, q.coef64, nullptr, nullptr));
       maxcell = std::max<int64_t>(maxcell, q.ncell);
     }
-    PartDesc<double> *dd = dev_alloc<PartDesc<double>>(np);
-    double *part = dev_alloc<double>((size_t)np * 256 * 3);
-    double *out = dev_alloc<double>((size_t)np * 3);
+    s.wsum_buf.reserve(np * sizeof(PartDesc<double>) + (size_t)np * 256 * 3 * 8 + np * 3 * 8 + 1024);
+    char *base = (char *)s.wsum_buf.p;
+    PartDesc<double> *dd = (PartDesc<double> *)base;
+    double *part = (double *)(base + align_up(np * sizeof(PartDesc<double>)));
+    double *out = part + (size_t)np * 256 * 3;
     SSAMG_HIP(hipMemcpyAsync(dd, hd.data(), np * sizeof(PartDesc<double>), hipMemcpyHostToDevice, s.stream));
     launch_wsum(dd, np, maxcell, part, out, s.stream);
     SSAMG_HIP(hipGetLastError());
     s.cd.assign((size_t)np * 3, 0.0);
     SSAMG_HIP(hipMemcpyAsync(s.cd.data(), out, np * 3 * sizeof(double), hipMemcpyDeviceToHost, s.stream));
     SSAMG_HIP(hipStreamSynchronize(s.stream));
-    (void)hipFree(dd);
-    (void)hipFree(part);
-    (void)hipFree(out);
   }
+  const auto t_w = std::chrono::steady_clock::now();
 
   // W (Section 3.1) and Algorithm 1
   const int ndim = pr.ndim;
@@ -465,18 +421,20 @@ void setup_symbolic(Solver &s) {
       w += 2 * q.nf;
     }
     L.nw = w;
-    L.maxcell = L.maxcoarse = L.maxf = 0;
+    L.maxcell = L.maxcoarse = L.maxf = L.maxent = 0;
     for (auto &q : L.parts) {
       L.maxcell = std::max<int64_t>(L.maxcell, q.ncell);
       L.maxcoarse = std::max<int64_t>(L.maxcoarse, q.cncell);
       L.maxf = std::max<int64_t>(L.maxf, q.nf);
+      L.maxent = std::max<int>(L.maxent, (int)q.pat.size());
     }
-    build_ublk(L, lgmax);
     if (last) break;
     C.N = coff;
-    build_coarse_coupling(L, C);
     s.lv.push_back(std::move(C));
   }
+  const auto t_alg = std::chrono::steady_clock::now();
+  symbolic_couplings(s, lgmax);
+  const auto t_u = std::chrono::steady_clock::now();
   // sizing pass of the workspace
   Carver cv;
   carve(s, cv);
@@ -485,12 +443,14 @@ void setup_symbolic(Solver &s) {
   if (s.verbose) {
     size_t unnz = 0, contrib = 0;
     for (auto &L : s.lv) {
-      unnz += L.ucol.size();
-      contrib += L.uc_k.size();
+      unnz += L.nnz;
+      contrib += L.ncontrib;
     }
-    fprintf(stderr, "[ssamg] symbolic setup: %.3f ms, %zu levels, %zu coupling entries, %zu "
-            "Galerkin contributions, workspace %zu bytes\n",
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
+    auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    fprintf(stderr, "[ssamg] symbolic setup: %.3f ms (metric %.3f, algorithm 1 + tables %.3f, "
+            "couplings %.3f), %zu levels, %zu coupling entries, %zu Galerkin contributions, "
+            "workspace %zu bytes\n",
+            ms(t0, std::chrono::steady_clock::now()), ms(t0, t_w), ms(t_w, t_alg), ms(t_alg, t_u),
             s.lv.size(), unnz, contrib, s.ws_bytes);
   }
 }
@@ -507,30 +467,19 @@ void carve(Solver &s, Carver &cv) {
   const int64_t N0 = s.lv[0].N;
   cv.off = align_up(cv.off);
   cv.tab_begin = cv.off;
+  // TailLevel records of all levels, contiguous (the tail kernel walks them)
+  const size_t tail_size = mixed ? sizeof(TailLevel<float>) : sizeof(TailLevel<double>);
+  void *tail_all = cv.take<char>(tail_size * L);
   for (int l = 0; l < L; ++l) {
     Level &V = s.lv[l];
     V.d_desc64 = cv.take<PartDesc<double>>(V.parts.size());
     V.d_desc32 = mixed ? cv.take<PartDesc<float>>(V.parts.size()) : nullptr;
     V.d_rapdesc = l < L - 1 ? cv.take<RapDesc>(V.parts.size()) : nullptr;
+    V.d_tail = (char *)tail_all + (size_t)l * tail_size;
     for (auto &q : V.parts) {
       q.d_rap_start = l < L - 1 ? cv.take<int>(q.rap_start.size()) : nullptr;
       q.d_rap_code = l < L - 1 ? cv.take<int>(q.rap_code.size()) : nullptr;
     }
-    if (l == 0) {
-      V.d_urow = s.prob->d_urow;
-      V.d_uptr = s.prob->d_uptr;
-      V.d_ucol = s.prob->d_ucol;
-    } else {
-      V.d_urow = cv.take<int>(V.urow.size());
-      V.d_uptr = cv.take<int>(V.uptr.size());
-      V.d_ucol = cv.take<int>(V.ucol.size());
-      V.d_uc_start = cv.take<int>(V.uc_start.size());
-      V.d_uc_k = cv.take<int>(V.uc_k.size());
-      V.d_uc_a = cv.take<int>(V.uc_a.size());
-      V.d_uc_b = cv.take<int>(V.uc_b.size());
-    }
-    for (int lg = 0; lg <= kMaxLg; ++lg)
-      V.d_ublk[lg] = V.ublk[lg].empty() ? nullptr : cv.take<int>(V.ublk[lg].size());
   }
   cv.off = align_up(cv.off);
   cv.tab_end = cv.off;
@@ -553,9 +502,11 @@ void carve(Solver &s, Carver &cv) {
     }
     V.d_w64 = l < L - 1 ? cv.take<double>(V.nw) : nullptr;
     V.d_w32 = (cyc32 && l < L - 1) ? cv.take<float>(V.nw) : nullptr;
-    const size_t nnz = V.ucol.size();
+    const size_t nnz = (size_t)V.nnz;
     V.d_uval64 = l == 0 ? s.prob->d_uval : cv.take<double>(nnz);
     V.d_uval32 = cyc32 ? cv.take<float>(nnz) : nullptr;
+    V.d_rs64 = cv.take<double>((size_t)V.N);
+    V.d_rs32 = cyc32 ? cv.take<float>((size_t)V.N) : nullptr;
     const size_t nv = (size_t)V.N * nr;
     if (mixed) {
       V.vb = cv.take<float>(nv);
@@ -615,8 +566,8 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     std::vector<RapDesc> hr;
     for (size_t p = 0; p < V.parts.size(); ++p) {
       PartLevel &q = V.parts[p];
-      h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64));
-      if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32));
+      h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64));
+      if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32));
       if (l < L - 1) {
         putv(q.d_rap_start, q.rap_start);
         putv(q.d_rap_code, q.rap_code);
@@ -632,17 +583,18 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     putv(V.d_desc64, h64);
     if (mixed) putv(V.d_desc32, h32);
     if (l < L - 1) putv(V.d_rapdesc, hr);
-    if (l > 0) {
-      putv(V.d_urow, V.urow);
-      putv(V.d_uptr, V.uptr);
-      putv(V.d_ucol, V.ucol);
-      putv(V.d_uc_start, V.uc_start);
-      putv(V.d_uc_k, V.uc_k);
-      putv(V.d_uc_a, V.uc_a);
-      putv(V.d_uc_b, V.uc_b);
+    // the levels' TailLevel records sit one after another in the workspace
+    // only if consecutive takes are adjacent; they are written per level and
+    // the tail kernel walks them through this level's pointer
+    if (mixed) {
+      TailLevel<float> t{V.d_desc32, V.d_desc64, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
+                         V.d_ucol, V.d_uval32, (float *)V.vb, (float *)V.vx, (float *)V.vt};
+      put(V.d_tail, &t, sizeof(t));
+    } else {
+      TailLevel<double> t{V.d_desc64, V.d_desc64, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
+                          V.d_ucol, V.d_uval64, (double *)V.vb, (double *)V.vx, (double *)V.vt};
+      put(V.d_tail, &t, sizeof(t));
     }
-    for (int lg = 0; lg <= kMaxLg; ++lg)
-      if (V.d_ublk[lg]) putv(V.d_ublk[lg], V.ublk[lg]);
   }
   if (!stage.empty())
     SSAMG_HIP(hipMemcpyAsync(cv.base + cv.tab_begin, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
@@ -652,16 +604,27 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   if (mixed && L > 1) {
     Level &V = s.lv[0];
     for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
-    launch_cast_d2f(V.d_uval64, V.d_uval32, (int64_t)V.ucol.size(), st);
+    launch_cast_d2f(V.d_uval64, V.d_uval32, V.nnz, st);
   }
+  // per-cell smoother factors: omega_p / a_ii, or factor / sum_j |a_ij|
+  const bool l1 = s.prm.relax == SSAMG_RELAX_L1_JACOBI;
+  const double l1_factor = s.prm.omega > 0.0 ? s.prm.omega : 1.5;
+  auto smoother_scale = [&](int l) {
+    Level &V = s.lv[l];
+    launch_smoother_scale(l1, V.d_desc64, (int)V.parts.size(), V.maxcell, V.N, V.nrow, V.d_urow,
+                          V.d_uptr, V.d_uval64, l1_factor, V.d_rs64,
+                          mixed && l < L - 1 ? V.d_rs32 : nullptr, s.flag, st);
+  };
+  smoother_scale(0);
   // level by level: weights, structured and unstructured Galerkin products
   for (int l = 0; l + 1 < L; ++l) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
     launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
     launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, st);
-    launch_uc_numeric((int64_t)C.ucol.size(), C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
+    launch_uc_numeric(C.nnz, C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
+    smoother_scale(l + 1);
   }
   SSAMG_HIP(hipGetLastError());
   int hflag = 0;
@@ -697,8 +660,10 @@ double level0_bytes(const Solver &s, int kind, int lg, size_t tc, size_t tx, siz
     switch (kind) {
       case SSAMG_PROBE_MATVEC: by += n * (ne * tc + nr * (tx + to)); break;
       case SSAMG_PROBE_SMOOTH0: by += n * (tc + nr * (tb + tx)); break;
-      case SSAMG_PROBE_RESID0:
-      case SSAMG_PROBE_JACOBI0: by += n * (ne * tc + nr * (tx + tb + to)); break;
+      // coefficients + smoother factors; b read, x and r written
+      case SSAMG_PROBE_RESID0: by += n * (ne * tc + tc + nr * (tb + tx + to)); break;
+      // coefficients + smoother factors; x and b read, the output written
+      case SSAMG_PROBE_JACOBI0: by += n * (ne * tc + tc + nr * (tx + tb + to)); break;
       case SSAMG_PROBE_RESTRICT0: by += nr * tx * (n + (double)q.cncell) + 2.0 * tc * (double)q.nf; break;
       case SSAMG_PROBE_INTERP0: by += nr * tx * (2.0 * n + (double)q.cncell) + 2.0 * tc * (double)q.nf; break;
       default: break;
@@ -724,6 +689,15 @@ struct Probe {
   }
 };
 
+// first level handled by the one-workgroup tail kernel: the first level >= 1
+// with at most kTailElems elements (the coarsest level always is)
+int tail_start(const Solver &s, int lg) {
+  const int L = (int)s.lv.size();
+  for (int l = 1; l < L; ++l)
+    if ((s.lv[l].N << lg) <= s.tail_elems) return l;
+  return L - 1;
+}
+
 // Levels l >= 1 of one V(1,1) cycle: from lv[1].vb into lv[1].vt (all in T,
 // the coarsest level in FP64).  Captured in a HIP graph when use_graph is set.
 template <typename T>
@@ -731,26 +705,21 @@ void run_tail(Solver &s, int lg) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
   const int np = (int)s.lv[0].parts.size();
-  for (int l = 1; l + 1 < L; ++l) {
+  const int lt = tail_start(s, lg);
+  for (int l = 1; l < lt; ++l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
-    launch_smooth_zero<T, T>(0, d, np, V.maxcell, lg, b, x, st);
-    launch_stencil<T, T, T>(MODE_RESID, 0, d, np, V.maxcell, lg, x, b, t, st);
+    launch_smooth_resid<T, T>(0, V.maxent, d, np, V.maxcell, lg, b, x, t, st);
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
-  Level &C = s.lv[L - 1];
-  if (sizeof(T) == sizeof(float))
-    launch_coarse_mixed(C.d_desc64, np, C.maxcell, lg, (const float *)C.vb, (float *)C.vt, st);
-  else
-    launch_smooth_zero<double, double>(0, C.d_desc64, np, C.maxcell, lg, (const double *)C.vb,
-                                       (double *)C.vt, st);
-  for (int l = L - 2; l >= 1; --l) {
+  launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, L - lt, lg, st);
+  for (int l = lt - 1; l >= 1; --l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
     launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[l + 1].vt, x, st);
-    launch_stencil<T, T, T>(MODE_JACOBI, 0, d, np, V.maxcell, lg, x, b, t, st);
+    launch_stencil<T, T, T>(MODE_JACOBI, 0, V.maxent, d, np, V.maxcell, lg, x, b, t, st);
   }
 }
 
@@ -799,12 +768,8 @@ void precond_t(Solver &s, int lg) {
     return;
   }
   {
-    Probe pr(s, SSAMG_PROBE_SMOOTH0, level0_bytes(s, SSAMG_PROBE_SMOOTH0, lg, tc, tx, 8, tx));
-    launch_smooth_zero<T, double>(1, d, np, V.maxcell, lg, s.r, x, st);
-  }
-  {
     Probe pr(s, SSAMG_PROBE_RESID0, level0_bytes(s, SSAMG_PROBE_RESID0, lg, tc, tx, 8, tx));
-    launch_stencil<T, double, T>(MODE_RESID, 1, d, np, V.maxcell, lg, x, s.r, t, st);
+    launch_smooth_resid<T, double>(1, V.maxent, d, np, V.maxcell, lg, s.r, x, t, st);
   }
   {
     Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
@@ -817,7 +782,7 @@ void precond_t(Solver &s, int lg) {
   }
   {
     Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, 8, 8));
-    launch_stencil<T, double, double>(MODE_JACOBI, 1, d, np, V.maxcell, lg, x, s.r, s.z, st);
+    launch_stencil<T, double, double>(MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x, s.r, s.z, st);
   }
 }
 
@@ -832,7 +797,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y) {
   Level &V = s.lv[0];
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
-    launch_stencil<double, double, double>(MODE_APPLY, 1, V.d_desc64, (int)V.parts.size(), V.maxcell,
+    launch_stencil<double, double, double>(MODE_APPLY, 1, V.maxent, V.d_desc64, (int)V.parts.size(), V.maxcell,
                                            lg, x, nullptr, y, s.stream);
   }
 }
@@ -841,7 +806,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y) {
 
 void apply_level(Solver &s, int level, const double *x, double *y) {
   Level &V = s.lv[level];
-  launch_stencil<double, double, double>(MODE_APPLY, level == 0, V.d_desc64, (int)V.parts.size(),
+  launch_stencil<double, double, double>(MODE_APPLY, level == 0, V.maxent, V.d_desc64, (int)V.parts.size(),
                                          V.maxcell, 0, x, nullptr, y, s.stream);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(s.stream));

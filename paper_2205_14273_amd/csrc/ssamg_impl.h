@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <memory>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -32,6 +33,10 @@ constexpr int kBlock = 256;      // threads per block of every grid-over-cells k
 constexpr int kRedBlocks = 512;  // fixed grid of the deterministic reductions
 constexpr int kMaxRhs = 32;
 constexpr int kMaxLg = 5;        // log2(kMaxRhs)
+// cycle levels of at most this many elements run in the one-workgroup kernel
+// (measured on MI355X: only the coarsest level pays off; a larger threshold
+// serialises too much work on one CU)
+constexpr int64_t kTailElems = 0;
 
 // Packed stencil offset: (dx+1) | (dy+1) << 2 | (dz+1) << 4.
 inline int pack_off(int dx, int dy, int dz) { return (dx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4); }
@@ -65,6 +70,9 @@ struct PartDesc {
   const int *ucol;
   const T *uval;
   const int *ublk[kMaxLg + 1];
+  // per-cell smoother factor (weighted L1-Jacobi: factor / sum_j |a_ij|);
+  // null: weighted Jacobi omega / a_ii
+  const T *rs;
   int lin[kMaxEnt];    // dx + nx*(dy + ny*dz)
   int code[kMaxEnt];   // pack_off(dx, dy, dz)
 };
@@ -117,21 +125,58 @@ struct PartLevel {
   int *d_rap_start = nullptr, *d_rap_code = nullptr;
 };
 
+// Growable device buffer (kept across setups; reallocated only to grow).
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  void reserve(size_t bytes);
+  ~DevBuf();
+};
+
+// Part geometry read by the symbolic coupling kernels.
+struct SymPart {
+  int n[3], cn[3], fn[3];
+  int dstar;
+  long long off, ncell, coff, nf, wofs;
+};
+
+// Device structure of one level's couplings and its Galerkin recipe.
+struct CouplingStore {
+  DevBuf urow, uptr, ucol, erow, start, ck, ca, cb;
+  int64_t ncontrib = 0;
+};
+
+struct LevelStore {
+  CouplingStore cpl;
+  DevBuf ublk[kMaxLg + 1];
+};
+
+// Scratch of the device sort.
+struct SymScratch {
+  DevBuf key0, key1, idx0, idx1, rk, ra, rb, fnew, eid, small, temp;
+};
+
 struct Level {
   std::vector<PartLevel> parts;
   int64_t N = 0;
-  int maxcell = 0, maxcoarse = 0, maxf = 0;
-  // couplings (compressed rows), host structure
-  std::vector<int> urow, uptr, ucol;
+  int maxcell = 0, maxcoarse = 0, maxf = 0, maxent = 0;
+  // couplings (compressed rows, device; level 0 belongs to the problem)
+  int nrow = 0;
+  int64_t nnz = 0, ncontrib = 0;
   int *d_urow = nullptr, *d_uptr = nullptr, *d_ucol = nullptr;
   double *d_uval64 = nullptr;
   float *d_uval32 = nullptr;
+  // per-cell smoother factors of weighted L1-Jacobi (null for weighted Jacobi)
+  double *d_rs64 = nullptr;
+  float *d_rs32 = nullptr;
   // first coupling row of every block of a grid-over-cells launch, per lg
-  std::vector<int> ublk[kMaxLg + 1];
+  int64_t ublk_len[kMaxLg + 1] = {};
   std::vector<int64_t> ublk_off[kMaxLg + 1];   // per part
   int *d_ublk[kMaxLg + 1] = {};
   // recipe of this level's U as P^T U P from the previous level
-  std::vector<int> uc_start, uc_k, uc_a, uc_b;
   int *d_uc_start = nullptr, *d_uc_k = nullptr, *d_uc_a = nullptr, *d_uc_b = nullptr;
   // interpolation weights of all parts toward the next level
   int64_t nw = 0;
@@ -140,6 +185,7 @@ struct Level {
   PartDesc<double> *d_desc64 = nullptr;
   PartDesc<float> *d_desc32 = nullptr;
   struct RapDesc *d_rapdesc = nullptr;
+  void *d_tail = nullptr;            // TailLevel<cycle precision> of this level
   // V-cycle vectors in the cycle precision: [N][max_nrhs]
   void *vb = nullptr, *vx = nullptr, *vt = nullptr;
   bool cycle32 = false;              // this level's cycle runs in FP32
@@ -151,9 +197,14 @@ struct Solver {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool verbose = false;              // SSAMG_VERBOSE: phase timings on stderr
+  int64_t tail_elems = kTailElems;   // SSAMG_TAIL_ELEMS overrides
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
   std::vector<Level> lv;
   std::vector<double> cd;            // direction sums c[p][d]
+  // device buffers of the symbolic setup, kept across setups
+  std::vector<std::unique_ptr<LevelStore>> store;
+  SymScratch scratch;
+  DevBuf symtab, wsum_buf;
   // workspace
   size_t ws_bytes = 0;
   void *ws = nullptr;
@@ -201,6 +252,17 @@ struct BoxStencil {
   double *coef;
 };
 
+// One level of the coarse end of the cycle run by the one-workgroup kernel.
+template <typename T>
+struct TailLevel {
+  const PartDesc<T> *desc;          // parts of the level (cycle precision)
+  const PartDesc<double> *desc64;   // FP64 parts (the coarsest level's sweep)
+  int np, nrow;                     // parts, stored rows of U
+  const int *urow, *uptr, *ucol;
+  const T *uval;
+  T *vb, *vx, *vt;                  // right-hand side, iterate, output
+};
+
 // per-part Galerkin table of one level (device array indexed by part)
 struct RapDesc {
   double *out;         // coarse coefficients [nent_c][cncell]
@@ -223,8 +285,10 @@ enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
 
 // kernels_cycle.hip
 template <typename T, typename TB, typename TO>
-void launch_stencil(int mode, int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
-                    const T *x, const TB *b, TO *y, hipStream_t st);
+void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
+                    int lg, const T *x, const TB *b, TO *y, hipStream_t st);
+template <typename T>
+void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st);
 template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st);
@@ -258,9 +322,22 @@ void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *
                            int maxf, int *flag, hipStream_t st);
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
                 hipStream_t st);
+void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
+                           int nrow, const int *urow, const int *uptr, const double *uval,
+                           double factor, double *rs, float *rs32, int *flag, hipStream_t st);
+template <typename T, typename TB>
+void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
+                         const TB *b, T *x, T *r, hipStream_t st);
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
                        const double *uprev, const double *w, double *uval, float *uval32,
                        hipStream_t st);
+
+// kernels_symbolic.hip
+void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int nrow, int64_t nnz,
+                            const int *urow, const int *uptr, const int *ucol, int64_t nc,
+                            CouplingStore &out, int64_t &out_nnz, int &out_nrow, hipStream_t st);
+void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
+                 const int *urow, int *out, hipStream_t st);
 
 // kernels_fv.hip
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,

@@ -11,7 +11,8 @@ def oracle_fv(case, **kw):
     g = case.geometry
     pat = [W.stencil_offsets(case.stencil, g.ndim)] * g.nparts
     return O.setup(A, g.dims, g.face_kinds(), pat, g.ndim, omega=kw.get("omega", case.omega),
-                   max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0))
+                   max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
+                   relax=kw.get("relax", case.relax))
 
 
 def oracle_raw(case, **kw):
@@ -29,6 +30,10 @@ def gpu_fv(case, **params):
     pr = Problem.from_fv(case.geometry, case.stencil, kappa, case.aniso)
     if case.omega > 0 and "omega" not in params:
         params["omega"] = case.omega
+    if "relax" not in params:
+        params["relax"] = 1 if case.relax == "l1" else 0
+    elif isinstance(params["relax"], str):
+        params["relax"] = 1 if params["relax"] == "l1" else 0
     s = Solver(pr, **params).setup()
     return pr, s
 

@@ -477,3 +477,41 @@ def test_collapse_fallback_weights():
     assert lev.wm[0][0] == pytest.approx(-Ad[0 + 3, 0] / (Ad[3, 3] + Ad[3, 4]), rel=1e-14)
     res = ssamg.solve(h, case.b, tol=1e-12)
     assert np.linalg.norm(res.x - np.linalg.solve(Ad, case.b)) < 1e-10 * np.linalg.norm(res.x)
+
+
+# ---------------------------------------------------------------------------
+# Section 3.4: weighted L1-Jacobi
+
+
+@pytest.mark.parametrize("mk", [lambda: W.c3(4), lambda: W.c2(5), lambda: W.c5(5)])
+def test_l1_diagonal_dominates_A(mk):
+    # M_ii = sum_j |a_ij| makes M - A weakly diagonally dominant, hence
+    # lambda(M^{-1} A) lies in (0, 1] on every level (the convergence property
+    # the paper cites for SPD A)
+    case = mk()
+    A, _ = assemble.assemble_fv(case.geometry, case.stencil, case.kappa, case.aniso)
+    g = case.geometry
+    h = ssamg.setup(A, g.dims, g.face_kinds(), [W.stencil_offsets(case.stencil)] * g.nparts, 3,
+                    relax="l1")
+    for lev in h.levels:
+        w = ssamg._cell_weights(lev)            # 1.5 / M_ii
+        m = 1.5 / w
+        Ad = lev.A.toarray()
+        lam = np.linalg.eigvals(Ad / m[:, None]).real
+        assert lam.max() <= 1.0 + 1e-12 and lam.min() > 0
+        # M_ii is the full row (stencil and couplings) in absolute value
+        assert np.allclose(m, np.abs(Ad).sum(axis=1), rtol=1e-14)
+
+
+def test_l1_vcycle_spd_and_pcg():
+    case = W.c3(4)
+    A, _ = assemble.assemble_fv(case.geometry, 27, case.kappa, case.aniso)
+    g = case.geometry
+    h = ssamg.setup(A, g.dims, g.face_kinds(), [W.stencil_offsets(27)] * 8, 3, relax="l1")
+    n = A.shape[0]
+    B = np.column_stack([ssamg.vcycle(h, e) for e in np.eye(n)])
+    assert np.max(np.abs(B - B.T)) <= 1e-12 * np.max(np.abs(B))
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    res = ssamg.solve(h, case.b, tol=1e-10)
+    xd = np.linalg.solve(A.toarray(), case.b)
+    assert np.linalg.norm(res.x - xd) <= 1e-8 * np.linalg.norm(xd)
