@@ -66,59 +66,71 @@ __device__ int prow(const SymPart *sp, int np, long long cell, int col[2], int s
   return 1;
 }
 
-// one thread per stored row of U_l; records of entry q sit at 4q .. 4q+3
-__global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp, int np, int nrow,
-                                                 const int *__restrict__ urow,
-                                                 const int *__restrict__ uptr,
+// one thread per entry q of U_l (row cell erow[q]); its records sit at 4q .. 4q+3
+__global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp, int np, long long nnz,
+                                                 const int *__restrict__ erow,
                                                  const int *__restrict__ ucol,
                                                  unsigned long long nc, unsigned long long invalid,
                                                  unsigned long long *__restrict__ key,
                                                  unsigned *__restrict__ idx, int *__restrict__ rk,
                                                  int *__restrict__ ra, int *__restrict__ rb) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= nrow) return;
+  const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= nnz) return;
   int cf[2], sf[2], cg[2], sg[2];
-  const int nf = prow(sp, np, urow[r], cf, sf);
-  for (int q = uptr[r]; q < uptr[r + 1]; ++q) {
-    const int ng = prow(sp, np, ucol[q], cg, sg);
-    for (int t = 0; t < 4; ++t) {
-      const long long i = 4LL * q + t;
-      const int a = t >> 1, b = t & 1;
-      idx[i] = (unsigned)i;
-      if (a < nf && b < ng) {
-        key[i] = (unsigned long long)cf[a] * nc + (unsigned long long)cg[b];
-        rk[i] = q;
-        ra[i] = sf[a];
-        rb[i] = sg[b];
-      } else {
-        key[i] = invalid;
-        rk[i] = ra[i] = rb[i] = 0;
-      }
+  const int nf = prow(sp, np, erow[q], cf, sf);
+  const int ng = prow(sp, np, ucol[q], cg, sg);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const long long i = 4LL * q + t;
+    const int a = t >> 1, b = t & 1;
+    idx[i] = (unsigned)i;
+    if (a < nf && b < ng) {
+      key[i] = (unsigned long long)cf[a] * nc + (unsigned long long)cg[b];
+      rk[i] = (int)q;
+      ra[i] = sf[a];
+      rb[i] = sg[b];
+    } else {
+      key[i] = invalid;
+      rk[i] = ra[i] = rb[i] = 0;
     }
   }
 }
 
-// after the sort: new-entry flags and the count of valid records
+// after the sort: flags of records that open a coarse entry / a coarse row,
+// and the count of valid records (invalid keys sort last)
 __global__ __launch_bounds__(kBlock) void k_flags(const unsigned long long *__restrict__ key,
-                                                  long long n, unsigned long long invalid,
-                                                  int *__restrict__ fnew, int *__restrict__ nvalid) {
+                                                  long long n, unsigned long long nc,
+                                                  unsigned long long invalid, int *__restrict__ fnew,
+                                                  int *__restrict__ frow, int *__restrict__ small) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const bool v = key[i] != invalid;
   fnew[i] = v && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
-  const bool last_valid = v && (i == n - 1 || key[i + 1] == invalid);
-  if (last_valid) nvalid[0] = (int)(i + 1);
+  frow[i] = v && (i == 0 || key[i] / nc != key[i - 1] / nc) ? 1 : 0;
+  if (v && (i == n - 1 || key[i + 1] == invalid)) small[0] = (int)(i + 1);
 }
 
-// coarse entries (column, row) and the contributions in sorted order
+// entry and row counts from the inclusive scans
+__global__ void k_counts(const int *__restrict__ eid, const int *__restrict__ rid,
+                         int *__restrict__ small) {
+  const int nvalid = small[0];
+  small[1] = nvalid > 0 ? eid[nvalid - 1] : 0;
+  small[2] = nvalid > 0 ? rid[nvalid - 1] : 0;
+}
+
+// coarse entries (column, row), rows (cell, first entry) and the
+// contributions in sorted order
 __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__restrict__ key,
                                                  const unsigned *__restrict__ idx,
                                                  const int *__restrict__ fnew,
-                                                 const int *__restrict__ eid, long long nvalid,
+                                                 const int *__restrict__ frow,
+                                                 const int *__restrict__ eid,
+                                                 const int *__restrict__ rid, long long nvalid,
                                                  unsigned long long nc, const int *__restrict__ rk,
                                                  const int *__restrict__ ra,
                                                  const int *__restrict__ rb, int *__restrict__ ucol,
                                                  int *__restrict__ erow, int *__restrict__ start,
+                                                 int *__restrict__ urow, int *__restrict__ uptr,
                                                  int *__restrict__ ck, int *__restrict__ ca,
                                                  int *__restrict__ cb) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -127,33 +139,29 @@ __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__res
   ck[i] = rk[s];
   ca[i] = ra[s];
   cb[i] = rb[s];
+  const int e = eid[i] - 1;
   if (fnew[i]) {
-    const int e = eid[i] - 1;
     ucol[e] = (int)(key[i] % nc);
     erow[e] = (int)(key[i] / nc);
     start[e] = (int)i;
   }
-  if (i == nvalid - 1) start[eid[i]] = (int)nvalid;
-}
-
-__global__ __launch_bounds__(kBlock) void k_rowflags(const int *__restrict__ erow, int nent,
-                                                     int *__restrict__ fnew) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= nent) return;
-  fnew[e] = (e == 0 || erow[e] != erow[e - 1]) ? 1 : 0;
-}
-
-__global__ __launch_bounds__(kBlock) void k_rowfill(const int *__restrict__ erow,
-                                                    const int *__restrict__ fnew,
-                                                    const int *__restrict__ rid, int nent,
-                                                    int *__restrict__ urow, int *__restrict__ uptr) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= nent) return;
-  if (fnew[e]) {
-    urow[rid[e] - 1] = erow[e];
-    uptr[rid[e] - 1] = e;
+  if (frow[i]) {
+    urow[rid[i] - 1] = (int)(key[i] / nc);
+    uptr[rid[i] - 1] = e;
   }
-  if (e == nent - 1) uptr[rid[e]] = nent;
+  if (i == nvalid - 1) {
+    start[e + 1] = (int)nvalid;
+    uptr[rid[i]] = e + 1;
+  }
+}
+
+// entry -> row cell of a compressed-row matrix (the emitter's input)
+__global__ __launch_bounds__(kBlock) void k_entry_rows(int nrow, const int *__restrict__ urow,
+                                                       const int *__restrict__ uptr,
+                                                       int *__restrict__ erow) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrow) return;
+  for (int q = uptr[r]; q < uptr[r + 1]; ++q) erow[q] = urow[r];
 }
 
 // first stored row of every block of a grid-over-cells launch (1 << lg rhs)
@@ -203,10 +211,11 @@ DevBuf::~DevBuf() {
   if (p) (void)hipFree(p);
 }
 
-// U_{l+1} structure and recipe from U_l; returns (nnz, nrow) of U_{l+1}.
-void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int nrow, int64_t nnz,
-                            const int *urow, const int *uptr, const int *ucol, int64_t nc,
-                            CouplingStore &out, int64_t &out_nnz, int &out_nrow, hipStream_t st) {
+// U_{l+1} structure and recipe from U_l (entries with row cells erow);
+// returns (nnz, nrow) of U_{l+1}.  One host synchronization.
+void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nnz, const int *erow,
+                            const int *ucol, int64_t nc, CouplingStore &out, int64_t &out_nnz,
+                            int &out_nrow, hipStream_t st) {
   out_nnz = 0;
   out_nrow = 0;
   if (nnz == 0) return;
@@ -222,56 +231,58 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int nrow, 
   w.ra.reserve(n * 4);
   w.rb.reserve(n * 4);
   w.fnew.reserve(n * 4);
+  w.frow.reserve(n * 4);
   w.eid.reserve(n * 4);
+  w.rid.reserve(n * 4);
   w.small.reserve(64);
+  if (!w.host_small) {
+    void *h = nullptr;
+    SSAMG_HIP(hipHostMalloc(&h, 64));
+    w.host_small = (int *)h;
+  }
   auto *k0 = (unsigned long long *)w.key0.p, *k1 = (unsigned long long *)w.key1.p;
   auto *i0 = (unsigned *)w.idx0.p, *i1 = (unsigned *)w.idx1.p;
   int *rk = (int *)w.rk.p, *ra = (int *)w.ra.p, *rb = (int *)w.rb.p;
-  int *fnew = (int *)w.fnew.p, *eid = (int *)w.eid.p, *small = (int *)w.small.p;
-  k_emit<<<nblk(nrow), kBlock, 0, st>>>(sp, np, nrow, urow, uptr, ucol, (unsigned long long)nc,
-                                        invalid, k0, i0, rk, ra, rb);
+  int *fnew = (int *)w.fnew.p, *frow = (int *)w.frow.p, *eid = (int *)w.eid.p, *rid = (int *)w.rid.p;
+  int *small = (int *)w.small.p;
+  k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
+                                       rk, ra, rb);
   size_t tbytes = 0;
   SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
   w.temp.reserve(tbytes);
   SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
   SSAMG_HIP(hipMemsetAsync(small, 0, 16, st));
-  k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, invalid, fnew, small);
+  k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, fnew, frow, small);
   tbytes = 0;
   SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, fnew, eid, (int)n, st));
   w.temp.reserve(tbytes);
   SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, fnew, eid, (int)n, st));
-  int nvalid = 0;
-  SSAMG_HIP(hipMemcpyAsync(&nvalid, small, sizeof(int), hipMemcpyDeviceToHost, st));
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, frow, rid, (int)n, st));
+  k_counts<<<1, 1, 0, st>>>(eid, rid, small);
+  SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   SSAMG_HIP(hipStreamSynchronize(st));
+  const int nvalid = w.host_small[0], nent = w.host_small[1], nr = w.host_small[2];
   if (nvalid == 0) return;
-  int nent = 0;
-  SSAMG_HIP(hipMemcpyAsync(&nent, eid + (nvalid - 1), sizeof(int), hipMemcpyDeviceToHost, st));
-  SSAMG_HIP(hipStreamSynchronize(st));
   out.ucol.reserve((size_t)nent * 4);
   out.erow.reserve((size_t)nent * 4);
   out.start.reserve((size_t)(nent + 1) * 4);
+  out.urow.reserve((size_t)nr * 4);
+  out.uptr.reserve((size_t)(nr + 1) * 4);
   out.ck.reserve((size_t)nvalid * 4);
   out.ca.reserve((size_t)nvalid * 4);
   out.cb.reserve((size_t)nvalid * 4);
-  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, fnew, eid, nvalid, (unsigned long long)nc, rk, ra, rb,
-                                          (int *)out.ucol.p, (int *)out.erow.p, (int *)out.start.p,
+  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, fnew, frow, eid, rid, nvalid, (unsigned long long)nc,
+                                          rk, ra, rb, (int *)out.ucol.p, (int *)out.erow.p,
+                                          (int *)out.start.p, (int *)out.urow.p, (int *)out.uptr.p,
                                           (int *)out.ck.p, (int *)out.ca.p, (int *)out.cb.p);
-  k_rowflags<<<nblk(nent), kBlock, 0, st>>>((const int *)out.erow.p, nent, fnew);
-  tbytes = 0;
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, fnew, eid, nent, st));
-  w.temp.reserve(tbytes);
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, fnew, eid, nent, st));
-  int nr = 0;
-  SSAMG_HIP(hipMemcpyAsync(&nr, eid + (nent - 1), sizeof(int), hipMemcpyDeviceToHost, st));
-  SSAMG_HIP(hipStreamSynchronize(st));
-  out.urow.reserve((size_t)nr * 4);
-  out.uptr.reserve((size_t)(nr + 1) * 4);
-  k_rowfill<<<nblk(nent), kBlock, 0, st>>>((const int *)out.erow.p, fnew, eid, nent, (int *)out.urow.p,
-                                           (int *)out.uptr.p);
   SSAMG_HIP(hipGetLastError());
   out_nnz = nent;
   out_nrow = nr;
   out.ncontrib = nvalid;
+}
+
+void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hipStream_t st) {
+  if (nrow > 0) k_entry_rows<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, erow);
 }
 
 void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,

@@ -28,9 +28,11 @@ void Problem::free_device() {
     c = nullptr;
   }
   for (void *p : {(void *)d_urow, (void *)d_uptr, (void *)d_ucol, (void *)d_uval, (void *)d_kappa,
-                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom})
+                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom, (void *)d_cptr})
     if (p) (void)hipFree(p);
   d_urow = d_uptr = d_ucol = d_ucode = d_geom = nullptr;
+  d_cptr = nullptr;
+  fv_structure_ready = false;
   d_uval = d_kappa = d_aniso = nullptr;
 }
 
@@ -189,6 +191,7 @@ ssamg_status ssamg_problem_set_box(ssamg_problem prob, int part, const int lo[3]
     if (pr->coef[part]) (void)hipFree(pr->coef[part]);
     pr->coef[part] = nullptr;
     pr->coef_set[part] = 0;
+    pr->fv_structure_ready = false;
   }
   API_END
 }
@@ -200,6 +203,7 @@ ssamg_status ssamg_problem_set_origin(ssamg_problem prob, int part, const int or
   if (!origin) throw Error(SSAMG_ERR_ARG, "NULL origin");
   pr->origin[part] = {origin[0], origin[1], pr->ndim == 2 ? 0 : origin[2]};
   pr->has_origin[part] = 1;
+  pr->fv_structure_ready = false;
   API_END
 }
 
@@ -210,6 +214,7 @@ ssamg_status ssamg_problem_set_face(ssamg_problem prob, int part, int face, int 
   if (face < 0 || face > 5) throw Error(SSAMG_ERR_ARG, "face must be 0..5");
   if (kind != SSAMG_FACE_PHYSICAL && kind != SSAMG_FACE_PART) throw Error(SSAMG_ERR_ARG, "bad face kind");
   pr->faces[part][face] = kind;
+  pr->fv_structure_ready = false;
   API_END
 }
 
@@ -237,6 +242,7 @@ ssamg_status ssamg_problem_set_stencil(ssamg_problem prob, int part, int nent, c
     if (pr->coef[part]) (void)hipFree(pr->coef[part]);
     pr->coef[part] = nullptr;
     pr->coef_set[part] = 0;
+    pr->fv_structure_ready = false;
   }
   API_END
 }
@@ -283,6 +289,7 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
   (void)hipFree(flag);
   SSAMG_HIP(hipGetLastError());
   pr->coef_set[part] = 1;
+  pr->fv_structure_ready = false;
   if (hflag) throw Error(SSAMG_ERR_NUMERIC, "nonpositive diagonal or non-finite coefficient");
   API_END
 }
@@ -312,6 +319,7 @@ ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const i
   dev_upload(pr->d_ucol, pr->ucol);
   dev_upload(pr->d_uval, pr->uval_host);
   pr->coupling_set = true;
+  pr->fv_structure_ready = false;
   API_END
 }
 
@@ -359,11 +367,23 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
     if (pr->stencil[p] != st_off || !pr->coef[p]) {
       if (pr->coef[p]) (void)hipFree(pr->coef[p]);
       pr->coef[p] = dev_alloc<double>((size_t)nent * nc);
+      pr->fv_structure_ready = false;
     }
     pr->stencil[p] = st_off;
     pr->center[p] = 0;
     pr->coef_set[p] = 1;
   }
+  // the face kinds, the geometry table and the coupling structure depend on
+  // the placement and the stencil only: rebuilt when those change
+  std::vector<int> sig = {pr->ndim, pr->nparts, stencil};
+  for (int p = 0; p < pr->nparts; ++p)
+    for (int d = 0; d < 3; ++d) {
+      sig.push_back(pr->dims[p][d]);
+      sig.push_back(pr->origin[p][d]);
+    }
+  const bool same_geometry = pr->fv_structure_ready && sig == pr->fv_signature;
+  if (!same_geometry) {
+  pr->fv_structure_ready = false;
   derive_faces(pr);
   // geometry table
   std::vector<int> geom(7 * pr->nparts);
@@ -440,12 +460,18 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
   if (pr->d_uval) (void)hipFree(pr->d_uval);
   pr->d_uval = dev_alloc<double>(pr->ucol.size());
   pr->coupling_set = true;
-  // conductivity and anisotropy copies
+  std::vector<double *> cptr(pr->coef.begin(), pr->coef.end());
+  dev_upload(pr->d_cptr, cptr);
   if (pr->d_kappa) (void)hipFree(pr->d_kappa);
   pr->d_kappa = dev_alloc<double>(N);
+  if (pr->d_aniso) (void)hipFree(pr->d_aniso);
+  pr->d_aniso = dev_alloc<double>(3 * pr->nparts);
+  pr->fv_signature = sig;
+  pr->fv_structure_ready = true;
+  }
+  // conductivity and anisotropy copies
   SSAMG_HIP(hipMemcpyAsync(pr->d_kappa, kappa, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-  std::vector<double> an(aniso, aniso + 3 * pr->nparts);
-  dev_upload(pr->d_aniso, an);
+  SSAMG_HIP(hipMemcpyAsync(pr->d_aniso, aniso, 3 * pr->nparts * sizeof(double), hipMemcpyHostToDevice, st));
   pr->fv_stencil = stencil;
   // kernels
   FvArgs fa{};
@@ -453,15 +479,11 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
   fa.nparts = pr->nparts;
   fa.nent = nent;
   for (int e = 0; e < nent; ++e) fa.code[e] = pack_off(st_off[e][0], st_off[e][1], st_off[e][2]);
-  std::vector<double *> cptr(pr->coef.begin(), pr->coef.end());
-  double **d_cptr = dev_alloc<double *>(cptr.size());
-  SSAMG_HIP(hipMemcpy(d_cptr, cptr.data(), cptr.size() * sizeof(double *), hipMemcpyHostToDevice));
-  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, d_cptr, st);
+  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, pr->d_cptr, st);
   launch_fv_coupling((int)pr->urow.size(), pr->d_urow, pr->d_uptr, pr->d_ucol, pr->d_ucode,
                      pr->d_kappa, pr->d_aniso, pr->d_uval, st);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(st));
-  (void)hipFree(d_cptr);
   API_END
 }
 

@@ -241,19 +241,28 @@ void symbolic_couplings(Solver &s, int lgmax) {
   SSAMG_HIP(hipMemcpyAsync(s.symtab.p, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
   const SymPart *d_sp = (const SymPart *)s.symtab.p;
   const long long *d_boff = (const long long *)((char *)s.symtab.p + sp_bytes);
+  {
+    // entry -> row cell of the input couplings
+    Level &V0 = s.lv[0];
+    DevBuf &e0 = s.store[0]->cpl.erow;
+    e0.reserve((size_t)std::max<int64_t>(V0.nnz, 1) * sizeof(int));
+    launch_entry_rows(V0.nrow, V0.d_urow, V0.d_uptr, (int *)e0.p, st);
+    V0.d_erow = (int *)e0.p;
+  }
   for (int l = 0; l + 1 < L; ++l) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     CouplingStore &cs = s.store[l + 1]->cpl;
     int64_t nnz = 0;
     int nrow = 0;
-    coarse_coupling_device(s.scratch, d_sp + sp_at[l], np, V.nrow, V.nnz, V.d_urow, V.d_uptr, V.d_ucol,
-                           C.N, cs, nnz, nrow, st);
+    coarse_coupling_device(s.scratch, d_sp + sp_at[l], np, V.nnz, V.d_erow, V.d_ucol, C.N, cs, nnz, nrow,
+                           st);
     C.nnz = nnz;
     C.nrow = nrow;
     C.ncontrib = nnz ? cs.ncontrib : 0;
     C.d_urow = nnz ? (int *)cs.urow.p : nullptr;
     C.d_uptr = nnz ? (int *)cs.uptr.p : nullptr;
     C.d_ucol = nnz ? (int *)cs.ucol.p : nullptr;
+    C.d_erow = nnz ? (int *)cs.erow.p : nullptr;
     C.d_uc_start = nnz ? (int *)cs.start.p : nullptr;
     C.d_uc_k = nnz ? (int *)cs.ck.p : nullptr;
     C.d_uc_a = nnz ? (int *)cs.ca.p : nullptr;

@@ -101,6 +101,9 @@ struct Problem {
   double *d_aniso = nullptr;
   int *d_ucode = nullptr;            // per coupling entry: offset code | p_i << 5 | p_j << 18
   int *d_geom = nullptr;             // per part: origin[3], dims[3], offset
+  double **d_cptr = nullptr;         // device copy of coef[]
+  std::vector<int> fv_signature;     // placement + stencil the FV structure was built for
+  bool fv_structure_ready = false;
   int64_t ncell_total() const;
   std::vector<int64_t> offsets() const;
   void free_device();
@@ -156,7 +159,11 @@ struct LevelStore {
 
 // Scratch of the device sort.
 struct SymScratch {
-  DevBuf key0, key1, idx0, idx1, rk, ra, rb, fnew, eid, small, temp;
+  DevBuf key0, key1, idx0, idx1, rk, ra, rb, fnew, frow, eid, rid, small, temp;
+  int *host_small = nullptr;         // pinned
+  ~SymScratch() {
+    if (host_small) (void)hipHostFree(host_small);
+  }
 };
 
 struct Level {
@@ -167,6 +174,7 @@ struct Level {
   int nrow = 0;
   int64_t nnz = 0, ncontrib = 0;
   int *d_urow = nullptr, *d_uptr = nullptr, *d_ucol = nullptr;
+  int *d_erow = nullptr;             // row cell of every entry
   double *d_uval64 = nullptr;
   float *d_uval32 = nullptr;
   // per-cell smoother factors of weighted L1-Jacobi (null for weighted Jacobi)
@@ -333,9 +341,10 @@ void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a
                        hipStream_t st);
 
 // kernels_symbolic.hip
-void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int nrow, int64_t nnz,
-                            const int *urow, const int *uptr, const int *ucol, int64_t nc,
-                            CouplingStore &out, int64_t &out_nnz, int &out_nrow, hipStream_t st);
+void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nnz, const int *erow,
+                            const int *ucol, int64_t nc, CouplingStore &out, int64_t &out_nnz,
+                            int &out_nrow, hipStream_t st);
+void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hipStream_t st);
 void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
                  const int *urow, int *out, hipStream_t st);
 
