@@ -50,11 +50,10 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the source file that defines the probed cycle kernels."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2205_14273_amd", "csrc"))):
-        if f.endswith(".hip"):
-            with open(os.path.join(ROOT, "paper_2205_14273_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2205_14273_amd", "csrc", "kernels_vcycle.hip"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -88,6 +87,9 @@ def main():
     ap.add_argument("--probe", default="jacobi0", choices=sorted(PROBES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the reference kernel "
+                         "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,6 +108,16 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}))
+        return
 
     mk = W.CONFIGS[args.config]
     case = mk(args.m) if args.m else mk()

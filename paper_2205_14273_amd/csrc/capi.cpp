@@ -93,7 +93,9 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   s->verbose = verbose && verbose[0] && verbose[0] != '0';
   // cycle levels of at most this many elements run in the one-workgroup kernel
   const char *tail = std::getenv("SSAMG_TAIL_ELEMS");
-  if (tail && tail[0]) s->tail_elems = std::max<int64_t>(0, std::atoll(tail));
+  if (tail && tail[0]) s->tail_elems = std::min<int64_t>(kTailMax, std::max<int64_t>(0, std::atoll(tail)));
+  const char *split = std::getenv("SSAMG_SPLIT_CELLS");
+  if (split && split[0]) s->split_cells = std::max<int64_t>(0, std::atoll(split));
   void *pin = nullptr;
   if (hipHostMalloc(&pin, kScalSlots * kMaxRhs * sizeof(double)) != hipSuccess) {
     delete s;

@@ -3,6 +3,7 @@
 // 3.2, eq:prolEx), the structured Galerkin product P^T S P as a stencil triple
 // product (Section 3.3), the numeric part of P^T U P, and the relaxation
 // scale of the coupling rows.
+#include "device_util.h"
 #include "ssamg_impl.h"
 
 namespace ssamg {
@@ -154,19 +155,30 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
 // q = r + s_d* is even and an F cell (weights wm(g), wp(g) toward its two
 // coarse neighbours) when q is odd.  The host table lists, for each coarse
 // entry, the (r, s, which-weight-of-g) triples that land on it.
+//
+// One thread per (coarse cell, coarse entry); a block covers one entry of a
+// tile of kBlock coarse cells, so its threads read the same table rows (scalar
+// loads) and neighbouring fine coefficients (coalesced).  The blocks of one
+// tile (one per coarse entry) are consecutive in the XCD-aware block order, so
+// they run together on one XCD and read the tile's fine coefficients through
+// its L2 rather than once per entry from HBM.  Each thread gathers its
+// contributions kRapBatch at a time with every load in flight before the sums,
+// which keep the table order.
+constexpr int kRapBatch = 4;
+
 __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restrict__ desc,
-                                                const RapDesc *__restrict__ rd) {
+                                                const RapDesc *__restrict__ rd, int nent_max) {
   const PartDesc<double> &d = desc[blockIdx.y];
   const RapDesc &t = rd[blockIdx.y];
-  const long long cidx = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (cidx >= d.cncell) return;
+  const int lb = dev::chunk_index();
+  const int e = lb % nent_max;
+  const long long cidx = (long long)(lb / nent_max) * kBlock + threadIdx.x;
+  if (e >= t.nent || cidx >= d.cncell) return;
   if (d.dstar < 0) {
     // identity transfer: same operator, entries permuted into the sorted pattern
-    for (int e = 0; e < t.nent; ++e) {
-      const double v = d.coef[(long long)t.code[e] * d.ncell + cidx];
-      t.out[(long long)e * d.cncell + cidx] = v;
-      if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)v;
-    }
+    const double v = d.coef[(long long)t.code[e] * d.ncell + cidx];
+    t.out[(long long)e * d.cncell + cidx] = v;
+    if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)v;
     return;
   }
   const int ds = d.dstar;
@@ -187,37 +199,47 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
     g[ds] = ci[ds];
     rho[2] = row_ok[2] ? d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
   }
-  for (int e = 0; e < t.nent; ++e) {
-    double acc = 0.0;
-    for (int q = t.start[e]; q < t.start[e + 1]; ++q) {
+  double acc = 0.0;
+  const int q0 = t.start[e], q1 = t.start[e + 1];
+  for (int qb = q0; qb < q1; qb += kRapBatch) {
+    double av[kRapBatch], wv[kRapBatch], rv[kRapBatch];
+#pragma unroll
+    for (int u = 0; u < kRapBatch; ++u) {
+      const int q = qb + u;
+      av[u] = 0.0;
+      wv[u] = 1.0;
+      rv[u] = 0.0;
+      if (q >= q1) continue;
       const int w = t.code[q];
       const int r = (w & 3) - 1;
-      const int s = (w >> 2) & 31;
+      const int sidx = (w >> 2) & 31;
       const int gsel = (w >> 7) & 3;
       if (!row_ok[r + 1]) continue;
       int f[3] = {ci[0], ci[1], ci[2]};
       f[ds] = fb + r;
       int g[3];
       bool in = true;
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
-        g[a] = f[a] + off_comp(d.code[s], a);
+        g[a] = f[a] + off_comp(d.code[sidx], a);
         in = in && g[a] >= 0 && g[a] < d.n[a];
       }
       if (!in) continue;
       const long long fl = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
-      const double a = d.coef[(long long)s * d.ncell + fl];
-      double wg = 1.0;
+      av[u] = d.coef[(long long)sidx * d.ncell + fl];
+      rv[u] = rho[r + 1];
       if (gsel != 0) {
         int h[3] = {g[0], g[1], g[2]};
         h[ds] = (g[ds] - 1) >> 1;
         const long long hl = h[0] + (long long)d.fn[0] * (h[1] + (long long)d.fn[1] * h[2]);
-        wg = gsel == 1 ? d.wm[hl] : d.wp[hl];
+        wv[u] = gsel == 1 ? d.wm[hl] : d.wp[hl];
       }
-      acc = fma(rho[r + 1] * a, wg, acc);
     }
-    t.out[(long long)e * d.cncell + cidx] = acc;
-    if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)acc;
+#pragma unroll
+    for (int u = 0; u < kRapBatch; ++u) acc = fma(rv[u] * av[u], wv[u], acc);
   }
+  t.out[(long long)e * d.cncell + cidx] = acc;
+  if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)acc;
 }
 
 // U_c = P^T U P on the host-built structure: each coarse entry sums, in a
@@ -331,8 +353,10 @@ void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, in
 }
 
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
-                hipStream_t st) {
-  k_rap<<<dim3(nblk(maxcoarse), nparts), kBlock, 0, st>>>(desc, rd);
+                int maxent_c, hipStream_t st) {
+  // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies
+  const unsigned nb = (nblk(maxcoarse) * (unsigned)maxent_c + 7u) & ~7u;
+  k_rap<<<dim3(nb, nparts), kBlock, 0, st>>>(desc, rd, maxent_c);
 }
 
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,

@@ -165,9 +165,11 @@ __global__ __launch_bounds__(kBlock) void k_entry_rows(int nrow, const int *__re
 }
 
 // first stored row of every block of a grid-over-cells launch (1 << lg rhs)
+// and that row's first entry: out[2b] = row, out[2b + 1] = uptr[row]
 __global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp, int np, int lg,
                                                  const long long *__restrict__ boff, int nrow,
-                                                 const int *__restrict__ urow, int *__restrict__ out) {
+                                                 const int *__restrict__ urow,
+                                                 const int *__restrict__ uptr, int *__restrict__ out) {
   const int p = blockIdx.y;
   const SymPart &q = sp[p];
   const long long cpb = kBlock >> lg;
@@ -183,7 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp,
     else
       hi = mid;
   }
-  out[boff[p] + b] = lo;
+  out[2 * (boff[p] + b)] = lo;
+  out[2 * (boff[p] + b) + 1] = nrow > 0 ? uptr[lo] : 0;
 }
 
 inline unsigned nblk(long long n) {
@@ -286,8 +289,8 @@ void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hi
 }
 
 void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
-                 const int *urow, int *out, hipStream_t st) {
-  k_ublk<<<dim3(nblk(maxchunk + 1), np), kBlock, 0, st>>>(sp, np, lg, boff, nrow, urow, out);
+                 const int *urow, const int *uptr, int *out, hipStream_t st) {
+  k_ublk<<<dim3(nblk(maxchunk + 1), np), kBlock, 0, st>>>(sp, np, lg, boff, nrow, urow, uptr, out);
 }
 
 }  // namespace ssamg

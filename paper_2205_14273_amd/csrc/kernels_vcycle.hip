@@ -13,6 +13,8 @@
 // eq:relax0), restriction R = P^T and interpolation by the two-point stencil
 // of eq:prolEx (Sections 3.2, 3.3), and the semi-structured product
 // A x = S x + U x (Section 2).
+#include <hip/hip_ext.h>
+
 #include "device_util.h"
 #include "ssamg_impl.h"
 
@@ -25,7 +27,6 @@ using dev::chunk_index;
 using dev::nb_mask;
 using dev::nb_ok;
 
-constexpr int kTailThreads = 1024;
 
 // smoother factor of cell c: omega_p / a_ii (Jacobi) or factor / sum|a_ij| (L1)
 template <typename T>
@@ -54,6 +55,30 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
   return acc;
 }
 
+// sum_s a_s(c) w(c + s) b(c + s): the stencil part of A x at cell c for the
+// iterate x = w b of a first sweep from zero (bp points at b of cell c)
+template <typename T, typename TB, int NENT>
+__device__ __forceinline__ T stencil_wb(const PartDesc<T> &d, int c, int lg, const TB *bp) {
+  int i, j, k;
+  cell_ijk(c, d.n[0], d.n[1], i, j, k);
+  const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
+  const T *cf = d.coef + c;
+  const T *wp = d.rs + c;
+  T a[NENT], bv[NENT], wv[NENT];
+#pragma unroll
+  for (int s = 0; s < NENT; ++s) {
+    const bool act = s < d.nent;
+    const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
+    a[s] = act ? cf[(long long)s * d.ncell] : T(0);
+    bv[s] = ok ? (T)bp[(long long)d.lin[s] << lg] : T(0);
+    wv[s] = ok ? wp[d.lin[s]] : T(0);
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int s = 0; s < NENT; ++s) acc = fma(a[s], wv[s] * bv[s], acc);
+  return acc;
+}
+
 // row r of U times x, four entries in flight at a time
 template <typename T>
 __device__ __forceinline__ T coupling_row(const int *__restrict__ uptr, const int *__restrict__ ucol,
@@ -76,6 +101,74 @@ __device__ __forceinline__ T coupling_row(const int *__restrict__ uptr, const in
     for (int t = 0; t < 4; ++t) acc = fma(vv[t], xx[t], acc);
   }
   return acc;
+}
+
+// coupling products staged in LDS per pass: large levels (short rows, and full
+// occupancy matters for bandwidth) and small levels (rows up to ~100 entries
+// across mismatched part interfaces; few blocks, so fewer passes matter)
+constexpr int kUChunkBig = 1024;
+constexpr int kUChunkSmall = 4096;
+constexpr long long kBigLevel = 1 << 18;   // cells from which a level counts as large
+
+// The U part of A x for every (cell, rhs) slot of one block: sum over the
+// entries of the slot's row of val * xs(col, rhs).  The rows of a block and
+// their entries are contiguous (rows sorted by cell), so all threads form the
+// products of a strided share of the entries (coalesced loads, every gather in
+// flight at once), stage them in LDS, and one thread per (row, rhs) adds its
+// row's products in entry order (deterministic).  Long rows, which coarse
+// levels build across mismatched part interfaces, thus cost no serial chain of
+// loads.  Must be called by every thread of the block.
+template <int UCH, typename T, typename XS>
+__device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int lg, XS xs,
+                                            T *__restrict__ prod, T *__restrict__ rsum) {
+  const int *ub = d.ublk[lg] + 2 * chunk;
+  const int u0 = ub[0], e0 = ub[1], u1 = ub[2], e1 = ub[3];
+  if (u0 == u1) return T(0);                          // block-uniform
+  const int tid = threadIdx.x;
+  const int mask = (1 << lg) - 1;
+  const int cell0 = (int)d.off + chunk * (kBlock >> lg);
+  const int nrt = (u1 - u0) << lg;                    // (row, rhs) slots of the block
+  int rq0 = 0, rq1 = 0, rslot = 0;
+  if (tid < nrt) {
+    const int r = u0 + (tid >> lg);
+    rq0 = d.uptr[r];
+    rq1 = d.uptr[r + 1];
+    rslot = ((d.urow[r] - cell0) << lg) | (tid & mask);
+  }
+  rsum[tid] = T(0);
+  T racc = T(0);
+  const int per = UCH >> lg;                      // entries per pass
+  for (int ec = e0; ec < e1; ec += per) {
+    const int np = min(per, e1 - ec) << lg;
+    int cc[UCH / kBlock];
+    T vv[UCH / kBlock], xx[UCH / kBlock];
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      const bool in = q < np;
+      cc[t] = in ? d.ucol[ec + (q >> lg)] : 0;
+      vv[t] = in ? d.uval[ec + (q >> lg)] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      xx[t] = q < np ? xs(cc[t], q & mask) : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      if (q < np) prod[q] = vv[t] * xx[t];
+    }
+    __syncthreads();
+    if (tid < nrt) {
+      const int qa = max(rq0, ec), qb = min(rq1, ec + (np >> lg));
+      for (int q = qa; q < qb; ++q) racc += prod[((q - ec) << lg) | (tid & mask)];
+    }
+    __syncthreads();
+  }
+  if (tid < nrt) rsum[rslot] = racc;
+  __syncthreads();
+  return rsum[tid];
 }
 
 // b_c = P^T r for coarse cell cc: r(2I) + wp(2I-1) r(2I-1) + wm(2I+1) r(2I+1)
@@ -144,14 +237,16 @@ __device__ __forceinline__ void interp_one(const PartDesc<T> &d, int c, int kr, 
 // y = S x + U x (APPLY), r = b - A x (RESID) or x' = x + w (b - A x) (JACOBI,
 // w the smoother factor) over every cell of every part.  T: coefficients and
 // x; TB: b; TO: output.  NENT bounds the entries of the level's stencils.
-// FINE marks finest-level launches (own instantiation: in a mixed-precision
-// cycle they read the FP64 residual and write the FP64 correction directly).
-// Blocks that hold rows of U map those rows to their cell slots in LDS.
-template <typename T, int MODE, typename TB, typename TO, int FINE, int NENT>
+// BIG marks launches on large levels (the finest level always; there, in a
+// mixed-precision cycle, they read the FP64 residual and write the FP64
+// correction directly); it sets the LDS chunk of the coupling products.
+template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
 __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restrict__ desc, int lg,
                                                     const T *__restrict__ x,
                                                     const TB *__restrict__ b, TO *__restrict__ y) {
-  __shared__ int urow_of[kBlock];
+  constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
+  __shared__ T prod[UCH];
+  __shared__ T rsum[kBlock];
   const PartDesc<T> &d = desc[blockIdx.y];
   const int chunk = chunk_index();
   const long long e = (long long)chunk * kBlock + threadIdx.x;
@@ -163,17 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   const long long o = ((d.off + c) << lg) + kr;
   const T *xp = x + o;
   T acc = valid ? stencil_acc<T, NENT>(d, c, lg, xp) : T(0);
-  const int u0 = d.ublk[lg][chunk], u1 = d.ublk[lg][chunk + 1];
-  if (u0 < u1) {
-    const int cpb = kBlock >> lg;
-    const int cell0 = (int)d.off + chunk * cpb;
-    if ((int)threadIdx.x < cpb) urow_of[threadIdx.x] = -1;
-    __syncthreads();
-    for (int t = u0 + (int)threadIdx.x; t < u1; t += kBlock) urow_of[d.urow[t] - cell0] = t;
-    __syncthreads();
-    const int r = urow_of[threadIdx.x >> lg];
-    if (valid && r >= 0) acc += coupling_row<T>(d.uptr, d.ucol, d.uval, r, lg, kr, x);
-  }
+  acc += block_coupling<UCH>(
+      d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
   if (!valid) return;
   if (MODE == MODE_APPLY) {
     y[o] = (TO)acc;
@@ -187,11 +273,13 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
 // The first sweep of eq:relax0 from a zero guess, x = w b, fused with the
 // residual r = b - A x: the iterate at a neighbour is formed there from its
 // own factor and right-hand side, so x and b are each read once.
-template <typename T, typename TB, int FINE, int NENT>
+template <typename T, typename TB, int BIG, int NENT>
 __global__ __launch_bounds__(kBlock) void k_smooth_resid(const PartDesc<T> *__restrict__ desc, int lg,
                                                          const TB *__restrict__ b,
                                                          T *__restrict__ x, T *__restrict__ r) {
-  __shared__ int urow_of[kBlock];
+  constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
+  __shared__ T prod[UCH];
+  __shared__ T rsum[kBlock];
   const PartDesc<T> &d = desc[blockIdx.y];
   const int chunk = chunk_index();
   const long long e = (long long)chunk * kBlock + threadIdx.x;
@@ -203,53 +291,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_resid(const PartDesc<T> *__re
   const long long o = ((d.off + c) << lg) + kr;
   const TB *bp = b + o;
   const T *wp = d.rs + c;
-  T acc = T(0);
-  if (valid) {
-    int i, j, k;
-    cell_ijk(c, d.n[0], d.n[1], i, j, k);
-    const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
-    const T *cf = d.coef + c;
-    T a[NENT], bv[NENT], wv[NENT];
-#pragma unroll
-    for (int s = 0; s < NENT; ++s) {
-      const bool act = s < d.nent;
-      const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
-      a[s] = act ? cf[(long long)s * d.ncell] : T(0);
-      bv[s] = ok ? (T)bp[(long long)d.lin[s] << lg] : T(0);
-      wv[s] = ok ? wp[d.lin[s]] : T(0);
-    }
-#pragma unroll
-    for (int s = 0; s < NENT; ++s) acc = fma(a[s], wv[s] * bv[s], acc);
-  }
-  const int u0 = d.ublk[lg][chunk], u1 = d.ublk[lg][chunk + 1];
-  if (u0 < u1) {
-    const int cpb = kBlock >> lg;
-    const int cell0 = (int)d.off + chunk * cpb;
-    if ((int)threadIdx.x < cpb) urow_of[threadIdx.x] = -1;
-    __syncthreads();
-    for (int t = u0 + (int)threadIdx.x; t < u1; t += kBlock) urow_of[d.urow[t] - cell0] = t;
-    __syncthreads();
-    const int rr = urow_of[threadIdx.x >> lg];
-    if (valid && rr >= 0) {
-      const T *wl = d.rs - d.off;   // factors of the whole level
-      const int q0 = d.uptr[rr], q1 = d.uptr[rr + 1];
-      for (int q = q0; q < q1; q += 4) {
-        int cc[4];
-        T vv[4], xx[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bool in = q + t < q1;
-          cc[t] = in ? d.ucol[q + t] : 0;
-          vv[t] = in ? d.uval[q + t] : T(0);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          xx[t] = q + t < q1 ? wl[cc[t]] * (T)b[((long long)cc[t] << lg) + kr] : T(0);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc = fma(vv[t], xx[t], acc);
-      }
-    }
-  }
+  T acc = valid ? stencil_wb<T, TB, NENT>(d, c, lg, bp) : T(0);
+  const T *wl = d.rs - d.off;   // factors of the whole level
+  acc += block_coupling<UCH>(
+      d, chunk, lg, [&](int col, int k) { return wl[col] * (T)b[((long long)col << lg) + k]; }, prod,
+      rsum);
   if (!valid) return;
   const T b0 = (T)bp[0];
   x[o] = wp[0] * b0;
@@ -300,88 +346,141 @@ __global__ __launch_bounds__(kBlock) void k_interp_add(const PartDesc<T> *__rest
   interp_one(d, (int)(e >> lg), (int)(e & ((1 << lg) - 1)), lg, xc, x);
 }
 
+// part of a level holding cell c (offsets ascending; coarse: the parts' offsets
+// in the next level's vector)
+template <typename T>
+__device__ __forceinline__ int part_at(const PartDesc<T> *desc, int np, long long c, bool coarse) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((coarse ? desc[mid].coff : desc[mid].off) <= c)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// acc[e] += (U xs)(e) for every element of a tail level (acc in LDS): the
+// products of all entries are staged in LDS kTailU at a time and each
+// (row, rhs) slot adds its row's products in entry order.
+template <typename T, int TT, typename XS>
+__device__ void tail_coupling(const TailLevel<T> &v, int lg, XS xs, T *__restrict__ prod,
+                              T *__restrict__ acc) {
+  if (v.nrow == 0) return;
+  const int tid = threadIdx.x, mask = (1 << lg) - 1;
+  const int nnz = v.uptr[v.nrow];
+  const int per = kTailU >> lg;
+  for (int ec = 0; ec < nnz; ec += per) {
+    const int np = min(per, nnz - ec) << lg;
+    int cc[kTailU / TT];
+    T vv[kTailU / TT];
+#pragma unroll
+    for (int t = 0; t < kTailU / TT; ++t) {
+      const int q = tid + t * TT;
+      cc[t] = q < np ? v.ucol[ec + (q >> lg)] : 0;
+      vv[t] = q < np ? v.uval[ec + (q >> lg)] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < kTailU / TT; ++t) {
+      const int q = tid + t * TT;
+      if (q < np) prod[q] = vv[t] * xs(cc[t], q & mask);
+    }
+    __syncthreads();
+    for (int t = tid; t < (v.nrow << lg); t += TT) {
+      const int r = t >> lg, kr = t & mask;
+      const int qa = max(v.uptr[r], ec), qb = min(v.uptr[r + 1], ec + (np >> lg));
+      if (qa >= qb) continue;
+      T a = T(0);
+      for (int q = qa; q < qb; ++q) a += prod[((q - ec) << lg) | kr];
+      acc[(v.urow[r] << lg) | kr] += a;
+    }
+    __syncthreads();
+  }
+}
+
 // The coarse end of one V(1,1) cycle, levels tl[0] .. tl[nl-1] (the last one
 // the coarsest), in a single workgroup: the same operations as the grid
-// kernels, one phase at a time with a workgroup barrier between phases.  The
-// couplings are applied as a separate phase over the rows of U.
-template <typename T>
-__global__ __launch_bounds__(kTailThreads) void k_tail(const TailLevel<T> *__restrict__ tl, int nl,
+// kernels over all cells of a level at once (the part of a cell found by
+// search), one phase at a time with a workgroup barrier between phases.  The
+// A x sums of a level are formed in LDS (stencil part per element, then the
+// coupling rows added), so every level above the coarsest must hold at most
+// kTailMax elements.  TT threads: 1024 in FP32, 512 in FP64 (register room for
+// the 27 coefficient, iterate and factor loads a thread keeps in flight).
+template <typename T, int TT>
+__global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl, int nl,
                                                        int lg) {
+  __shared__ T prod[kTailU];
+  __shared__ T acc[kTailMax];
   const int tid = threadIdx.x;
   const int mask = (1 << lg) - 1;
   for (int i = 0; i + 1 < nl; ++i) {
     const TailLevel<T> &v = tl[i];
-    for (int p = 0; p < v.np; ++p) {
-      const PartDesc<T> &d = v.desc[p];
-      for (long long e = tid; e < (d.ncell << lg); e += kTailThreads) {
-        const int c = (int)(e >> lg);
-        const long long o = ((d.off + c) << lg) + (e & mask);
-        v.vx[o] = smooth_factor(d, c) * v.vb[o];
-      }
+    const int nel = (int)(v.ncell << lg);
+    // x = w b and the stencil part of A x
+    for (int e = tid; e < nel; e += TT) {
+      const int c = e >> lg;
+      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
+      const int cl = c - (int)d.off;
+      acc[e] = stencil_wb<T, T, kMaxEnt>(d, cl, lg, v.vb + e);
+      v.vx[e] = d.rs[cl] * v.vb[e];
     }
     __syncthreads();
-    for (int p = 0; p < v.np; ++p) {
-      const PartDesc<T> &d = v.desc[p];
-      for (long long e = tid; e < (d.ncell << lg); e += kTailThreads) {
-        const int c = (int)(e >> lg);
-        const long long o = ((d.off + c) << lg) + (e & mask);
-        v.vt[o] = v.vb[o] - stencil_acc<T, kMaxEnt>(d, c, lg, v.vx + o);
-      }
-    }
+    const T *wl = v.desc[0].rs;   // factors of the whole level (part 0 starts it)
+    tail_coupling<T, TT>(v, lg, [&](int col, int k) { return wl[col] * v.vb[(col << lg) | k]; }, prod, acc);
+    for (int e = tid; e < nel; e += TT) v.vt[e] = v.vb[e] - acc[e];
     __syncthreads();
-    for (long long e = tid; e < ((long long)v.nrow << lg); e += kTailThreads) {
-      const int r = (int)(e >> lg), kr = (int)(e & mask);
-      v.vt[((long long)v.urow[r] << lg) + kr] -= coupling_row<T>(v.uptr, v.ucol, v.uval, r, lg, kr, v.vx);
-    }
-    __syncthreads();
-    for (int p = 0; p < v.np; ++p) {
-      const PartDesc<T> &d = v.desc[p];
-      for (long long e = tid; e < (d.cncell << lg); e += kTailThreads)
-        restrict_one(d, (int)(e >> lg), (int)(e & mask), lg, v.vt, tl[i + 1].vb);
+    const TailLevel<T> &w = tl[i + 1];
+    const int ncel = (int)(w.ncell << lg);
+    for (int e = tid; e < ncel; e += TT) {
+      const int c = e >> lg;
+      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, true)];
+      restrict_one(d, c - (int)d.coff, e & mask, lg, v.vt, w.vb);
     }
     __syncthreads();
   }
   {
     const TailLevel<T> &v = tl[nl - 1];
-    for (int p = 0; p < v.np; ++p) {
-      const PartDesc<double> &d = v.desc64[p];
-      for (long long e = tid; e < (d.ncell << lg); e += kTailThreads) {
-        const int c = (int)(e >> lg);
-        const long long o = ((d.off + c) << lg) + (e & mask);
-        v.vt[o] = (T)(smooth_factor(d, c) * (double)v.vb[o]);
-      }
+    const long long nel = v.ncell << lg;
+    for (long long e = tid; e < nel; e += TT) {
+      const long long c = e >> lg;
+      const PartDesc<double> &d = v.desc64[part_at(v.desc64, v.np, c, false)];
+      v.vt[e] = (T)(smooth_factor(d, c - d.off) * (double)v.vb[e]);
     }
     __syncthreads();
   }
   for (int i = nl - 2; i >= 0; --i) {
     const TailLevel<T> &v = tl[i];
-    for (int p = 0; p < v.np; ++p) {
-      const PartDesc<T> &d = v.desc[p];
-      for (long long e = tid; e < (d.ncell << lg); e += kTailThreads)
-        interp_one(d, (int)(e >> lg), (int)(e & mask), lg, tl[i + 1].vt, v.vx);
+    const int nel = (int)(v.ncell << lg);
+    for (int e = tid; e < nel; e += TT) {
+      const int c = e >> lg;
+      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
+      interp_one(d, c - (int)d.off, e & mask, lg, tl[i + 1].vt, v.vx);
     }
     __syncthreads();
-    for (int p = 0; p < v.np; ++p) {
-      const PartDesc<T> &d = v.desc[p];
-      for (long long e = tid; e < (d.ncell << lg); e += kTailThreads) {
-        const int c = (int)(e >> lg);
-        const long long o = ((d.off + c) << lg) + (e & mask);
-        const T acc = stencil_acc<T, kMaxEnt>(d, c, lg, v.vx + o);
-        v.vt[o] = v.vx[o] + smooth_factor(d, c) * (v.vb[o] - acc);
-      }
+    for (int e = tid; e < nel; e += TT) {
+      const int c = e >> lg;
+      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
+      acc[e] = stencil_acc<T, kMaxEnt>(d, c - (int)d.off, lg, v.vx + e);
     }
     __syncthreads();
-    for (long long e = tid; e < ((long long)v.nrow << lg); e += kTailThreads) {
-      const int r = (int)(e >> lg), kr = (int)(e & mask);
-      const int cell = v.urow[r];
-      int p = 0;
-      while (p + 1 < v.np && v.desc[p + 1].off <= cell) ++p;
-      const PartDesc<T> &d = v.desc[p];
-      const T w = smooth_factor(d, cell - d.off);
-      v.vt[((long long)cell << lg) + kr] -= w * coupling_row<T>(v.uptr, v.ucol, v.uval, r, lg, kr, v.vx);
+    tail_coupling<T, TT>(v, lg, [&](int col, int k) { return v.vx[(col << lg) | k]; }, prod, acc);
+    for (int e = tid; e < nel; e += TT) {
+      const int c = e >> lg;
+      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
+      v.vt[e] = v.vx[e] + d.rs[c - (int)d.off] * (v.vb[e] - acc[e]);
     }
     __syncthreads();
   }
+}
+
+// kernel<<<grid, kBlock>>>(args...) on st, timed by ev when ev.start is set
+template <typename K, typename... A>
+inline void dispatch(K kernel, dim3 grid, hipStream_t st, const LaunchEvents &ev, A... args) {
+  if (ev.start)
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, ev.start, ev.stop, 0, args...);
+  else
+    kernel<<<grid, kBlock, 0, st>>>(args...);
 }
 
 inline unsigned grid_cells(long long n, int lg) {
@@ -389,15 +488,15 @@ inline unsigned grid_cells(long long n, int lg) {
   return (unsigned)(nb > 0 ? nb : 1);
 }
 
-template <typename T, typename TB, typename TO, int FINE, int NENT>
+template <typename T, typename TB, typename TO, int BIG, int NENT>
 void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T *x, const TB *b, TO *y,
-                  hipStream_t st) {
+                  hipStream_t st, const LaunchEvents &ev) {
   if (mode == MODE_APPLY)
-    k_stencil<T, MODE_APPLY, TB, TO, FINE, NENT><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y);
+    dispatch(k_stencil<T, MODE_APPLY, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
   else if (mode == MODE_RESID)
-    k_stencil<T, MODE_RESID, TB, TO, FINE, NENT><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y);
+    dispatch(k_stencil<T, MODE_RESID, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
   else
-    k_stencil<T, MODE_JACOBI, TB, TO, FINE, NENT><<<grid, kBlock, 0, st>>>(desc, lg, x, b, y);
+    dispatch(k_stencil<T, MODE_JACOBI, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
 }
 
 }  // namespace
@@ -406,22 +505,22 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
-                    int lg, const T *x, const TB *b, TO *y, hipStream_t st) {
+                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev) {
   dim3 grid(grid_cells(maxcell, lg), nparts);
-  if (fine) {
+  if (fine || (long long)maxcell * nparts >= kBigLevel) {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st);
+      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st);
+      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev);
     else
-      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st);
+      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev);
   } else {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st);
+      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st);
+      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev);
     else
-      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st);
+      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev);
   }
 }
 
@@ -436,14 +535,14 @@ void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxce
 
 template <typename T>
 void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
-                     hipStream_t st) {
-  k_restrict<T><<<dim3(grid_cells(maxcoarse, lg), nparts), kBlock, 0, st>>>(desc, lg, r, bc);
+                     hipStream_t st, LaunchEvents ev) {
+  dispatch(k_restrict<T>, dim3(grid_cells(maxcoarse, lg), nparts), st, ev, desc, lg, r, bc);
 }
 
 template <typename T>
 void launch_interp_add(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *xc, T *x,
-                       hipStream_t st) {
-  k_interp_add<T><<<dim3(grid_cells(maxcell, lg), nparts), kBlock, 0, st>>>(desc, lg, xc, x);
+                       hipStream_t st, LaunchEvents ev) {
+  dispatch(k_interp_add<T>, dim3(grid_cells(maxcell, lg), nparts), st, ev, desc, lg, xc, x);
 }
 
 void launch_coarse_mixed(const PartDesc<double> *desc, int nparts, int maxcell, int lg, const float *b,
@@ -453,10 +552,10 @@ void launch_coarse_mixed(const PartDesc<double> *desc, int nparts, int maxcell, 
 
 template <typename T, typename TB>
 void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
-                         const TB *b, T *x, T *r, hipStream_t st) {
+                         const TB *b, T *x, T *r, hipStream_t st, LaunchEvents ev) {
   dim3 grid(grid_cells(maxcell, lg), nparts);
-#define SSAMG_SR(F, N) k_smooth_resid<T, TB, F, N><<<grid, kBlock, 0, st>>>(desc, lg, b, x, r)
-  if (fine) {
+#define SSAMG_SR(F, N) dispatch(k_smooth_resid<T, TB, F, N>, grid, st, ev, desc, lg, b, x, r)
+  if (fine || (long long)maxcell * nparts >= kBigLevel) {
     if (maxent <= 7) SSAMG_SR(1, 7);
     else if (maxent <= 15) SSAMG_SR(1, 15);
     else SSAMG_SR(1, 27);
@@ -470,18 +569,19 @@ void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int npar
 
 template <typename T>
 void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
-  k_tail<T><<<1, kTailThreads, 0, st>>>(tl, nl, lg);
+  constexpr int tt = sizeof(T) == 8 ? kTailThreads / 2 : kTailThreads;
+  k_tail<T, tt><<<1, tt, 0, st>>>(tl, nl, lg);
 }
 
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
                                                      int, const double *, const double *, double *,
-                                                     hipStream_t);
+                                                     hipStream_t, LaunchEvents);
 template void launch_stencil<float, float, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                  const float *, const float *, float *, hipStream_t);
+                                                  const float *, const float *, float *, hipStream_t, LaunchEvents);
 template void launch_stencil<float, double, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                   const float *, const double *, float *, hipStream_t);
+                                                   const float *, const double *, float *, hipStream_t, LaunchEvents);
 template void launch_stencil<float, double, double>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                    const float *, const double *, double *, hipStream_t);
+                                                    const float *, const double *, double *, hipStream_t, LaunchEvents);
 template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
                                                  const double *, double *, hipStream_t);
 template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,
@@ -489,19 +589,19 @@ template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int
 template void launch_smooth_zero<float, double>(int, const PartDesc<float> *, int, int, int,
                                                 const double *, float *, hipStream_t);
 template void launch_restrict<double>(const PartDesc<double> *, int, int, int, const double *, double *,
-                                      hipStream_t);
+                                      hipStream_t, LaunchEvents);
 template void launch_restrict<float>(const PartDesc<float> *, int, int, int, const float *, float *,
-                                     hipStream_t);
+                                     hipStream_t, LaunchEvents);
 template void launch_interp_add<double>(const PartDesc<double> *, int, int, int, const double *, double *,
-                                        hipStream_t);
+                                        hipStream_t, LaunchEvents);
 template void launch_interp_add<float>(const PartDesc<float> *, int, int, int, const float *, float *,
-                                       hipStream_t);
+                                       hipStream_t, LaunchEvents);
 template void launch_smooth_resid<double, double>(int, int, const PartDesc<double> *, int, int, int,
-                                                  const double *, double *, double *, hipStream_t);
+                                                  const double *, double *, double *, hipStream_t, LaunchEvents);
 template void launch_smooth_resid<float, float>(int, int, const PartDesc<float> *, int, int, int,
-                                                const float *, float *, float *, hipStream_t);
+                                                const float *, float *, float *, hipStream_t, LaunchEvents);
 template void launch_smooth_resid<float, double>(int, int, const PartDesc<float> *, int, int, int,
-                                                 const double *, float *, float *, hipStream_t);
+                                                 const double *, float *, float *, hipStream_t, LaunchEvents);
 template void launch_tail<double>(const TailLevel<double> *, int, int, hipStream_t);
 template void launch_tail<float>(const TailLevel<float> *, int, int, hipStream_t);
 

@@ -160,7 +160,7 @@ PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coe
   d.ucol = V.d_ucol;
   d.uval = uval;
   for (int lg = 0; lg <= kMaxLg; ++lg)
-    d.ublk[lg] = V.d_ublk[lg] ? V.d_ublk[lg] + V.ublk_off[lg][p] : nullptr;
+    d.ublk[lg] = V.d_ublk[lg] ? V.d_ublk[lg] + 2 * V.ublk_off[lg][p] : nullptr;
   for (size_t e = 0; e < q.pat.size(); ++e) {
     const auto &o = q.pat[e];
     d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
@@ -276,9 +276,9 @@ void symbolic_couplings(Solver &s, int lgmax) {
       V.d_ublk[lg] = nullptr;
       if (lg > lgmax) continue;
       DevBuf &ub = s.store[l]->ublk[lg];
-      ub.reserve((size_t)V.ublk_len[lg] * sizeof(int));
+      ub.reserve((size_t)V.ublk_len[lg] * 2 * sizeof(int));
       launch_ublk(d_sp + sp_at[l], np, lg, (maxchunk + (kBlock >> lg) - 1) / (kBlock >> lg),
-                  d_boff + boff_at[l * (kMaxLg + 1) + lg], V.nrow, V.d_urow, (int *)ub.p, st);
+                  d_boff + boff_at[l * (kMaxLg + 1) + lg], V.nrow, V.d_urow, V.d_uptr, (int *)ub.p, st);
       V.d_ublk[lg] = (int *)ub.p;
     }
   }
@@ -596,11 +596,11 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     // only if consecutive takes are adjacent; they are written per level and
     // the tail kernel walks them through this level's pointer
     if (mixed) {
-      TailLevel<float> t{V.d_desc32, V.d_desc64, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
+      TailLevel<float> t{V.d_desc32, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
                          V.d_ucol, V.d_uval32, (float *)V.vb, (float *)V.vx, (float *)V.vt};
       put(V.d_tail, &t, sizeof(t));
     } else {
-      TailLevel<double> t{V.d_desc64, V.d_desc64, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
+      TailLevel<double> t{V.d_desc64, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
                           V.d_ucol, V.d_uval64, (double *)V.vb, (double *)V.vx, (double *)V.vt};
       put(V.d_tail, &t, sizeof(t));
     }
@@ -630,7 +630,7 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
     launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
-    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, st);
+    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, st);
     launch_uc_numeric(C.nnz, C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
     smoother_scale(l + 1);
@@ -681,25 +681,40 @@ double level0_bytes(const Solver &s, int kind, int lg, size_t tc, size_t tx, siz
   return by;
 }
 
-// HIP-event bracket of one launch of the probed kernel kind
+// HIP events of one launch of the probed kernel kind (recorded by the kernel's
+// own dispatch); empty when this kind is not probed
 struct Probe {
-  Solver &s;
-  int slot = -1;
-  Probe(Solver &s_, int kind, double bytes) : s(s_) {
+  LaunchEvents e;
+  Probe(Solver &s, int kind, double bytes) {
     if (s.probe_kind != kind || s.pev_next + 2 > s.pev.size()) return;
-    slot = (int)s.pev_next;
+    e.start = s.pev[s.pev_next];
+    e.stop = s.pev[s.pev_next + 1];
     s.pev_next += 2;
     s.probe_launches += 1;
     s.probe_bytes += bytes;
-    SSAMG_HIP(hipEventRecord(s.pev[slot], s.stream));
-  }
-  ~Probe() {
-    if (slot >= 0) (void)hipEventRecord(s.pev[slot + 1], s.stream);
   }
 };
 
+// First half of a level's down-sweep: x = w b (the first sweep of eq:relax0
+// from zero) and t = b - A x.  One fused kernel that forms the iterate at each
+// neighbour from its factor and right-hand side, except on large levels with
+// more than 15-point stencils, where the fused kernel's three neighbour
+// streams (coefficients, b, w) hold so many registers that writing x and
+// running the plain residual sweep is faster.
+template <typename T, typename TB>
+void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int lg, const TB *b, T *x, T *t,
+                LaunchEvents ev = {}) {
+  const int np = (int)V.parts.size();
+  if (V.maxent > 15 && V.N >= s.split_cells) {
+    launch_smooth_zero<T, TB>(fine, d, np, V.maxcell, lg, b, x, s.stream);
+    launch_stencil<T, TB, T>(MODE_RESID, fine, V.maxent, d, np, V.maxcell, lg, x, b, t, s.stream, ev);
+  } else {
+    launch_smooth_resid<T, TB>(fine, V.maxent, d, np, V.maxcell, lg, b, x, t, s.stream, ev);
+  }
+}
+
 // first level handled by the one-workgroup tail kernel: the first level >= 1
-// with at most kTailElems elements (the coarsest level always is)
+// with at most tail_elems (<= kTailMax) elements; the coarsest level always is
 int tail_start(const Solver &s, int lg) {
   const int L = (int)s.lv.size();
   for (int l = 1; l < L; ++l)
@@ -719,7 +734,7 @@ void run_tail(Solver &s, int lg) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
-    launch_smooth_resid<T, T>(0, V.maxent, d, np, V.maxcell, lg, b, x, t, st);
+    down_sweep<T, T>(s, V, d, 0, lg, b, x, t);
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, L - lt, lg, st);
@@ -778,20 +793,21 @@ void precond_t(Solver &s, int lg) {
   }
   {
     Probe pr(s, SSAMG_PROBE_RESID0, level0_bytes(s, SSAMG_PROBE_RESID0, lg, tc, tx, 8, tx));
-    launch_smooth_resid<T, double>(1, V.maxent, d, np, V.maxcell, lg, s.r, x, t, st);
+    down_sweep<T, double>(s, V, d, 1, lg, s.r, x, t, pr.e);
   }
   {
     Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
-    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[1].vb, st);
+    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[1].vb, st, pr.e);
   }
   tail<T>(s, lg);
   {
     Probe pr(s, SSAMG_PROBE_INTERP0, level0_bytes(s, SSAMG_PROBE_INTERP0, lg, tc, tx, tx, tx));
-    launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[1].vt, x, st);
+    launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[1].vt, x, st, pr.e);
   }
   {
     Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, 8, 8));
-    launch_stencil<T, double, double>(MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x, s.r, s.z, st);
+    launch_stencil<T, double, double>(MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x, s.r, s.z, st,
+                                      pr.e);
   }
 }
 
@@ -807,7 +823,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y) {
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
     launch_stencil<double, double, double>(MODE_APPLY, 1, V.maxent, V.d_desc64, (int)V.parts.size(), V.maxcell,
-                                           lg, x, nullptr, y, s.stream);
+                                           lg, x, nullptr, y, s.stream, pr.e);
   }
 }
 

@@ -33,10 +33,20 @@ constexpr int kBlock = 256;      // threads per block of every grid-over-cells k
 constexpr int kRedBlocks = 512;  // fixed grid of the deterministic reductions
 constexpr int kMaxRhs = 32;
 constexpr int kMaxLg = 5;        // log2(kMaxRhs)
-// cycle levels of at most this many elements run in the one-workgroup kernel
-// (measured on MI355X: only the coarsest level pays off; a larger threshold
-// serialises too much work on one CU)
+// The coarse end of the cycle runs in one workgroup of kTailThreads threads:
+// the coarsest level and the levels of at most tail_elems elements (cells x
+// right-hand sides; never more than kTailMax, the LDS row-sum capacity).
+// kTailU coupling products are staged in LDS per pass.  Default 0 (coarsest
+// level only): on MI355X every phase of the one-workgroup kernel waits on
+// loads that miss its XCD's L2, about 30 us per level against about 20 us for
+// a level's four grid launches.
+constexpr int kTailThreads = 1024;
+constexpr int kTailMax = 4096;
+constexpr int kTailU = 2048;
 constexpr int64_t kTailElems = 0;
+// levels with more than 15-point stencils and at least this many cells run the
+// first smoothing sweep and the residual as two kernels instead of one
+constexpr int64_t kSplitCells = 1 << 20;
 
 // Packed stencil offset: (dx+1) | (dy+1) << 2 | (dz+1) << 4.
 inline int pack_off(int dx, int dy, int dz) { return (dx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4); }
@@ -64,7 +74,8 @@ struct PartDesc {
   const T *wp;         // [nf] weight toward the +dstar coarse neighbour
   // couplings U of the level (compressed rows, shared by all parts); the rows
   // of the part's block `b` of a grid-over-cells launch with 1 << lg
-  // right-hand sides are urow[ublk[lg][b] .. ublk[lg][b+1])
+  // right-hand sides are urow[ublk[lg][2b] .. ublk[lg][2b+2]) and their
+  // entries ucol[ublk[lg][2b+1] .. ublk[lg][2b+3])
   const int *urow;     // cell id of each stored row (ascending)
   const int *uptr;
   const int *ucol;
@@ -206,6 +217,7 @@ struct Solver {
   bool own_stream = false;
   bool verbose = false;              // SSAMG_VERBOSE: phase timings on stderr
   int64_t tail_elems = kTailElems;   // SSAMG_TAIL_ELEMS overrides
+  int64_t split_cells = kSplitCells; // SSAMG_SPLIT_CELLS overrides
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
   std::vector<Level> lv;
   std::vector<double> cd;            // direction sums c[p][d]
@@ -265,6 +277,7 @@ template <typename T>
 struct TailLevel {
   const PartDesc<T> *desc;          // parts of the level (cycle precision)
   const PartDesc<double> *desc64;   // FP64 parts (the coarsest level's sweep)
+  long long ncell;                  // cells of the level
   int np, nrow;                     // parts, stored rows of U
   const int *urow, *uptr, *ucol;
   const T *uval;
@@ -291,10 +304,17 @@ struct FvArgs {
 
 enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
 
+// Optional timing of one launch: when start is set the kernel is dispatched
+// with hipExtLaunchKernelGGL, which records the two events with the kernel's
+// own dispatch (its execution time, without the gaps around it).
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // kernels_cycle.hip
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
-                    int lg, const T *x, const TB *b, TO *y, hipStream_t st);
+                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {});
 template <typename T>
 void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st);
 template <typename T, typename TB>
@@ -302,10 +322,10 @@ void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxce
                         T *x, hipStream_t st);
 template <typename T>
 void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
-                     hipStream_t st);
+                     hipStream_t st, LaunchEvents ev = {});
 template <typename T>
 void launch_interp_add(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *xc, T *x,
-                       hipStream_t st);
+                       hipStream_t st, LaunchEvents ev = {});
 void launch_coarse_mixed(const PartDesc<double> *desc, int nparts, int maxcell, int lg, const float *b,
                          float *x, hipStream_t st);
 void launch_cast_d2f(const double *in, float *out, int64_t n, hipStream_t st);
@@ -329,13 +349,13 @@ void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *
 void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
                            int maxf, int *flag, hipStream_t st);
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
-                hipStream_t st);
+                int maxent_c, hipStream_t st);
 void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
                            int nrow, const int *urow, const int *uptr, const double *uval,
                            double factor, double *rs, float *rs32, int *flag, hipStream_t st);
 template <typename T, typename TB>
 void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
-                         const TB *b, T *x, T *r, hipStream_t st);
+                         const TB *b, T *x, T *r, hipStream_t st, LaunchEvents ev = {});
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
                        const double *uprev, const double *w, double *uval, float *uval32,
                        hipStream_t st);
@@ -346,7 +366,7 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
                             int &out_nrow, hipStream_t st);
 void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hipStream_t st);
 void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
-                 const int *urow, int *out, hipStream_t st);
+                 const int *urow, const int *uptr, int *out, hipStream_t st);
 
 // kernels_fv.hip
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,

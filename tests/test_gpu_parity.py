@@ -220,3 +220,53 @@ def test_graph_and_eager_agree():
         z2 = s2.apply_precond(b)
         torch.cuda.synchronize()
         assert torch.equal(z1, z2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tail_kernel_matches_grid_kernels(monkeypatch, precision):
+    """The one-workgroup coarse-end kernel (levels of up to 4096 elements, set
+    through SSAMG_TAIL_ELEMS) gives the V-cycle of the per-level grid kernels,
+    for one and for eight right-hand sides; both match the oracle's cycle."""
+    _print_case(f"tail precision={precision}")
+    case = W.c2(13)
+    h = oracle_fv(case)
+    r = np.random.default_rng(8).uniform(-1, 1, h.levels[0].n)
+    monkeypatch.setenv("SSAMG_TAIL_ELEMS", "0")
+    _, s0 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
+    monkeypatch.setenv("SSAMG_TAIL_ELEMS", "4096")
+    _, s1 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
+    z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
+    z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
+    tol = 1e-13 if precision == 0 else 1e-5
+    assert np.linalg.norm(z1 - z0) <= tol * np.linalg.norm(z0)
+    want = O.vcycle(h, r)
+    assert np.linalg.norm(z1 - want) <= (1e-11 if precision == 0 else 1e-5) * np.linalg.norm(want)
+    R = np.random.default_rng(9).uniform(-1, 1, (h.levels[0].n, 8))
+    x0, st0, i0 = s0.solve(_cuda(R))
+    x1, st1, i1 = s1.solve(_cuda(R))
+    assert st0 == st1 == 0
+    assert max(abs(i0.iters[k] - i1.iters[k]) for k in range(8)) <= (0 if precision == 0 else 1)
+    X0, X1 = x0.cpu().numpy(), x1.cpu().numpy()
+    assert np.linalg.norm(X1 - X0) <= 1e-6 * np.linalg.norm(X0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_split_down_sweep_matches_fused(monkeypatch, precision):
+    """On large 27-point levels the first sweep and the residual run as two
+    kernels; forced on every level here (SSAMG_SPLIT_CELLS=0) it must give the
+    fused kernel's cycle, and both the oracle's."""
+    _print_case(f"split precision={precision}")
+    case = W.c3(9)
+    h = oracle_fv(case)
+    r = np.random.default_rng(10).uniform(-1, 1, h.levels[0].n)
+    monkeypatch.setenv("SSAMG_SPLIT_CELLS", "0")
+    _, s0 = gpu_fv(case, cycle_precision=precision)
+    monkeypatch.setenv("SSAMG_SPLIT_CELLS", str(1 << 40))
+    _, s1 = gpu_fv(case, cycle_precision=precision)
+    z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
+    z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
+    want = O.vcycle(h, r)
+    tol = 1e-11 if precision == 0 else 1e-5
+    assert np.linalg.norm(z0 - want) <= tol * np.linalg.norm(want)
+    assert np.linalg.norm(z1 - want) <= tol * np.linalg.norm(want)
+    assert np.linalg.norm(z0 - z1) <= (1e-13 if precision == 0 else 1e-5) * np.linalg.norm(z1)
