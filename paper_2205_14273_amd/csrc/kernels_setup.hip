@@ -199,6 +199,16 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
     g[ds] = ci[ds];
     rho[2] = row_ok[2] ? d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
   }
+  // Per-thread bases; every contribution then adds block-uniform offsets: the
+  // fine row f = 2I + r is f0 + r*stride(d*), the neighbour g = f + s is in the
+  // box when each coordinate is, and an odd g's F-box cell is h0 plus the
+  // offsets of s (with (r + s_d* - 1)/2 along d*).
+  int fc[3] = {ci[0], ci[1], ci[2]};
+  fc[ds] = fb;
+  const long long f0 = fc[0] + (long long)d.n[0] * (fc[1] + (long long)d.n[1] * fc[2]);
+  const long long h0 = ci[0] + (long long)d.fn[0] * (ci[1] + (long long)d.fn[1] * ci[2]);
+  const long long str[3] = {1, d.n[0], (long long)d.n[0] * d.n[1]};
+  const long long fstr[3] = {1, d.fn[0], (long long)d.fn[0] * d.fn[1]};
   double acc = 0.0;
   const int q0 = t.start[e], q1 = t.start[e + 1];
   for (int qb = q0; qb < q1; qb += kRapBatch) {
@@ -214,26 +224,20 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
       const int r = (w & 3) - 1;
       const int sidx = (w >> 2) & 31;
       const int gsel = (w >> 7) & 3;
-      if (!row_ok[r + 1]) continue;
-      int f[3] = {ci[0], ci[1], ci[2]};
-      f[ds] = fb + r;
-      int g[3];
-      bool in = true;
+      const int cs = d.code[sidx];
+      const int o[3] = {off_comp(cs, 0), off_comp(cs, 1), off_comp(cs, 2)};
+      bool in = row_ok[r + 1] && (unsigned)(fb + r + o[ds]) < (unsigned)nd;
+      long long dfine = r * str[ds], dh = ((r + o[ds] - 1) >> 1) * fstr[ds];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        g[a] = f[a] + off_comp(d.code[sidx], a);
-        in = in && g[a] >= 0 && g[a] < d.n[a];
+        if (a == ds) continue;
+        in = in && (unsigned)(ci[a] + o[a]) < (unsigned)d.n[a];
+        dh += o[a] * fstr[a];
       }
       if (!in) continue;
-      const long long fl = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
-      av[u] = d.coef[(long long)sidx * d.ncell + fl];
+      av[u] = d.coef[(long long)sidx * d.ncell + f0 + dfine];
       rv[u] = rho[r + 1];
-      if (gsel != 0) {
-        int h[3] = {g[0], g[1], g[2]};
-        h[ds] = (g[ds] - 1) >> 1;
-        const long long hl = h[0] + (long long)d.fn[0] * (h[1] + (long long)d.fn[1] * h[2]);
-        wv[u] = gsel == 1 ? d.wm[hl] : d.wp[hl];
-      }
+      if (gsel != 0) wv[u] = gsel == 1 ? d.wm[h0 + dh] : d.wp[h0 + dh];
     }
 #pragma unroll
     for (int u = 0; u < kRapBatch; ++u) acc = fma(rv[u] * av[u], wv[u], acc);
