@@ -110,6 +110,22 @@ constexpr int kUChunkBig = 1024;
 constexpr int kUChunkSmall = 4096;
 constexpr long long kBigLevel = 1 << 18;   // cells from which a level counts as large
 
+// acc + prod[q0] + ... + prod[q1 - 1] (slot kr of each entry), added in entry
+// order; the LDS reads are issued eight at a time so that long rows do not
+// wait on one read per entry
+template <typename T>
+__device__ __forceinline__ T row_sum(const T *__restrict__ prod, int q0, int q1, int lg, int kr, T acc) {
+  for (int q = q0; q < q1; q += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = q + u < q1 ? prod[((q + u) << lg) | kr] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q + u < q1) acc += v[u];
+  }
+  return acc;
+}
+
 // The U part of A x for every (cell, rhs) slot of one block: sum over the
 // entries of the slot's row of val * xs(col, rhs).  The rows of a block and
 // their entries are contiguous (rows sorted by cell), so all threads form the
@@ -162,7 +178,7 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
     __syncthreads();
     if (tid < nrt) {
       const int qa = max(rq0, ec), qb = min(rq1, ec + (np >> lg));
-      for (int q = qa; q < qb; ++q) racc += prod[((q - ec) << lg) | (tid & mask)];
+      racc = row_sum(prod, qa - ec, qb - ec, lg, tid & mask, racc);
     }
     __syncthreads();
   }
@@ -391,8 +407,7 @@ __device__ void tail_coupling(const TailLevel<T> &v, int lg, XS xs, T *__restric
       const int r = t >> lg, kr = t & mask;
       const int qa = max(v.uptr[r], ec), qb = min(v.uptr[r + 1], ec + (np >> lg));
       if (qa >= qb) continue;
-      T a = T(0);
-      for (int q = qa; q < qb; ++q) a += prod[((q - ec) << lg) | kr];
+      const T a = row_sum(prod, qa - ec, qb - ec, lg, kr, T(0));
       acc[(v.urow[r] << lg) | kr] += a;
     }
     __syncthreads();
