@@ -139,7 +139,12 @@ typedef struct {
   double omega;              /* JACOBI: > 0 fixed weight, <= 0 per-part omega_p of
                                 eq:relax1 (default); L1_JACOBI: > 0 the factor, <= 0 3/2
                                 (the paper's SSAMG-base setting) */
-  int coarse;                /* SSAMG_COARSE_SWEEP (default, Section 3.5) */
+  int coarse;                /* SSAMG_COARSE_SWEEP (default, Section 3.5): one sweep
+                                from zero; SSAMG_COARSE_DIRECT: exact solve with the
+                                coarsest operator's inverse, formed at setup_numeric
+                                (at most 64 unknowns, else setup_symbolic returns
+                                SSAMG_ERR_UNSUPPORTED; SSAMG_ERR_NUMERIC when the
+                                operator is not positive definite) */
   int cycle_precision;       /* SSAMG_FP64 (default) or SSAMG_FP32: V-cycle in FP32
                                 inside FP64 PCG, coarsest level in FP64 */
   double tol;                /* ||r||_2 < tol ||b||_2 (default 1e-8) */

@@ -69,7 +69,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (p.min_coarse_size < 0) throw Error(SSAMG_ERR_ARG, "min_coarse_size must be >= 0");
   if (p.relax != SSAMG_RELAX_JACOBI && p.relax != SSAMG_RELAX_L1_JACOBI)
     throw Error(SSAMG_ERR_ARG, "relax must be SSAMG_RELAX_JACOBI or SSAMG_RELAX_L1_JACOBI");
-  if (p.coarse != SSAMG_COARSE_SWEEP) throw Error(SSAMG_ERR_UNSUPPORTED, "only the one-sweep coarsest level");
+  if (p.coarse != SSAMG_COARSE_SWEEP && p.coarse != SSAMG_COARSE_DIRECT)
+    throw Error(SSAMG_ERR_ARG, "coarse must be SSAMG_COARSE_SWEEP or SSAMG_COARSE_DIRECT");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
     throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
   if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw Error(SSAMG_ERR_ARG, "tol must be positive");

@@ -246,6 +246,63 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
   if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)acc;
 }
 
+// Direct coarsest solve (Section 3.5 option): the coarsest operator A = S + U
+// assembled densely in LDS and inverted in place by Gauss-Jordan elimination
+// without pivoting (A is symmetric positive definite, so every pivot is
+// positive; a pivot that is not sets flag 2).  One workgroup, n <= kDirectMax.
+__global__ __launch_bounds__(kBlock) void k_direct_setup(const PartDesc<double> *__restrict__ desc, int np,
+                                                         int n, int nrow, const int *__restrict__ urow,
+                                                         const int *__restrict__ uptr,
+                                                         const int *__restrict__ ucol,
+                                                         const double *__restrict__ uval,
+                                                         double *__restrict__ ainv, int *__restrict__ flag) {
+  __shared__ double a[kDirectMax * kDirectMax];
+  __shared__ double fcol[kDirectMax];
+  __shared__ double piv;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n * n; i += kBlock) a[i] = 0.0;
+  __syncthreads();
+  if (tid < n) {   // stencil part of row tid
+    int p = 0;
+    while (p + 1 < np && desc[p + 1].off <= tid) ++p;
+    const PartDesc<double> &d = desc[p];
+    const int cl = tid - (int)d.off;
+    int c[3];
+    cell_ijk(cl, d.n[0], d.n[1], c[0], c[1], c[2]);
+    for (int s = 0; s < d.nent; ++s) {
+      int g[3];
+      bool in = true;
+      for (int k = 0; k < 3; ++k) {
+        g[k] = c[k] + off_comp(d.code[s], k);
+        in = in && g[k] >= 0 && g[k] < d.n[k];
+      }
+      if (in)
+        a[tid * n + (int)d.off + g[0] + d.n[0] * (g[1] + d.n[1] * g[2])] += d.coef[(long long)s * d.ncell + cl];
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < nrow; r += kBlock)   // couplings: one thread per stored row
+    for (int q = uptr[r]; q < uptr[r + 1]; ++q) a[urow[r] * n + ucol[q]] += uval[q];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      piv = a[k * n + k];
+      if (!(piv > 0.0) || !isfinite(piv)) flag[0] = 2;
+    }
+    if (tid < n) fcol[tid] = a[tid * n + k];
+    __syncthreads();
+    const double pv = piv;
+    if (tid < n) a[k * n + tid] = (tid == k ? 1.0 : a[k * n + tid]) / pv;
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += kBlock) {
+      const int i = idx / n, j = idx - i * n;
+      if (i != k) a[idx] = (j == k ? 0.0 : a[idx]) - fcol[i] * a[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n * n; i += kBlock) ainv[i] = a[i];
+}
+
 // U_c = P^T U P on the host-built structure: each coarse entry sums, in a
 // fixed order, w(a) * U[k] * w(b) over its contributions (w(-1) = 1).
 __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int *__restrict__ start,
@@ -361,6 +418,12 @@ void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int
   // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies
   const unsigned nb = (nblk(maxcoarse) * (unsigned)maxent_c + 7u) & ~7u;
   k_rap<<<dim3(nb, nparts), kBlock, 0, st>>>(desc, rd, maxent_c);
+}
+
+void launch_direct_setup(const PartDesc<double> *desc, int np, int n, int nrow, const int *urow,
+                         const int *uptr, const int *ucol, const double *uval, double *ainv, int *flag,
+                         hipStream_t st) {
+  k_direct_setup<<<1, kBlock, 0, st>>>(desc, np, n, nrow, urow, uptr, ucol, uval, ainv, flag);
 }
 
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,

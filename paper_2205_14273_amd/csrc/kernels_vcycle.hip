@@ -457,10 +457,21 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
   {
     const TailLevel<T> &v = tl[nl - 1];
     const long long nel = v.ncell << lg;
-    for (long long e = tid; e < nel; e += TT) {
-      const long long c = e >> lg;
-      const PartDesc<double> &d = v.desc64[part_at(v.desc64, v.np, c, false)];
-      v.vt[e] = (T)(smooth_factor(d, c - d.off) * (double)v.vb[e]);
+    if (v.ndirect > 0) {
+      // direct solve: x = A^{-1} b with the inverse formed at setup, in FP64
+      for (long long e = tid; e < nel; e += TT) {
+        const int row = (int)(e >> lg), kr = (int)(e & mask);
+        const double *ar = v.ainv + (long long)row * v.ndirect;
+        double acc = 0.0;
+        for (int j = 0; j < v.ndirect; ++j) acc = fma(ar[j], (double)v.vb[((long long)j << lg) + kr], acc);
+        v.vt[e] = (T)acc;
+      }
+    } else {
+      for (long long e = tid; e < nel; e += TT) {
+        const long long c = e >> lg;
+        const PartDesc<double> &d = v.desc64[part_at(v.desc64, v.np, c, false)];
+        v.vt[e] = (T)(smooth_factor(d, c - d.off) * (double)v.vb[e]);
+      }
     }
     __syncthreads();
   }

@@ -441,6 +441,10 @@ void setup_symbolic(Solver &s) {
     C.N = coff;
     s.lv.push_back(std::move(C));
   }
+  if (s.prm.coarse == SSAMG_COARSE_DIRECT && s.lv.back().N > kDirectMax)
+    throw Error(SSAMG_ERR_UNSUPPORTED, "the direct coarsest solve takes at most " +
+                                           std::to_string(kDirectMax) + " unknowns; the coarsest level has " +
+                                           std::to_string(s.lv.back().N));
   const auto t_alg = std::chrono::steady_clock::now();
   symbolic_couplings(s, lgmax);
   const auto t_u = std::chrono::steady_clock::now();
@@ -501,6 +505,9 @@ void carve(Solver &s, Carver &cv) {
   s.scal = cv.take<double>((size_t)kScalSlots * kMaxRhs);
   s.active = cv.take<int>(kMaxRhs);
   s.flag = cv.take<int>(1);
+  s.lv.back().d_ainv = s.prm.coarse == SSAMG_COARSE_DIRECT
+                           ? cv.take<double>((size_t)s.lv.back().N * s.lv.back().N)
+                           : nullptr;
   for (int l = 0; l < L; ++l) {
     Level &V = s.lv[l];
     const bool cyc32 = mixed && l < L - 1;
@@ -597,11 +604,13 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     // the tail kernel walks them through this level's pointer
     if (mixed) {
       TailLevel<float> t{V.d_desc32, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
-                         V.d_ucol, V.d_uval32, (float *)V.vb, (float *)V.vx, (float *)V.vt};
+                         V.d_ucol, V.d_uval32, (float *)V.vb, (float *)V.vx, (float *)V.vt,
+                         V.d_ainv, V.d_ainv ? (int)V.N : 0, 0};
       put(V.d_tail, &t, sizeof(t));
     } else {
       TailLevel<double> t{V.d_desc64, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
-                          V.d_ucol, V.d_uval64, (double *)V.vb, (double *)V.vx, (double *)V.vt};
+                          V.d_ucol, V.d_uval64, (double *)V.vb, (double *)V.vx, (double *)V.vt,
+                         V.d_ainv, V.d_ainv ? (int)V.N : 0, 0};
       put(V.d_tail, &t, sizeof(t));
     }
   }
@@ -635,6 +644,11 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
     smoother_scale(l + 1);
   }
+  if (s.prm.coarse == SSAMG_COARSE_DIRECT) {
+    Level &V = s.lv.back();
+    launch_direct_setup(V.d_desc64, (int)V.parts.size(), (int)V.N, V.nrow, V.d_urow, V.d_uptr, V.d_ucol,
+                        V.d_uval64, V.d_ainv, s.flag, st);
+  }
   SSAMG_HIP(hipGetLastError());
   int hflag = 0;
   SSAMG_HIP(hipMemcpyAsync(&hflag, s.flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -644,6 +658,7 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     fprintf(stderr, "[ssamg] numeric setup: tables %.3f ms (%zu bytes), kernels %.3f ms\n",
             std::chrono::duration<double, std::milli>(t1 - t0).count(), stage.size(),
             std::chrono::duration<double, std::milli>(t2 - t1).count());
+  if (hflag == 2) throw Error(SSAMG_ERR_NUMERIC, "coarsest operator is not positive definite (direct solve)");
   if (hflag) throw Error(SSAMG_ERR_NUMERIC, "non-finite interpolation weight");
   s.state = 2;
 }
@@ -782,10 +797,16 @@ void precond_t(Solver &s, int lg) {
   const size_t tc = sizeof(T), tx = sizeof(T);
   T *x = (T *)V.vx, *t = (T *)V.vt;
   if (L == 1) {
+    const bool direct = V.d_ainv != nullptr;
     if (sizeof(T) == sizeof(float)) {
       launch_cast_d2f(s.r, (float *)V.vb, V.N << lg, st);
-      launch_coarse_mixed(V.d_desc64, np, V.maxcell, lg, (const float *)V.vb, (float *)V.vt, st);
+      if (direct)
+        launch_tail<T>((const TailLevel<T> *)V.d_tail, 1, lg, st);
+      else
+        launch_coarse_mixed(V.d_desc64, np, V.maxcell, lg, (const float *)V.vb, (float *)V.vt, st);
       launch_cast_f2d((const float *)V.vt, s.z, V.N << lg, st);
+    } else if (direct) {
+      launch_tail<T>((const TailLevel<T> *)V.d_tail, 1, lg, st);   // vb = r, vt = z
     } else {
       launch_smooth_zero<double, double>(1, V.d_desc64, np, V.maxcell, lg, s.r, s.z, st);
     }

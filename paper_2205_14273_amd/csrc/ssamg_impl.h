@@ -47,6 +47,8 @@ constexpr int64_t kTailElems = 0;
 // levels with more than 15-point stencils and at least this many cells run the
 // first smoothing sweep and the residual as two kernels instead of one
 constexpr int64_t kSplitCells = 1 << 20;
+// largest coarsest level the direct solve accepts (its inverse is formed in LDS)
+constexpr int kDirectMax = 64;
 
 // Packed stencil offset: (dx+1) | (dy+1) << 2 | (dz+1) << 4.
 inline int pack_off(int dx, int dy, int dz) { return (dx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4); }
@@ -204,6 +206,7 @@ struct Level {
   PartDesc<double> *d_desc64 = nullptr;
   PartDesc<float> *d_desc32 = nullptr;
   struct RapDesc *d_rapdesc = nullptr;
+  double *d_ainv = nullptr;          // coarsest level, direct solve: dense inverse
   void *d_tail = nullptr;            // TailLevel<cycle precision> of this level
   // V-cycle vectors in the cycle precision: [N][max_nrhs]
   void *vb = nullptr, *vx = nullptr, *vt = nullptr;
@@ -282,6 +285,8 @@ struct TailLevel {
   const int *urow, *uptr, *ucol;
   const T *uval;
   T *vb, *vx, *vt;                  // right-hand side, iterate, output
+  const double *ainv;               // coarsest level, direct solve: A^{-1} (row-major), else null
+  int ndirect, pad;                 // its order (0: one relaxation sweep)
 };
 
 // per-part Galerkin table of one level (device array indexed by part)
@@ -356,6 +361,9 @@ void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, in
 template <typename T, typename TB>
 void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
                          const TB *b, T *x, T *r, hipStream_t st, LaunchEvents ev = {});
+void launch_direct_setup(const PartDesc<double> *desc, int np, int n, int nrow, const int *urow,
+                         const int *uptr, const int *ucol, const double *uval, double *ainv, int *flag,
+                         hipStream_t st);
 void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a, const int *b,
                        const double *uprev, const double *w, double *uval, float *uval32,
                        hipStream_t st);

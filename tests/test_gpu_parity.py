@@ -270,3 +270,40 @@ def test_split_down_sweep_matches_fused(monkeypatch, precision):
     assert np.linalg.norm(z0 - want) <= tol * np.linalg.norm(want)
     assert np.linalg.norm(z1 - want) <= tol * np.linalg.norm(want)
     assert np.linalg.norm(z0 - z1) <= (1e-13 if precision == 0 else 1e-5) * np.linalg.norm(z1)
+
+
+@pytest.mark.parametrize("name,precision", [("c1_16", 0), ("c2_13", 1), ("c3_9", 0), ("c5_11", 1)])
+def test_direct_coarsest_solve(name, precision):
+    """SSAMG_COARSE_DIRECT: the coarsest level is solved exactly; the cycle and
+    the solve match the oracle's cycle with a dense solve there."""
+    _print_case(f"direct {name} precision={precision}")
+    case = CASES[name]()
+    h = oracle_fv(case, coarse="direct")
+    pr, s = gpu_fv(case, coarse=1, cycle_precision=precision)
+    r = np.random.default_rng(15).uniform(-1, 1, h.levels[0].n)
+    z = s.apply_precond(_cuda(r)).cpu().numpy()
+    want = O.vcycle(h, r)
+    tol = 1e-11 if precision == 0 else 1e-5
+    assert np.linalg.norm(z - want) <= tol * np.linalg.norm(want)
+    b = case.b if case.b.ndim == 1 else case.b[0]
+    ref = O.solve(h, b, tol=1e-8, flexible=(precision == 1))
+    x, st, info = s.solve(_cuda(b))
+    assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
+    assert info.true_relres[0] < 1e-8
+
+
+def test_direct_single_level_is_exact():
+    """One level (max_levels = 1) with the direct option: the preconditioner is
+    A^{-1}, so PCG converges in one iteration."""
+    case = W.c1(4)
+    pr, s = gpu_fv(case, coarse=1, max_levels=1, tol=1e-10)
+    x, st, info = s.solve(_cuda(case.b))
+    assert st == 0 and info.iters[0] == 1 and info.true_relres[0] < 1e-12
+
+
+def test_direct_too_large_is_unsupported():
+    from paper_2205_14273_amd.ssamg import SSAMGError
+    case = W.c2(13)
+    with pytest.raises(SSAMGError) as e:
+        gpu_fv(case, coarse=1, max_levels=3)
+    assert e.value.status == -3
