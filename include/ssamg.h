@@ -151,6 +151,9 @@ typedef struct {
   int max_iter;              /* default 100 */
   int max_nrhs;              /* right-hand sides per solve, power of two <= 32 (default 1) */
   int use_graph;             /* capture the V-cycle in a HIP graph (default 1) */
+  int skip;                  /* 1: the "skip" option of Section 3.4 - a part does not
+                                relax at level l >= n_d where it coarsens along the
+                                same direction as at level l - n_d (default 0) */
 } ssamg_params;
 
 typedef struct {
@@ -171,6 +174,7 @@ typedef struct {
   int pattern[27][3];        /* stencil offsets (level 0: as given; coarser: sorted
                                 by (dz, dy, dx)) */
   int fdims[3];              /* F-box (cells odd along dstar) extents */
+  int skip;                  /* 1: the part does not relax at this level (skip option) */
 } ssamg_level_desc;
 
 ssamg_status ssamg_params_default(ssamg_params *params);
@@ -193,6 +197,13 @@ ssamg_status ssamg_workspace_bytes(ssamg_solver s, size_t *bytes);
  * SSAMG_FP32.  ws: caller-owned device buffer of at least workspace_bytes
  * (kept until the solver is destroyed), or NULL to let the library allocate. */
 ssamg_status ssamg_setup_numeric(ssamg_solver s, void *ws, size_t bytes);
+
+/* Replace the stencil coefficients of one part of the solver's problem (same
+ * pattern; vals and where as in ssamg_problem_set_coeffs with constant = 0).
+ * The hierarchy depends on the values (Section 3.1 metric, Algorithm 1), so
+ * the solver returns to the created state: setup_symbolic and setup_numeric
+ * must run again before the next solve (SSAMG_ERR_STATE otherwise). */
+ssamg_status ssamg_update_coeffs(ssamg_solver s, int part, const double *vals, int where);
 
 /* Solve A X = B for nrhs right-hand sides (1 <= nrhs <= max_nrhs, power of two).
  * b, x: device, [N][nrhs] doubles (right-hand side index fastest; for nrhs = 1

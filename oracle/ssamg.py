@@ -40,6 +40,11 @@ Readings where the paper is silent or garbled (all are listed in the design note
            unless max_levels or min_coarse_size stops earlier.
   R-last   the coarsest level gets one sweep of the same relaxation from zero
            (Section 3.5, non-hybrid case), or optionally a dense direct solve.
+  R-skip   the "skip" option (Section 3.4): a part does not relax at level l >= n_d
+           when it coarsens there along the same direction as at level l - n_d
+           (d*_l = d*_{l-n_d} >= 0); the coarsest level and parts that no
+           longer coarsen always relax.  Not relaxing means a zero smoother
+           factor: no pre-sweep contribution and no post-sweep change.
 """
 from __future__ import annotations
 
@@ -327,6 +332,7 @@ class Hierarchy:
     coarse: str = "sweep"
     relax: str = "jacobi"
     l1_factor: float = 1.5
+    skip: bool = False
 
     @property
     def nlevels(self):
@@ -334,7 +340,7 @@ class Hierarchy:
 
 
 def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=64,
-          min_coarse_size=0, coarse="sweep", relax="jacobi"):
+          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False):
     """Full SSAMG setup.  ``pattern0[p]`` is the input stencil of part p.
 
     ``ustruct0``: 0/1 structure of the input couplings (defaults to A0's
@@ -377,10 +383,20 @@ def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=
         ust.sort_indices()
         levels.append(Level(list(cdims), coffs, Ac, pats, ust))
     h = Hierarchy(ndim, levels, np.asarray(faces), W0, cd, coarse, relax,
-                  omega if (relax == "l1" and omega > 0) else 1.5)
-    for lev in levels:
+                  omega if (relax == "l1" and omega > 0) else 1.5, skip)
+    for l, lev in enumerate(levels):
         lev._cache["relax"] = (relax, h.l1_factor)
+        lev._cache["skip"] = skip_mask(levels, l, ndim) if skip else np.zeros(len(dims), dtype=bool)
     return h
+
+
+def skip_mask(levels, l, ndim):
+    """Parts that do not relax at level l under the skip option (reading R-skip)."""
+    ds = levels[l].dstar
+    if l < ndim:
+        return np.zeros(len(ds), dtype=bool)
+    prev = levels[l - ndim].dstar
+    return np.array([ds[p] >= 0 and ds[p] == prev[p] for p in range(len(ds))], dtype=bool)
 
 
 # ---------------------------------------------------------------------------
@@ -446,6 +462,10 @@ def _cell_weights(level):
         else:
             part = np.repeat(np.arange(len(level.dims)), np.diff(level.offsets))
             level._cache["wd"] = level.omega[part] / level.A.diagonal()
+        skip = level._cache.get("skip")
+        if skip is not None and skip.any():
+            part = np.repeat(np.arange(len(level.dims)), np.diff(level.offsets))
+            level._cache["wd"] = np.where(skip[part], 0.0, level._cache["wd"])
     return level._cache["wd"]
 
 

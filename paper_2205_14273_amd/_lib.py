@@ -46,7 +46,7 @@ class ssamg_params(C.Structure):
     _fields_ = [("max_levels", C.c_int), ("min_coarse_size", C.c_int64), ("relax", C.c_int),
                 ("omega", C.c_double), ("coarse", C.c_int), ("cycle_precision", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
-                ("use_graph", C.c_int)]
+                ("use_graph", C.c_int), ("skip", C.c_int)]
 
 
 class ssamg_info(C.Structure):
@@ -58,7 +58,7 @@ class ssamg_info(C.Structure):
 class ssamg_level_desc(C.Structure):
     _fields_ = [("dims", C.c_int * 3), ("offset", C.c_int64), ("dstar", C.c_int),
                 ("omega", C.c_double), ("nent", C.c_int), ("pattern", (C.c_int * 3) * 27),
-                ("fdims", C.c_int * 3)]
+                ("fdims", C.c_int * 3), ("skip", C.c_int)]
 
 
 P = C.c_void_p
@@ -85,6 +85,7 @@ SIGNATURES = {
     "ssamg_problem_num_cells": [P, PI64],
     "ssamg_params_default": [C.POINTER(ssamg_params)],
     "ssamg_solver_create": [P, C.POINTER(ssamg_params), P, PP],
+    "ssamg_update_coeffs": [P, I, P, I],
     "ssamg_solver_destroy": [P],
     "ssamg_setup_symbolic": [P],
     "ssamg_workspace_bytes": [P, C.POINTER(C.c_size_t)],

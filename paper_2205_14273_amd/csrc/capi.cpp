@@ -53,6 +53,7 @@ ssamg_status ssamg_params_default(ssamg_params *p) {
   p->max_iter = 100;
   p->max_nrhs = 1;
   p->use_graph = 1;
+  p->skip = 0;
   API_END
 }
 
@@ -71,6 +72,7 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
     throw Error(SSAMG_ERR_ARG, "relax must be SSAMG_RELAX_JACOBI or SSAMG_RELAX_L1_JACOBI");
   if (p.coarse != SSAMG_COARSE_SWEEP && p.coarse != SSAMG_COARSE_DIRECT)
     throw Error(SSAMG_ERR_ARG, "coarse must be SSAMG_COARSE_SWEEP or SSAMG_COARSE_DIRECT");
+  if (p.skip != 0 && p.skip != 1) throw Error(SSAMG_ERR_ARG, "skip must be 0 or 1");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
     throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
   if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw Error(SSAMG_ERR_ARG, "tol must be positive");
@@ -131,6 +133,15 @@ ssamg_status ssamg_workspace_bytes(ssamg_solver h, size_t *bytes) {
 ssamg_status ssamg_setup_numeric(ssamg_solver h, void *ws, size_t bytes) {
   API_BEGIN
   setup_numeric(*S(h), ws, bytes);
+  API_END
+}
+
+ssamg_status ssamg_update_coeffs(ssamg_solver h, int part, const double *vals, int where) {
+  API_BEGIN
+  Solver *s = S(h);
+  const ssamg_status st = ssamg_problem_set_coeffs((ssamg_problem)s->prob, part, vals, where, 0);
+  if (st != SSAMG_OK) return st;
+  s->state = 0;
   API_END
 }
 
@@ -198,6 +209,7 @@ ssamg_status ssamg_level_info(ssamg_solver h, int level, int part, ssamg_level_d
   info->dstar = q.dstar;
   info->omega = q.omega;
   info->nent = (int)q.pat.size();
+  info->skip = q.skip ? 1 : 0;
   for (size_t e = 0; e < q.pat.size(); ++e)
     for (int d = 0; d < 3; ++d) info->pattern[e][d] = q.pat[e][d];
   API_END

@@ -441,6 +441,14 @@ void setup_symbolic(Solver &s) {
     C.N = coff;
     s.lv.push_back(std::move(C));
   }
+  // skip option (Section 3.4): no relaxation where a part coarsens along the
+  // same direction as n_d levels above
+  for (int l = 0; l < (int)s.lv.size(); ++l)
+    for (size_t p = 0; p < s.lv[l].parts.size(); ++p) {
+      const int ds = s.lv[l].parts[p].dstar;
+      s.lv[l].parts[p].skip =
+          s.prm.skip && l >= ndim && ds >= 0 && ds == s.lv[l - ndim].parts[p].dstar;
+    }
   if (s.prm.coarse == SSAMG_COARSE_DIRECT && s.lv.back().N > kDirectMax)
     throw Error(SSAMG_ERR_UNSUPPORTED, "the direct coarsest solve takes at most " +
                                            std::to_string(kDirectMax) + " unknowns; the coarsest level has " +
@@ -629,9 +637,15 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   const double l1_factor = s.prm.omega > 0.0 ? s.prm.omega : 1.5;
   auto smoother_scale = [&](int l) {
     Level &V = s.lv[l];
+    float *rs32 = mixed && l < L - 1 ? V.d_rs32 : nullptr;
     launch_smoother_scale(l1, V.d_desc64, (int)V.parts.size(), V.maxcell, V.N, V.nrow, V.d_urow,
-                          V.d_uptr, V.d_uval64, l1_factor, V.d_rs64,
-                          mixed && l < L - 1 ? V.d_rs32 : nullptr, s.flag, st);
+                          V.d_uptr, V.d_uval64, l1_factor, V.d_rs64, rs32, s.flag, st);
+    // skipped parts: factor 0, so neither sweep changes their cells
+    for (auto &q : V.parts) {
+      if (!q.skip) continue;
+      SSAMG_HIP(hipMemsetAsync(V.d_rs64 + q.off, 0, (size_t)q.ncell * sizeof(double), st));
+      if (rs32) SSAMG_HIP(hipMemsetAsync(rs32 + q.off, 0, (size_t)q.ncell * sizeof(float), st));
+    }
   };
   smoother_scale(0);
   // level by level: weights, structured and unstructured Galerkin products

@@ -131,6 +131,7 @@ struct PartLevel {
   int dstar = -1;
   double omega = 0.0;
   int faces = 0;
+  bool skip = false;                 // no relaxation on this part at this level (skip option)
   std::vector<std::array<int, 3>> pat;
   int center = 0;
   double *coef64 = nullptr;

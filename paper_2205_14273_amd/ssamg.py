@@ -128,6 +128,14 @@ def ssamg_setup_numeric(h, ws=None):
         check(lib().ssamg_setup_numeric(h, _ptr(ws), ws.numel() * ws.element_size()))
 
 
+def ssamg_update_coeffs(h, part, vals, where):
+    if isinstance(vals, torch.Tensor):
+        check(lib().ssamg_update_coeffs(h, part, _ptr(vals), where))
+    else:
+        arr = np.ascontiguousarray(vals, dtype=np.float64)
+        check(lib().ssamg_update_coeffs(h, part, arr.ctypes.data_as(C.c_void_p), where))
+
+
 def ssamg_solve(h, nrhs, b, x):
     info = L.ssamg_info()
     st = lib().ssamg_solve(h, nrhs, _ptr(b), _ptr(x), C.byref(info))
@@ -307,6 +315,16 @@ class Solver:
         st, info = ssamg_solve(self.h, nrhs, b, x)
         return x, st, info
 
+    def update_coeffs(self, part, vals):
+        """New stencil values of one part ([nent][nz][ny][nx], same pattern: a
+        CUDA float64 tensor or a host array); run setup() again before solving."""
+        if isinstance(vals, torch.Tensor):
+            vals = vals.to(dtype=torch.float64).contiguous()
+            ssamg_update_coeffs(self.h, part, vals, L.MEM_DEVICE)
+        else:
+            ssamg_update_coeffs(self.h, part, np.ascontiguousarray(vals, dtype=np.float64).reshape(-1),
+                                L.MEM_HOST)
+
     def apply_A(self, level, x):
         y = torch.empty_like(x)
         ssamg_apply_A(self.h, level, x.contiguous(), y)
@@ -322,7 +340,7 @@ class Solver:
         return {"dims": tuple(d.dims), "offset": d.offset, "dstar": d.dstar, "omega": d.omega,
                 "nent": d.nent, "pattern": np.array([[d.pattern[e][a] for a in range(3)]
                                                       for e in range(d.nent)], dtype=np.int32),
-                "fdims": tuple(d.fdims)}
+                "fdims": tuple(d.fdims), "skip": d.skip}
 
     def level_cells(self, level):
         return sum(int(np.prod(self.level_info(level, p)["dims"])) for p in range(self.problem.nparts))

@@ -12,7 +12,8 @@ def oracle_fv(case, **kw):
     pat = [W.stencil_offsets(case.stencil, g.ndim)] * g.nparts
     return O.setup(A, g.dims, g.face_kinds(), pat, g.ndim, omega=kw.get("omega", case.omega),
                    max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
-                   relax=kw.get("relax", case.relax), coarse=kw.get("coarse", "sweep"))
+                   relax=kw.get("relax", case.relax), coarse=kw.get("coarse", "sweep"),
+                   skip=kw.get("skip", False))
 
 
 def oracle_raw(case, **kw):

@@ -515,3 +515,62 @@ def test_l1_vcycle_spd_and_pcg():
     res = ssamg.solve(h, case.b, tol=1e-10)
     xd = np.linalg.solve(A.toarray(), case.b)
     assert np.linalg.norm(res.x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+# ---------------------------------------------------------------------------
+# Section 3.4: the "skip" option
+
+
+def _skip_levels(h, p=0):
+    return {l for l, lev in enumerate(h.levels) if lev._cache["skip"][p]}
+
+
+def test_skip_levels_from_hand_sequences():
+    """Relaxation is off at level l when d*_l = d*_{l-3} (3D).  Worked by hand
+    on the Algorithm 1 sequences of tests/golden: the isotropic 16^3 box,
+    x y z repeating over 12 coarsening levels, skips levels 3..11; the
+    (100,1,1) 64^3 box, xxxx yz xyz xyz yzyzyz, skips 3, 6, 7, 8, 9, 10, 11;
+    the coarsest level never skips."""
+    _, h = fv_hierarchy(W.c1(16), skip=True)
+    assert _skip_levels(h) == set(range(3, 12))
+    assert seq_of(h) == "xyzxyzxyzxyz"
+    case = W.c2(64)
+    case.geometry.dims = case.geometry.dims[:1]
+    case.geometry.origins = case.geometry.origins[:1]
+    case.aniso = case.aniso[:1]
+    case.kappa = case.kappa[:64 ** 3]
+    _, h = fv_hierarchy(case, skip=True)
+    assert seq_of(h) == "xxxxyzxyzxyzyzyzyz"
+    assert _skip_levels(h) == {3, 6, 7, 8, 9, 10, 11}
+    _, h0 = fv_hierarchy(W.c1(16))
+    assert _skip_levels(h0) == set()
+
+
+def test_skip_zeroes_exactly_the_skipped_parts():
+    _, h = fv_hierarchy(W.c2(8), skip=True, relax="l1")
+    for l, lev in enumerate(h.levels):
+        wd = ssamg._cell_weights(lev)
+        for p in range(len(lev.dims)):
+            seg = wd[lev.offsets[p]:lev.offsets[p + 1]]
+            if lev._cache["skip"][p]:
+                assert np.all(seg == 0.0), (l, p)
+            else:
+                assert np.all(seg > 0.0), (l, p)
+
+
+@pytest.mark.parametrize("relax", ["jacobi", "l1"])
+def test_skip_vcycle_spd_and_pcg(relax):
+    """With relaxation off on some levels the cycle is still symmetric positive
+    definite (the finest level always relaxes) and PCG reaches the dense
+    solution."""
+    case = W.c1(6)
+    A, h = fv_hierarchy(case, skip=True, relax=relax)
+    assert _skip_levels(h)
+    n = A.shape[0]
+    B = np.column_stack([ssamg.vcycle(h, e) for e in np.eye(n)])
+    assert np.max(np.abs(B - B.T)) <= 1e-12 * np.max(np.abs(B))
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    x_direct = sla.solve(A.toarray(), case.b, assume_a="pos")
+    res = ssamg.solve(h, case.b, tol=1e-10, max_iter=200)
+    assert res.converged
+    assert np.linalg.norm(res.x - x_direct) <= 1e-8 * np.linalg.norm(x_direct)
