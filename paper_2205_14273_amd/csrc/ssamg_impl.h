@@ -30,7 +30,7 @@ struct Error : std::runtime_error {
 
 constexpr int kMaxEnt = 27;      // stencils live in the 27-point neighbourhood
 constexpr int kBlock = 256;      // threads per block of every grid-over-cells kernel
-constexpr int kRedBlocks = 512;  // fixed grid of the deterministic reductions
+constexpr int kRedBlocks = 2048; // fixed grid of the deterministic reductions (8 per CU)
 constexpr int kMaxRhs = 32;
 constexpr int kMaxLg = 5;        // log2(kMaxRhs)
 // The coarse end of the cycle runs in one workgroup of kTailThreads threads:
