@@ -98,34 +98,34 @@ __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp,
 
 // after the sort: flags of records that open a coarse entry / a coarse row,
 // and the count of valid records (invalid keys sort last)
+// packed flags: bit 0 a record that opens a coarse entry, bit 32 one that
+// opens a coarse row (one 64-bit scan then counts both)
 __global__ __launch_bounds__(kBlock) void k_flags(const unsigned long long *__restrict__ key,
                                                   long long n, unsigned long long nc,
-                                                  unsigned long long invalid, int *__restrict__ fnew,
-                                                  int *__restrict__ frow, int *__restrict__ small) {
+                                                  unsigned long long invalid,
+                                                  long long *__restrict__ flags, int *__restrict__ small) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const bool v = key[i] != invalid;
-  fnew[i] = v && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
-  frow[i] = v && (i == 0 || key[i] / nc != key[i - 1] / nc) ? 1 : 0;
+  const long long fnew = v && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+  const long long frow = v && (i == 0 || key[i] / nc != key[i - 1] / nc) ? 1 : 0;
+  flags[i] = fnew | (frow << 32);
   if (v && (i == n - 1 || key[i + 1] == invalid)) small[0] = (int)(i + 1);
 }
 
-// entry and row counts from the inclusive scans
-__global__ void k_counts(const int *__restrict__ eid, const int *__restrict__ rid,
-                         int *__restrict__ small) {
+// entry and row counts from the inclusive scan of the packed flags
+__global__ void k_counts(const long long *__restrict__ scan, int *__restrict__ small) {
   const int nvalid = small[0];
-  small[1] = nvalid > 0 ? eid[nvalid - 1] : 0;
-  small[2] = nvalid > 0 ? rid[nvalid - 1] : 0;
+  small[1] = nvalid > 0 ? (int)(scan[nvalid - 1] & 0xffffffffLL) : 0;
+  small[2] = nvalid > 0 ? (int)(scan[nvalid - 1] >> 32) : 0;
 }
 
 // coarse entries (column, row), rows (cell, first entry) and the
 // contributions in sorted order
 __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__restrict__ key,
                                                  const unsigned *__restrict__ idx,
-                                                 const int *__restrict__ fnew,
-                                                 const int *__restrict__ frow,
-                                                 const int *__restrict__ eid,
-                                                 const int *__restrict__ rid, long long nvalid,
+                                                 const long long *__restrict__ flags,
+                                                 const long long *__restrict__ scan, long long nvalid,
                                                  unsigned long long nc, const int *__restrict__ rk,
                                                  const int *__restrict__ ra,
                                                  const int *__restrict__ rb, int *__restrict__ ucol,
@@ -139,19 +139,20 @@ __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__res
   ck[i] = rk[s];
   ca[i] = ra[s];
   cb[i] = rb[s];
-  const int e = eid[i] - 1;
-  if (fnew[i]) {
+  const long long f = flags[i], sc = scan[i];
+  const int e = (int)(sc & 0xffffffffLL) - 1, rid = (int)(sc >> 32);
+  if (f & 1) {
     ucol[e] = (int)(key[i] % nc);
     erow[e] = (int)(key[i] / nc);
     start[e] = (int)i;
   }
-  if (frow[i]) {
-    urow[rid[i] - 1] = (int)(key[i] / nc);
-    uptr[rid[i] - 1] = e;
+  if (f >> 32) {
+    urow[rid - 1] = (int)(key[i] / nc);
+    uptr[rid - 1] = e;
   }
   if (i == nvalid - 1) {
     start[e + 1] = (int)nvalid;
-    uptr[rid[i]] = e + 1;
+    uptr[rid] = e + 1;
   }
 }
 
@@ -233,10 +234,8 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   w.rk.reserve(n * 4);
   w.ra.reserve(n * 4);
   w.rb.reserve(n * 4);
-  w.fnew.reserve(n * 4);
-  w.frow.reserve(n * 4);
-  w.eid.reserve(n * 4);
-  w.rid.reserve(n * 4);
+  w.flags.reserve(n * 8);
+  w.scan.reserve(n * 8);
   w.small.reserve(64);
   if (!w.host_small) {
     void *h = nullptr;
@@ -246,7 +245,7 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   auto *k0 = (unsigned long long *)w.key0.p, *k1 = (unsigned long long *)w.key1.p;
   auto *i0 = (unsigned *)w.idx0.p, *i1 = (unsigned *)w.idx1.p;
   int *rk = (int *)w.rk.p, *ra = (int *)w.ra.p, *rb = (int *)w.rb.p;
-  int *fnew = (int *)w.fnew.p, *frow = (int *)w.frow.p, *eid = (int *)w.eid.p, *rid = (int *)w.rid.p;
+  long long *flags = (long long *)w.flags.p, *scan = (long long *)w.scan.p;
   int *small = (int *)w.small.p;
   k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
                                        rk, ra, rb);
@@ -255,13 +254,12 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   w.temp.reserve(tbytes);
   SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
   SSAMG_HIP(hipMemsetAsync(small, 0, 16, st));
-  k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, fnew, frow, small);
+  k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, flags, small);
   tbytes = 0;
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, fnew, eid, (int)n, st));
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, flags, scan, (int)n, st));
   w.temp.reserve(tbytes);
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, fnew, eid, (int)n, st));
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, frow, rid, (int)n, st));
-  k_counts<<<1, 1, 0, st>>>(eid, rid, small);
+  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, flags, scan, (int)n, st));
+  k_counts<<<1, 1, 0, st>>>(scan, small);
   SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   SSAMG_HIP(hipStreamSynchronize(st));
   const int nvalid = w.host_small[0], nent = w.host_small[1], nr = w.host_small[2];
@@ -274,7 +272,7 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   out.ck.reserve((size_t)nvalid * 4);
   out.ca.reserve((size_t)nvalid * 4);
   out.cb.reserve((size_t)nvalid * 4);
-  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, fnew, frow, eid, rid, nvalid, (unsigned long long)nc,
+  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, flags, scan, nvalid, (unsigned long long)nc,
                                           rk, ra, rb, (int *)out.ucol.p, (int *)out.erow.p,
                                           (int *)out.start.p, (int *)out.urow.p, (int *)out.uptr.p,
                                           (int *)out.ck.p, (int *)out.ca.p, (int *)out.cb.p);

@@ -173,7 +173,7 @@ struct LevelStore {
 
 // Scratch of the device sort.
 struct SymScratch {
-  DevBuf key0, key1, idx0, idx1, rk, ra, rb, fnew, frow, eid, rid, small, temp;
+  DevBuf key0, key1, idx0, idx1, rk, ra, rb, flags, scan, small, temp;
   int *host_small = nullptr;         // pinned
   ~SymScratch() {
     if (host_small) (void)hipHostFree(host_small);
