@@ -318,6 +318,291 @@ __global__ __launch_bounds__(kBlock) void k_smooth_resid(const PartDesc<T> *__re
   r[o] = b0 - acc;
 }
 
+// ---------------------------------------------------------------------------
+// Batched solves (4 or more right-hand sides): each thread takes four
+// consecutive columns of one cell.  The per-cell work (coordinates, masks,
+// coefficient loads, addresses) is then shared by four columns, the vector
+// loads and stores are 16 or 32 bytes, and a 256-thread block covers
+// 1024 >> lg cells (the coupling-row table of lg - 2).  Every value is formed
+// with the same operations in the same order as in the one-column kernels.
+
+__device__ __forceinline__ void load4(const float *p, float v[4]) {
+  const float4 t = *reinterpret_cast<const float4 *>(p);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+__device__ __forceinline__ void load4(const double *p, double v[4]) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+__device__ __forceinline__ void store4(float *p, const float v[4]) {
+  *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(double *p, const double v[4]) {
+  reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// stencil_acc for the four columns at xp (x of the cell's first column)
+template <typename T, int NENT>
+__device__ __forceinline__ void stencil_acc4(const PartDesc<T> &d, int c, int lg, const T *xp, T acc[4]) {
+  int i, j, k;
+  cell_ijk(c, d.n[0], d.n[1], i, j, k);
+  const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
+  const T *cf = d.coef + c;
+  T a[NENT], xv[NENT][4];
+#pragma unroll
+  for (int s = 0; s < NENT; ++s) {
+    const bool act = s < d.nent;
+    a[s] = act ? cf[(long long)s * d.ncell] : T(0);
+    if (act && nb_ok(mx, my, mz, d.code[s])) {
+      load4(xp + ((long long)d.lin[s] << lg), xv[s]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[s][q] = T(0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[q] = T(0);
+#pragma unroll
+    for (int s = 0; s < NENT; ++s) acc[q] = fma(a[s], xv[s][q], acc[q]);
+  }
+}
+
+// block_coupling for blocks of 1024 >> lg cells: up to four (row, column)
+// slots per thread; out[q] receives the sum of the thread's column 4t + q
+template <int UCH, typename T, typename XS>
+__device__ __forceinline__ void block_coupling4(const PartDesc<T> &d, int chunk, int lg, XS xs,
+                                                T *__restrict__ prod, T *__restrict__ rsum, T out[4]) {
+  const int lgc = lg - 2;
+  const int *ub = d.ublk[lgc] + 2 * chunk;
+  const int u0 = ub[0], e0 = ub[1], u1 = ub[2], e1 = ub[3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = T(0);
+  if (u0 == u1) return;                               // block-uniform
+  const int tid = threadIdx.x;
+  const int mask = (1 << lg) - 1;
+  const int cell0 = (int)d.off + chunk * (kBlock >> lgc);
+  const int nrt = (u1 - u0) << lg;                    // (row, column) slots, <= 4 kBlock
+  int rq0[4], rq1[4], rslot[4];
+  T racc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = tid + q * kBlock;
+    rq0[q] = rq1[q] = rslot[q] = 0;
+    racc[q] = T(0);
+    if (t < nrt) {
+      const int r = u0 + (t >> lg);
+      rq0[q] = d.uptr[r];
+      rq1[q] = d.uptr[r + 1];
+      rslot[q] = ((d.urow[r] - cell0) << lg) | (t & mask);
+    }
+    rsum[t] = T(0);
+  }
+  const int per = UCH >> lg;
+  for (int ec = e0; ec < e1; ec += per) {
+    const int np = min(per, e1 - ec) << lg;
+    int cc[UCH / kBlock];
+    T vv[UCH / kBlock], xx[UCH / kBlock];
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      const bool in = q < np;
+      cc[t] = in ? d.ucol[ec + (q >> lg)] : 0;
+      vv[t] = in ? d.uval[ec + (q >> lg)] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      xx[t] = q < np ? xs(cc[t], q & mask) : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      if (q < np) prod[q] = vv[t] * xx[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = tid + q * kBlock;
+      if (t < nrt) {
+        const int qa = max(rq0[q], ec), qb = min(rq1[q], ec + (np >> lg));
+        racc[q] = row_sum(prod, qa - ec, qb - ec, lg, t & mask, racc[q]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (tid + q * kBlock < nrt) rsum[rslot[q]] = racc[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = rsum[(tid << 2) + q];
+}
+
+template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
+__global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restrict__ desc, int lg,
+                                                     const T *__restrict__ x,
+                                                     const TB *__restrict__ b, TO *__restrict__ y) {
+  constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
+  __shared__ T prod[UCH];
+  __shared__ T rsum[4 * kBlock];
+  const PartDesc<T> &d = desc[blockIdx.y];
+  const int chunk = chunk_index();
+  const int lgc = lg - 2;
+  const long long e = (long long)chunk * kBlock + threadIdx.x;
+  const long long nel = d.ncell << lgc;
+  if ((long long)chunk * kBlock >= nel) return;      // whole block past the part's end
+  const bool valid = e < nel;
+  const int c = valid ? (int)(e >> lgc) : 0;
+  const long long o = ((d.off + c) << lg) + 4 * (e & ((1 << lgc) - 1));
+  const T *xp = x + o;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  if (valid) stencil_acc4<T, NENT>(d, c, lg, xp, acc);
+  T cu[4];
+  block_coupling4<UCH>(
+      d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum, cu);
+  if (!valid) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] += cu[q];
+  TO out[4];
+  if (MODE == MODE_APPLY) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = (TO)acc[q];
+  } else {
+    TB bv[4];
+    load4(b + o, bv);
+    if (MODE == MODE_RESID) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q] = (TO)((T)bv[q] - acc[q]);
+    } else {
+      T xv[4];
+      load4(xp, xv);
+      const T w = smooth_factor(d, c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q] = (TO)(xv[q] + w * ((T)bv[q] - acc[q]));
+    }
+  }
+  store4(y + o, out);
+}
+
+// x = w b for four columns per thread
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_smooth_zero4(const PartDesc<T> *__restrict__ desc, int lg,
+                                                         const TB *__restrict__ b, T *__restrict__ x) {
+  const PartDesc<T> &d = desc[blockIdx.y];
+  const int lgc = lg - 2;
+  const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
+  if (e >= (d.ncell << lgc)) return;
+  const int c = (int)(e >> lgc);
+  const long long o = ((d.off + c) << lg) + 4 * (e & ((1 << lgc) - 1));
+  TB bv[4];
+  load4(b + o, bv);
+  const T w = smooth_factor(d, c);
+  T xv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) xv[q] = w * (T)bv[q];
+  store4(x + o, xv);
+}
+
+// restrict_one for four columns per thread
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict4(const PartDesc<T> *__restrict__ desc, int lg,
+                                                      const T *__restrict__ r, T *__restrict__ bc) {
+  const PartDesc<T> &d = desc[blockIdx.y];
+  const int lgc = lg - 2;
+  const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
+  if (e >= (d.cncell << lgc)) return;
+  const int cc = (int)(e >> lgc);
+  const int k4 = 4 * (int)(e & ((1 << lgc) - 1));
+  T v[4];
+  if (d.dstar < 0) {
+    load4(r + ((d.off + cc) << lg) + k4, v);
+    store4(bc + ((d.coff + cc) << lg) + k4, v);
+    return;
+  }
+  int ci[3];
+  cell_ijk(cc, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
+  const int ds = d.dstar;
+  int fi[3] = {ci[0], ci[1], ci[2]};
+  fi[ds] = 2 * ci[ds];
+  const int f0 = fi[0] + d.n[0] * (fi[1] + d.n[1] * fi[2]);
+  const int stride = ds == 0 ? 1 : (ds == 1 ? d.n[0] : d.n[0] * d.n[1]);
+  const T *rp = r + ((d.off + f0) << lg) + k4;
+  load4(rp, v);
+  int g[3] = {ci[0], ci[1], ci[2]};
+  if (fi[ds] - 1 >= 0) {
+    g[ds] = ci[ds] - 1;
+    const T w = d.wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
+    T t[4];
+    load4(rp - ((long long)stride << lg), t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = fma(w, t[q], v[q]);
+  }
+  if (fi[ds] + 1 <= d.n[ds] - 1) {
+    g[ds] = ci[ds];
+    const T w = d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
+    T t[4];
+    load4(rp + ((long long)stride << lg), t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = fma(w, t[q], v[q]);
+  }
+  store4(bc + ((d.coff + cc) << lg) + k4, v);
+}
+
+// interp_one for four columns per thread
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_interp_add4(const PartDesc<T> *__restrict__ desc, int lg,
+                                                        const T *__restrict__ xc, T *__restrict__ x) {
+  const PartDesc<T> &d = desc[blockIdx.y];
+  const int lgc = lg - 2;
+  const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
+  if (e >= (d.ncell << lgc)) return;
+  const int c = (int)(e >> lgc);
+  const int k4 = 4 * (int)(e & ((1 << lgc) - 1));
+  T *xp = x + ((d.off + c) << lg) + k4;
+  T xv[4], v[4];
+  load4(xp, xv);
+  if (d.dstar < 0) {
+    load4(xc + ((d.coff + c) << lg) + k4, v);
+  } else {
+    int f[3];
+    cell_ijk(c, d.n[0], d.n[1], f[0], f[1], f[2]);
+    const int ds = d.dstar;
+    const int id = f[ds];
+    int g[3] = {f[0], f[1], f[2]};
+    if ((id & 1) == 0) {
+      g[ds] = id >> 1;
+      load4(xc + ((d.coff + g[0] + d.cn[0] * (g[1] + d.cn[1] * g[2])) << lg) + k4, v);
+    } else {
+      g[ds] = (id - 1) >> 1;
+      const int fl = g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2]);
+      const int cm = g[0] + d.cn[0] * (g[1] + d.cn[1] * g[2]);
+      T t[4];
+      load4(xc + ((d.coff + cm) << lg) + k4, t);
+      const T wm = d.wm[fl];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = wm * t[q];
+      if (id + 1 <= d.n[ds] - 1) {
+        const int cstride = ds == 0 ? 1 : (ds == 1 ? d.cn[0] : d.cn[0] * d.cn[1]);
+        load4(xc + ((d.coff + cm + cstride) << lg) + k4, t);
+        const T wp = d.wp[fl];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = fma(wp, t[q], v[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) xv[q] += v[q];
+  store4(xp, xv);
+}
+
 // x = w b: the first sweep of eq:relax0 from a zero guess
 template <typename T, typename TB, int FINE>
 __global__ __launch_bounds__(kBlock) void k_smooth_zero(const PartDesc<T> *__restrict__ desc, int lg,
@@ -517,6 +802,18 @@ inline unsigned grid_cells(long long n, int lg) {
 template <typename T, typename TB, typename TO, int BIG, int NENT>
 void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T *x, const TB *b, TO *y,
                   hipStream_t st, const LaunchEvents &ev) {
+  // four columns per thread for batched solves (not for FP64 27-point stencils,
+  // whose 108 neighbour values would not fit the register file)
+  if (lg >= 2 && !(sizeof(T) == 8 && NENT > 15)) {
+    dim3 g4((grid.x + 3) / 4 > 0 ? (unsigned)(((long long)grid.x + 3) / 4) : 1u, grid.y);
+    if (mode == MODE_APPLY)
+      dispatch(k_stencil4<T, MODE_APPLY, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
+    else if (mode == MODE_RESID)
+      dispatch(k_stencil4<T, MODE_RESID, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
+    else
+      dispatch(k_stencil4<T, MODE_JACOBI, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
+    return;
+  }
   if (mode == MODE_APPLY)
     dispatch(k_stencil<T, MODE_APPLY, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
   else if (mode == MODE_RESID)
@@ -553,7 +850,9 @@ void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int
 template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st) {
-  if (fine)
+  if (lg >= 2)
+    k_smooth_zero4<T, TB><<<dim3(grid_cells(maxcell, lg - 2), nparts), kBlock, 0, st>>>(desc, lg, b, x);
+  else if (fine)
     k_smooth_zero<T, TB, 1><<<dim3(grid_cells(maxcell, lg), nparts), kBlock, 0, st>>>(desc, lg, b, x);
   else
     k_smooth_zero<T, TB, 0><<<dim3(grid_cells(maxcell, lg), nparts), kBlock, 0, st>>>(desc, lg, b, x);
@@ -562,13 +861,19 @@ void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxce
 template <typename T>
 void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
                      hipStream_t st, LaunchEvents ev) {
-  dispatch(k_restrict<T>, dim3(grid_cells(maxcoarse, lg), nparts), st, ev, desc, lg, r, bc);
+  if (lg >= 2)
+    dispatch(k_restrict4<T>, dim3(grid_cells(maxcoarse, lg - 2), nparts), st, ev, desc, lg, r, bc);
+  else
+    dispatch(k_restrict<T>, dim3(grid_cells(maxcoarse, lg), nparts), st, ev, desc, lg, r, bc);
 }
 
 template <typename T>
 void launch_interp_add(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *xc, T *x,
                        hipStream_t st, LaunchEvents ev) {
-  dispatch(k_interp_add<T>, dim3(grid_cells(maxcell, lg), nparts), st, ev, desc, lg, xc, x);
+  if (lg >= 2)
+    dispatch(k_interp_add4<T>, dim3(grid_cells(maxcell, lg - 2), nparts), st, ev, desc, lg, xc, x);
+  else
+    dispatch(k_interp_add<T>, dim3(grid_cells(maxcell, lg), nparts), st, ev, desc, lg, xc, x);
 }
 
 void launch_coarse_mixed(const PartDesc<double> *desc, int nparts, int maxcell, int lg, const float *b,

@@ -727,14 +727,15 @@ struct Probe {
 // First half of a level's down-sweep: x = w b (the first sweep of eq:relax0
 // from zero) and t = b - A x.  One fused kernel that forms the iterate at each
 // neighbour from its factor and right-hand side, except on large levels with
-// more than 15-point stencils or four and more right-hand sides, where the
-// fused kernel's neighbour streams (coefficients, b, w) cost more than writing
-// x and running the plain residual sweep.
+// more than 15-point stencils, and on levels of at least split_cells elements
+// with four or more right-hand sides (then run four columns per thread), where
+// the fused kernel's neighbour streams (coefficients, b, w) cost more than
+// writing x and running the plain residual sweep.
 template <typename T, typename TB>
 void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int lg, const TB *b, T *x, T *t,
                 LaunchEvents ev = {}) {
   const int np = (int)V.parts.size();
-  if ((V.maxent > 15 || lg >= 2) && V.N >= s.split_cells) {
+  if (lg >= 2 ? (V.N << lg) >= s.split_cells : (V.maxent > 15 && V.N >= s.split_cells)) {
     launch_smooth_zero<T, TB>(fine, d, np, V.maxcell, lg, b, x, s.stream);
     launch_stencil<T, TB, T>(MODE_RESID, fine, V.maxent, d, np, V.maxcell, lg, x, b, t, s.stream, ev);
   } else {

@@ -151,3 +151,22 @@ def test_batched_full_c4_sampled():
         want = A[idx] @ X[:, k]
         scale = np.abs(A[idx]) @ np.abs(X[:, k])
         assert np.max(np.abs(ax - want) / scale) <= 1e-13
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_batched_split_and_fused_first_sweep_agree(monkeypatch, precision):
+    """Batched levels run the first sweep and the residual either fused (one
+    column per thread) or split (four columns per thread); both form the same
+    values, so the solves agree bit for bit."""
+    _print_case(f"c4_12 split/fused precision={precision}")
+    case = W.c4(12, nrhs=8)
+    B = np.ascontiguousarray(case.b.T)
+    monkeypatch.setenv("SSAMG_SPLIT_CELLS", "0")
+    _, s0 = gpu_fv(case, max_nrhs=8, cycle_precision=precision)
+    monkeypatch.setenv("SSAMG_SPLIT_CELLS", str(1 << 40))
+    _, s1 = gpu_fv(case, max_nrhs=8, cycle_precision=precision)
+    x0, st0, i0 = s0.solve(_cuda(B))
+    x1, st1, i1 = s1.solve(_cuda(B))
+    assert st0 == st1 == 0
+    assert torch.equal(x0, x1)
+    assert [i0.iters[k] for k in range(8)] == [i1.iters[k] for k in range(8)]
