@@ -63,18 +63,32 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const double *__restrict
   if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
 }
 
-// slot <- sum of partials; shift_rz: first move S_RZN to S_RZ (PCG bookkeeping)
-__global__ __launch_bounds__(kBlock) void k_dot_final(const double *__restrict__ partial, int nblk,
-                                                      int lg, double *__restrict__ scal, int slot,
-                                                      int shift_rz) {
-  __shared__ double sh[kBlock];
+// slot <- sum of partials; shift_rz: first move S_RZN to S_RZ (PCG bookkeeping).
+// kFinalThreads threads; each adds a fixed strided set of partials of its
+// right-hand side with four independent accumulators (loads in flight), then
+// a fixed LDS tree.
+constexpr int kFinalThreads = 1024;
+
+__global__ __launch_bounds__(kFinalThreads) void k_dot_final(const double *__restrict__ partial, int nblk,
+                                                             int lg, double *__restrict__ scal, int slot,
+                                                             int shift_rz) {
+  __shared__ double sh[kFinalThreads];
   const int nr = 1 << lg;
   const int kr = threadIdx.x & (nr - 1);
-  double acc = 0.0;
-  for (int bidx = threadIdx.x >> lg; bidx < nblk; bidx += kBlock >> lg)
-    acc += partial[bidx * kMaxRhs + kr];
-  sh[threadIdx.x] = acc;
-  block_tree(sh, nr);
+  const int step = kFinalThreads >> lg;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int bidx = threadIdx.x >> lg;
+  for (; bidx + 3 * step < nblk; bidx += 4 * step) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] += partial[(bidx + u * step) * kMaxRhs + kr];
+  }
+  for (; bidx < nblk; bidx += step) a[0] += partial[bidx * kMaxRhs + kr];
+  sh[threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
+  for (int s = kFinalThreads / 2; s >= nr; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  }
+  __syncthreads();
   if ((int)threadIdx.x < nr) {
     if (shift_rz) scal[S_RZ * kMaxRhs + threadIdx.x] = scal[S_RZN * kMaxRhs + threadIdx.x];
     scal[slot * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
@@ -178,7 +192,7 @@ void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *p
                 int slot, int shift_rz, hipStream_t st) {
   const unsigned nb = red_blocks(nel);
   k_dot_partial<<<nb, kBlock, 0, st>>>(a, b, nel, lg, partial);
-  k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal, slot, shift_rz);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, shift_rz);
 }
 
 void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
@@ -186,7 +200,7 @@ void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, d
                    hipStream_t st) {
   const unsigned nb = red_blocks(nel);
   k_pcg_xr<<<nb, kBlock, 0, st>>>(nel, lg, scal, active, x, r, p, q, partial);
-  k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal_out, S_RR, 0);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal_out, S_RR, 0);
 }
 
 void launch_pcg_p(int64_t nel, int lg, const double *scal, const int *active, int flexible,
@@ -198,7 +212,7 @@ void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, d
                        double *scal, int slot, hipStream_t st) {
   const unsigned nb = red_blocks(nel);
   k_resid_partial<<<nb, kBlock, 0, st>>>(b, ax, nel, lg, partial);
-  k_dot_final<<<1, kBlock, 0, st>>>(partial, (int)nb, lg, scal, slot, 0);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, 0);
 }
 
 }  // namespace ssamg
