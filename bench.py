@@ -186,7 +186,11 @@ def main():
 
     log("timed run: FP32 V-cycle inside FP64 PCG")
     probe_kind, probe_name = PROBES[args.probe]
-    probe_name = probe_name.format(n=7 if case.stencil in (5, 7) else 27)
+    nent = 7 if case.stencil in (5, 7) else 27
+    probe_name = probe_name.format(n=nent)
+    if nrhs >= 4 and not (probe_name.startswith("k_stencil<double") and nent == 27):
+        # four right-hand-side columns per thread on batched levels
+        probe_name = probe_name.replace("k_stencil<", "k_stencil4<")
     mixed, x32, probe, s32 = run(B.L.FP32, args.steps, args.warmup, probe_kind)
     fp64 = None
     x64 = None
