@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--probe", default="jacobi0", choices=sorted(PROBES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched configurations: keep the default launch options")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference kernel "
                          "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings) and exit")
@@ -157,9 +159,23 @@ def main():
             raise RuntimeError(f"solve did not converge: status {st}")
         return x, info, (t1 - t0, t2 - t1, t3 - t2, ts - t1, t2 - ts)
 
+    tune_s = {}
+
     def run(precision, steps, warmup, probe_kind=None):
         pr, s = make_solver(precision)
         x = torch.empty_like(b)
+        if nrhs >= 4 and not args.no_autotune:
+            # launch options of the batched cycle: timed once on this hierarchy,
+            # kept by the solver across the setups of the timed steps
+            s.setup()
+            t0 = time.perf_counter()
+            s.autotune(nrhs)
+            tune_s[precision] = time.perf_counter() - t0
+            log(f"  autotune ({'fp32' if precision else 'fp64'} cycle): {tune_s[precision]*1e3:.1f} ms")
+            for lev in range(s.nlevels):
+                rec = s.tune_get(lev, nrhs)
+                if rec.pop("stored"):
+                    log(f"    level {lev}: {rec}")
         for _ in range(warmup):
             x, info, _ = step(pr, s, x)
         if probe_kind is not None:
@@ -270,7 +286,8 @@ def main():
                    "assemble_s": round(mixed["assemble_s"], 6), "setup_s": round(mixed["setup_s"], 6),
                    "setup_symbolic_s": round(mixed["symbolic_s"], 6),
                    "setup_numeric_s": round(mixed["numeric_s"], 6),
-                   "solve_s": round(mixed["solve_s"], 6), "true_relres": mixed["true_relres"]},
+                   "solve_s": round(mixed["solve_s"], 6), "true_relres": mixed["true_relres"],
+                   "autotune_s": round(tune_s[1], 4) if 1 in tune_s else None},
         "fp64_cycle": None if fp64 is None else {
             "ms_per_step": round(fp64["ms_per_step"], 4), "setup_s": round(fp64["setup_s"], 6),
             "solve_s": round(fp64["solve_s"], 6), "iters": fp64["iters"],

@@ -154,6 +154,9 @@ typedef struct {
   int skip;                  /* 1: the "skip" option of Section 3.4 - a part does not
                                 relax at level l >= n_d where it coarsens along the
                                 same direction as at level l - n_d (default 0) */
+  int autotune;              /* 1: the first solve of each batch width >= 4 times the
+                                launch options of its larger levels and keeps the
+                                fastest (ssamg_autotune); 0: defaults (default 0) */
 } ssamg_params;
 
 typedef struct {
@@ -210,6 +213,45 @@ ssamg_status ssamg_update_coeffs(ssamg_solver s, int part, const double *vals, i
  * a plain vector).  x0 = 0.  Returns SSAMG_NOT_CONVERGED when some right-hand
  * side did not meet tol within max_iter.  info may be NULL. */
 ssamg_status ssamg_solve(ssamg_solver s, int nrhs, const double *b, double *x, ssamg_info *info);
+
+/* Launch options of the batched V-cycle (batch widths of 4 or more right-hand
+ * sides), per level and width.  They choose how the kernels cover a level, not
+ * what they compute: every choice gives bit-identical results.  The record is
+ * int[5]:
+ *   [0] strips    block order of the four-columns-per-thread stencil sweeps: each
+ *                 z-plane of a part is cut into this many strips and a GPU die
+ *                 sweeps one strip through its planes before the next, so the
+ *                 planes above and below stay in its cache (1: plain order)
+ *   [1] cols4     stencil sweeps with four columns per thread (1), one (0), or
+ *                 the default (-1: four for widths >= 4 except FP64 27-point)
+ *   [2] split     first sweep from zero as its own kernel before the residual
+ *                 (1), fused with it (0), or the default rule (-1)
+ *   [3] strips_mv, [4] cols4_mv   the same for the FP64 product of PCG on level 0
+ *                 when cycle_precision = SSAMG_FP32 (it then has its own part
+ *                 descriptors; in an FP64 cycle the product follows [0] and [1])
+ * Records are kept per level shape (cycle precision, boxes, stencil sizes,
+ * coarsening directions) and width, so they survive a new setup of the same
+ * shapes. */
+
+/* Time the candidate options of every level of width nrhs that has at least
+ * 2^16 (cell, right-hand side) elements and runs grid kernels, and keep the
+ * fastest (a candidate must beat the current choice by 2 %).  Needs the numeric
+ * setup; overwrites the work vectors (not x or b of any solve).  cache_path:
+ * NULL, or a JSON file of records (read first: levels found there are not
+ * timed; written back with every record the solver holds, records of other
+ * shapes in the file kept).  Widths below 4 have nothing to tune (SSAMG_OK).
+ * SSAMG_ERR_ARG: nrhs not a power of two <= max_nrhs; SSAMG_ERR_STATE: no
+ * numeric setup; SSAMG_ERR_ARG with a message when the file cannot be read or
+ * written. */
+ssamg_status ssamg_autotune(ssamg_solver s, int nrhs, const char *cache_path);
+
+/* rec[0..4] = the options level `level` uses for width nrhs (stored or
+ * defaults), rec[5] = 1 when a record is stored.  Needs the symbolic setup. */
+ssamg_status ssamg_tune_get(ssamg_solver s, int level, int nrhs, int rec[6]);
+
+/* Store a record (values as above; SSAMG_ERR_ARG for values out of range or
+ * four columns per thread where not available). */
+ssamg_status ssamg_tune_set(ssamg_solver s, int level, int nrhs, const int rec[5]);
 
 /* y = A_l x at level `level` in FP64 (device vectors of that level's size). */
 ssamg_status ssamg_apply_A(ssamg_solver s, int level, const double *x, double *y);

@@ -46,7 +46,7 @@ class ssamg_params(C.Structure):
     _fields_ = [("max_levels", C.c_int), ("min_coarse_size", C.c_int64), ("relax", C.c_int),
                 ("omega", C.c_double), ("coarse", C.c_int), ("cycle_precision", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
-                ("use_graph", C.c_int), ("skip", C.c_int)]
+                ("use_graph", C.c_int), ("skip", C.c_int), ("autotune", C.c_int)]
 
 
 class ssamg_info(C.Structure):
@@ -86,6 +86,9 @@ SIGNATURES = {
     "ssamg_params_default": [C.POINTER(ssamg_params)],
     "ssamg_solver_create": [P, C.POINTER(ssamg_params), P, PP],
     "ssamg_update_coeffs": [P, I, P, I],
+    "ssamg_autotune": [P, I, C.c_char_p],
+    "ssamg_tune_get": [P, I, I, C.POINTER(C.c_int)],
+    "ssamg_tune_set": [P, I, I, C.POINTER(C.c_int)],
     "ssamg_solver_destroy": [P],
     "ssamg_setup_symbolic": [P],
     "ssamg_workspace_bytes": [P, C.POINTER(C.c_size_t)],

@@ -1,8 +1,12 @@
 // C ABI of the solver object (include/ssamg.h).
 #include <cmath>
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 
 #include "capi_common.h"
 #include "ssamg_impl.h"
@@ -33,6 +37,62 @@ void check_part(const Solver *s, int level, int part) {
   if (part < 0 || part >= (int)s->lv[level].parts.size()) throw Error(SSAMG_ERR_ARG, "part out of range");
 }
 
+int width_lg(const Solver *s, int nrhs) {
+  if (nrhs < 1 || nrhs > s->prm.max_nrhs || (nrhs & (nrhs - 1)))
+    throw Error(SSAMG_ERR_ARG, "nrhs must be a power of two <= max_nrhs");
+  int lg = 0;
+  while ((1 << lg) < nrhs) ++lg;
+  return lg;
+}
+
+// Autotuner cache: a JSON object whose "records" array holds one object per
+// line, {"key": ..., "strips": ..., "cols4": ..., "split": ..., "strips_mv":
+// ..., "cols4_mv": ...}, keys in this order (the file is written here).
+const char *kCacheFormat = "ssamg-autotune-1";
+
+std::map<std::string, TuneRec> read_cache(const char *path) {
+  std::map<std::string, TuneRec> out;
+  std::ifstream f(path);
+  if (!f) return out;                 // no file yet
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  if (text.find(kCacheFormat) == std::string::npos)
+    throw Error(SSAMG_ERR_ARG, std::string("not an autotuner cache: ") + path);
+  size_t at = 0;
+  while ((at = text.find("{\"key\":", at)) != std::string::npos) {
+    char key[1024];
+    TuneRec r;
+    const int n = std::sscanf(text.c_str() + at,
+                              "{\"key\": \"%1023[^\"]\", \"strips\": %d, \"cols4\": %d, \"split\": %d, "
+                              "\"strips_mv\": %d, \"cols4_mv\": %d}",
+                              key, &r.strips, &r.cols4, &r.split, &r.strips_mv, &r.cols4_mv);
+    if (n != 6) throw Error(SSAMG_ERR_ARG, std::string("malformed record in ") + path);
+    out[key] = r;
+    ++at;
+  }
+  return out;
+}
+
+void write_cache(const char *path, const std::map<std::string, TuneRec> &recs) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) throw Error(SSAMG_ERR_ARG, std::string("cannot write ") + tmp);
+    f << "{\"format\": \"" << kCacheFormat << "\", \"records\": [\n";
+    size_t i = 0;
+    for (const auto &kv : recs) {
+      const TuneRec &r = kv.second;
+      f << "  {\"key\": \"" << kv.first << "\", \"strips\": " << r.strips << ", \"cols4\": " << r.cols4
+        << ", \"split\": " << r.split << ", \"strips_mv\": " << r.strips_mv << ", \"cols4_mv\": " << r.cols4_mv
+        << "}" << (++i < recs.size() ? "," : "") << "\n";
+    }
+    f << "]}\n";
+    if (!f) throw Error(SSAMG_ERR_ARG, std::string("cannot write ") + tmp);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) throw Error(SSAMG_ERR_ARG, std::string("cannot write ") + path);
+}
+
 }  // namespace
 
 extern "C" {
@@ -54,6 +114,7 @@ ssamg_status ssamg_params_default(ssamg_params *p) {
   p->max_nrhs = 1;
   p->use_graph = 1;
   p->skip = 0;
+  p->autotune = 0;
   API_END
 }
 
@@ -73,6 +134,7 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (p.coarse != SSAMG_COARSE_SWEEP && p.coarse != SSAMG_COARSE_DIRECT)
     throw Error(SSAMG_ERR_ARG, "coarse must be SSAMG_COARSE_SWEEP or SSAMG_COARSE_DIRECT");
   if (p.skip != 0 && p.skip != 1) throw Error(SSAMG_ERR_ARG, "skip must be 0 or 1");
+  if (p.autotune != 0 && p.autotune != 1) throw Error(SSAMG_ERR_ARG, "autotune must be 0 or 1");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
     throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
   if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw Error(SSAMG_ERR_ARG, "tol must be positive");
@@ -163,6 +225,62 @@ ssamg_status ssamg_solve(ssamg_solver h, int nrhs, const double *b, double *x, s
     set_last_error(e.what());
     return SSAMG_ERR_ARG;
   }
+}
+
+ssamg_status ssamg_autotune(ssamg_solver h, int nrhs, const char *cache_path) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 2, "setup_numeric must come first");
+  const int lg = width_lg(s, nrhs);
+  std::map<std::string, TuneRec> file;
+  if (cache_path) {
+    file = read_cache(cache_path);
+    for (int l = 0; l < (int)s->lv.size(); ++l) {
+      bool have = false;
+      (void)tune_rec(*s, l, lg, &have);
+      auto it = file.find(tune_key(*s, l, lg));
+      if (!have && it != file.end()) tune_store(*s, l, lg, it->second);
+    }
+  }
+  autotune(*s, lg);
+  if (cache_path) {
+    for (const auto &kv : s->tune) file[kv.first] = kv.second;
+    write_cache(cache_path, file);
+  }
+  API_END
+}
+
+ssamg_status ssamg_tune_get(ssamg_solver h, int level, int nrhs, int rec[6]) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  check_level(s, level);
+  if (!rec) throw Error(SSAMG_ERR_ARG, "NULL output");
+  bool found = false;
+  const TuneRec r = tune_rec(*s, level, width_lg(s, nrhs), &found);
+  rec[0] = r.strips;
+  rec[1] = r.cols4;
+  rec[2] = r.split;
+  rec[3] = r.strips_mv;
+  rec[4] = r.cols4_mv;
+  rec[5] = found ? 1 : 0;
+  API_END
+}
+
+ssamg_status ssamg_tune_set(ssamg_solver h, int level, int nrhs, const int rec[5]) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  check_level(s, level);
+  if (!rec) throw Error(SSAMG_ERR_ARG, "NULL record");
+  TuneRec r;
+  r.strips = rec[0];
+  r.cols4 = rec[1];
+  r.split = rec[2];
+  r.strips_mv = rec[3];
+  r.cols4_mv = rec[4];
+  tune_store(*s, level, width_lg(s, nrhs), r);
+  API_END
 }
 
 ssamg_status ssamg_apply_A(ssamg_solver h, int level, const double *x, double *y) {

@@ -24,6 +24,9 @@ namespace {
 
 using dev::cell_ijk;
 using dev::chunk_index;
+using dev::chunk_index_tiled;
+using dev::G;
+using dev::gload;
 using dev::nb_mask;
 using dev::nb_ok;
 
@@ -31,7 +34,7 @@ using dev::nb_ok;
 // smoother factor of cell c: omega_p / a_ii (Jacobi) or factor / sum|a_ij| (L1)
 template <typename T>
 __device__ __forceinline__ T smooth_factor(const PartDesc<T> &d, long long c) {
-  return d.rs ? d.rs[c] : d.omega / d.coef[(long long)d.center * d.ncell + c];
+  return d.rs ? G(d.rs)[c] : d.omega / G(d.coef)[(long long)d.center * d.ncell + c];
 }
 
 // sum_s a_s(c) x(c + s) over the part's stencil; all loads are issued before
@@ -41,7 +44,7 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
   const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
-  const T *cf = d.coef + c;
+  const auto cf = G(d.coef) + c;
   T a[NENT], xv[NENT];
 #pragma unroll
   for (int s = 0; s < NENT; ++s) {
@@ -62,8 +65,8 @@ __device__ __forceinline__ T stencil_wb(const PartDesc<T> &d, int c, int lg, con
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
   const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
-  const T *cf = d.coef + c;
-  const T *wp = d.rs + c;
+  const auto cf = G(d.coef) + c;
+  const auto wp = G(d.rs) + c;
   T a[NENT], bv[NENT], wv[NENT];
 #pragma unroll
   for (int s = 0; s < NENT; ++s) {
@@ -137,7 +140,7 @@ __device__ __forceinline__ T row_sum(const T *__restrict__ prod, int q0, int q1,
 template <int UCH, typename T, typename XS>
 __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int lg, XS xs,
                                             T *__restrict__ prod, T *__restrict__ rsum) {
-  const int *ub = d.ublk[lg] + 2 * chunk;
+  const auto ub = G(d.ublk[lg]) + 2 * chunk;
   const int u0 = ub[0], e0 = ub[1], u1 = ub[2], e1 = ub[3];
   if (u0 == u1) return T(0);                          // block-uniform
   const int tid = threadIdx.x;
@@ -147,9 +150,9 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
   int rq0 = 0, rq1 = 0, rslot = 0;
   if (tid < nrt) {
     const int r = u0 + (tid >> lg);
-    rq0 = d.uptr[r];
-    rq1 = d.uptr[r + 1];
-    rslot = ((d.urow[r] - cell0) << lg) | (tid & mask);
+    rq0 = G(d.uptr)[r];
+    rq1 = G(d.uptr)[r + 1];
+    rslot = ((G(d.urow)[r] - cell0) << lg) | (tid & mask);
   }
   rsum[tid] = T(0);
   T racc = T(0);
@@ -162,8 +165,8 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
     for (int t = 0; t < UCH / kBlock; ++t) {
       const int q = tid + t * kBlock;
       const bool in = q < np;
-      cc[t] = in ? d.ucol[ec + (q >> lg)] : 0;
-      vv[t] = in ? d.uval[ec + (q >> lg)] : T(0);
+      cc[t] = in ? gload(d.ucol + ec + (q >> lg)) : 0;
+      vv[t] = in ? gload(d.uval + ec + (q >> lg)) : T(0);
     }
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
@@ -209,12 +212,12 @@ __device__ __forceinline__ void restrict_one(const PartDesc<T> &d, int cc, int k
   if (fi[ds] - 1 >= 0) {
     g[ds] = ci[ds] - 1;
     const int fl = g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2]);
-    v = fma(d.wp[fl], rp[-((long long)stride << lg)], v);
+    v = fma(G(d.wp)[fl], rp[-((long long)stride << lg)], v);
   }
   if (fi[ds] + 1 <= d.n[ds] - 1) {
     g[ds] = ci[ds];
     const int fl = g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2]);
-    v = fma(d.wm[fl], rp[(long long)stride << lg], v);
+    v = fma(G(d.wm)[fl], rp[(long long)stride << lg], v);
   }
   bc[oc] = v;
 }
@@ -242,10 +245,10 @@ __device__ __forceinline__ void interp_one(const PartDesc<T> &d, int c, int kr, 
   g[ds] = (id - 1) >> 1;
   const int fl = g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2]);
   const int cm = g[0] + d.cn[0] * (g[1] + d.cn[1] * g[2]);
-  T v = d.wm[fl] * xc[((d.coff + cm) << lg) + kr];
+  T v = G(d.wm)[fl] * xc[((d.coff + cm) << lg) + kr];
   if (id + 1 <= d.n[ds] - 1) {
     const int cstride = ds == 0 ? 1 : (ds == 1 ? d.cn[0] : d.cn[0] * d.cn[1]);
-    v = fma(d.wp[fl], xc[((d.coff + cm + cstride) << lg) + kr], v);
+    v = fma(G(d.wp)[fl], xc[((d.coff + cm + cstride) << lg) + kr], v);
   }
   x[o] += v;
 }
@@ -306,9 +309,9 @@ __global__ __launch_bounds__(kBlock) void k_smooth_resid(const PartDesc<T> *__re
   const int kr = (int)(e & ((1 << lg) - 1));
   const long long o = ((d.off + c) << lg) + kr;
   const TB *bp = b + o;
-  const T *wp = d.rs + c;
+  const auto wp = G(d.rs) + c;
   T acc = valid ? stencil_wb<T, TB, NENT>(d, c, lg, bp) : T(0);
-  const T *wl = d.rs - d.off;   // factors of the whole level
+  const auto wl = G(d.rs) - d.off;   // factors of the whole level
   acc += block_coupling<UCH>(
       d, chunk, lg, [&](int col, int k) { return wl[col] * (T)b[((long long)col << lg) + k]; }, prod,
       rsum);
@@ -348,7 +351,10 @@ __device__ __forceinline__ void store4(double *p, const double v[4]) {
   reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
 }
 
-// stencil_acc for the four columns at xp (x of the cell's first column)
+// stencil_acc for the four columns at xp (x of the cell's first column).  Every
+// load is issued unconditionally (an absent entry reads entry 0, an absent
+// neighbour the cell itself) and the value is zeroed afterwards, so all loads
+// of the stencil are in flight together.
 template <typename T, int NENT>
 __device__ __forceinline__ void stencil_acc4(const PartDesc<T> &d, int c, int lg, const T *xp, T acc[4]) {
   int i, j, k;
@@ -356,22 +362,20 @@ __device__ __forceinline__ void stencil_acc4(const PartDesc<T> &d, int c, int lg
   const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
   const T *cf = d.coef + c;
   T a[NENT], xv[NENT][4];
+  bool act[NENT], ok[NENT];
 #pragma unroll
   for (int s = 0; s < NENT; ++s) {
-    const bool act = s < d.nent;
-    a[s] = act ? cf[(long long)s * d.ncell] : T(0);
-    if (act && nb_ok(mx, my, mz, d.code[s])) {
-      load4(xp + ((long long)d.lin[s] << lg), xv[s]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xv[s][q] = T(0);
-    }
+    act[s] = s < d.nent;
+    ok[s] = act[s] && nb_ok(mx, my, mz, d.code[s]);
+    a[s] = gload(cf + (act[s] ? (long long)s * d.ncell : 0LL));
+    load4(xp + (ok[s] ? ((long long)d.lin[s] << lg) : 0LL), xv[s]);
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     acc[q] = T(0);
 #pragma unroll
-    for (int s = 0; s < NENT; ++s) acc[q] = fma(a[s], xv[s][q], acc[q]);
+    for (int s = 0; s < NENT; ++s)
+      acc[q] = fma(act[s] ? a[s] : T(0), ok[s] ? xv[s][q] : T(0), acc[q]);
   }
 }
 
@@ -382,7 +386,7 @@ __device__ __forceinline__ void block_coupling4(const PartDesc<T> &d, int chunk,
                                                 T *__restrict__ prod, T *__restrict__ rsum, T out[4]) {
   const int lgc = lg - 2;
   const int *ub = d.ublk[lgc] + 2 * chunk;
-  const int u0 = ub[0], e0 = ub[1], u1 = ub[2], e1 = ub[3];
+  const int u0 = gload(ub), e0 = gload(ub + 1), u1 = gload(ub + 2), e1 = gload(ub + 3);
 #pragma unroll
   for (int q = 0; q < 4; ++q) out[q] = T(0);
   if (u0 == u1) return;                               // block-uniform
@@ -399,9 +403,9 @@ __device__ __forceinline__ void block_coupling4(const PartDesc<T> &d, int chunk,
     racc[q] = T(0);
     if (t < nrt) {
       const int r = u0 + (t >> lg);
-      rq0[q] = d.uptr[r];
-      rq1[q] = d.uptr[r + 1];
-      rslot[q] = ((d.urow[r] - cell0) << lg) | (t & mask);
+      rq0[q] = gload(d.uptr + r);
+      rq1[q] = gload(d.uptr + r + 1);
+      rslot[q] = ((gload(d.urow + r) - cell0) << lg) | (t & mask);
     }
     rsum[t] = T(0);
   }
@@ -414,8 +418,8 @@ __device__ __forceinline__ void block_coupling4(const PartDesc<T> &d, int chunk,
     for (int t = 0; t < UCH / kBlock; ++t) {
       const int q = tid + t * kBlock;
       const bool in = q < np;
-      cc[t] = in ? d.ucol[ec + (q >> lg)] : 0;
-      vv[t] = in ? d.uval[ec + (q >> lg)] : T(0);
+      cc[t] = in ? gload(d.ucol + ec + (q >> lg)) : 0;
+      vv[t] = in ? gload(d.uval + ec + (q >> lg)) : T(0);
     }
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
   __shared__ T prod[UCH];
   __shared__ T rsum[4 * kBlock];
   const PartDesc<T> &d = desc[blockIdx.y];
-  const int chunk = chunk_index();
+  const int chunk = chunk_index_tiled(d.tbp[lg], d.tsb[lg]);
   const int lgc = lg - 2;
   const long long e = (long long)chunk * kBlock + threadIdx.x;
   const long long nel = d.ncell << lgc;
@@ -539,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict4(const PartDesc<T> *__restr
   int g[3] = {ci[0], ci[1], ci[2]};
   if (fi[ds] - 1 >= 0) {
     g[ds] = ci[ds] - 1;
-    const T w = d.wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
+    const T w = G(d.wp)[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
     T t[4];
     load4(rp - ((long long)stride << lg), t);
 #pragma unroll
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict4(const PartDesc<T> *__restr
   }
   if (fi[ds] + 1 <= d.n[ds] - 1) {
     g[ds] = ci[ds];
-    const T w = d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
+    const T w = G(d.wm)[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
     T t[4];
     load4(rp + ((long long)stride << lg), t);
 #pragma unroll
@@ -586,13 +590,13 @@ __global__ __launch_bounds__(kBlock) void k_interp_add4(const PartDesc<T> *__res
       const int cm = g[0] + d.cn[0] * (g[1] + d.cn[1] * g[2]);
       T t[4];
       load4(xc + ((d.coff + cm) << lg) + k4, t);
-      const T wm = d.wm[fl];
+      const T wm = G(d.wm)[fl];
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] = wm * t[q];
       if (id + 1 <= d.n[ds] - 1) {
         const int cstride = ds == 0 ? 1 : (ds == 1 ? d.cn[0] : d.cn[0] * d.cn[1]);
         load4(xc + ((d.coff + cm + cstride) << lg) + k4, t);
-        const T wp = d.wp[fl];
+        const T wp = G(d.wp)[fl];
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = fma(wp, t[q], v[q]);
       }
@@ -801,10 +805,8 @@ inline unsigned grid_cells(long long n, int lg) {
 
 template <typename T, typename TB, typename TO, int BIG, int NENT>
 void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T *x, const TB *b, TO *y,
-                  hipStream_t st, const LaunchEvents &ev) {
-  // four columns per thread for batched solves (not for FP64 27-point stencils,
-  // whose 108 neighbour values would not fit the register file)
-  if (lg >= 2 && !(sizeof(T) == 8 && NENT > 15)) {
+                  hipStream_t st, const LaunchEvents &ev, bool c4) {
+  if (c4) {
     dim3 g4((grid.x + 3) / 4 > 0 ? (unsigned)(((long long)grid.x + 3) / 4) : 1u, grid.y);
     if (mode == MODE_APPLY)
       dispatch(k_stencil4<T, MODE_APPLY, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
@@ -828,22 +830,23 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
-                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev) {
+                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev, int cols4) {
   dim3 grid(grid_cells(maxcell, lg), nparts);
+  const bool c4 = cols4 != 0 && stencil_cols4_ok<T>(lg, maxent);
   if (fine || (long long)maxcell * nparts >= kBigLevel) {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev);
+      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev);
+      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4);
     else
-      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev);
+      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4);
   } else {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev);
+      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev);
+      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4);
     else
-      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev);
+      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4);
   }
 }
 
@@ -906,13 +909,13 @@ void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
 
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
                                                      int, const double *, const double *, double *,
-                                                     hipStream_t, LaunchEvents);
+                                                     hipStream_t, LaunchEvents, int);
 template void launch_stencil<float, float, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                  const float *, const float *, float *, hipStream_t, LaunchEvents);
+                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int);
 template void launch_stencil<float, double, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                   const float *, const double *, float *, hipStream_t, LaunchEvents);
+                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int);
 template void launch_stencil<float, double, double>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                    const float *, const double *, double *, hipStream_t, LaunchEvents);
+                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int);
 template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
                                                  const double *, double *, hipStream_t);
 template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,

@@ -134,7 +134,7 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
 
 template <typename T>
 PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coef, const T *w,
-                      const T *uval, const T *rs = nullptr) {
+                      const T *uval, const T *rs, const int strips[kMaxLg + 1]) {
   PartDesc<T> d{};
   d.rs = rs ? rs + q.off : nullptr;
   for (int a = 0; a < 3; ++a) {
@@ -161,6 +161,12 @@ PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coe
   d.uval = uval;
   for (int lg = 0; lg <= kMaxLg; ++lg)
     d.ublk[lg] = V.d_ublk[lg] ? V.d_ublk[lg] + 2 * V.ublk_off[lg][p] : nullptr;
+  // block order of the four-column sweeps: whole blocks per z-plane, strips of it
+  for (int lg = 2; lg <= kMaxLg; ++lg) {
+    const long long cpb = (long long)(kBlock * 4) >> lg, plane = (long long)q.n[0] * q.n[1];
+    d.tbp[lg] = (plane % cpb == 0) ? (int)(plane / cpb) : 0;
+    d.tsb[lg] = (d.tbp[lg] > 0 && strips[lg] > 1) ? (d.tbp[lg] + strips[lg] - 1) / strips[lg] : 0;
+  }
   for (size_t e = 0; e < q.pat.size(); ++e) {
     const auto &o = q.pat[e];
     d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
@@ -175,7 +181,92 @@ void upload(T *dst, const std::vector<T> &src, hipStream_t st) {
     SSAMG_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
+// Part descriptors of level l in FP64 and (mixed-precision cycle) FP32, with
+// the block order of the stored launch options: the cycle's descriptors take
+// the cycle's strips; in a mixed-precision cycle the FP64 ones of level 0 serve
+// the FP64 product of PCG and take its strips.
+void build_descs(const Solver &s, int l, std::vector<PartDesc<double>> &h64,
+                 std::vector<PartDesc<float>> &h32) {
+  const Level &V = s.lv[l];
+  const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
+  int cyc[kMaxLg + 1], mv[kMaxLg + 1];
+  for (int lg = 0; lg <= kMaxLg; ++lg) {
+    const TuneRec r = tune_rec(s, l, lg);
+    cyc[lg] = r.strips;
+    mv[lg] = mixed ? (l == 0 ? r.strips_mv : 1) : r.strips;
+  }
+  h64.clear();
+  h32.clear();
+  for (size_t p = 0; p < V.parts.size(); ++p) {
+    const PartLevel &q = V.parts[p];
+    h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64, mv));
+    if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32, cyc));
+  }
+}
+
+// Shape of level l as the launch options see it (cycle precision, first level
+// or not, and per part the box, stencil size and coarsening direction).
+std::string level_sig(const Solver &s, int l) {
+  const Level &V = s.lv[l];
+  std::string k = (s.prm.cycle_precision == SSAMG_FP32 ? "f32" : "f64");
+  k += l == 0 ? ":fine" : ":coarse";
+  for (const auto &q : V.parts)
+    k += ":" + std::to_string(q.n[0]) + "x" + std::to_string(q.n[1]) + "x" + std::to_string(q.n[2]) + "e" +
+         std::to_string(q.pat.size()) + "d" + std::to_string(q.dstar);
+  return k;
+}
+
+void drop_graph(Solver &s) {
+  if (s.graph_exec) (void)hipGraphExecDestroy(s.graph_exec);
+  if (s.graph) (void)hipGraphDestroy(s.graph);
+  s.graph_exec = nullptr;
+  s.graph = nullptr;
+  s.graph_nrhs = 0;
+}
+
 }  // namespace
+
+std::string tune_key(const Solver &s, int l, int lg) {
+  return s.sig.at(l) + "|lg" + std::to_string(lg);
+}
+
+TuneRec tune_rec(const Solver &s, int l, int lg, bool *found) {
+  if (found) *found = false;
+  if (l < 0 || l >= (int)s.sig.size() || s.tune.empty()) return TuneRec{};
+  auto it = s.tune.find(tune_key(s, l, lg));
+  if (it == s.tune.end()) return TuneRec{};
+  if (found) *found = true;
+  return it->second;
+}
+
+void tune_store(Solver &s, int l, int lg, const TuneRec &r) {
+  if (s.state < 1) throw Error(SSAMG_ERR_STATE, "launch options need the symbolic setup");
+  if (l < 0 || l >= (int)s.lv.size()) throw Error(SSAMG_ERR_ARG, "level out of range");
+  if (lg < 0 || lg > kMaxLg) throw Error(SSAMG_ERR_ARG, "batch width out of range");
+  auto tri = [](int v) { return v >= -1 && v <= 1; };
+  if (r.strips < 1 || r.strips > 64 || r.strips_mv < 1 || r.strips_mv > 64)
+    throw Error(SSAMG_ERR_ARG, "strips must be in 1..64");
+  if (!tri(r.cols4) || !tri(r.split) || !tri(r.cols4_mv))
+    throw Error(SSAMG_ERR_ARG, "cols4, split and cols4_mv take -1, 0 or 1");
+  const Level &V = s.lv[l];
+  const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
+  const bool ok_cyc = mixed ? stencil_cols4_ok<float>(lg, V.maxent) : stencil_cols4_ok<double>(lg, V.maxent);
+  if (r.cols4 == 1 && !ok_cyc)
+    throw Error(SSAMG_ERR_ARG, "four columns per thread need a batch of 4 or more (and no FP64 27-point stencil)");
+  if (r.cols4_mv == 1 && !stencil_cols4_ok<double>(lg, V.maxent))
+    throw Error(SSAMG_ERR_ARG, "four columns per thread for the FP64 product need a batch of 4 or more "
+                               "and at most 15-point stencils");
+  s.tune[tune_key(s, l, lg)] = r;
+  drop_graph(s);
+  if (s.state >= 2) {
+    std::vector<PartDesc<double>> h64;
+    std::vector<PartDesc<float>> h32;
+    build_descs(s, l, h64, h32);
+    upload(s.lv[l].d_desc64, h64, s.stream);
+    if (mixed) upload(s.lv[l].d_desc32, h32, s.stream);
+    SSAMG_HIP(hipStreamSynchronize(s.stream));
+  }
+}
 
 Solver::~Solver() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -340,9 +431,10 @@ void setup_symbolic(Solver &s) {
   {
     std::vector<PartDesc<double>> hd;
     int maxcell = 0;
+    const int plain[kMaxLg + 1] = {1, 1, 1, 1, 1, 1};
     for (size_t p = 0; p < L0.parts.size(); ++p) {
       const PartLevel &q = L0.parts[p];
-      hd.push_back(make_desc<double>(L0, q, p, q.coef64, nullptr, nullptr));
+      hd.push_back(make_desc<double>(L0, q, p, q.coef64, nullptr, nullptr, nullptr, plain));
       maxcell = std::max<int64_t>(maxcell, q.ncell);
     }
     s.wsum_buf.reserve(np * sizeof(PartDesc<double>) + (size_t)np * 256 * 3 * 8 + np * 3 * 8 + 1024);
@@ -460,6 +552,8 @@ void setup_symbolic(Solver &s) {
   Carver cv;
   carve(s, cv);
   s.ws_bytes = cv.off + 256;
+  s.sig.clear();
+  for (int l = 0; l < (int)s.lv.size(); ++l) s.sig.push_back(level_sig(s, l));
   s.state = 1;
   if (s.verbose) {
     size_t unnz = 0, contrib = 0;
@@ -588,10 +682,9 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     std::vector<PartDesc<double>> h64;
     std::vector<PartDesc<float>> h32;
     std::vector<RapDesc> hr;
+    build_descs(s, l, h64, h32);
     for (size_t p = 0; p < V.parts.size(); ++p) {
       PartLevel &q = V.parts[p];
-      h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64));
-      if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32));
       if (l < L - 1) {
         putv(q.d_rap_start, q.rap_start);
         putv(q.d_rap_code, q.rap_code);
@@ -733,11 +826,14 @@ struct Probe {
 // writing x and running the plain residual sweep.
 template <typename T, typename TB>
 void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int lg, const TB *b, T *x, T *t,
-                LaunchEvents ev = {}) {
+                const TuneRec &o, LaunchEvents ev = {}) {
   const int np = (int)V.parts.size();
-  if (lg >= 2 ? (V.N << lg) >= s.split_cells : (V.maxent > 15 && V.N >= s.split_cells)) {
+  const bool split = o.split >= 0 ? o.split == 1
+                                  : (lg >= 2 ? (V.N << lg) >= s.split_cells
+                                             : (V.maxent > 15 && V.N >= s.split_cells));
+  if (split) {
     launch_smooth_zero<T, TB>(fine, d, np, V.maxcell, lg, b, x, s.stream);
-    launch_stencil<T, TB, T>(MODE_RESID, fine, V.maxent, d, np, V.maxcell, lg, x, b, t, s.stream, ev);
+    launch_stencil<T, TB, T>(MODE_RESID, fine, V.maxent, d, np, V.maxcell, lg, x, b, t, s.stream, ev, o.cols4);
   } else {
     launch_smooth_resid<T, TB>(fine, V.maxent, d, np, V.maxcell, lg, b, x, t, s.stream, ev);
   }
@@ -764,7 +860,7 @@ void run_tail(Solver &s, int lg) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
-    down_sweep<T, T>(s, V, d, 0, lg, b, x, t);
+    down_sweep<T, T>(s, V, d, 0, lg, b, x, t, tune_rec(s, l, lg));
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, L - lt, lg, st);
@@ -773,7 +869,8 @@ void run_tail(Solver &s, int lg) {
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
     launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[l + 1].vt, x, st);
-    launch_stencil<T, T, T>(MODE_JACOBI, 0, V.maxent, d, np, V.maxcell, lg, x, b, t, st);
+    launch_stencil<T, T, T>(MODE_JACOBI, 0, V.maxent, d, np, V.maxcell, lg, x, b, t, st, {},
+                            tune_rec(s, l, lg).cols4);
   }
 }
 
@@ -827,9 +924,10 @@ void precond_t(Solver &s, int lg) {
     }
     return;
   }
+  const TuneRec o = tune_rec(s, 0, lg);
   {
     Probe pr(s, SSAMG_PROBE_RESID0, level0_bytes(s, SSAMG_PROBE_RESID0, lg, tc, tx, 8, tx));
-    down_sweep<T, double>(s, V, d, 1, lg, s.r, x, t, pr.e);
+    down_sweep<T, double>(s, V, d, 1, lg, s.r, x, t, o, pr.e);
   }
   {
     Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
@@ -843,7 +941,7 @@ void precond_t(Solver &s, int lg) {
   {
     Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, 8, 8));
     launch_stencil<T, double, double>(MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x, s.r, s.z, st,
-                                      pr.e);
+                                      pr.e, o.cols4);
   }
 }
 
@@ -856,10 +954,12 @@ void precond(Solver &s, int lg) {
 
 void apply_A0(Solver &s, int lg, const double *x, double *y) {
   Level &V = s.lv[0];
+  const TuneRec o = tune_rec(s, 0, lg);
+  const int cols4 = s.prm.cycle_precision == SSAMG_FP32 ? o.cols4_mv : o.cols4;
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
     launch_stencil<double, double, double>(MODE_APPLY, 1, V.maxent, V.d_desc64, (int)V.parts.size(), V.maxcell,
-                                           lg, x, nullptr, y, s.stream, pr.e);
+                                           lg, x, nullptr, y, s.stream, pr.e, cols4);
   }
 }
 
@@ -871,6 +971,183 @@ void apply_level(Solver &s, int level, const double *x, double *y) {
                                          V.maxcell, 0, x, nullptr, y, s.stream);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(s.stream));
+}
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+// Fastest of three timed launches (after one untimed), in milliseconds.
+template <typename F>
+double time_best(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&launch) {
+  launch();
+  double best = 1e30;
+  for (int r = 0; r < 3; ++r) {
+    SSAMG_HIP(hipEventRecord(e0, st));
+    launch();
+    SSAMG_HIP(hipEventRecord(e1, st));
+    SSAMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SSAMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    best = std::min(best, (double)ms);
+  }
+  return best;
+}
+
+// Strip counts worth timing for a level's four-column sweeps: more than one
+// only when some part's blocks tile its z-planes and the grid's eight XCD
+// ranges hold whole planes (otherwise every count gives the plain order).
+std::vector<int> strip_candidates(const Level &V, int lg) {
+  std::vector<int> c;
+  const long long cpb = (long long)(kBlock * 4) >> lg;
+  const long long nblk = (((long long)V.maxcell << lg) + kBlock * 4 - 1) / (kBlock * 4);
+  bool tiles = false;
+  for (const auto &q : V.parts) {
+    const long long plane = (long long)q.n[0] * q.n[1];
+    if (plane % cpb) continue;
+    const long long bp = plane / cpb;
+    if (bp >= 2 && nblk % 8 == 0 && (nblk / 8) % bp == 0) tiles = true;
+  }
+  if (tiles)
+    for (int n : kTuneStrips)
+      if (n > 1) c.push_back(n);
+  return c;
+}
+
+// Times the launch options of every level of width 2^lg that runs grid kernels,
+// holds at least kTuneMinElems elements and has no stored record, and stores
+// the fastest: the stencil sweep (columns per thread, block order), the first
+// sweep (split or fused), and on level 0 of a mixed-precision cycle the FP64
+// product.  A candidate replaces the current choice only if it is at least 2 %
+// faster.  The level's vectors are zeroed first; every option computes the
+// same values, so the timing runs on the hierarchy itself.
+template <typename T>
+int autotune_t(Solver &s, int lg) {
+  hipStream_t st = s.stream;
+  const int np = (int)s.lv[0].parts.size();
+  const bool mixed = sizeof(T) == sizeof(float);
+  const int lt = tail_start(s, lg);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SSAMG_HIP(hipEventCreate(&e0));
+  SSAMG_HIP(hipEventCreate(&e1));
+  int ntuned = 0;
+  try {
+    for (int l = 0; l < lt; ++l) {
+      Level &V = s.lv[l];
+      const int64_t nel = V.N << lg;
+      bool found = false;
+      (void)tune_rec(s, l, lg, &found);
+      if (nel < kTuneMinElems || found) continue;
+      SSAMG_HIP(hipMemsetAsync(V.vx, 0, nel * sizeof(T), st));
+      SSAMG_HIP(hipMemsetAsync(V.vb, 0, nel * sizeof(T), st));
+      SSAMG_HIP(hipMemsetAsync(V.vt, 0, nel * sizeof(T), st));
+      if (l == 0)
+        for (double *v : {s.r, s.z, s.p, s.q}) SSAMG_HIP(hipMemsetAsync(v, 0, nel * sizeof(double), st));
+      T *x = (T *)V.vx, *b = (T *)V.vb, *t = (T *)V.vt;
+      TuneRec best;
+      auto pick = [&](std::vector<TuneRec> cand, auto &&run) {
+        tune_store(s, l, lg, best);
+        double tb = time_best(st, e0, e1, run);
+        for (const TuneRec &r : cand) {
+          tune_store(s, l, lg, r);
+          const double tr = time_best(st, e0, e1, run);
+          if (tr < 0.98 * tb) {
+            best = r;
+            tb = tr;
+          }
+        }
+        tune_store(s, l, lg, best);
+      };
+      // stencil sweep of the cycle
+      {
+        std::vector<TuneRec> cand;
+        TuneRec r = best;
+        r.cols4 = 0;
+        cand.push_back(r);
+        if (stencil_cols4_ok<T>(lg, V.maxent))
+          for (int n : strip_candidates(V, lg)) {
+            r.cols4 = 1;
+            r.strips = n;
+            cand.push_back(r);
+          }
+        pick(cand, [&] {
+          const TuneRec o = tune_rec(s, l, lg);
+          const PartDesc<T> *d = desc_of<T>(V);
+          if (l == 0)
+            launch_stencil<T, double, double>(MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x, s.r, s.z, st,
+                                              {}, o.cols4);
+          else
+            launch_stencil<T, T, T>(MODE_JACOBI, 0, V.maxent, d, np, V.maxcell, lg, x, b, t, st, {}, o.cols4);
+        });
+      }
+      // first sweep: split from the residual or fused with it
+      {
+        std::vector<TuneRec> cand;
+        for (int sp = 0; sp <= 1; ++sp) {
+          TuneRec r = best;
+          r.split = sp;
+          cand.push_back(r);
+        }
+        pick(cand, [&] {
+          const TuneRec o = tune_rec(s, l, lg);
+          const PartDesc<T> *d = desc_of<T>(V);
+          if (l == 0)
+            down_sweep<T, double>(s, V, d, 1, lg, s.r, x, t, o);
+          else
+            down_sweep<T, T>(s, V, d, 0, lg, b, x, t, o);
+        });
+      }
+      // FP64 product of PCG (its own descriptors in a mixed-precision cycle)
+      if (l == 0 && mixed) {
+        std::vector<TuneRec> cand;
+        TuneRec r = best;
+        r.cols4_mv = 0;
+        cand.push_back(r);
+        if (stencil_cols4_ok<double>(lg, V.maxent))
+          for (int n : strip_candidates(V, lg)) {
+            r.cols4_mv = 1;
+            r.strips_mv = n;
+            cand.push_back(r);
+          }
+        pick(cand, [&] {
+          const TuneRec o = tune_rec(s, 0, lg);
+          launch_stencil<double, double, double>(MODE_APPLY, 1, V.maxent, V.d_desc64, np, V.maxcell, lg, s.p,
+                                                 nullptr, s.q, st, {}, o.cols4_mv);
+        });
+      }
+      ++ntuned;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  SSAMG_HIP(hipEventDestroy(e0));
+  SSAMG_HIP(hipEventDestroy(e1));
+  return ntuned;
+}
+
+}  // namespace
+
+int autotune(Solver &s, int lg) {
+  if (s.state < 2) throw Error(SSAMG_ERR_STATE, "autotuning needs the numeric setup");
+  if (lg < 2) return 0;   // the options concern batches of four or more right-hand sides
+  const auto t0 = std::chrono::steady_clock::now();
+  const int n = s.prm.cycle_precision == SSAMG_FP32 ? autotune_t<float>(s, lg) : autotune_t<double>(s, lg);
+  SSAMG_HIP(hipGetLastError());
+  s.tune_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return n;
+}
+
+bool tuned(const Solver &s, int lg) {
+  if (lg < 2) return true;
+  const int lt = tail_start(s, lg);
+  for (int l = 0; l < lt; ++l) {
+    bool found = false;
+    (void)tune_rec(s, l, lg, &found);
+    if ((s.lv[l].N << lg) >= kTuneMinElems && !found) return false;
+  }
+  return true;
 }
 
 void probe_set(Solver &s, int kind) {
@@ -912,10 +1189,11 @@ void apply_precond(Solver &s, const double *r, double *z) {
 // ---------------------------------------------------------------- PCG
 
 ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_info *info) {
-  const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t st = s.stream;
   int lg = 0;
   while ((1 << lg) < nrhs) ++lg;
+  if (s.prm.autotune && !tuned(s, lg)) autotune(s, lg);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = s.stream;
   const int64_t nel = s.lv[0].N << lg;
   const bool flexible = s.prm.cycle_precision == SSAMG_FP32;
   double *h = s.h_pin;   // [kScalSlots][kMaxRhs] mirror

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <map>
 #include <memory>
 #include <cstdint>
 #include <stdexcept>
@@ -49,6 +50,22 @@ constexpr int64_t kTailElems = 0;
 constexpr int64_t kSplitCells = 1 << 20;
 // largest coarsest level the direct solve accepts (its inverse is formed in LDS)
 constexpr int kDirectMax = 64;
+// the autotuner times a level's launch options only if the level holds at
+// least this many (cell, right-hand side) elements; below it launches are
+// latency-bound and the defaults stand
+constexpr int64_t kTuneMinElems = 1 << 16;
+// strip counts per z-plane the autotuner tries for the four-column sweeps
+constexpr int kTuneStrips[] = {1, 2, 3, 4, 6, 8};
+
+// Launch options of one level's cycle for one batch width (autotuned, or set
+// through the C ABI); every option gives bit-identical results.
+struct TuneRec {
+  int strips = 1;      // z-plane strips of the four-column sweeps' block order (1: plain order)
+  int cols4 = -1;      // stencil sweeps: four columns per thread (1), one (0), default (-1)
+  int split = -1;      // first sweep: split from the residual (1), fused (0), default rule (-1)
+  int strips_mv = 1;   // level 0, FP64 product of PCG in a mixed-precision cycle: strips
+  int cols4_mv = -1;   // and its columns per thread
+};
 
 // Packed stencil offset: (dx+1) | (dy+1) << 2 | (dz+1) << 4.
 inline int pack_off(int dx, int dy, int dz) { return (dx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4); }
@@ -83,6 +100,11 @@ struct PartDesc {
   const int *ucol;
   const T *uval;
   const int *ublk[kMaxLg + 1];
+  // block order of the four-columns-per-thread sweeps at each lg: blocks per
+  // z-plane (0: planes do not split into whole blocks) and strip width in
+  // blocks (0: plain order)
+  int tbp[kMaxLg + 1];
+  int tsb[kMaxLg + 1];
   // per-cell smoother factor (weighted L1-Jacobi: factor / sum_j |a_ij|);
   // null: weighted Jacobi omega / a_ii
   const T *rs;
@@ -250,6 +272,11 @@ struct Solver {
   size_t pev_next = 0;
   int64_t probe_launches = 0;
   double probe_bytes = 0.0;
+  // autotuned launch options, keyed by level signature and lg (kept across
+  // setups: a level with the same shape finds its record again)
+  std::map<std::string, TuneRec> tune;
+  std::vector<std::string> sig;      // signature of each level of the current hierarchy
+  double tune_s = 0.0;               // seconds spent timing candidates
   ~Solver();
 };
 
@@ -260,6 +287,12 @@ void apply_precond(Solver &s, const double *r, double *z);
 ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_info *info);
 void probe_set(Solver &s, int kind);
 void probe_read(Solver &s, int64_t *launches, double *ms, double *bytes);
+// launch options of level l for width 2^lg: the stored record or defaults
+TuneRec tune_rec(const Solver &s, int l, int lg, bool *found = nullptr);
+void tune_store(Solver &s, int l, int lg, const TuneRec &r);   // validates, re-uploads descriptors
+int autotune(Solver &s, int lg);   // times candidates of every untuned level; returns levels tuned
+bool tuned(const Solver &s, int lg);
+std::string tune_key(const Solver &s, int l, int lg);
 
 enum ScalSlot { S_RZ = 0, S_RZN, S_PQ, S_RR, S_ZQ, S_BB, S_TR, kScalSlots };
 
@@ -318,9 +351,17 @@ struct LaunchEvents {
 };
 
 // kernels_cycle.hip
+// Stencil sweeps of batched solves (lg >= 2) run four right-hand-side columns
+// per thread unless cols4 is 0; never for FP64 27-point stencils, whose 108
+// neighbour values would not fit the register file.
+template <typename T>
+inline bool stencil_cols4_ok(int lg, int maxent) {
+  return lg >= 2 && !(sizeof(T) == 8 && maxent > 15);
+}
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
-                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {});
+                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {},
+                    int cols4 = -1);
 template <typename T>
 void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st);
 template <typename T, typename TB>

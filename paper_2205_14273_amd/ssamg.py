@@ -128,6 +128,26 @@ def ssamg_setup_numeric(h, ws=None):
         check(lib().ssamg_setup_numeric(h, _ptr(ws), ws.numel() * ws.element_size()))
 
 
+TUNE_FIELDS = ("strips", "cols4", "split", "strips_mv", "cols4_mv")
+
+
+def ssamg_autotune(h, nrhs, cache_path=None):
+    check(lib().ssamg_autotune(h, nrhs, None if cache_path is None else str(cache_path).encode()))
+
+
+def ssamg_tune_get(h, level, nrhs):
+    rec = (C.c_int * 6)()
+    check(lib().ssamg_tune_get(h, level, nrhs, rec))
+    out = dict(zip(TUNE_FIELDS, rec[:5]))
+    out["stored"] = bool(rec[5])
+    return out
+
+
+def ssamg_tune_set(h, level, nrhs, rec):
+    arr = (C.c_int * 5)(*[int(rec[k]) for k in TUNE_FIELDS])
+    check(lib().ssamg_tune_set(h, level, nrhs, arr))
+
+
 def ssamg_update_coeffs(h, part, vals, where):
     if isinstance(vals, torch.Tensor):
         check(lib().ssamg_update_coeffs(h, part, _ptr(vals), where))
@@ -324,6 +344,22 @@ class Solver:
         else:
             ssamg_update_coeffs(self.h, part, np.ascontiguousarray(vals, dtype=np.float64).reshape(-1),
                                 L.MEM_HOST)
+
+    def autotune(self, nrhs, cache_path=None):
+        """Time and keep the fastest launch options of the batched cycle for
+        width nrhs (optionally through a JSON cache file)."""
+        ssamg_autotune(self.h, nrhs, cache_path)
+
+    def tune_get(self, level, nrhs):
+        """Launch options of a level for width nrhs: strips, cols4, split,
+        strips_mv, cols4_mv, and whether they are a stored record."""
+        return ssamg_tune_get(self.h, level, nrhs)
+
+    def tune_set(self, level, nrhs, **rec):
+        """Store launch options (missing fields take the current values)."""
+        cur = ssamg_tune_get(self.h, level, nrhs)
+        cur.update(rec)
+        ssamg_tune_set(self.h, level, nrhs, cur)
 
     def apply_A(self, level, x):
         y = torch.empty_like(x)
