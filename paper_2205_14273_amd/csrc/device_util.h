@@ -39,6 +39,14 @@ __device__ __forceinline__ T gload(const T *p) {
   return *G(p);
 }
 
+template <typename T>
+using gptr_w = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr_w<T> Gw(T *p) {
+  return (gptr_w<T>)p;
+}
+
 // XCD-aware block order: consecutive chunks of one part land on one XCD (the
 // hardware deals blocks round-robin over the 8 XCDs), so the neighbour planes a
 // block re-reads sit in that XCD's L2.

@@ -11,6 +11,7 @@
 // Gradient of L(x): dL/dkappa_c = -lambda^T (dA/dkappa_c) x with A lambda = dL/dx,
 //   i.e. minus the sum over the links of c of dt/dkappa_c times
 //   (lambda_c - lambda_j)(x_c - x_j), or lambda_c x_c for a ghost link.
+#include "device_util.h"
 #include "ssamg_impl.h"
 
 namespace ssamg {
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *
   const int k = (int)(c / ((long long)me.n[0] * me.n[1]));
   const int loc[3] = {i, j, k};
   const double kc = kappa[me.off + c];
-  double *cf = coef[p];
+  const auto cf = dev::Gw(coef[p]);
   double diag = 0.0;
   for (int s = 1; s < fa.nent; ++s) {
     const int code = fa.code[s];

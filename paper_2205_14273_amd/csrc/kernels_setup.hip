@@ -52,11 +52,11 @@ __global__ __launch_bounds__(kBlock) void k_wsum_partial(const PartDesc<double> 
   double acc[3] = {0.0, 0.0, 0.0};
   for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < d.ncell;
        c += (long long)gridDim.x * kBlock) {
-    const double ac = d.coef[(long long)d.center * d.ncell + c];
+    const double ac = dev::G(d.coef)[(long long)d.center * d.ncell + c];
     const double sg = ac < 0.0 ? 1.0 : -1.0;
     for (int s = 0; s < d.nent; ++s) {
       if (s == d.center) continue;
-      const double v = sg * d.coef[(long long)s * d.ncell + c];
+      const double v = sg * dev::G(d.coef)[(long long)s * d.ncell + c];
       for (int q = 0; q < 3; ++q)
         if (off_comp(d.code[s], q) != 0) acc[q] += v;
     }
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
   const long long c = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
   double den = 0.0, sm = 0.0, sp = 0.0;
   for (int s = 0; s < d.nent; ++s) {
-    const double v = d.coef[(long long)s * d.ncell + c];
+    const double v = dev::G(d.coef)[(long long)s * d.ncell + c];
     const int o = off_comp(d.code[s], ds);
     if (o == 0)
       den += v;
@@ -139,12 +139,12 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
     wp = 0.0;
     if ((d.faces >> (2 * ds + 1)) & 1) wm = 1.0;
   }
-  const_cast<double *>(d.wm)[fidx] = wm;
-  const_cast<double *>(d.wp)[fidx] = wp;
+  dev::Gw(const_cast<double *>(d.wm))[fidx] = wm;
+  dev::Gw(const_cast<double *>(d.wp))[fidx] = wp;
   if (desc32) {
     const PartDesc<float> &d32 = desc32[blockIdx.y];
-    const_cast<float *>(d32.wm)[fidx] = (float)wm;
-    const_cast<float *>(d32.wp)[fidx] = (float)wp;
+    dev::Gw(const_cast<float *>(d32.wm))[fidx] = (float)wm;
+    dev::Gw(const_cast<float *>(d32.wp))[fidx] = (float)wp;
   }
 }
 
@@ -156,18 +156,18 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
 // coarse neighbours) when q is odd.  The host table lists, for each coarse
 // entry, the (r, s, which-weight-of-g) triples that land on it.
 //
-// One thread per (coarse cell, coarse entry); a block covers one entry of a
-// tile of kBlock coarse cells, so its threads read the same table rows (scalar
-// loads) and neighbouring fine coefficients (coalesced).  The blocks of one
-// tile (one per coarse entry) are consecutive in the XCD-aware block order, so
-// they run together on one XCD and read the tile's fine coefficients through
-// its L2 rather than once per entry from HBM.  Each thread gathers its
-// contributions kRapBatch at a time with every load in flight before the sums,
-// which keep the table order.
-constexpr int kRapBatch = 4;
+// Two thread layouts form the same sums in the same order, so the same values.
+// Small coarse levels: one thread per (coarse cell, coarse entry), so that
+// even a few thousand coarse cells give enough threads; a block covers one
+// entry of a tile of kBlock coarse cells, its threads read the same table rows
+// and neighbouring fine coefficients, and each thread gathers its entry's
+// contributions kRapEntryBatch at a time.  The blocks of one tile are
+// consecutive in the XCD-aware block order, so they read the tile's fine
+// coefficients through one XCD's L2.
+constexpr int kRapEntryBatch = 4;
 
-__global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restrict__ desc,
-                                                const RapDesc *__restrict__ rd, int nent_max) {
+__global__ __launch_bounds__(kBlock) void k_rap_entry(const PartDesc<double> *__restrict__ desc,
+                                                      const RapDesc *__restrict__ rd, int nent_max) {
   const PartDesc<double> &d = desc[blockIdx.y];
   const RapDesc &t = rd[blockIdx.y];
   const int lb = dev::chunk_index();
@@ -176,9 +176,9 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
   if (e >= t.nent || cidx >= d.cncell) return;
   if (d.dstar < 0) {
     // identity transfer: same operator, entries permuted into the sorted pattern
-    const double v = d.coef[(long long)t.code[e] * d.ncell + cidx];
-    t.out[(long long)e * d.cncell + cidx] = v;
-    if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)v;
+    const double v = dev::G(d.coef)[(long long)dev::G(t.code)[e] * d.ncell + cidx];
+    dev::Gw(t.out)[(long long)e * d.cncell + cidx] = v;
+    if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)v;
     return;
   }
   const int ds = d.dstar;
@@ -194,10 +194,10 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
     row_ok[1] = true;
     row_ok[2] = fb + 1 <= nd - 1;
     g[ds] = ci[ds] - 1;
-    rho[0] = row_ok[0] ? d.wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
+    rho[0] = row_ok[0] ? dev::G(d.wp)[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
     rho[1] = 1.0;
     g[ds] = ci[ds];
-    rho[2] = row_ok[2] ? d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
+    rho[2] = row_ok[2] ? dev::G(d.wm)[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
   }
   // Per-thread bases; every contribution then adds block-uniform offsets: the
   // fine row f = 2I + r is f0 + r*stride(d*), the neighbour g = f + s is in the
@@ -210,17 +210,17 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
   const long long str[3] = {1, d.n[0], (long long)d.n[0] * d.n[1]};
   const long long fstr[3] = {1, d.fn[0], (long long)d.fn[0] * d.fn[1]};
   double acc = 0.0;
-  const int q0 = t.start[e], q1 = t.start[e + 1];
-  for (int qb = q0; qb < q1; qb += kRapBatch) {
-    double av[kRapBatch], wv[kRapBatch], rv[kRapBatch];
+  const int q0 = dev::G(t.start)[e], q1 = dev::G(t.start)[e + 1];
+  for (int qb = q0; qb < q1; qb += kRapEntryBatch) {
+    double av[kRapEntryBatch], wv[kRapEntryBatch], rv[kRapEntryBatch];
 #pragma unroll
-    for (int u = 0; u < kRapBatch; ++u) {
+    for (int u = 0; u < kRapEntryBatch; ++u) {
       const int q = qb + u;
       av[u] = 0.0;
       wv[u] = 1.0;
       rv[u] = 0.0;
       if (q >= q1) continue;
-      const int w = t.code[q];
+      const int w = dev::G(t.code)[q];
       const int r = (w & 3) - 1;
       const int sidx = (w >> 2) & 31;
       const int gsel = (w >> 7) & 3;
@@ -235,15 +235,141 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
         dh += o[a] * fstr[a];
       }
       if (!in) continue;
-      av[u] = d.coef[(long long)sidx * d.ncell + f0 + dfine];
+      av[u] = dev::G(d.coef)[(long long)sidx * d.ncell + f0 + dfine];
       rv[u] = rho[r + 1];
-      if (gsel != 0) wv[u] = gsel == 1 ? d.wm[h0 + dh] : d.wp[h0 + dh];
+      if (gsel != 0) wv[u] = gsel == 1 ? dev::G(d.wm)[h0 + dh] : dev::G(d.wp)[h0 + dh];
     }
 #pragma unroll
-    for (int u = 0; u < kRapBatch; ++u) acc = fma(rv[u] * av[u], wv[u], acc);
+    for (int u = 0; u < kRapEntryBatch; ++u) acc = fma(rv[u] * av[u], wv[u], acc);
   }
-  t.out[(long long)e * d.cncell + cidx] = acc;
-  if (t.out32) t.out32[(long long)e * d.cncell + cidx] = (float)acc;
+  dev::Gw(t.out)[(long long)e * d.cncell + cidx] = acc;
+  if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)acc;
+}
+
+// Large coarse levels: one thread per coarse cell and all coarse entries.  The
+// per-cell work (coarse coordinates, restriction weights, fine and F-box bases)
+// is done once, and the whole table (at most kRapMaxTab rows) is staged in LDS first with its
+// block-uniform parts worked out (coefficient offset, F-box offset, row r,
+// weight selector, neighbour offsets), so no thread waits on a table load
+// before its gathers.  Each thread walks the table kRapBatch rows at a time
+// with every load of a batch in flight before the sums, which keep the table
+// order within each entry; an entry's sum is stored when the walk passes its
+// last row.
+constexpr int kRapBatch = 8;
+
+__global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restrict__ desc,
+                                                const RapDesc *__restrict__ rd) {
+  __shared__ long long s_cof[kRapMaxTab], s_dh[kRapMaxTab];
+  __shared__ int s_w[kRapMaxTab];
+  __shared__ int s_start[kMaxEnt + 1];
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const RapDesc &t = rd[blockIdx.y];
+  const long long tile = (long long)dev::chunk_index() * kBlock;
+  if (tile >= d.cncell) return;                      // block-uniform
+  const long long cidx = tile + threadIdx.x;
+  const bool valid = cidx < d.cncell;
+  const auto coef = dev::G(d.coef);
+  const auto out = dev::Gw(t.out);
+  const auto out32 = dev::Gw(t.out32);
+  const int nent = t.nent;
+  if (d.dstar < 0) {
+    // identity transfer: same operator, entries permuted into the sorted pattern
+    if (!valid) return;
+    for (int e = 0; e < nent; ++e) {
+      const double v = coef[(long long)dev::G(t.code)[e] * d.ncell + cidx];
+      out[(long long)e * d.cncell + cidx] = v;
+      if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)v;
+    }
+    return;
+  }
+  const int ds = d.dstar;
+  const long long str[3] = {1, d.n[0], (long long)d.n[0] * d.n[1]};
+  const long long fstr[3] = {1, d.fn[0], (long long)d.fn[0] * d.fn[1]};
+  const int ntab = dev::G(t.start)[nent];
+  for (int q = threadIdx.x; q < ntab; q += kBlock) {
+    const int w = dev::G(t.code)[q];
+    const int r = (w & 3) - 1;
+    const int sidx = (w >> 2) & 31;
+    const int gsel = (w >> 7) & 3;
+    const int cs = d.code[sidx];
+    long long dh = ((r + off_comp(cs, ds) - 1) >> 1) * fstr[ds];
+    for (int a = 0; a < 3; ++a)
+      if (a != ds) dh += off_comp(cs, a) * fstr[a];
+    s_cof[q] = (long long)sidx * d.ncell + r * str[ds];
+    s_dh[q] = dh;
+    s_w[q] = (r + 1) | (gsel << 2) | ((cs & 63) << 4);
+  }
+  if ((int)threadIdx.x <= nent) s_start[threadIdx.x] = dev::G(t.start)[threadIdx.x];
+  __syncthreads();
+  if (!valid) return;
+  int ci[3];
+  cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
+  const int nd = d.n[ds];
+  const int fb = 2 * ci[ds];
+  const auto wm = dev::G(d.wm), wp = dev::G(d.wp);
+  double rho[3];
+  bool row_ok[3];
+  {
+    int g[3] = {ci[0], ci[1], ci[2]};
+    row_ok[0] = fb - 1 >= 0;
+    row_ok[1] = true;
+    row_ok[2] = fb + 1 <= nd - 1;
+    g[ds] = ci[ds] - 1;
+    rho[0] = row_ok[0] ? wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
+    rho[1] = 1.0;
+    g[ds] = ci[ds];
+    rho[2] = row_ok[2] ? wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
+  }
+  // Per-thread bases; every row then adds block-uniform offsets: the fine row
+  // f = 2I + r is f0 + r*stride(d*), the neighbour g = f + s is in the box when
+  // each coordinate is, and an odd g's F-box cell is h0 plus the offsets of s
+  // (with (r + s_d* - 1)/2 along d*).
+  int fc[3] = {ci[0], ci[1], ci[2]};
+  fc[ds] = fb;
+  const long long f0 = fc[0] + (long long)d.n[0] * (fc[1] + (long long)d.n[1] * fc[2]);
+  const long long h0 = ci[0] + (long long)d.fn[0] * (ci[1] + (long long)d.fn[1] * ci[2]);
+  double acc = 0.0;
+  int e = 0;
+  int next = s_start[1];
+  for (int qb = 0; qb < ntab; qb += kRapBatch) {
+    double av[kRapBatch], wv[kRapBatch], rv[kRapBatch];
+#pragma unroll
+    for (int u = 0; u < kRapBatch; ++u) {
+      const int q = qb + u;
+      av[u] = 0.0;
+      wv[u] = 1.0;
+      rv[u] = 0.0;
+      if (q >= ntab) continue;                       // block-uniform
+      const int w = s_w[q];
+      const int r = (w & 3) - 1, gsel = (w >> 2) & 3, cs = w >> 4;
+      bool in = row_ok[r + 1] && (unsigned)(fb + r + off_comp(cs, ds)) < (unsigned)nd;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (a != ds) in = in && (unsigned)(ci[a] + off_comp(cs, a)) < (unsigned)d.n[a];
+      if (!in) continue;
+      av[u] = coef[s_cof[q] + f0];
+      rv[u] = rho[r + 1];
+      if (gsel != 0) wv[u] = gsel == 1 ? wm[h0 + s_dh[q]] : wp[h0 + s_dh[q]];
+    }
+#pragma unroll
+    for (int u = 0; u < kRapBatch; ++u) {
+      const int q = qb + u;
+      if (q >= ntab) break;                          // block-uniform
+      while (q == next) {                            // entry e complete (block-uniform)
+        out[(long long)e * d.cncell + cidx] = acc;
+        if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)acc;
+        acc = 0.0;
+        ++e;
+        next = s_start[e + 1];
+      }
+      acc = fma(rv[u] * av[u], wv[u], acc);
+    }
+  }
+  for (; e < nent; ++e) {                            // the last entry, and any empty ones after it
+    out[(long long)e * d.cncell + cidx] = acc;
+    if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)acc;
+    acc = 0.0;
+  }
 }
 
 // Direct coarsest solve (Section 3.5 option): the coarsest operator A = S + U
@@ -333,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_l1_cells(const PartDesc<double> *__r
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.ncell) return;
   double acc = 0.0;
-  for (int s = 0; s < d.nent; ++s) acc += fabs(d.coef[(long long)s * d.ncell + c]);
+  for (int s = 0; s < d.nent; ++s) acc += fabs(dev::G(d.coef)[(long long)s * d.ncell + c]);
   l1[d.off + c] = acc;
 }
 
@@ -369,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_scale(const PartDesc<double> 
   const PartDesc<double> &d = desc[blockIdx.y];
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.ncell) return;
-  const double a = d.coef[(long long)d.center * d.ncell + c];
+  const double a = dev::G(d.coef)[(long long)d.center * d.ncell + c];
   const double v = d.omega / a;
   if (!(a > 0.0) || !isfinite(v)) flag[0] = 1;
   rs[d.off + c] = v;
@@ -415,9 +541,13 @@ void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, in
 
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
                 int maxent_c, hipStream_t st) {
-  // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies
-  const unsigned nb = (nblk(maxcoarse) * (unsigned)maxent_c + 7u) & ~7u;
-  k_rap<<<dim3(nb, nparts), kBlock, 0, st>>>(desc, rd, maxent_c);
+  if ((int64_t)maxcoarse * nparts >= kRapCellMin) {
+    k_rap<<<dim3(nblk(maxcoarse), nparts), kBlock, 0, st>>>(desc, rd);
+  } else {
+    // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies
+    const unsigned nb = (nblk(maxcoarse) * (unsigned)maxent_c + 7u) & ~7u;
+    k_rap_entry<<<dim3(nb, nparts), kBlock, 0, st>>>(desc, rd, maxent_c);
+  }
 }
 
 void launch_direct_setup(const PartDesc<double> *desc, int np, int n, int nrow, const int *urow,

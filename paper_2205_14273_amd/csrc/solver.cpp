@@ -130,6 +130,8 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
     f.rap_code.insert(f.rap_code.end(), l.begin(), l.end());
     f.rap_start.push_back((int)f.rap_code.size());
   }
+  if (f.rap_code.size() > (size_t)kRapMaxTab)
+    throw Error(SSAMG_ERR_STATE, "internal: Galerkin table longer than kRapMaxTab");
 }
 
 template <typename T>

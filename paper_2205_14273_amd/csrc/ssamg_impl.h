@@ -50,6 +50,13 @@ constexpr int64_t kTailElems = 0;
 constexpr int64_t kSplitCells = 1 << 20;
 // largest coarsest level the direct solve accepts (its inverse is formed in LDS)
 constexpr int kDirectMax = 64;
+// rows of one part's Galerkin table, staged in LDS by the kernel (3 fine rows x
+// 27 entries x at most 2 weights = 162)
+constexpr int kRapMaxTab = 256;
+// coarse levels of at least this many cells (over all parts) take the
+// one-thread-per-coarse-cell Galerkin kernel; smaller ones one thread per
+// (coarse cell, entry), whose shorter gather chains win when threads are few
+constexpr int64_t kRapCellMin = 3 << 16;
 // the autotuner times a level's launch options only if the level holds at
 // least this many (cell, right-hand side) elements; below it launches are
 // latency-bound and the defaults stand
