@@ -63,16 +63,55 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const double *__restrict
   if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
 }
 
+// a.b and b.c in one pass over the three vectors (the same per-thread sums
+// and trees as two k_dot_partial launches, so the same values); the second
+// set of partials goes to partial + kRedBlocks * kMaxRhs
+__global__ __launch_bounds__(kBlock) void k_dot2_partial(const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const double *__restrict__ c, long long nel,
+                                                         int lg, double *__restrict__ partial) {
+  __shared__ double sh[kBlock], sh2[kBlock];
+  const int nr = 1 << lg;
+  double acc = 0.0, acc2 = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
+       i += (long long)gridDim.x * kBlock) {
+    const double bi = b[i];
+    acc = fma(a[i], bi, acc);
+    acc2 = fma(bi, c[i], acc2);
+  }
+  sh[threadIdx.x] = acc;
+  sh2[threadIdx.x] = acc2;
+  for (int s = kBlock / 2; s >= nr; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) {
+      sh[threadIdx.x] += sh[threadIdx.x + s];
+      sh2[threadIdx.x] += sh2[threadIdx.x + s];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+    partial[(kRedBlocks + blockIdx.x) * kMaxRhs + threadIdx.x] = sh2[threadIdx.x];
+  }
+}
+
 // slot <- sum of partials; shift_rz: first move S_RZN to S_RZ (PCG bookkeeping).
 // kFinalThreads threads; each adds a fixed strided set of partials of its
 // right-hand side with four independent accumulators (loads in flight), then
 // a fixed LDS tree.
 constexpr int kFinalThreads = 1024;
 
+// Block b of the grid reduces the partials at partial + b * kRedBlocks * kMaxRhs
+// into slot + b * (slot2 - slot): one launch finishes one or two dot products.
 __global__ __launch_bounds__(kFinalThreads) void k_dot_final(const double *__restrict__ partial, int nblk,
                                                              int lg, double *__restrict__ scal, int slot,
-                                                             int shift_rz) {
+                                                             int shift_rz, int slot2) {
   __shared__ double sh[kFinalThreads];
+  if (blockIdx.x == 1) {
+    partial += (size_t)kRedBlocks * kMaxRhs;
+    slot = slot2;
+    shift_rz = 0;
+  }
   const int nr = 1 << lg;
   const int kr = threadIdx.x & (nr - 1);
   const int step = kFinalThreads >> lg;
@@ -192,7 +231,14 @@ void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *p
                 int slot, int shift_rz, hipStream_t st) {
   const unsigned nb = red_blocks(nel);
   k_dot_partial<<<nb, kBlock, 0, st>>>(a, b, nel, lg, partial);
-  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, shift_rz);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, shift_rz, slot);
+}
+
+void launch_dot2(const double *a, const double *b, const double *c, int64_t nel, int lg, double *partial,
+                 double *scal, int slot_ab, int shift_rz, int slot_bc, hipStream_t st) {
+  const unsigned nb = red_blocks(nel);
+  k_dot2_partial<<<nb, kBlock, 0, st>>>(a, b, c, nel, lg, partial);
+  k_dot_final<<<2, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot_ab, shift_rz, slot_bc);
 }
 
 void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
@@ -200,7 +246,7 @@ void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, d
                    hipStream_t st) {
   const unsigned nb = red_blocks(nel);
   k_pcg_xr<<<nb, kBlock, 0, st>>>(nel, lg, scal, active, x, r, p, q, partial);
-  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal_out, S_RR, 0);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal_out, S_RR, 0, S_RR);
 }
 
 void launch_pcg_p(int64_t nel, int lg, const double *scal, const int *active, int flexible,
@@ -212,7 +258,7 @@ void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, d
                        double *scal, int slot, hipStream_t st) {
   const unsigned nb = red_blocks(nel);
   k_resid_partial<<<nb, kBlock, 0, st>>>(b, ax, nel, lg, partial);
-  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, 0);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, 0, slot);
 }
 
 }  // namespace ssamg

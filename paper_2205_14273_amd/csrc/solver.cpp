@@ -605,7 +605,7 @@ void carve(Solver &s, Carver &cv) {
   s.z = cv.take<double>((size_t)N0 * nr);
   s.p = cv.take<double>((size_t)N0 * nr);
   s.q = cv.take<double>((size_t)N0 * nr);
-  s.partial = cv.take<double>((size_t)kRedBlocks * kMaxRhs);
+  s.partial = cv.take<double>((size_t)2 * kRedBlocks * kMaxRhs);
   s.scal = cv.take<double>((size_t)kScalSlots * kMaxRhs);
   s.active = cv.take<int>(kMaxRhs);
   s.flag = cv.take<int>(1);
@@ -1247,8 +1247,10 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
       SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
     if (nact == 0 || it == s.prm.max_iter) break;
     precond(s, lg);
-    launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 1, st);
-    if (flexible) launch_dot(s.z, s.q, nel, lg, s.partial, s.scal, S_ZQ, 0, st);
+    if (flexible)
+      launch_dot2(s.r, s.z, s.q, nel, lg, s.partial, s.scal, S_RZN, 1, S_ZQ, st);
+    else
+      launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 1, st);
     launch_pcg_p(nel, lg, s.scal, s.active, flexible ? 1 : 0, s.z, s.p, st);
   }
   // true residual

@@ -264,7 +264,7 @@ struct Solver {
   bool ws_owned = false;
   // PCG vectors (FP64, [N0][max_nrhs])
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  double *partial = nullptr;         // [kRedBlocks][kMaxRhs]
+  double *partial = nullptr;         // [2][kRedBlocks][kMaxRhs]
   double *scal = nullptr;            // [kScalSlots][kMaxRhs]
   int *active = nullptr;             // [kMaxRhs]
   int *flag = nullptr;               // device error flag
@@ -388,6 +388,10 @@ void launch_fill(double *x, double v, int64_t n, hipStream_t st);
 void launch_copy(const double *in, double *out, int64_t n, hipStream_t st);
 void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *partial, double *scal,
                 int slot, int shift_rz, hipStream_t st);
+// a.b into slot_ab (shift_rz as launch_dot) and b.c into slot_bc in one pass;
+// partial holds 2 * kRedBlocks * kMaxRhs doubles
+void launch_dot2(const double *a, const double *b, const double *c, int64_t nel, int lg, double *partial,
+                 double *scal, int slot_ab, int shift_rz, int slot_bc, hipStream_t st);
 void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
                    const double *p, const double *q, double *partial, double *scal_out,
                    hipStream_t st);
