@@ -234,6 +234,10 @@ void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *p
   k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot, shift_rz, slot);
 }
 
+void launch_dot_final(const double *partial, int nblk, int lg, double *scal, int slot, hipStream_t st) {
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, nblk, lg, scal, slot, 0, slot);
+}
+
 void launch_dot2(const double *a, const double *b, const double *c, int64_t nel, int lg, double *partial,
                  double *scal, int slot_ab, int shift_rz, int slot_bc, hipStream_t st) {
   const unsigned nb = red_blocks(nel);

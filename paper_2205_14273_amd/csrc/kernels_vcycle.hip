@@ -253,6 +253,21 @@ __device__ __forceinline__ void interp_one(const PartDesc<T> &d, int c, int kr, 
   x[o] += v;
 }
 
+// Sum of v over the block's cells for each right-hand side (fixed tree over
+// the 256 threads, strides multiples of 1 << lg), written to out[0 .. 1 << lg).
+// Must be called by every thread of the block; sh: kBlock doubles of LDS.
+__device__ __forceinline__ void block_dot(double *sh, double v, int lg, double *out) {
+  const int nr = 1 << lg;
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  for (int s = kBlock / 2; s >= nr; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nr) out[threadIdx.x] = sh[threadIdx.x];
+}
+
 // y = S x + U x (APPLY), r = b - A x (RESID) or x' = x + w (b - A x) (JACOBI,
 // w the smoother factor) over every cell of every part.  T: coefficients and
 // x; TB: b; TO: output.  NENT bounds the entries of the level's stencils.
@@ -262,7 +277,8 @@ __device__ __forceinline__ void interp_one(const PartDesc<T> &d, int c, int kr, 
 template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
 __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restrict__ desc, int lg,
                                                     const T *__restrict__ x,
-                                                    const TB *__restrict__ b, TO *__restrict__ y) {
+                                                    const TB *__restrict__ b, TO *__restrict__ y,
+                                                    double *__restrict__ dotp) {
   constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
   __shared__ T prod[UCH];
   __shared__ T rsum[kBlock];
@@ -270,7 +286,16 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   const int chunk = chunk_index();
   const long long e = (long long)chunk * kBlock + threadIdx.x;
   const long long nel = d.ncell << lg;
-  if ((long long)chunk * kBlock >= nel) return;      // whole block past the part's end
+  // MODE_APPLY_DOT: this block's partial slot (blocks past the grid's last one
+  // up to the rounded slot count are covered by the last block, with zeros)
+  const long long slots = 4LL * ((gridDim.x + 3) / 4);
+  double *dslot = MODE == MODE_APPLY_DOT ? dotp + (((long long)blockIdx.y * slots + chunk) << lg) : nullptr;
+  if (MODE == MODE_APPLY_DOT && chunk == (int)gridDim.x - 1 && (int)threadIdx.x < ((int)(slots - gridDim.x) << lg))
+    dslot[(1 << lg) + threadIdx.x] = 0.0;
+  if ((long long)chunk * kBlock >= nel) {            // whole block past the part's end
+    if (MODE == MODE_APPLY_DOT && (int)threadIdx.x < (1 << lg)) dslot[threadIdx.x] = 0.0;
+    return;
+  }
   const bool valid = e < nel;
   const int c = valid ? (int)(e >> lg) : 0;
   const int kr = (int)(e & ((1 << lg) - 1));
@@ -279,6 +304,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   T acc = valid ? stencil_acc<T, NENT>(d, c, lg, xp) : T(0);
   acc += block_coupling<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
+  if (MODE == MODE_APPLY_DOT) {
+    if (valid) y[o] = (TO)acc;
+    block_dot((double *)rsum, valid ? (double)xp[0] * (double)acc : 0.0, lg, dslot);
+    return;
+  }
   if (!valid) return;
   if (MODE == MODE_APPLY) {
     y[o] = (TO)acc;
@@ -450,10 +480,33 @@ __device__ __forceinline__ void block_coupling4(const PartDesc<T> &d, int chunk,
   for (int q = 0; q < 4; ++q) out[q] = rsum[(tid << 2) + q];
 }
 
+// block_dot for a four-column block: its 1024 elements are the four 256-element
+// blocks of the one-column launch, each reduced with block_dot's tree and the
+// four sums then added in order, ((s0 + s1) + s2) + s3, as the final pass adds
+// the one-column launch's four slots of a group; so both layouts give the same
+// group sums.  sh: 4 kBlock doubles; out: the group slot.
+__device__ __forceinline__ void block_dot4(double *sh, const double v[4], int lg, double *out) {
+  const int nr = 1 << lg;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sh[4 * threadIdx.x + q] = v[q];
+  for (int s = kBlock / 2; s >= nr; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sh[j * kBlock + threadIdx.x] += sh[j * kBlock + threadIdx.x + s];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nr)
+    out[threadIdx.x] = ((sh[threadIdx.x] + sh[kBlock + threadIdx.x]) + sh[2 * kBlock + threadIdx.x]) +
+                       sh[3 * kBlock + threadIdx.x];
+}
+
 template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
 __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restrict__ desc, int lg,
                                                      const T *__restrict__ x,
-                                                     const TB *__restrict__ b, TO *__restrict__ y) {
+                                                     const TB *__restrict__ b, TO *__restrict__ y,
+                                                     double *__restrict__ dotp) {
   constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
   __shared__ T prod[UCH];
   __shared__ T rsum[4 * kBlock];
@@ -462,7 +515,12 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
   const int lgc = lg - 2;
   const long long e = (long long)chunk * kBlock + threadIdx.x;
   const long long nel = d.ncell << lgc;
-  if ((long long)chunk * kBlock >= nel) return;      // whole block past the part's end
+  // MODE_APPLY_DOT: the group slot of the four one-column slots this block covers
+  double *dslot = MODE == MODE_APPLY_DOT ? dotp + (((long long)blockIdx.y * gridDim.x + chunk) << lg) : nullptr;
+  if ((long long)chunk * kBlock >= nel) {            // whole block past the part's end
+    if (MODE == MODE_APPLY_DOT && (int)threadIdx.x < (1 << lg)) dslot[threadIdx.x] = 0.0;
+    return;
+  }
   const bool valid = e < nel;
   const int c = valid ? (int)(e >> lgc) : 0;
   const long long o = ((d.off + c) << lg) + 4 * (e & ((1 << lgc) - 1));
@@ -472,6 +530,21 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
   T cu[4];
   block_coupling4<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum, cu);
+  if (MODE == MODE_APPLY_DOT) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      T pv[4], out[4];
+      load4(xp, pv);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        out[q] = acc[q] + cu[q];
+        v[q] = (double)pv[q] * (double)out[q];
+      }
+      store4((T *)(y + o), out);
+    }
+    block_dot4((double *)rsum, v, lg, dslot);
+    return;
+  }
   if (!valid) return;
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] += cu[q];
@@ -789,6 +862,38 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
   }
 }
 
+// First pass of the fused product dot over the groups of four one-column slots
+// (per = 4: the one-column product's slots, added as ((s0 + s1) + s2) + s3;
+// per = 1: the four-column product's group sums).  Block g takes a fixed
+// range of groups; within it, lane u of right-hand side k takes every
+// (kBlock >> lg)-th group in order, then a fixed tree; out[g][k] with row
+// stride kMaxRhs (the layout k_dot_final reads).
+__global__ __launch_bounds__(kBlock) void k_dot_groups(const double *__restrict__ dotp, long long ngroups,
+                                                       int lg, int per, double *__restrict__ out) {
+  __shared__ double sh[kBlock];
+  const int nr = 1 << lg;
+  const int k = threadIdx.x & (nr - 1), u = threadIdx.x >> lg, nu = kBlock >> lg;
+  const long long gpb = (ngroups + gridDim.x - 1) / gridDim.x;
+  const long long g0 = (long long)blockIdx.x * gpb;
+  const long long g1 = g0 + gpb < ngroups ? g0 + gpb : ngroups;
+  double acc = 0.0;
+  for (long long g = g0 + u; g < g1; g += nu) {
+    if (per == 4) {
+      const double *q = dotp + ((4 * g) << lg) + k;
+      acc += ((q[0] + q[nr]) + q[2 * nr]) + q[3 * nr];
+    } else {
+      acc += dotp[(g << lg) + k];
+    }
+  }
+  sh[threadIdx.x] = acc;
+  for (int s = kBlock / 2; s >= nr; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nr) out[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+}
+
 // kernel<<<grid, kBlock>>>(args...) on st, timed by ev when ev.start is set
 template <typename K, typename... A>
 inline void dispatch(K kernel, dim3 grid, hipStream_t st, const LaunchEvents &ev, A... args) {
@@ -805,23 +910,27 @@ inline unsigned grid_cells(long long n, int lg) {
 
 template <typename T, typename TB, typename TO, int BIG, int NENT>
 void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T *x, const TB *b, TO *y,
-                  hipStream_t st, const LaunchEvents &ev, bool c4) {
+                  hipStream_t st, const LaunchEvents &ev, bool c4, double *dotp) {
   if (c4) {
     dim3 g4((grid.x + 3) / 4 > 0 ? (unsigned)(((long long)grid.x + 3) / 4) : 1u, grid.y);
     if (mode == MODE_APPLY)
-      dispatch(k_stencil4<T, MODE_APPLY, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
+      dispatch(k_stencil4<T, MODE_APPLY, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
     else if (mode == MODE_RESID)
-      dispatch(k_stencil4<T, MODE_RESID, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
-    else
-      dispatch(k_stencil4<T, MODE_JACOBI, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y);
+      dispatch(k_stencil4<T, MODE_RESID, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
+    else if (mode == MODE_JACOBI)
+      dispatch(k_stencil4<T, MODE_JACOBI, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
+    else if constexpr (sizeof(T) == 8 && sizeof(TO) == 8)
+      dispatch(k_stencil4<T, MODE_APPLY_DOT, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
     return;
   }
   if (mode == MODE_APPLY)
-    dispatch(k_stencil<T, MODE_APPLY, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
+    dispatch(k_stencil<T, MODE_APPLY, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
   else if (mode == MODE_RESID)
-    dispatch(k_stencil<T, MODE_RESID, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
-  else
-    dispatch(k_stencil<T, MODE_JACOBI, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y);
+    dispatch(k_stencil<T, MODE_RESID, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
+  else if (mode == MODE_JACOBI)
+    dispatch(k_stencil<T, MODE_JACOBI, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
+  else if constexpr (sizeof(T) == 8 && sizeof(TO) == 8)
+    dispatch(k_stencil<T, MODE_APPLY_DOT, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
 }
 
 }  // namespace
@@ -830,23 +939,26 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
-                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev, int cols4) {
+                    int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev, int cols4,
+                    double *dotp) {
+  if (mode == MODE_APPLY_DOT && !(sizeof(T) == 8 && sizeof(TO) == 8 && dotp))
+    throw Error(SSAMG_ERR_STATE, "internal: the fused product dot needs FP64 and a partial buffer");
   dim3 grid(grid_cells(maxcell, lg), nparts);
   const bool c4 = cols4 != 0 && stencil_cols4_ok<T>(lg, maxent);
   if (fine || (long long)maxcell * nparts >= kBigLevel) {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4);
+      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4);
+      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
     else
-      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4);
+      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
   } else {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4);
+      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4);
+      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
     else
-      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4);
+      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
   }
 }
 
@@ -901,6 +1013,10 @@ void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int npar
 #undef SSAMG_SR
 }
 
+void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, double *partial, hipStream_t st) {
+  k_dot_groups<<<kDotGroupBlocks, kBlock, 0, st>>>(dotp, ngroups, lg, per, partial);
+}
+
 template <typename T>
 void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
   constexpr int tt = sizeof(T) == 8 ? kTailThreads / 2 : kTailThreads;
@@ -909,13 +1025,13 @@ void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
 
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
                                                      int, const double *, const double *, double *,
-                                                     hipStream_t, LaunchEvents, int);
+                                                     hipStream_t, LaunchEvents, int, double *);
 template void launch_stencil<float, float, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int);
+                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int, double *);
 template void launch_stencil<float, double, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int);
+                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int, double *);
 template void launch_stencil<float, double, double>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int);
+                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int, double *);
 template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
                                                  const double *, double *, hipStream_t);
 template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,

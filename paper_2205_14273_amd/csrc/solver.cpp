@@ -606,6 +606,13 @@ void carve(Solver &s, Carver &cv) {
   s.p = cv.take<double>((size_t)N0 * nr);
   s.q = cv.take<double>((size_t)N0 * nr);
   s.partial = cv.take<double>((size_t)2 * kRedBlocks * kMaxRhs);
+  {
+    // p.q partials of the fused FP64 product, batched widths (4 or more)
+    int64_t slots = 0;
+    for (int lg = 2; (1 << lg) <= s.prm.max_nrhs; ++lg)
+      slots = std::max<int64_t>(slots, (int64_t)s.lv[0].parts.size() * dot_slots(s.lv[0].maxcell, lg) << lg);
+    s.dotp = slots > 0 ? cv.take<double>((size_t)slots) : nullptr;
+  }
   s.scal = cv.take<double>((size_t)kScalSlots * kMaxRhs);
   s.active = cv.take<int>(kMaxRhs);
   s.flag = cv.take<int>(1);
@@ -954,14 +961,25 @@ void precond(Solver &s, int lg) {
     precond_t<double>(s, lg);
 }
 
-void apply_A0(Solver &s, int lg, const double *x, double *y) {
+// y = A x on level 0 in FP64; with dot_slot >= 0 (batched widths only) the
+// product also forms x.y per right-hand side into that scalar slot
+void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) {
   Level &V = s.lv[0];
+  const int np = (int)V.parts.size();
   const TuneRec o = tune_rec(s, 0, lg);
   const int cols4 = s.prm.cycle_precision == SSAMG_FP32 ? o.cols4_mv : o.cols4;
+  const bool dot = dot_slot >= 0;
+  if (dot && (lg < 2 || !s.dotp)) throw Error(SSAMG_ERR_STATE, "internal: fused product dot needs a batch of 4+");
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
-    launch_stencil<double, double, double>(MODE_APPLY, 1, V.maxent, V.d_desc64, (int)V.parts.size(), V.maxcell,
-                                           lg, x, nullptr, y, s.stream, pr.e, cols4);
+    launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
+                                           V.maxcell, lg, x, nullptr, y, s.stream, pr.e, cols4,
+                                           dot ? s.dotp : nullptr);
+  }
+  if (dot) {
+    const bool c4 = cols4 != 0 && stencil_cols4_ok<double>(lg, V.maxent);
+    launch_dot_groups(s.dotp, (int64_t)np * dot_slots(V.maxcell, lg) / 4, lg, c4 ? 1 : 4, s.partial, s.stream);
+    launch_dot_final(s.partial, kDotGroupBlocks, lg, s.scal, dot_slot, s.stream);
   }
 }
 
@@ -1113,8 +1131,8 @@ int autotune_t(Solver &s, int lg) {
           }
         pick(cand, [&] {
           const TuneRec o = tune_rec(s, 0, lg);
-          launch_stencil<double, double, double>(MODE_APPLY, 1, V.maxent, V.d_desc64, np, V.maxcell, lg, s.p,
-                                                 nullptr, s.q, st, {}, o.cols4_mv);
+          launch_stencil<double, double, double>(MODE_APPLY_DOT, 1, V.maxent, V.d_desc64, np, V.maxcell, lg,
+                                                 s.p, nullptr, s.q, st, {}, o.cols4_mv, s.dotp);
         });
       }
       ++ntuned;
@@ -1223,8 +1241,12 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   }
   const double tol = s.prm.tol;
   for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
-    apply_A0(s, lg, s.p, s.q);
-    launch_dot(s.p, s.q, nel, lg, s.partial, s.scal, S_PQ, 0, st);
+    if (lg >= 2) {
+      apply_A0(s, lg, s.p, s.q, S_PQ);      // p.q formed by the product itself
+    } else {
+      apply_A0(s, lg, s.p, s.q);
+      launch_dot(s.p, s.q, nel, lg, s.partial, s.scal, S_PQ, 0, st);
+    }
     launch_pcg_xr(nel, lg, s.scal, s.active, x, s.r, s.p, s.q, s.partial, s.scal, st);
     SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
     SSAMG_HIP(hipStreamSynchronize(st));

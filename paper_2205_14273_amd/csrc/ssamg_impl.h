@@ -265,6 +265,7 @@ struct Solver {
   // PCG vectors (FP64, [N0][max_nrhs])
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *partial = nullptr;         // [2][kRedBlocks][kMaxRhs]
+  double *dotp = nullptr;            // p.q partials of the batched FP64 product (MODE_APPLY_DOT)
   double *scal = nullptr;            // [kScalSlots][kMaxRhs]
   int *active = nullptr;             // [kMaxRhs]
   int *flag = nullptr;               // device error flag
@@ -348,7 +349,20 @@ struct FvArgs {
   int code[kMaxEnt];   // stencil offsets, entry 0 = center
 };
 
-enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
+// MODE_APPLY_DOT (FP64 only): y = A x and the per-right-hand-side partial sums
+// of x.y: per block of 256 (cell, rhs) elements in the one-column kernel, per
+// group of four such blocks in the four-column kernel (see dot_slots)
+enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3 };
+
+// Partial slots of MODE_APPLY_DOT per part: the one-column grid's blocks of
+// 256 elements, rounded up to a multiple of 4, so that every group of four
+// slots is one block of the four-column kernel; slot (part * dot_slots +
+// block) holds 1 << lg sums (the four-column kernel fills the first quarter
+// of the buffer with one sum per group).
+inline int64_t dot_slots(int64_t maxcell, int lg) {
+  const int64_t nb = (((maxcell << lg) + kBlock - 1) / kBlock);
+  return 4 * ((nb + 3) / 4);
+}
 
 // Optional timing of one launch: when start is set the kernel is dispatched
 // with hipExtLaunchKernelGGL, which records the two events with the kernel's
@@ -368,7 +382,14 @@ inline bool stencil_cols4_ok(int lg, int maxent) {
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
                     int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {},
-                    int cols4 = -1);
+                    int cols4 = -1, double *dotp = nullptr);
+// First pass of the fused product dot: kDotGroupBlocks partial sums per
+// right-hand side into partial[b][k] (row stride kMaxRhs) from ngroups groups
+// of dotp (per = 4 one-column slots each, or per = 1 group sum); k_dot_final
+// (launch_dot_final) finishes it.
+constexpr int kDotGroupBlocks = 512;
+void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, double *partial, hipStream_t st);
+void launch_dot_final(const double *partial, int nblk, int lg, double *scal, int slot, hipStream_t st);
 template <typename T>
 void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st);
 template <typename T, typename TB>
