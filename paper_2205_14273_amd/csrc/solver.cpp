@@ -607,9 +607,9 @@ void carve(Solver &s, Carver &cv) {
   s.q = cv.take<double>((size_t)N0 * nr);
   s.partial = cv.take<double>((size_t)2 * kRedBlocks * kMaxRhs);
   {
-    // p.q partials of the fused FP64 product, batched widths (4 or more)
+    // p.q partials of the FP64 product of PCG (MODE_APPLY_DOT), widest case
     int64_t slots = 0;
-    for (int lg = 2; (1 << lg) <= s.prm.max_nrhs; ++lg)
+    for (int lg = 0; (1 << lg) <= s.prm.max_nrhs; ++lg)
       slots = std::max<int64_t>(slots, (int64_t)s.lv[0].parts.size() * dot_slots(s.lv[0].maxcell, lg) << lg);
     s.dotp = slots > 0 ? cv.take<double>((size_t)slots) : nullptr;
   }
@@ -961,15 +961,15 @@ void precond(Solver &s, int lg) {
     precond_t<double>(s, lg);
 }
 
-// y = A x on level 0 in FP64; with dot_slot >= 0 (batched widths only) the
-// product also forms x.y per right-hand side into that scalar slot
+// y = A x on level 0 in FP64; with dot_slot >= 0 the product also forms x.y
+// per right-hand side into that scalar slot (two small reduction launches)
 void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) {
   Level &V = s.lv[0];
   const int np = (int)V.parts.size();
   const TuneRec o = tune_rec(s, 0, lg);
   const int cols4 = s.prm.cycle_precision == SSAMG_FP32 ? o.cols4_mv : o.cols4;
   const bool dot = dot_slot >= 0;
-  if (dot && (lg < 2 || !s.dotp)) throw Error(SSAMG_ERR_STATE, "internal: fused product dot needs a batch of 4+");
+  if (dot && !s.dotp) throw Error(SSAMG_ERR_STATE, "internal: fused product dot needs a batch of 4+");
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
     launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
@@ -1241,12 +1241,7 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   }
   const double tol = s.prm.tol;
   for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
-    if (lg >= 2) {
-      apply_A0(s, lg, s.p, s.q, S_PQ);      // p.q formed by the product itself
-    } else {
-      apply_A0(s, lg, s.p, s.q);
-      launch_dot(s.p, s.q, nel, lg, s.partial, s.scal, S_PQ, 0, st);
-    }
+    apply_A0(s, lg, s.p, s.q, S_PQ);        // p.q formed by the product itself
     launch_pcg_xr(nel, lg, s.scal, s.active, x, s.r, s.p, s.q, s.partial, s.scal, st);
     SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
     SSAMG_HIP(hipStreamSynchronize(st));
