@@ -134,26 +134,25 @@ __global__ __launch_bounds__(kFinalThreads) void k_dot_final(const double *__res
   }
 }
 
-// x += alpha p, r -= alpha q with alpha = rz/pq per right-hand side (0 when
-// frozen), plus the partial sums of r.r
-__global__ __launch_bounds__(kBlock) void k_pcg_xr(long long nel, int lg,
-                                                   const double *__restrict__ scal,
-                                                   const int *__restrict__ active,
-                                                   double *__restrict__ x, double *__restrict__ r,
-                                                   const double *__restrict__ p,
-                                                   const double *__restrict__ q,
-                                                   double *__restrict__ partial) {
+// r -= alpha q with alpha = rz/pq per right-hand side (0 when frozen), plus
+// the partial sums of r.r; alpha is kept in S_ALPHA for the x update, which
+// waits for the next p update (k_pcg_xp) or the end of the solve (k_pcg_x), so
+// that p is read once per iteration
+__global__ __launch_bounds__(kBlock) void k_pcg_r(long long nel, int lg, double *__restrict__ scal,
+                                                  const int *__restrict__ active, double *__restrict__ r,
+                                                  const double *__restrict__ q,
+                                                  double *__restrict__ partial) {
   __shared__ double sh[kBlock];
   const int nr = 1 << lg;
   const int kr = threadIdx.x & (nr - 1);
   const bool act = active[kr] != 0;
   const double alpha = act ? scal[S_RZN * kMaxRhs + kr] / scal[S_PQ * kMaxRhs + kr] : 0.0;
+  if (blockIdx.x == 0 && (int)threadIdx.x < nr) scal[S_ALPHA * kMaxRhs + kr] = alpha;
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
        i += (long long)gridDim.x * kBlock) {
     double ri = r[i];
     if (act) {
-      x[i] = fma(alpha, p[i], x[i]);
       ri = fma(-alpha, q[i], ri);
       r[i] = ri;
     }
@@ -164,20 +163,37 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(long long nel, int lg,
   if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
 }
 
-// p = z + beta p; beta = rz_new/rz_old, or -(z.q)/(p.q) for flexible CG
-__global__ __launch_bounds__(kBlock) void k_pcg_p(long long nel, int lg,
-                                                  const double *__restrict__ scal,
-                                                  const int *__restrict__ active, int flexible,
-                                                  const double *__restrict__ z,
-                                                  double *__restrict__ p) {
+// x += alpha p (alpha of the last r update, 0 for a right-hand side that was
+// frozen then), then p = z + beta p; beta = rz_new/rz_old, or -(z.q)/(p.q) for
+// flexible CG, 0 for a frozen right-hand side
+__global__ __launch_bounds__(kBlock) void k_pcg_xp(long long nel, int lg,
+                                                   const double *__restrict__ scal,
+                                                   const int *__restrict__ active, int flexible,
+                                                   const double *__restrict__ z,
+                                                   double *__restrict__ p, double *__restrict__ x) {
   const int nr = 1 << lg;
   const int kr = threadIdx.x & (nr - 1);
+  const double alpha = scal[S_ALPHA * kMaxRhs + kr];
   double beta = flexible ? -scal[S_ZQ * kMaxRhs + kr] / scal[S_PQ * kMaxRhs + kr]
                          : scal[S_RZN * kMaxRhs + kr] / scal[S_RZ * kMaxRhs + kr];
   if (!active[kr]) beta = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
+       i += (long long)gridDim.x * kBlock) {
+    const double pi = p[i];
+    x[i] = fma(alpha, pi, x[i]);
+    p[i] = fma(beta, pi, z[i]);
+  }
+}
+
+// the last x += alpha p of a solve
+__global__ __launch_bounds__(kBlock) void k_pcg_x(long long nel, int lg, const double *__restrict__ scal,
+                                                  const double *__restrict__ p, double *__restrict__ x) {
+  const int nr = 1 << lg;
+  const int kr = threadIdx.x & (nr - 1);
+  const double alpha = scal[S_ALPHA * kMaxRhs + kr];
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nel;
        i += (long long)gridDim.x * kBlock)
-    p[i] = fma(beta, p[i], z[i]);
+    x[i] = fma(alpha, p[i], x[i]);
 }
 
 // partial sums of (b - Ax)^2
@@ -245,17 +261,20 @@ void launch_dot2(const double *a, const double *b, const double *c, int64_t nel,
   k_dot_final<<<2, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, slot_ab, shift_rz, slot_bc);
 }
 
-void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
-                   const double *p, const double *q, double *partial, double *scal_out,
-                   hipStream_t st) {
+void launch_pcg_r(int64_t nel, int lg, double *scal, const int *active, double *r, const double *q,
+                  double *partial, hipStream_t st) {
   const unsigned nb = red_blocks(nel);
-  k_pcg_xr<<<nb, kBlock, 0, st>>>(nel, lg, scal, active, x, r, p, q, partial);
-  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal_out, S_RR, 0, S_RR);
+  k_pcg_r<<<nb, kBlock, 0, st>>>(nel, lg, scal, active, r, q, partial);
+  k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, S_RR, 0, S_RR);
 }
 
-void launch_pcg_p(int64_t nel, int lg, const double *scal, const int *active, int flexible,
-                  const double *z, double *p, hipStream_t st) {
-  k_pcg_p<<<grid_stream(nel), kBlock, 0, st>>>(nel, lg, scal, active, flexible, z, p);
+void launch_pcg_xp(int64_t nel, int lg, const double *scal, const int *active, int flexible,
+                   const double *z, double *p, double *x, hipStream_t st) {
+  k_pcg_xp<<<grid_stream(nel), kBlock, 0, st>>>(nel, lg, scal, active, flexible, z, p, x);
+}
+
+void launch_pcg_x(int64_t nel, int lg, const double *scal, const double *p, double *x, hipStream_t st) {
+  k_pcg_x<<<grid_stream(nel), kBlock, 0, st>>>(nel, lg, scal, p, x);
 }
 
 void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, double *partial,

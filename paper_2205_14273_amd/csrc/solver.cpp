@@ -1240,9 +1240,11 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
     launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 0, st);
   }
   const double tol = s.prm.tol;
+  bool pending_x = false;            // x += alpha p of the last iteration not yet applied
   for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
     apply_A0(s, lg, s.p, s.q, S_PQ);        // p.q formed by the product itself
-    launch_pcg_xr(nel, lg, s.scal, s.active, x, s.r, s.p, s.q, s.partial, s.scal, st);
+    launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st);
+    pending_x = true;
     SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
     SSAMG_HIP(hipStreamSynchronize(st));
     bool changed = false;
@@ -1268,8 +1270,10 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
       launch_dot2(s.r, s.z, s.q, nel, lg, s.partial, s.scal, S_RZN, 1, S_ZQ, st);
     else
       launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 1, st);
-    launch_pcg_p(nel, lg, s.scal, s.active, flexible ? 1 : 0, s.z, s.p, st);
+    launch_pcg_xp(nel, lg, s.scal, s.active, flexible ? 1 : 0, s.z, s.p, x, st);
+    pending_x = false;
   }
+  if (pending_x) launch_pcg_x(nel, lg, s.scal, s.p, x, st);
   // true residual
   apply_A0(s, lg, x, s.q);
   launch_resid_norm(b, s.q, nel, lg, s.partial, s.scal, S_TR, st);

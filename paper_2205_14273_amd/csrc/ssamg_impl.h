@@ -302,7 +302,7 @@ int autotune(Solver &s, int lg);   // times candidates of every untuned level; r
 bool tuned(const Solver &s, int lg);
 std::string tune_key(const Solver &s, int l, int lg);
 
-enum ScalSlot { S_RZ = 0, S_RZN, S_PQ, S_RR, S_ZQ, S_BB, S_TR, kScalSlots };
+enum ScalSlot { S_RZ = 0, S_RZN, S_PQ, S_RR, S_ZQ, S_BB, S_TR, S_ALPHA, kScalSlots };
 
 // ------------------------------------------------------------------ launchers
 
@@ -413,11 +413,11 @@ void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *p
 // partial holds 2 * kRedBlocks * kMaxRhs doubles
 void launch_dot2(const double *a, const double *b, const double *c, int64_t nel, int lg, double *partial,
                  double *scal, int slot_ab, int shift_rz, int slot_bc, hipStream_t st);
-void launch_pcg_xr(int64_t nel, int lg, const double *scal, const int *active, double *x, double *r,
-                   const double *p, const double *q, double *partial, double *scal_out,
-                   hipStream_t st);
-void launch_pcg_p(int64_t nel, int lg, const double *scal, const int *active, int flexible,
-                  const double *z, double *p, hipStream_t st);
+void launch_pcg_r(int64_t nel, int lg, double *scal, const int *active, double *r, const double *q,
+                  double *partial, hipStream_t st);
+void launch_pcg_xp(int64_t nel, int lg, const double *scal, const int *active, int flexible,
+                   const double *z, double *p, double *x, hipStream_t st);
+void launch_pcg_x(int64_t nel, int lg, const double *scal, const double *p, double *x, hipStream_t st);
 void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, double *partial,
                        double *scal, int slot, hipStream_t st);
 
