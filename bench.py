@@ -37,12 +37,14 @@ DESCR = {
 # finest-level kernel kinds the library can time with HIP events, and the
 # kernel names rocprofv3 reports for them in a mixed-precision cycle
 PROBES = {
-    "matvec": (0, "k_stencil<double, 0, double, double, 1, {n}>"),
+    "matvec": (0, "k_stencil<double, 3, double, double, 1, {n}>"),      # product that also forms p.q
     "resid0": (2, "k_smooth_resid<float, double, 1, {n}>"),
     "restrict0": (3, "k_restrict<float>"),
     "interp0": (4, "k_interp_add<float>"),
     "jacobi0": (5, "k_stencil<float, 2, double, double, 1, {n}>"),
 }
+# batched solves: the post-sweep also forms r.z and z.q (mode 4)
+PROBES_BATCHED = {"jacobi0": "k_stencil<float, 4, double, double, 1, {n}>"}
 
 
 def log(*a):
@@ -203,6 +205,8 @@ def main():
     log("timed run: FP32 V-cycle inside FP64 PCG")
     probe_kind, probe_name = PROBES[args.probe]
     nent = 7 if case.stencil in (5, 7) else 27
+    if nrhs >= 4 and args.probe in PROBES_BATCHED:
+        probe_name = PROBES_BATCHED[args.probe]
     probe_name = probe_name.format(n=nent)
     if nrhs >= 4 and not (probe_name.startswith("k_stencil<double") and nent == 27):
         # four right-hand-side columns per thread on batched levels

@@ -254,6 +254,11 @@ void launch_dot_final(const double *partial, int nblk, int lg, double *scal, int
   k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, nblk, lg, scal, slot, 0, slot);
 }
 
+void launch_dot_final2(const double *partial, int nblk, int lg, double *scal, int slot_a, int shift_rz,
+                       int slot_b, int nset, hipStream_t st) {
+  k_dot_final<<<nset, kFinalThreads, 0, st>>>(partial, nblk, lg, scal, slot_a, shift_rz, slot_b);
+}
+
 void launch_dot2(const double *a, const double *b, const double *c, int64_t nel, int lg, double *partial,
                  double *scal, int slot_ab, int shift_rz, int slot_bc, hipStream_t st) {
   const unsigned nb = red_blocks(nel);

@@ -278,22 +278,27 @@ template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
 __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restrict__ desc, int lg,
                                                     const T *__restrict__ x,
                                                     const TB *__restrict__ b, TO *__restrict__ y,
-                                                    double *__restrict__ dotp) {
+                                                    double *__restrict__ dotp, const double *__restrict__ aux) {
   constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
+  constexpr bool DOT = MODE == MODE_APPLY_DOT || MODE == MODE_JACOBI_DOT;
   __shared__ T prod[UCH];
   __shared__ T rsum[kBlock];
   const PartDesc<T> &d = desc[blockIdx.y];
   const int chunk = chunk_index();
   const long long e = (long long)chunk * kBlock + threadIdx.x;
   const long long nel = d.ncell << lg;
-  // MODE_APPLY_DOT: this block's partial slot (blocks past the grid's last one
-  // up to the rounded slot count are covered by the last block, with zeros)
+  // DOT modes: this block's partial slot (blocks past the grid's last one up
+  // to the rounded slot count are covered by the last block, with zeros); the
+  // second set (z.q of MODE_JACOBI_DOT, when aux is given) follows the first
   const long long slots = 4LL * ((gridDim.x + 3) / 4);
-  double *dslot = MODE == MODE_APPLY_DOT ? dotp + (((long long)blockIdx.y * slots + chunk) << lg) : nullptr;
-  if (MODE == MODE_APPLY_DOT && chunk == (int)gridDim.x - 1 && (int)threadIdx.x < ((int)(slots - gridDim.x) << lg))
-    dslot[(1 << lg) + threadIdx.x] = 0.0;
+  double *dslot = DOT ? dotp + (((long long)blockIdx.y * slots + chunk) << lg) : nullptr;
+  const long long dset = ((long long)gridDim.y * slots) << lg;
+  const int nset = MODE == MODE_JACOBI_DOT && aux ? 2 : 1;
+  if (DOT && chunk == (int)gridDim.x - 1 && (int)threadIdx.x < ((int)(slots - gridDim.x) << lg))
+    for (int t = 0; t < nset; ++t) dslot[t * dset + (1 << lg) + threadIdx.x] = 0.0;
   if ((long long)chunk * kBlock >= nel) {            // whole block past the part's end
-    if (MODE == MODE_APPLY_DOT && (int)threadIdx.x < (1 << lg)) dslot[threadIdx.x] = 0.0;
+    if (DOT && (int)threadIdx.x < (1 << lg))
+      for (int t = 0; t < nset; ++t) dslot[t * dset + threadIdx.x] = 0.0;
     return;
   }
   const bool valid = e < nel;
@@ -304,9 +309,23 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   T acc = valid ? stencil_acc<T, NENT>(d, c, lg, xp) : T(0);
   acc += block_coupling<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
-  if (MODE == MODE_APPLY_DOT) {
+  if constexpr (MODE == MODE_APPLY_DOT) {
     if (valid) y[o] = (TO)acc;
     block_dot((double *)rsum, valid ? (double)xp[0] * (double)acc : 0.0, lg, dslot);
+    return;
+  }
+  if constexpr (MODE == MODE_JACOBI_DOT) {
+    // z = x + w (b - A x) with b = r, and the partial sums of r.z and z.q
+    __shared__ double dsh[kBlock];
+    double v = 0.0, w = 0.0;
+    if (valid) {
+      const TO z = (TO)(xp[0] + smooth_factor(d, c) * ((T)b[o] - acc));
+      y[o] = z;
+      v = (double)b[o] * (double)z;
+      if (aux) w = (double)z * aux[o];
+    }
+    block_dot(dsh, v, lg, dslot);
+    if (aux) block_dot(dsh, w, lg, dslot + dset);
     return;
   }
   if (!valid) return;
@@ -506,8 +525,9 @@ template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
 __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restrict__ desc, int lg,
                                                      const T *__restrict__ x,
                                                      const TB *__restrict__ b, TO *__restrict__ y,
-                                                     double *__restrict__ dotp) {
+                                                     double *__restrict__ dotp, const double *__restrict__ aux) {
   constexpr int UCH = BIG ? kUChunkBig : kUChunkSmall;
+  constexpr bool DOT = MODE == MODE_APPLY_DOT || MODE == MODE_JACOBI_DOT;
   __shared__ T prod[UCH];
   __shared__ T rsum[4 * kBlock];
   const PartDesc<T> &d = desc[blockIdx.y];
@@ -515,10 +535,14 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
   const int lgc = lg - 2;
   const long long e = (long long)chunk * kBlock + threadIdx.x;
   const long long nel = d.ncell << lgc;
-  // MODE_APPLY_DOT: the group slot of the four one-column slots this block covers
-  double *dslot = MODE == MODE_APPLY_DOT ? dotp + (((long long)blockIdx.y * gridDim.x + chunk) << lg) : nullptr;
+  // DOT modes: the group slot of the four one-column slots this block covers
+  // (second set after gridDim.y * gridDim.x groups)
+  double *dslot = DOT ? dotp + (((long long)blockIdx.y * gridDim.x + chunk) << lg) : nullptr;
+  const long long dset = ((long long)gridDim.y * gridDim.x) << lg;
+  const int nset = MODE == MODE_JACOBI_DOT && aux ? 2 : 1;
   if ((long long)chunk * kBlock >= nel) {            // whole block past the part's end
-    if (MODE == MODE_APPLY_DOT && (int)threadIdx.x < (1 << lg)) dslot[threadIdx.x] = 0.0;
+    if (DOT && (int)threadIdx.x < (1 << lg))
+      for (int t = 0; t < nset; ++t) dslot[t * dset + threadIdx.x] = 0.0;
     return;
   }
   const bool valid = e < nel;
@@ -530,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
   T cu[4];
   block_coupling4<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum, cu);
-  if (MODE == MODE_APPLY_DOT) {
+  if constexpr (MODE == MODE_APPLY_DOT) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
       T pv[4], out[4];
@@ -543,6 +567,35 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
       store4((T *)(y + o), out);
     }
     block_dot4((double *)rsum, v, lg, dslot);
+    return;
+  }
+  if constexpr (MODE == MODE_JACOBI_DOT) {
+    // z = x + w (b - A x) with b = r, and the partial sums of r.z and z.q
+    __shared__ double dsh[4 * kBlock];
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      TB bv[4];
+      T xv[4];
+      TO out[4];
+      load4(b + o, bv);
+      load4(xp, xv);
+      const T wf = smooth_factor(d, c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T a = acc[q] + cu[q];
+        out[q] = (TO)(xv[q] + wf * ((T)bv[q] - a));
+        v[q] = (double)bv[q] * (double)out[q];
+      }
+      store4(y + o, out);
+      if (aux) {
+        double qv[4];
+        load4(aux + o, qv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (double)out[q] * qv[q];
+      }
+    }
+    block_dot4(dsh, v, lg, dslot);
+    if (aux) block_dot4(dsh, w, lg, dslot + dset);
     return;
   }
   if (!valid) return;
@@ -871,6 +924,9 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
 __global__ __launch_bounds__(kBlock) void k_dot_groups(const double *__restrict__ dotp, long long ngroups,
                                                        int lg, int per, double *__restrict__ out) {
   __shared__ double sh[kBlock];
+  // blockIdx.y: the set (the second one follows the first in both buffers)
+  dotp += ((long long)blockIdx.y * ngroups * per) << lg;
+  out += (size_t)blockIdx.y * kRedBlocks * kMaxRhs;
   const int nr = 1 << lg;
   const int k = threadIdx.x & (nr - 1), u = threadIdx.x >> lg, nu = kBlock >> lg;
   const long long gpb = (ngroups + gridDim.x - 1) / gridDim.x;
@@ -910,27 +966,26 @@ inline unsigned grid_cells(long long n, int lg) {
 
 template <typename T, typename TB, typename TO, int BIG, int NENT>
 void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T *x, const TB *b, TO *y,
-                  hipStream_t st, const LaunchEvents &ev, bool c4, double *dotp) {
+                  hipStream_t st, const LaunchEvents &ev, bool c4, double *dotp, const double *aux) {
+  constexpr bool fp64_out = sizeof(TO) == 8 && sizeof(TB) == 8;
   if (c4) {
     dim3 g4((grid.x + 3) / 4 > 0 ? (unsigned)(((long long)grid.x + 3) / 4) : 1u, grid.y);
-    if (mode == MODE_APPLY)
-      dispatch(k_stencil4<T, MODE_APPLY, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
-    else if (mode == MODE_RESID)
-      dispatch(k_stencil4<T, MODE_RESID, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
-    else if (mode == MODE_JACOBI)
-      dispatch(k_stencil4<T, MODE_JACOBI, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
-    else if constexpr (sizeof(T) == 8 && sizeof(TO) == 8)
-      dispatch(k_stencil4<T, MODE_APPLY_DOT, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp);
+#define SSAMG_S4(M) dispatch(k_stencil4<T, M, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp, aux)
+    if (mode == MODE_APPLY) SSAMG_S4(MODE_APPLY);
+    else if (mode == MODE_RESID) SSAMG_S4(MODE_RESID);
+    else if (mode == MODE_JACOBI) SSAMG_S4(MODE_JACOBI);
+    else if constexpr (fp64_out && sizeof(T) == 8) { if (mode == MODE_APPLY_DOT) SSAMG_S4(MODE_APPLY_DOT); }
+    if constexpr (fp64_out && BIG) { if (mode == MODE_JACOBI_DOT) SSAMG_S4(MODE_JACOBI_DOT); }
+#undef SSAMG_S4
     return;
   }
-  if (mode == MODE_APPLY)
-    dispatch(k_stencil<T, MODE_APPLY, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
-  else if (mode == MODE_RESID)
-    dispatch(k_stencil<T, MODE_RESID, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
-  else if (mode == MODE_JACOBI)
-    dispatch(k_stencil<T, MODE_JACOBI, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
-  else if constexpr (sizeof(T) == 8 && sizeof(TO) == 8)
-    dispatch(k_stencil<T, MODE_APPLY_DOT, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp);
+#define SSAMG_S1(M) dispatch(k_stencil<T, M, TB, TO, BIG, NENT>, grid, st, ev, desc, lg, x, b, y, dotp, aux)
+  if (mode == MODE_APPLY) SSAMG_S1(MODE_APPLY);
+  else if (mode == MODE_RESID) SSAMG_S1(MODE_RESID);
+  else if (mode == MODE_JACOBI) SSAMG_S1(MODE_JACOBI);
+  else if constexpr (fp64_out && sizeof(T) == 8) { if (mode == MODE_APPLY_DOT) SSAMG_S1(MODE_APPLY_DOT); }
+  if constexpr (fp64_out && BIG) { if (mode == MODE_JACOBI_DOT) SSAMG_S1(MODE_JACOBI_DOT); }
+#undef SSAMG_S1
 }
 
 }  // namespace
@@ -940,25 +995,27 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
                     int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev, int cols4,
-                    double *dotp) {
+                    double *dotp, const double *aux) {
   if (mode == MODE_APPLY_DOT && !(sizeof(T) == 8 && sizeof(TO) == 8 && dotp))
     throw Error(SSAMG_ERR_STATE, "internal: the fused product dot needs FP64 and a partial buffer");
+  if (mode == MODE_JACOBI_DOT && !(sizeof(TB) == 8 && sizeof(TO) == 8 && fine && dotp))
+    throw Error(SSAMG_ERR_STATE, "internal: the fused sweep dots need the finest level and a partial buffer");
   dim3 grid(grid_cells(maxcell, lg), nparts);
   const bool c4 = cols4 != 0 && stencil_cols4_ok<T>(lg, maxent);
   if (fine || (long long)maxcell * nparts >= kBigLevel) {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
+      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
+      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
     else
-      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
+      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
   } else {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
+      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
+      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
     else
-      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp);
+      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
   }
 }
 
@@ -1013,8 +1070,9 @@ void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int npar
 #undef SSAMG_SR
 }
 
-void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, double *partial, hipStream_t st) {
-  k_dot_groups<<<kDotGroupBlocks, kBlock, 0, st>>>(dotp, ngroups, lg, per, partial);
+void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, int nset, double *partial,
+                       hipStream_t st) {
+  k_dot_groups<<<dim3(kDotGroupBlocks, nset), kBlock, 0, st>>>(dotp, ngroups, lg, per, partial);
 }
 
 template <typename T>
@@ -1025,13 +1083,13 @@ void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
 
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
                                                      int, const double *, const double *, double *,
-                                                     hipStream_t, LaunchEvents, int, double *);
+                                                     hipStream_t, LaunchEvents, int, double *, const double *);
 template void launch_stencil<float, float, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int, double *);
+                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int, double *, const double *);
 template void launch_stencil<float, double, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int, double *);
+                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int, double *, const double *);
 template void launch_stencil<float, double, double>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int, double *);
+                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int, double *, const double *);
 template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
                                                  const double *, double *, hipStream_t);
 template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,

@@ -607,11 +607,13 @@ void carve(Solver &s, Carver &cv) {
   s.q = cv.take<double>((size_t)N0 * nr);
   s.partial = cv.take<double>((size_t)2 * kRedBlocks * kMaxRhs);
   {
-    // p.q partials of the FP64 product of PCG (MODE_APPLY_DOT), widest case
+    // partial sums of the dot products formed by level-0 kernels (p.q by the
+    // FP64 product; r.z and z.q by the last sweep of a batched cycle): two
+    // sets, widest case
     int64_t slots = 0;
     for (int lg = 0; (1 << lg) <= s.prm.max_nrhs; ++lg)
       slots = std::max<int64_t>(slots, (int64_t)s.lv[0].parts.size() * dot_slots(s.lv[0].maxcell, lg) << lg);
-    s.dotp = slots > 0 ? cv.take<double>((size_t)slots) : nullptr;
+    s.dotp = slots > 0 ? cv.take<double>((size_t)2 * slots) : nullptr;
   }
   s.scal = cv.take<double>((size_t)kScalSlots * kMaxRhs);
   s.active = cv.take<int>(kMaxRhs);
@@ -908,8 +910,10 @@ void tail(Solver &s, int lg) {
 // z = B r: one V(1,1) cycle from s.r into s.z.  Level 0 is launched directly
 // (large kernels; in a mixed-precision cycle they read r and write z in FP64),
 // the coarser levels as one graph.
+// With dots (batched widths), the last sweep also forms r.z into S_RZN (after
+// moving the old value to S_RZ) and, for flexible CG, z.q into S_ZQ.
 template <typename T>
-void precond_t(Solver &s, int lg) {
+void precond_t(Solver &s, int lg, bool dots) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
   const int np = (int)s.lv[0].parts.size();
@@ -947,18 +951,27 @@ void precond_t(Solver &s, int lg) {
     Probe pr(s, SSAMG_PROBE_INTERP0, level0_bytes(s, SSAMG_PROBE_INTERP0, lg, tc, tx, tx, tx));
     launch_interp_add<T>(d, np, V.maxcell, lg, (const T *)s.lv[1].vt, x, st, pr.e);
   }
+  const bool flexible = s.prm.cycle_precision == SSAMG_FP32;
   {
-    Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, 8, 8));
-    launch_stencil<T, double, double>(MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x, s.r, s.z, st,
-                                      pr.e, o.cols4);
+    // with dots the sweep also reads q (flexible CG)
+    Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, dots && flexible ? 16 : 8, 8));
+    launch_stencil<T, double, double>(dots ? MODE_JACOBI_DOT : MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x,
+                                      s.r, s.z, st, pr.e, o.cols4, dots ? s.dotp : nullptr,
+                                      dots && flexible ? s.q : nullptr);
+  }
+  if (dots) {
+    const bool c4 = o.cols4 != 0 && stencil_cols4_ok<T>(lg, V.maxent);
+    const int nset = flexible ? 2 : 1;
+    launch_dot_groups(s.dotp, (int64_t)np * dot_slots(V.maxcell, lg) / 4, lg, c4 ? 1 : 4, nset, s.partial, st);
+    launch_dot_final2(s.partial, kDotGroupBlocks, lg, s.scal, S_RZN, 1, S_ZQ, nset, st);
   }
 }
 
-void precond(Solver &s, int lg) {
+void precond(Solver &s, int lg, bool dots = false) {
   if (s.prm.cycle_precision == SSAMG_FP32)
-    precond_t<float>(s, lg);
+    precond_t<float>(s, lg, dots);
   else
-    precond_t<double>(s, lg);
+    precond_t<double>(s, lg, dots);
 }
 
 // y = A x on level 0 in FP64; with dot_slot >= 0 the product also forms x.y
@@ -978,7 +991,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
   }
   if (dot) {
     const bool c4 = cols4 != 0 && stencil_cols4_ok<double>(lg, V.maxent);
-    launch_dot_groups(s.dotp, (int64_t)np * dot_slots(V.maxcell, lg) / 4, lg, c4 ? 1 : 4, s.partial, s.stream);
+    launch_dot_groups(s.dotp, (int64_t)np * dot_slots(V.maxcell, lg) / 4, lg, c4 ? 1 : 4, 1, s.partial, s.stream);
     launch_dot_final(s.partial, kDotGroupBlocks, lg, s.scal, dot_slot, s.stream);
   }
 }
@@ -1265,11 +1278,15 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
     if (changed)
       SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
     if (nact == 0 || it == s.prm.max_iter) break;
-    precond(s, lg);
-    if (flexible)
-      launch_dot2(s.r, s.z, s.q, nel, lg, s.partial, s.scal, S_RZN, 1, S_ZQ, st);
-    else
-      launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 1, st);
+    if (lg >= 2 && s.lv.size() > 1) {
+      precond(s, lg, true);                 // r.z (and z.q) formed by the last sweep
+    } else {
+      precond(s, lg);
+      if (flexible)
+        launch_dot2(s.r, s.z, s.q, nel, lg, s.partial, s.scal, S_RZN, 1, S_ZQ, st);
+      else
+        launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 1, st);
+    }
     launch_pcg_xp(nel, lg, s.scal, s.active, flexible ? 1 : 0, s.z, s.p, x, st);
     pending_x = false;
   }

@@ -352,7 +352,9 @@ struct FvArgs {
 // MODE_APPLY_DOT (FP64 only): y = A x and the per-right-hand-side partial sums
 // of x.y: per block of 256 (cell, rhs) elements in the one-column kernel, per
 // group of four such blocks in the four-column kernel (see dot_slots)
-enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3 };
+// MODE_JACOBI_DOT (finest level, FP64 b = r and output z): the sweep and the
+// partial sums of r.z (first set) and, when aux = q is given, z.q (second set)
+enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3, MODE_JACOBI_DOT = 4 };
 
 // Partial slots of MODE_APPLY_DOT per part: the one-column grid's blocks of
 // 256 elements, rounded up to a multiple of 4, so that every group of four
@@ -382,14 +384,19 @@ inline bool stencil_cols4_ok(int lg, int maxent) {
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
                     int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {},
-                    int cols4 = -1, double *dotp = nullptr);
+                    int cols4 = -1, double *dotp = nullptr, const double *aux = nullptr);
 // First pass of the fused product dot: kDotGroupBlocks partial sums per
 // right-hand side into partial[b][k] (row stride kMaxRhs) from ngroups groups
 // of dotp (per = 4 one-column slots each, or per = 1 group sum); k_dot_final
 // (launch_dot_final) finishes it.
 constexpr int kDotGroupBlocks = 512;
-void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, double *partial, hipStream_t st);
+void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, int nset, double *partial,
+                       hipStream_t st);
 void launch_dot_final(const double *partial, int nblk, int lg, double *scal, int slot, hipStream_t st);
+// the first set into slot_a (with the S_RZN -> S_RZ shift when shift_rz) and,
+// with nset = 2, the second into slot_b
+void launch_dot_final2(const double *partial, int nblk, int lg, double *scal, int slot_a, int shift_rz,
+                       int slot_b, int nset, hipStream_t st);
 template <typename T>
 void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st);
 template <typename T, typename TB>
