@@ -164,9 +164,11 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
       const int q = tid + t * kBlock;
-      const bool in = q < np;
-      cc[t] = in ? gload(d.ucol + ec + (q >> lg)) : 0;
-      vv[t] = in ? gload(d.uval + ec + (q >> lg)) : T(0);
+      // unconditional loads (a slot past the chunk reads its first entry and is
+      // masked below), so that every entry load of the chunk is in flight at once
+      const int qe = ec + (q < np ? (q >> lg) : 0);
+      cc[t] = gload(d.ucol + qe);
+      vv[t] = gload(d.uval + qe);
     }
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
@@ -466,9 +468,11 @@ __device__ __forceinline__ void block_coupling4(const PartDesc<T> &d, int chunk,
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
       const int q = tid + t * kBlock;
-      const bool in = q < np;
-      cc[t] = in ? gload(d.ucol + ec + (q >> lg)) : 0;
-      vv[t] = in ? gload(d.uval + ec + (q >> lg)) : T(0);
+      // unconditional loads (a slot past the chunk reads its first entry and is
+      // masked below), so that every entry load of the chunk is in flight at once
+      const int qe = ec + (q < np ? (q >> lg) : 0);
+      cc[t] = gload(d.ucol + qe);
+      vv[t] = gload(d.uval + qe);
     }
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
@@ -809,8 +813,9 @@ __device__ void tail_coupling(const TailLevel<T> &v, int lg, XS xs, T *__restric
 #pragma unroll
     for (int t = 0; t < kTailU / TT; ++t) {
       const int q = tid + t * TT;
-      cc[t] = q < np ? v.ucol[ec + (q >> lg)] : 0;
-      vv[t] = q < np ? v.uval[ec + (q >> lg)] : T(0);
+      const int qe = ec + (q < np ? (q >> lg) : 0);   // unconditional (masked below)
+      cc[t] = gload(v.ucol + qe);
+      vv[t] = gload(v.uval + qe);
     }
 #pragma unroll
     for (int t = 0; t < kTailU / TT; ++t) {
