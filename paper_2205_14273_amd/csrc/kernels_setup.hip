@@ -453,13 +453,22 @@ __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int 
 
 // Weighted L1-Jacobi (Section 3.4): M_ii = sum_j |a_ij| over the whole row
 // of A = S + U; the smoother factor of cell i is factor / M_ii.
+// desc32 (finest level of a mixed-precision cycle, else null): the pass also
+// writes the FP32 copy of the coefficients it reads.
 __global__ __launch_bounds__(kBlock) void k_l1_cells(const PartDesc<double> *__restrict__ desc,
+                                                     const PartDesc<float> *__restrict__ desc32,
                                                      double *__restrict__ l1) {
   const PartDesc<double> &d = desc[blockIdx.y];
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.ncell) return;
+  const auto cf = dev::G(d.coef);
+  const auto c32 = desc32 ? dev::Gw(const_cast<float *>(desc32[blockIdx.y].coef)) : nullptr;
   double acc = 0.0;
-  for (int s = 0; s < d.nent; ++s) acc += fabs(dev::G(d.coef)[(long long)s * d.ncell + c]);
+  for (int s = 0; s < d.nent; ++s) {
+    const double v = cf[(long long)s * d.ncell + c];
+    acc += fabs(v);
+    if (desc32) c32[(long long)s * d.ncell + c] = (float)v;
+  }
   l1[d.off + c] = acc;
 }
 
@@ -529,9 +538,10 @@ void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *
 
 void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
                            int nrow, const int *urow, const int *uptr, const double *uval,
-                           double factor, double *rs, float *rs32, int *flag, hipStream_t st) {
+                           double factor, double *rs, float *rs32, int *flag, hipStream_t st,
+                           const PartDesc<float> *cast32) {
   if (l1) {
-    k_l1_cells<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, rs);
+    k_l1_cells<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, cast32, rs);
     if (nrow > 0) k_l1_urows<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, uval, rs);
     k_l1_finish<<<nblk(n), kBlock, 0, st>>>(n, factor, rs, rs32, flag);
   } else {

@@ -731,19 +731,21 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   SSAMG_HIP(hipMemsetAsync(s.flag, 0, sizeof(int), st));
   const auto t1 = std::chrono::steady_clock::now();
   // finest-level FP32 copies; coarser ones are written by the kernels below
-  if (mixed && L > 1) {
-    Level &V = s.lv[0];
-    for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
-    launch_cast_d2f(V.d_uval64, V.d_uval32, V.nnz, st);
-  }
   // per-cell smoother factors: omega_p / a_ii, or factor / sum_j |a_ij|
   const bool l1 = s.prm.relax == SSAMG_RELAX_L1_JACOBI;
+  if (mixed && L > 1) {
+    Level &V = s.lv[0];
+    if (!l1)   // with L1-Jacobi the factor pass writes them as it reads the coefficients
+      for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
+    launch_cast_d2f(V.d_uval64, V.d_uval32, V.nnz, st);
+  }
   const double l1_factor = s.prm.omega > 0.0 ? s.prm.omega : 1.5;
   auto smoother_scale = [&](int l) {
     Level &V = s.lv[l];
     float *rs32 = mixed && l < L - 1 ? V.d_rs32 : nullptr;
     launch_smoother_scale(l1, V.d_desc64, (int)V.parts.size(), V.maxcell, V.N, V.nrow, V.d_urow,
-                          V.d_uptr, V.d_uval64, l1_factor, V.d_rs64, rs32, s.flag, st);
+                          V.d_uptr, V.d_uval64, l1_factor, V.d_rs64, rs32, s.flag, st,
+                          l == 0 && mixed && L > 1 ? V.d_desc32 : nullptr);
     // skipped parts: factor 0, so neither sweep changes their cells
     for (auto &q : V.parts) {
       if (!q.skip) continue;

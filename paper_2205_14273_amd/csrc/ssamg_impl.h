@@ -436,9 +436,12 @@ void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *
                            int maxf, int *flag, hipStream_t st);
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
                 int maxent_c, hipStream_t st);
+// weighted L1-Jacobi: cast32 (finest level, mixed precision) also receives
+// the FP32 copy of the coefficients the pass reads
 void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
                            int nrow, const int *urow, const int *uptr, const double *uval,
-                           double factor, double *rs, float *rs32, int *flag, hipStream_t st);
+                           double factor, double *rs, float *rs32, int *flag, hipStream_t st,
+                           const PartDesc<float> *cast32 = nullptr);
 template <typename T, typename TB>
 void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
                          const TB *b, T *x, T *r, hipStream_t st, LaunchEvents ev = {});
