@@ -157,6 +157,17 @@ typedef struct {
   int autotune;              /* 1: the first solve of each batch width >= 4 times the
                                 launch options of its larger levels and keeps the
                                 fastest (ssamg_autotune); 0: defaults (default 0) */
+  int symmetric;             /* 1 (default): A is symmetric, as conjugate gradients
+                                requires, so within each part a_s(c) = a_{-s}(c+s);
+                                the FP64 product of PCG (and ssamg_apply_A) on
+                                stencils of more than 7 points reads the center and
+                                the entries of positive offset (last nonzero
+                                component of (dx, dy, dz) positive) and takes every
+                                other entry from the neighbour's mirrored one,
+                                halving its coefficient traffic (parts whose
+                                pattern lacks a mirror read every entry).  The
+                                V-cycle always reads every entry.  0: the product
+                                reads every entry too */
 } ssamg_params;
 
 typedef struct {

@@ -46,7 +46,8 @@ class ssamg_params(C.Structure):
     _fields_ = [("max_levels", C.c_int), ("min_coarse_size", C.c_int64), ("relax", C.c_int),
                 ("omega", C.c_double), ("coarse", C.c_int), ("cycle_precision", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
-                ("use_graph", C.c_int), ("skip", C.c_int), ("autotune", C.c_int)]
+                ("use_graph", C.c_int), ("skip", C.c_int), ("autotune", C.c_int),
+                ("symmetric", C.c_int)]
 
 
 class ssamg_info(C.Structure):

@@ -115,6 +115,7 @@ ssamg_status ssamg_params_default(ssamg_params *p) {
   p->use_graph = 1;
   p->skip = 0;
   p->autotune = 0;
+  p->symmetric = 1;
   API_END
 }
 
@@ -135,6 +136,7 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
     throw Error(SSAMG_ERR_ARG, "coarse must be SSAMG_COARSE_SWEEP or SSAMG_COARSE_DIRECT");
   if (p.skip != 0 && p.skip != 1) throw Error(SSAMG_ERR_ARG, "skip must be 0 or 1");
   if (p.autotune != 0 && p.autotune != 1) throw Error(SSAMG_ERR_ARG, "autotune must be 0 or 1");
+  if (p.symmetric != 0 && p.symmetric != 1) throw Error(SSAMG_ERR_ARG, "symmetric must be 0 or 1");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
     throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
   if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw Error(SSAMG_ERR_ARG, "tol must be positive");

@@ -39,7 +39,8 @@ __device__ __forceinline__ T smooth_factor(const PartDesc<T> &d, long long c) {
 
 // sum_s a_s(c) x(c + s) over the part's stencil; all loads are issued before
 // the first multiply (entries s >= nent are masked off)
-template <typename T, int NENT>
+// MIR: coefficients read through the mirror tables (PartDesc::mir)
+template <typename T, int NENT, bool MIR = false>
 __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, const T *xp) {
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
@@ -49,8 +50,14 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
 #pragma unroll
   for (int s = 0; s < NENT; ++s) {
     const bool act = s < d.nent;
-    a[s] = act ? cf[(long long)s * d.ncell] : T(0);
-    xv[s] = (act && nb_ok(mx, my, mz, d.code[s])) ? xp[(long long)d.lin[s] << lg] : T(0);
+    if constexpr (MIR) {
+      const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
+      a[s] = act ? cf[(long long)d.mir[s] * d.ncell + (ok ? d.mlin[s] : 0)] : T(0);
+      xv[s] = ok ? xp[(long long)d.lin[s] << lg] : T(0);
+    } else {
+      a[s] = act ? cf[(long long)s * d.ncell] : T(0);
+      xv[s] = (act && nb_ok(mx, my, mz, d.code[s])) ? xp[(long long)d.lin[s] << lg] : T(0);
+    }
   }
   T acc = T(0);
 #pragma unroll
@@ -276,7 +283,7 @@ __device__ __forceinline__ void block_dot(double *sh, double v, int lg, double *
 // BIG marks launches on large levels (the finest level always; there, in a
 // mixed-precision cycle, they read the FP64 residual and write the FP64
 // correction directly); it sets the LDS chunk of the coupling products.
-template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
+template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT, bool MIR = false>
 __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restrict__ desc, int lg,
                                                     const T *__restrict__ x,
                                                     const TB *__restrict__ b, TO *__restrict__ y,
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   const int kr = (int)(e & ((1 << lg) - 1));
   const long long o = ((d.off + c) << lg) + kr;
   const T *xp = x + o;
-  T acc = valid ? stencil_acc<T, NENT>(d, c, lg, xp) : T(0);
+  T acc = valid ? stencil_acc<T, NENT, MIR>(d, c, lg, xp) : T(0);
   acc += block_coupling<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
   if constexpr (MODE == MODE_APPLY_DOT) {
@@ -406,7 +413,7 @@ __device__ __forceinline__ void store4(double *p, const double v[4]) {
 // load is issued unconditionally (an absent entry reads entry 0, an absent
 // neighbour the cell itself) and the value is zeroed afterwards, so all loads
 // of the stencil are in flight together.
-template <typename T, int NENT>
+template <typename T, int NENT, bool MIR = false>
 __device__ __forceinline__ void stencil_acc4(const PartDesc<T> &d, int c, int lg, const T *xp, T acc[4]) {
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
@@ -418,7 +425,10 @@ __device__ __forceinline__ void stencil_acc4(const PartDesc<T> &d, int c, int lg
   for (int s = 0; s < NENT; ++s) {
     act[s] = s < d.nent;
     ok[s] = act[s] && nb_ok(mx, my, mz, d.code[s]);
-    a[s] = gload(cf + (act[s] ? (long long)s * d.ncell : 0LL));
+    if constexpr (MIR)
+      a[s] = gload(cf + (act[s] ? (long long)d.mir[s] * d.ncell + (ok[s] ? d.mlin[s] : 0) : 0LL));
+    else
+      a[s] = gload(cf + (act[s] ? (long long)s * d.ncell : 0LL));
     load4(xp + (ok[s] ? ((long long)d.lin[s] << lg) : 0LL), xv[s]);
   }
 #pragma unroll
@@ -525,7 +535,7 @@ __device__ __forceinline__ void block_dot4(double *sh, const double v[4], int lg
                        sh[3 * kBlock + threadIdx.x];
 }
 
-template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT>
+template <typename T, int MODE, typename TB, typename TO, int BIG, int NENT, bool MIR = false>
 __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restrict__ desc, int lg,
                                                      const T *__restrict__ x,
                                                      const TB *__restrict__ b, TO *__restrict__ y,
@@ -554,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil4(const PartDesc<T> *__restri
   const long long o = ((d.off + c) << lg) + 4 * (e & ((1 << lgc) - 1));
   const T *xp = x + o;
   T acc[4] = {T(0), T(0), T(0), T(0)};
-  if (valid) stencil_acc4<T, NENT>(d, c, lg, xp, acc);
+  if (valid) stencil_acc4<T, NENT, MIR>(d, c, lg, xp, acc);
   T cu[4];
   block_coupling4<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum, cu);
@@ -971,8 +981,29 @@ inline unsigned grid_cells(long long n, int lg) {
 
 template <typename T, typename TB, typename TO, int BIG, int NENT>
 void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T *x, const TB *b, TO *y,
-                  hipStream_t st, const LaunchEvents &ev, bool c4, double *dotp, const double *aux) {
+                  hipStream_t st, const LaunchEvents &ev, bool c4, double *dotp, const double *aux,
+                  bool mir) {
   constexpr bool fp64_out = sizeof(TO) == 8 && sizeof(TB) == 8;
+  // the FP64 product of a symmetric stencil of more than 7 points: mirrored reads
+  if constexpr (sizeof(T) == 8 && fp64_out && NENT > 7) {
+    if (mir && (mode == MODE_APPLY || mode == MODE_APPLY_DOT)) {
+      if (c4) {
+        dim3 g4((unsigned)(((long long)grid.x + 3) / 4), grid.y);
+        if (mode == MODE_APPLY)
+          dispatch(k_stencil4<T, MODE_APPLY, TB, TO, BIG, NENT, true>, g4, st, ev, desc, lg, x, b, y, dotp, aux);
+        else
+          dispatch(k_stencil4<T, MODE_APPLY_DOT, TB, TO, BIG, NENT, true>, g4, st, ev, desc, lg, x, b, y, dotp,
+                   aux);
+      } else {
+        if (mode == MODE_APPLY)
+          dispatch(k_stencil<T, MODE_APPLY, TB, TO, BIG, NENT, true>, grid, st, ev, desc, lg, x, b, y, dotp, aux);
+        else
+          dispatch(k_stencil<T, MODE_APPLY_DOT, TB, TO, BIG, NENT, true>, grid, st, ev, desc, lg, x, b, y, dotp,
+                   aux);
+      }
+      return;
+    }
+  }
   if (c4) {
     dim3 g4((grid.x + 3) / 4 > 0 ? (unsigned)(((long long)grid.x + 3) / 4) : 1u, grid.y);
 #define SSAMG_S4(M) dispatch(k_stencil4<T, M, TB, TO, BIG, NENT>, g4, st, ev, desc, lg, x, b, y, dotp, aux)
@@ -1000,7 +1031,7 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
                     int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev, int cols4,
-                    double *dotp, const double *aux) {
+                    double *dotp, const double *aux, bool mir) {
   if (mode == MODE_APPLY_DOT && !(sizeof(T) == 8 && sizeof(TO) == 8 && dotp))
     throw Error(SSAMG_ERR_STATE, "internal: the fused product dot needs FP64 and a partial buffer");
   if (mode == MODE_JACOBI_DOT && !(sizeof(TB) == 8 && sizeof(TO) == 8 && fine && dotp))
@@ -1009,18 +1040,18 @@ void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int
   const bool c4 = cols4 != 0 && stencil_cols4_ok<T>(lg, maxent);
   if (fine || (long long)maxcell * nparts >= kBigLevel) {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
+      stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
+      stencil_mode<T, TB, TO, 1, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
     else
-      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
+      stencil_mode<T, TB, TO, 1, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
   } else {
     if (maxent <= 7)
-      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
+      stencil_mode<T, TB, TO, 0, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
     else if (maxent <= 15)
-      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
+      stencil_mode<T, TB, TO, 0, 15>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
     else
-      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux);
+      stencil_mode<T, TB, TO, 0, 27>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
   }
 }
 
@@ -1088,13 +1119,13 @@ void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
 
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
                                                      int, const double *, const double *, double *,
-                                                     hipStream_t, LaunchEvents, int, double *, const double *);
+                                                     hipStream_t, LaunchEvents, int, double *, const double *, bool);
 template void launch_stencil<float, float, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int, double *, const double *);
+                                                  const float *, const float *, float *, hipStream_t, LaunchEvents, int, double *, const double *, bool);
 template void launch_stencil<float, double, float>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int, double *, const double *);
+                                                   const float *, const double *, float *, hipStream_t, LaunchEvents, int, double *, const double *, bool);
 template void launch_stencil<float, double, double>(int, int, int, const PartDesc<float> *, int, int, int,
-                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int, double *, const double *);
+                                                    const float *, const double *, double *, hipStream_t, LaunchEvents, int, double *, const double *, bool);
 template void launch_smooth_zero<double, double>(int, const PartDesc<double> *, int, int, int,
                                                  const double *, double *, hipStream_t);
 template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int, int, int, const float *,

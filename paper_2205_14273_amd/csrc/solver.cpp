@@ -134,9 +134,32 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
     throw Error(SSAMG_ERR_STATE, "internal: Galerkin table longer than kRapMaxTab");
 }
 
+// Mirror reads of a symmetric stencil (see PartDesc::mir): an offset is
+// positive when its last nonzero component (z, then y, then x) is positive.
+bool positive_offset(const std::array<int, 3> &o) {
+  for (int a = 2; a >= 0; --a)
+    if (o[a] != 0) return o[a] > 0;
+  return false;
+}
+
+// coefficient arrays the kernels stream for a part (all, or the center and the
+// positive half when mirrored reads apply)
+int streamed_entries(const PartLevel &q, bool symmetric) {
+  int neg = 0;
+  bool all = true;
+  for (const auto &o : q.pat) {
+    if (!positive_offset({-o[0], -o[1], -o[2]})) continue;
+    ++neg;
+    bool found = false;
+    for (const auto &t : q.pat) found = found || (t[0] == -o[0] && t[1] == -o[1] && t[2] == -o[2]);
+    all = all && found;
+  }
+  return symmetric && all ? (int)q.pat.size() - neg : (int)q.pat.size();
+}
+
 template <typename T>
 PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coef, const T *w,
-                      const T *uval, const T *rs, const int strips[kMaxLg + 1]) {
+                      const T *uval, const T *rs, const int strips[kMaxLg + 1], bool symmetric = false) {
   PartDesc<T> d{};
   d.rs = rs ? rs + q.off : nullptr;
   for (int a = 0; a < 3; ++a) {
@@ -173,6 +196,26 @@ PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coe
     const auto &o = q.pat[e];
     d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
     d.code[e] = pack_off(o[0], o[1], o[2]);
+    d.mir[e] = (int)e;
+    d.mlin[e] = 0;
+  }
+  if (symmetric) {
+    // every negative offset needs its mirror in the pattern, else full reads
+    std::vector<int> mir(q.pat.size(), -1);
+    bool all = true;
+    for (size_t e = 0; e < q.pat.size(); ++e) {
+      if (!positive_offset({-q.pat[e][0], -q.pat[e][1], -q.pat[e][2]})) continue;   // e not negative
+      for (size_t f = 0; f < q.pat.size(); ++f)
+        if (q.pat[f][0] == -q.pat[e][0] && q.pat[f][1] == -q.pat[e][1] && q.pat[f][2] == -q.pat[e][2])
+          mir[e] = (int)f;
+      all = all && mir[e] >= 0;
+    }
+    if (all)
+      for (size_t e = 0; e < q.pat.size(); ++e)
+        if (mir[e] >= 0) {
+          d.mir[e] = mir[e];
+          d.mlin[e] = d.lin[e];
+        }
   }
   return d;
 }
@@ -201,8 +244,10 @@ void build_descs(const Solver &s, int l, std::vector<PartDesc<double>> &h64,
   h32.clear();
   for (size_t p = 0; p < V.parts.size(); ++p) {
     const PartLevel &q = V.parts[p];
-    h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64, mv));
-    if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32, cyc));
+    // mirror tables for the FP64 product (used only by its mirrored kernels)
+    const bool sym = s.prm.symmetric != 0;
+    h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64, mv, sym));
+    if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32, cyc, false));
   }
 }
 
@@ -800,7 +845,9 @@ double level0_bytes(const Solver &s, int kind, int lg, size_t tc, size_t tx, siz
   const double nr = (double)(1 << lg);
   double by = 0.0;
   for (const auto &q : V.parts) {
-    const double n = (double)q.ncell, ne = (double)q.pat.size();
+    // the FP64 product streams the mirrored subset (see build_descs)
+    const bool mir = kind == SSAMG_PROBE_MATVEC && s.prm.symmetric != 0 && q.pat.size() > 7;
+    const double n = (double)q.ncell, ne = (double)streamed_entries(q, mir);
     switch (kind) {
       case SSAMG_PROBE_MATVEC: by += n * (ne * tc + nr * (tx + to)); break;
       case SSAMG_PROBE_SMOOTH0: by += n * (tc + nr * (tb + tx)); break;
@@ -989,7 +1036,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
     launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
                                            V.maxcell, lg, x, nullptr, y, s.stream, pr.e, cols4,
-                                           dot ? s.dotp : nullptr);
+                                           dot ? s.dotp : nullptr, nullptr, s.prm.symmetric != 0);
   }
   if (dot) {
     const bool c4 = cols4 != 0 && stencil_cols4_ok<double>(lg, V.maxent);
@@ -1003,7 +1050,8 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
 void apply_level(Solver &s, int level, const double *x, double *y) {
   Level &V = s.lv[level];
   launch_stencil<double, double, double>(MODE_APPLY, level == 0, V.maxent, V.d_desc64, (int)V.parts.size(),
-                                         V.maxcell, 0, x, nullptr, y, s.stream);
+                                         V.maxcell, 0, x, nullptr, y, s.stream, {}, -1, nullptr, nullptr,
+                                         s.prm.symmetric != 0);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(s.stream));
 }
@@ -1147,7 +1195,8 @@ int autotune_t(Solver &s, int lg) {
         pick(cand, [&] {
           const TuneRec o = tune_rec(s, 0, lg);
           launch_stencil<double, double, double>(MODE_APPLY_DOT, 1, V.maxent, V.d_desc64, np, V.maxcell, lg,
-                                                 s.p, nullptr, s.q, st, {}, o.cols4_mv, s.dotp);
+                                                 s.p, nullptr, s.q, st, {}, o.cols4_mv, s.dotp, nullptr,
+                                                 s.prm.symmetric != 0);
         });
       }
       ++ntuned;

@@ -117,6 +117,13 @@ struct PartDesc {
   const T *rs;
   int lin[kMaxEnt];    // dx + nx*(dy + ny*dz)
   int code[kMaxEnt];   // pack_off(dx, dy, dz)
+  // where the cycle and product kernels read a_s(c): entry mir[s] at cell
+  // c + mlin[s].  Symmetric stencils: an entry with a negative offset s is
+  // read as the mirrored entry -s of the neighbour c + s (a_s(c) = a_{-s}(c+s)),
+  // so only the center and the positive half are streamed; otherwise mir[s] =
+  // s, mlin[s] = 0.
+  int mir[kMaxEnt];
+  int mlin[kMaxEnt];
 };
 
 // ------------------------------------------------------------------ problem
@@ -384,7 +391,8 @@ inline bool stencil_cols4_ok(int lg, int maxent) {
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,
                     int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {},
-                    int cols4 = -1, double *dotp = nullptr, const double *aux = nullptr);
+                    int cols4 = -1, double *dotp = nullptr, const double *aux = nullptr,
+                    bool mir = false);
 // First pass of the fused product dot: kDotGroupBlocks partial sums per
 // right-hand side into partial[b][k] (row stride kMaxRhs) from ngroups groups
 // of dotp (per = 4 one-column slots each, or per = 1 group sum); k_dot_final
