@@ -791,14 +791,24 @@ __global__ __launch_bounds__(kBlock) void k_interp_add(const PartDesc<T> *__rest
   interp_one(d, (int)(e >> lg), (int)(e & ((1 << lg) - 1)), lg, xc, x);
 }
 
-// part of a level holding cell c (offsets ascending; coarse: the parts' offsets
-// in the next level's vector)
+// ------------------------------------------------------------ coarse end
+
+// part descriptor j of the LDS-staged array (kTailDescBytes apart; only the
+// fields before the mirror tables are present)
 template <typename T>
-__device__ __forceinline__ int part_at(const PartDesc<T> *desc, int np, long long c, bool coarse) {
+__device__ __forceinline__ const PartDesc<T> &tail_desc(const char *base, int j) {
+  return *reinterpret_cast<const PartDesc<T> *>(base + j * kTailDescBytes);
+}
+
+// part of a level holding cell c (offsets ascending; coarse: the parts' offsets
+// in the next level's vector), by bisection over the staged descriptors
+template <typename T>
+__device__ __forceinline__ int tail_part(const char *base, int np, long long c, bool coarse) {
   int lo = 0, hi = np - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if ((coarse ? desc[mid].coff : desc[mid].off) <= c)
+    const PartDesc<T> &d = tail_desc<T>(base, mid);
+    if ((coarse ? d.coff : d.off) <= c)
       lo = mid;
     else
       hi = mid - 1;
@@ -806,127 +816,234 @@ __device__ __forceinline__ int part_at(const PartDesc<T> *desc, int np, long lon
   return lo;
 }
 
-// acc[e] += (U xs)(e) for every element of a tail level (acc in LDS): the
-// products of all entries are staged in LDS kTailU at a time and each
-// (row, rhs) slot adds its row's products in entry order.
-template <typename T, int TT, typename XS>
-__device__ void tail_coupling(const TailLevel<T> &v, int lg, XS xs, T *__restrict__ prod,
-                              T *__restrict__ acc) {
-  if (v.nrow == 0) return;
+// dst[w] = src(w) for w < n (32-bit words), up to eight loads per thread in
+// flight (clamped indices, so that no load sits behind a branch)
+template <int TT, typename F>
+__device__ __forceinline__ void stage_words(int *__restrict__ dst, int n, F src) {
+  for (int w0 = 0; w0 < n; w0 += 8 * TT) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src(min(w0 + u * TT + (int)threadIdx.x, n - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int w = w0 + u * TT + (int)threadIdx.x;
+      if (w < n) dst[w] = v[u];
+    }
+  }
+}
+
+// acc[slot] += (U x)(slot) for every (row, rhs) slot of a level, x in LDS: all
+// threads form the products of a strided share of up to prodcap entries per
+// pass (loads of entries and of the thread's row ranges in flight together),
+// stage them in LDS, and each slot adds its row's products in entry order.
+// Rows x rhs <= kTailMax.  Ends with a workgroup barrier.
+template <typename T, int TT>
+__device__ void tail_u(const TailLevel<T> &v, int lg, const T *__restrict__ x, T *__restrict__ prod,
+                       int prodcap, T *__restrict__ acc) {
+  if (v.nrow == 0) return;   // uniform
+  constexpr int RPT = kTailMax / TT, EPT = kTailU / TT;
   const int tid = threadIdx.x, mask = (1 << lg) - 1;
-  const int nnz = v.uptr[v.nrow];
-  const int per = kTailU >> lg;
+  const int nslot = v.nrow << lg, nnz = v.nnz;
+  int qa[RPT], qb[RPT], slot[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int t = min(tid + j * TT, nslot - 1);
+    const int r = t >> lg;
+    qa[j] = gload(v.uptr + r);
+    qb[j] = gload(v.uptr + r + 1);
+    slot[j] = (gload(v.urow + r) << lg) | (t & mask);
+  }
+  const int per = prodcap >> lg;
   for (int ec = 0; ec < nnz; ec += per) {
     const int np = min(per, nnz - ec) << lg;
-    int cc[kTailU / TT];
-    T vv[kTailU / TT];
+    int cc[EPT];
+    T vv[EPT];
 #pragma unroll
-    for (int t = 0; t < kTailU / TT; ++t) {
+    for (int t = 0; t < EPT; ++t) {
       const int q = tid + t * TT;
-      const int qe = ec + (q < np ? (q >> lg) : 0);   // unconditional (masked below)
+      const int qe = ec + (q < np ? (q >> lg) : 0);
       cc[t] = gload(v.ucol + qe);
       vv[t] = gload(v.uval + qe);
     }
 #pragma unroll
-    for (int t = 0; t < kTailU / TT; ++t) {
+    for (int t = 0; t < EPT; ++t) {
       const int q = tid + t * TT;
-      if (q < np) prod[q] = vv[t] * xs(cc[t], q & mask);
+      if (q < np) prod[q] = vv[t] * x[(cc[t] << lg) | (q & mask)];
     }
     __syncthreads();
-    for (int t = tid; t < (v.nrow << lg); t += TT) {
-      const int r = t >> lg, kr = t & mask;
-      const int qa = max(v.uptr[r], ec), qb = min(v.uptr[r + 1], ec + (np >> lg));
-      if (qa >= qb) continue;
-      const T a = row_sum(prod, qa - ec, qb - ec, lg, kr, T(0));
-      acc[(v.urow[r] << lg) | kr] += a;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int t = tid + j * TT;
+      const int a = max(qa[j], ec), b = min(qb[j], ec + (np >> lg));
+      if (t < nslot && a < b) acc[slot[j]] = row_sum(prod, a - ec, b - ec, lg, t & mask, acc[slot[j]]);
     }
     __syncthreads();
   }
 }
 
-// The coarse end of one V(1,1) cycle, levels tl[0] .. tl[nl-1] (the last one
-// the coarsest), in a single workgroup: the same operations as the grid
-// kernels over all cells of a level at once (the part of a cell found by
-// search), one phase at a time with a workgroup barrier between phases.  The
-// A x sums of a level are formed in LDS (stencil part per element, then the
-// coupling rows added), so every level above the coarsest must hold at most
-// kTailMax elements.  TT threads: 1024 in FP32, 512 in FP64 (register room for
-// the 27 coefficient, iterate and factor loads a thread keeps in flight).
+// The coarse end of one V(1,1) cycle, levels tl[0] .. tl[pl.nl - 1] (the last
+// one the coarsest), in a single workgroup whose vectors and part descriptors
+// live in LDS: from tl[0].vb (global) into tl[0].vt (global).  The same
+// operations as the grid kernels, over all elements of a level at once (the
+// part of a cell found by bisection), one phase at a time with a workgroup
+// barrier between phases; the A x sums are formed in LDS (stencil part per
+// element, then the coupling rows added).  Every level above the coarsest
+// holds at most kTailMax elements.  TT threads: 1024 in FP32, 512 in FP64
+// (register room for the 27 coefficient and iterate loads a thread keeps in
+// flight).
 template <typename T, int TT>
-__global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl, int nl,
-                                                       int lg) {
-  __shared__ T prod[kTailU];
-  __shared__ T acc[kTailMax];
-  const int tid = threadIdx.x;
-  const int mask = (1 << lg) - 1;
+__global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl, TailPlan pl, int lg) {
+  extern __shared__ __align__(16) char sm[];
+  const int tid = threadIdx.x, mask = (1 << lg) - 1;
+  const int nl = pl.nl, np = pl.np;
+  const TailLevel<T> *L = reinterpret_cast<const TailLevel<T> *>(sm);
+  int *voff = reinterpret_cast<int *>(sm + pl.off_tab);   // [nl]: b of level i at vec + voff[i]
+  const int **src = reinterpret_cast<const int **>(sm + pl.off_src);
+  const char *dsm = sm + pl.off_desc, *d64 = sm + pl.off_d64;
+  T *vec = reinterpret_cast<T *>(sm + pl.off_vec);
+  T *tv = reinterpret_cast<T *>(sm + pl.off_tv), *acc = reinterpret_cast<T *>(sm + pl.off_acc);
+  T *prod = reinterpret_cast<T *>(sm + pl.off_prod);
+  // records, vector offsets and descriptor sources
+  stage_words<TT>(reinterpret_cast<int *>(sm), nl * (int)(sizeof(TailLevel<T>) / 4),
+                  [&](int w) { return gload(reinterpret_cast<const int *>(tl) + w); });
+  __syncthreads();
+  if (tid < nl) {
+    int o = 0;
+    for (int i = 0; i < tid; ++i) o += 2 * (int)(L[i].ncell << lg);
+    voff[tid] = o;
+    for (int p = 0; p < np; ++p) src[tid * np + p] = reinterpret_cast<const int *>(L[tid].desc + p);
+  }
+  const bool sweep = L[nl - 1].ndirect == 0;
+  if (sweep && tid < np) src[nl * np + tid] = reinterpret_cast<const int *>(L[nl - 1].desc64 + tid);
+  __syncthreads();
+  // descriptors (prefixes) and b of the first level
+  {
+    constexpr int dw = kTailDescBytes / 4;
+    const int nd = (nl + (sweep ? 1 : 0)) * np;
+    // the FP64 descriptors follow the others directly (off_d64 = off_desc + nl np kTailDescBytes)
+    stage_words<TT>(reinterpret_cast<int *>(sm + pl.off_desc), nd * dw,
+                    [&](int w) { return gload(src[w / dw] + (w % dw)); });
+    const int nb = (int)(L[0].ncell << lg) * (int)(sizeof(T) / 4);
+    stage_words<TT>(reinterpret_cast<int *>(vec), nb,
+                    [&](int w) { return gload(reinterpret_cast<const int *>(L[0].vb) + w); });
+  }
+  __syncthreads();
+  // down: x = w b, t = b - A x, b_c = P^T t
   for (int i = 0; i + 1 < nl; ++i) {
-    const TailLevel<T> &v = tl[i];
+    const TailLevel<T> &v = L[i];
+    const char *ds = dsm + i * np * kTailDescBytes;
     const int nel = (int)(v.ncell << lg);
-    // x = w b and the stencil part of A x
+    const T *b = vec + voff[i];
+    T *x = vec + voff[i] + nel;
     for (int e = tid; e < nel; e += TT) {
       const int c = e >> lg;
-      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
+      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
       const int cl = c - (int)d.off;
-      acc[e] = stencil_wb<T, T, kMaxEnt>(d, cl, lg, v.vb + e);
-      v.vx[e] = d.rs[cl] * v.vb[e];
+      acc[e] = stencil_wb<T, T, kMaxEnt>(d, cl, lg, b + e);
+      x[e] = G(d.rs)[cl] * b[e];
     }
     __syncthreads();
-    const T *wl = v.desc[0].rs;   // factors of the whole level (part 0 starts it)
-    tail_coupling<T, TT>(v, lg, [&](int col, int k) { return wl[col] * v.vb[(col << lg) | k]; }, prod, acc);
-    for (int e = tid; e < nel; e += TT) v.vt[e] = v.vb[e] - acc[e];
+    tail_u<T, TT>(v, lg, x, prod, pl.prodcap, acc);
+    for (int e = tid; e < nel; e += TT) tv[e] = b[e] - acc[e];
     __syncthreads();
-    const TailLevel<T> &w = tl[i + 1];
-    const int ncel = (int)(w.ncell << lg);
+    const int ncel = (int)(L[i + 1].ncell << lg);
+    T *bc = vec + voff[i + 1];
     for (int e = tid; e < ncel; e += TT) {
       const int c = e >> lg;
-      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, true)];
-      restrict_one(d, c - (int)d.coff, e & mask, lg, v.vt, w.vb);
+      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, true));
+      restrict_one(d, c - (int)d.coff, e & mask, lg, tv, bc);
     }
     __syncthreads();
   }
+  // coarsest: one FP64 sweep from zero, or the direct solve, into tv
   {
-    const TailLevel<T> &v = tl[nl - 1];
-    const long long nel = v.ncell << lg;
-    if (v.ndirect > 0) {
-      // direct solve: x = A^{-1} b with the inverse formed at setup, in FP64
-      for (long long e = tid; e < nel; e += TT) {
-        const int row = (int)(e >> lg), kr = (int)(e & mask);
-        const double *ar = v.ainv + (long long)row * v.ndirect;
-        double acc = 0.0;
-        for (int j = 0; j < v.ndirect; ++j) acc = fma(ar[j], (double)v.vb[((long long)j << lg) + kr], acc);
-        v.vt[e] = (T)acc;
+    const TailLevel<T> &v = L[nl - 1];
+    const int nel = (int)(v.ncell << lg);
+    const T *b = vec + voff[nl - 1];
+    T *out = nl == 1 ? v.vt : tv;
+    if (!sweep) {
+      for (int e = tid; e < nel; e += TT) {
+        const int row = e >> lg, kr = e & mask;
+        const auto ar = G(v.ainv) + (long long)row * v.ndirect;
+        double a = 0.0;
+        for (int j = 0; j < v.ndirect; ++j) a = fma(ar[j], (double)b[(j << lg) + kr], a);
+        out[e] = (T)a;
       }
     } else {
-      for (long long e = tid; e < nel; e += TT) {
-        const long long c = e >> lg;
-        const PartDesc<double> &d = v.desc64[part_at(v.desc64, v.np, c, false)];
-        v.vt[e] = (T)(smooth_factor(d, c - d.off) * (double)v.vb[e]);
+      for (int e = tid; e < nel; e += TT) {
+        const int c = e >> lg;
+        const PartDesc<double> &d = tail_desc<double>(d64, tail_part<double>(d64, np, c, false));
+        out[e] = (T)(smooth_factor(d, c - d.off) * (double)b[e]);
       }
     }
     __syncthreads();
   }
+  // up: x += P x_c, then x + w (b - A x) into tv (level 0: into tl[0].vt)
   for (int i = nl - 2; i >= 0; --i) {
-    const TailLevel<T> &v = tl[i];
+    const TailLevel<T> &v = L[i];
+    const char *ds = dsm + i * np * kTailDescBytes;
     const int nel = (int)(v.ncell << lg);
+    const T *b = vec + voff[i];
+    T *x = vec + voff[i] + nel;
     for (int e = tid; e < nel; e += TT) {
       const int c = e >> lg;
-      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
-      interp_one(d, c - (int)d.off, e & mask, lg, tl[i + 1].vt, v.vx);
+      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
+      interp_one(d, c - (int)d.off, e & mask, lg, tv, x);
     }
     __syncthreads();
     for (int e = tid; e < nel; e += TT) {
       const int c = e >> lg;
-      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
-      acc[e] = stencil_acc<T, kMaxEnt>(d, c - (int)d.off, lg, v.vx + e);
+      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
+      acc[e] = stencil_acc<T, kMaxEnt>(d, c - (int)d.off, lg, x + e);
     }
     __syncthreads();
-    tail_coupling<T, TT>(v, lg, [&](int col, int k) { return v.vx[(col << lg) | k]; }, prod, acc);
-    for (int e = tid; e < nel; e += TT) {
-      const int c = e >> lg;
-      const PartDesc<T> &d = v.desc[part_at(v.desc, v.np, c, false)];
-      v.vt[e] = v.vx[e] + d.rs[c - (int)d.off] * (v.vb[e] - acc[e]);
+    tail_u<T, TT>(v, lg, x, prod, pl.prodcap, acc);
+    if (i == 0) {
+      const auto out = dev::Gw(v.vt);
+      for (int e = tid; e < nel; e += TT) {
+        const int c = e >> lg;
+        const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
+        out[e] = x[e] + G(d.rs)[c - (int)d.off] * (b[e] - acc[e]);
+      }
+    } else {
+      for (int e = tid; e < nel; e += TT) {
+        const int c = e >> lg;
+        const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
+        tv[e] = x[e] + G(d.rs)[c - (int)d.off] * (b[e] - acc[e]);
+      }
     }
     __syncthreads();
+  }
+}
+
+// One coarsest level of any size with its vectors in global memory (the
+// hierarchy's only level, or a coarsest level whose vectors do not fit in
+// LDS): vt = (FP64 sweep from zero or A^{-1}) vb.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarsest(const TailLevel<T> *__restrict__ tl, int lg) {
+  const TailLevel<T> &v = *tl;
+  const long long nel = v.ncell << lg;
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nel) return;
+  const int mask = (1 << lg) - 1;
+  if (v.ndirect > 0) {
+    const int row = (int)(e >> lg), kr = (int)(e & mask);
+    const double *ar = v.ainv + (long long)row * v.ndirect;
+    double a = 0.0;
+    for (int j = 0; j < v.ndirect; ++j) a = fma(ar[j], (double)v.vb[((long long)j << lg) + kr], a);
+    v.vt[e] = (T)a;
+  } else {
+    const long long c = e >> lg;
+    int lo = 0, hi = v.np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (v.desc64[mid].off <= c)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const PartDesc<double> &d = v.desc64[lo];
+    v.vt[e] = (T)(smooth_factor(d, c - d.off) * (double)v.vb[e]);
   }
 }
 
@@ -1112,9 +1229,14 @@ void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, int
 }
 
 template <typename T>
-void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st) {
+void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t st) {
   constexpr int tt = sizeof(T) == 8 ? kTailThreads / 2 : kTailThreads;
-  k_tail<T, tt><<<1, tt, 0, st>>>(tl, nl, lg);
+  k_tail<T, tt><<<1, tt, pl.bytes, st>>>(tl, pl, lg);
+}
+
+template <typename T>
+void launch_coarsest(const TailLevel<T> *tl, int64_t nel, int lg, hipStream_t st) {
+  k_coarsest<T><<<grid_cells(nel, 0), kBlock, 0, st>>>(tl, lg);
 }
 
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
@@ -1146,7 +1268,9 @@ template void launch_smooth_resid<float, float>(int, int, const PartDesc<float> 
                                                 const float *, float *, float *, hipStream_t, LaunchEvents);
 template void launch_smooth_resid<float, double>(int, int, const PartDesc<float> *, int, int, int,
                                                  const double *, float *, float *, hipStream_t, LaunchEvents);
-template void launch_tail<double>(const TailLevel<double> *, int, int, hipStream_t);
-template void launch_tail<float>(const TailLevel<float> *, int, int, hipStream_t);
+template void launch_tail<double>(const TailLevel<double> *, const TailPlan &, int, hipStream_t);
+template void launch_tail<float>(const TailLevel<float> *, const TailPlan &, int, hipStream_t);
+template void launch_coarsest<double>(const TailLevel<double> *, int64_t, int, hipStream_t);
+template void launch_coarsest<float>(const TailLevel<float> *, int64_t, int, hipStream_t);
 
 }  // namespace ssamg

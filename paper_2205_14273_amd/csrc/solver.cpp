@@ -762,12 +762,12 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     if (mixed) {
       TailLevel<float> t{V.d_desc32, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
                          V.d_ucol, V.d_uval32, (float *)V.vb, (float *)V.vx, (float *)V.vt,
-                         V.d_ainv, V.d_ainv ? (int)V.N : 0, 0};
+                         V.d_ainv, V.d_ainv ? (int)V.N : 0, (int)V.nnz};
       put(V.d_tail, &t, sizeof(t));
     } else {
       TailLevel<double> t{V.d_desc64, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
                           V.d_ucol, V.d_uval64, (double *)V.vb, (double *)V.vx, (double *)V.vt,
-                         V.d_ainv, V.d_ainv ? (int)V.N : 0, 0};
+                         V.d_ainv, V.d_ainv ? (int)V.N : 0, (int)V.nnz};
       put(V.d_tail, &t, sizeof(t));
     }
   }
@@ -899,12 +899,58 @@ void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int l
   }
 }
 
-// first level handled by the one-workgroup tail kernel: the first level >= 1
-// with at most tail_elems (<= kTailMax) elements; the coarsest level always is
+}  // namespace
+
+bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
+  const int L = (int)s.lv.size();
+  const size_t ts = s.prm.cycle_precision == SSAMG_FP32 ? sizeof(float) : sizeof(double);
+  const int np = (int)s.lv[0].parts.size();
+  const bool sweep = s.lv[L - 1].d_ainv == nullptr;
+  auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  size_t nvec = 0, maxel = 1;
+  for (int l = lt; l < L; ++l) {
+    nvec += 2 * ((size_t)s.lv[l].N << lg);
+    if (l < L - 1) maxel = std::max(maxel, (size_t)s.lv[l].N << lg);
+  }
+  if (L - lt > 1 && maxel > (size_t)kTailMax) return false;
+  pl = TailPlan{};
+  pl.nl = L - lt;
+  pl.np = np;
+  pl.maxel = (int)maxel;
+  pl.prodcap = kTailU;
+  size_t o = al(sizeof(TailLevel<double>) * pl.nl);
+  pl.off_tab = (int)o;
+  o = al(o + sizeof(int) * pl.nl);
+  pl.off_src = (int)o;
+  o = al(o + sizeof(void *) * (size_t)(pl.nl + 1) * np);
+  pl.off_desc = (int)o;
+  o += (size_t)kTailDescBytes * pl.nl * np;
+  pl.off_d64 = (int)o;
+  o = al(o + (sweep ? (size_t)kTailDescBytes * np : 0));
+  pl.off_vec = (int)o;
+  o = al(o + ts * nvec);
+  pl.off_tv = (int)o;
+  o = al(o + ts * maxel);
+  pl.off_acc = (int)o;
+  o = al(o + ts * maxel);
+  pl.off_prod = (int)o;
+  o = al(o + ts * kTailU);
+  if (o > (size_t)kTailLds) return false;
+  pl.bytes = (int)o;
+  return true;
+}
+
+namespace {
+
+// first level handled by the one-workgroup coarse-end kernel: the first level
+// >= 1 with at most tail_elems (<= kTailMax) elements whose coarse end fits in
+// LDS; the coarsest level always is (when it alone does not fit, it runs as a
+// grid kernel on global vectors)
 int tail_start(const Solver &s, int lg) {
   const int L = (int)s.lv.size();
+  TailPlan pl;
   for (int l = 1; l < L; ++l)
-    if ((s.lv[l].N << lg) <= s.tail_elems) return l;
+    if ((s.lv[l].N << lg) <= s.tail_elems && tail_plan(s, l, lg, pl)) return l;
   return L - 1;
 }
 
@@ -923,7 +969,11 @@ void run_tail(Solver &s, int lg) {
     down_sweep<T, T>(s, V, d, 0, lg, b, x, t, tune_rec(s, l, lg));
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
-  launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, L - lt, lg, st);
+  TailPlan pl;
+  if (tail_plan(s, lt, lg, pl))
+    launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, pl, lg, st);
+  else   // a coarsest level too large for LDS
+    launch_coarsest<T>((const TailLevel<T> *)s.lv[lt].d_tail, s.lv[lt].N << lg, lg, st);
   for (int l = lt - 1; l >= 1; --l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
@@ -975,12 +1025,12 @@ void precond_t(Solver &s, int lg, bool dots) {
     if (sizeof(T) == sizeof(float)) {
       launch_cast_d2f(s.r, (float *)V.vb, V.N << lg, st);
       if (direct)
-        launch_tail<T>((const TailLevel<T> *)V.d_tail, 1, lg, st);
+        launch_coarsest<T>((const TailLevel<T> *)V.d_tail, V.N << lg, lg, st);
       else
         launch_coarse_mixed(V.d_desc64, np, V.maxcell, lg, (const float *)V.vb, (float *)V.vt, st);
       launch_cast_f2d((const float *)V.vt, s.z, V.N << lg, st);
     } else if (direct) {
-      launch_tail<T>((const TailLevel<T> *)V.d_tail, 1, lg, st);   // vb = r, vt = z
+      launch_coarsest<T>((const TailLevel<T> *)V.d_tail, V.N << lg, lg, st);   // vb = r, vt = z
     } else {
       launch_smooth_zero<double, double>(1, V.d_desc64, np, V.maxcell, lg, s.r, s.z, st);
     }

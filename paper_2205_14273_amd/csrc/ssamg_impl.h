@@ -8,6 +8,7 @@
 #include <array>
 #include <map>
 #include <memory>
+#include <cstddef>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -34,17 +35,18 @@ constexpr int kBlock = 256;      // threads per block of every grid-over-cells k
 constexpr int kRedBlocks = 2048; // fixed grid of the deterministic reductions (8 per CU)
 constexpr int kMaxRhs = 32;
 constexpr int kMaxLg = 5;        // log2(kMaxRhs)
-// The coarse end of the cycle runs in one workgroup of kTailThreads threads:
-// the coarsest level and the levels of at most tail_elems elements (cells x
-// right-hand sides; never more than kTailMax, the LDS row-sum capacity).
-// kTailU coupling products are staged in LDS per pass.  Default 0 (coarsest
-// level only): on MI355X every phase of the one-workgroup kernel waits on
-// loads that miss its XCD's L2, about 30 us per level against about 20 us for
-// a level's four grid launches.
+// The coarse end of the cycle runs in one workgroup of kTailThreads threads
+// (half of them in FP64): the coarsest level and the levels of at most
+// tail_elems elements (cells x right-hand sides; never more than kTailMax).
+// The levels' vectors and part descriptors live in LDS (at most kTailLds
+// bytes; fewer levels are taken when they do not fit), so each phase of the
+// kernel waits on one round of coefficient loads instead of a launch and a
+// chain of dependent loads.  kTailU coupling products are staged per pass.
 constexpr int kTailThreads = 1024;
 constexpr int kTailMax = 4096;
 constexpr int kTailU = 2048;
-constexpr int64_t kTailElems = 0;
+constexpr int64_t kTailElems = 1024;
+constexpr int kTailLds = 65536;
 // levels with more than 15-point stencils and at least this many cells run the
 // first smoothing sweep and the residual as two kernels instead of one
 constexpr int64_t kSplitCells = 1 << 20;
@@ -125,6 +127,12 @@ struct PartDesc {
   int mir[kMaxEnt];
   int mlin[kMaxEnt];
 };
+
+// bytes of a part descriptor that the V-cycle reads (everything before the
+// mirror tables); the coarse-end kernel stages only these in LDS
+constexpr int kTailDescBytes = (int)offsetof(PartDesc<float>, mir);
+static_assert(kTailDescBytes == (int)offsetof(PartDesc<double>, mir), "descriptor prefix");
+static_assert(kTailDescBytes % 16 == 0, "descriptor prefix alignment");
 
 // ------------------------------------------------------------------ problem
 
@@ -335,7 +343,18 @@ struct TailLevel {
   const T *uval;
   T *vb, *vx, *vt;                  // right-hand side, iterate, output
   const double *ainv;               // coarsest level, direct solve: A^{-1} (row-major), else null
-  int ndirect, pad;                 // its order (0: one relaxation sweep)
+  int ndirect, nnz;                 // its order (0: one relaxation sweep); entries of U
+};
+
+// Dynamic LDS layout of the coarse-end kernel for nl levels (byte offsets, 16
+// aligned): the TailLevel records, two int tables (vector offsets, first
+// descriptor), the descriptors' source pointers, the part descriptors of all
+// levels and the coarsest level's FP64 ones (kTailDescBytes each: the fields
+// before the mirror tables), the b and x vectors of every level, then a
+// scratch and a sum vector of maxel elements and prodcap coupling products.
+struct TailPlan {
+  int nl, np, maxel, prodcap;
+  int off_tab, off_src, off_desc, off_d64, off_vec, off_tv, off_acc, off_prod, bytes;
 };
 
 // per-part Galerkin table of one level (device array indexed by part)
@@ -405,8 +424,16 @@ void launch_dot_final(const double *partial, int nblk, int lg, double *scal, int
 // with nset = 2, the second into slot_b
 void launch_dot_final2(const double *partial, int nblk, int lg, double *scal, int slot_a, int shift_rz,
                        int slot_b, int nset, hipStream_t st);
+// the coarse end of one cycle (levels tl[0 .. pl.nl), LDS-resident)
 template <typename T>
-void launch_tail(const TailLevel<T> *tl, int nl, int lg, hipStream_t st);
+void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t st);
+// one coarsest level of nel elements, any size (vectors in global memory): a
+// sweep from zero or the direct solve, vb into vt
+template <typename T>
+void launch_coarsest(const TailLevel<T> *tl, int64_t nel, int lg, hipStream_t st);
+// LDS layout of the coarse end from level lt at width 2^lg; false when it
+// exceeds kTailLds bytes
+bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl);
 template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st);

@@ -148,6 +148,25 @@ def test_max_levels_and_min_coarse_size():
         assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_coarsest_level(precision):
+    """max_levels = 2 leaves a coarsest level of 16000 cells, too large for the
+    LDS-resident coarse end: it runs as a grid kernel on global vectors (one
+    sweep from zero), and the cycle and the solve still match the oracle."""
+    _print_case(f"large coarsest precision={precision}")
+    case = W.c2(20)
+    h = oracle_fv(case, max_levels=2)
+    pr, s = gpu_fv(case, max_levels=2, cycle_precision=precision)
+    assert s.nlevels == 2 and s.level_cells(1) == 16000
+    r = np.random.default_rng(12).uniform(-1, 1, h.levels[0].n)
+    z = s.apply_precond(_cuda(r)).cpu().numpy()
+    want = O.vcycle(h, r)
+    assert np.linalg.norm(z - want) <= (1e-12 if precision == 0 else 1e-5) * np.linalg.norm(want)
+    ref = O.solve(h, case.b, tol=1e-8)
+    x, st, info = s.solve(_cuda(case.b))
+    assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
+
+
 def test_single_cell_parts():
     # degenerate: every part is one cell, the hierarchy has one level
     g = W.Geometry(3, [(1, 1, 1)] * 3, [(0, 0, 0), (1, 0, 0), (2, 0, 0)])
@@ -224,9 +243,11 @@ def test_graph_and_eager_agree():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tail_kernel_matches_grid_kernels(monkeypatch, precision):
-    """The one-workgroup coarse-end kernel (levels of up to 4096 elements, set
-    through SSAMG_TAIL_ELEMS) gives the V-cycle of the per-level grid kernels,
-    for one and for eight right-hand sides; both match the oracle's cycle."""
+    """The one-workgroup coarse-end kernel (vectors and descriptors in LDS; the
+    levels of up to 4096 elements that fit, set through SSAMG_TAIL_ELEMS) gives
+    the V-cycle of the per-level grid kernels (SSAMG_TAIL_ELEMS=0: the coarsest
+    level only), for one and for eight right-hand sides; both match the
+    oracle's cycle."""
     _print_case(f"tail precision={precision}")
     case = W.c2(13)
     h = oracle_fv(case)
