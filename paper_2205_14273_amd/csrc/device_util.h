@@ -47,6 +47,15 @@ __device__ __forceinline__ gptr_w<T> Gw(T *p) {
   return (gptr_w<T>)p;
 }
 
+// v through an empty asm statement, so that the optimiser cannot see how it
+// was formed: an index chosen by a select (a neighbour's offset or 0) then
+// keeps its load unconditional instead of being folded into a branch around
+// the load, where the load would wait for the one before it.
+__device__ __forceinline__ int opaque(int v) {
+  __asm__("" : "+v"(v));
+  return v;
+}
+
 // XCD-aware block order: consecutive chunks of one part land on one XCD (the
 // hardware deals blocks round-robin over the 8 XCDs), so the neighbour planes a
 // block re-reads sit in that XCD's L2.

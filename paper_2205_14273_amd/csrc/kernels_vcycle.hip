@@ -15,6 +15,9 @@
 // A x = S x + U x (Section 2).
 #include <hip/hip_ext.h>
 
+#include <cstddef>
+#include <type_traits>
+
 #include "device_util.h"
 #include "ssamg_impl.h"
 
@@ -38,9 +41,15 @@ __device__ __forceinline__ T smooth_factor(const PartDesc<T> &d, long long c) {
 }
 
 // sum_s a_s(c) x(c + s) over the part's stencil; all loads are issued before
-// the first multiply (entries s >= nent are masked off)
-// MIR: coefficients read through the mirror tables (PartDesc::mir)
-template <typename T, int NENT, bool MIR = false>
+// the first multiply (entries s >= nent are masked off).
+// MIR: coefficients read through the mirror tables (PartDesc::mir).
+// LAT (launches on small levels, bound by latency): every load unconditional
+// (an absent entry reads entry 0, an absent neighbour the cell itself; the
+// value is zeroed afterwards), so that no load and no read of the descriptor's
+// offset tables sits behind a branch, where each would wait for the one
+// before.  Large levels keep the guarded loads: the unconditional form needs
+// about 30 more registers, which costs occupancy and bandwidth there.
+template <typename T, int NENT, bool MIR = false, bool LAT = false>
 __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, const T *xp) {
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
@@ -54,6 +63,12 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
       const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
       a[s] = act ? cf[(long long)d.mir[s] * d.ncell + (ok ? d.mlin[s] : 0)] : T(0);
       xv[s] = ok ? xp[(long long)d.lin[s] << lg] : T(0);
+    } else if constexpr (LAT) {
+      const bool ok = nb_ok(mx, my, mz, d.code[s]) & act;   // no short circuit: no branch
+      const T av = cf[act ? (long long)s * d.ncell : 0LL];
+      const T xq = xp[(long long)dev::opaque(ok ? d.lin[s] : 0) << lg];
+      a[s] = act ? av : T(0);
+      xv[s] = ok ? xq : T(0);
     } else {
       a[s] = act ? cf[(long long)s * d.ncell] : T(0);
       xv[s] = (act && nb_ok(mx, my, mz, d.code[s])) ? xp[(long long)d.lin[s] << lg] : T(0);
@@ -67,7 +82,7 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
 
 // sum_s a_s(c) w(c + s) b(c + s): the stencil part of A x at cell c for the
 // iterate x = w b of a first sweep from zero (bp points at b of cell c)
-template <typename T, typename TB, int NENT>
+template <typename T, typename TB, int NENT, bool LAT = false>
 __device__ __forceinline__ T stencil_wb(const PartDesc<T> &d, int c, int lg, const TB *bp) {
   int i, j, k;
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
@@ -76,12 +91,23 @@ __device__ __forceinline__ T stencil_wb(const PartDesc<T> &d, int c, int lg, con
   const auto wp = G(d.rs) + c;
   T a[NENT], bv[NENT], wv[NENT];
 #pragma unroll
-  for (int s = 0; s < NENT; ++s) {
+  for (int s = 0; s < NENT; ++s) {   // LAT: unconditional loads, as in stencil_acc
     const bool act = s < d.nent;
-    const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
-    a[s] = act ? cf[(long long)s * d.ncell] : T(0);
-    bv[s] = ok ? (T)bp[(long long)d.lin[s] << lg] : T(0);
-    wv[s] = ok ? wp[d.lin[s]] : T(0);
+    if constexpr (LAT) {
+      const bool ok = nb_ok(mx, my, mz, d.code[s]) & act;
+      const T av = cf[act ? (long long)s * d.ncell : 0LL];
+      const int ls = dev::opaque(ok ? d.lin[s] : 0);
+      const T bq = (T)bp[(long long)ls << lg];
+      const T wq = wp[ls];
+      a[s] = act ? av : T(0);
+      bv[s] = ok ? bq : T(0);
+      wv[s] = ok ? wq : T(0);
+    } else {
+      const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
+      a[s] = act ? cf[(long long)s * d.ncell] : T(0);
+      bv[s] = ok ? (T)bp[(long long)d.lin[s] << lg] : T(0);
+      wv[s] = ok ? wp[d.lin[s]] : T(0);
+    }
   }
   T acc = T(0);
 #pragma unroll
@@ -144,9 +170,13 @@ __device__ __forceinline__ T row_sum(const T *__restrict__ prod, int q0, int q1,
 // row's products in entry order (deterministic).  Long rows, which coarse
 // levels build across mismatched part interfaces, thus cost no serial chain of
 // loads.  Must be called by every thread of the block.
-template <int UCH, typename T, typename XS>
+template <int UCH, typename T, typename XS, typename XW = std::nullptr_t>
 __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int lg, XS xs,
-                                            T *__restrict__ prod, T *__restrict__ rsum) {
+                                            T *__restrict__ prod, T *__restrict__ rsum,
+                                            XW xw = nullptr) {
+  // xw (optional): a second factor of the column's value, xw(col, k) * xs(col, k),
+  // gathered separately so that no multiply waits between the gathers
+  constexpr bool WB = !std::is_same<XW, std::nullptr_t>::value;
   const auto ub = G(d.ublk[lg]) + 2 * chunk;
   const int u0 = ub[0], e0 = ub[1], u1 = ub[2], e1 = ub[3];
   if (u0 == u1) return T(0);                          // block-uniform
@@ -167,7 +197,7 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
   for (int ec = e0; ec < e1; ec += per) {
     const int np = min(per, e1 - ec) << lg;
     int cc[UCH / kBlock];
-    T vv[UCH / kBlock], xx[UCH / kBlock];
+    T vv[UCH / kBlock], xx[UCH / kBlock], ww[UCH / kBlock];
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
       const int q = tid + t * kBlock;
@@ -179,13 +209,19 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
     }
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
-      const int q = tid + t * kBlock;
-      xx[t] = q < np ? xs(cc[t], q & mask) : T(0);
+      // gathers behind a block-uniform test only (a slot past the chunk
+      // gathers its first entry's column and is masked below)
+      xx[t] = ww[t] = T(0);
+      if (t * kBlock < np) {
+        const int k = (tid + t * kBlock) & mask;
+        xx[t] = xs(cc[t], k);
+        if constexpr (WB) ww[t] = xw(cc[t], k);
+      }
     }
 #pragma unroll
     for (int t = 0; t < UCH / kBlock; ++t) {
       const int q = tid + t * kBlock;
-      if (q < np) prod[q] = vv[t] * xx[t];
+      if (q < np) prod[q] = vv[t] * (WB ? ww[t] * xx[t] : xx[t]);
     }
     __syncthreads();
     if (tid < nrt) {
@@ -315,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   const int kr = (int)(e & ((1 << lg) - 1));
   const long long o = ((d.off + c) << lg) + kr;
   const T *xp = x + o;
-  T acc = valid ? stencil_acc<T, NENT, MIR>(d, c, lg, xp) : T(0);
+  T acc = valid ? stencil_acc<T, NENT, MIR, !BIG>(d, c, lg, xp) : T(0);
   acc += block_coupling<UCH>(
       d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
   if constexpr (MODE == MODE_APPLY_DOT) {
@@ -368,11 +404,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_resid(const PartDesc<T> *__re
   const long long o = ((d.off + c) << lg) + kr;
   const TB *bp = b + o;
   const auto wp = G(d.rs) + c;
-  T acc = valid ? stencil_wb<T, TB, NENT>(d, c, lg, bp) : T(0);
+  T acc = valid ? stencil_wb<T, TB, NENT, !BIG>(d, c, lg, bp) : T(0);
   const auto wl = G(d.rs) - d.off;   // factors of the whole level
   acc += block_coupling<UCH>(
-      d, chunk, lg, [&](int col, int k) { return wl[col] * (T)b[((long long)col << lg) + k]; }, prod,
-      rsum);
+      d, chunk, lg, [&](int col, int k) { return (T)b[((long long)col << lg) + k]; }, prod, rsum,
+      [&](int col, int) { return wl[col]; });
   if (!valid) return;
   const T b0 = (T)bp[0];
   x[o] = wp[0] * b0;
@@ -939,7 +975,7 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
       const int c = e >> lg;
       const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
       const int cl = c - (int)d.off;
-      acc[e] = stencil_wb<T, T, kMaxEnt>(d, cl, lg, b + e);
+      acc[e] = stencil_wb<T, T, kMaxEnt, true>(d, cl, lg, b + e);
       x[e] = G(d.rs)[cl] * b[e];
     }
     __syncthreads();
@@ -994,7 +1030,7 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
     for (int e = tid; e < nel; e += TT) {
       const int c = e >> lg;
       const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
-      acc[e] = stencil_acc<T, kMaxEnt>(d, c - (int)d.off, lg, x + e);
+      acc[e] = stencil_acc<T, kMaxEnt, false, true>(d, c - (int)d.off, lg, x + e);
     }
     __syncthreads();
     tail_u<T, TT>(v, lg, x, prod, pl.prodcap, acc);
