@@ -829,29 +829,6 @@ __global__ __launch_bounds__(kBlock) void k_interp_add(const PartDesc<T> *__rest
 
 // ------------------------------------------------------------ coarse end
 
-// part descriptor j of the LDS-staged array (kTailDescBytes apart; only the
-// fields before the mirror tables are present)
-template <typename T>
-__device__ __forceinline__ const PartDesc<T> &tail_desc(const char *base, int j) {
-  return *reinterpret_cast<const PartDesc<T> *>(base + j * kTailDescBytes);
-}
-
-// part of a level holding cell c (offsets ascending; coarse: the parts' offsets
-// in the next level's vector), by bisection over the staged descriptors
-template <typename T>
-__device__ __forceinline__ int tail_part(const char *base, int np, long long c, bool coarse) {
-  int lo = 0, hi = np - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const PartDesc<T> &d = tail_desc<T>(base, mid);
-    if ((coarse ? d.coff : d.off) <= c)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 // dst[w] = src(w) for w < n (32-bit words), up to eight loads per thread in
 // flight (clamped indices, so that no load sits behind a branch)
 template <int TT, typename F>
@@ -868,19 +845,21 @@ __device__ __forceinline__ void stage_words(int *__restrict__ dst, int n, F src)
   }
 }
 
-// acc[slot] += (U x)(slot) for every (row, rhs) slot of a level, x in LDS: all
+// The U part of A x for every (row, rhs) slot of a level, x in LDS: all
 // threads form the products of a strided share of up to prodcap entries per
 // pass (loads of entries and of the thread's row ranges in flight together),
-// stage them in LDS, and each slot adds its row's products in entry order.
-// Rows x rhs <= kTailMax.  Ends with a workgroup barrier.
-template <typename T, int TT>
+// stage them in LDS, and each slot adds its row's products in entry order,
+// from zero, as block_coupling does.  fin(element, sum) then receives each
+// slot's sum.  Rows x rhs <= kTailMax.  Ends with a workgroup barrier.
+template <typename T, int TT, typename FIN>
 __device__ void tail_u(const TailLevel<T> &v, int lg, const T *__restrict__ x, T *__restrict__ prod,
-                       int prodcap, T *__restrict__ acc) {
+                       int prodcap, FIN fin) {
   if (v.nrow == 0) return;   // uniform
   constexpr int RPT = kTailMax / TT, EPT = kTailU / TT;
   const int tid = threadIdx.x, mask = (1 << lg) - 1;
   const int nslot = v.nrow << lg, nnz = v.nnz;
   int qa[RPT], qb[RPT], slot[RPT];
+  T racc[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int t = min(tid + j * TT, nslot - 1);
@@ -888,12 +867,13 @@ __device__ void tail_u(const TailLevel<T> &v, int lg, const T *__restrict__ x, T
     qa[j] = gload(v.uptr + r);
     qb[j] = gload(v.uptr + r + 1);
     slot[j] = (gload(v.urow + r) << lg) | (t & mask);
+    racc[j] = T(0);
   }
   const int per = prodcap >> lg;
   for (int ec = 0; ec < nnz; ec += per) {
     const int np = min(per, nnz - ec) << lg;
     int cc[EPT];
-    T vv[EPT];
+    T vv[EPT], xx[EPT];
 #pragma unroll
     for (int t = 0; t < EPT; ++t) {
       const int q = tid + t * TT;
@@ -902,44 +882,67 @@ __device__ void tail_u(const TailLevel<T> &v, int lg, const T *__restrict__ x, T
       vv[t] = gload(v.uval + qe);
     }
 #pragma unroll
+    for (int t = 0; t < EPT; ++t) xx[t] = x[(cc[t] << lg) | ((tid + t * TT) & mask)];
+#pragma unroll
     for (int t = 0; t < EPT; ++t) {
       const int q = tid + t * TT;
-      if (q < np) prod[q] = vv[t] * x[(cc[t] << lg) | (q & mask)];
+      if (q < np) prod[q] = vv[t] * xx[t];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const int t = tid + j * TT;
       const int a = max(qa[j], ec), b = min(qb[j], ec + (np >> lg));
-      if (t < nslot && a < b) acc[slot[j]] = row_sum(prod, a - ec, b - ec, lg, t & mask, acc[slot[j]]);
+      if (tid + j * TT < nslot && a < b) racc[j] = row_sum(prod, a - ec, b - ec, lg, (tid + j * TT) & mask, racc[j]);
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int j = 0; j < RPT; ++j)
+    if (tid + j * TT < nslot) fin(slot[j], racc[j]);
+  __syncthreads();
+}
+
+// sum_s ca[s][c] x(nb[s][c]) over the pack's stencil of element e (the order
+// and operations of stencil_acc: absent entries add 0)
+template <typename T>
+__device__ __forceinline__ T tail_stencil(const TailLevel<T> &v, int e, int lg, const T *__restrict__ x) {
+  const int c = e >> lg, k = e & ((1 << lg) - 1);
+  const int n = (int)v.ncell, nw = v.nw;
+  const auto nb = G(v.nb) + c;
+  const auto ca = G(v.ca) + c;
+  int id[kMaxEnt];
+  T a[kMaxEnt], xv[kMaxEnt];
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) {   // entries past nw read entry 0 and add 0
+    const int ss = s < nw ? s : 0;
+    id[s] = nb[ss * n];
+    a[s] = ca[ss * n];
+  }
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) xv[s] = x[(id[s] << lg) | k];
+  T acc = T(0);
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) acc = fma(s < nw ? a[s] : T(0), s < nw ? xv[s] : T(0), acc);
+  return acc;
 }
 
 // The coarse end of one V(1,1) cycle, levels tl[0] .. tl[pl.nl - 1] (the last
-// one the coarsest), in a single workgroup whose vectors and part descriptors
-// live in LDS: from tl[0].vb (global) into tl[0].vt (global).  The same
-// operations as the grid kernels, over all elements of a level at once (the
-// part of a cell found by bisection), one phase at a time with a workgroup
-// barrier between phases; the A x sums are formed in LDS (stencil part per
-// element, then the coupling rows added).  Every level above the coarsest
-// holds at most kTailMax elements.  TT threads: 1024 in FP32, 512 in FP64
-// (register room for the 27 coefficient and iterate loads a thread keeps in
-// flight).
+// one the coarsest), in a single workgroup whose vectors live in LDS: from
+// tl[0].vb (global) into tl[0].vt (global).  The same operations in the same
+// order as the grid kernels, over all elements of a level at once, one phase
+// at a time with a workgroup barrier between phases; the operands come from
+// the levels' packs.  Every level above the coarsest holds at most kTailMax
+// elements.  TT threads: 1024 in FP32, 512 in FP64.
 template <typename T, int TT>
 __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl, TailPlan pl, int lg) {
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, mask = (1 << lg) - 1;
-  const int nl = pl.nl, np = pl.np;
+  const int nl = pl.nl;
   const TailLevel<T> *L = reinterpret_cast<const TailLevel<T> *>(sm);
   int *voff = reinterpret_cast<int *>(sm + pl.off_tab);   // [nl]: b of level i at vec + voff[i]
-  const int **src = reinterpret_cast<const int **>(sm + pl.off_src);
-  const char *dsm = sm + pl.off_desc, *d64 = sm + pl.off_d64;
   T *vec = reinterpret_cast<T *>(sm + pl.off_vec);
   T *tv = reinterpret_cast<T *>(sm + pl.off_tv), *acc = reinterpret_cast<T *>(sm + pl.off_acc);
   T *prod = reinterpret_cast<T *>(sm + pl.off_prod);
-  // records, vector offsets and descriptor sources
   stage_words<TT>(reinterpret_cast<int *>(sm), nl * (int)(sizeof(TailLevel<T>) / 4),
                   [&](int w) { return gload(reinterpret_cast<const int *>(tl) + w); });
   __syncthreads();
@@ -947,47 +950,49 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
     int o = 0;
     for (int i = 0; i < tid; ++i) o += 2 * (int)(L[i].ncell << lg);
     voff[tid] = o;
-    for (int p = 0; p < np; ++p) src[tid * np + p] = reinterpret_cast<const int *>(L[tid].desc + p);
   }
-  const bool sweep = L[nl - 1].ndirect == 0;
-  if (sweep && tid < np) src[nl * np + tid] = reinterpret_cast<const int *>(L[nl - 1].desc64 + tid);
-  __syncthreads();
-  // descriptors (prefixes) and b of the first level
+  // b of the first level, and its first iterate x = w b (x follows b)
   {
-    constexpr int dw = kTailDescBytes / 4;
-    const int nd = (nl + (sweep ? 1 : 0)) * np;
-    // the FP64 descriptors follow the others directly (off_d64 = off_desc + nl np kTailDescBytes)
-    stage_words<TT>(reinterpret_cast<int *>(sm + pl.off_desc), nd * dw,
-                    [&](int w) { return gload(src[w / dw] + (w % dw)); });
-    const int nb = (int)(L[0].ncell << lg) * (int)(sizeof(T) / 4);
-    stage_words<TT>(reinterpret_cast<int *>(vec), nb,
-                    [&](int w) { return gload(reinterpret_cast<const int *>(L[0].vb) + w); });
+    const TailLevel<T> &v = L[0];
+    const int nel = (int)(v.ncell << lg);
+    const bool coarsest = nl == 1;
+    for (int e = tid; e < nel; e += TT) {
+      const T b = gload(v.vb + e);
+      vec[e] = b;
+      if (!coarsest) vec[nel + e] = gload(v.rs + (e >> lg)) * b;
+    }
   }
   __syncthreads();
-  // down: x = w b, t = b - A x, b_c = P^T t
+  // down: t = b - A x (x = w b), b_c = P^T t, x_c = w_c b_c
   for (int i = 0; i + 1 < nl; ++i) {
     const TailLevel<T> &v = L[i];
-    const char *ds = dsm + i * np * kTailDescBytes;
     const int nel = (int)(v.ncell << lg);
     const T *b = vec + voff[i];
-    T *x = vec + voff[i] + nel;
+    const T *x = b + nel;
     for (int e = tid; e < nel; e += TT) {
-      const int c = e >> lg;
-      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
-      const int cl = c - (int)d.off;
-      acc[e] = stencil_wb<T, T, kMaxEnt, true>(d, cl, lg, b + e);
-      x[e] = G(d.rs)[cl] * b[e];
+      const T a = tail_stencil(v, e, lg, x);
+      if (gload(v.rowof + (e >> lg)) < 0)
+        tv[e] = b[e] - a;
+      else
+        acc[e] = a;
     }
     __syncthreads();
-    tail_u<T, TT>(v, lg, x, prod, pl.prodcap, acc);
-    for (int e = tid; e < nel; e += TT) tv[e] = b[e] - acc[e];
-    __syncthreads();
-    const int ncel = (int)(L[i + 1].ncell << lg);
+    tail_u<T, TT>(v, lg, x, prod, pl.prodcap, [&](int e, T u) { tv[e] = b[e] - (acc[e] + u); });
+    const TailLevel<T> &w = L[i + 1];
+    const int ncel = (int)(w.ncell << lg), nc = (int)w.ncell;
     T *bc = vec + voff[i + 1];
+    const bool xnext = i + 2 < nl;   // the coarsest level needs no x
     for (int e = tid; e < ncel; e += TT) {
-      const int c = e >> lg;
-      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, true));
-      restrict_one(d, c - (int)d.coff, e & mask, lg, tv, bc);
+      const int cc = e >> lg, k = e & mask;
+      const auto ri = G(v.ri) + cc;
+      const auto rw = G(v.rw) + cc;
+      const int j0 = ri[0], j1 = ri[nc], j2 = ri[2 * nc];
+      const T u1 = rw[0], u2 = rw[nc];
+      T r = tv[(j0 << lg) | k];
+      r = fma(u1, tv[(j1 << lg) | k], r);
+      r = fma(u2, tv[(j2 << lg) | k], r);
+      bc[e] = r;
+      if (xnext) bc[ncel + e] = gload(w.rs + cc) * r;
     }
     __syncthreads();
   }
@@ -997,7 +1002,7 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
     const int nel = (int)(v.ncell << lg);
     const T *b = vec + voff[nl - 1];
     T *out = nl == 1 ? v.vt : tv;
-    if (!sweep) {
+    if (v.ndirect > 0) {
       for (int e = tid; e < nel; e += TT) {
         const int row = e >> lg, kr = e & mask;
         const auto ar = G(v.ainv) + (long long)row * v.ndirect;
@@ -1006,55 +1011,154 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
         out[e] = (T)a;
       }
     } else {
-      for (int e = tid; e < nel; e += TT) {
-        const int c = e >> lg;
-        const PartDesc<double> &d = tail_desc<double>(d64, tail_part<double>(d64, np, c, false));
-        out[e] = (T)(smooth_factor(d, c - d.off) * (double)b[e]);
-      }
+      for (int e = tid; e < nel; e += TT) out[e] = (T)(gload(v.rs64 + (e >> lg)) * (double)b[e]);
     }
     __syncthreads();
   }
   // up: x += P x_c, then x + w (b - A x) into tv (level 0: into tl[0].vt)
   for (int i = nl - 2; i >= 0; --i) {
     const TailLevel<T> &v = L[i];
-    const char *ds = dsm + i * np * kTailDescBytes;
-    const int nel = (int)(v.ncell << lg);
+    const int nel = (int)(v.ncell << lg), n = (int)v.ncell;
     const T *b = vec + voff[i];
     T *x = vec + voff[i] + nel;
     for (int e = tid; e < nel; e += TT) {
-      const int c = e >> lg;
-      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
-      interp_one(d, c - (int)d.off, e & mask, lg, tv, x);
+      const int c = e >> lg, k = e & mask;
+      const auto pi = G(v.pi) + c;
+      const auto pw = G(v.pw) + c;
+      const int i1 = pi[0], i2 = pi[n];
+      const T w1 = pw[0], w2 = pw[n];
+      T u = w1 * tv[(i1 << lg) | k];
+      u = fma(w2, tv[(i2 << lg) | k], u);
+      x[e] += u;
     }
     __syncthreads();
+    T *out = i == 0 ? v.vt : tv;
     for (int e = tid; e < nel; e += TT) {
+      const T a = tail_stencil(v, e, lg, x);
       const int c = e >> lg;
-      const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
-      acc[e] = stencil_acc<T, kMaxEnt, false, true>(d, c - (int)d.off, lg, x + e);
+      if (gload(v.rowof + c) < 0)
+        out[e] = x[e] + gload(v.rs + c) * (b[e] - a);
+      else
+        acc[e] = a;
     }
     __syncthreads();
-    tail_u<T, TT>(v, lg, x, prod, pl.prodcap, acc);
-    if (i == 0) {
-      const auto out = dev::Gw(v.vt);
-      for (int e = tid; e < nel; e += TT) {
-        const int c = e >> lg;
-        const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
-        out[e] = x[e] + G(d.rs)[c - (int)d.off] * (b[e] - acc[e]);
+    tail_u<T, TT>(v, lg, x, prod, pl.prodcap,
+                  [&](int e, T u) { out[e] = x[e] + gload(v.rs + (e >> lg)) * (b[e] - (acc[e] + u)); });
+  }
+}
+
+// Pack of the level records tl[blockIdx.y] (levels 1 .. of at most kTailMax
+// cells): one thread per cell of the level, and per cell of the next level
+// for the restriction, from the part descriptors as the grid kernels read them.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tail_pack(TailLevel<T> *__restrict__ tl) {
+  TailLevel<T> &v = tl[blockIdx.y];
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int n = (int)v.ncell, nc = (int)v.nnext;
+  auto part = [&](long long cell, bool coarse) {
+    int lo = 0, hi = v.np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((coarse ? v.desc[mid].coff : v.desc[mid].off) <= cell)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    return lo;
+  };
+  if (c < n) {
+    const PartDesc<T> &d = v.desc[part(c, false)];
+    const int cl = c - (int)d.off;
+    int i, j, k;
+    cell_ijk(cl, d.n[0], d.n[1], i, j, k);
+    const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
+    for (int s = 0; s < v.nw; ++s) {
+      const bool ok = s < d.nent && nb_ok(mx, my, mz, d.code[s]);
+      v.nb[(long long)s * n + c] = ok ? c + d.lin[s] : c;
+      v.ca[(long long)s * n + c] = ok ? d.coef[(long long)s * d.ncell + cl] : T(0);
+    }
+    // interpolation from the next level (interp_one's cases)
+    int i1 = 0, i2 = 0;
+    T w1 = T(0), w2 = T(0);
+    if (nc > 0) {
+      if (d.dstar < 0) {
+        i1 = i2 = (int)d.coff + cl;
+        w1 = T(1);
+      } else {
+        int f[3] = {i, j, k};
+        const int ds = d.dstar, id = f[ds];
+        int g[3] = {i, j, k};
+        if ((id & 1) == 0) {
+          g[ds] = id >> 1;
+          i1 = i2 = (int)d.coff + g[0] + d.cn[0] * (g[1] + d.cn[1] * g[2]);
+          w1 = T(1);
+        } else {
+          g[ds] = (id - 1) >> 1;
+          const int fl = g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2]);
+          const int cm = g[0] + d.cn[0] * (g[1] + d.cn[1] * g[2]);
+          i1 = i2 = (int)d.coff + cm;
+          w1 = d.wm[fl];
+          if (id + 1 <= d.n[ds] - 1) {
+            const int cstride = ds == 0 ? 1 : (ds == 1 ? d.cn[0] : d.cn[0] * d.cn[1]);
+            i2 = i1 + cstride;
+            w2 = d.wp[fl];
+          }
+        }
       }
+    }
+    v.pi[c] = i1;
+    v.pi[n + c] = i2;
+    v.pw[c] = w1;
+    v.pw[n + c] = w2;
+    int lo = 0, hi = v.nrow;   // row of U holding c (urow ascending)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (v.urow[mid] < c)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    v.rowof[c] = lo < v.nrow && v.urow[lo] == c ? lo : -1;
+  }
+  if (c < nc) {   // restriction into next-level cell c (restrict_one's cases)
+    const PartDesc<T> &d = v.desc[part(c, true)];
+    const int cc = c - (int)d.coff;
+    int j0, j1, j2;
+    T u1 = T(0), u2 = T(0);
+    if (d.dstar < 0) {
+      j0 = j1 = j2 = (int)d.off + cc;
     } else {
-      for (int e = tid; e < nel; e += TT) {
-        const int c = e >> lg;
-        const PartDesc<T> &d = tail_desc<T>(ds, tail_part<T>(ds, np, c, false));
-        tv[e] = x[e] + G(d.rs)[c - (int)d.off] * (b[e] - acc[e]);
+      int ci[3];
+      cell_ijk(cc, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
+      const int ds = d.dstar;
+      int fi[3] = {ci[0], ci[1], ci[2]};
+      fi[ds] = 2 * ci[ds];
+      const int f0 = fi[0] + d.n[0] * (fi[1] + d.n[1] * fi[2]);
+      const int stride = ds == 0 ? 1 : (ds == 1 ? d.n[0] : d.n[0] * d.n[1]);
+      j0 = j1 = j2 = (int)d.off + f0;
+      int g[3] = {ci[0], ci[1], ci[2]};
+      if (fi[ds] - 1 >= 0) {
+        g[ds] = ci[ds] - 1;
+        u1 = d.wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
+        j1 = j0 - stride;
+      }
+      if (fi[ds] + 1 <= d.n[ds] - 1) {
+        g[ds] = ci[ds];
+        u2 = d.wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])];
+        j2 = j0 + stride;
       }
     }
-    __syncthreads();
+    v.ri[c] = j0;
+    v.ri[nc + c] = j1;
+    v.ri[2 * nc + c] = j2;
+    v.rw[c] = u1;
+    v.rw[nc + c] = u2;
   }
 }
 
 // One coarsest level of any size with its vectors in global memory (the
-// hierarchy's only level, or a coarsest level whose vectors do not fit in
-// LDS): vt = (FP64 sweep from zero or A^{-1}) vb.
+// hierarchy's only level, or a coarsest level too large for the coarse-end
+// kernel): vt = (FP64 sweep from zero or A^{-1}) vb.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarsest(const TailLevel<T> *__restrict__ tl, int lg) {
   const TailLevel<T> &v = *tl;
@@ -1069,17 +1173,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const TailLevel<T> *__restr
     for (int j = 0; j < v.ndirect; ++j) a = fma(ar[j], (double)v.vb[((long long)j << lg) + kr], a);
     v.vt[e] = (T)a;
   } else {
-    const long long c = e >> lg;
-    int lo = 0, hi = v.np - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (v.desc64[mid].off <= c)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const PartDesc<double> &d = v.desc64[lo];
-    v.vt[e] = (T)(smooth_factor(d, c - d.off) * (double)v.vb[e]);
+    v.vt[e] = (T)(v.rs64[e >> lg] * (double)v.vb[e]);
   }
 }
 
@@ -1275,6 +1369,11 @@ void launch_coarsest(const TailLevel<T> *tl, int64_t nel, int lg, hipStream_t st
   k_coarsest<T><<<grid_cells(nel, 0), kBlock, 0, st>>>(tl, lg);
 }
 
+template <typename T>
+void launch_tail_pack(TailLevel<T> *tl, int nlev, int64_t maxcell, hipStream_t st) {
+  if (nlev > 0) k_tail_pack<T><<<dim3(grid_cells(maxcell, 0), nlev), kBlock, 0, st>>>(tl);
+}
+
 template void launch_stencil<double, double, double>(int, int, int, const PartDesc<double> *, int, int,
                                                      int, const double *, const double *, double *,
                                                      hipStream_t, LaunchEvents, int, double *, const double *, bool);
@@ -1308,5 +1407,7 @@ template void launch_tail<double>(const TailLevel<double> *, const TailPlan &, i
 template void launch_tail<float>(const TailLevel<float> *, const TailPlan &, int, hipStream_t);
 template void launch_coarsest<double>(const TailLevel<double> *, int64_t, int, hipStream_t);
 template void launch_coarsest<float>(const TailLevel<float> *, int64_t, int, hipStream_t);
+template void launch_tail_pack<double>(TailLevel<double> *, int, int64_t, hipStream_t);
+template void launch_tail_pack<float>(TailLevel<float> *, int, int64_t, hipStream_t);
 
 }  // namespace ssamg

@@ -681,6 +681,25 @@ void carve(Solver &s, Carver &cv) {
     V.d_uval32 = cyc32 ? cv.take<float>(nnz) : nullptr;
     V.d_rs64 = cv.take<double>((size_t)V.N);
     V.d_rs32 = cyc32 ? cv.take<float>((size_t)V.N) : nullptr;
+    if (l >= 1 && l < L - 1 && V.N <= kTailMax) {   // pack of the coarse-end kernel
+      const size_t n = (size_t)V.N, nc = (size_t)s.lv[l + 1].N, w = (size_t)V.maxent;
+      V.d_pk_nb = cv.take<int>(w * n);
+      V.d_pk_pi = cv.take<int>(2 * n);
+      V.d_pk_ri = cv.take<int>(3 * nc);
+      V.d_pk_row = cv.take<int>(n);
+      if (mixed) {
+        V.d_pk_ca = cv.take<float>(w * n);
+        V.d_pk_pw = cv.take<float>(2 * n);
+        V.d_pk_rw = cv.take<float>(2 * nc);
+      } else {
+        V.d_pk_ca = cv.take<double>(w * n);
+        V.d_pk_pw = cv.take<double>(2 * n);
+        V.d_pk_rw = cv.take<double>(2 * nc);
+      }
+    } else {
+      V.d_pk_nb = V.d_pk_pi = V.d_pk_ri = V.d_pk_row = nullptr;
+      V.d_pk_ca = V.d_pk_pw = V.d_pk_rw = nullptr;
+    }
     const size_t nv = (size_t)V.N * nr;
     if (mixed) {
       V.vb = cv.take<float>(nv);
@@ -759,16 +778,41 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     // the levels' TailLevel records sit one after another in the workspace
     // only if consecutive takes are adjacent; they are written per level and
     // the tail kernel walks them through this level's pointer
-    if (mixed) {
-      TailLevel<float> t{V.d_desc32, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
-                         V.d_ucol, V.d_uval32, (float *)V.vb, (float *)V.vx, (float *)V.vt,
-                         V.d_ainv, V.d_ainv ? (int)V.N : 0, (int)V.nnz};
-      put(V.d_tail, &t, sizeof(t));
-    } else {
-      TailLevel<double> t{V.d_desc64, V.d_desc64, (long long)V.N, (int)V.parts.size(), V.nrow, V.d_urow, V.d_uptr,
-                          V.d_ucol, V.d_uval64, (double *)V.vb, (double *)V.vx, (double *)V.vt,
-                         V.d_ainv, V.d_ainv ? (int)V.N : 0, (int)V.nnz};
-      put(V.d_tail, &t, sizeof(t));
+    {
+      auto rec = [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        TailLevel<T> t{};
+        t.desc = mixed ? (const PartDesc<T> *)V.d_desc32 : (const PartDesc<T> *)V.d_desc64;
+        t.ncell = V.N;
+        t.nnext = l + 1 < L ? s.lv[l + 1].N : 0;
+        t.np = (int)V.parts.size();
+        t.nrow = V.nrow;
+        t.nnz = (int)V.nnz;
+        t.nw = V.maxent;
+        t.urow = V.d_urow;
+        t.uptr = V.d_uptr;
+        t.ucol = V.d_ucol;
+        t.uval = mixed ? (const T *)V.d_uval32 : (const T *)V.d_uval64;
+        t.vb = (T *)V.vb;
+        t.vt = (T *)V.vt;
+        t.rs = mixed ? (const T *)V.d_rs32 : (const T *)V.d_rs64;
+        t.rs64 = V.d_rs64;
+        t.ainv = V.d_ainv;
+        t.ndirect = V.d_ainv ? (int)V.N : 0;
+        t.packed = V.d_pk_nb != nullptr;
+        t.nb = V.d_pk_nb;
+        t.ca = (T *)V.d_pk_ca;
+        t.pi = V.d_pk_pi;
+        t.pw = (T *)V.d_pk_pw;
+        t.ri = V.d_pk_ri;
+        t.rw = (T *)V.d_pk_rw;
+        t.rowof = V.d_pk_row;
+        put(V.d_tail, &t, sizeof(t));
+      };
+      if (mixed)
+        rec((float *)nullptr);
+      else
+        rec((double *)nullptr);
     }
   }
   if (!stage.empty())
@@ -808,6 +852,18 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     launch_uc_numeric(C.nnz, C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
     smoother_scale(l + 1);
+  }
+  // operator packs of the coarse-end kernel: levels l0 .. L-2 (consecutive
+  // records; level sizes do not grow, so the packed levels are a suffix)
+  {
+    int l0 = L - 1;
+    while (l0 - 1 >= 1 && s.lv[l0 - 1].d_pk_nb) --l0;
+    if (l0 < L - 1) {
+      if (mixed)
+        launch_tail_pack<float>((TailLevel<float> *)s.lv[l0].d_tail, L - 1 - l0, s.lv[l0].N, st);
+      else
+        launch_tail_pack<double>((TailLevel<double> *)s.lv[l0].d_tail, L - 1 - l0, s.lv[l0].N, st);
+    }
   }
   if (s.prm.coarse == SSAMG_COARSE_DIRECT) {
     Level &V = s.lv.back();
@@ -904,29 +960,22 @@ void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int l
 bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
   const int L = (int)s.lv.size();
   const size_t ts = s.prm.cycle_precision == SSAMG_FP32 ? sizeof(float) : sizeof(double);
-  const int np = (int)s.lv[0].parts.size();
-  const bool sweep = s.lv[L - 1].d_ainv == nullptr;
   auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  // every level above the coarsest needs its pack
+  for (int l = lt; l < L - 1; ++l)
+    if (!s.lv[l].d_pk_nb) return false;
   size_t nvec = 0, maxel = 1;
   for (int l = lt; l < L; ++l) {
     nvec += 2 * ((size_t)s.lv[l].N << lg);
-    if (l < L - 1) maxel = std::max(maxel, (size_t)s.lv[l].N << lg);
+    maxel = std::max(maxel, (size_t)s.lv[l].N << lg);
   }
   if (L - lt > 1 && maxel > (size_t)kTailMax) return false;
   pl = TailPlan{};
   pl.nl = L - lt;
-  pl.np = np;
-  pl.maxel = (int)maxel;
   pl.prodcap = kTailU;
-  size_t o = al(sizeof(TailLevel<double>) * pl.nl);
+  size_t o = al(std::max(sizeof(TailLevel<double>), sizeof(TailLevel<float>)) * pl.nl);
   pl.off_tab = (int)o;
   o = al(o + sizeof(int) * pl.nl);
-  pl.off_src = (int)o;
-  o = al(o + sizeof(void *) * (size_t)(pl.nl + 1) * np);
-  pl.off_desc = (int)o;
-  o += (size_t)kTailDescBytes * pl.nl * np;
-  pl.off_d64 = (int)o;
-  o = al(o + (sweep ? (size_t)kTailDescBytes * np : 0));
   pl.off_vec = (int)o;
   o = al(o + ts * nvec);
   pl.off_tv = (int)o;
@@ -936,6 +985,7 @@ bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
   pl.off_prod = (int)o;
   o = al(o + ts * kTailU);
   if (o > (size_t)kTailLds) return false;
+  pl.maxel = (int)maxel;
   pl.bytes = (int)o;
   return true;
 }

@@ -38,10 +38,11 @@ constexpr int kMaxLg = 5;        // log2(kMaxRhs)
 // The coarse end of the cycle runs in one workgroup of kTailThreads threads
 // (half of them in FP64): the coarsest level and the levels of at most
 // tail_elems elements (cells x right-hand sides; never more than kTailMax).
-// The levels' vectors and part descriptors live in LDS (at most kTailLds
-// bytes; fewer levels are taken when they do not fit), so each phase of the
-// kernel waits on one round of coefficient loads instead of a launch and a
-// chain of dependent loads.  kTailU coupling products are staged per pass.
+// The levels' vectors live in LDS (at most kTailLds bytes; fewer levels are
+// taken when they do not fit) and their operators are packed in level-wide
+// arrays, so each phase of the kernel waits on one round of coalesced loads
+// and LDS gathers instead of a launch and a chain of dependent loads.  kTailU
+// coupling products are staged per pass.
 constexpr int kTailThreads = 1024;
 constexpr int kTailMax = 4096;
 constexpr int kTailU = 2048;
@@ -127,12 +128,6 @@ struct PartDesc {
   int mir[kMaxEnt];
   int mlin[kMaxEnt];
 };
-
-// bytes of a part descriptor that the V-cycle reads (everything before the
-// mirror tables); the coarse-end kernel stages only these in LDS
-constexpr int kTailDescBytes = (int)offsetof(PartDesc<float>, mir);
-static_assert(kTailDescBytes == (int)offsetof(PartDesc<double>, mir), "descriptor prefix");
-static_assert(kTailDescBytes % 16 == 0, "descriptor prefix alignment");
 
 // ------------------------------------------------------------------ problem
 
@@ -253,6 +248,10 @@ struct Level {
   struct RapDesc *d_rapdesc = nullptr;
   double *d_ainv = nullptr;          // coarsest level, direct solve: dense inverse
   void *d_tail = nullptr;            // TailLevel<cycle precision> of this level
+  // operator pack of the coarse-end kernel (levels 1 .. L-2 of at most
+  // kTailMax cells; see TailLevel), cycle precision
+  int *d_pk_nb = nullptr, *d_pk_pi = nullptr, *d_pk_ri = nullptr, *d_pk_row = nullptr;
+  void *d_pk_ca = nullptr, *d_pk_pw = nullptr, *d_pk_rw = nullptr;
   // V-cycle vectors in the cycle precision: [N][max_nrhs]
   void *vb = nullptr, *vx = nullptr, *vt = nullptr;
   bool cycle32 = false;              // this level's cycle runs in FP32
@@ -333,28 +332,40 @@ struct BoxStencil {
 };
 
 // One level of the coarse end of the cycle run by the one-workgroup kernel.
+// Levels 1 .. of at most kTailMax cells also carry a pack of their operators
+// in level-wide arrays (written by k_tail_pack at numeric setup), so that the
+// kernel finds every operand from the cell index alone: the stencil as
+// (neighbour cell, coefficient) pairs, P and P^T as index and weight lists.
+// Absent entries point at the cell itself with weight 0, which leaves the
+// sums of the grid kernels unchanged.
 template <typename T>
 struct TailLevel {
-  const PartDesc<T> *desc;          // parts of the level (cycle precision)
-  const PartDesc<double> *desc64;   // FP64 parts (the coarsest level's sweep)
-  long long ncell;                  // cells of the level
-  int np, nrow;                     // parts, stored rows of U
+  const PartDesc<T> *desc;          // parts of the level (cycle precision; read by the pack kernel)
+  long long ncell, nnext;           // cells of the level and of the next one (0 for the coarsest)
+  int np, nrow, nnz, nw;            // parts, stored rows of U, entries of U, stencil width of the pack
   const int *urow, *uptr, *ucol;
   const T *uval;
-  T *vb, *vx, *vt;                  // right-hand side, iterate, output
+  T *vb, *vt;                       // right-hand side and output of the level (global)
+  const T *rs;                      // smoother factors (cycle precision; null on the coarsest)
+  const double *rs64;               // FP64 smoother factors (the coarsest level's sweep)
   const double *ainv;               // coarsest level, direct solve: A^{-1} (row-major), else null
-  int ndirect, nnz;                 // its order (0: one relaxation sweep); entries of U
+  int ndirect, packed;              // its order (0: one relaxation sweep); 1 if the pack below is set
+  int *nb;                          // [nw][ncell] neighbour cell of entry s (the cell itself if absent)
+  T *ca;                            // [nw][ncell] its coefficient (0 if absent)
+  int *pi;                          // [2][ncell] interpolation: the two next-level cells
+  T *pw;                            // [2][ncell] and their weights
+  int *ri;                          // [3][nnext] restriction: the three cells of this level
+  T *rw;                            // [2][nnext] and the weights of the second and third
+  int *rowof;                       // [ncell] row of U holding the cell, -1 if none
 };
 
 // Dynamic LDS layout of the coarse-end kernel for nl levels (byte offsets, 16
-// aligned): the TailLevel records, two int tables (vector offsets, first
-// descriptor), the descriptors' source pointers, the part descriptors of all
-// levels and the coarsest level's FP64 ones (kTailDescBytes each: the fields
-// before the mirror tables), the b and x vectors of every level, then a
-// scratch and a sum vector of maxel elements and prodcap coupling products.
+// aligned): the TailLevel records, the vector offset table, the b and x
+// vectors of every level, then a scratch and a sum vector of maxel elements
+// and prodcap coupling products.
 struct TailPlan {
-  int nl, np, maxel, prodcap;
-  int off_tab, off_src, off_desc, off_d64, off_vec, off_tv, off_acc, off_prod, bytes;
+  int nl, maxel, prodcap;
+  int off_tab, off_vec, off_tv, off_acc, off_prod, bytes;
 };
 
 // per-part Galerkin table of one level (device array indexed by part)
@@ -431,6 +442,9 @@ void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t
 // sweep from zero or the direct solve, vb into vt
 template <typename T>
 void launch_coarsest(const TailLevel<T> *tl, int64_t nel, int lg, hipStream_t st);
+// writes the packs of the nlev consecutive records tl[0 .. nlev) (maxcell: their largest level)
+template <typename T>
+void launch_tail_pack(TailLevel<T> *tl, int nlev, int64_t maxcell, hipStream_t st);
 // LDS layout of the coarse end from level lt at width 2^lg; false when it
 // exceeds kTailLds bytes
 bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl);
