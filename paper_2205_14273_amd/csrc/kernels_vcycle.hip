@@ -55,6 +55,8 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
   const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
   const auto cf = G(d.coef) + c;
+  const auto cfb = G(d.coef);
+  int co = c;   // LAT: offset of entry s
   T a[NENT], xv[NENT];
 #pragma unroll
   for (int s = 0; s < NENT; ++s) {
@@ -64,11 +66,17 @@ __device__ __forceinline__ T stencil_acc(const PartDesc<T> &d, int c, int lg, co
       a[s] = act ? cf[(long long)d.mir[s] * d.ncell + (ok ? d.mlin[s] : 0)] : T(0);
       xv[s] = ok ? xp[(long long)d.lin[s] << lg] : T(0);
     } else if constexpr (LAT) {
-      const bool ok = nb_ok(mx, my, mz, d.code[s]) & act;   // no short circuit: no branch
-      const T av = cf[act ? (long long)s * d.ncell : 0LL];
-      const T xq = xp[(long long)dev::opaque(ok ? d.lin[s] : 0) << lg];
-      a[s] = act ? av : T(0);
-      xv[s] = ok ? xq : T(0);
+      // 32-bit coefficient offsets stepped in a vector register, one packed
+      // scalar per entry, and absent values zeroed by a 0/1 factor rather than
+      // a select (27 lane masks would not fit the scalar registers): all loads
+      // stay in flight together.  Exact for finite values.
+      const int w = d.lc[s];
+      const bool ok = nb_ok(mx, my, mz, w & 63) & act;   // no short circuit: no branch
+      const T av = cfb[(unsigned)(act ? co : c)];
+      const T xq = xp[(long long)dev::opaque(ok ? (w >> 6) : 0) << lg];
+      a[s] = av * (act ? T(1) : T(0));
+      xv[s] = xq * (T)dev::opaque((int)ok);
+      co = dev::opaque(co + (int)d.ncell);
     } else {
       a[s] = act ? cf[(long long)s * d.ncell] : T(0);
       xv[s] = (act && nb_ok(mx, my, mz, d.code[s])) ? xp[(long long)d.lin[s] << lg] : T(0);
@@ -88,20 +96,24 @@ __device__ __forceinline__ T stencil_wb(const PartDesc<T> &d, int c, int lg, con
   cell_ijk(c, d.n[0], d.n[1], i, j, k);
   const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
   const auto cf = G(d.coef) + c;
+  const auto cfb = G(d.coef);
+  int co = c;   // LAT: offset of entry s
   const auto wp = G(d.rs) + c;
   T a[NENT], bv[NENT], wv[NENT];
 #pragma unroll
   for (int s = 0; s < NENT; ++s) {   // LAT: unconditional loads, as in stencil_acc
     const bool act = s < d.nent;
-    if constexpr (LAT) {
-      const bool ok = nb_ok(mx, my, mz, d.code[s]) & act;
-      const T av = cf[act ? (long long)s * d.ncell : 0LL];
-      const int ls = dev::opaque(ok ? d.lin[s] : 0);
+    if constexpr (LAT) {   // as in stencil_acc
+      const int w = d.lc[s];
+      const bool ok = nb_ok(mx, my, mz, w & 63) & act;
+      const T av = cfb[(unsigned)(act ? co : c)];
+      const int ls = dev::opaque(ok ? (w >> 6) : 0);
       const T bq = (T)bp[(long long)ls << lg];
       const T wq = wp[ls];
-      a[s] = act ? av : T(0);
-      bv[s] = ok ? bq : T(0);
-      wv[s] = ok ? wq : T(0);
+      a[s] = av * (act ? T(1) : T(0));
+      bv[s] = bq;
+      wv[s] = wq * (T)dev::opaque((int)ok);
+      co = dev::opaque(co + (int)d.ncell);
     } else {
       const bool ok = act && nb_ok(mx, my, mz, d.code[s]);
       a[s] = act ? cf[(long long)s * d.ncell] : T(0);

@@ -196,6 +196,7 @@ PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coe
     const auto &o = q.pat[e];
     d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
     d.code[e] = pack_off(o[0], o[1], o[2]);
+    d.lc[e] = d.lin[e] * 64 + d.code[e];
     d.mir[e] = (int)e;
     d.mlin[e] = 0;
   }

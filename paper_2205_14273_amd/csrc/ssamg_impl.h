@@ -127,6 +127,9 @@ struct PartDesc {
   // s, mlin[s] = 0.
   int mir[kMaxEnt];
   int mlin[kMaxEnt];
+  // lin[s] * 64 + code[s] (code < 64): the small-level sweeps read one scalar
+  // per entry, which keeps the 27-point tables within the scalar registers
+  int lc[kMaxEnt];
 };
 
 // ------------------------------------------------------------------ problem
