@@ -329,8 +329,161 @@ Solver::~Solver() {
 
 namespace {
 
-// Structure of every coarse coupling matrix (device: emit, sort, segment) and
-// the per-block row ranges the stencil kernels use, for all levels.
+// ---- host form of the coupling product, for the small coarse levels
+
+// nonzeros of row `cell` of P (coarse cells and weight sources: -1 = 1.0, else
+// an index into the level's weight buffer, wm block then wp block per part);
+// the same cases as the device emitter
+int host_prow(const SymPart *sp, int np, long long cell, int col[2], int src[2]) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sp[mid].off <= cell)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const SymPart &q = sp[lo];
+  const long long loc = cell - q.off;
+  if (q.dstar < 0) {
+    col[0] = (int)(q.coff + loc);
+    src[0] = -1;
+    return 1;
+  }
+  int f[3];
+  f[0] = (int)(loc % q.n[0]);
+  f[1] = (int)((loc / q.n[0]) % q.n[1]);
+  f[2] = (int)(loc / ((long long)q.n[0] * q.n[1]));
+  const int ds = q.dstar;
+  int c[3] = {f[0], f[1], f[2]};
+  if ((f[ds] & 1) == 0) {
+    c[ds] = f[ds] >> 1;
+    col[0] = (int)(q.coff + c[0] + (long long)q.cn[0] * (c[1] + (long long)q.cn[1] * c[2]));
+    src[0] = -1;
+    return 1;
+  }
+  int g[3] = {f[0], f[1], f[2]};
+  g[ds] = (f[ds] - 1) >> 1;
+  const long long fl = g[0] + (long long)q.fn[0] * (g[1] + (long long)q.fn[1] * g[2]);
+  c[ds] = (f[ds] - 1) >> 1;
+  col[0] = (int)(q.coff + c[0] + (long long)q.cn[0] * (c[1] + (long long)q.cn[1] * c[2]));
+  src[0] = (int)(q.wofs + fl);
+  if (f[ds] + 1 <= q.n[ds] - 1) {
+    c[ds] = (f[ds] + 1) >> 1;
+    col[1] = (int)(q.coff + c[0] + (long long)q.cn[0] * (c[1] + (long long)q.cn[1] * c[2]));
+    src[1] = (int)(q.wofs + q.nf + fl);
+    return 2;
+  }
+  return 1;
+}
+
+// Structure and recipe of U_{l+1} from U_l (entries with row cells erow and
+// columns ucol), as the device path forms them: every entry q emits a record
+// for each pair of its rows' P nonzeros, a stable sort by coarse pair keeps the
+// emission order within a pair, runs of equal pairs are the entries and runs
+// of equal rows the stored rows.
+struct HostCpl {
+  std::vector<int> urow, uptr, ucol, erow, start, ck, ca, cb;
+};
+
+void host_coarse_coupling(const SymPart *sp, int np, const std::vector<int> &erow,
+                          const std::vector<int> &ucol, int64_t nc, HostCpl &out) {
+  out = HostCpl{};
+  const size_t nnz = erow.size();
+  if (nnz == 0) return;
+  // the valid records in emission order (the device's invalid keys sort last
+  // and are never read)
+  std::vector<uint64_t> key, key2;
+  std::vector<uint32_t> idx, idx2;
+  std::vector<int> rk, ra, rb;
+  key.reserve(4 * nnz);
+  idx.reserve(4 * nnz);
+  rk.reserve(4 * nnz);
+  ra.reserve(4 * nnz);
+  rb.reserve(4 * nnz);
+  const uint64_t ncu = (uint64_t)nc;
+  uint64_t kmax = 0;
+  for (size_t q = 0; q < nnz; ++q) {
+    int cf[2], sf[2], cg[2], sg[2];
+    const int nf = host_prow(sp, np, erow[q], cf, sf);
+    const int ng = host_prow(sp, np, ucol[q], cg, sg);
+    for (int t = 0; t < 4; ++t) {
+      const int a = t >> 1, b = t & 1;
+      if (a < nf && b < ng) {
+        const uint64_t k = (uint64_t)cf[a] * ncu + (uint64_t)cg[b];
+        kmax = std::max(kmax, k);
+        idx.push_back((uint32_t)rk.size());
+        key.push_back(k);
+        rk.push_back((int)q);
+        ra.push_back(sf[a]);
+        rb.push_back(sg[b]);
+      }
+    }
+  }
+  const size_t nvalid = key.size();
+  if (nvalid == 0) return;
+  // stable LSD radix sort of (key, idx), eight bits a pass
+  key2.resize(nvalid);
+  idx2.resize(nvalid);
+  int bits = 1;
+  while (bits < 64 && (kmax >> bits) != 0) ++bits;
+  for (int shift = 0; shift < bits; shift += 8) {
+    size_t cnt[257] = {0};
+    for (size_t i = 0; i < nvalid; ++i) ++cnt[((key[i] >> shift) & 255) + 1];
+    for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
+    for (size_t i = 0; i < nvalid; ++i) {
+      const size_t at = cnt[(key[i] >> shift) & 255]++;
+      key2[at] = key[i];
+      idx2[at] = idx[i];
+    }
+    key.swap(key2);
+    idx.swap(idx2);
+  }
+  out.ck.resize(nvalid);
+  out.ca.resize(nvalid);
+  out.cb.resize(nvalid);
+  for (size_t i = 0; i < nvalid; ++i) {
+    const uint32_t r = idx[i];
+    out.ck[i] = rk[r];
+    out.ca[i] = ra[r];
+    out.cb[i] = rb[r];
+    const bool fnew = i == 0 || key[i] != key[i - 1];
+    const bool frow = i == 0 || key[i] / ncu != key[i - 1] / ncu;
+    if (fnew) {
+      out.ucol.push_back((int)(key[i] % ncu));
+      out.erow.push_back((int)(key[i] / ncu));
+      out.start.push_back((int)i);
+    }
+    if (frow) {
+      out.urow.push_back((int)(key[i] / ncu));
+      out.uptr.push_back((int)out.ucol.size() - 1);
+    }
+  }
+  out.start.push_back((int)nvalid);
+  out.uptr.push_back((int)out.ucol.size());
+}
+
+// host k_ublk: first stored row of every block of a grid-over-cells launch
+// (1 << lg rhs) and that row's first entry
+void host_ublk(const SymPart *sp, int np, int lg, const long long *boff, const std::vector<int> &urow,
+               const std::vector<int> &uptr, int *out) {
+  const int nrow = (int)urow.size();
+  for (int p = 0; p < np; ++p) {
+    const SymPart &q = sp[p];
+    const long long cpb = kBlock >> lg;
+    const long long nchunk = (q.ncell + cpb - 1) / cpb;
+    for (long long b = 0; b <= nchunk; ++b) {
+      const long long first = q.off + (b * cpb < q.ncell ? b * cpb : q.ncell);
+      const int lo = (int)(std::lower_bound(urow.begin(), urow.end(), (int)first) - urow.begin());
+      out[2 * (boff[p] + b)] = lo;
+      out[2 * (boff[p] + b) + 1] = nrow > 0 ? uptr[lo] : 0;
+    }
+  }
+}
+
+// Structure of every coarse coupling matrix (device: emit, sort, segment;
+// host for the small coarse levels) and the per-block row ranges the stencil
+// kernels use, for all levels.
 void symbolic_couplings(Solver &s, int lgmax) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
@@ -388,26 +541,95 @@ void symbolic_couplings(Solver &s, int lgmax) {
     launch_entry_rows(V0.nrow, V0.d_urow, V0.d_uptr, (int *)e0.p, st);
     V0.d_erow = (int *)e0.p;
   }
-  for (int l = 0; l + 1 < L; ++l) {
-    Level &V = s.lv[l], &C = s.lv[l + 1];
-    CouplingStore &cs = s.store[l + 1]->cpl;
-    int64_t nnz = 0;
-    int nrow = 0;
-    coarse_coupling_device(s.scratch, d_sp + sp_at[l], np, V.nnz, V.d_erow, V.d_ucol, C.N, cs, nnz, nrow,
-                           st);
-    C.nnz = nnz;
-    C.nrow = nrow;
-    C.ncontrib = nnz ? cs.ncontrib : 0;
-    C.d_urow = nnz ? (int *)cs.urow.p : nullptr;
-    C.d_uptr = nnz ? (int *)cs.uptr.p : nullptr;
-    C.d_ucol = nnz ? (int *)cs.ucol.p : nullptr;
-    C.d_erow = nnz ? (int *)cs.erow.p : nullptr;
-    C.d_uc_start = nnz ? (int *)cs.start.p : nullptr;
-    C.d_uc_k = nnz ? (int *)cs.ck.p : nullptr;
-    C.d_uc_a = nnz ? (int *)cs.ca.p : nullptr;
-    C.d_uc_b = nnz ? (int *)cs.cb.p : nullptr;
+  // levels from lh on are formed on the host (their inputs shrink below
+  // host_sym records); lh = L: none
+  int lh = L;
+  std::vector<HostCpl> hc(L);
+  {
+    std::vector<int> h_erow, h_ucol;
+    for (int l = 0; l + 1 < L; ++l) {
+      Level &V = s.lv[l], &C = s.lv[l + 1];
+      if (lh == L && 4 * V.nnz <= s.host_sym) {
+        lh = l + 1;
+        h_erow.resize((size_t)V.nnz);
+        h_ucol.resize((size_t)V.nnz);
+        if (V.nnz > 0) {
+          SSAMG_HIP(hipMemcpyAsync(h_erow.data(), V.d_erow, (size_t)V.nnz * sizeof(int), hipMemcpyDeviceToHost, st));
+          SSAMG_HIP(hipMemcpyAsync(h_ucol.data(), V.d_ucol, (size_t)V.nnz * sizeof(int), hipMemcpyDeviceToHost, st));
+          SSAMG_HIP(hipStreamSynchronize(st));
+        }
+      }
+      if (lh <= l + 1) {
+        HostCpl &o = hc[l + 1];
+        host_coarse_coupling(sp.data() + sp_at[l], np, h_erow, h_ucol, C.N, o);
+        C.nnz = (int64_t)o.ucol.size();
+        C.nrow = (int)o.urow.size();
+        C.ncontrib = (int64_t)o.ck.size();
+        h_erow = o.erow;
+        h_ucol = o.ucol;
+        continue;
+      }
+      CouplingStore &cs = s.store[l + 1]->cpl;
+      int64_t nnz = 0;
+      int nrow = 0;
+      coarse_coupling_device(s.scratch, d_sp + sp_at[l], np, V.nnz, V.d_erow, V.d_ucol, C.N, cs, nnz, nrow,
+                             st);
+      C.nnz = nnz;
+      C.nrow = nrow;
+      C.ncontrib = nnz ? cs.ncontrib : 0;
+      C.d_urow = nnz ? (int *)cs.urow.p : nullptr;
+      C.d_uptr = nnz ? (int *)cs.uptr.p : nullptr;
+      C.d_ucol = nnz ? (int *)cs.ucol.p : nullptr;
+      C.d_erow = nnz ? (int *)cs.erow.p : nullptr;
+      C.d_uc_start = nnz ? (int *)cs.start.p : nullptr;
+      C.d_uc_k = nnz ? (int *)cs.ck.p : nullptr;
+      C.d_uc_a = nnz ? (int *)cs.ca.p : nullptr;
+      C.d_uc_b = nnz ? (int *)cs.cb.p : nullptr;
+    }
   }
-  for (int l = 0; l < L; ++l) {
+  // host-formed levels: arrays and block tables in one buffer, one copy
+  if (lh < L) {
+    std::vector<int> stage;
+    struct Ofs { size_t a[8]; size_t ub[kMaxLg + 1]; };
+    std::vector<Ofs> ofs(L);
+    for (int l = lh; l < L; ++l) {
+      HostCpl &o = hc[l];
+      const std::vector<int> *arr[8] = {&o.urow, &o.uptr, &o.ucol, &o.erow, &o.start, &o.ck, &o.ca, &o.cb};
+      for (int k = 0; k < 8; ++k) {
+        ofs[l].a[k] = stage.size();
+        stage.insert(stage.end(), arr[k]->begin(), arr[k]->end());
+        stage.resize((stage.size() + 63) & ~size_t(63));   // 256-byte aligned pieces
+      }
+      for (int lg = 0; lg <= kMaxLg; ++lg) {
+        ofs[l].ub[lg] = stage.size();
+        if (lg > lgmax) continue;
+        std::vector<int> ub((size_t)s.lv[l].ublk_len[lg] * 2);
+        host_ublk(sp.data() + sp_at[l], np, lg, boff.data() + boff_at[l * (kMaxLg + 1) + lg], o.urow, o.uptr,
+                  ub.data());
+        stage.insert(stage.end(), ub.begin(), ub.end());
+        stage.resize((stage.size() + 63) & ~size_t(63));
+      }
+    }
+    s.host_cpl.reserve(stage.size() * sizeof(int) + 256);
+    int *base = (int *)s.host_cpl.p;
+    SSAMG_HIP(hipMemcpyAsync(base, stage.data(), stage.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    for (int l = lh; l < L; ++l) {
+      Level &C = s.lv[l];
+      const bool any = C.nnz > 0;
+      C.d_urow = any ? base + ofs[l].a[0] : nullptr;
+      C.d_uptr = any ? base + ofs[l].a[1] : nullptr;
+      C.d_ucol = any ? base + ofs[l].a[2] : nullptr;
+      C.d_erow = any ? base + ofs[l].a[3] : nullptr;
+      C.d_uc_start = any ? base + ofs[l].a[4] : nullptr;
+      C.d_uc_k = any ? base + ofs[l].a[5] : nullptr;
+      C.d_uc_a = any ? base + ofs[l].a[6] : nullptr;
+      C.d_uc_b = any ? base + ofs[l].a[7] : nullptr;
+      for (int lg = 0; lg <= kMaxLg; ++lg) C.d_ublk[lg] = lg <= lgmax ? base + ofs[l].ub[lg] : nullptr;
+    }
+    // the host vectors must outlive the asynchronous copy
+    SSAMG_HIP(hipStreamSynchronize(st));
+  }
+  for (int l = 0; l < lh; ++l) {
     Level &V = s.lv[l];
     int64_t maxchunk = 0;
     for (auto &q : V.parts) maxchunk = std::max<int64_t>(maxchunk, q.ncell);

@@ -48,6 +48,11 @@ constexpr int kTailMax = 4096;
 constexpr int kTailU = 2048;
 constexpr int64_t kTailElems = 1024;
 constexpr int kTailLds = 65536;
+// coarse coupling structures whose product emits at most this many records
+// (four per fine entry) are formed on the host: below it a handful of
+// microseconds of host work beats the ten launches and the synchronisation
+// of the device sort
+constexpr int64_t kHostSymRecords = 16384;
 // levels with more than 15-point stencils and at least this many cells run the
 // first smoothing sweep and the residual as two kernels instead of one
 constexpr int64_t kSplitCells = 1 << 20;
@@ -268,6 +273,8 @@ struct Solver {
   bool verbose = false;              // SSAMG_VERBOSE: phase timings on stderr
   int64_t tail_elems = kTailElems;   // SSAMG_TAIL_ELEMS overrides
   int64_t split_cells = kSplitCells; // SSAMG_SPLIT_CELLS overrides
+  int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
+  DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
   std::vector<Level> lv;
   std::vector<double> cd;            // direction sums c[p][d]

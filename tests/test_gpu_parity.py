@@ -271,6 +271,28 @@ def test_tail_kernel_matches_grid_kernels(monkeypatch, precision):
     assert np.linalg.norm(X1 - X0) <= 1e-6 * np.linalg.norm(X0)
 
 
+@pytest.mark.parametrize("name", ["c2_12", "c3_8"])
+def test_host_formed_couplings_match_device(monkeypatch, name):
+    """The coupling products of the small coarse levels are formed on the host
+    (SSAMG_HOST_SYM records and below): with every level on the device, every
+    level on the host and the default split, the hierarchies match the oracle
+    and the cycles are bitwise equal."""
+    _print_case(f"host couplings {name}")
+    case = {"c2_12": lambda: W.c2(12), "c3_8": lambda: W.c3(8)}[name]()
+    h = oracle_fv(case)
+    r = _cuda(np.random.default_rng(21).uniform(-1, 1, h.levels[0].n))
+    out = []
+    for hs in ("0", str(1 << 40), None):
+        if hs is None:
+            monkeypatch.delenv("SSAMG_HOST_SYM", raising=False)
+        else:
+            monkeypatch.setenv("SSAMG_HOST_SYM", hs)
+        _, s = gpu_fv(case)
+        compare_hierarchy(h, s, len(case.geometry.dims))
+        out.append(s.apply_precond(r).cpu())
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_split_down_sweep_matches_fused(monkeypatch, precision):
     """On large 27-point levels the first sweep and the residual run as two
