@@ -247,6 +247,97 @@ __device__ __forceinline__ T block_coupling(const PartDesc<T> &d, int chunk, int
   return rsum[tid];
 }
 
+// The block's coupling range, its rows' entry ranges and output slots, and the
+// first kUPre entry loads of every thread, issued before the stencil in the
+// small-level sweeps so that their chain of loads runs beside the stencil's
+// (block_coupling waits on each link after the stencil has finished).
+constexpr int kUPre = 4;
+template <typename T>
+struct UPre {
+  int u0, e0, u1, e1, rq0, rq1, rslot;
+  int cc[kUPre];
+  T vv[kUPre];
+};
+
+template <typename T>
+__device__ __forceinline__ void upre_load(const PartDesc<T> &d, int chunk, int lg, UPre<T> &u) {
+  const auto ub = G(d.ublk[lg]) + 2 * chunk;
+  u.u0 = ub[0];
+  u.e0 = ub[1];
+  u.u1 = ub[2];
+  u.e1 = ub[3];
+  u.rq0 = u.rq1 = u.rslot = 0;
+  if (u.u0 == u.u1) return;   // block-uniform
+  const int tid = threadIdx.x, mask = (1 << lg) - 1;
+  const int cell0 = (int)d.off + chunk * (kBlock >> lg);
+  // clamped, unconditional loads (slots and entries past the block's are masked later)
+  const int r = u.u0 + min(tid >> lg, u.u1 - u.u0 - 1);
+  u.rq0 = G(d.uptr)[r];
+  u.rq1 = G(d.uptr)[r + 1];
+  u.rslot = ((G(d.urow)[r] - cell0) << lg) | (tid & mask);
+#pragma unroll
+  for (int t = 0; t < kUPre; ++t) {
+    const int qe = u.e0 + min((tid + t * kBlock) >> lg, u.e1 - u.e0 - 1);
+    u.cc[t] = gload(d.ucol + qe);
+    u.vv[t] = gload(d.uval + qe);
+  }
+}
+
+// block_coupling from the prefetched state (the same sums, in the same order)
+template <int UCH, typename T, typename XS, typename XW = std::nullptr_t>
+__device__ __forceinline__ T upre_apply(const PartDesc<T> &d, int lg, const UPre<T> &u, XS xs,
+                                        T *__restrict__ prod, T *__restrict__ rsum, XW xw = nullptr) {
+  constexpr bool WB = !std::is_same<XW, std::nullptr_t>::value;
+  static_assert(UCH / kBlock >= kUPre, "prefetch within the first pass");
+  if (u.u0 == u.u1) return T(0);                      // block-uniform
+  const int tid = threadIdx.x;
+  const int mask = (1 << lg) - 1;
+  const int nrt = (u.u1 - u.u0) << lg;
+  rsum[tid] = T(0);
+  T racc = T(0);
+  const int per = UCH >> lg;
+  for (int ec = u.e0; ec < u.e1; ec += per) {
+    const int np = min(per, u.e1 - ec) << lg;
+    int cc[UCH / kBlock];
+    T vv[UCH / kBlock], xx[UCH / kBlock], ww[UCH / kBlock];
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      if (t < kUPre && ec == u.e0) {   // block-uniform: the prefetched entries
+        cc[t] = u.cc[t];
+        vv[t] = u.vv[t];
+      } else {
+        const int qe = ec + (q < np ? (q >> lg) : 0);
+        cc[t] = gload(d.ucol + qe);
+        vv[t] = gload(d.uval + qe);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      xx[t] = ww[t] = T(0);
+      if (t * kBlock < np) {
+        const int k = (tid + t * kBlock) & mask;
+        xx[t] = xs(cc[t], k);
+        if constexpr (WB) ww[t] = xw(cc[t], k);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < UCH / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      if (q < np) prod[q] = vv[t] * (WB ? ww[t] * xx[t] : xx[t]);
+    }
+    __syncthreads();
+    if (tid < nrt) {
+      const int qa = max(u.rq0, ec), qb = min(u.rq1, ec + (np >> lg));
+      racc = row_sum(prod, qa - ec, qb - ec, lg, tid & mask, racc);
+    }
+    __syncthreads();
+  }
+  if (tid < nrt) rsum[u.rslot] = racc;
+  __syncthreads();
+  return rsum[tid];
+}
+
 // b_c = P^T r for coarse cell cc: r(2I) + wp(2I-1) r(2I-1) + wm(2I+1) r(2I+1)
 template <typename T>
 __device__ __forceinline__ void restrict_one(const PartDesc<T> &d, int cc, int kr, int lg,
@@ -363,9 +454,29 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   const int kr = (int)(e & ((1 << lg) - 1));
   const long long o = ((d.off + c) << lg) + kr;
   const T *xp = x + o;
-  T acc = valid ? stencil_acc<T, NENT, MIR, !BIG>(d, c, lg, xp) : T(0);
-  acc += block_coupling<UCH>(
-      d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
+  T acc;
+  TB bo = TB(0);
+  T wo = T(0);
+  if constexpr (!BIG && (MODE == MODE_RESID || MODE == MODE_JACOBI)) {
+    // small levels: every load the sweep needs is requested before the
+    // stencil is summed (the coupling chain, b and the factor included)
+    UPre<T> u;
+    upre_load(d, chunk, lg, u);
+    bo = b[o];
+    if (MODE == MODE_JACOBI) wo = smooth_factor(d, c);
+    acc = stencil_acc<T, NENT, MIR, true>(d, c, lg, xp);
+    if (!valid) acc = T(0);
+    acc += upre_apply<UCH>(
+        d, lg, u, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
+  } else {
+    acc = valid ? stencil_acc<T, NENT, MIR, !BIG>(d, c, lg, xp) : T(0);
+    acc += block_coupling<UCH>(
+        d, chunk, lg, [&](int col, int k) { return x[((long long)col << lg) + k]; }, prod, rsum);
+    if (valid && (MODE == MODE_RESID || MODE == MODE_JACOBI)) {
+      bo = b[o];
+      if (MODE == MODE_JACOBI) wo = smooth_factor(d, c);
+    }
+  }
   if constexpr (MODE == MODE_APPLY_DOT) {
     if (valid) y[o] = (TO)acc;
     block_dot((double *)rsum, valid ? (double)xp[0] * (double)acc : 0.0, lg, dslot);
@@ -389,9 +500,9 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const PartDesc<T> *__restric
   if (MODE == MODE_APPLY) {
     y[o] = (TO)acc;
   } else if (MODE == MODE_RESID) {
-    y[o] = (TO)((T)b[o] - acc);
+    y[o] = (TO)((T)bo - acc);
   } else {
-    y[o] = (TO)(xp[0] + smooth_factor(d, c) * ((T)b[o] - acc));
+    y[o] = (TO)(xp[0] + wo * ((T)bo - acc));
   }
 }
 
@@ -416,14 +527,29 @@ __global__ __launch_bounds__(kBlock) void k_smooth_resid(const PartDesc<T> *__re
   const long long o = ((d.off + c) << lg) + kr;
   const TB *bp = b + o;
   const auto wp = G(d.rs) + c;
-  T acc = valid ? stencil_wb<T, TB, NENT, !BIG>(d, c, lg, bp) : T(0);
   const auto wl = G(d.rs) - d.off;   // factors of the whole level
-  acc += block_coupling<UCH>(
-      d, chunk, lg, [&](int col, int k) { return (T)b[((long long)col << lg) + k]; }, prod, rsum,
-      [&](int col, int) { return wl[col]; });
+  T acc, b0, w0;
+  if constexpr (!BIG) {   // small levels: all loads requested before the stencil is summed
+    UPre<T> u;
+    upre_load(d, chunk, lg, u);
+    b0 = (T)bp[0];
+    w0 = wp[0];
+    acc = stencil_wb<T, TB, NENT, true>(d, c, lg, bp);
+    if (!valid) acc = T(0);
+    acc += upre_apply<UCH>(
+        d, lg, u, [&](int col, int k) { return (T)b[((long long)col << lg) + k]; }, prod, rsum,
+        [&](int col, int) { return wl[col]; });
+  } else {
+    acc = valid ? stencil_wb<T, TB, NENT, false>(d, c, lg, bp) : T(0);
+    acc += block_coupling<UCH>(
+        d, chunk, lg, [&](int col, int k) { return (T)b[((long long)col << lg) + k]; }, prod, rsum,
+        [&](int col, int) { return wl[col]; });
+    if (!valid) return;
+    b0 = (T)bp[0];
+    w0 = wp[0];
+  }
   if (!valid) return;
-  const T b0 = (T)bp[0];
-  x[o] = wp[0] * b0;
+  x[o] = w0 * b0;
   r[o] = b0 - acc;
 }
 
