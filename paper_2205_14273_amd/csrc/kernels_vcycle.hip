@@ -156,7 +156,7 @@ __device__ __forceinline__ T coupling_row(const int *__restrict__ uptr, const in
 // across mismatched part interfaces; few blocks, so fewer passes matter)
 constexpr int kUChunkBig = 1024;
 constexpr int kUChunkSmall = 4096;
-constexpr long long kBigLevel = 1 << 18;   // cells from which a level counts as large
+constexpr long long kBigLevel = 1 << 18;   // elements (cells x rhs) from which a level counts as large
 
 // acc + prod[q0] + ... + prod[q1 - 1] (slot kr of each entry), added in entry
 // order; the LDS reads are issued eight at a time so that long rows do not
@@ -1423,7 +1423,7 @@ void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int
     throw Error(SSAMG_ERR_STATE, "internal: the fused sweep dots need the finest level and a partial buffer");
   dim3 grid(grid_cells(maxcell, lg), nparts);
   const bool c4 = cols4 != 0 && stencil_cols4_ok<T>(lg, maxent);
-  if (fine || (long long)maxcell * nparts >= kBigLevel) {
+  if (fine || (((long long)maxcell * nparts) << lg) >= kBigLevel) {
     if (maxent <= 7)
       stencil_mode<T, TB, TO, 1, 7>(mode, grid, desc, lg, x, b, y, st, ev, c4, dotp, aux, mir);
     else if (maxent <= 15)
@@ -1479,7 +1479,7 @@ void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int npar
                          const TB *b, T *x, T *r, hipStream_t st, LaunchEvents ev) {
   dim3 grid(grid_cells(maxcell, lg), nparts);
 #define SSAMG_SR(F, N) dispatch(k_smooth_resid<T, TB, F, N>, grid, st, ev, desc, lg, b, x, r)
-  if (fine || (long long)maxcell * nparts >= kBigLevel) {
+  if (fine || (((long long)maxcell * nparts) << lg) >= kBigLevel) {
     if (maxent <= 7) SSAMG_SR(1, 7);
     else if (maxent <= 15) SSAMG_SR(1, 15);
     else SSAMG_SR(1, 27);
