@@ -1210,10 +1210,21 @@ __global__ __launch_bounds__(kBlock) void k_tail_pack(TailLevel<T> *__restrict__
     int i, j, k;
     cell_ijk(cl, d.n[0], d.n[1], i, j, k);
     const unsigned mx = nb_mask(i, d.n[0]), my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
-    for (int s = 0; s < v.nw; ++s) {
-      const bool ok = s < d.nent && nb_ok(mx, my, mz, d.code[s]);
-      v.nb[(long long)s * n + c] = ok ? c + d.lin[s] : c;
-      v.ca[(long long)s * n + c] = ok ? d.coef[(long long)s * d.ncell + cl] : T(0);
+    // all table and coefficient loads first (clamped to entry 0), then the stores
+    int lcv[kMaxEnt];
+    T cv[kMaxEnt];
+#pragma unroll
+    for (int s = 0; s < kMaxEnt; ++s) {
+      const int ss = s < d.nent ? s : 0;
+      lcv[s] = d.lc[ss];
+      cv[s] = d.coef[(long long)ss * d.ncell + cl];
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxEnt; ++s) {
+      if (s >= v.nw) break;
+      const bool ok = s < d.nent && nb_ok(mx, my, mz, lcv[s] & 63);
+      v.nb[(long long)s * n + c] = ok ? c + (lcv[s] >> 6) : c;
+      v.ca[(long long)s * n + c] = ok ? cv[s] : T(0);
     }
     // interpolation from the next level (interp_one's cases)
     int i1 = 0, i2 = 0;

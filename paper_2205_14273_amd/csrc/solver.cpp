@@ -1216,14 +1216,16 @@ bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
 namespace {
 
 // first level handled by the one-workgroup coarse-end kernel: the first level
-// >= 1 with at most tail_elems (<= kTailMax) elements whose coarse end fits in
+// >= 1 with at most tail_elems (<= kTailMax; by default kTailElems, or
+// kTailElemsBatched for four or more right-hand sides) elements whose coarse end fits in
 // LDS; the coarsest level always is (when it alone does not fit, it runs as a
 // grid kernel on global vectors)
 int tail_start(const Solver &s, int lg) {
   const int L = (int)s.lv.size();
   TailPlan pl;
+  const int64_t lim = s.tail_elems >= 0 ? s.tail_elems : (lg >= 2 ? kTailElemsBatched : kTailElems);
   for (int l = 1; l < L; ++l)
-    if ((s.lv[l].N << lg) <= s.tail_elems && tail_plan(s, l, lg, pl)) return l;
+    if ((s.lv[l].N << lg) <= lim && tail_plan(s, l, lg, pl)) return l;
   return L - 1;
 }
 

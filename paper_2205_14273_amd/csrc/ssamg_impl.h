@@ -46,7 +46,8 @@ constexpr int kMaxLg = 5;        // log2(kMaxRhs)
 constexpr int kTailThreads = 1024;
 constexpr int kTailMax = 4096;
 constexpr int kTailU = 2048;
-constexpr int64_t kTailElems = 1024;
+constexpr int64_t kTailElems = 1024;          // one or two right-hand sides
+constexpr int64_t kTailElemsBatched = 2048;   // four or more (measured on 2 x 96^3, 32 rhs)
 constexpr int kTailLds = 65536;
 // coarse coupling structures whose product emits at most this many records
 // (four per fine entry) are formed on the host: below it a handful of
@@ -271,7 +272,7 @@ struct Solver {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool verbose = false;              // SSAMG_VERBOSE: phase timings on stderr
-  int64_t tail_elems = kTailElems;   // SSAMG_TAIL_ELEMS overrides
+  int64_t tail_elems = -1;           // SSAMG_TAIL_ELEMS overrides (-1: kTailElems / kTailElemsBatched)
   int64_t split_cells = kSplitCells; // SSAMG_SPLIT_CELLS overrides
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
