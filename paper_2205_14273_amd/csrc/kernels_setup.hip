@@ -110,9 +110,16 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
   int f[3] = {g[0], g[1], g[2]};
   f[ds] = 2 * g[ds] + 1;
   const long long c = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
+  // all coefficient loads first (entries past nent read entry 0 and are
+  // skipped), then the sums in entry order
+  double cv[kMaxEnt];
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) cv[s] = dev::G(d.coef)[(long long)(s < d.nent ? s : 0) * d.ncell + c];
   double den = 0.0, sm = 0.0, sp = 0.0;
-  for (int s = 0; s < d.nent; ++s) {
-    const double v = dev::G(d.coef)[(long long)s * d.ncell + c];
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) {
+    if (s >= d.nent) break;
+    const double v = cv[s];
     const int o = off_comp(d.code[s], ds);
     if (o == 0)
       den += v;
@@ -442,10 +449,29 @@ __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int 
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= nnz) return;
   double acc = 0.0;
-  for (int q = start[e]; q < start[e + 1]; ++q) {
-    const double wa = ia[q] < 0 ? 1.0 : w[ia[q]];
-    const double wb = ib[q] < 0 ? 1.0 : w[ib[q]];
-    acc = fma(wa * uprev[kk[q]], wb, acc);
+  const int q0 = start[e], q1 = start[e + 1];
+  // four contributions at a time, every load issued before the sums (clamped
+  // indices, masked afterwards), added in contribution order
+  for (int q = q0; q < q1; q += 4) {
+    int a[4], b[4], k[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int qq = min(q + t, q1 - 1);
+      a[t] = ia[qq];
+      b[t] = ib[qq];
+      k[t] = kk[qq];
+    }
+    double wa[4], wb[4], u[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double va = w[max(a[t], 0)], vb = w[max(b[t], 0)];
+      wa[t] = a[t] < 0 ? 1.0 : va;
+      wb[t] = b[t] < 0 ? 1.0 : vb;
+      u[t] = uprev[k[t]];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (q + t < q1) acc = fma(wa[t] * u[t], wb[t], acc);
   }
   uval[e] = acc;
   if (uval32) uval32[e] = (float)acc;
@@ -463,11 +489,15 @@ __global__ __launch_bounds__(kBlock) void k_l1_cells(const PartDesc<double> *__r
   if (c >= d.ncell) return;
   const auto cf = dev::G(d.coef);
   const auto c32 = desc32 ? dev::Gw(const_cast<float *>(desc32[blockIdx.y].coef)) : nullptr;
+  double cv[kMaxEnt];   // all loads first, as in k_interp_weights
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) cv[s] = cf[(long long)(s < d.nent ? s : 0) * d.ncell + c];
   double acc = 0.0;
-  for (int s = 0; s < d.nent; ++s) {
-    const double v = cf[(long long)s * d.ncell + c];
-    acc += fabs(v);
-    if (desc32) c32[(long long)s * d.ncell + c] = (float)v;
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) {
+    if (s >= d.nent) break;
+    acc += fabs(cv[s]);
+    if (desc32) c32[(long long)s * d.ncell + c] = (float)cv[s];
   }
   l1[d.off + c] = acc;
 }
