@@ -322,6 +322,7 @@ Solver::~Solver() {
   if (ws_owned && ws) (void)hipFree(ws);
   if (h_pin) (void)hipHostFree(h_pin);
   for (auto e : pev) (void)hipEventDestroy(e);
+  if (ev_scal) (void)hipEventDestroy(ev_scal);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -1630,30 +1631,8 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   }
   const double tol = s.prm.tol;
   bool pending_x = false;            // x += alpha p of the last iteration not yet applied
-  for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
-    apply_A0(s, lg, s.p, s.q, S_PQ);        // p.q formed by the product itself
-    launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st);
-    pending_x = true;
-    SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    SSAMG_HIP(hipStreamSynchronize(st));
-    bool changed = false;
-    for (int k = 0; k < nrhs; ++k) {
-      if (!act[k]) continue;
-      const double pq = h[S_PQ * kMaxRhs + k], rr = h[S_RR * kMaxRhs + k];
-      if (!(pq > 0.0) || !std::isfinite(pq)) throw Error(SSAMG_ERR_NUMERIC, "PCG breakdown: p^T A p <= 0");
-      if (!std::isfinite(rr)) throw Error(SSAMG_ERR_NUMERIC, "non-finite residual");
-      iters[k] = it;
-      relres[k] = std::sqrt(rr / bb[k]);
-      if (relres[k] < tol) {
-        act[k] = 0;
-        conv[k] = 1;
-        --nact;
-        changed = true;
-      }
-    }
-    if (changed)
-      SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
-    if (nact == 0 || it == s.prm.max_iter) break;
+  // z = B r, the dot products and the x/p update of the next direction
+  auto next_direction = [&] {
     if (lg >= 2 && s.lv.size() > 1) {
       precond(s, lg, true);                 // r.z (and z.q) formed by the last sweep
     } else {
@@ -1665,6 +1644,54 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
     }
     launch_pcg_xp(nel, lg, s.scal, s.active, flexible ? 1 : 0, s.z, s.p, x, st);
     pending_x = false;
+  };
+  // residual history per right-hand side, to predict whether the next
+  // iteration is needed
+  std::vector<double> rel1(nrhs, 1.0), rel2(nrhs, 1.0);   // x0 = 0: the initial relative residual is 1
+  if (!s.ev_scal) SSAMG_HIP(hipEventCreateWithFlags(&s.ev_scal, hipEventDisableTiming));
+  for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
+    apply_A0(s, lg, s.p, s.q, S_PQ);        // p.q formed by the product itself
+    launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st);
+    pending_x = true;
+    SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    SSAMG_HIP(hipEventRecord(s.ev_scal, st));
+    // Speculation: when some active right-hand side is predicted (from the
+    // ratio of its last two residuals) to stay above the tolerance, the next
+    // direction is queued before this iteration's residual is read, so the
+    // device does not idle during the read.  Always correct: a right-hand side
+    // that has converged meanwhile still gets its last x += alpha p (beta and
+    // p are discarded, its later alphas are 0); only when every one has
+    // converged is the queued preconditioner wasted.
+    bool spec = false;
+    if (it < s.prm.max_iter)
+      for (int k = 0; k < nrhs && !spec; ++k) {
+        if (!act[k]) continue;
+        const double rho = rel2[k] > 0.0 ? std::min(1.0, rel1[k] / rel2[k]) : 0.0;
+        spec = rel1[k] * rho > 4.0 * tol;
+      }
+    if (spec) next_direction();
+    SSAMG_HIP(hipEventSynchronize(s.ev_scal));
+    bool changed = false;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!act[k]) continue;
+      const double pq = h[S_PQ * kMaxRhs + k], rr = h[S_RR * kMaxRhs + k];
+      if (!(pq > 0.0) || !std::isfinite(pq)) throw Error(SSAMG_ERR_NUMERIC, "PCG breakdown: p^T A p <= 0");
+      if (!std::isfinite(rr)) throw Error(SSAMG_ERR_NUMERIC, "non-finite residual");
+      iters[k] = it;
+      relres[k] = std::sqrt(rr / bb[k]);
+      rel2[k] = rel1[k];
+      rel1[k] = relres[k];
+      if (relres[k] < tol) {
+        act[k] = 0;
+        conv[k] = 1;
+        --nact;
+        changed = true;
+      }
+    }
+    if (changed)
+      SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
+    if (nact == 0 || it == s.prm.max_iter) break;
+    if (!spec) next_direction();
   }
   if (pending_x) launch_pcg_x(nel, lg, s.scal, s.p, x, st);
   // true residual

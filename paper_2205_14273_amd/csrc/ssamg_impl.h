@@ -276,6 +276,7 @@ struct Solver {
   int64_t split_cells = kSplitCells; // SSAMG_SPLIT_CELLS overrides
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
+  hipEvent_t ev_scal = nullptr;      // PCG: the scalars of an iteration have reached the host
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
   std::vector<Level> lv;
   std::vector<double> cd;            // direction sums c[p][d]
