@@ -219,7 +219,7 @@ DevBuf::~DevBuf() {
 // returns (nnz, nrow) of U_{l+1}.  One host synchronization.
 void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nnz, const int *erow,
                             const int *ucol, int64_t nc, CouplingStore &out, int64_t &out_nnz,
-                            int &out_nrow, hipStream_t st) {
+                            int &out_nrow, hipStream_t st, const std::function<void()> &before_sync) {
   out_nnz = 0;
   out_nrow = 0;
   if (nnz == 0) return;
@@ -261,6 +261,7 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, flags, scan, (int)n, st));
   k_counts<<<1, 1, 0, st>>>(scan, small);
   SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (before_sync) before_sync();   // host work that overlaps the device's
   SSAMG_HIP(hipStreamSynchronize(st));
   const int nvalid = w.host_small[0], nent = w.host_small[1], nr = w.host_small[2];
   if (nvalid == 0) return;

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <numeric>
 
@@ -489,6 +490,13 @@ void symbolic_couplings(Solver &s, int lgmax) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
   const int np = (int)s.lv[0].parts.size();
+  // the structured Galerkin tables (host) of levels 0 .. L-2, built two levels
+  // at a time while the device forms a coupling product, the rest at the end
+  int next_tab = 0;
+  auto tables = [&](int nlev) {
+    for (; nlev > 0 && next_tab < L - 1; --nlev, ++next_tab)
+      for (int p = 0; p < np; ++p) build_rap_table(s.lv[next_tab].parts[p], s.lv[next_tab + 1].parts[p].pat);
+  };
   while ((int)s.store.size() < L) s.store.emplace_back(new LevelStore());
   // one upload: SymPart tables of all levels and the block offsets of ublk
   std::vector<SymPart> sp;
@@ -574,7 +582,7 @@ void symbolic_couplings(Solver &s, int lgmax) {
       int64_t nnz = 0;
       int nrow = 0;
       coarse_coupling_device(s.scratch, d_sp + sp_at[l], np, V.nnz, V.d_erow, V.d_ucol, C.N, cs, nnz, nrow,
-                             st);
+                             st, [&] { tables(2); });
       C.nnz = nnz;
       C.nrow = nrow;
       C.ncontrib = nnz ? cs.ncontrib : 0;
@@ -588,6 +596,7 @@ void symbolic_couplings(Solver &s, int lgmax) {
       C.d_uc_b = nnz ? (int *)cs.cb.p : nullptr;
     }
   }
+  tables(L);
   // host-formed levels: arrays and block tables in one buffer, one copy
   if (lh < L) {
     std::vector<int> stage;
@@ -782,8 +791,7 @@ void setup_symbolic(Solver &s) {
         c.faces = q.faces;
         c.pat = coarse_pattern(q.pat, ds);
         c.center = index_of(c.pat, {0, 0, 0});
-        build_rap_table(q, c.pat);
-        C.parts.push_back(std::move(c));
+        C.parts.push_back(std::move(c));   // Galerkin table: built in symbolic_couplings
       }
     }
     // weight buffer layout of this level
@@ -1614,7 +1622,14 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   launch_copy(b, s.r, nel, st);
   launch_dot(b, b, nel, lg, s.partial, s.scal, S_BB, 0, st);
   SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
-  SSAMG_HIP(hipStreamSynchronize(st));
+  if (!s.ev_scal) SSAMG_HIP(hipEventCreateWithFlags(&s.ev_scal, hipEventDisableTiming));
+  SSAMG_HIP(hipEventRecord(s.ev_scal, st));
+  // the first direction does not depend on which right-hand sides are zero
+  // (none of its kernels reads the active mask): queued before |b| is read
+  precond(s, lg);
+  launch_copy(s.z, s.p, nel, st);
+  launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 0, st);
+  SSAMG_HIP(hipEventSynchronize(s.ev_scal));
   int nact = 0;
   for (int k = 0; k < nrhs; ++k) {
     bb[k] = h[S_BB * kMaxRhs + k];
@@ -1624,11 +1639,6 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
     nact += act[k];
   }
   SSAMG_HIP(hipMemcpyAsync(s.active, act.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
-  if (nact > 0) {
-    precond(s, lg);
-    launch_copy(s.z, s.p, nel, st);
-    launch_dot(s.r, s.z, nel, lg, s.partial, s.scal, S_RZN, 0, st);
-  }
   const double tol = s.prm.tol;
   bool pending_x = false;            // x += alpha p of the last iteration not yet applied
   // z = B r, the dot products and the x/p update of the next direction
@@ -1648,7 +1658,6 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   // residual history per right-hand side, to predict whether the next
   // iteration is needed
   std::vector<double> rel1(nrhs, 1.0), rel2(nrhs, 1.0);   // x0 = 0: the initial relative residual is 1
-  if (!s.ev_scal) SSAMG_HIP(hipEventCreateWithFlags(&s.ev_scal, hipEventDisableTiming));
   for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
     apply_A0(s, lg, s.p, s.q, S_PQ);        // p.q formed by the product itself
     launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st);

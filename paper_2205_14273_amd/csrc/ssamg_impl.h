@@ -10,6 +10,7 @@
 #include <memory>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -516,7 +517,8 @@ void launch_uc_numeric(int64_t nnz, const int *start, const int *k, const int *a
 // kernels_symbolic.hip
 void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nnz, const int *erow,
                             const int *ucol, int64_t nc, CouplingStore &out, int64_t &out_nnz,
-                            int &out_nrow, hipStream_t st);
+                            int &out_nrow, hipStream_t st,
+                            const std::function<void()> &before_sync = {});
 void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hipStream_t st);
 void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
                  const int *urow, const int *uptr, int *out, hipStream_t st);
