@@ -167,6 +167,23 @@ def test_large_coarsest_level(precision):
     assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
 
 
+def test_solution_buffer_not_16_byte_aligned():
+    """x may be any float64 buffer: a view one element into a larger one (8-byte
+    aligned only) takes the one-element-per-thread update and gives the same
+    solution bitwise."""
+    _print_case("unaligned x")
+    case = W.c2(9)
+    _, s = gpu_fv(case, cycle_precision=1)
+    b = _cuda(case.b)
+    x0, st0, i0 = s.solve(b)
+    buf = torch.zeros(b.numel() + 1, dtype=torch.float64, device="cuda")
+    xv = buf[1:]
+    assert xv.data_ptr() % 16 == 8
+    x1, st1, i1 = s.solve(b, x=xv)
+    assert st0 == st1 == 0 and i0.iters[0] == i1.iters[0]
+    assert torch.equal(x0, x1)
+
+
 def test_single_cell_parts():
     # degenerate: every part is one cell, the hierarchy has one level
     g = W.Geometry(3, [(1, 1, 1)] * 3, [(0, 0, 0), (1, 0, 0), (2, 0, 0)])
