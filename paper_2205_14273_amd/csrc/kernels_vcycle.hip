@@ -993,7 +993,7 @@ template <typename T, int TT, typename FIN>
 __device__ void tail_u(const TailLevel<T> &v, int lg, const T *__restrict__ x, T *__restrict__ prod,
                        int prodcap, FIN fin) {
   if (v.nrow == 0) return;   // uniform
-  constexpr int RPT = kTailMax / TT, EPT = kTailU / TT;
+  constexpr int RPT = kTailMax / TT, EPT = kTailUPer;
   const int tid = threadIdx.x, mask = (1 << lg) - 1;
   const int nslot = v.nrow << lg, nnz = v.nnz;
   int qa[RPT], qb[RPT], slot[RPT];

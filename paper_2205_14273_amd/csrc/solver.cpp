@@ -1204,7 +1204,8 @@ bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
   if (L - lt > 1 && maxel > (size_t)kTailMax) return false;
   pl = TailPlan{};
   pl.nl = L - lt;
-  pl.prodcap = kTailU;
+  const int tt = ts == sizeof(double) ? kTailThreads / 2 : kTailThreads;
+  pl.prodcap = kTailUPer * tt;
   size_t o = al(std::max(sizeof(TailLevel<double>), sizeof(TailLevel<float>)) * pl.nl);
   pl.off_tab = (int)o;
   o = al(o + sizeof(int) * pl.nl);
@@ -1215,7 +1216,7 @@ bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
   pl.off_acc = (int)o;
   o = al(o + ts * maxel);
   pl.off_prod = (int)o;
-  o = al(o + ts * kTailU);
+  o = al(o + ts * (size_t)pl.prodcap);
   if (o > (size_t)kTailLds) return false;
   pl.maxel = (int)maxel;
   pl.bytes = (int)o;

@@ -42,11 +42,11 @@ constexpr int kMaxLg = 5;        // log2(kMaxRhs)
 // The levels' vectors live in LDS (at most kTailLds bytes; fewer levels are
 // taken when they do not fit) and their operators are packed in level-wide
 // arrays, so each phase of the kernel waits on one round of coalesced loads
-// and LDS gathers instead of a launch and a chain of dependent loads.  kTailU
-// coupling products are staged per pass.
+// and LDS gathers instead of a launch and a chain of dependent loads.
+// kTailUPer coupling products per thread are staged per pass.
 constexpr int kTailThreads = 1024;
 constexpr int kTailMax = 4096;
-constexpr int kTailU = 2048;
+constexpr int kTailUPer = 4;   // coupling products staged per thread and pass (4096 in FP32, 2048 in FP64)
 constexpr int64_t kTailElems = 1024;          // one or two right-hand sides
 constexpr int64_t kTailElemsBatched = 2048;   // four or more (measured on 2 x 96^3, 32 rhs)
 constexpr int kTailLds = 65536;
