@@ -73,8 +73,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp,
                                                  unsigned long long nc, unsigned long long invalid,
                                                  unsigned long long *__restrict__ key,
                                                  unsigned *__restrict__ idx, int *__restrict__ rk,
-                                                 int *__restrict__ ra, int *__restrict__ rb) {
+                                                 int *__restrict__ ra, int *__restrict__ rb,
+                                                 int *__restrict__ small) {
   const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (q < 4) small[q] = 0;   // counts of k_flags / k_counts start at zero
   if (q >= nnz) return;
   int cf[2], sf[2], cg[2], sg[2];
   const int nf = prow(sp, np, erow[q], cf, sf);
@@ -248,12 +250,11 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   long long *flags = (long long *)w.flags.p, *scan = (long long *)w.scan.p;
   int *small = (int *)w.small.p;
   k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
-                                       rk, ra, rb);
+                                       rk, ra, rb, small);
   size_t tbytes = 0;
   SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
   w.temp.reserve(tbytes);
   SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
-  SSAMG_HIP(hipMemsetAsync(small, 0, 16, st));
   k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, flags, small);
   tbytes = 0;
   SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, flags, scan, (int)n, st));
