@@ -163,6 +163,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (tail && tail[0]) s->tail_elems = std::min<int64_t>(kTailMax, std::max<int64_t>(0, std::atoll(tail)));
   const char *split = std::getenv("SSAMG_SPLIT_CELLS");
   if (split && split[0]) s->split_cells = std::max<int64_t>(0, std::atoll(split));
+  const char *coll = std::getenv("SSAMG_COLLAPSE_CELLS");
+  if (coll && coll[0]) s->collapse_cells = std::max<int64_t>(0, std::atoll(coll));
   const char *hsym = std::getenv("SSAMG_HOST_SYM");
   if (hsym && hsym[0]) s->host_sym = std::max<int64_t>(0, std::atoll(hsym));
   void *pin = nullptr;

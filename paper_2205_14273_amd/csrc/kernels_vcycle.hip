@@ -1071,8 +1071,12 @@ __device__ __forceinline__ T tail_stencil(const TailLevel<T> &v, int e, int lg, 
 // at a time with a workgroup barrier between phases; the operands come from
 // the levels' packs.  Every level above the coarsest holds at most kTailMax
 // elements.  TT threads: 1024 in FP32, 512 in FP64.
+// mcol (one workgroup per column, lg = 0): the right-hand side is the unit
+// vector e_j (j = blockIdx.x) instead of tl[0].vb, and the result goes to
+// column j of mcol (FP64) instead of tl[0].vt.
 template <typename T, int TT>
-__global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl, TailPlan pl, int lg) {
+__global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl, TailPlan pl, int lg,
+                                             double *__restrict__ mcol) {
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, mask = (1 << lg) - 1;
   const int nl = pl.nl;
@@ -1090,16 +1094,24 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
     voff[tid] = o;
   }
   // b of the first level, and its first iterate x = w b (x follows b)
+  const int n0 = (int)L[0].ncell;
   {
     const TailLevel<T> &v = L[0];
     const int nel = (int)(v.ncell << lg);
     const bool coarsest = nl == 1;
     for (int e = tid; e < nel; e += TT) {
-      const T b = gload(v.vb + e);
+      const T b = mcol ? (e == (int)blockIdx.x ? T(1) : T(0)) : gload(v.vb + e);
       vec[e] = b;
       if (!coarsest) vec[nel + e] = gload(v.rs + (e >> lg)) * b;
     }
   }
+  // the result of the first level: tl[0].vt, or column blockIdx.x of mcol
+  auto store0 = [&](int e, T val) {
+    if (mcol)
+      mcol[(long long)blockIdx.x * n0 + e] = (double)val;
+    else
+      dev::Gw(L[0].vt)[e] = val;
+  };
   __syncthreads();
   // down: t = b - A x (x = w b), b_c = P^T t, x_c = w_c b_c
   for (int i = 0; i + 1 < nl; ++i) {
@@ -1134,22 +1146,33 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
     }
     __syncthreads();
   }
-  // coarsest: one FP64 sweep from zero, or the direct solve, into tv
+  // coarsest: one FP64 sweep from zero, or the direct solve (or the collapsed
+  // cycle's matrix, by columns), into tv
   {
     const TailLevel<T> &v = L[nl - 1];
     const int nel = (int)(v.ncell << lg);
     const T *b = vec + voff[nl - 1];
-    T *out = nl == 1 ? v.vt : tv;
     if (v.ndirect > 0) {
+      const int nd = v.ndirect;
+      const long long rs_ = v.colmajor ? 1 : nd, cs_ = v.colmajor ? nd : 1;   // strides of a row, a column
       for (int e = tid; e < nel; e += TT) {
         const int row = e >> lg, kr = e & mask;
-        const auto ar = G(v.ainv) + (long long)row * v.ndirect;
+        const auto ar = G(v.ainv) + (long long)row * rs_;
         double a = 0.0;
-        for (int j = 0; j < v.ndirect; ++j) a = fma(ar[j], (double)b[(j << lg) + kr], a);
-        out[e] = (T)a;
+        for (int j = 0; j < nd; ++j) a = fma(ar[j * cs_], (double)b[(j << lg) + kr], a);
+        if (nl == 1)
+          store0(e, (T)a);
+        else
+          tv[e] = (T)a;
       }
     } else {
-      for (int e = tid; e < nel; e += TT) out[e] = (T)(gload(v.rs64 + (e >> lg)) * (double)b[e]);
+      for (int e = tid; e < nel; e += TT) {
+        const T val = (T)(gload(v.rs64 + (e >> lg)) * (double)b[e]);
+        if (nl == 1)
+          store0(e, val);
+        else
+          tv[e] = val;
+      }
     }
     __syncthreads();
   }
@@ -1170,18 +1193,23 @@ __global__ __launch_bounds__(TT) void k_tail(const TailLevel<T> *__restrict__ tl
       x[e] += u;
     }
     __syncthreads();
-    T *out = i == 0 ? v.vt : tv;
+    auto put = [&](int e, T val) {
+      if (i == 0)
+        store0(e, val);
+      else
+        tv[e] = val;
+    };
     for (int e = tid; e < nel; e += TT) {
       const T a = tail_stencil(v, e, lg, x);
       const int c = e >> lg;
       if (gload(v.rowof + c) < 0)
-        out[e] = x[e] + gload(v.rs + c) * (b[e] - a);
+        put(e, x[e] + gload(v.rs + c) * (b[e] - a));
       else
         acc[e] = a;
     }
     __syncthreads();
     tail_u<T, TT>(v, lg, x, prod, pl.prodcap,
-                  [&](int e, T u) { out[e] = x[e] + gload(v.rs + (e >> lg)) * (b[e] - (acc[e] + u)); });
+                  [&](int e, T u) { put(e, x[e] + gload(v.rs + (e >> lg)) * (b[e] - (acc[e] + u))); });
   }
 }
 
@@ -1508,9 +1536,9 @@ void launch_dot_groups(const double *dotp, int64_t ngroups, int lg, int per, int
 }
 
 template <typename T>
-void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t st) {
+void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t st, double *mcol, int n) {
   constexpr int tt = sizeof(T) == 8 ? kTailThreads / 2 : kTailThreads;
-  k_tail<T, tt><<<1, tt, pl.bytes, st>>>(tl, pl, lg);
+  k_tail<T, tt><<<mcol ? n : 1, tt, pl.bytes, st>>>(tl, pl, lg, mcol);
 }
 
 template <typename T>
@@ -1552,8 +1580,8 @@ template void launch_smooth_resid<float, float>(int, int, const PartDesc<float> 
                                                 const float *, float *, float *, hipStream_t, LaunchEvents);
 template void launch_smooth_resid<float, double>(int, int, const PartDesc<float> *, int, int, int,
                                                  const double *, float *, float *, hipStream_t, LaunchEvents);
-template void launch_tail<double>(const TailLevel<double> *, const TailPlan &, int, hipStream_t);
-template void launch_tail<float>(const TailLevel<float> *, const TailPlan &, int, hipStream_t);
+template void launch_tail<double>(const TailLevel<double> *, const TailPlan &, int, hipStream_t, double *, int);
+template void launch_tail<float>(const TailLevel<float> *, const TailPlan &, int, hipStream_t, double *, int);
 template void launch_coarsest<double>(const TailLevel<double> *, int64_t, int, hipStream_t);
 template void launch_coarsest<float>(const TailLevel<float> *, int64_t, int, hipStream_t);
 template void launch_tail_pack<double>(TailLevel<double> *, int, int64_t, hipStream_t);

@@ -827,6 +827,15 @@ void setup_symbolic(Solver &s) {
   const auto t_alg = std::chrono::steady_clock::now();
   symbolic_couplings(s, lgmax);
   const auto t_u = std::chrono::steady_clock::now();
+  // collapse level: the first level >= 1 of at most collapse_cells cells, when
+  // it is not the coarsest
+  s.lk = -1;
+  if (s.collapse_cells > 0)
+    for (int l = 1; l + 1 < (int)s.lv.size(); ++l)
+      if (s.lv[l].N <= s.collapse_cells && s.lv[l].N <= kTailMax) {
+        s.lk = l;
+        break;
+      }
   // sizing pass of the workspace
   Carver cv;
   carve(s, cv);
@@ -864,12 +873,14 @@ void carve(Solver &s, Carver &cv) {
   // TailLevel records of all levels, contiguous (the tail kernel walks them)
   const size_t tail_size = mixed ? sizeof(TailLevel<float>) : sizeof(TailLevel<double>);
   void *tail_all = cv.take<char>(tail_size * L);
+  void *ctail_all = cv.take<char>(tail_size * L);   // the records the cycle reads (collapse level changed)
   for (int l = 0; l < L; ++l) {
     Level &V = s.lv[l];
     V.d_desc64 = cv.take<PartDesc<double>>(V.parts.size());
     V.d_desc32 = mixed ? cv.take<PartDesc<float>>(V.parts.size()) : nullptr;
     V.d_rapdesc = l < L - 1 ? cv.take<RapDesc>(V.parts.size()) : nullptr;
     V.d_tail = (char *)tail_all + (size_t)l * tail_size;
+    V.d_ctail = (char *)ctail_all + (size_t)l * tail_size;
     for (auto &q : V.parts) {
       q.d_rap_start = l < L - 1 ? cv.take<int>(q.rap_start.size()) : nullptr;
       q.d_rap_code = l < L - 1 ? cv.take<int>(q.rap_code.size()) : nullptr;
@@ -898,6 +909,8 @@ void carve(Solver &s, Carver &cv) {
   s.lv.back().d_ainv = s.prm.coarse == SSAMG_COARSE_DIRECT
                            ? cv.take<double>((size_t)s.lv.back().N * s.lv.back().N)
                            : nullptr;
+  for (int l = 0; l < L; ++l)
+    s.lv[l].d_mcyc = l == s.lk ? cv.take<double>((size_t)s.lv[l].N * s.lv[l].N) : nullptr;
   for (int l = 0; l < L; ++l) {
     Level &V = s.lv[l];
     const bool cyc32 = mixed && l < L - 1;
@@ -1040,6 +1053,12 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
         t.rw = (T *)V.d_pk_rw;
         t.rowof = V.d_pk_row;
         put(V.d_tail, &t, sizeof(t));
+        if (l == s.lk) {   // the cycle ends here: the collapsed operator as a direct solve
+          t.ndirect = (int)V.N;
+          t.ainv = V.d_mcyc;
+          t.colmajor = 1;
+        }
+        put(V.d_ctail, &t, sizeof(t));
       };
       if (mixed)
         rec((float *)nullptr);
@@ -1101,6 +1120,17 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     Level &V = s.lv.back();
     launch_direct_setup(V.d_desc64, (int)V.parts.size(), (int)V.N, V.nrow, V.d_urow, V.d_uptr, V.d_ucol,
                         V.d_uval64, V.d_ainv, s.flag, st);
+  }
+  // the collapsed cycle's matrix: the coarse end from level lk run once per
+  // unit right-hand side (one workgroup each)
+  if (s.lk >= 0) {
+    Level &V = s.lv[s.lk];
+    TailPlan pl;
+    if (!tail_plan(s, s.lk, 0, pl)) throw Error(SSAMG_ERR_STATE, "internal: collapse level without a plan");
+    if (mixed)
+      launch_tail<float>((const TailLevel<float> *)V.d_tail, pl, 0, st, V.d_mcyc, (int)V.N);
+    else
+      launch_tail<double>((const TailLevel<double> *)V.d_tail, pl, 0, st, V.d_mcyc, (int)V.N);
   }
   SSAMG_HIP(hipGetLastError());
   int hflag = 0;
@@ -1189,8 +1219,8 @@ void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int l
 
 }  // namespace
 
-bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl) {
-  const int L = (int)s.lv.size();
+bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl, int lend) {
+  const int L = lend >= 0 ? lend + 1 : (int)s.lv.size();   // levels lt .. L-1
   const size_t ts = s.prm.cycle_precision == SSAMG_FP32 ? sizeof(float) : sizeof(double);
   auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
   // every level above the coarsest needs its pack
@@ -1255,7 +1285,9 @@ void run_tail(Solver &s, int lg) {
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   TailPlan pl;
-  if (tail_plan(s, lt, lg, pl))
+  if (s.lk >= lt && tail_plan(s, lt, lg, pl, s.lk))   // the cycle ends at the collapse level
+    launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_ctail, pl, lg, st);
+  else if (tail_plan(s, lt, lg, pl))
     launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, pl, lg, st);
   else   // a coarsest level too large for LDS
     launch_coarsest<T>((const TailLevel<T> *)s.lv[lt].d_tail, s.lv[lt].N << lg, lg, st);

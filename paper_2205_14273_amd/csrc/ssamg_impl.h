@@ -50,6 +50,11 @@ constexpr int kTailUPer = 4;   // coupling products staged per thread and pass (
 constexpr int64_t kTailElems = 1024;          // one or two right-hand sides
 constexpr int64_t kTailElemsBatched = 2048;   // four or more (measured on 2 x 96^3, 32 rhs)
 constexpr int kTailLds = 65536;
+// The cycle below the first level of at most kCollapseCells cells (when that
+// level is not the coarsest) is a fixed linear map of its right-hand side; it
+// is formed at numeric setup as a dense FP64 matrix (one column per unit
+// right-hand side, by the coarse-end kernel itself) and applied in its place.
+constexpr int64_t kCollapseCells = 128;
 // coarse coupling structures whose product emits at most this many records
 // (four per fine entry) are formed on the host: below it a handful of
 // microseconds of host work beats the ten launches and the synchronisation
@@ -258,6 +263,8 @@ struct Level {
   struct RapDesc *d_rapdesc = nullptr;
   double *d_ainv = nullptr;          // coarsest level, direct solve: dense inverse
   void *d_tail = nullptr;            // TailLevel<cycle precision> of this level
+  void *d_ctail = nullptr;           // the same, except at the collapse level (its operator as the end)
+  double *d_mcyc = nullptr;          // collapse level: the collapsed cycle's matrix, [N][N] by columns
   // operator pack of the coarse-end kernel (levels 1 .. L-2 of at most
   // kTailMax cells; see TailLevel), cycle precision
   int *d_pk_nb = nullptr, *d_pk_pi = nullptr, *d_pk_ri = nullptr, *d_pk_row = nullptr;
@@ -276,6 +283,8 @@ struct Solver {
   int64_t tail_elems = -1;           // SSAMG_TAIL_ELEMS overrides (-1: kTailElems / kTailElemsBatched)
   int64_t split_cells = kSplitCells; // SSAMG_SPLIT_CELLS overrides
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
+  int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
+  int lk = -1;                       // collapse level (-1: none)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
   hipEvent_t ev_scal = nullptr;      // PCG: the scalars of an iteration have reached the host
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
@@ -363,6 +372,7 @@ struct TailLevel {
   const double *rs64;               // FP64 smoother factors (the coarsest level's sweep)
   const double *ainv;               // coarsest level, direct solve: A^{-1} (row-major), else null
   int ndirect, packed;              // its order (0: one relaxation sweep); 1 if the pack below is set
+  int colmajor, pad1;               // 1: ainv is stored by columns (the collapsed cycle operator)
   int *nb;                          // [nw][ncell] neighbour cell of entry s (the cell itself if absent)
   T *ca;                            // [nw][ncell] its coefficient (0 if absent)
   int *pi;                          // [2][ncell] interpolation: the two next-level cells
@@ -448,9 +458,13 @@ void launch_dot_final(const double *partial, int nblk, int lg, double *scal, int
 // with nset = 2, the second into slot_b
 void launch_dot_final2(const double *partial, int nblk, int lg, double *scal, int slot_a, int shift_rz,
                        int slot_b, int nset, hipStream_t st);
-// the coarse end of one cycle (levels tl[0 .. pl.nl), LDS-resident)
+// the coarse end of one cycle (levels tl[0 .. pl.nl), LDS-resident); with
+// mcol, pl.nl = levels from a level of n cells to the coarsest: one workgroup
+// per unit right-hand side e_j writes column j of that coarse end's operator
+// (FP64, by columns) to mcol instead
 template <typename T>
-void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t st);
+void launch_tail(const TailLevel<T> *tl, const TailPlan &pl, int lg, hipStream_t st, double *mcol = nullptr,
+                 int n = 1);
 // one coarsest level of nel elements, any size (vectors in global memory): a
 // sweep from zero or the direct solve, vb into vt
 template <typename T>
@@ -460,7 +474,8 @@ template <typename T>
 void launch_tail_pack(TailLevel<T> *tl, int nlev, int64_t maxcell, hipStream_t st);
 // LDS layout of the coarse end from level lt at width 2^lg; false when it
 // exceeds kTailLds bytes
-bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl);
+// ... for the levels lt .. lend (default: to the coarsest)
+bool tail_plan(const Solver &s, int lt, int lg, TailPlan &pl, int lend = -1);
 template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st);

@@ -288,6 +288,35 @@ def test_tail_kernel_matches_grid_kernels(monkeypatch, precision):
     assert np.linalg.norm(X1 - X0) <= 1e-6 * np.linalg.norm(X0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_collapsed_coarse_cycle(monkeypatch, precision):
+    """Below the first level of at most SSAMG_COLLAPSE_CELLS cells the cycle is
+    one dense matrix formed at setup; the cycle with it matches the cycle
+    without it (to rounding), for one and for eight right-hand sides, and the
+    oracle's cycle; the solves take the same iterations."""
+    _print_case(f"collapse precision={precision}")
+    case = W.c2(13)
+    h = oracle_fv(case)
+    r = np.random.default_rng(31).uniform(-1, 1, h.levels[0].n)
+    monkeypatch.setenv("SSAMG_COLLAPSE_CELLS", "0")
+    _, s0 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
+    monkeypatch.setenv("SSAMG_COLLAPSE_CELLS", "256")
+    _, s1 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
+    z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
+    z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
+    tol = 1e-13 if precision == 0 else 1e-5
+    assert np.linalg.norm(z1 - z0) <= tol * np.linalg.norm(z0)
+    want = O.vcycle(h, r)
+    assert np.linalg.norm(z1 - want) <= (1e-11 if precision == 0 else 1e-5) * np.linalg.norm(want)
+    R = np.random.default_rng(32).uniform(-1, 1, (h.levels[0].n, 8))
+    x0, st0, i0 = s0.solve(_cuda(R))
+    x1, st1, i1 = s1.solve(_cuda(R))
+    assert st0 == st1 == 0
+    assert max(abs(i0.iters[k] - i1.iters[k]) for k in range(8)) <= 1
+    X0, X1 = x0.cpu().numpy(), x1.cpu().numpy()
+    assert np.linalg.norm(X1 - X0) <= 1e-6 * np.linalg.norm(X0)
+
+
 @pytest.mark.parametrize("name", ["c2_12", "c3_8"])
 def test_host_formed_couplings_match_device(monkeypatch, name):
     """The coupling products of the small coarse levels are formed on the host
