@@ -1343,11 +1343,12 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const TailLevel<T> *__restr
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= nel) return;
   const int mask = (1 << lg) - 1;
-  if (v.ndirect > 0) {
+  if (v.ndirect > 0) {   // the direct solve's inverse by rows, or the collapsed cycle's matrix by columns
     const int row = (int)(e >> lg), kr = (int)(e & mask);
-    const double *ar = v.ainv + (long long)row * v.ndirect;
+    const long long rs_ = v.colmajor ? 1 : v.ndirect, cs_ = v.colmajor ? v.ndirect : 1;
+    const double *ar = v.ainv + (long long)row * rs_;
     double a = 0.0;
-    for (int j = 0; j < v.ndirect; ++j) a = fma(ar[j], (double)v.vb[((long long)j << lg) + kr], a);
+    for (int j = 0; j < v.ndirect; ++j) a = fma(ar[j * cs_], (double)v.vb[((long long)j << lg) + kr], a);
     v.vt[e] = (T)a;
   } else {
     v.vt[e] = (T)(v.rs64[e >> lg] * (double)v.vb[e]);

@@ -1276,7 +1276,11 @@ void run_tail(Solver &s, int lg) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
   const int np = (int)s.lv[0].parts.size();
-  const int lt = tail_start(s, lg);
+  // with a collapse level above the coarse end's first level (wide batches),
+  // the grid levels stop there and its operator is applied as a grid kernel
+  const int lt0 = tail_start(s, lg);
+  const bool grid_collapse = s.lk >= 1 && s.lk < lt0;
+  const int lt = grid_collapse ? s.lk : lt0;
   for (int l = 1; l < lt; ++l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
@@ -1285,7 +1289,9 @@ void run_tail(Solver &s, int lg) {
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   TailPlan pl;
-  if (s.lk >= lt && tail_plan(s, lt, lg, pl, s.lk))   // the cycle ends at the collapse level
+  if (grid_collapse)
+    launch_coarsest<T>((const TailLevel<T> *)s.lv[lt].d_ctail, s.lv[lt].N << lg, lg, st);
+  else if (s.lk >= lt && tail_plan(s, lt, lg, pl, s.lk))   // the cycle ends at the collapse level
     launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_ctail, pl, lg, st);
   else if (tail_plan(s, lt, lg, pl))
     launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_tail, pl, lg, st);

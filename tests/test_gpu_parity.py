@@ -288,19 +288,22 @@ def test_tail_kernel_matches_grid_kernels(monkeypatch, precision):
     assert np.linalg.norm(X1 - X0) <= 1e-6 * np.linalg.norm(X0)
 
 
+@pytest.mark.parametrize("cells", ["256", "512"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_collapsed_coarse_cycle(monkeypatch, precision):
+def test_collapsed_coarse_cycle(monkeypatch, precision, cells):
     """Below the first level of at most SSAMG_COLLAPSE_CELLS cells the cycle is
     one dense matrix formed at setup; the cycle with it matches the cycle
     without it (to rounding), for one and for eight right-hand sides, and the
-    oracle's cycle; the solves take the same iterations."""
-    _print_case(f"collapse precision={precision}")
+    oracle's cycle; the solves take the same iterations.  With 512 cells and
+    eight right-hand sides the collapse level lies above the coarse-end kernel
+    and the matrix is applied by a grid kernel."""
+    _print_case(f"collapse precision={precision} cells={cells}")
     case = W.c2(13)
     h = oracle_fv(case)
     r = np.random.default_rng(31).uniform(-1, 1, h.levels[0].n)
     monkeypatch.setenv("SSAMG_COLLAPSE_CELLS", "0")
     _, s0 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
-    monkeypatch.setenv("SSAMG_COLLAPSE_CELLS", "256")
+    monkeypatch.setenv("SSAMG_COLLAPSE_CELLS", cells)
     _, s1 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
     z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
     z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
