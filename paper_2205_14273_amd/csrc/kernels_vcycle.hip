@@ -1409,9 +1409,10 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
                   hipStream_t st, const LaunchEvents &ev, bool c4, double *dotp, const double *aux,
                   bool mir) {
   constexpr bool fp64_out = sizeof(TO) == 8 && sizeof(TB) == 8;
-  // the FP64 product of a symmetric stencil of more than 7 points: mirrored reads
-  if constexpr (sizeof(T) == 8 && fp64_out && NENT > 7) {
-    if (mir && (mode == MODE_APPLY || mode == MODE_APPLY_DOT)) {
+  // the FP64 product of a symmetric stencil: mirrored reads, for one column at
+  // any stencil size and for batches on stencils of more than 7 points
+  if constexpr (sizeof(T) == 8 && fp64_out) {
+    if (mir && (NENT > 7 || lg == 0) && (mode == MODE_APPLY || mode == MODE_APPLY_DOT)) {
       if (c4) {
         dim3 g4((unsigned)(((long long)grid.x + 3) / 4), grid.y);
         if (mode == MODE_APPLY)
