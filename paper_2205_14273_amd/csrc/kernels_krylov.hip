@@ -96,17 +96,20 @@ __global__ __launch_bounds__(kBlock) void k_dot2_partial(const double *__restric
 }
 
 // slot <- sum of partials; shift_rz: first move S_RZN to S_RZ (PCG bookkeeping).
-// kFinalThreads threads; each adds a fixed strided set of partials of its
-// right-hand side with four independent accumulators (loads in flight), then
-// a fixed LDS tree.
+// kFinalThreads threads; each requests its first four partials of its
+// right-hand side at once (then four at a time), adds them in a fixed order,
+// and the sums of one right-hand side are combined by a fixed tree of
+// cross-lane exchanges inside each wave and a fixed pairwise tree over the
+// waves.
 constexpr int kFinalThreads = 1024;
+constexpr int kFinalWaves = kFinalThreads / 64;
 
 // Block b of the grid reduces the partials at partial + b * kRedBlocks * kMaxRhs
 // into slot + b * (slot2 - slot): one launch finishes one or two dot products.
 __global__ __launch_bounds__(kFinalThreads) void k_dot_final(const double *__restrict__ partial, int nblk,
                                                              int lg, double *__restrict__ scal, int slot,
                                                              int shift_rz, int slot2) {
-  __shared__ double sh[kFinalThreads];
+  __shared__ double sh[kFinalWaves * kMaxRhs];
   if (blockIdx.x == 1) {
     partial += (size_t)kRedBlocks * kMaxRhs;
     slot = slot2;
@@ -115,22 +118,37 @@ __global__ __launch_bounds__(kFinalThreads) void k_dot_final(const double *__res
   const int nr = 1 << lg;
   const int kr = threadIdx.x & (nr - 1);
   const int step = kFinalThreads >> lg;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
   int bidx = threadIdx.x >> lg;
-  for (; bidx + 3 * step < nblk; bidx += 4 * step) {
+  double a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] += partial[(bidx + u * step) * kMaxRhs + kr];
+  for (int u = 0; u < 4; ++u) {
+    // out-of-range slots load partial 0 (always present) and add nothing
+    const int bb = bidx + u * step;
+    const double t = partial[(long long)(bb < nblk ? bb : 0) * kMaxRhs + kr];
+    a[u] = bb < nblk ? t : 0.0;
   }
-  for (; bidx < nblk; bidx += step) a[0] += partial[bidx * kMaxRhs + kr];
-  sh[threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
-  for (int s = kFinalThreads / 2; s >= nr; s >>= 1) {
-    __syncthreads();
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  for (bidx += 4 * step; bidx + 3 * step < nblk; bidx += 4 * step) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] += partial[(long long)(bidx + u * step) * kMaxRhs + kr];
   }
+  for (; bidx < nblk; bidx += step) a[0] += partial[(long long)bidx * kMaxRhs + kr];
+  double v = (a[0] + a[1]) + (a[2] + a[3]);
+  // lanes l and l ^ off hold the same right-hand side for every off >= nr
+  for (int off = 32; off >= nr; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < nr) sh[wave * nr + lane] = v;
   __syncthreads();
   if ((int)threadIdx.x < nr) {
+    double w[kFinalWaves];
+#pragma unroll
+    for (int q = 0; q < kFinalWaves; ++q) w[q] = sh[q * nr + threadIdx.x];
+#pragma unroll
+    for (int h = kFinalWaves / 2; h >= 1; h >>= 1) {
+#pragma unroll
+      for (int q = 0; q < h; ++q) w[q] += w[q + h];
+    }
     if (shift_rz) scal[S_RZ * kMaxRhs + threadIdx.x] = scal[S_RZN * kMaxRhs + threadIdx.x];
-    scal[slot * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
+    scal[slot * kMaxRhs + threadIdx.x] = w[0];
   }
 }
 
