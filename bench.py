@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched configurations: keep the default launch options")
+    ap.add_argument("--autotune-cache", default=None, metavar="PATH",
+                    help="batched configurations: read the launch options of tuned levels from "
+                         "this JSON file (levels not in it are timed) and write them back")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference kernel "
                          "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings) and exit")
@@ -171,7 +174,7 @@ def main():
             # kept by the solver across the setups of the timed steps
             s.setup()
             t0 = time.perf_counter()
-            s.autotune(nrhs)
+            s.autotune(nrhs, args.autotune_cache)
             tune_s[precision] = time.perf_counter() - t0
             log(f"  autotune ({'fp32' if precision else 'fp64'} cycle): {tune_s[precision]*1e3:.1f} ms")
             for lev in range(s.nlevels):
