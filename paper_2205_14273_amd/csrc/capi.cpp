@@ -165,6 +165,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (split && split[0]) s->split_cells = std::max<int64_t>(0, std::atoll(split));
   const char *coll = std::getenv("SSAMG_COLLAPSE_CELLS");
   if (coll && coll[0]) s->collapse_cells = std::max<int64_t>(0, std::atoll(coll));
+  const char *rsort = std::getenv("SSAMG_ROW_SORT");
+  if (rsort && rsort[0]) s->scratch.row_sort = std::max<int64_t>(0, std::atoll(rsort));
   const char *hsym = std::getenv("SSAMG_HOST_SYM");
   if (hsym && hsym[0]) s->host_sym = std::max<int64_t>(0, std::atoll(hsym));
   void *pin = nullptr;

@@ -98,6 +98,63 @@ __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp,
   }
 }
 
+// The records in key order, ties in record order (the order of a stable sort):
+// count the valid records of every coarse row, scan the counts into row
+// offsets, scatter every valid record into its row's range (any order), then
+// place each at its row offset plus its rank among the row's records by
+// (key, record index).  Positions past the valid records get the invalid key.
+__global__ __launch_bounds__(kBlock) void k_row_count(const unsigned long long *__restrict__ key, long long n,
+                                                      unsigned long long nc, unsigned long long invalid,
+                                                      int *__restrict__ cnt) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long k = key[i];
+  if (k != invalid) atomicAdd(&cnt[k / nc], 1);
+}
+
+// cnt holds the row counts on entry and zeros on exit
+__global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long *__restrict__ key,
+                                                        const unsigned *__restrict__ idx, long long n,
+                                                        unsigned long long nc, unsigned long long invalid,
+                                                        const int *__restrict__ roff, int *__restrict__ cnt,
+                                                        unsigned long long *__restrict__ tk,
+                                                        unsigned *__restrict__ ti) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long k = key[i];
+  if (k == invalid) return;
+  const long long r = (long long)(k / nc);
+  const int pos = roff[r] + atomicSub(&cnt[r], 1) - 1;
+  tk[pos] = k;
+  ti[pos] = idx[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_rank(const unsigned long long *__restrict__ tk,
+                                                     const unsigned *__restrict__ ti, long long n,
+                                                     unsigned long long nc, unsigned long long invalid,
+                                                     const int *__restrict__ roff,
+                                                     unsigned long long *__restrict__ key,
+                                                     unsigned *__restrict__ idx) {
+  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  if (p >= roff[nc]) {
+    key[p] = invalid;
+    return;
+  }
+  const unsigned long long k = tk[p];
+  const unsigned s = ti[p];
+  const long long r = (long long)(k / nc);
+  const int b = roff[r], e = roff[r + 1];
+  int rank = 0;
+  for (int j = b; j < e; ++j) {
+    const unsigned long long kj = tk[j];
+    const unsigned sj = ti[j];
+    rank += (kj < k || (kj == k && sj < s)) ? 1 : 0;
+  }
+  key[b + rank] = k;
+  idx[b + rank] = s;
+}
+
 // after the sort: flags of records that open a coarse entry / a coarse row,
 // and the count of valid records (invalid keys sort last)
 // packed flags: bit 0 a record that opens a coarse entry, bit 32 one that
@@ -251,12 +308,31 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   int *small = (int *)w.small.p;
   k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
                                        rk, ra, rb, small);
-  size_t tbytes = 0;
-  SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
-  w.temp.reserve(tbytes);
-  SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, tbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
+  // key order, ties in record order.  Up to w.row_sort records: k0/i0 ->
+  // row buckets in k1/i1 -> ranked in k0/i0 (five launches); above, a stable
+  // radix sort k0/i0 -> k1/i1 (its passes pay off on large levels)
+  if (n > w.row_sort) {
+    size_t rbytes = 0;
+    SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, rbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
+    w.temp.reserve(rbytes);
+    SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, rbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
+  } else {
+    w.rcnt.reserve((size_t)(nc + 1) * 4);
+    w.roff.reserve((size_t)(nc + 1) * 4);
+    int *rcnt = (int *)w.rcnt.p, *roff = (int *)w.roff.p;
+    SSAMG_HIP(hipMemsetAsync(rcnt, 0, (size_t)(nc + 1) * 4, st));
+    k_row_count<<<nblk(n), kBlock, 0, st>>>(k0, n, (unsigned long long)nc, invalid, rcnt);
+    size_t tbytes = 0;
+    SSAMG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tbytes, rcnt, roff, (int)(nc + 1), st));
+    w.temp.reserve(tbytes);
+    SSAMG_HIP(hipcub::DeviceScan::ExclusiveSum(w.temp.p, tbytes, rcnt, roff, (int)(nc + 1), st));
+    k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, i0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
+    k_row_rank<<<nblk(n), kBlock, 0, st>>>(k1, i1, n, (unsigned long long)nc, invalid, roff, k0, i0);
+    std::swap(k0, k1);
+    std::swap(i0, i1);
+  }
   k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, flags, small);
-  tbytes = 0;
+  size_t tbytes = 0;
   SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, flags, scan, (int)n, st));
   w.temp.reserve(tbytes);
   SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, flags, scan, (int)n, st));

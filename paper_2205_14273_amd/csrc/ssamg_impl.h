@@ -60,6 +60,7 @@ constexpr int64_t kCollapseCells = 128;
 // microseconds of host work beats the ten launches and the synchronisation
 // of the device sort
 constexpr int64_t kHostSymRecords = 16384;
+constexpr int64_t kRowSortRecords = int64_t(1) << 20;   // larger coupling products use a radix sort
 // levels with more than 15-point stencils and at least this many cells run the
 // first smoothing sweep and the residual as two kernels instead of one
 constexpr int64_t kSplitCells = 1 << 20;
@@ -227,8 +228,9 @@ struct LevelStore {
 
 // Scratch of the device sort.
 struct SymScratch {
-  DevBuf key0, key1, idx0, idx1, rk, ra, rb, flags, scan, small, temp;
+  DevBuf key0, key1, idx0, idx1, rk, ra, rb, flags, scan, small, temp, rcnt, roff;
   int *host_small = nullptr;         // pinned
+  int64_t row_sort = kRowSortRecords; // record counts up to this are ordered by row buckets
   ~SymScratch() {
     if (host_small) (void)hipHostFree(host_small);
   }
