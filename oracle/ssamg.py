@@ -26,6 +26,13 @@ Readings where the paper is silent or garbled (all are listed in the design note
            are coarse; coarse index i/2; coarse extent ceil(n/2).
   R-pb     part-boundary rule: the weight that would cross a part face is absent
            and the opposite weight is set to 1.
+  R-pb2    (option pb="lump") the opposite weight instead takes the dropped
+           weight on top, the dropped weight being the collapse of the row's
+           couplings, -(sum_j u_fj)/den over all of the row's cross-part entries
+           (the only reading available on coarse levels, where entries of U
+           carry no offset); on rows of zero sum it equals R-pb, next to a
+           Dirichlet face it is smaller than 1.  Rows whose denominator is not
+           positive keep weight 1.
   R-den    the collapse is undefined where its denominator (the sum of the
            row's coefficients with zero d* component) is not positive, which
            happens on Galerkin operators of strongly heterogeneous problems;
@@ -203,13 +210,15 @@ def coarse_pattern(fine_pattern, dstar):
     return np.asarray(sorted(out, key=lambda t: (t[2], t[1], t[0])), dtype=np.int32)
 
 
-def interpolation_weights(level, p, dstar, faces):
+def interpolation_weights(level, p, dstar, faces, pb="one"):
     """(wm, wp) over the F-box of part p: F cells are the odd cells along d*.
 
     wm multiplies the coarse neighbour at -d*, wp the one at +d* (P_W, P_E of
     eq:prolEx, with the sign reading R-sign).  A neighbour outside the box on a
     physical face is simply absent; on a part face the crossing weight is zero
-    and the opposite weight is 1 (R-pb).
+    and the opposite weight is 1 (R-pb, pb="one"), or (pb="lump", reading R-pb2)
+    the opposite weight plus the dropped one, taken as the collapse of the
+    row's couplings: -(sum over the row's cross-part entries)/den.
     """
     nx, ny, nz = level.dims[p]
     n = [nx, ny, nz]
@@ -249,10 +258,19 @@ def interpolation_weights(level, p, dstar, faces):
     hi_out = fc[dstar] + 1 > n[dstar] - 1
     wm = np.where(lo_out, 0.0, wm)
     wp = np.where(hi_out, 0.0, wp)
+    one_m = one_p = 1.0
+    if pb == "lump":
+        cross = ~same & (part[r] == p)
+        usum = np.bincount(r[cross] - level.offsets[p], weights=v[cross], minlength=ncell)[lin]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            one_m = np.where(good, -(sml + usum) / np.where(good, dd, 1.0), 1.0)
+            one_p = np.where(good, -(spll + usum) / np.where(good, dd, 1.0), 1.0)
+    elif pb != "one":
+        raise ValueError("pb must be 'one' or 'lump'")
     if faces[p][2 * dstar + 1]:          # + face is a part boundary
-        wm = np.where(hi_out & ~lo_out, 1.0, wm)
+        wm = np.where(hi_out & ~lo_out, one_m, wm)
     if faces[p][2 * dstar]:              # - face is a part boundary
-        wp = np.where(lo_out & ~hi_out, 1.0, wp)
+        wp = np.where(lo_out & ~hi_out, one_p, wp)
     return wm, wp
 
 
@@ -340,7 +358,7 @@ class Hierarchy:
 
 
 def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=64,
-          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False):
+          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False, pb="one"):
     """Full SSAMG setup.  ``pattern0[p]`` is the input stencil of part p.
 
     ``ustruct0``: 0/1 structure of the input couplings (defaults to A0's
@@ -369,7 +387,7 @@ def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=
         lev.wm, lev.wp = [], []
         for p in range(len(dims)):
             if lev.dstar[p] >= 0:
-                wm, wp = interpolation_weights(lev, p, lev.dstar[p], faces)
+                wm, wp = interpolation_weights(lev, p, lev.dstar[p], faces, pb)
             else:
                 wm, wp = np.zeros(0), np.zeros(0)
             lev.wm.append(wm)

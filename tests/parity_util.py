@@ -13,7 +13,7 @@ def oracle_fv(case, **kw):
     return O.setup(A, g.dims, g.face_kinds(), pat, g.ndim, omega=kw.get("omega", case.omega),
                    max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
                    relax=kw.get("relax", case.relax), coarse=kw.get("coarse", "sweep"),
-                   skip=kw.get("skip", False))
+                   skip=kw.get("skip", False), pb=kw.get("pb", "one"))
 
 
 def oracle_raw(case, **kw):
@@ -21,7 +21,8 @@ def oracle_raw(case, **kw):
     A, _ = assemble.assemble_raw(g.dims, case.stencils, case.coeffs, case.urow, case.ucol, case.uval)
     return O.setup(A, g.dims, case.faces, case.stencils, g.ndim, omega=kw.get("omega", 0.0),
                    ustruct0=assemble.u_structure(case.urow, case.ucol, A.shape[0]),
-                   max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0))
+                   max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
+                   pb=kw.get("pb", "one"))
 
 
 def gpu_fv(case, **params):
@@ -83,3 +84,44 @@ def compare_hierarchy(h, s, nparts, rtol=1e-12, check_values=True):
             diag = np.abs(lev.A.diagonal())
             rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
             assert np.max(np.abs(val - oval) / diag[rows]) <= rtol, l
+
+
+# Element-wise tolerances of the V-cycle z = B r against the oracle: FP64 kernels
+# differ from the oracle only in summation order; the FP32 cycle rounds every
+# operation to FP32 (unit roundoff 6e-8) through ~20 levels of a few operations.
+CYCLE_RTOL = {0: 1e-12, 1: 2e-5}
+
+
+def vcycle_scale(h, r):
+    """Rounding scale of each entry of the oracle's V-cycle z = B r: the same
+    recursion with every operator (A_l, P_l, the smoother factors, the coarsest
+    solve) replaced by its entrywise absolute value, applied to |r|.  Any
+    implementation that forms the same sums in another order or precision
+    changes z_i by at most a small multiple of this value, so a local error on a
+    row of small magnitude cannot hide under a norm of the whole vector."""
+    L = h.nlevels
+
+    def rec(l, bl):
+        lev = h.levels[l]
+        wd = np.abs(O._cell_weights(lev))
+        Aa = abs(lev.A)
+        if l == L - 1:
+            if h.coarse == "direct":
+                return np.abs(np.linalg.inv(lev.A.toarray())) @ bl
+            return wd * bl
+        x = wd * bl
+        rr = bl + Aa @ x
+        xc = rec(l + 1, abs(lev.P).T @ rr)
+        x = x + abs(lev.P) @ xc
+        return x + wd * (bl + Aa @ x)
+
+    return rec(0, np.abs(np.asarray(r, dtype=np.float64)))
+
+
+def assert_cycle_close(z, want, scale, rtol, what=""):
+    """|z_i - want_i| <= rtol * scale_i for every entry."""
+    err = np.abs(np.asarray(z) - np.asarray(want))
+    ratio = err / np.maximum(scale, 1e-300)
+    worst = int(np.argmax(ratio))
+    assert ratio[worst] <= rtol, (what, worst, float(ratio[worst]), rtol)
+    return float(ratio[worst])

@@ -574,3 +574,219 @@ def test_skip_vcycle_spd_and_pcg(relax):
     res = ssamg.solve(h, case.b, tol=1e-10, max_iter=200)
     assert res.converged
     assert np.linalg.norm(res.x - x_direct) <= 1e-8 * np.linalg.norm(x_direct)
+
+
+# ---------------------------------------------------------------------------
+# extraction helpers: the stencil and coupling layouts the parity tests read
+
+
+def _cases_small():
+    g = W.Geometry(3, [(9, 7, 5), (6, 7, 5), (5, 4, 6)], [(0, 0, 0), (9, 0, 0), (9, 7, 0)])
+    raw = W.random_link_case(1, g, 27, junk_outside=True)
+    A, _ = assemble.assemble_raw(g.dims, raw.stencils, raw.coeffs, raw.urow, raw.ucol, raw.uval)
+    hraw = ssamg.setup(A, g.dims, raw.faces, raw.stencils, 3,
+                       ustruct0=assemble.u_structure(raw.urow, raw.ucol, A.shape[0]))
+    out = [("raw", hraw)]
+    for name, mk in (("c1", lambda: W.c1(6)), ("c2", lambda: W.c2(5)), ("c3", lambda: W.c3(4)),
+                     ("c4", lambda: W.c4(5, nrhs=1)), ("c5", lambda: W.c5(5))):
+        out.append((name, fv_hierarchy(mk())[1]))
+    return out
+
+
+def _same_part_from_stencils(lev, values):
+    """Rebuild the same-part operator of a level from per-part stencil arrays."""
+    rows, cols, vals = [], [], []
+    for p, (nx, ny, nz) in enumerate(lev.dims):
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        i, j, k = i.reshape(-1), j.reshape(-1), k.reshape(-1)
+        for e, (dx, dy, dz) in enumerate(lev.pattern[p]):
+            inb = ((i + dx >= 0) & (i + dx < nx) & (j + dy >= 0) & (j + dy < ny)
+                   & (k + dz >= 0) & (k + dz < nz))
+            r = lev.offsets[p] + i + nx * (j + ny * k)
+            c = lev.offsets[p] + (i + dx) + nx * ((j + dy) + ny * (k + dz))
+            rows.append(r[inb])
+            cols.append(c[inb])
+            vals.append(values[p][e][inb])
+            # nothing may be stored for a neighbour outside the box
+            assert np.all(values[p][e][~inb] == 0.0)
+    import scipy.sparse as sps
+    return sps.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=lev.A.shape)
+
+
+def test_stencil_extraction_rebuilds_the_operator():
+    """stencil_values (entry by entry) and stencil_values_fast (vectorised)
+    agree bit for bit on every level of every workload shape, and the stencils
+    put back in place give exactly the same-part entries of A_l (a transposed
+    offset, a wrong code or a dropped entry changes the rebuilt matrix)."""
+    for name, h in _cases_small():
+        for l, lev in enumerate(h.levels):
+            slow = [ssamg.stencil_values(lev, p) for p in range(len(lev.dims))]
+            fast = [ssamg.stencil_values_fast(lev, p) for p in range(len(lev.dims))]
+            for p in range(len(lev.dims)):
+                assert np.array_equal(slow[p], fast[p]), (name, l, p)
+            S = _same_part_from_stencils(lev, fast)
+            part = np.repeat(np.arange(len(lev.dims)), np.diff(lev.offsets))
+            A = lev.A.tocoo()
+            m = part[A.row] == part[A.col]
+            import scipy.sparse as sps
+            AS = sps.csr_matrix((A.data[m], (A.row[m], A.col[m])), shape=A.shape)
+            assert abs(S - AS).max() == 0.0, (name, l)
+
+
+def test_coupling_extraction_is_the_cross_part_operator():
+    """coupling_csr reads exactly the cross-part entries of A_l on the symbolic
+    structure: stencils + couplings rebuild A_l, every stored entry crosses
+    parts, and every nonzero cross-part entry of A_l is stored."""
+    import scipy.sparse as sps
+    for name, h in _cases_small():
+        for l, lev in enumerate(h.levels):
+            rp, col, val = ssamg.coupling_csr(lev)
+            n = lev.n
+            rows = np.repeat(np.arange(n), np.diff(rp))
+            part = np.repeat(np.arange(len(lev.dims)), np.diff(lev.offsets))
+            assert np.all(part[rows] != part[col]), (name, l)
+            assert np.all(np.diff(col)[np.diff(rows) == 0] > 0), (name, l)   # sorted, no duplicates
+            U = sps.csr_matrix((val, (rows, col)), shape=(n, n))
+            S = _same_part_from_stencils(lev, [ssamg.stencil_values_fast(lev, p)
+                                               for p in range(len(lev.dims))])
+            assert abs(S + U - lev.A).max() == 0.0, (name, l)
+            A = lev.A.tocoo()
+            cross = (part[A.row] != part[A.col]) & (A.data != 0)
+            if cross.any():
+                st = lev.ustruct.tocsr()
+                got = np.asarray(st[A.row[cross], A.col[cross]]).ravel()
+                assert np.all(got == 1.0), (name, l)
+
+
+def _zero_smoother(h):
+    for lev in h.levels:
+        lev._cache["wd"] = np.zeros(lev.n)
+
+
+def test_direct_coarsest_branch_is_the_exact_inverse():
+    """coarse = "direct": with one level the cycle is A^{-1} b itself; with two
+    levels and the smoother switched off it is P (P^T A P)^{-1} P^T, so B A P = P
+    (the coarse correction reproduces every interpolated vector exactly)."""
+    case = W.c2(4)
+    _, h1 = fv_hierarchy(case, max_levels=1, coarse="direct")
+    A = h1.levels[0].A.toarray()
+    b = np.random.default_rng(4).uniform(-1, 1, A.shape[0])
+    assert np.allclose(ssamg.vcycle(h1, b), np.linalg.inv(A) @ b, rtol=0, atol=1e-12)
+    _, h2 = fv_hierarchy(case, max_levels=2, coarse="direct")
+    _zero_smoother(h2)
+    P = h2.levels[0].P.toarray()
+    A0 = h2.levels[0].A.toarray()
+    B = np.column_stack([ssamg.vcycle(h2, e) for e in np.eye(A0.shape[0])])
+    Ac = h2.levels[1].A.toarray()
+    assert np.allclose(B, P @ np.linalg.inv(Ac) @ P.T, rtol=0, atol=1e-12)
+    assert np.allclose(B @ A0 @ P, P, rtol=0, atol=1e-10)
+
+
+def test_fv_27_point_edge_corner_and_interface_conductances():
+    """Hand values of the finite-volume rule: an edge link has geometric weight
+    1/2, a corner link 1/4, across a part face the conductivity is the harmonic
+    mean of the two sides, and a side's directional factor is the mean of its
+    part's factors over the link's nonzero directions."""
+    g = W.Geometry(3, [(2, 2, 2), (2, 2, 2)], [(0, 0, 0), (2, 0, 0)])
+    kap = np.arange(1.0, 17.0)            # cell c has kappa c + 1
+    aniso = np.array([[2.0, 1.0, 1.0], [1.0, 3.0, 1.0]])
+    A, _ = assemble.assemble_fv(g, 27, kap, aniso)
+
+    def cid(p, i, j, k):
+        return 8 * p + i + 2 * (j + 2 * k)
+
+    def H(x, y):
+        return 2 * x * y / (x + y)
+
+    i0 = cid(0, 0, 0, 0)
+    # inside part 0: edge (0,1,1) -> factor (1+1)/2 = 1, corner (1,1,1) -> (2+1+1)/3
+    e = cid(0, 0, 1, 1)
+    assert A[i0, e] == pytest.approx(-0.5 * H(1.0 * kap[i0], 1.0 * kap[e]), rel=1e-15)
+    c = cid(0, 1, 1, 1)
+    assert A[i0, c] == pytest.approx(-0.25 * H(4 / 3 * kap[i0], 4 / 3 * kap[c]), rel=1e-15)
+    # across the part face x = 2: cell (1,0,0) of part 0 to (0,1,0) of part 1 (edge
+    # (1,1,0)): factors (2+1)/2 and (1+3)/2; corner (1,1,1): (2+1+1)/3 and (1+3+1)/3
+    a = cid(0, 1, 0, 0)
+    eb = cid(1, 0, 1, 0)
+    assert A[a, eb] == pytest.approx(-0.5 * H(1.5 * kap[a], 2.0 * kap[eb]), rel=1e-15)
+    cb = cid(1, 0, 1, 1)
+    assert A[a, cb] == pytest.approx(-0.25 * H(4 / 3 * kap[a], 5 / 3 * kap[cb]), rel=1e-15)
+    # face link across the interface: harmonic mean of 2 kappa_a and 1 kappa_b
+    fb = cid(1, 0, 0, 0)
+    assert A[a, fb] == pytest.approx(-H(2.0 * kap[a], 1.0 * kap[fb]), rel=1e-15)
+    assert A[a, fb] == A[fb, a]
+    # a corner cell of the domain: its row sum is its ghost links, with the
+    # ghost's kappa equal to its own: 3 faces, 9 edges (3 in-domain), 7 corners
+    # (1 in-domain) of the 26 links point outside for cell (0,0,0) of part 0
+    k0 = kap[i0]
+    fsum = (2.0 + 1.0 + 1.0) * k0            # -x, -y, -z faces
+    esum = 0.0
+    for s in [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+              if sum(v != 0 for v in (dx, dy, dz)) == 2]:
+        if min(s) < 0:   # some component points out of the domain
+            f = np.mean([aniso[0][d] for d in range(3) if s[d] != 0])
+            esum += 0.5 * f * k0
+    csum = sum(0.25 * (4 / 3) * k0 for s in range(8) if s != 7)   # 7 of 8 corners leave
+    assert float(A[i0].sum()) == pytest.approx(fsum + esum + csum, rel=1e-13)
+
+
+def _pb_case(a=10.0):
+    """Two parts of 4 x 3 x 3 along x, 7-point, anisotropy (a,1,1) in both: d* = x
+    on level 0 and the last x cell of part 0 (odd) has its +x neighbour across
+    the part face."""
+    g = W.Geometry(3, [(4, 3, 3), (4, 3, 3)], [(0, 0, 0), (4, 0, 0)])
+    return W.FVCase("pb", g, 7, np.ones(g.n), np.array([[a, 1.0, 1.0]] * 2),
+                    np.random.default_rng(0).uniform(-1, 1, g.n))
+
+
+def test_lumped_part_boundary_weight_by_hand():
+    """R-pb2 next to a Dirichlet face: the F cell (3,0,1) of part 0 has links
+    a (-x, same part), a (+x, across the part face), ghost 1 (-y), 1 (+y), 1, 1
+    (z): diagonal 2a + 4, collapse denominator 2a + 1, so the lumped weight is
+    (a + a)/(2a + 1) where the literal reading gives 1; on the zero-sum row of
+    cell (3,1,1) (no Dirichlet face) both give exactly 1."""
+    a = 10.0
+    case = _pb_case(a)
+    _, h1 = fv_hierarchy(case, pb="one")
+    _, h2 = fv_hierarchy(case, pb="lump")
+    assert h1.levels[0].dstar[0] == 0 and h2.levels[0].dstar[0] == 0
+    fn = (2, 3, 3)                       # F-box of part 0: odd x cells 1 and 3
+
+    def fidx(i, j, k):
+        return (i - 1) // 2 + fn[0] * (j + fn[1] * k)
+
+    assert h1.levels[0].wm[0][fidx(3, 0, 1)] == 1.0
+    assert h2.levels[0].wm[0][fidx(3, 0, 1)] == pytest.approx(2 * a / (2 * a + 1), rel=1e-15)
+    assert h2.levels[0].wm[0][fidx(3, 1, 1)] == pytest.approx(1.0, rel=1e-15)
+    assert h1.levels[0].wm[0][fidx(3, 1, 1)] == 1.0
+    # away from the part face the two readings give the same weights
+    assert h1.levels[0].wm[0][fidx(1, 0, 1)] == h2.levels[0].wm[0][fidx(1, 0, 1)]
+
+
+@pytest.mark.parametrize("mk", [lambda: W.c2(6), lambda: W.c3(4), lambda: W.c5(6)])
+def test_lumped_part_boundary_hierarchy(mk):
+    """With R-pb2 every coarse operator stays SPD, P's row sums stay in [0, 1]
+    on M-matrix levels, the V-cycle is SPD and PCG reaches the dense solution."""
+    case = mk()
+    _, h = fv_hierarchy(case, pb="lump")
+    nm = 0
+    for lev in h.levels[:-1]:
+        rs = np.asarray(lev.P.sum(axis=1)).ravel()
+        Ac = lev.A.tocoo()
+        if np.all(Ac.data[Ac.row != Ac.col] <= 0):      # M-matrix level
+            nm += 1
+            assert np.all(rs >= -1e-14) and np.all(rs <= 1 + 1e-14)
+    assert nm >= 1
+    for lev in h.levels[1:4]:
+        Ad = lev.A.toarray()
+        assert np.allclose(Ad, Ad.T, rtol=0, atol=1e-12 * np.abs(Ad).max())
+        assert np.linalg.eigvalsh(Ad).min() > 0
+    n = h.levels[0].n
+    if n <= 1500:
+        B = np.column_stack([ssamg.vcycle(h, e) for e in np.eye(n)])
+        assert np.allclose(B, B.T, atol=1e-12 * np.abs(B).max())
+        assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    ref = ssamg.solve(h, case.b, tol=1e-10)
+    xd = np.linalg.solve(h.levels[0].A.toarray(), case.b)
+    assert ref.converged and np.linalg.norm(ref.x - xd) <= 1e-8 * np.linalg.norm(xd)
