@@ -9,7 +9,12 @@ resident in HBM: finite-volume assembly from kappa, symbolic + numeric setup
 preconditioned CG solve.  Prints exactly one JSON line on stdout; progress goes
 to stderr.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
+
+The default workload is the largest single-GPU configuration: 8 parts of 128^3
+(16.8M cells), 27-point heterogeneous diffusion.  The main roofline is that of
+its dominant kernel, the FP64 product q = A p of PCG; the finest-level
+post-smoothing sweep of the cycle is reported beside it.
 """
 from __future__ import annotations
 
@@ -59,6 +64,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def stencil_entries(case):
+    return 7 if case.stencil in (5, 7) else (9 if case.stencil == 9 else 27)
+
+
 def stored_traffic(config, probe):
     """HBM bytes per launch measured with rocprofv3 --pmc for this kernel, if the
     stored measurement was taken on the current kernel sources."""
@@ -84,9 +93,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(DESCR))
+    ap.add_argument("--config", default="c3", choices=sorted(DESCR))
     ap.add_argument("--m", type=int, default=None, help="box size override (smaller runs)")
-    ap.add_argument("--probe", default="jacobi0", choices=sorted(PROBES))
+    ap.add_argument("--probe", default="matvec", choices=sorted(PROBES),
+                    help="kernel of the main roofline (timed with HIP events in the timed run)")
+    ap.add_argument("--probe2", default="jacobi0", choices=sorted(PROBES) + ["none"],
+                    help="kernel of the second roofline (a short extra run of the FP32 cycle)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -205,45 +217,76 @@ def main():
                "true_relres": max(info.true_relres[k] for k in range(nrhs)), "levels": s.nlevels}
         return res, x, probe, s
 
+    nent = stencil_entries(case)
+
+    def probe_name_of(probe):
+        kind, name = PROBES[probe]
+        if nrhs >= 4 and probe in PROBES_BATCHED:
+            name = PROBES_BATCHED[probe]
+        name = name.format(n=nent)
+        if probe == "matvec" and nent > 7:
+            name = name[:-1] + ", true>"       # mirrored reads of a symmetric stencil
+        if nrhs >= 4 and not (name.startswith("k_stencil<double") and nent == 27):
+            # four right-hand-side columns per thread on batched levels
+            name = name.replace("k_stencil<", "k_stencil4<")
+        return kind, name
+
+    def roofline(probe, meas):
+        """Achieved bandwidth of one kernel: algorithmic bytes per launch over
+        its average duration (HIP events recorded by the kernel's own dispatch,
+        on the solver's stream, over every launch of the timed steps)."""
+        if not meas or meas[0] <= 0:
+            return None
+        launches, ms, by = meas
+        avg_s = ms / launches * 1e-3
+        streamed = by / launches                     # what the kernel must stream
+        alg = streamed
+        if probe == "matvec":
+            # the product's algorithmic bytes as the survey counts them: every
+            # stencil entry, x and y, (s + 2) * 8 bytes per cell and column
+            alg = float(N) * (nent + 2 * nrhs) * 8
+        achieved = alg / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4),
+               "traffic": stored_traffic(args.config, probe),
+               "kernel": probe_name_of(probe)[1], "launches": launches,
+               "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": alg}
+        if streamed != alg:
+            # mirrored reads: only the center and the positive half of the
+            # symmetric stencil are streamed
+            out["streamed_bytes_per_launch"] = streamed
+            out["achieved_streamed"] = round(streamed / avg_s / 1e9, 1)
+            out["frac_streamed"] = round(streamed / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+        return out
+
     log("timed run: FP32 V-cycle inside FP64 PCG")
-    probe_kind, probe_name = PROBES[args.probe]
-    nent = 7 if case.stencil in (5, 7) else 27
-    if nrhs >= 4 and args.probe in PROBES_BATCHED:
-        probe_name = PROBES_BATCHED[args.probe]
-    probe_name = probe_name.format(n=nent)
-    if nrhs >= 4 and not (probe_name.startswith("k_stencil<double") and nent == 27):
-        # four right-hand-side columns per thread on batched levels
-        probe_name = probe_name.replace("k_stencil<", "k_stencil4<")
-    mixed, x32, probe, s32 = run(B.L.FP32, args.steps, args.warmup, probe_kind)
+    mixed, x32, probe, s32 = run(B.L.FP32, args.steps, args.warmup, probe_name_of(args.probe)[0])
     fp64 = None
     x64 = None
     if not args.no_fp64:
-        log("comparison run: FP64 V-cycle")
-        fp64, x64, _, _ = run(B.L.FP64, max(1, min(args.steps, 3)), 1)
-
-    roof = None
-    if probe and probe[0] > 0:
-        launches, ms, by = probe
-        avg_s = ms / launches * 1e-3
-        achieved = by / launches / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(args.config, args.probe),
-                "kernel": probe_name, "launches": launches,
-                "avg_launch_us": round(avg_s * 1e6, 2),
-                "alg_bytes_per_launch": by / launches}
+        log("comparison run: FP64 V-cycle (same steps)")
+        fp64, x64, _, _ = run(B.L.FP64, args.steps, args.warmup)
+    roof = roofline(args.probe, probe)
+    roof2 = None
+    if args.probe2 != "none" and args.probe2 != args.probe:
+        log(f"second roofline: {args.probe2}, two more FP32-cycle steps")
+        _, _, probe2, _ = run(B.L.FP32, 2, 0, probe_name_of(args.probe2)[0])
+        roof2 = roofline(args.probe2, probe2)
 
     cpu = None
     err = {}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host cores")
         from oracle import assemble, ssamg as O
-        t0 = time.perf_counter()
         scale = 1.0
+        iter_scale = 1.0
         if args.config in ("c3",) and not args.m:
-            sample_case = W.c3(32)
-            sample = "c3 recipe at 8 parts of 32^3 (262,144 cells), time scaled by the cell ratio 64"
+            sample_case = W.c3(64)
             scale = N / sample_case.geometry.n
+            sample = (f"c3 recipe at 8 parts of 64^3 ({sample_case.geometry.n:,} cells; the full "
+                      f"workload does not fit the oracle's time bound): assembly and setup scaled by "
+                      f"the cell ratio {scale:g}, the solve by the cell ratio times the ratio of the "
+                      f"GPU's iterations at full size to the oracle's on the sample")
         elif args.config == "c4":
             sample_case = case
             sample = "full c4 problem with its first right-hand side, time scaled by 32"
@@ -252,15 +295,24 @@ def main():
             sample_case = case
             sample = f"full {args.config} workload, one step (FV assembly + setup + PCG to 1e-8), FP64"
         sg = sample_case.geometry
+        t0 = time.perf_counter()
         A, _ = assemble.assemble_fv(sg, sample_case.stencil, sample_case.kappa, sample_case.aniso)
         h = O.setup(A, sg.dims, sg.face_kinds(), [W.stencil_offsets(sample_case.stencil, sg.ndim)]
                     * sg.nparts, sg.ndim, omega=sample_case.omega, relax=sample_case.relax)
+        ts = time.perf_counter()
         bb = sample_case.b if sample_case.b.ndim == 1 else sample_case.b[0]
         ref = O.solve(h, bb, tol=sample_case.tol, max_iter=sample_case.max_iter)
         t1 = time.perf_counter()
-        cpu = {"value": round((t1 - t0) * scale, 3), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": sample, "iters": ref.iters, "measured_s": round(t1 - t0, 3)}
-        log(f"  oracle: {t1 - t0:.2f} s, iters {ref.iters}")
+        gpu_iters = mixed["iters"] if nrhs == 1 else mixed["iters"][0]
+        if sample_case is not case and args.config == "c3":
+            iter_scale = gpu_iters / max(ref.iters, 1)
+        value = ((ts - t0) + (t1 - ts) * iter_scale) * scale
+        cpu = {"value": round(value, 3), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": sample, "iters": ref.iters, "measured_s": round(t1 - t0, 3),
+               "measured_setup_s": round(ts - t0, 3), "measured_solve_s": round(t1 - ts, 3),
+               "cell_ratio": scale, "iter_ratio": round(iter_scale, 4)}
+        log(f"  oracle: {t1 - t0:.2f} s (assembly + setup {ts - t0:.2f}, solve {t1 - ts:.2f}), "
+            f"iters {ref.iters}")
         if sample_case is case:
             xo = ref.x
             for name, xg in (("fp32_cycle", x32), ("fp64_cycle", x64)):
@@ -273,6 +325,10 @@ def main():
             cpu["iters_vs_gpu"] = {"oracle": ref.iters,
                                    "gpu_fp32_cycle": mixed["iters"] if nrhs == 1 else mixed["iters"][0]}
 
+    if x64 is not None:
+        # the FP32 cycle's solution against the FP64 cycle's at full size (the
+        # oracle's own solution is compared at the sizes it reaches, in tests)
+        err["fp32_vs_fp64_cycle"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
     ms = mixed["ms_per_step"]
     line = {
         "metric": METRIC,
@@ -295,6 +351,7 @@ def main():
                    "setup_numeric_s": round(mixed["numeric_s"], 6),
                    "solve_s": round(mixed["solve_s"], 6), "true_relres": mixed["true_relres"],
                    "autotune_s": round(tune_s[1], 4) if 1 in tune_s else None},
+        "roofline_cycle_sweep": roof2,
         "fp64_cycle": None if fp64 is None else {
             "ms_per_step": round(fp64["ms_per_step"], 4), "setup_s": round(fp64["setup_s"], 6),
             "solve_s": round(fp64["solve_s"], 6), "iters": fp64["iters"],

@@ -57,6 +57,8 @@ enum { SSAMG_MEM_HOST = 0, SSAMG_MEM_DEVICE = 1 };
 enum { SSAMG_RELAX_JACOBI = 0, SSAMG_RELAX_L1_JACOBI = 1 };
 enum { SSAMG_COARSE_SWEEP = 0, SSAMG_COARSE_DIRECT = 1 };
 enum { SSAMG_FP64 = 0, SSAMG_FP32 = 1 };
+enum { SSAMG_PB_ONE = 0, SSAMG_PB_LUMP = 1 };
+enum { SSAMG_LAYOUT_CELL_MAJOR = 0, SSAMG_LAYOUT_RHS_MAJOR = 1 };
 
 typedef struct ssamg_problem_s *ssamg_problem;
 typedef struct ssamg_solver_s *ssamg_solver;
@@ -100,11 +102,13 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
                                       int where, int constant);
 
 /* Inter-part couplings U (Section 2): nnz entries (row[k], col[k], val[k]) with
- * global cell ids; host arrays; copied; duplicates are summed, explicit zeros
- * kept as structure.  An entry inside one part is SSAMG_ERR_ARG (assumption of
- * the theorem of Section 3.3).  May be called once; nnz = 0 means none. */
+ * global cell ids, in COO form; `where` = SSAMG_MEM_HOST or SSAMG_MEM_DEVICE
+ * for all three arrays; copied; duplicates are summed, explicit zeros kept as
+ * structure.  An entry inside one part is SSAMG_ERR_ARG (assumption of the
+ * theorem of Section 3.3); a non-finite value SSAMG_ERR_NUMERIC.  A second
+ * call replaces the couplings; nnz = 0 means none. */
 ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const int64_t *row,
-                                        const int64_t *col, const double *val);
+                                        const int64_t *col, const double *val, int where);
 
 /* Finite-volume diffusion operator from per-cell conductivity (the synthetic
  * workloads): kappa (device, N doubles, copied), aniso (host, [nparts][3]
@@ -118,14 +122,21 @@ ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const i
 ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa,
                                        const double *aniso, int stencil, void *hip_stream);
 
-/* Gradient of L(x(kappa)) for the operator of the last fv_assemble:
- * grad[c] = -lambda^T (dA/dkappa_c) x, where lambda solves A lambda = dL/dx.
- * lambda, x, grad: device, N doubles each. */
-ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, const double *lambda, const double *x,
+/* Gradient of L(x(kappa)) for the operator of the last fv_assemble (adjoint
+ * method): grad[c] = -sum_k lambda_k^T (dA/dkappa_c) x_k over the nrhs columns
+ * (1..32), where lambda_k solves A lambda_k = dL/dx_k.  lambda, x: device,
+ * [N][nrhs] doubles (right-hand side fastest); grad: device, N doubles,
+ * overwritten. */
+ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, int nrhs, const double *lambda, const double *x,
                                    double *grad, void *hip_stream);
 
-/* Number of cells N of the problem. */
+/* Number of cells N of the problem, and its number of parts. */
 ssamg_status ssamg_problem_num_cells(ssamg_problem prob, int64_t *n);
+ssamg_status ssamg_problem_num_parts(ssamg_problem prob, int *nparts);
+
+/* Stencil entries (0 before set_stencil) and cells of part `part`, so that a
+ * caller can size the coefficient array of set_coeffs. */
+ssamg_status ssamg_problem_part_size(ssamg_problem prob, int part, int *nent, int64_t *ncell);
 
 /* ---------------------------------------------------------------- solver */
 
@@ -165,9 +176,19 @@ typedef struct {
                                 component of (dx, dy, dz) positive) and takes every
                                 other entry from the neighbour's mirrored one,
                                 halving its coefficient traffic (parts whose
-                                pattern lacks a mirror read every entry).  The
-                                V-cycle always reads every entry.  0: the product
-                                reads every entry too */
+                                pattern lacks a mirror read every entry, and so
+                                does every part of a problem whose given
+                                coefficients are not symmetric to a relative
+                                1e-12).  The V-cycle always reads every entry.
+                                0: the product reads every entry too */
+  int pb_interp;             /* interpolation at a part face crossed along d* (Section 3.2):
+                                the weight across the face is dropped and
+                                SSAMG_PB_ONE (default): the opposite weight is set to 1;
+                                SSAMG_PB_LUMP: the dropped weight, the collapse of the
+                                row's couplings U (-sum_j u_fj over the collapse
+                                denominator), is added to the opposite weight.  Both
+                                interpolate constants exactly on rows of zero sum; they
+                                differ on rows next to a Dirichlet face */
 } ssamg_params;
 
 typedef struct {
@@ -176,6 +197,8 @@ typedef struct {
   double relres[32];         /* ||r_k||/||b|| of the recursive residual at exit */
   double true_relres[32];    /* ||b - A x||/||b|| recomputed at exit */
   int converged[32];
+  double t_setup;            /* seconds, host wall clock of the last setup_symbolic +
+                                setup_numeric of this solver */
   double t_solve;            /* seconds, host wall clock around the solve */
 } ssamg_info;
 
@@ -219,11 +242,20 @@ ssamg_status ssamg_setup_numeric(ssamg_solver s, void *ws, size_t bytes);
  * must run again before the next solve (SSAMG_ERR_STATE otherwise). */
 ssamg_status ssamg_update_coeffs(ssamg_solver s, int part, const double *vals, int where);
 
-/* Solve A X = B for nrhs right-hand sides (1 <= nrhs <= max_nrhs, power of two).
- * b, x: device, [N][nrhs] doubles (right-hand side index fastest; for nrhs = 1
- * a plain vector).  x0 = 0.  Returns SSAMG_NOT_CONVERGED when some right-hand
- * side did not meet tol within max_iter.  info may be NULL. */
-ssamg_status ssamg_solve(ssamg_solver s, int nrhs, const double *b, double *x, ssamg_info *info);
+/* Solve A X = B for nrhs right-hand sides (1 <= nrhs <= max_nrhs, power of two)
+ * by PCG with one V(1,1) cycle as preconditioner (Section 4 protocol).
+ * b, x: device, N * nrhs doubles each, laid out as `layout` says:
+ *   SSAMG_LAYOUT_CELL_MAJOR  [N][nrhs], right-hand side index fastest (the
+ *                            library's own layout);
+ *   SSAMG_LAYOUT_RHS_MAJOR   [nrhs][N], one contiguous vector per right-hand
+ *                            side (transposed into the library's layout and
+ *                            back, through two device buffers of N * nrhs
+ *                            doubles that the solver allocates on first use).
+ * For nrhs = 1 both layouts are the same plain vector.  x0 = 0.  Returns
+ * SSAMG_NOT_CONVERGED when some right-hand side did not meet tol within
+ * max_iter.  info may be NULL. */
+ssamg_status ssamg_solve(ssamg_solver s, int nrhs, const double *b, double *x, int layout,
+                         ssamg_info *info);
 
 /* Launch options of the batched V-cycle (batch widths of 4 or more right-hand
  * sides), per level and width.  They choose how the kernels cover a level, not
@@ -271,6 +303,8 @@ ssamg_status ssamg_apply_A(ssamg_solver s, int level, const double *x, double *y
 ssamg_status ssamg_apply_precond(ssamg_solver s, const double *r, double *z);
 
 ssamg_status ssamg_num_levels(ssamg_solver s, int *nlevels);
+/* Cells N_l of level `level` (all parts). */
+ssamg_status ssamg_level_cells(ssamg_solver s, int level, int64_t *ncell);
 ssamg_status ssamg_level_info(ssamg_solver s, int level, int part, ssamg_level_desc *info);
 
 /* c[p][d] of Section 3.1 as reduced on the device (host out, nparts*3). */

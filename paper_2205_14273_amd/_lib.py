@@ -30,6 +30,10 @@ COARSE_SWEEP = 0
 COARSE_DIRECT = 1
 FP64 = 0
 FP32 = 1
+PB_ONE = 0
+PB_LUMP = 1
+LAYOUT_CELL_MAJOR = 0
+LAYOUT_RHS_MAJOR = 1
 PROBE_NONE = -1
 PROBE_MATVEC = 0
 PROBE_SMOOTH0 = 1
@@ -47,13 +51,13 @@ class ssamg_params(C.Structure):
                 ("omega", C.c_double), ("coarse", C.c_int), ("cycle_precision", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
                 ("use_graph", C.c_int), ("skip", C.c_int), ("autotune", C.c_int),
-                ("symmetric", C.c_int)]
+                ("symmetric", C.c_int), ("pb_interp", C.c_int)]
 
 
 class ssamg_info(C.Structure):
     _fields_ = [("nrhs", C.c_int), ("iters", C.c_int * 32), ("relres", C.c_double * 32),
                 ("true_relres", C.c_double * 32), ("converged", C.c_int * 32),
-                ("t_solve", C.c_double)]
+                ("t_setup", C.c_double), ("t_solve", C.c_double)]
 
 
 class ssamg_level_desc(C.Structure):
@@ -80,10 +84,12 @@ SIGNATURES = {
     "ssamg_problem_set_face": [P, I, I, I],
     "ssamg_problem_set_stencil": [P, I, I, PI],
     "ssamg_problem_set_coeffs": [P, I, P, I, I],
-    "ssamg_problem_set_coupling": [P, I64, PI64, PI64, PD],
+    "ssamg_problem_set_coupling": [P, I64, P, P, P, I],
     "ssamg_problem_fv_assemble": [P, P, PD, I, P],
-    "ssamg_problem_fv_grad": [P, P, P, P, P],
+    "ssamg_problem_fv_grad": [P, I, P, P, P, P],
     "ssamg_problem_num_cells": [P, PI64],
+    "ssamg_problem_num_parts": [P, PI],
+    "ssamg_problem_part_size": [P, I, PI, PI64],
     "ssamg_params_default": [C.POINTER(ssamg_params)],
     "ssamg_solver_create": [P, C.POINTER(ssamg_params), P, PP],
     "ssamg_update_coeffs": [P, I, P, I],
@@ -94,10 +100,11 @@ SIGNATURES = {
     "ssamg_setup_symbolic": [P],
     "ssamg_workspace_bytes": [P, C.POINTER(C.c_size_t)],
     "ssamg_setup_numeric": [P, P, C.c_size_t],
-    "ssamg_solve": [P, I, P, P, C.POINTER(ssamg_info)],
+    "ssamg_solve": [P, I, P, P, I, C.POINTER(ssamg_info)],
     "ssamg_apply_A": [P, I, P, P],
     "ssamg_apply_precond": [P, P, P],
     "ssamg_num_levels": [P, PI],
+    "ssamg_level_cells": [P, I, PI64],
     "ssamg_level_info": [P, I, I, C.POINTER(ssamg_level_desc)],
     "ssamg_direction_sums": [P, PD],
     "ssamg_copy_stencil": [P, I, I, PD],

@@ -73,13 +73,8 @@ class _SSAMGSolve(torch.autograd.Function):
         lam = fv._solve(kappa, gx.contiguous())
         grad_kappa = None
         if ctx.needs_input_grad[0]:
-            if x.dim() == 1:
-                grad_kappa = fv.problem.fv_grad(lam, x)
-            else:
-                # one gradient pass per right-hand side; the contributions add up
-                grad_kappa = torch.zeros_like(kappa)
-                for k in range(x.shape[1]):
-                    grad_kappa += fv.problem.fv_grad(lam[:, k].contiguous(), x[:, k].contiguous())
+            # one kernel pass sums the contributions of every right-hand side
+            grad_kappa = fv.problem.fv_grad(lam, x)
         grad_b = lam if ctx.needs_input_grad[1] else None
         return grad_kappa, grad_b, None
 

@@ -116,6 +116,7 @@ ssamg_status ssamg_params_default(ssamg_params *p) {
   p->skip = 0;
   p->autotune = 0;
   p->symmetric = 1;
+  p->pb_interp = SSAMG_PB_ONE;
   API_END
 }
 
@@ -137,6 +138,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (p.skip != 0 && p.skip != 1) throw Error(SSAMG_ERR_ARG, "skip must be 0 or 1");
   if (p.autotune != 0 && p.autotune != 1) throw Error(SSAMG_ERR_ARG, "autotune must be 0 or 1");
   if (p.symmetric != 0 && p.symmetric != 1) throw Error(SSAMG_ERR_ARG, "symmetric must be 0 or 1");
+  if (p.pb_interp != SSAMG_PB_ONE && p.pb_interp != SSAMG_PB_LUMP)
+    throw Error(SSAMG_ERR_ARG, "pb_interp must be SSAMG_PB_ONE or SSAMG_PB_LUMP");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)
     throw Error(SSAMG_ERR_ARG, "cycle_precision must be SSAMG_FP64 or SSAMG_FP32");
   if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw Error(SSAMG_ERR_ARG, "tol must be positive");
@@ -165,6 +168,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (split && split[0]) s->split_cells = std::max<int64_t>(0, std::atoll(split));
   const char *coll = std::getenv("SSAMG_COLLAPSE_CELLS");
   if (coll && coll[0]) s->collapse_cells = std::max<int64_t>(0, std::atoll(coll));
+  const char *rapmin = std::getenv("SSAMG_RAP_CELL_MIN");
+  if (rapmin && rapmin[0]) s->rap_cell_min = std::max<int64_t>(0, std::atoll(rapmin));
   const char *rsort = std::getenv("SSAMG_ROW_SORT");
   if (rsort && rsort[0]) s->scratch.row_sort = std::max<int64_t>(0, std::atoll(rsort));
   const char *hsym = std::getenv("SSAMG_HOST_SYM");
@@ -175,6 +180,10 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
     throw Error(SSAMG_ERR_ALLOC, "hipHostMalloc failed");
   }
   s->h_pin = (double *)pin;
+  if (hipEventCreateWithFlags(&s->ev_scal, hipEventDisableTiming) != hipSuccess) {
+    delete s;
+    throw Error(SSAMG_ERR_DEVICE, "hipEventCreateWithFlags failed");
+  }
   *out = reinterpret_cast<ssamg_solver>(s);
   API_END
 }
@@ -215,7 +224,8 @@ ssamg_status ssamg_update_coeffs(ssamg_solver h, int part, const double *vals, i
   API_END
 }
 
-ssamg_status ssamg_solve(ssamg_solver h, int nrhs, const double *b, double *x, ssamg_info *info) {
+ssamg_status ssamg_solve(ssamg_solver h, int nrhs, const double *b, double *x, int layout,
+                         ssamg_info *info) {
   Solver *s = nullptr;
   try {
     s = S(h);
@@ -223,7 +233,25 @@ ssamg_status ssamg_solve(ssamg_solver h, int nrhs, const double *b, double *x, s
     if (!b || !x) throw Error(SSAMG_ERR_ARG, "NULL vector");
     if (nrhs < 1 || nrhs > s->prm.max_nrhs || (nrhs & (nrhs - 1)))
       throw Error(SSAMG_ERR_ARG, "nrhs must be a power of two <= max_nrhs");
-    const ssamg_status st = pcg_solve(*s, nrhs, b, x, info);
+    if (layout != SSAMG_LAYOUT_CELL_MAJOR && layout != SSAMG_LAYOUT_RHS_MAJOR)
+      throw Error(SSAMG_ERR_ARG, "layout must be SSAMG_LAYOUT_CELL_MAJOR or SSAMG_LAYOUT_RHS_MAJOR");
+    ssamg_status st;
+    if (layout == SSAMG_LAYOUT_RHS_MAJOR && nrhs > 1) {
+      const int lg = width_lg(s, nrhs);
+      const int64_t n = s->lv[0].N;
+      const size_t bytes = (size_t)n * nrhs * sizeof(double);
+      s->lay_b.reserve(bytes);
+      s->lay_x.reserve(bytes);
+      double *bt = (double *)s->lay_b.p, *xt = (double *)s->lay_x.p;
+      launch_transpose(b, bt, n, lg, 1, s->stream);
+      SSAMG_HIP(hipGetLastError());
+      st = pcg_solve(*s, nrhs, bt, xt, info);
+      launch_transpose(xt, x, n, lg, 0, s->stream);
+      SSAMG_HIP(hipGetLastError());
+      SSAMG_HIP(hipStreamSynchronize(s->stream));
+    } else {
+      st = pcg_solve(*s, nrhs, b, x, info);
+    }
     set_last_error(st == SSAMG_OK ? "" : "not converged within max_iter");
     return st;
   } catch (const Error &e) {
@@ -307,6 +335,16 @@ ssamg_status ssamg_apply_precond(ssamg_solver h, const double *r, double *z) {
   need(s, 2, "setup_numeric must come first");
   if (!r || !z) throw Error(SSAMG_ERR_ARG, "NULL vector");
   apply_precond(*s, r, z);
+  API_END
+}
+
+ssamg_status ssamg_level_cells(ssamg_solver h, int level, int64_t *ncell) {
+  API_BEGIN
+  Solver *s = S(h);
+  need(s, 1, "setup_symbolic must come first");
+  check_level(s, level);
+  if (!ncell) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *ncell = s->lv[level].N;
   API_END
 }
 

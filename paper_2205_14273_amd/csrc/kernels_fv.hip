@@ -10,7 +10,9 @@
 //   stencil S, cross-part entries the couplings U.
 // Gradient of L(x): dL/dkappa_c = -lambda^T (dA/dkappa_c) x with A lambda = dL/dx,
 //   i.e. minus the sum over the links of c of dt/dkappa_c times
-//   (lambda_c - lambda_j)(x_c - x_j), or lambda_c x_c for a ghost link.
+//   (lambda_c - lambda_j)(x_c - x_j), or lambda_c x_c for a ghost link.  With
+//   several right-hand sides (x and lambda [cell][nrhs]) the loss is the sum
+//   over the columns, and so is each link's factor.
 #include "device_util.h"
 #include "ssamg_impl.h"
 
@@ -135,10 +137,27 @@ __global__ __launch_bounds__(kBlock) void k_fv_coupling(int nrow, const int *__r
   }
 }
 
+// sum over the nrhs right-hand sides k of (lam_i,k - lam_j,k)(x_i,k - x_j,k)
+// (vectors [cell][nrhs], right-hand side fastest)
+__device__ __forceinline__ double pair_sum(const double *__restrict__ lam, const double *__restrict__ x,
+                                           long long i, long long j, int nrhs) {
+  double s = 0.0;
+  for (int k = 0; k < nrhs; ++k)
+    s += (lam[i * nrhs + k] - lam[j * nrhs + k]) * (x[i * nrhs + k] - x[j * nrhs + k]);
+  return s;
+}
+
+__device__ __forceinline__ double self_sum(const double *__restrict__ lam, const double *__restrict__ x,
+                                           long long i, int nrhs) {
+  double s = 0.0;
+  for (int k = 0; k < nrhs; ++k) s += lam[i * nrhs + k] * x[i * nrhs + k];
+  return s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fv_grad(FvArgs fa, const double *__restrict__ kappa,
                                                     const double *__restrict__ aniso,
                                                     const double *__restrict__ lam,
-                                                    const double *__restrict__ x,
+                                                    const double *__restrict__ x, int nrhs,
                                                     double *__restrict__ grad) {
   const int p = blockIdx.y;
   const Geo me = geo_of(fa.geom, p);
@@ -148,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_fv_grad(FvArgs fa, const double *__r
   const int loc[3] = {(int)(c % me.n[0]), (int)((c / me.n[0]) % me.n[1]),
                       (int)(c / ((long long)me.n[0] * me.n[1]))};
   const long long gi = me.off + c;
-  const double kc = kappa[gi], lc = lam[gi], xc = x[gi];
+  const double kc = kappa[gi];
   double acc = 0.0;
   for (int s = 1; s < fa.nent; ++s) {
     const int code = fa.code[s];
@@ -165,11 +184,11 @@ __global__ __launch_bounds__(kBlock) void k_fv_grad(FvArgs fa, const double *__r
       const long long gj = me.off + nb[0] + (long long)me.n[0] * (nb[1] + (long long)me.n[1] * nb[2]);
       const double xj = as * kappa[gj];
       const double dt = gw * as * 2.0 * xj * xj / ((xi + xj) * (xi + xj));
-      acc += dt * (lc - lam[gj]) * (xc - x[gj]);
+      acc += dt * pair_sum(lam, x, gi, gj, nrhs);
     } else {
       const int G[3] = {me.o[0] + nb[0], me.o[1] + nb[1], me.o[2] + nb[2]};
       int cell = 0;
-      if (find_part(fa.geom, fa.nparts, p, G, cell) < 0) acc += gw * as * lc * xc;
+      if (find_part(fa.geom, fa.nparts, p, G, cell) < 0) acc += gw * as * self_sum(lam, x, gi, nrhs);
     }
   }
   grad[gi] = -acc;
@@ -182,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_fv_grad_u(int nrow, const int *__res
                                                       const double *__restrict__ kappa,
                                                       const double *__restrict__ aniso,
                                                       const double *__restrict__ lam,
-                                                      const double *__restrict__ x,
+                                                      const double *__restrict__ x, int nrhs,
                                                       double *__restrict__ grad) {
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= nrow) return;
@@ -196,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_fv_grad_u(int nrow, const int *__res
     const double xi = ai * kappa[i];
     const double xj = link_factor(aniso, pj, code) * kappa[j];
     const double dt = geom_weight(code) * ai * 2.0 * xj * xj / ((xi + xj) * (xi + xj));
-    acc += dt * (lam[i] - lam[j]) * (x[i] - x[j]);
+    acc += dt * pair_sum(lam, x, i, j, nrhs);
   }
   grad[i] -= acc;
 }
@@ -221,12 +240,12 @@ void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *u
 }
 
 void launch_fv_grad(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
-                    const double *lam, const double *x, double *grad, int nrow, const int *urow,
+                    const double *lam, const double *x, int nrhs, double *grad, int nrow, const int *urow,
                     const int *uptr, const int *ucol, const int *ucode, hipStream_t st) {
-  k_fv_grad<<<dim3(nblk(maxcell), fa.nparts), kBlock, 0, st>>>(fa, kappa, aniso, lam, x, grad);
+  k_fv_grad<<<dim3(nblk(maxcell), fa.nparts), kBlock, 0, st>>>(fa, kappa, aniso, lam, x, nrhs, grad);
   if (nrow > 0)
     k_fv_grad_u<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, ucol, ucode, kappa, aniso, lam, x,
-                                               grad);
+                                               nrhs, grad);
 }
 
 }  // namespace ssamg

@@ -232,6 +232,41 @@ __global__ __launch_bounds__(kBlock) void k_resid_partial(const double *__restri
   if ((int)threadIdx.x < nr) partial[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
 }
 
+// Layout change between [nrhs][N] (one vector per right-hand side) and the
+// library's [N][nrhs]: a block moves a tile of kTrCells cells x nrhs columns
+// through LDS, so both the read and the write are unit-stride across lanes.
+constexpr int kTrCells = 128;
+__global__ __launch_bounds__(kBlock) void k_transpose(const double *__restrict__ in,
+                                                      double *__restrict__ out, long long n, int lg,
+                                                      int to_cell_major) {
+  __shared__ double tile[kMaxRhs][kTrCells + 1];
+  const int nrhs = 1 << lg;
+  const long long c0 = (long long)blockIdx.x * kTrCells;
+  const int nc = (int)min((long long)kTrCells, n - c0);
+  const int tot = nrhs * kTrCells;
+  for (int t = threadIdx.x; t < tot; t += kBlock) {
+    // column-major side: [nrhs][N], cells fastest
+    const int k = t / kTrCells, cc = t % kTrCells;
+    // cell-major side: [N][nrhs], right-hand sides fastest
+    const int cm = t >> lg, km = t & (nrhs - 1);
+    if (to_cell_major) {
+      if (cc < nc) tile[k][cc] = in[(long long)k * n + c0 + cc];
+    } else {
+      if (cm < nc) tile[km][cm] = in[(c0 + cm) * nrhs + km];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < tot; t += kBlock) {
+    const int k = t / kTrCells, cc = t % kTrCells;
+    const int cm = t >> lg, km = t & (nrhs - 1);
+    if (to_cell_major) {
+      if (cm < nc) out[(c0 + cm) * nrhs + km] = tile[km][cm];
+    } else {
+      if (cc < nc) out[(long long)k * n + c0 + cc] = tile[k][cc];
+    }
+  }
+}
+
 inline unsigned grid_stream(long long n) {
   long long nb = (n + kBlock - 1) / kBlock;
   if (nb > 4096) nb = 4096;
@@ -247,6 +282,11 @@ inline unsigned red_blocks(long long nel) {
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+
+void launch_transpose(const double *in, double *out, int64_t n, int lg, int to_cell_major, hipStream_t st) {
+  if (n > 0)
+    k_transpose<<<(unsigned)((n + kTrCells - 1) / kTrCells), kBlock, 0, st>>>(in, out, n, lg, to_cell_major);
+}
 
 void launch_cast_d2f(const double *in, float *out, int64_t n, hipStream_t st) {
   if (n > 0) k_cast_d2f<<<grid_stream(n), kBlock, 0, st>>>(in, out, n);

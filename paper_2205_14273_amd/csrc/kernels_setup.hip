@@ -20,14 +20,16 @@ __device__ __forceinline__ void cell_ijk(int c, int nx, int ny, int &i, int &j, 
 __device__ __forceinline__ int off_comp(int code, int d) { return ((code >> (2 * d)) & 3) - 1; }
 
 // Zero every coefficient whose neighbour lies outside the box; flag a
-// nonpositive or non-finite diagonal or a non-finite coefficient.
+// nonpositive or non-finite diagonal or a non-finite coefficient, and
+// (separately) an in-box pair that breaks a_s(c) = a_{-s}(c+s).  Both members
+// of an in-box pair keep their values, so the test reads them unchanged.
 __global__ __launch_bounds__(kBlock) void k_normalise(BoxStencil bs, int *__restrict__ flag) {
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (c >= bs.ncell) return;
   int i, j, k;
   cell_ijk((int)c, bs.n[0], bs.n[1], i, j, k);
   const int p[3] = {i, j, k};
-  int bad = 0;
+  int bad = 0, asym = 0;
   for (int s = 0; s < bs.nent; ++s) {
     bool in = true;
     for (int d = 0; d < 3; ++d) {
@@ -35,12 +37,21 @@ __global__ __launch_bounds__(kBlock) void k_normalise(BoxStencil bs, int *__rest
       in = in && q >= 0 && q < bs.n[d];
     }
     double *a = bs.coef + (long long)s * bs.ncell + c;
+    const double v = in ? *a : 0.0;
     if (!in) *a = 0.0;
-    const double v = *a;
     if (!isfinite(v)) bad = 1;
     if (s == bs.center && !(v > 0.0)) bad = 1;
+    if (in && s != bs.center) {
+      if (bs.mir[s] < 0) {
+        asym = 1;
+      } else {
+        const double m = bs.coef[(long long)bs.mir[s] * bs.ncell + c + bs.lin[s]];
+        if (!(fabs(v - m) <= 1e-12 * fmax(fabs(v), fabs(m)))) asym = 1;
+      }
+    }
   }
   if (bad) flag[0] = 1;
+  if (asym) flag[1] = 1;
 }
 
 // c_d of Section 3.1 for each part: sum over cells of minus the off-diagonal
@@ -93,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_wsum_final(const double *__restrict_
 //   den = sum of the coefficients with zero d* component,
 //   wm = -(sum of those at -1)/den, wp = -(sum of those at +1)/den;
 // a coarse neighbour outside the box is absent (weight 0); if it lies across a
-// part face the opposite weight becomes 1 (Section 3.2).  Where den is not
+// part face the opposite weight becomes 1 (Section 3.2), or, in the lumped
+// reading, takes the dropped weight of the row's couplings on top.  Where den is not
 // positive (the collapse is undefined; it happens on Galerkin operators of
 // strongly heterogeneous problems) the two off-plane sums are normalised by
 // their total so constants are interpolated, or 1/2 each if that total is not
@@ -140,12 +152,30 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
     wm = 0.5;
     wp = 0.5;
   }
-  if (!isfinite(wm) || !isfinite(wp)) flag[0] = 1;
   const bool hi_out = f[ds] + 1 > d.n[ds] - 1;   // lower corner 0: f-1 >= 0 always
   if (hi_out) {
     wp = 0.0;
-    if ((d.faces >> (2 * ds + 1)) & 1) wm = 1.0;
+    if ((d.faces >> (2 * ds + 1)) & 1) {
+      if (d.pblump && den > 0.0) {
+        // lumped reading: the dropped weight is the collapse of the row's
+        // couplings, -(sum_j u_fj)/den, added to the opposite one.  The row
+        // of cell c lies among the stored rows of its 256-cell block.
+        const auto ub = dev::G(d.ublk[0]) + 2 * (c / kBlock);
+        const int r0 = ub[0], r1 = ub[2];
+        const int cell = (int)(d.off + c);
+        double us = 0.0;
+        for (int r = r0; r < r1; ++r) {
+          if (dev::G(d.urow)[r] != cell) continue;
+          for (int q = dev::G(d.uptr)[r]; q < dev::G(d.uptr)[r + 1]; ++q) us += dev::G(d.uval)[q];
+          break;
+        }
+        wm = -(sm + us) / den;
+      } else {
+        wm = 1.0;
+      }
+    }
   }
+  if (!isfinite(wm) || !isfinite(wp)) flag[0] = 1;
   dev::Gw(const_cast<double *>(d.wm))[fidx] = wm;
   dev::Gw(const_cast<double *>(d.wp))[fidx] = wp;
   if (desc32) {
@@ -580,8 +610,8 @@ void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, in
 }
 
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
-                int maxent_c, hipStream_t st) {
-  if ((int64_t)maxcoarse * nparts >= kRapCellMin) {
+                int maxent_c, int64_t cell_min, hipStream_t st) {
+  if ((int64_t)maxcoarse * nparts >= cell_min) {
     k_rap<<<dim3(nblk(maxcoarse), nparts), kBlock, 0, st>>>(desc, rd);
   } else {
     // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies

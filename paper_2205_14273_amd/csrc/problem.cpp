@@ -164,6 +164,7 @@ ssamg_status ssamg_problem_create(int ndim, int nparts, ssamg_problem *out) {
   pr->center.assign(nparts, -1);
   pr->coef.assign(nparts, nullptr);
   pr->coef_set.assign(nparts, 0);
+  pr->sym_ok.assign(nparts, 1);
   *out = reinterpret_cast<ssamg_problem>(pr);
   API_END
 }
@@ -278,29 +279,53 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
   bs.nent = nent;
   bs.center = pr->center[part];
   bs.ncell = ncell;
-  for (int e = 0; e < nent; ++e)
-    bs.code[e] = pack_off(pr->stencil[part][e][0], pr->stencil[part][e][1], pr->stencil[part][e][2]);
+  for (int e = 0; e < nent; ++e) {
+    const auto &o = pr->stencil[part][e];
+    bs.code[e] = pack_off(o[0], o[1], o[2]);
+    bs.lin[e] = o[0] + bs.n[0] * (o[1] + bs.n[1] * o[2]);
+    bs.mir[e] = -1;
+    for (int f = 0; f < nent; ++f) {
+      const auto &t = pr->stencil[part][f];
+      if (t[0] == -o[0] && t[1] == -o[1] && t[2] == -o[2]) bs.mir[e] = f;
+    }
+  }
   bs.coef = dst;
-  int *flag = dev_alloc<int>(1);
-  SSAMG_HIP(hipMemset(flag, 0, sizeof(int)));
+  int *flag = dev_alloc<int>(2);
+  SSAMG_HIP(hipMemset(flag, 0, 2 * sizeof(int)));
   launch_normalise(bs, flag, nullptr);
-  int hflag = 0;
-  SSAMG_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+  int hflag[2] = {0, 0};
+  SSAMG_HIP(hipMemcpy(hflag, flag, 2 * sizeof(int), hipMemcpyDeviceToHost));
   (void)hipFree(flag);
   SSAMG_HIP(hipGetLastError());
   pr->coef_set[part] = 1;
+  pr->sym_ok[part] = hflag[1] == 0;
   pr->fv_structure_ready = false;
-  if (hflag) throw Error(SSAMG_ERR_NUMERIC, "nonpositive diagonal or non-finite coefficient");
+  if (hflag[0]) throw Error(SSAMG_ERR_NUMERIC, "nonpositive diagonal or non-finite coefficient");
   API_END
 }
 
 ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const int64_t *row,
-                                        const int64_t *col, const double *val) {
+                                        const int64_t *col, const double *val, int where) {
   API_BEGIN
   Problem *pr = P(prob);
   if (nnz < 0) throw Error(SSAMG_ERR_ARG, "negative nnz");
   if (nnz > 0 && (!row || !col || !val)) throw Error(SSAMG_ERR_ARG, "NULL coupling arrays");
+  if (where != SSAMG_MEM_HOST && where != SSAMG_MEM_DEVICE) throw Error(SSAMG_ERR_ARG, "bad memory kind");
   for (int p = 0; p < pr->nparts; ++p) check_box(pr, p);
+  // device COO: the canonical form is built on the host from a copy
+  std::vector<int64_t> hrow, hcol;
+  std::vector<double> hval;
+  if (where == SSAMG_MEM_DEVICE && nnz > 0) {
+    hrow.resize(nnz);
+    hcol.resize(nnz);
+    hval.resize(nnz);
+    SSAMG_HIP(hipMemcpy(hrow.data(), row, nnz * sizeof(int64_t), hipMemcpyDeviceToHost));
+    SSAMG_HIP(hipMemcpy(hcol.data(), col, nnz * sizeof(int64_t), hipMemcpyDeviceToHost));
+    SSAMG_HIP(hipMemcpy(hval.data(), val, nnz * sizeof(double), hipMemcpyDeviceToHost));
+    row = hrow.data();
+    col = hcol.data();
+    val = hval.data();
+  }
   const auto off = pr->offsets();
   const int64_t N = off.back();
   auto part_of = [&](int64_t id) {
@@ -328,6 +353,24 @@ ssamg_status ssamg_problem_num_cells(ssamg_problem prob, int64_t *n) {
   Problem *pr = P(prob);
   if (!n) throw Error(SSAMG_ERR_ARG, "NULL output");
   *n = pr->ncell_total();
+  API_END
+}
+
+ssamg_status ssamg_problem_num_parts(ssamg_problem prob, int *nparts) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  if (!nparts) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *nparts = pr->nparts;
+  API_END
+}
+
+ssamg_status ssamg_problem_part_size(ssamg_problem prob, int part, int *nent, int64_t *ncell) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  if (!nent || !ncell) throw Error(SSAMG_ERR_ARG, "NULL output");
+  *nent = (int)pr->stencil[part].size();
+  *ncell = (int64_t)pr->dims[part][0] * pr->dims[part][1] * pr->dims[part][2];
   API_END
 }
 
@@ -372,6 +415,7 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
     pr->stencil[p] = st_off;
     pr->center[p] = 0;
     pr->coef_set[p] = 1;
+    pr->sym_ok[p] = 1;   // two-point conductances are symmetric by construction
   }
   // the face kinds, the geometry table and the coupling structure depend on
   // the placement and the stencil only: rebuilt when those change
@@ -487,12 +531,13 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
   API_END
 }
 
-ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, const double *lambda, const double *x,
+ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, int nrhs, const double *lambda, const double *x,
                                    double *grad, void *hip_stream) {
   API_BEGIN
   Problem *pr = P(prob);
   if (!pr->fv_stencil) throw Error(SSAMG_ERR_STATE, "fv_assemble has not been called");
   if (!lambda || !x || !grad) throw Error(SSAMG_ERR_ARG, "NULL vector");
+  if (nrhs < 1 || nrhs > kMaxRhs) throw Error(SSAMG_ERR_ARG, "nrhs must be in 1..32");
   hipStream_t st = (hipStream_t)hip_stream;
   const auto st_off = fv_offsets(pr->fv_stencil, pr->ndim);
   FvArgs fa{};
@@ -503,7 +548,7 @@ ssamg_status ssamg_problem_fv_grad(ssamg_problem prob, const double *lambda, con
   const auto off = pr->offsets();
   int64_t maxcell = 0;
   for (int p = 0; p < pr->nparts; ++p) maxcell = std::max(maxcell, off[p + 1] - off[p]);
-  launch_fv_grad(fa, (int)maxcell, pr->d_kappa, pr->d_aniso, lambda, x, grad, (int)pr->urow.size(),
+  launch_fv_grad(fa, (int)maxcell, pr->d_kappa, pr->d_aniso, lambda, x, nrhs, grad, (int)pr->urow.size(),
                  pr->d_urow, pr->d_uptr, pr->d_ucol, pr->d_ucode, st);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(st));

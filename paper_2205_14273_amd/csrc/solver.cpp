@@ -135,6 +135,15 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
     throw Error(SSAMG_ERR_STATE, "internal: Galerkin table longer than kRapMaxTab");
 }
 
+// The FP64 product reads mirrored entries when the caller declares A symmetric
+// and every part's given coefficients passed the symmetry test of set_coeffs.
+bool mirrored(const Solver &s) {
+  if (s.prm.symmetric == 0) return false;
+  for (int ok : s.prob->sym_ok)
+    if (!ok) return false;
+  return true;
+}
+
 // Mirror reads of a symmetric stencil (see PartDesc::mir): an offset is
 // positive when its last nonzero component (z, then y, then x) is positive.
 bool positive_offset(const std::array<int, 3> &o) {
@@ -247,8 +256,9 @@ void build_descs(const Solver &s, int l, std::vector<PartDesc<double>> &h64,
   for (size_t p = 0; p < V.parts.size(); ++p) {
     const PartLevel &q = V.parts[p];
     // mirror tables for the FP64 product (used only by its mirrored kernels)
-    const bool sym = s.prm.symmetric != 0;
+    const bool sym = mirrored(s);
     h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64, mv, sym));
+    h64.back().pblump = s.prm.pb_interp == SSAMG_PB_LUMP;
     if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32, cyc, false));
   }
 }
@@ -843,6 +853,8 @@ void setup_symbolic(Solver &s) {
   s.sig.clear();
   for (int l = 0; l < (int)s.lv.size(); ++l) s.sig.push_back(level_sig(s, l));
   s.state = 1;
+  s.t_sym = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  s.t_num = 0.0;
   if (s.verbose) {
     size_t unnz = 0, contrib = 0;
     for (auto &L : s.lv) {
@@ -1099,7 +1111,7 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
     launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
-    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, st);
+    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, s.rap_cell_min, st);
     launch_uc_numeric(C.nnz, C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
     smoother_scale(l + 1);
@@ -1143,6 +1155,7 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
             std::chrono::duration<double, std::milli>(t2 - t1).count());
   if (hflag == 2) throw Error(SSAMG_ERR_NUMERIC, "coarsest operator is not positive definite (direct solve)");
   if (hflag) throw Error(SSAMG_ERR_NUMERIC, "non-finite interpolation weight");
+  s.t_num = std::chrono::duration<double>(t2 - t0).count();
   s.state = 2;
 }
 
@@ -1164,7 +1177,7 @@ double level0_bytes(const Solver &s, int kind, int lg, size_t tc, size_t tx, siz
   double by = 0.0;
   for (const auto &q : V.parts) {
     // the FP64 product streams the mirrored subset (see build_descs)
-    const bool mir = kind == SSAMG_PROBE_MATVEC && s.prm.symmetric != 0 && q.pat.size() > 7;
+    const bool mir = kind == SSAMG_PROBE_MATVEC && mirrored(s) && q.pat.size() > 7;
     const double n = (double)q.ncell, ne = (double)streamed_entries(q, mir);
     switch (kind) {
       case SSAMG_PROBE_MATVEC: by += n * (ne * tc + nr * (tx + to)); break;
@@ -1409,7 +1422,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
     launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
                                            V.maxcell, lg, x, nullptr, y, s.stream, pr.e, cols4,
-                                           dot ? s.dotp : nullptr, nullptr, s.prm.symmetric != 0);
+                                           dot ? s.dotp : nullptr, nullptr, mirrored(s));
   }
   if (dot) {
     const bool c4 = cols4 != 0 && stencil_cols4_ok<double>(lg, V.maxent);
@@ -1424,7 +1437,7 @@ void apply_level(Solver &s, int level, const double *x, double *y) {
   Level &V = s.lv[level];
   launch_stencil<double, double, double>(MODE_APPLY, level == 0, V.maxent, V.d_desc64, (int)V.parts.size(),
                                          V.maxcell, 0, x, nullptr, y, s.stream, {}, -1, nullptr, nullptr,
-                                         s.prm.symmetric != 0);
+                                         mirrored(s));
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(s.stream));
 }
@@ -1569,7 +1582,7 @@ int autotune_t(Solver &s, int lg) {
           const TuneRec o = tune_rec(s, 0, lg);
           launch_stencil<double, double, double>(MODE_APPLY_DOT, 1, V.maxent, V.d_desc64, np, V.maxcell, lg,
                                                  s.p, nullptr, s.q, st, {}, o.cols4_mv, s.dotp, nullptr,
-                                                 s.prm.symmetric != 0);
+                                                 mirrored(s));
         });
       }
       ++ntuned;
@@ -1661,7 +1674,6 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   launch_copy(b, s.r, nel, st);
   launch_dot(b, b, nel, lg, s.partial, s.scal, S_BB, 0, st);
   SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
-  if (!s.ev_scal) SSAMG_HIP(hipEventCreateWithFlags(&s.ev_scal, hipEventDisableTiming));
   SSAMG_HIP(hipEventRecord(s.ev_scal, st));
   // the first direction does not depend on which right-hand sides are zero
   // (none of its kernels reads the active mask): queued before |b| is read
@@ -1760,6 +1772,7 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
       info->true_relres[k] = bb[k] > 0.0 ? std::sqrt(h[S_TR * kMaxRhs + k] / bb[k]) : 0.0;
       info->converged[k] = conv[k];
     }
+    info->t_setup = s.t_sym + s.t_num;
     info->t_solve = std::chrono::duration<double>(t1 - t0).count();
   }
   return all ? SSAMG_OK : SSAMG_NOT_CONVERGED;

@@ -104,7 +104,7 @@ struct PartDesc {
   int faces;           // bit f set: face f (-x,+x,-y,+y,-z,+z) is a part boundary
   int fn[3];           // F-box extents (cells odd along dstar)
   int cn[3];           // coarse box extents
-  int pad0;
+  int pblump;          // 1: lumped part-boundary interpolation (SSAMG_PB_LUMP)
   long long off;       // first cell of the part in the level vector
   long long ncell;
   long long coff;      // first cell of the part in the next level vector
@@ -157,6 +157,9 @@ struct Problem {
   std::vector<int> center;
   std::vector<double *> coef;        // device [nent][ncell] per part, problem-owned
   std::vector<int> coef_set;
+  // 1: the part's given coefficients satisfy a_s(c) = a_{-s}(c+s) to a relative
+  // 1e-12 (checked by set_coeffs; finite-volume assembly is symmetric)
+  std::vector<int> sym_ok;
   // couplings, canonical compressed-row CSR (host copy + device copy)
   std::vector<int> urow, uptr, ucol;
   std::vector<double> uval_host;
@@ -286,10 +289,14 @@ struct Solver {
   int64_t split_cells = kSplitCells; // SSAMG_SPLIT_CELLS overrides
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
+  int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
   int lk = -1;                       // collapse level (-1: none)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
   hipEvent_t ev_scal = nullptr;      // PCG: the scalars of an iteration have reached the host
   int state = 0;                     // 0 created, 1 symbolic done, 2 numeric done
+  double t_sym = 0.0, t_num = 0.0;   // host seconds of the last symbolic and numeric setup
+  // RHS-major solves: the right-hand sides and solutions in [N][nrhs] order
+  DevBuf lay_b, lay_x;
   std::vector<Level> lv;
   std::vector<double> cd;            // direction sums c[p][d]
   // device buffers of the symbolic setup, kept across setups
@@ -352,6 +359,8 @@ struct BoxStencil {
   int pad;
   long long ncell;
   int code[kMaxEnt];
+  int lin[kMaxEnt];    // dx + nx*(dy + ny*dz)
+  int mir[kMaxEnt];    // entry with the opposite offset, -1 if none
   double *coef;
 };
 
@@ -489,6 +498,8 @@ void launch_interp_add(const PartDesc<T> *desc, int nparts, int maxcell, int lg,
                        hipStream_t st, LaunchEvents ev = {});
 void launch_coarse_mixed(const PartDesc<double> *desc, int nparts, int maxcell, int lg, const float *b,
                          float *x, hipStream_t st);
+// [nrhs][n] -> [n][nrhs] (to_cell_major = 1) or back, nrhs = 1 << lg <= kMaxRhs
+void launch_transpose(const double *in, double *out, int64_t n, int lg, int to_cell_major, hipStream_t st);
 void launch_cast_d2f(const double *in, float *out, int64_t n, hipStream_t st);
 void launch_cast_f2d(const float *in, double *out, int64_t n, hipStream_t st);
 void launch_fill(double *x, double v, int64_t n, hipStream_t st);
@@ -508,13 +519,18 @@ void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, d
                        double *scal, int slot, hipStream_t st);
 
 // kernels_setup.hip
+// flag[0] = 1: nonpositive diagonal or non-finite coefficient; flag[1] = 1: some
+// in-box pair a_s(c), a_{-s}(c+s) differs by more than a relative 1e-12
 void launch_normalise(const BoxStencil &bs, int *flag, hipStream_t st);
 void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *partial, double *out,
                  hipStream_t st);
 void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
                            int maxf, int *flag, hipStream_t st);
+// one thread per coarse cell when the level has at least cell_min coarse cells
+// (over all parts), else one thread per (coarse cell, entry); same sums in the
+// same order either way
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
-                int maxent_c, hipStream_t st);
+                int maxent_c, int64_t cell_min, hipStream_t st);
 // weighted L1-Jacobi: cast32 (finest level, mixed precision) also receives
 // the FP32 copy of the coefficients the pass reads
 void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
@@ -547,7 +563,7 @@ void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *u
                         const int *ucode, const double *kappa, const double *aniso, double *uval,
                         hipStream_t st);
 void launch_fv_grad(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
-                    const double *lam, const double *x, double *grad, int nrow, const int *urow,
+                    const double *lam, const double *x, int nrhs, double *grad, int nrow, const int *urow,
                     const int *uptr, const int *ucol, const int *ucode, hipStream_t st);
 
 }  // namespace ssamg

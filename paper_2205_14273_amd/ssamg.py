@@ -29,6 +29,38 @@ def _ints(v):
     return a
 
 
+# The C ABI takes raw pointers and cannot see buffer sizes: a tensor of the
+# wrong dtype, device or length would make the kernels read or write out of
+# bounds.  Every device vector is therefore checked here before the call.
+
+
+def _dev_vec(t, n, name):
+    """``t`` must be a contiguous float64 tensor on the HIP device with n elements."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise TypeError(f"{name}: expected a tensor on the HIP device, got device {t.device}")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: the tensor must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    return t
+
+
+def _host_f64(a, n, name):
+    """A host float64 array of exactly n elements (numpy, or a CPU tensor)."""
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda:
+            raise TypeError(f"{name}: expected host memory")
+        a = a.detach().numpy()
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"{name}: expected {n} elements, got {a.size}")
+    return a
+
+
 # ---------------------------------------------------------------- raw ABI
 
 
@@ -59,38 +91,81 @@ def ssamg_problem_set_stencil(h, part, offsets):
     check(lib().ssamg_problem_set_stencil(h, part, len(off) // 3, _ints(off)))
 
 
+def ssamg_problem_part_size(h, part):
+    nent, ncell = C.c_int(), C.c_int64()
+    check(lib().ssamg_problem_part_size(h, part, C.byref(nent), C.byref(ncell)))
+    return nent.value, ncell.value
+
+
 def ssamg_problem_set_coeffs(h, part, vals, constant=0):
-    """vals: a CUDA float64 tensor (device) or a numpy float64 array (host)."""
-    if isinstance(vals, torch.Tensor):
-        t = vals.contiguous()
-        where = L.MEM_DEVICE if t.is_cuda else L.MEM_HOST
-        check(lib().ssamg_problem_set_coeffs(h, part, _ptr(t), where, constant))
+    """vals: a float64 tensor on the HIP device, or a host array (numpy / CPU
+    tensor) of nent * ncell values (nent with constant = 1)."""
+    nent, ncell = ssamg_problem_part_size(h, part)
+    if nent == 0:
+        raise ValueError(f"part {part}: set the stencil before the coefficients")
+    n = nent if constant else nent * ncell
+    if isinstance(vals, torch.Tensor) and vals.is_cuda:
+        t = _dev_vec(vals, n, "coefficients")
+        check(lib().ssamg_problem_set_coeffs(h, part, _ptr(t), L.MEM_DEVICE, constant))
     else:
-        a = np.ascontiguousarray(vals, dtype=np.float64)
+        a = _host_f64(vals, n, "coefficients")
         check(lib().ssamg_problem_set_coeffs(h, part, a.ctypes.data_as(C.c_void_p), L.MEM_HOST,
                                              constant))
 
 
 def ssamg_problem_set_coupling(h, rows, cols, vals):
-    r = np.ascontiguousarray(rows, dtype=np.int64)
-    c = np.ascontiguousarray(cols, dtype=np.int64)
-    v = np.ascontiguousarray(vals, dtype=np.float64)
-    check(lib().ssamg_problem_set_coupling(h, len(r), r.ctypes.data_as(L.PI64),
-                                           c.ctypes.data_as(L.PI64), v.ctypes.data_as(L.PD)))
+    """COO couplings: three host arrays, or three tensors on the HIP device
+    (int64 rows and columns, float64 values) of equal length."""
+    dev = [isinstance(a, torch.Tensor) and a.is_cuda for a in (rows, cols, vals)]
+    if any(dev):
+        if not all(dev):
+            raise TypeError("couplings: rows, cols and vals must all be device tensors or all host")
+        for t, dt, name in ((rows, torch.int64, "rows"), (cols, torch.int64, "cols"),
+                            (vals, torch.float64, "vals")):
+            if t.dtype != dt or not t.is_contiguous() or t.dim() != 1:
+                raise TypeError(f"couplings: {name} must be a contiguous 1-D {dt} tensor")
+        if not rows.numel() == cols.numel() == vals.numel():
+            raise ValueError("couplings: rows, cols and vals differ in length")
+        check(lib().ssamg_problem_set_coupling(h, rows.numel(), _ptr(rows), _ptr(cols), _ptr(vals),
+                                               L.MEM_DEVICE))
+        return
+    r = np.ascontiguousarray(rows, dtype=np.int64).reshape(-1)
+    c = np.ascontiguousarray(cols, dtype=np.int64).reshape(-1)
+    v = np.ascontiguousarray(vals, dtype=np.float64).reshape(-1)
+    if not r.size == c.size == v.size:
+        raise ValueError("couplings: rows, cols and vals differ in length")
+    check(lib().ssamg_problem_set_coupling(h, len(r), r.ctypes.data_as(C.c_void_p),
+                                           c.ctypes.data_as(C.c_void_p),
+                                           v.ctypes.data_as(C.c_void_p), L.MEM_HOST))
 
 
 def ssamg_problem_fv_assemble(h, kappa, aniso, stencil):
-    a = np.ascontiguousarray(aniso, dtype=np.float64)
+    n = ssamg_problem_num_cells(h)
+    np_ = ssamg_problem_num_parts(h)
+    _dev_vec(kappa, n, "kappa")
+    a = _host_f64(aniso, 3 * np_, "aniso")
     check(lib().ssamg_problem_fv_assemble(h, _ptr(kappa), a.ctypes.data_as(L.PD), stencil, _stream()))
 
 
 def ssamg_problem_fv_grad(h, lam, x, grad):
-    check(lib().ssamg_problem_fv_grad(h, _ptr(lam), _ptr(x), _ptr(grad), _stream()))
+    """lam, x: [N] or [N, nrhs] float64 device tensors; grad: [N]."""
+    n = ssamg_problem_num_cells(h)
+    nrhs = 1 if x.dim() == 1 else int(x.shape[1])
+    _dev_vec(lam, n * nrhs, "lambda")
+    _dev_vec(x, n * nrhs, "x")
+    _dev_vec(grad, n, "grad")
+    check(lib().ssamg_problem_fv_grad(h, nrhs, _ptr(lam), _ptr(x), _ptr(grad), _stream()))
 
 
 def ssamg_problem_num_cells(h):
     n = C.c_int64()
     check(lib().ssamg_problem_num_cells(h, C.byref(n)))
+    return n.value
+
+
+def ssamg_problem_num_parts(h):
+    n = C.c_int()
+    check(lib().ssamg_problem_num_parts(h, C.byref(n)))
     return n.value
 
 
@@ -125,6 +200,8 @@ def ssamg_setup_numeric(h, ws=None):
     if ws is None:
         check(lib().ssamg_setup_numeric(h, None, 0))
     else:
+        if not (isinstance(ws, torch.Tensor) and ws.is_cuda and ws.is_contiguous()):
+            raise TypeError("workspace: expected a contiguous tensor on the HIP device")
         check(lib().ssamg_setup_numeric(h, _ptr(ws), ws.numel() * ws.element_size()))
 
 
@@ -148,32 +225,50 @@ def ssamg_tune_set(h, level, nrhs, rec):
     check(lib().ssamg_tune_set(h, level, nrhs, arr))
 
 
-def ssamg_update_coeffs(h, part, vals, where):
-    if isinstance(vals, torch.Tensor):
-        check(lib().ssamg_update_coeffs(h, part, _ptr(vals), where))
+def ssamg_update_coeffs(h, part, vals, where, expected):
+    """New values of one part of the solver's problem; ``expected`` is the
+    part's nent * ncell (the solver handle does not expose its problem)."""
+    if where == L.MEM_DEVICE:
+        t = _dev_vec(vals, expected, "coefficients")
+        check(lib().ssamg_update_coeffs(h, part, _ptr(t), where))
     else:
-        arr = np.ascontiguousarray(vals, dtype=np.float64)
+        arr = _host_f64(vals, expected, "coefficients")
         check(lib().ssamg_update_coeffs(h, part, arr.ctypes.data_as(C.c_void_p), where))
 
 
-def ssamg_solve(h, nrhs, b, x):
+def ssamg_solve(h, nrhs, b, x, layout=L.LAYOUT_CELL_MAJOR):
+    n = ssamg_level_cells(h, 0) * nrhs
+    _dev_vec(b, n, "b")
+    _dev_vec(x, n, "x")
     info = L.ssamg_info()
-    st = lib().ssamg_solve(h, nrhs, _ptr(b), _ptr(x), C.byref(info))
+    st = lib().ssamg_solve(h, nrhs, _ptr(b), _ptr(x), layout, C.byref(info))
     check(st, allow_not_converged=True)
     return st, info
 
 
 def ssamg_apply_A(h, level, x, y):
+    n = ssamg_level_cells(h, level)
+    _dev_vec(x, n, "x")
+    _dev_vec(y, n, "y")
     check(lib().ssamg_apply_A(h, level, _ptr(x), _ptr(y)))
 
 
 def ssamg_apply_precond(h, r, z):
+    n = ssamg_level_cells(h, 0)
+    _dev_vec(r, n, "r")
+    _dev_vec(z, n, "z")
     check(lib().ssamg_apply_precond(h, _ptr(r), _ptr(z)))
 
 
 def ssamg_num_levels(h):
     n = C.c_int()
     check(lib().ssamg_num_levels(h, C.byref(n)))
+    return n.value
+
+
+def ssamg_level_cells(h, level):
+    n = C.c_int64()
+    check(lib().ssamg_level_cells(h, level, C.byref(n)))
     return n.value
 
 
@@ -274,13 +369,13 @@ class Problem:
         return pr
 
     def fv_assemble(self, kappa, aniso, stencil):
-        if not isinstance(kappa, torch.Tensor):
-            kappa = torch.as_tensor(np.asarray(kappa, dtype=np.float64), device="cuda")
-        self._kappa = kappa.to(device="cuda", dtype=torch.float64).contiguous()
-        ssamg_problem_fv_assemble(self.h, self._kappa, aniso, stencil)
+        """kappa: float64 tensor on the HIP device, one value per cell."""
+        self._kappa = kappa
+        ssamg_problem_fv_assemble(self.h, kappa, aniso, stencil)
 
     def fv_grad(self, lam, x):
-        g = torch.empty_like(x)
+        """-sum_k lam_k^T (dA/dkappa) x_k for [N] or [N, nrhs] lam and x."""
+        g = torch.empty(self.n, dtype=torch.float64, device=x.device)
         ssamg_problem_fv_grad(self.h, lam.contiguous(), x.contiguous(), g)
         return g
 
@@ -326,24 +421,28 @@ class Solver:
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         ssamg_setup_numeric(self.h, self.ws)
 
-    def solve(self, b, x=None):
-        """b: CUDA float64 [N] or [N, nrhs] (rhs fastest).  Returns (x, status, info)."""
+    def solve(self, b, x=None, layout=L.LAYOUT_CELL_MAJOR):
+        """b: float64 device tensor, [N] or [N, nrhs] (rhs fastest) in the
+        default layout, [nrhs, N] with ``layout=LAYOUT_RHS_MAJOR``.
+        Returns (x, status, info); x has b's shape."""
         b = b.contiguous()
-        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        if b.dim() == 1:
+            nrhs = 1
+        else:
+            nrhs = int(b.shape[0] if layout == L.LAYOUT_RHS_MAJOR else b.shape[1])
         if x is None:
             x = torch.empty_like(b)
-        st, info = ssamg_solve(self.h, nrhs, b, x)
+        st, info = ssamg_solve(self.h, nrhs, b, x, layout)
         return x, st, info
 
     def update_coeffs(self, part, vals):
         """New stencil values of one part ([nent][nz][ny][nx], same pattern: a
         CUDA float64 tensor or a host array); run setup() again before solving."""
-        if isinstance(vals, torch.Tensor):
-            vals = vals.to(dtype=torch.float64).contiguous()
-            ssamg_update_coeffs(self.h, part, vals, L.MEM_DEVICE)
+        nent, ncell = ssamg_problem_part_size(self.problem.h, part)
+        if isinstance(vals, torch.Tensor) and vals.is_cuda:
+            ssamg_update_coeffs(self.h, part, vals.contiguous().reshape(-1), L.MEM_DEVICE, nent * ncell)
         else:
-            ssamg_update_coeffs(self.h, part, np.ascontiguousarray(vals, dtype=np.float64).reshape(-1),
-                                L.MEM_HOST)
+            ssamg_update_coeffs(self.h, part, vals, L.MEM_HOST, nent * ncell)
 
     def autotune(self, nrhs, cache_path=None):
         """Time and keep the fastest launch options of the batched cycle for

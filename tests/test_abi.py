@@ -64,3 +64,54 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libssamg.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_binding_checks_buffers_before_the_call(libpath):
+    """The ABI takes raw pointers, so the binding refuses a wrong dtype, host
+    memory where device memory is expected, or a wrong length, before any call
+    that could touch a buffer (no GPU is needed to reach these checks)."""
+    import numpy as np
+    import torch
+    from paper_2205_14273_amd import ssamg as B
+    pr = B.Problem(3, [(4, 4, 4), (2, 4, 4)], [(0, 0, 0), (4, 0, 0)])
+    assert B.ssamg_problem_num_parts(pr.h) == 2
+    offs = np.array([[0, 0, 0], [-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0], [0, 0, -1], [0, 0, 1]])
+    B.ssamg_problem_set_stencil(pr.h, 0, offs)
+    assert B.ssamg_problem_part_size(pr.h, 0) == (7, 64)
+    assert B.ssamg_problem_part_size(pr.h, 1) == (0, 32)
+    with pytest.raises(ValueError):
+        B.ssamg_problem_set_coeffs(pr.h, 0, np.ones(7 * 64 + 1))
+    with pytest.raises(ValueError):
+        B.ssamg_problem_set_coeffs(pr.h, 0, np.ones(6), constant=1)
+    with pytest.raises(ValueError):
+        B.ssamg_problem_set_coeffs(pr.h, 1, np.ones(7 * 32))        # no stencil yet
+    with pytest.raises(TypeError):
+        B.ssamg_problem_fv_assemble(pr.h, torch.ones(96, dtype=torch.float64), np.ones((2, 3)), 7)
+    with pytest.raises(TypeError):
+        B.ssamg_problem_fv_grad(pr.h, torch.ones(96, dtype=torch.float64),
+                                torch.ones(96, dtype=torch.float64), torch.ones(96, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        B.ssamg_problem_set_coupling(pr.h, [0, 1], [64], [1.0])
+
+
+def test_new_entry_points_validate_without_gpu(libpath):
+    """Argument errors of the boundary's newer calls are reported on the host."""
+    import ctypes as C
+    from paper_2205_14273_amd import _lib
+    lib = _lib.lib()
+    prob = C.c_void_p()
+    assert lib.ssamg_problem_create(3, 2, C.byref(prob)) == _lib.OK
+    n = C.c_int()
+    assert lib.ssamg_problem_num_parts(prob, C.byref(n)) == _lib.OK and n.value == 2
+    ne, nc = C.c_int(), C.c_int64()
+    assert lib.ssamg_problem_part_size(prob, 5, C.byref(ne), C.byref(nc)) == _lib.ERR_ARG
+    # bad memory kind for the couplings
+    assert lib.ssamg_problem_set_coupling(prob, 0, None, None, None, 7) == _lib.ERR_ARG
+    p = _lib.ssamg_params()
+    lib.ssamg_params_default(C.byref(p))
+    assert p.pb_interp == _lib.PB_ONE
+    p.pb_interp = 3
+    s = C.c_void_p()
+    assert lib.ssamg_solver_create(prob, C.byref(p), None, C.byref(s)) == _lib.ERR_ARG
+    assert b"pb_interp" in lib.ssamg_last_error()
+    assert lib.ssamg_problem_destroy(prob) == _lib.OK

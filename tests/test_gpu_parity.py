@@ -13,8 +13,8 @@ import scipy.linalg as sla
 
 import workloads as W
 from oracle import assemble, ssamg as O
-from tests.parity_util import (compare_hierarchy, gpu_fv, gpu_raw, oracle_fv, oracle_raw,
-                               row_rel_err)
+from tests.parity_util import (CYCLE_RTOL, assert_cycle_close, compare_hierarchy, gpu_fv, gpu_raw,
+                               oracle_fv, oracle_raw, row_rel_err, vcycle_scale)
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +74,7 @@ def test_vcycle_parity(name):
     r = np.random.default_rng(3).uniform(-1, 1, h.levels[0].n)
     z = s.apply_precond(_cuda(r)).cpu().numpy()
     want = O.vcycle(h, r)
-    assert np.linalg.norm(z - want) <= 1e-11 * np.linalg.norm(want)
+    assert_cycle_close(z, want, vcycle_scale(h, r), CYCLE_RTOL[0], name)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -161,7 +161,7 @@ def test_large_coarsest_level(precision):
     r = np.random.default_rng(12).uniform(-1, 1, h.levels[0].n)
     z = s.apply_precond(_cuda(r)).cpu().numpy()
     want = O.vcycle(h, r)
-    assert np.linalg.norm(z - want) <= (1e-12 if precision == 0 else 1e-5) * np.linalg.norm(want)
+    assert_cycle_close(z, want, vcycle_scale(h, r), CYCLE_RTOL[precision])
     ref = O.solve(h, case.b, tol=1e-8)
     x, st, info = s.solve(_cuda(case.b))
     assert st == 0 and abs(info.iters[0] - ref.iters) <= 1
@@ -275,10 +275,10 @@ def test_tail_kernel_matches_grid_kernels(monkeypatch, precision):
     _, s1 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
     z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
     z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
-    tol = 1e-13 if precision == 0 else 1e-5
-    assert np.linalg.norm(z1 - z0) <= tol * np.linalg.norm(z0)
     want = O.vcycle(h, r)
-    assert np.linalg.norm(z1 - want) <= (1e-11 if precision == 0 else 1e-5) * np.linalg.norm(want)
+    scale = vcycle_scale(h, r)
+    assert_cycle_close(z1, z0, scale, CYCLE_RTOL[precision], "tail vs grid")
+    assert_cycle_close(z1, want, scale, CYCLE_RTOL[precision], "tail vs oracle")
     R = np.random.default_rng(9).uniform(-1, 1, (h.levels[0].n, 8))
     x0, st0, i0 = s0.solve(_cuda(R))
     x1, st1, i1 = s1.solve(_cuda(R))
@@ -307,10 +307,10 @@ def test_collapsed_coarse_cycle(monkeypatch, precision, cells):
     _, s1 = gpu_fv(case, cycle_precision=precision, max_nrhs=8)
     z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
     z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
-    tol = 1e-13 if precision == 0 else 1e-5
-    assert np.linalg.norm(z1 - z0) <= tol * np.linalg.norm(z0)
     want = O.vcycle(h, r)
-    assert np.linalg.norm(z1 - want) <= (1e-11 if precision == 0 else 1e-5) * np.linalg.norm(want)
+    scale = vcycle_scale(h, r)
+    assert_cycle_close(z1, z0, scale, CYCLE_RTOL[precision], "collapsed vs full")
+    assert_cycle_close(z1, want, scale, CYCLE_RTOL[precision], "collapsed vs oracle")
     R = np.random.default_rng(32).uniform(-1, 1, (h.levels[0].n, 8))
     x0, st0, i0 = s0.solve(_cuda(R))
     x1, st1, i1 = s1.solve(_cuda(R))
@@ -361,10 +361,10 @@ def test_split_down_sweep_matches_fused(monkeypatch, precision):
     z0 = s0.apply_precond(_cuda(r)).cpu().numpy()
     z1 = s1.apply_precond(_cuda(r)).cpu().numpy()
     want = O.vcycle(h, r)
-    tol = 1e-11 if precision == 0 else 1e-5
-    assert np.linalg.norm(z0 - want) <= tol * np.linalg.norm(want)
-    assert np.linalg.norm(z1 - want) <= tol * np.linalg.norm(want)
-    assert np.linalg.norm(z0 - z1) <= (1e-13 if precision == 0 else 1e-5) * np.linalg.norm(z1)
+    scale = vcycle_scale(h, r)
+    assert_cycle_close(z0, want, scale, CYCLE_RTOL[precision], "split vs oracle")
+    assert_cycle_close(z1, want, scale, CYCLE_RTOL[precision], "fused vs oracle")
+    assert_cycle_close(z0, z1, scale, CYCLE_RTOL[precision], "split vs fused")
 
 
 @pytest.mark.parametrize("name,precision", [("c1_16", 0), ("c2_13", 1), ("c3_9", 0), ("c5_11", 1)])
@@ -378,8 +378,7 @@ def test_direct_coarsest_solve(name, precision):
     r = np.random.default_rng(15).uniform(-1, 1, h.levels[0].n)
     z = s.apply_precond(_cuda(r)).cpu().numpy()
     want = O.vcycle(h, r)
-    tol = 1e-11 if precision == 0 else 1e-5
-    assert np.linalg.norm(z - want) <= tol * np.linalg.norm(want)
+    assert_cycle_close(z, want, vcycle_scale(h, r), CYCLE_RTOL[precision], name)
     b = case.b if case.b.ndim == 1 else case.b[0]
     ref = O.solve(h, b, tol=1e-8, flexible=(precision == 1))
     x, st, info = s.solve(_cuda(b))
@@ -422,8 +421,7 @@ def test_skip_option_parity(name, precision):
     r = np.random.default_rng(16).uniform(-1, 1, h.levels[0].n)
     z = s.apply_precond(_cuda(r)).cpu().numpy()
     want = O.vcycle(h, r)
-    tol = 1e-11 if precision == 0 else 1e-5
-    assert np.linalg.norm(z - want) <= tol * np.linalg.norm(want)
+    assert_cycle_close(z, want, vcycle_scale(h, r), CYCLE_RTOL[precision], name)
     b = case.b if case.b.ndim == 1 else case.b[0]
     ref = O.solve(h, b, tol=1e-8, flexible=(precision == 1))
     x, st, info = s.solve(_cuda(b))
