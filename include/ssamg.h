@@ -257,6 +257,25 @@ ssamg_status ssamg_update_coeffs(ssamg_solver s, int part, const double *vals, i
 ssamg_status ssamg_solve(ssamg_solver s, int nrhs, const double *b, double *x, int layout,
                          ssamg_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ssamg_solve with the
+ * same arguments and results (bit for bit), except that the PCG work vectors
+ * r, z, p, q, the reduction partials and scalars, and for
+ * SSAMG_LAYOUT_RHS_MAJOR with nrhs > 1 the layout staging, come from one fixed
+ * device array of SSAMG_NOALLOC_SCRATCH_BYTES per GPU (held until the process
+ * ends) instead of the solver's workspace or buffers allocated on first use.
+ * It calls no allocating routine: a V-cycle graph not yet instantiated for
+ * this width is not built (the coarse levels are launched directly), and
+ * autotune = 1 needs the width tuned beforehand (SSAMG_ERR_STATE otherwise).
+ * Needs (4 N nrhs + 2 N nrhs if staged) doubles plus about 1 MiB of partials:
+ * larger solves return SSAMG_ERR_ARG with the size in the message.  The
+ * solver's device must be current.  Every call on one GPU shares its array:
+ * calls that overlap on one GPU (two streams or threads) race and must be
+ * serialised by the caller. */
+#define SSAMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+ssamg_status ssamg_solve_noalloc(ssamg_solver s, int nrhs, const double *b, double *x, int layout,
+                                 ssamg_info *info);
+
 /* Launch options of the batched V-cycle (batch widths of 4 or more right-hand
  * sides), per level and width.  They choose how the kernels cover a level, not
  * what they compute: every choice gives bit-identical results.  The record is

@@ -34,6 +34,7 @@ PB_ONE = 0
 PB_LUMP = 1
 LAYOUT_CELL_MAJOR = 0
 LAYOUT_RHS_MAJOR = 1
+NOALLOC_SCRATCH_BYTES = 64 << 20
 PROBE_NONE = -1
 PROBE_MATVEC = 0
 PROBE_SMOOTH0 = 1
@@ -101,6 +102,7 @@ SIGNATURES = {
     "ssamg_workspace_bytes": [P, C.POINTER(C.c_size_t)],
     "ssamg_setup_numeric": [P, P, C.c_size_t],
     "ssamg_solve": [P, I, P, P, I, C.POINTER(ssamg_info)],
+    "ssamg_solve_noalloc": [P, I, P, P, I, C.POINTER(ssamg_info)],
     "ssamg_apply_A": [P, I, P, P],
     "ssamg_apply_precond": [P, P, P],
     "ssamg_num_levels": [P, PI],

@@ -246,6 +246,17 @@ def ssamg_solve(h, nrhs, b, x, layout=L.LAYOUT_CELL_MAJOR):
     return st, info
 
 
+def ssamg_solve_noalloc(h, nrhs, b, x, layout=L.LAYOUT_CELL_MAJOR):
+    """ssamg_solve without device allocation (fixed per-GPU scratch array)."""
+    n = ssamg_level_cells(h, 0) * nrhs
+    _dev_vec(b, n, "b")
+    _dev_vec(x, n, "x")
+    info = L.ssamg_info()
+    st = lib().ssamg_solve_noalloc(h, nrhs, _ptr(b), _ptr(x), layout, C.byref(info))
+    check(st, allow_not_converged=True)
+    return st, info
+
+
 def ssamg_apply_A(h, level, x, y):
     n = ssamg_level_cells(h, level)
     _dev_vec(x, n, "x")
