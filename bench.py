@@ -99,6 +99,9 @@ def main():
                     help="kernel of the main roofline (timed with HIP events in the timed run)")
     ap.add_argument("--probe2", default="jacobi0", choices=sorted(PROBES) + ["none"],
                     help="kernel of the second roofline (a short extra run of the FP32 cycle)")
+    ap.add_argument("--hybrid-level", type=int, default=0, metavar="K",
+                    help="hybrid coarse tail: end the hierarchy at level K and solve it exactly "
+                         "(0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -158,6 +161,8 @@ def main():
                       relax=B.L.RELAX_L1_JACOBI if case.relax == "l1" else B.L.RELAX_JACOBI)
         if case.omega > 0:
             params["omega"] = case.omega
+        if args.hybrid_level > 0:
+            params["hybrid_level"] = args.hybrid_level
         pr.fv_assemble(kappa, aniso, case.stencil)
         s = B.Solver(pr, **params)
         return pr, s
@@ -298,7 +303,8 @@ def main():
         t0 = time.perf_counter()
         A, _ = assemble.assemble_fv(sg, sample_case.stencil, sample_case.kappa, sample_case.aniso)
         h = O.setup(A, sg.dims, sg.face_kinds(), [W.stencil_offsets(sample_case.stencil, sg.ndim)]
-                    * sg.nparts, sg.ndim, omega=sample_case.omega, relax=sample_case.relax)
+                    * sg.nparts, sg.ndim, omega=sample_case.omega, relax=sample_case.relax,
+                    hybrid_level=args.hybrid_level)
         ts = time.perf_counter()
         bb = sample_case.b if sample_case.b.ndim == 1 else sample_case.b[0]
         ref = O.solve(h, bb, tol=sample_case.tol, max_iter=sample_case.max_iter)
@@ -344,7 +350,9 @@ def main():
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {DESCR[args.config]}; FP32 V(1,1) cycle in FP64 PCG, "
-                               f"tol {case.tol}", "cells": N, "nrhs": nrhs,
+                               f"tol {case.tol}"
+                               + (f"; hybrid tail at level {args.hybrid_level}" if args.hybrid_level else ""),
+                   "cells": N, "nrhs": nrhs,
                    "levels": mixed["levels"], "iters": mixed["iters"],
                    "assemble_s": round(mixed["assemble_s"], 6), "setup_s": round(mixed["setup_s"], 6),
                    "setup_symbolic_s": round(mixed["symbolic_s"], 6),

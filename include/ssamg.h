@@ -71,10 +71,42 @@ ssamg_status ssamg_problem_create(int ndim, int nparts, ssamg_problem *out);
 ssamg_status ssamg_problem_destroy(ssamg_problem prob);
 
 /* Box of part `part`: cells lo[d] .. hi[d] inclusive, lo must be {0,0,0}.
- * One box per part (Section 2 allows several; bounding boxes of Algorithm 1
- * then coincide with the box). */
+ * This is the part's index-space box (its bounding box, on which Algorithm 1
+ * coarsens); the part's cells are all of it unless ssamg_problem_add_box
+ * lists the boxes the part is made of (Section 2). */
 ssamg_status ssamg_problem_set_box(ssamg_problem prob, int part, const int lo[3],
                                    const int hi[3]);
+
+/* A part made of several boxes (Section 2): adds the box lo .. hi (inclusive,
+ * inside the part's box) to the part's list.  When a part has a list, each of
+ * its cells in none of the listed boxes is a ghost unknown (the treatment of
+ * coarse cells under a refined patch in adaptive refinement, Section 4): its
+ * row is the identity (set_coeffs replaces its given coefficients), every
+ * stencil entry pointing at it is dropped, and no coupling may touch it.
+ * Vectors still span the part's whole box; with b = 0 on ghost cells, x is
+ * zero there up to the solver's tolerance.  Boxes may overlap.  Invalidates every part's coefficients (call
+ * set_coeffs again).  Needs set_box first. */
+ssamg_status ssamg_problem_add_box(ssamg_problem prob, int part, const int lo[3], const int hi[3]);
+
+/* Glue face `face` (0..5 = -x,+x,-y,+y,-z,+z) of part `part` to part
+ * `nbr_part` (another part) for non-Cartesian connectivity (Section 2; the
+ * rotated index spaces of Section 4's three-part intersection): a point x just
+ * across the face, in part's index space, is the point y of the neighbour's
+ * index space with y[map[d]] = nbr_at[map[d]] + dir[d] * (x[d] - at[d]), where
+ * `at` is a point just across the face (at[axis] = -1 or n[axis], the other
+ * components inside the box), `nbr_at` its image (inside the neighbour's box),
+ * map a permutation of {0,1,2} and dir[d] = +-1.  set_coeffs then moves every
+ * stencil entry a_s(c) whose neighbour c + s leaves the box through a glued
+ * face into the couplings, U(c, y) = a_s(c) (entries leaving through two faces
+ * at an edge or corner take the first glued face, in face order, whose image
+ * is an active cell of its neighbour; all others are dropped as Dirichlet).
+ * The face becomes SSAMG_FACE_PART.  The caller glues both sides, with
+ * symmetric coefficients, to keep A symmetric.  Invalidates every part's
+ * coefficients.  SSAMG_ERR_ARG for a bad map, a point not across the face or
+ * an image outside the neighbour's box. */
+ssamg_status ssamg_problem_set_neighbor(ssamg_problem prob, int part, int face, int nbr_part,
+                                        const int at[3], const int nbr_at[3], const int map[3],
+                                        const int dir[3]);
 
 /* Placement of part `part` in a shared global index space.  Used only by
  * ssamg_problem_fv_assemble (neighbour lookup across parts) and to derive
@@ -97,16 +129,21 @@ ssamg_status ssamg_problem_set_stencil(ssamg_problem prob, int part, int nent,
  * fastest), or vals[nent] when constant = 1 (one value per stencil entry for
  * the whole part, Section 2).  `where` = SSAMG_MEM_HOST or SSAMG_MEM_DEVICE.
  * Copied.  Entries whose neighbour lies outside the box are discarded
- * (Dirichlet elimination).  Requires set_box and set_stencil first. */
+ * (Dirichlet elimination) or, across a glued face, moved to the couplings;
+ * ghost cells of a part of several boxes get identity rows.  Requires
+ * set_box and set_stencil first, and the boxes and glued faces of every part
+ * when there are any. */
 ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double *vals,
                                       int where, int constant);
 
 /* Inter-part couplings U (Section 2): nnz entries (row[k], col[k], val[k]) with
  * global cell ids, in COO form; `where` = SSAMG_MEM_HOST or SSAMG_MEM_DEVICE
- * for all three arrays; copied; duplicates are summed, explicit zeros kept as
- * structure.  An entry inside one part is SSAMG_ERR_ARG (assumption of the
- * theorem of Section 3.3); a non-finite value SSAMG_ERR_NUMERIC.  A second
- * call replaces the couplings; nnz = 0 means none. */
+ * for all three arrays; copied; duplicates are summed (also with the entries
+ * moved across glued faces), explicit zeros kept as structure.  An entry
+ * inside one part or on a ghost cell is SSAMG_ERR_ARG (the first is an
+ * assumption of the theorem of Section 3.3); a non-finite value
+ * SSAMG_ERR_NUMERIC.  A second call replaces the given couplings; nnz = 0
+ * means none. */
 ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const int64_t *row,
                                         const int64_t *col, const double *val, int where);
 
@@ -118,7 +155,8 @@ ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const i
  * mean of the part's factors over the nonzero components of s; neighbours
  * outside every part are zero-Dirichlet ghosts with kappa_j = kappa_i.
  * A_ii = sum of t, A_ij = -t; same-part entries go to S, the rest to U.  Needs
- * boxes and origins of every part; sets the stencils, the face kinds and U. */
+ * boxes and origins of every part; sets the stencils, the face kinds and U.
+ * Problems with add_box or set_neighbor are SSAMG_ERR_UNSUPPORTED here. */
 ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa,
                                        const double *aniso, int stencil, void *hip_stream);
 
@@ -189,6 +227,14 @@ typedef struct {
                                 denominator), is added to the opposite weight.  Both
                                 interpolate constants exactly on rows of zero sum; they
                                 differ on rows next to a Dirichlet face */
+  int hybrid_level;          /* 0 (default): off.  k >= 1: the hybrid coarse tail of
+                                Section 3.5 - the hierarchy ends at level k (or earlier,
+                                if it is shorter) and that level is solved exactly, in
+                                FP64, with its dense inverse formed at setup_numeric
+                                (blocked Gauss-Jordan on the device).  The level may
+                                have at most 16384 unknowns (SSAMG_ERR_UNSUPPORTED from
+                                setup_symbolic otherwise); SSAMG_ERR_NUMERIC when its
+                                operator is not positive definite.  Overrides coarse */
 } ssamg_params;
 
 typedef struct {

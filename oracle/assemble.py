@@ -187,3 +187,121 @@ def fv_gradient(geometry, stencil, kappa, aniso, lam, x):
         term = np.where(has, (lam[ids] - lam[jj]) * (x[ids] - x[jj]), lam[ids] * x[ids])
         np.add.at(g, ids, -dt * term)
     return g
+
+
+# ---------------------------------------------------------------------------
+# parts of several boxes and glued part faces (Section 2: a part is a set of
+# boxes in its own index space; parts may be connected in non-Cartesian ways,
+# and adaptive refinement keeps coarse cells under a patch as ghost unknowns)
+
+FACE_ORDER = ((0, -1), (0, +1), (1, -1), (1, +1), (2, -1), (2, +1))
+
+
+def neighbor_image(nb, x):
+    """Index of point x (outside the part, across the glued face) in the
+    neighbour part's space: y[map[d]] = nbr_at[map[d]] + dir[d] (x[d] - at[d])."""
+    y = [0, 0, 0]
+    for d in range(3):
+        y[nb["map"][d]] = nb["nbr_at"][nb["map"][d]] + nb["dir"][d] * (x[d] - nb["at"][d])
+    return y
+
+
+def active_mask(dims_p, boxes_p):
+    """Cells of the part's bounding box that lie in one of its boxes (all when
+    the part has no box list)."""
+    nx, ny, nz = dims_p
+    if not boxes_p:
+        return np.ones(nx * ny * nz, dtype=bool)
+    m = np.zeros((nz, ny, nx), dtype=bool)
+    for lo, hi in boxes_p:
+        m[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] = True
+    return m.reshape(-1)
+
+
+def assemble_semistructured(dims, stencils, coeffs, urow, ucol, uval, boxes=None, neighbors=None):
+    """Global CSR of A = S + U for parts made of boxes and glued faces.
+
+    boxes[p]: list of (lo, hi) inclusive sub-boxes of part p's bounding box
+    [0, dims[p]) (None or empty: the whole box).  A cell in none of them is a
+    ghost unknown: its row is the identity, and every entry pointing at it is
+    dropped.  neighbors[p][f]: None, or a dict {"part", "at", "nbr_at", "map",
+    "dir"} gluing face f of part p (order -x, +x, -y, +y, -z, +z) to another
+    part.  A stencil entry whose neighbour c + s lies outside the box goes, in
+    face order, through the first glued face it crosses whose image is an
+    active cell of that face's neighbour, and becomes the coupling
+    U(c, image) = a_s(c); otherwise it is dropped (Dirichlet).  Returns (A,
+    offsets, faces) with faces[p][f] = 1 on glued faces.
+    """
+    nparts = len(dims)
+    boxes = boxes or [None] * nparts
+    neighbors = neighbors or [[None] * 6 for _ in range(nparts)]
+    offsets = np.concatenate([[0], np.cumsum([a * b * c for a, b, c in dims])]).astype(np.int64)
+    N = int(offsets[-1])
+    act = [active_mask(dims[p], boxes[p]) for p in range(nparts)]
+    rows, cols, vals = [], [], []
+    for p, (nx, ny, nz) in enumerate(dims):
+        st = np.asarray(stencils[p])
+        co = np.asarray(coeffs[p], dtype=np.float64).reshape(len(st), -1)
+        for c in range(nx * ny * nz):
+            g = int(offsets[p]) + c
+            if not act[p][c]:
+                rows.append(g)
+                cols.append(g)
+                vals.append(1.0)
+                continue
+            x = (c % nx, (c // nx) % ny, c // (nx * ny))
+            for e, s in enumerate(st):
+                t = [x[d] + int(s[d]) for d in range(3)]
+                if all(0 <= t[d] < dims[p][d] for d in range(3)):
+                    tc = t[0] + nx * (t[1] + ny * t[2])
+                    if act[p][tc]:
+                        rows.append(g)
+                        cols.append(int(offsets[p]) + tc)
+                        vals.append(co[e][c])
+                    continue
+                for f, (ax, sg) in enumerate(FACE_ORDER):
+                    nb = neighbors[p][f]
+                    crossed = t[ax] < 0 if sg < 0 else t[ax] >= dims[p][ax]
+                    if nb is None or not crossed:
+                        continue
+                    q = nb["part"]
+                    y = neighbor_image(nb, t)
+                    if all(0 <= y[d] < dims[q][d] for d in range(3)):
+                        yc = y[0] + dims[q][0] * (y[1] + dims[q][1] * y[2])
+                        if act[q][yc]:
+                            rows.append(g)
+                            cols.append(int(offsets[q]) + yc)
+                            vals.append(co[e][c])
+                            break
+    urow = np.asarray(urow, dtype=np.int64)
+    ucol = np.asarray(ucol, dtype=np.int64)
+    if urow.size:
+        pr = np.searchsorted(offsets, urow, side="right") - 1
+        pc = np.searchsorted(offsets, ucol, side="right") - 1
+        if np.any(pr == pc):
+            raise ValueError("U holds a coupling inside one part")
+        for r, c_ in zip(urow, ucol):
+            for gg in (r, c_):
+                q = int(np.searchsorted(offsets, gg, side="right") - 1)
+                if not act[q][gg - offsets[q]]:
+                    raise ValueError("U touches a ghost cell")
+    A = sp.csr_matrix((np.concatenate([np.asarray(vals, dtype=np.float64), np.asarray(uval, dtype=np.float64)]),
+                       (np.concatenate([np.asarray(rows, dtype=np.int64), urow]),
+                        np.concatenate([np.asarray(cols, dtype=np.int64), ucol]))), shape=(N, N))
+    A.sum_duplicates()
+    A.sort_indices()
+    faces = np.array([[1 if neighbors[p][f] is not None else 0 for f in range(6)] for p in range(nparts)])
+    return A, offsets, faces
+
+
+def cross_structure(A, offsets):
+    """0/1 pattern of A's cross-part entries (the coupling structure U starts with)."""
+    C = A.tocoo()
+    part = np.searchsorted(offsets, C.row, side="right") - 1
+    partc = np.searchsorted(offsets, C.col, side="right") - 1
+    m = part != partc
+    P = sp.csr_matrix((np.ones(int(m.sum())), (C.row[m], C.col[m])), shape=A.shape)
+    P.sum_duplicates()
+    P.data[:] = 1.0
+    P.sort_indices()
+    return P

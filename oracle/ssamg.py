@@ -59,6 +59,7 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .assemble import cell_coords
@@ -358,12 +359,20 @@ class Hierarchy:
 
 
 def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=64,
-          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False, pb="one"):
+          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False, pb="one", hybrid_level=0):
     """Full SSAMG setup.  ``pattern0[p]`` is the input stencil of part p.
+
+    ``hybrid_level`` = k > 0: the hybrid scheme of Section 3.5 - SSAMG builds
+    levels 0 .. k-1 and the problem left at level k is solved exactly (here by
+    a dense direct solve, standing in for the unstructured solver the paper
+    switches to), i.e. the hierarchy ends at level k with coarse = "direct".
 
     ``ustruct0``: 0/1 structure of the input couplings (defaults to A0's
     cross-part entries).
     """
+    if hybrid_level > 0:
+        max_levels = min(max_levels, hybrid_level + 1)
+        coarse = "direct"
     offsets = _offsets(dims)
     part = cell_coords(dims, offsets)[0]
     if ustruct0 is None:
@@ -498,7 +507,10 @@ def vcycle(h, b):
         wd = _cell_weights(lev)
         if l == L - 1:
             if h.coarse == "direct":
-                return np.linalg.solve(lev.A.toarray(), bl)
+                # dense Cholesky factor of the coarsest operator, formed once
+                if "chol" not in lev._cache:
+                    lev._cache["chol"] = sla.cho_factor(lev.A.toarray())
+                return sla.cho_solve(lev._cache["chol"], bl)
             return wd * bl
         x = wd * bl
         r = bl - lev.A @ x

@@ -52,7 +52,8 @@ class ssamg_params(C.Structure):
                 ("omega", C.c_double), ("coarse", C.c_int), ("cycle_precision", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
                 ("use_graph", C.c_int), ("skip", C.c_int), ("autotune", C.c_int),
-                ("symmetric", C.c_int), ("pb_interp", C.c_int)]
+                ("symmetric", C.c_int), ("pb_interp", C.c_int),
+                ("hybrid_level", C.c_int)]
 
 
 class ssamg_info(C.Structure):
@@ -82,6 +83,8 @@ SIGNATURES = {
     "ssamg_problem_destroy": [P],
     "ssamg_problem_set_box": [P, I, PI, PI],
     "ssamg_problem_set_origin": [P, I, PI],
+    "ssamg_problem_add_box": [P, I, PI, PI],
+    "ssamg_problem_set_neighbor": [P, I, I, I, PI, PI, PI, PI],
     "ssamg_problem_set_face": [P, I, I, I],
     "ssamg_problem_set_stencil": [P, I, I, PI],
     "ssamg_problem_set_coeffs": [P, I, P, I, I],

@@ -22,6 +22,15 @@ std::vector<int64_t> Problem::offsets() const {
   return off;
 }
 
+bool Problem::has_topology() const {
+  for (int p = 0; p < nparts; ++p) {
+    if (!boxes[p].empty()) return true;
+    for (int f = 0; f < 6; ++f)
+      if (glue[p][f].part >= 0) return true;
+  }
+  return false;
+}
+
 void Problem::free_device() {
   for (auto &c : coef) {
     if (c) (void)hipFree(c);
@@ -89,6 +98,117 @@ void canonical_csr(int64_t nnz, const int64_t *row, const int64_t *col, const do
     pc = col[k];
   }
   if (!urow.empty()) uptr.push_back((int)ucol.size());
+}
+
+// cells of part p's box that lie in one of its boxes (all without a box list)
+std::vector<char> active_mask(const Problem *pr, int p) {
+  const auto &n = pr->dims[p];
+  const int64_t nc = (int64_t)n[0] * n[1] * n[2];
+  if (pr->boxes[p].empty()) return std::vector<char>(nc, 1);
+  std::vector<char> m(nc, 0);
+  for (const auto &b : pr->boxes[p])
+    for (int k = b[2]; k <= b[5]; ++k)
+      for (int j = b[1]; j <= b[4]; ++j)
+        for (int i = b[0]; i <= b[3]; ++i) m[i + (int64_t)n[0] * (j + (int64_t)n[1] * k)] = 1;
+  return m;
+}
+
+// canonical CSR of the couplings: the given COO plus every part's entries
+// moved across glued faces; rows and columns must be cells of different parts
+// and active (not ghost) cells
+void rebuild_coupling(Problem *pr) {
+  const auto off = pr->offsets();
+  const int64_t N = off.back();
+  auto part_of = [&](int64_t id) {
+    return (int)(std::upper_bound(off.begin(), off.end(), id) - off.begin()) - 1;
+  };
+  std::vector<int64_t> row(pr->ucoo_row), col(pr->ucoo_col);
+  std::vector<double> val(pr->ucoo_val);
+  for (int p = 0; p < pr->nparts; ++p) {
+    row.insert(row.end(), pr->ux_row[p].begin(), pr->ux_row[p].end());
+    col.insert(col.end(), pr->ux_col[p].begin(), pr->ux_col[p].end());
+    val.insert(val.end(), pr->ux_val[p].begin(), pr->ux_val[p].end());
+  }
+  std::vector<std::vector<char>> act(pr->nparts);
+  bool any_boxes = false;
+  for (int p = 0; p < pr->nparts; ++p) any_boxes = any_boxes || !pr->boxes[p].empty();
+  if (any_boxes)
+    for (int p = 0; p < pr->nparts; ++p) act[p] = active_mask(pr, p);
+  for (size_t k = 0; k < row.size(); ++k) {
+    if (row[k] < 0 || row[k] >= N || col[k] < 0 || col[k] >= N)
+      throw Error(SSAMG_ERR_ARG, "coupling index out of range");
+    const int pr_ = part_of(row[k]), pc = part_of(col[k]);
+    if (pr_ == pc) throw Error(SSAMG_ERR_ARG, "coupling inside one part (U must couple different parts)");
+    if (!std::isfinite(val[k])) throw Error(SSAMG_ERR_NUMERIC, "non-finite coupling value");
+    if (any_boxes && (!act[pr_][row[k] - off[pr_]] || !act[pc][col[k] - off[pc]]))
+      throw Error(SSAMG_ERR_ARG, "coupling touches a ghost cell (a cell in none of its part's boxes)");
+  }
+  canonical_csr((int64_t)row.size(), row.data(), col.data(), val.data(), pr->urow, pr->uptr, pr->ucol,
+                pr->uval_host);
+  dev_upload(pr->d_urow, pr->urow);
+  dev_upload(pr->d_uptr, pr->uptr);
+  dev_upload(pr->d_ucol, pr->ucol);
+  dev_upload(pr->d_uval, pr->uval_host);
+  pr->coupling_set = true;
+  pr->fv_structure_ready = false;
+}
+
+// Stencil values of part p given topology (host, [nent][ncell], changed in
+// place): ghost cells get an identity row; entries pointing at a ghost cell are
+// dropped; an entry leaving the box goes, in face order, through the first
+// glued face it crosses whose image is an active cell of that face's
+// neighbour, and is moved to the part's crossing couplings.
+void apply_topology(Problem *pr, int p, std::vector<double> &h) {
+  const auto &n = pr->dims[p];
+  const int64_t nc = (int64_t)n[0] * n[1] * n[2];
+  const auto &st = pr->stencil[p];
+  const int nent = (int)st.size(), center = pr->center[p];
+  const auto off = pr->offsets();
+  const auto act = active_mask(pr, p);
+  std::vector<std::vector<char>> nact(pr->nparts);
+  for (int f = 0; f < 6; ++f) {
+    const int q = pr->glue[p][f].part;
+    if (q >= 0 && nact[q].empty()) nact[q] = active_mask(pr, q);
+  }
+  auto &xr = pr->ux_row[p], &xc = pr->ux_col[p];
+  auto &xv = pr->ux_val[p];
+  xr.clear();
+  xc.clear();
+  xv.clear();
+  for (int64_t c = 0; c < nc; ++c) {
+    if (!act[c]) {
+      for (int e = 0; e < nent; ++e) h[(size_t)e * nc + c] = e == center ? 1.0 : 0.0;
+      continue;
+    }
+    const int x[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
+    for (int e = 0; e < nent; ++e) {
+      if (e == center) continue;
+      const int t[3] = {x[0] + st[e][0], x[1] + st[e][1], x[2] + st[e][2]};
+      double &a = h[(size_t)e * nc + c];
+      const bool inside = t[0] >= 0 && t[0] < n[0] && t[1] >= 0 && t[1] < n[1] && t[2] >= 0 && t[2] < n[2];
+      if (inside) {
+        if (!act[t[0] + (int64_t)n[0] * (t[1] + (int64_t)n[1] * t[2])]) a = 0.0;
+        continue;
+      }
+      for (int f = 0; f < 6; ++f) {
+        const Problem::Glue &g = pr->glue[p][f];
+        const int ax = f / 2;
+        const bool crossed = (f & 1) ? t[ax] >= n[ax] : t[ax] < 0;
+        if (g.part < 0 || !crossed) continue;
+        int y[3];
+        for (int d = 0; d < 3; ++d) y[g.map[d]] = g.nbr_at[g.map[d]] + g.dir[d] * (t[d] - g.at[d]);
+        const auto &m = pr->dims[g.part];
+        if (y[0] < 0 || y[0] >= m[0] || y[1] < 0 || y[1] >= m[1] || y[2] < 0 || y[2] >= m[2]) continue;
+        const int64_t yc = y[0] + (int64_t)m[0] * (y[1] + (int64_t)m[1] * y[2]);
+        if (!nact[g.part][yc]) continue;
+        xr.push_back(off[p] + c);
+        xc.push_back(off[g.part] + yc);
+        xv.push_back(a);
+        break;
+      }
+      a = 0.0;   // moved to U, or dropped (Dirichlet)
+    }
+  }
 }
 
 }  // namespace
@@ -165,6 +285,11 @@ ssamg_status ssamg_problem_create(int ndim, int nparts, ssamg_problem *out) {
   pr->coef.assign(nparts, nullptr);
   pr->coef_set.assign(nparts, 0);
   pr->sym_ok.assign(nparts, 1);
+  pr->boxes.assign(nparts, {});
+  pr->glue.assign(nparts, {});
+  pr->ux_row.assign(nparts, {});
+  pr->ux_col.assign(nparts, {});
+  pr->ux_val.assign(nparts, {});
   *out = reinterpret_cast<ssamg_problem>(pr);
   API_END
 }
@@ -219,6 +344,65 @@ ssamg_status ssamg_problem_set_face(ssamg_problem prob, int part, int face, int 
   API_END
 }
 
+// every part's coefficients depend on the boxes and glued faces of the parts
+// they reach: topology changes ask for the coefficients again
+static void topology_changed(Problem *pr) {
+  for (int p = 0; p < pr->nparts; ++p) pr->coef_set[p] = 0;
+  pr->fv_structure_ready = false;
+}
+
+ssamg_status ssamg_problem_add_box(ssamg_problem prob, int part, const int lo[3], const int hi[3]) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  check_box(pr, part);
+  if (!lo || !hi) throw Error(SSAMG_ERR_ARG, "NULL corner");
+  const auto &n = pr->dims[part];
+  for (int d = 0; d < 3; ++d)
+    if (lo[d] < 0 || hi[d] >= n[d] || lo[d] > hi[d])
+      throw Error(SSAMG_ERR_ARG, "box must be non-empty and lie in the part's box");
+  pr->boxes[part].push_back({lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]});
+  topology_changed(pr);
+  API_END
+}
+
+ssamg_status ssamg_problem_set_neighbor(ssamg_problem prob, int part, int face, int nbr_part, const int at[3],
+                                        const int nbr_at[3], const int map[3], const int dir[3]) {
+  API_BEGIN
+  Problem *pr = P(prob);
+  check_part(pr, part);
+  check_part(pr, nbr_part);
+  check_box(pr, part);
+  check_box(pr, nbr_part);
+  if (nbr_part == part) throw Error(SSAMG_ERR_ARG, "a face glued to its own part would put couplings inside it");
+  if (face < 0 || face > 5 || face / 2 >= pr->ndim) throw Error(SSAMG_ERR_ARG, "bad face");
+  if (!at || !nbr_at || !map || !dir) throw Error(SSAMG_ERR_ARG, "NULL argument");
+  const auto &n = pr->dims[part], &m = pr->dims[nbr_part];
+  int seen = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (map[d] < 0 || map[d] > 2 || (seen >> map[d]) & 1) throw Error(SSAMG_ERR_ARG, "map must be a permutation");
+    seen |= 1 << map[d];
+    if (dir[d] != 1 && dir[d] != -1) throw Error(SSAMG_ERR_ARG, "dir must be +1 or -1");
+    if (nbr_at[d] < 0 || nbr_at[d] >= m[d]) throw Error(SSAMG_ERR_ARG, "nbr_at must lie in the neighbour's box");
+  }
+  const int ax = face / 2;
+  for (int d = 0; d < 3; ++d) {
+    const bool ok = d == ax ? at[d] == ((face & 1) ? n[d] : -1) : (at[d] >= 0 && at[d] < n[d]);
+    if (!ok) throw Error(SSAMG_ERR_ARG, "at must be a point just across the face");
+  }
+  Problem::Glue &g = pr->glue[part][face];
+  g.part = nbr_part;
+  for (int d = 0; d < 3; ++d) {
+    g.at[d] = at[d];
+    g.nbr_at[d] = nbr_at[d];
+    g.map[d] = map[d];
+    g.dir[d] = dir[d];
+  }
+  pr->faces[part][face] = SSAMG_FACE_PART;
+  topology_changed(pr);
+  API_END
+}
+
 ssamg_status ssamg_problem_set_stencil(ssamg_problem prob, int part, int nent, const int *off) {
   API_BEGIN
   Problem *pr = P(prob);
@@ -261,7 +445,28 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
   const int64_t ncell = (int64_t)pr->dims[part][0] * pr->dims[part][1] * pr->dims[part][2];
   if (!pr->coef[part]) pr->coef[part] = dev_alloc<double>((size_t)nent * ncell);
   double *dst = pr->coef[part];
-  if (constant) {
+  bool topo = !pr->boxes[part].empty();
+  for (int f = 0; f < 6; ++f) topo = topo || pr->glue[part][f].part >= 0;
+  if (topo) {
+    // ghost cells and glued faces: the values are rearranged on the host
+    for (int f = 0; f < 6; ++f)
+      if (pr->glue[part][f].part >= 0) check_box(pr, pr->glue[part][f].part);
+    std::vector<double> h((size_t)nent * ncell);
+    if (constant) {
+      std::vector<double> cv(nent);
+      if (where == SSAMG_MEM_HOST)
+        std::memcpy(cv.data(), vals, nent * sizeof(double));
+      else
+        SSAMG_HIP(hipMemcpy(cv.data(), vals, nent * sizeof(double), hipMemcpyDeviceToHost));
+      for (int e = 0; e < nent; ++e) std::fill(h.begin() + e * ncell, h.begin() + (e + 1) * ncell, cv[e]);
+    } else if (where == SSAMG_MEM_HOST) {
+      std::memcpy(h.data(), vals, h.size() * sizeof(double));
+    } else {
+      SSAMG_HIP(hipMemcpy(h.data(), vals, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    apply_topology(pr, part, h);
+    SSAMG_HIP(hipMemcpy(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else if (constant) {
     std::vector<double> host(nent);
     if (where == SSAMG_MEM_HOST)
       std::memcpy(host.data(), vals, nent * sizeof(double));
@@ -273,6 +478,11 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
   } else {
     SSAMG_HIP(hipMemcpy(dst, vals, (size_t)nent * ncell * sizeof(double),
                         where == SSAMG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice));
+  }
+  if (!topo) {
+    pr->ux_row[part].clear();
+    pr->ux_col[part].clear();
+    pr->ux_val[part].clear();
   }
   BoxStencil bs{};
   for (int d = 0; d < 3; ++d) bs.n[d] = pr->dims[part][d];
@@ -301,6 +511,7 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
   pr->sym_ok[part] = hflag[1] == 0;
   pr->fv_structure_ready = false;
   if (hflag[0]) throw Error(SSAMG_ERR_NUMERIC, "nonpositive diagonal or non-finite coefficient");
+  if (topo || pr->has_topology()) rebuild_coupling(pr);
   API_END
 }
 
@@ -338,13 +549,10 @@ ssamg_status ssamg_problem_set_coupling(ssamg_problem prob, int64_t nnz, const i
       throw Error(SSAMG_ERR_ARG, "coupling inside one part (U must couple different parts)");
     if (!std::isfinite(val[k])) throw Error(SSAMG_ERR_NUMERIC, "non-finite coupling value");
   }
-  canonical_csr(nnz, row, col, val, pr->urow, pr->uptr, pr->ucol, pr->uval_host);
-  dev_upload(pr->d_urow, pr->urow);
-  dev_upload(pr->d_uptr, pr->uptr);
-  dev_upload(pr->d_ucol, pr->ucol);
-  dev_upload(pr->d_uval, pr->uval_host);
-  pr->coupling_set = true;
-  pr->fv_structure_ready = false;
+  pr->ucoo_row.assign(row, row + nnz);
+  pr->ucoo_col.assign(col, col + nnz);
+  pr->ucoo_val.assign(val, val + nnz);
+  rebuild_coupling(pr);
   API_END
 }
 
@@ -383,6 +591,9 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
   const bool ok3 = pr->ndim == 3 && (stencil == 7 || stencil == 27);
   const bool ok2 = pr->ndim == 2 && (stencil == 5 || stencil == 9);
   if (!ok3 && !ok2) throw Error(SSAMG_ERR_ARG, "stencil must be 7|27 (3D) or 5|9 (2D)");
+  if (pr->has_topology())
+    throw Error(SSAMG_ERR_UNSUPPORTED, "fv_assemble places parts by origins: parts of several boxes and "
+                                       "glued faces take set_coeffs and set_coupling");
   for (int p = 0; p < pr->nparts; ++p) {
     check_box(pr, p);
     if (!pr->has_origin[p]) throw Error(SSAMG_ERR_STATE, "origin of every part is needed");

@@ -762,7 +762,10 @@ void setup_symbolic(Solver &s) {
     const int l = (int)s.lv.size() - 1;
     bool all_one = true;
     for (auto &q : L.parts) all_one = all_one && q.ncell == 1;
-    const bool last = all_one || l >= s.prm.max_levels - 1 ||
+    // the hybrid tail (Section 3.5) ends the hierarchy at its switch level
+    const int lmax = s.prm.hybrid_level > 0 ? std::min(s.prm.max_levels, s.prm.hybrid_level + 1)
+                                            : s.prm.max_levels;
+    const bool last = all_one || l >= lmax - 1 ||
                       (s.prm.min_coarse_size > 0 && L.N < s.prm.min_coarse_size);
     Level C;
     int64_t coff = 0;
@@ -830,7 +833,11 @@ void setup_symbolic(Solver &s) {
       s.lv[l].parts[p].skip =
           s.prm.skip && l >= ndim && ds >= 0 && ds == s.lv[l - ndim].parts[p].dstar;
     }
-  if (s.prm.coarse == SSAMG_COARSE_DIRECT && s.lv.back().N > kDirectMax)
+  if (s.prm.hybrid_level > 0 && s.lv.back().N > kDenseMax)
+    throw Error(SSAMG_ERR_UNSUPPORTED, "the hybrid tail solves at most " + std::to_string(kDenseMax) +
+                                           " unknowns exactly; level " + std::to_string(s.lv.size() - 1) +
+                                           " has " + std::to_string(s.lv.back().N) + " (choose a coarser level)");
+  if (s.prm.hybrid_level <= 0 && s.prm.coarse == SSAMG_COARSE_DIRECT && s.lv.back().N > kDirectMax)
     throw Error(SSAMG_ERR_UNSUPPORTED, "the direct coarsest solve takes at most " +
                                            std::to_string(kDirectMax) + " unknowns; the coarsest level has " +
                                            std::to_string(s.lv.back().N));
@@ -840,7 +847,7 @@ void setup_symbolic(Solver &s) {
   // collapse level: the first level >= 1 of at most collapse_cells cells, when
   // it is not the coarsest
   s.lk = -1;
-  if (s.collapse_cells > 0)
+  if (s.collapse_cells > 0 && s.prm.hybrid_level <= 0)
     for (int l = 1; l + 1 < (int)s.lv.size(); ++l)
       if (s.lv[l].N <= s.collapse_cells && s.lv[l].N <= kTailMax) {
         s.lk = l;
@@ -918,9 +925,20 @@ void carve(Solver &s, Carver &cv) {
   s.scal = cv.take<double>((size_t)kScalSlots * kMaxRhs);
   s.active = cv.take<int>(kMaxRhs);
   s.flag = cv.take<int>(1);
-  s.lv.back().d_ainv = s.prm.coarse == SSAMG_COARSE_DIRECT
+  const bool hybrid = s.prm.hybrid_level > 0;
+  s.lv.back().d_ainv = !hybrid && s.prm.coarse == SSAMG_COARSE_DIRECT
                            ? cv.take<double>((size_t)s.lv.back().N * s.lv.back().N)
                            : nullptr;
+  // hybrid tail: the coarsest level's dense inverse (padded), the Gauss-Jordan
+  // scratch (transposed column panel, pivot block inverse) and the partial
+  // sums of the applied product
+  {
+    const int64_t nc = s.lv.back().N, npad = hybrid ? dense_pad(nc) : 0;
+    s.d_hyb = hybrid ? cv.take<double>((size_t)npad * npad) : nullptr;
+    s.d_hyb_pt = hybrid ? cv.take<double>((size_t)64 * npad) : nullptr;
+    s.d_hyb_dinv = hybrid ? cv.take<double>(64 * 64) : nullptr;
+    s.d_hyb_part = hybrid ? cv.take<double>((size_t)dense_apply_chunks(nc) * nc * nr) : nullptr;
+  }
   for (int l = 0; l < L; ++l)
     s.lv[l].d_mcyc = l == s.lk ? cv.take<double>((size_t)s.lv[l].N * s.lv[l].N) : nullptr;
   for (int l = 0; l < L; ++l) {
@@ -1128,7 +1146,11 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
         launch_tail_pack<double>((TailLevel<double> *)s.lv[l0].d_tail, L - 1 - l0, s.lv[l0].N, st);
     }
   }
-  if (s.prm.coarse == SSAMG_COARSE_DIRECT) {
+  if (s.d_hyb) {
+    Level &V = s.lv.back();
+    launch_dense_inverse(V.d_desc64, (int)V.parts.size(), V.maxcell, V.N, V.nrow, V.d_urow, V.d_uptr,
+                         V.d_ucol, V.d_uval64, s.d_hyb, s.d_hyb_pt, s.d_hyb_dinv, s.flag, st);
+  } else if (s.prm.coarse == SSAMG_COARSE_DIRECT) {
     Level &V = s.lv.back();
     launch_direct_setup(V.d_desc64, (int)V.parts.size(), (int)V.N, V.nrow, V.d_urow, V.d_uptr, V.d_ucol,
                         V.d_uval64, V.d_ainv, s.flag, st);
@@ -1275,6 +1297,7 @@ namespace {
 // grid kernel on global vectors)
 int tail_start(const Solver &s, int lg) {
   const int L = (int)s.lv.size();
+  if (s.d_hyb) return L - 1;   // hybrid tail: grid levels down to the dense solve
   TailPlan pl;
   const int64_t lim = s.tail_elems >= 0 ? s.tail_elems : (lg >= 2 ? kTailElemsBatched : kTailElems);
   for (int l = 1; l < L; ++l)
@@ -1302,7 +1325,9 @@ void run_tail(Solver &s, int lg) {
     launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
   }
   TailPlan pl;
-  if (grid_collapse)
+  if (s.d_hyb)   // hybrid tail: the exact solve of the switch level, FP64 inverse
+    launch_dense_apply<T>(s.d_hyb, s.lv[lt].N, lg, (const T *)s.lv[lt].vb, (T *)s.lv[lt].vt, s.d_hyb_part, st);
+  else if (grid_collapse)
     launch_coarsest<T>((const TailLevel<T> *)s.lv[lt].d_ctail, s.lv[lt].N << lg, lg, st);
   else if (s.lk >= lt && tail_plan(s, lt, lg, pl, s.lk))   // the cycle ends at the collapse level
     launch_tail<T>((const TailLevel<T> *)s.lv[lt].d_ctail, pl, lg, st);
@@ -1356,6 +1381,10 @@ void precond_t(Solver &s, int lg, bool dots) {
   const PartDesc<T> *d = desc_of<T>(V);
   const size_t tc = sizeof(T), tx = sizeof(T);
   T *x = (T *)V.vx, *t = (T *)V.vt;
+  if (L == 1 && s.d_hyb) {   // one level, solved exactly (hybrid tail at the finest level)
+    launch_dense_apply<double>(s.d_hyb, V.N, lg, s.r, s.z, s.d_hyb_part, st);
+    return;
+  }
   if (L == 1) {
     const bool direct = V.d_ainv != nullptr;
     if (sizeof(T) == sizeof(float)) {

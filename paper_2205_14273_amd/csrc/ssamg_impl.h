@@ -66,6 +66,8 @@ constexpr int64_t kRowSortRecords = int64_t(1) << 20;   // larger coupling produ
 constexpr int64_t kSplitCells = 1 << 20;
 // largest coarsest level the direct solve accepts (its inverse is formed in LDS)
 constexpr int kDirectMax = 64;
+// largest switch level of the hybrid tail (dense FP64 inverse of at most 2 GiB)
+constexpr int64_t kDenseMax = 16384;
 // rows of one part's Galerkin table, staged in LDS by the kernel (3 fine rows x
 // 27 entries x at most 2 weights = 162)
 constexpr int kRapMaxTab = 256;
@@ -160,6 +162,24 @@ struct Problem {
   // 1: the part's given coefficients satisfy a_s(c) = a_{-s}(c+s) to a relative
   // 1e-12 (checked by set_coeffs; finite-volume assembly is symmetric)
   std::vector<int> sym_ok;
+  // parts of several boxes: inclusive sub-boxes {lo[3], hi[3]} of the part's
+  // box (empty: the whole box); cells in none of them are ghost unknowns
+  std::vector<std::vector<std::array<int, 6>>> boxes;
+  // glued faces: face f of part p continues into part `part` through an
+  // index map (point `at` across the face is `nbr_at` there; axis d maps to
+  // axis map[d] with direction dir[d])
+  struct Glue {
+    int part = -1;
+    int at[3], nbr_at[3], map[3], dir[3];
+  };
+  std::vector<std::array<Glue, 6>> glue;
+  // couplings as given (COO, host) and the entries of each part's stencils
+  // that cross a glued face, moved to U by set_coeffs
+  std::vector<int64_t> ucoo_row, ucoo_col;
+  std::vector<double> ucoo_val;
+  std::vector<std::vector<int64_t>> ux_row, ux_col;
+  std::vector<std::vector<double>> ux_val;
+  bool has_topology() const;
   // couplings, canonical compressed-row CSR (host copy + device copy)
   std::vector<int> urow, uptr, ucol;
   std::vector<double> uval_host;
@@ -315,6 +335,9 @@ struct Solver {
   int *active = nullptr;             // [kMaxRhs]
   int *flag = nullptr;               // device error flag
   double *h_pin = nullptr;           // pinned host mirror of a few scalar slots
+  // hybrid tail (hybrid_level > 0): dense inverse of the coarsest level, padded
+  // to a multiple of 64 (row-major, symmetric), and its scratch
+  double *d_hyb = nullptr, *d_hyb_pt = nullptr, *d_hyb_dinv = nullptr, *d_hyb_part = nullptr;
   // graph of one V-cycle
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -555,6 +578,20 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
 void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hipStream_t st);
 void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
                  const int *urow, const int *uptr, int *out, hipStream_t st);
+
+// kernels_dense.hip: exact solve of the hybrid tail's switch level
+int64_t dense_pad(int64_t n);            // order of the padded dense matrix
+int64_t dense_apply_chunks(int64_t n);   // column chunks of the applied product
+// the level's operator (FP64 descriptors and couplings) assembled densely into
+// a (npad x npad) and inverted in place; pt: 64 * npad, dinv: 64 * 64 doubles;
+// flag = 2 when a pivot block is not positive definite
+void launch_dense_inverse(const PartDesc<double> *desc, int nparts, int maxcell, int64_t n, int nrow,
+                          const int *urow, const int *uptr, const int *ucol, const double *uval, double *a,
+                          double *pt, double *dinv, int *flag, hipStream_t st);
+// vt = M vb for 1 << lg right-hand sides ([cell][rhs]); part holds
+// dense_apply_chunks(n) * n << lg doubles
+template <typename T>
+void launch_dense_apply(const double *m, int64_t n, int lg, const T *vb, T *vt, double *part, hipStream_t st);
 
 // kernels_fv.hip
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,

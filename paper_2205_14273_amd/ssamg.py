@@ -82,6 +82,15 @@ def ssamg_problem_set_origin(h, part, origin):
     check(lib().ssamg_problem_set_origin(h, part, _ints(origin)))
 
 
+def ssamg_problem_add_box(h, part, lo, hi):
+    check(lib().ssamg_problem_add_box(h, part, _ints(lo), _ints(hi)))
+
+
+def ssamg_problem_set_neighbor(h, part, face, nbr_part, at, nbr_at, map_, dir_):
+    check(lib().ssamg_problem_set_neighbor(h, part, face, nbr_part, _ints(at), _ints(nbr_at), _ints(map_),
+                                           _ints(dir_)))
+
+
 def ssamg_problem_set_face(h, part, face, kind):
     check(lib().ssamg_problem_set_face(h, part, face, kind))
 
@@ -374,6 +383,28 @@ class Problem:
         for p in range(pr.nparts):
             for f in range(6):
                 ssamg_problem_set_face(pr.h, p, f, int(case.faces[p][f]))
+            ssamg_problem_set_stencil(pr.h, p, case.stencils[p])
+            ssamg_problem_set_coeffs(pr.h, p, np.asarray(case.coeffs[p]).reshape(-1))
+        ssamg_problem_set_coupling(pr.h, case.urow, case.ucol, case.uval)
+        return pr
+
+    @classmethod
+    def from_topo(cls, case):
+        """Problem with parts of several boxes and glued faces: per-part stencil
+        arrays, box lists, neighbour maps and couplings (host arrays)."""
+        pr = cls(case.ndim, case.dims)
+        faces = case.face_kinds()
+        for p in range(pr.nparts):
+            for f in range(6):
+                ssamg_problem_set_face(pr.h, p, f, int(faces[p][f]))
+            for lo, hi in (case.boxes[p] or []):
+                ssamg_problem_add_box(pr.h, p, lo, hi)
+        for p in range(pr.nparts):
+            for f, nb in enumerate(case.neighbors[p]):
+                if nb is not None:
+                    ssamg_problem_set_neighbor(pr.h, p, f, nb["part"], nb["at"], nb["nbr_at"], nb["map"],
+                                               nb["dir"])
+        for p in range(pr.nparts):
             ssamg_problem_set_stencil(pr.h, p, case.stencils[p])
             ssamg_problem_set_coeffs(pr.h, p, np.asarray(case.coeffs[p]).reshape(-1))
         ssamg_problem_set_coupling(pr.h, case.urow, case.ucol, case.uval)

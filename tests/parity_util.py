@@ -13,7 +13,8 @@ def oracle_fv(case, **kw):
     return O.setup(A, g.dims, g.face_kinds(), pat, g.ndim, omega=kw.get("omega", case.omega),
                    max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
                    relax=kw.get("relax", case.relax), coarse=kw.get("coarse", "sweep"),
-                   skip=kw.get("skip", False), pb=kw.get("pb", "one"))
+                   skip=kw.get("skip", False), pb=kw.get("pb", "one"),
+                   hybrid_level=kw.get("hybrid_level", 0))
 
 
 def oracle_raw(case, **kw):
@@ -125,3 +126,18 @@ def assert_cycle_close(z, want, scale, rtol, what=""):
     worst = int(np.argmax(ratio))
     assert ratio[worst] <= rtol, (what, worst, float(ratio[worst]), rtol)
     return float(ratio[worst])
+
+
+def oracle_topo(case, **kw):
+    """Oracle hierarchy of a problem with parts of several boxes and glued faces."""
+    A, off, faces = assemble.assemble_semistructured(case.dims, case.stencils, case.coeffs, case.urow,
+                                                     case.ucol, case.uval, case.boxes, case.neighbors)
+    return O.setup(A, case.dims, case.face_kinds(), case.stencils, case.ndim,
+                   ustruct0=assemble.cross_structure(A, off), **kw)
+
+
+def gpu_topo(case, **params):
+    from paper_2205_14273_amd.ssamg import Problem, Solver
+    pr = Problem.from_topo(case)
+    s = Solver(pr, **params).setup()
+    return pr, s

@@ -790,3 +790,178 @@ def test_lumped_part_boundary_hierarchy(mk):
     ref = ssamg.solve(h, case.b, tol=1e-10)
     xd = np.linalg.solve(h.levels[0].A.toarray(), case.b)
     assert ref.converged and np.linalg.norm(ref.x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_hybrid_tail_is_an_exact_solve_at_the_switch_level():
+    """hybrid_level = k (Section 3.5): k + 1 levels, and the cycle equals the
+    same hierarchy's cycle with an exact coarsest solve; with the smoother off
+    and k = 1 it is P A_1^{-1} P^T, so B A P = P."""
+    case = W.c2(6)
+    _, hk = fv_hierarchy(case, hybrid_level=3)
+    _, hd = fv_hierarchy(case, max_levels=4, coarse="direct")
+    assert hk.nlevels == 4 and hk.coarse == "direct"
+    r = np.random.default_rng(8).uniform(-1, 1, hk.levels[0].n)
+    assert np.array_equal(ssamg.vcycle(hk, r), ssamg.vcycle(hd, r))
+    zk = ssamg.vcycle(hk, r)
+    _, hs = fv_hierarchy(case, max_levels=4)
+    assert np.linalg.norm(zk - ssamg.vcycle(hs, r)) > 0     # the exact solve changes the cycle
+    _, h1 = fv_hierarchy(case, hybrid_level=1)
+    _zero_smoother(h1)
+    A0 = h1.levels[0].A.toarray()
+    P = h1.levels[0].P.toarray()
+    B = np.column_stack([ssamg.vcycle(h1, e) for e in np.eye(A0.shape[0])])
+    assert np.allclose(B @ A0 @ P, P, rtol=0, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# parts of several boxes and glued faces (Section 2; test cases 3 and 4)
+
+
+def _topo_matrix(case):
+    A, off, faces = assemble.assemble_semistructured(case.dims, case.stencils, case.coeffs, case.urow,
+                                                     case.ucol, case.uval, case.boxes, case.neighbors)
+    return A, off, faces
+
+
+def _two_cubes(m, rotated, seed=3):
+    """Two m^3 parts along x, isotropic Laplacian with a random diagonal margin,
+    glued through part 0's +x face; part 1 either in the same orientation or
+    turned by a quarter about z ((i, j, k) -> (m-1-j, i, k))."""
+    offs = W.stencil_offsets(7)
+    rng = np.random.default_rng(seed)
+    marg = [rng.uniform(0, 1, (m, m, m)) for _ in range(2)]      # [k][j][i]
+    co = []
+    for p in range(2):
+        c = np.zeros((7, m, m, m))
+        c[1:] = -1.0
+        c[0] = 6.0 + marg[p]
+        co.append(c)
+    nb = [[None] * 6 for _ in range(2)]
+    if not rotated:
+        nb[0][1] = {"part": 1, "at": (m, 0, 0), "nbr_at": (0, 0, 0), "map": (0, 1, 2), "dir": (1, 1, 1)}
+        nb[1][0] = {"part": 0, "at": (-1, 0, 0), "nbr_at": (m - 1, 0, 0), "map": (0, 1, 2), "dir": (1, 1, 1)}
+    else:
+        rot = np.empty_like(co[1])
+        for i in range(m):
+            for j in range(m):
+                rot[:, :, i, m - 1 - j] = co[1][:, :, j, i]      # rotated cell (m-1-j, i) holds cell (i, j)
+        co[1] = rot
+        nb[0][1] = {"part": 1, "at": (m, 0, 0), "nbr_at": (m - 1, 0, 0), "map": (1, 0, 2), "dir": (1, -1, 1)}
+        nb[1][2] = {"part": 0, "at": (0, -1, 0), "nbr_at": (m - 1, m - 1, 0), "map": (1, 0, 2),
+                    "dir": (-1, 1, 1)}
+    return W.TopoCase("two", [(m, m, m)] * 2, [offs] * 2, co, [None, None], nb,
+                      np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64), np.zeros(0),
+                      rng.uniform(-1, 1, 2 * m ** 3))
+
+
+def test_cartesian_glue_is_the_placed_operator():
+    """Gluing part 0's +x face to part 1's -x face without rotation gives the
+    operator of the same two cubes placed side by side (the finite-volume rule
+    with kappa = 1 and no margin: -1 per link, 6 on the diagonal)."""
+    m = 4
+    case = _two_cubes(m, rotated=False)
+    for c in case.coeffs:
+        c[0] = 6.0
+    A, off, faces = _topo_matrix(case)
+    g = W.geometry_along_x(2, [(m, m, m)] * 2)
+    B, _ = assemble.assemble_fv(g, 7, np.ones(g.n), np.ones((2, 3)))
+    assert abs(A - B).max() == 0.0
+    assert faces.tolist() == [[0, 1, 0, 0, 0, 0], [1, 0, 0, 0, 0, 0]]
+
+
+def test_quarter_turned_part_is_a_permutation():
+    """Turning part 1's index space by a quarter (and its gluing with it) gives
+    the same matrix with part 1's cells renumbered: east couplings of part 0
+    meet north-south couplings of part 1, as in the paper's non-Cartesian case."""
+    m = 4
+    A, off, _ = _topo_matrix(_two_cubes(m, rotated=False))
+    R, _, faces = _topo_matrix(_two_cubes(m, rotated=True))
+    assert faces.tolist() == [[0, 1, 0, 0, 0, 0], [0, 0, 1, 0, 0, 0]]
+    perm = np.arange(2 * m ** 3)             # rotated numbering of each Cartesian cell
+    for k in range(m):
+        for j in range(m):
+            for i in range(m):
+                perm[m ** 3 + i + m * (j + m * k)] = m ** 3 + (m - 1 - j) + m * (i + m * k)
+    P = np.zeros((2 * m ** 3, 2 * m ** 3))
+    P[perm, np.arange(2 * m ** 3)] = 1.0
+    assert np.array_equal(P @ A.toarray() @ P.T, R.toarray())
+
+
+def test_l_shaped_part_by_brute_force():
+    """A part made of two boxes (an L) inside a 6 x 6 x 3 box: the active cells'
+    rows are the 7-point Laplacian of the L-shaped domain built cell by cell;
+    the cells outside both boxes have identity rows and no couplings."""
+    offs = W.stencil_offsets(7)
+    dims = [(6, 6, 3)]
+    co = np.random.default_rng(5).uniform(-3, 3, (7, 3, 6, 6))      # junk everywhere
+    co[1:] = -1.0
+    co[0] = 6.0
+    boxes = [[((0, 0, 0), (5, 2, 2)), ((0, 3, 0), (2, 5, 2))]]
+    case = W.TopoCase("L", dims, [offs], [co], boxes, [[None] * 6], np.zeros(0, dtype=np.int64),
+                      np.zeros(0, dtype=np.int64), np.zeros(0), np.zeros(108))
+    A, _, _ = _topo_matrix(case)
+    act = lambda i, j, k: 0 <= k < 3 and ((0 <= i < 6 and 0 <= j < 3) or (0 <= i < 3 and 3 <= j < 6))
+    D = A.toarray()
+    for k in range(3):
+        for j in range(6):
+            for i in range(6):
+                r = i + 6 * (j + 6 * k)
+                want = np.zeros(108)
+                if not act(i, j, k):
+                    want[r] = 1.0
+                else:
+                    want[r] = 6.0
+                    for dx, dy, dz in offs[1:]:
+                        if act(i + dx, j + dy, k + dz):
+                            want[(i + dx) + 6 * ((j + dy) + 6 * (k + dz))] = -1.0
+                assert np.array_equal(D[r], want), (i, j, k)
+
+
+def test_tc3_junction_invariants():
+    """Three cubes glued around one edge: A is symmetric and SPD, every glued
+    face contributes m^2 couplings of -1 each way, interior and glued rows sum
+    to zero, and PCG with SSAMG reaches the dense solution."""
+    m = 5
+    case = W.tc3_junction(m)
+    A, off, faces = _topo_matrix(case)
+    D = A.toarray()
+    assert np.array_equal(D, D.T) and np.linalg.eigvalsh(D).min() > 0
+    C = assemble.cross_structure(A, off)
+    assert C.nnz == 2 * 3 * m * m
+    assert np.all(A[C.nonzero()] == -1.0)
+    part = np.repeat(np.arange(3), m ** 3)
+    h = ssamg.setup(A, case.dims, faces, case.stencils, 3, ustruct0=C)
+    ref = ssamg.solve(h, case.b, tol=1e-10)
+    xd = np.linalg.solve(D, case.b)
+    assert ref.converged and np.linalg.norm(ref.x - xd) <= 1e-8 * np.linalg.norm(xd)
+    # every part coarsens along the same directions (isotropic, equal boxes)
+    assert [l.dstar[0] for l in h.levels] == [l.dstar[1] for l in h.levels] == [l.dstar[2] for l in h.levels]
+    assert part.size == A.shape[0]
+
+
+def test_tc4_samr_invariants():
+    """SAMR: ghost rows are the identity, fine-coarse couplings are -2/3 both
+    ways (four per coarse face of the patch), the patch's rows sum to zero,
+    A is symmetric and SPD, and PCG with SSAMG reaches the dense solution."""
+    m = 8
+    case = W.tc4_samr(m)
+    A, off, _ = _topo_matrix(case)
+    D = A.toarray()
+    assert np.array_equal(D, D.T) and np.linalg.eigvalsh(D).min() > 0
+    a, b = m // 4, 3 * m // 4
+    for k in range(a, b):
+        for j in range(a, b):
+            for i in range(a, b):
+                r = i + m * (j + m * k)
+                row = np.zeros(D.shape[0])
+                row[r] = 1.0
+                assert np.array_equal(D[r], row)
+    C = assemble.cross_structure(A, off)
+    assert np.allclose(A[C.nonzero()], -2.0 / 3.0, rtol=0, atol=0)
+    assert C.nnz == 2 * 6 * m * m                    # every fine boundary cell face, both ways
+    rs = np.asarray(A.sum(axis=1)).ravel()
+    assert np.max(np.abs(rs[m ** 3:])) <= 1e-13      # the patch is interior
+    h = ssamg.setup(A, case.dims, case.face_kinds(), case.stencils, 3, ustruct0=C)
+    ref = ssamg.solve(h, case.b, tol=1e-10)
+    xd = np.linalg.solve(D, case.b)
+    assert ref.converged and np.linalg.norm(ref.x - xd) <= 1e-8 * np.linalg.norm(xd)

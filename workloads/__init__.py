@@ -321,3 +321,163 @@ def geometry_along_x(nparts: int, dims) -> Geometry:
         origins.append((x, 0, 0))
         x += d[0]
     return Geometry(3 if any(d[2] > 1 for d in dims) else 2, list(dims), origins)
+
+
+# ---------------------------------------------------------------------------
+# parts glued with rotated index spaces, and parts of several boxes
+# (the shapes of the paper's test cases 3 and 4, Section 4)
+
+
+@dataclass
+class TopoCase:
+    """A semi-structured problem given as per-part stencils plus topology: the
+    boxes of each part (None: the whole box; cells in no box are ghost
+    unknowns) and glued faces (neighbour maps), with user couplings U.
+
+    ``neighbors[p][f]`` is None or {"part", "at", "nbr_at", "map", "dir"}: the
+    point ``at`` just across face f of part p has index ``nbr_at`` in the
+    neighbour part, and part p's axis d maps to the neighbour's axis map[d]
+    with direction dir[d].
+    """
+    name: str
+    dims: list
+    stencils: list                    # [nent][3] per part
+    coeffs: list                      # [nent][nz][ny][nx] per part
+    boxes: list                       # per part: None or [(lo, hi), ...] inclusive
+    neighbors: list                   # per part: 6 entries, None or a dict
+    urow: np.ndarray
+    ucol: np.ndarray
+    uval: np.ndarray
+    b: np.ndarray
+    ndim: int = 3
+    faces: Optional[list] = None      # [nparts][6] face kinds; None: glued faces are part faces
+
+    @property
+    def n(self) -> int:
+        return int(sum(a * b * c for a, b, c in self.dims))
+
+    def face_kinds(self):
+        if self.faces is not None:
+            return np.asarray(self.faces)
+        return np.array([[0 if nb is None else 1 for nb in self.neighbors[p]] for p in range(len(self.dims))])
+
+
+def _laplacian_coeffs(dims, offs, off_value, rng=None, spread=0.0):
+    """Constant 7-point coefficients (off-diagonal off_value, diagonal the sum of
+    their magnitudes) on every cell of a box, optionally perturbed per link
+    symmetrically would need a global view, so only the diagonal is perturbed
+    (a positive random margin keeps the matrix an M-matrix)."""
+    nx, ny, nz = dims
+    co = np.zeros((len(offs), nz, ny, nx))
+    for e, s in enumerate(offs):
+        if tuple(s) != (0, 0, 0):
+            co[e] = off_value
+    co[0] = -off_value * (len(offs) - 1)
+    if rng is not None and spread > 0:
+        co[0] += rng.uniform(0.0, spread, (nz, ny, nx))
+    return co
+
+
+def tc3_junction(m: int = 16, seed: int = 6000) -> TopoCase:
+    """Three m^3 parts around a common edge along z (a three-point intersection
+    in the xy-plane): the +x face of part p is glued to the +y face of part
+    p+1 (mod 3) with the index space rotated by a quarter turn, so an east
+    coefficient of one part couples to a north coefficient of the next.
+    Isotropic 7-point Laplacian (diagonal 6, off-diagonal -1), zero Dirichlet
+    on every other face, right-hand side U[-1, 1]."""
+    offs = stencil_offsets(7)
+    dims = [(m, m, m)] * 3
+    neighbors = [[None] * 6 for _ in range(3)]
+    for p in range(3):
+        q = (p + 1) % 3
+        # across p's +x face: (m + a, j, k) -> (j, m - 1 - a, k) in part q
+        neighbors[p][1] = {"part": q, "at": (m, 0, 0), "nbr_at": (0, m - 1, 0),
+                           "map": (1, 0, 2), "dir": (-1, 1, 1)}
+        # across q's +y face: (i, m + a, k) -> (m - 1 - a, i, k) in part p
+        neighbors[q][3] = {"part": p, "at": (0, m, 0), "nbr_at": (m - 1, 0, 0),
+                           "map": (1, 0, 2), "dir": (1, -1, 1)}
+    coeffs = [_laplacian_coeffs(d, offs, -1.0) for d in dims]
+    rng = np.random.default_rng(seed)
+    n = 3 * m ** 3
+    return TopoCase("tc3", dims, [offs] * 3, coeffs, [None] * 3, neighbors,
+                    np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64), np.zeros(0),
+                    rng.uniform(-1, 1, n))
+
+
+def tc4_samr(m: int = 16, seed: int = 7000, junk: bool = True) -> TopoCase:
+    """One level of refinement: part 0 is the coarse m^3 grid, part 1 an m^3
+    patch refined by two covering the central (m/2)^3 coarse cells, which are
+    ghost unknowns of part 0 (part 0 is the union of the six slabs around
+    them).  7-point finite-volume couplings scaled by the fine spacing: -1
+    between fine cells, -2 between coarse cells, -2/3 between a fine cell and
+    the coarse cell across the patch face (both ways, in U); diagonals are the
+    sums of a row's couplings, a zero-Dirichlet ghost outside the domain
+    counting as a coarse link.  With ``junk`` the ghost cells' given
+    coefficients are random and must be replaced by an identity row."""
+    if m % 4:
+        raise ValueError("m must be a multiple of 4")
+    offs = stencil_offsets(7)
+    a, b = m // 4, 3 * m // 4            # hole [a, b)^3 in coarse indices
+    rng = np.random.default_rng(seed)
+    dims = [(m, m, m), (m, m, m)]
+    # part 0: the six slabs around the hole
+    boxes0 = [((0, 0, 0), (m - 1, m - 1, a - 1)), ((0, 0, b), (m - 1, m - 1, m - 1)),
+              ((0, 0, a), (m - 1, a - 1, b - 1)), ((0, b, a), (m - 1, m - 1, b - 1)),
+              ((0, a, a), (a - 1, b - 1, b - 1)), ((b, a, a), (m - 1, b - 1, b - 1))]
+
+    def in_hole(i, j, k):
+        return a <= i < b and a <= j < b and a <= k < b
+
+    co0 = np.zeros((7, m, m, m))
+    co1 = np.zeros((7, m, m, m))
+    urow, ucol, uval = [], [], []
+    off0, off1 = 0, m ** 3
+    for k in range(m):
+        for j in range(m):
+            for i in range(m):
+                # coarse cell
+                if in_hole(i, j, k):
+                    co0[:, k, j, i] = rng.uniform(-3, 3, 7) if junk else 0.0
+                else:
+                    diag = 0.0
+                    for e, (dx, dy, dz) in enumerate(offs[1:], start=1):
+                        t = (i + dx, j + dy, k + dz)
+                        if not all(0 <= t[d] < m for d in range(3)):
+                            diag += 2.0                      # Dirichlet ghost
+                        elif in_hole(*t):
+                            # the face of the patch: four fine cells across it
+                            ax = [d for d in range(3) if (dx, dy, dz)[d] != 0][0]
+                            f0 = [2 * (v - a) for v in (i, j, k)]
+                            f0[ax] = 0 if (dx, dy, dz)[ax] > 0 else m - 1
+                            others = [d for d in range(3) if d != ax]
+                            for u in range(2):
+                                for v in range(2):
+                                    f = list(f0)
+                                    f[others[0]] += u
+                                    f[others[1]] += v
+                                    fid = off1 + f[0] + m * (f[1] + m * f[2])
+                                    cid = off0 + i + m * (j + m * k)
+                                    urow += [cid, fid]
+                                    ucol += [fid, cid]
+                                    uval += [-2.0 / 3.0, -2.0 / 3.0]
+                                    diag += 2.0 / 3.0
+                        else:
+                            co0[e, k, j, i] = -2.0
+                            diag += 2.0
+                    co0[0, k, j, i] = diag
+                # fine cell (i, j, k) of the patch
+                diag = 0.0
+                for e, (dx, dy, dz) in enumerate(offs[1:], start=1):
+                    t = (i + dx, j + dy, k + dz)
+                    if all(0 <= t[d] < m for d in range(3)):
+                        co1[e, k, j, i] = -1.0
+                        diag += 1.0
+                    else:
+                        diag += 2.0 / 3.0                # the coupling to the coarse cell across
+                co1[0, k, j, i] = diag
+    n = 2 * m ** 3
+    # the patch's faces all border the coarse part (couplings in U)
+    return TopoCase("tc4", dims, [offs, offs], [co0, co1], [boxes0, None],
+                    [[None] * 6, [None] * 6], np.asarray(urow, dtype=np.int64),
+                    np.asarray(ucol, dtype=np.int64), np.asarray(uval), rng.uniform(-1, 1, n),
+                    faces=[[0] * 6, [1] * 6])
