@@ -185,24 +185,210 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
   }
 }
 
-// Structured Galerkin product for one coarse cell I of a part coarsened along
-// d*: fine rows f = 2I + r (r = -1, 0, 1) carry the restriction weights
-// rho_{-1} = wp(2I-1), rho_0 = 1, rho_{+1} = wm(2I+1); each fine coefficient
-// a_s(f) reaches fine cell g = f + s, which is coarse (weight 1) when
-// q = r + s_d* is even and an F cell (weights wm(g), wp(g) toward its two
-// coarse neighbours) when q is odd.  The host table lists, for each coarse
-// entry, the (r, s, which-weight-of-g) triples that land on it.
+// Structured Galerkin product P^T S P (Section 3.3, eq:galerkin), factorised
+// along d*.  Coarse cell I of a part coarsened along d* has the fine rows
+// f_r = 2I + r (r = -1, 0, 1) with restriction weights rho_{-1} = wp(2I-1),
+// rho_0 = 1, rho_{+1} = wm(2I+1).  Write a stencil offset as (t, s) with t its
+// two components across d* and s its d* component.  The coefficient a_(t,s)(f_r)
+// reaches the fine cell at d* offset q = r + s from 2I, so for each t the sums
+//   B_t(q) = sum_r rho_r a_(t, q-r)(f_r),   q = -2 .. 2,   (r ascending)
+// collect everything that lands there.  An even q is a coarse cell (weight 1)
+// at coarse offset q/2; an odd q is an F cell whose weights wm, wp carry it to
+// the coarse offsets (q-1)/2 and (q+1)/2.  Hence the coarse entry
+//   c_(t,Q)(I) = B_t(2Q) + B_t(2Q-1) wp(F_{2Q-1}) + B_t(2Q+1) wm(F_{2Q+1}),
+// with every term whose fine or F cell lies outside the box left out.  Each of
+// the 3 x 27 fine coefficients is read once per coarse cell and each F weight
+// once per perpendicular offset.
 //
-// Two thread layouts form the same sums in the same order, so the same values.
-// Small coarse levels: one thread per (coarse cell, coarse entry), so that
-// even a few thousand coarse cells give enough threads; a block covers one
-// entry of a tile of kBlock coarse cells, its threads read the same table rows
-// and neighbouring fine coefficients, and each thread gathers its entry's
-// contributions kRapEntryBatch at a time.  The blocks of one tile are
-// consecutive in the XCD-aware block order, so they read the tile's fine
-// coefficients through one XCD's L2.
-constexpr int kRapEntryBatch = 4;
+// Two thread layouts evaluate the same expressions with the same operations:
+// one thread per coarse cell for large levels (all entries; it also reads every
+// coefficient of rows 2I and 2I+1, so it forms their L1 row sums and the FP32
+// copy of the finest level on the way), one thread per (coarse cell, entry)
+// for small ones.  The results agree bit for bit.
 
+__host__ __device__ constexpr int cube_stride(int a) { return a == 0 ? 1 : a == 1 ? 3 : 9; }
+
+__device__ __forceinline__ int cube_comp(int o, int a) {
+  return (a == 0 ? o % 3 : a == 1 ? (o / 3) % 3 : o / 9) - 1;
+}
+
+// B_t(q) from the three rows' coefficients a[r+1][s+1] (pres[s+1]: the fine
+// stencil has the offset (t, s))
+__device__ __forceinline__ double rap_b(int q, const double (&a)[3][3], const bool (&pres)[3],
+                                        const double (&rho)[3]) {
+  double b = 0.0;
+#pragma unroll
+  for (int r = -1; r <= 1; ++r) {
+    const int sd = q - r;
+    if (sd < -1 || sd > 1 || !pres[sd + 1]) continue;
+    b = fma(rho[r + 1], a[r + 1][sd + 1], b);
+  }
+  return b;
+}
+
+// c_(t,Q) from B_t(2Q) (ve: its cell is in the box) and the F cells below
+// (vl, weight wl) and above (vh, weight wh)
+__device__ __forceinline__ double rap_combine(bool ve, double be, bool vl, double bl, double wl, bool vh,
+                                              double bh, double wh) {
+  double acc = ve ? be : 0.0;
+  acc = fma(vl ? bl : 0.0, wl, acc);
+  acc = fma(vh ? bh : 0.0, wh, acc);
+  return acc;
+}
+
+// per coarse cell: coordinates, the fine rows (clamped into the box; a row
+// outside has rho = 0), restriction weights and the F-box cell of index
+// (I across d*, I along d*)
+struct RapGeo {
+  int ci[3];
+  int fb, nd;
+  bool row_ok[3];
+  double rho[3];
+  long long fr[3];
+  long long h0;
+};
+
+template <int DS>
+__device__ __forceinline__ void rap_geo(const PartDesc<double> &d, long long cidx, RapGeo &g) {
+  cell_ijk((int)cidx, d.cn[0], d.cn[1], g.ci[0], g.ci[1], g.ci[2]);
+  g.nd = d.n[DS];
+  g.fb = 2 * g.ci[DS];
+  g.row_ok[0] = g.fb >= 1;
+  g.row_ok[1] = true;
+  g.row_ok[2] = g.fb + 1 <= g.nd - 1;
+  const long long strd = DS == 0 ? 1 : DS == 1 ? (long long)d.n[0] : (long long)d.n[0] * d.n[1];
+  const long long fstrd = DS == 0 ? 1 : DS == 1 ? (long long)d.fn[0] : (long long)d.fn[0] * d.fn[1];
+  int fc[3] = {g.ci[0], g.ci[1], g.ci[2]};
+  fc[DS] = g.fb;
+  const long long f0 = fc[0] + (long long)d.n[0] * (fc[1] + (long long)d.n[1] * fc[2]);
+  g.fr[0] = g.row_ok[0] ? f0 - strd : f0;
+  g.fr[1] = f0;
+  g.fr[2] = g.row_ok[2] ? f0 + strd : f0;
+  g.h0 = g.ci[0] + (long long)d.fn[0] * (g.ci[1] + (long long)d.fn[1] * g.ci[2]);
+  g.rho[0] = g.row_ok[0] ? dev::G(d.wp)[g.h0 - fstrd] : 0.0;
+  g.rho[1] = 1.0;
+  g.rho[2] = g.row_ok[2] ? dev::G(d.wm)[g.h0] : 0.0;
+}
+
+template <int DS>
+__device__ __forceinline__ long long fstride(const PartDesc<double> &d) {
+  return DS == 0 ? 1 : DS == 1 ? (long long)d.fn[0] : (long long)d.fn[0] * d.fn[1];
+}
+
+// the three rows' coefficients of perpendicular offset (ta, tb)
+template <int DS>
+__device__ __forceinline__ void rap_rows(const PartDesc<double> &d, const RapDesc &t, const RapGeo &g,
+                                         int ob, double (&a)[3][3], bool (&pres)[3], int (&ent)[3]) {
+  const auto coef = dev::G(d.coef);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    ent[s] = t.fmap[ob + s * cube_stride(DS)];
+    pres[s] = ent[s] >= 0;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+      a[r][s] = pres[s] ? coef[(long long)ent[s] * d.ncell + g.fr[r]] : 0.0;
+}
+
+// one coarse cell, every entry
+template <int DS>
+__device__ __forceinline__ void rap_cell(const PartDesc<double> &d, const RapDesc &t, long long cidx) {
+  constexpr int AX = (DS + 1) % 3, BX = (DS + 2) % 3;
+  RapGeo g;
+  rap_geo<DS>(d, cidx, g);
+  const auto wm = dev::G(d.wm), wp = dev::G(d.wp);
+  const auto out = dev::Gw(t.out);
+  const auto out32 = dev::Gw(t.out32);
+  const auto f32 = dev::Gw(t.fine32);
+  const long long fa = AX == 0 ? 1 : AX == 1 ? (long long)d.fn[0] : (long long)d.fn[0] * d.fn[1];
+  const long long fbx = BX == 0 ? 1 : BX == 1 ? (long long)d.fn[0] : (long long)d.fn[0] * d.fn[1];
+  const long long fd = fstride<DS>(d);
+  const bool okm = g.row_ok[0], okp = g.row_ok[2];
+  const bool ok2m = g.fb - 2 >= 0, ok2p = g.fb + 2 <= g.nd - 1;
+  double l1c = 0.0, l1f = 0.0;
+#pragma unroll
+  for (int tb = -1; tb <= 1; ++tb) {
+#pragma unroll
+    for (int ta = -1; ta <= 1; ++ta) {
+      const int ob = (ta + 1) * cube_stride(AX) + (tb + 1) * cube_stride(BX);
+      double a[3][3];
+      bool pres[3];
+      int ent[3];
+      rap_rows<DS>(d, t, g, ob, a, pres, ent);
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        if (!pres[s]) continue;
+        l1c += fabs(a[1][s]);
+        l1f += fabs(a[2][s]);
+        if (t.fine32) {
+          f32[(long long)ent[s] * d.ncell + g.fr[1]] = (float)a[1][s];
+          if (okp) f32[(long long)ent[s] * d.ncell + g.fr[2]] = (float)a[2][s];
+        }
+      }
+      const bool perp = (unsigned)(g.ci[AX] + ta) < (unsigned)d.n[AX] &&
+                        (unsigned)(g.ci[BX] + tb) < (unsigned)d.n[BX];
+      const long long tl = ta * fa + tb * fbx;
+      const bool vm = perp && okm, vp = perp && okp;
+      const long long gm = vm ? g.h0 - fd + tl : 0, gp = vp ? g.h0 + tl : 0;
+      const double wmm = wm[gm], wpm = wp[gm], wmp = wm[gp], wpp = wp[gp];
+      const double bm1 = rap_b(-1, a, pres, g.rho), bp1 = rap_b(1, a, pres, g.rho);
+      double v[3];
+      v[0] = rap_combine(perp && ok2m, rap_b(-2, a, pres, g.rho), false, 0.0, 0.0, vm, bm1, wmm);
+      v[1] = rap_combine(perp, rap_b(0, a, pres, g.rho), vm, bm1, wpm, vp, bp1, wmp);
+      v[2] = rap_combine(perp && ok2p, rap_b(2, a, pres, g.rho), vp, bp1, wpp, false, 0.0, 0.0);
+#pragma unroll
+      for (int Q = 0; Q < 3; ++Q) {
+        const int e = t.cmap[ob + Q * cube_stride(DS)];
+        if (e < 0) continue;
+        out[(long long)e * d.cncell + cidx] = v[Q];
+        if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)v[Q];
+      }
+    }
+  }
+  if (t.l1) {
+    const auto l1 = dev::Gw(t.l1);
+    l1[g.fr[1]] = l1c;
+    if (okp) l1[g.fr[2]] = l1f;
+  }
+}
+
+// one coarse cell, one entry (cube offset o)
+template <int DS>
+__device__ __forceinline__ double rap_entry_value(const PartDesc<double> &d, const RapDesc &t, long long cidx,
+                                                  int o) {
+  constexpr int AX = (DS + 1) % 3, BX = (DS + 2) % 3;
+  RapGeo g;
+  rap_geo<DS>(d, cidx, g);
+  const int ta = cube_comp(o, AX), tb = cube_comp(o, BX), Q = cube_comp(o, DS);
+  const int ob = (ta + 1) * cube_stride(AX) + (tb + 1) * cube_stride(BX);
+  double a[3][3];
+  bool pres[3];
+  int ent[3];
+  rap_rows<DS>(d, t, g, ob, a, pres, ent);
+  const long long fa = AX == 0 ? 1 : AX == 1 ? (long long)d.fn[0] : (long long)d.fn[0] * d.fn[1];
+  const long long fbx = BX == 0 ? 1 : BX == 1 ? (long long)d.fn[0] : (long long)d.fn[0] * d.fn[1];
+  const bool perp = (unsigned)(g.ci[AX] + ta) < (unsigned)d.n[AX] &&
+                    (unsigned)(g.ci[BX] + tb) < (unsigned)d.n[BX];
+  const long long tl = ta * fa + tb * fbx;
+  const bool vm = perp && g.row_ok[0], vp = perp && g.row_ok[2];
+  const long long gm = vm ? g.h0 - fstride<DS>(d) + tl : 0, gp = vp ? g.h0 + tl : 0;
+  const auto wm = dev::G(d.wm), wp = dev::G(d.wp);
+  if (Q < 0)
+    return rap_combine(perp && g.fb - 2 >= 0, rap_b(-2, a, pres, g.rho), false, 0.0, 0.0, vm,
+                       rap_b(-1, a, pres, g.rho), wm[gm]);
+  if (Q == 0)
+    return rap_combine(perp, rap_b(0, a, pres, g.rho), vm, rap_b(-1, a, pres, g.rho), wp[gm], vp,
+                       rap_b(1, a, pres, g.rho), wm[gp]);
+  return rap_combine(perp && g.fb + 2 <= g.nd - 1, rap_b(2, a, pres, g.rho), vp, rap_b(1, a, pres, g.rho),
+                     wp[gp], false, 0.0, 0.0);
+}
+
+// Small coarse levels: one thread per (coarse cell, coarse entry); a block
+// covers one entry of a tile of kBlock coarse cells, and the blocks of one
+// tile are consecutive in the XCD-aware order, so they read the tile's fine
+// coefficients through one XCD's L2.
 __global__ __launch_bounds__(kBlock) void k_rap_entry(const PartDesc<double> *__restrict__ desc,
                                                       const RapDesc *__restrict__ rd, int nent_max) {
   const PartDesc<double> &d = desc[blockIdx.y];
@@ -211,201 +397,42 @@ __global__ __launch_bounds__(kBlock) void k_rap_entry(const PartDesc<double> *__
   const int e = lb % nent_max;
   const long long cidx = (long long)(lb / nent_max) * kBlock + threadIdx.x;
   if (e >= t.nent || cidx >= d.cncell) return;
-  if (d.dstar < 0) {
-    // identity transfer: same operator, entries permuted into the sorted pattern
-    const double v = dev::G(d.coef)[(long long)dev::G(t.code)[e] * d.ncell + cidx];
-    dev::Gw(t.out)[(long long)e * d.cncell + cidx] = v;
-    if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)v;
-    return;
+  const int o = t.cofs[e];
+  double v;
+  switch (d.dstar) {
+    case 0: v = rap_entry_value<0>(d, t, cidx, o); break;
+    case 1: v = rap_entry_value<1>(d, t, cidx, o); break;
+    case 2: v = rap_entry_value<2>(d, t, cidx, o); break;
+    default:   // identity transfer: the same operator, entries in the coarse order
+      v = dev::G(d.coef)[(long long)t.fmap[o] * d.ncell + cidx];
   }
-  const int ds = d.dstar;
-  int ci[3];
-  cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
-  const int nd = d.n[ds];
-  const int fb = 2 * ci[ds];
-  double rho[3];
-  bool row_ok[3];
-  {
-    int g[3] = {ci[0], ci[1], ci[2]};
-    row_ok[0] = fb - 1 >= 0;
-    row_ok[1] = true;
-    row_ok[2] = fb + 1 <= nd - 1;
-    g[ds] = ci[ds] - 1;
-    rho[0] = row_ok[0] ? dev::G(d.wp)[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
-    rho[1] = 1.0;
-    g[ds] = ci[ds];
-    rho[2] = row_ok[2] ? dev::G(d.wm)[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
-  }
-  // Per-thread bases; every contribution then adds block-uniform offsets: the
-  // fine row f = 2I + r is f0 + r*stride(d*), the neighbour g = f + s is in the
-  // box when each coordinate is, and an odd g's F-box cell is h0 plus the
-  // offsets of s (with (r + s_d* - 1)/2 along d*).
-  int fc[3] = {ci[0], ci[1], ci[2]};
-  fc[ds] = fb;
-  const long long f0 = fc[0] + (long long)d.n[0] * (fc[1] + (long long)d.n[1] * fc[2]);
-  const long long h0 = ci[0] + (long long)d.fn[0] * (ci[1] + (long long)d.fn[1] * ci[2]);
-  const long long str[3] = {1, d.n[0], (long long)d.n[0] * d.n[1]};
-  const long long fstr[3] = {1, d.fn[0], (long long)d.fn[0] * d.fn[1]};
-  double acc = 0.0;
-  const int q0 = dev::G(t.start)[e], q1 = dev::G(t.start)[e + 1];
-  for (int qb = q0; qb < q1; qb += kRapEntryBatch) {
-    double av[kRapEntryBatch], wv[kRapEntryBatch], rv[kRapEntryBatch];
-#pragma unroll
-    for (int u = 0; u < kRapEntryBatch; ++u) {
-      const int q = qb + u;
-      av[u] = 0.0;
-      wv[u] = 1.0;
-      rv[u] = 0.0;
-      if (q >= q1) continue;
-      const int w = dev::G(t.code)[q];
-      const int r = (w & 3) - 1;
-      const int sidx = (w >> 2) & 31;
-      const int gsel = (w >> 7) & 3;
-      const int cs = d.code[sidx];
-      const int o[3] = {off_comp(cs, 0), off_comp(cs, 1), off_comp(cs, 2)};
-      bool in = row_ok[r + 1] && (unsigned)(fb + r + o[ds]) < (unsigned)nd;
-      long long dfine = r * str[ds], dh = ((r + o[ds] - 1) >> 1) * fstr[ds];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (a == ds) continue;
-        in = in && (unsigned)(ci[a] + o[a]) < (unsigned)d.n[a];
-        dh += o[a] * fstr[a];
-      }
-      if (!in) continue;
-      av[u] = dev::G(d.coef)[(long long)sidx * d.ncell + f0 + dfine];
-      rv[u] = rho[r + 1];
-      if (gsel != 0) wv[u] = gsel == 1 ? dev::G(d.wm)[h0 + dh] : dev::G(d.wp)[h0 + dh];
-    }
-#pragma unroll
-    for (int u = 0; u < kRapEntryBatch; ++u) acc = fma(rv[u] * av[u], wv[u], acc);
-  }
-  dev::Gw(t.out)[(long long)e * d.cncell + cidx] = acc;
-  if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)acc;
+  dev::Gw(t.out)[(long long)e * d.cncell + cidx] = v;
+  if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)v;
 }
 
-// Large coarse levels: one thread per coarse cell and all coarse entries.  The
-// per-cell work (coarse coordinates, restriction weights, fine and F-box bases)
-// is done once, and the whole table (at most kRapMaxTab rows) is staged in LDS first with its
-// block-uniform parts worked out (coefficient offset, F-box offset, row r,
-// weight selector, neighbour offsets), so no thread waits on a table load
-// before its gathers.  Each thread walks the table kRapBatch rows at a time
-// with every load of a batch in flight before the sums, which keep the table
-// order within each entry; an entry's sum is stored when the walk passes its
-// last row.
-constexpr int kRapBatch = 8;
-
+// Large coarse levels: one thread per coarse cell.
 __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restrict__ desc,
                                                 const RapDesc *__restrict__ rd) {
-  __shared__ long long s_cof[kRapMaxTab], s_dh[kRapMaxTab];
-  __shared__ int s_w[kRapMaxTab];
-  __shared__ int s_start[kMaxEnt + 1];
   const PartDesc<double> &d = desc[blockIdx.y];
   const RapDesc &t = rd[blockIdx.y];
-  const long long tile = (long long)dev::chunk_index() * kBlock;
-  if (tile >= d.cncell) return;                      // block-uniform
-  const long long cidx = tile + threadIdx.x;
-  const bool valid = cidx < d.cncell;
-  const auto coef = dev::G(d.coef);
-  const auto out = dev::Gw(t.out);
-  const auto out32 = dev::Gw(t.out32);
-  const int nent = t.nent;
-  if (d.dstar < 0) {
-    // identity transfer: same operator, entries permuted into the sorted pattern
-    if (!valid) return;
-    for (int e = 0; e < nent; ++e) {
-      const double v = coef[(long long)dev::G(t.code)[e] * d.ncell + cidx];
-      out[(long long)e * d.cncell + cidx] = v;
-      if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)v;
-    }
-    return;
-  }
-  const int ds = d.dstar;
-  const long long str[3] = {1, d.n[0], (long long)d.n[0] * d.n[1]};
-  const long long fstr[3] = {1, d.fn[0], (long long)d.fn[0] * d.fn[1]};
-  const int ntab = dev::G(t.start)[nent];
-  for (int q = threadIdx.x; q < ntab; q += kBlock) {
-    const int w = dev::G(t.code)[q];
-    const int r = (w & 3) - 1;
-    const int sidx = (w >> 2) & 31;
-    const int gsel = (w >> 7) & 3;
-    const int cs = d.code[sidx];
-    long long dh = ((r + off_comp(cs, ds) - 1) >> 1) * fstr[ds];
-    for (int a = 0; a < 3; ++a)
-      if (a != ds) dh += off_comp(cs, a) * fstr[a];
-    s_cof[q] = (long long)sidx * d.ncell + r * str[ds];
-    s_dh[q] = dh;
-    s_w[q] = (r + 1) | (gsel << 2) | ((cs & 63) << 4);
-  }
-  if ((int)threadIdx.x <= nent) s_start[threadIdx.x] = dev::G(t.start)[threadIdx.x];
-  __syncthreads();
-  if (!valid) return;
-  int ci[3];
-  cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
-  const int nd = d.n[ds];
-  const int fb = 2 * ci[ds];
-  const auto wm = dev::G(d.wm), wp = dev::G(d.wp);
-  double rho[3];
-  bool row_ok[3];
-  {
-    int g[3] = {ci[0], ci[1], ci[2]};
-    row_ok[0] = fb - 1 >= 0;
-    row_ok[1] = true;
-    row_ok[2] = fb + 1 <= nd - 1;
-    g[ds] = ci[ds] - 1;
-    rho[0] = row_ok[0] ? wp[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
-    rho[1] = 1.0;
-    g[ds] = ci[ds];
-    rho[2] = row_ok[2] ? wm[g[0] + d.fn[0] * (g[1] + d.fn[1] * g[2])] : 0.0;
-  }
-  // Per-thread bases; every row then adds block-uniform offsets: the fine row
-  // f = 2I + r is f0 + r*stride(d*), the neighbour g = f + s is in the box when
-  // each coordinate is, and an odd g's F-box cell is h0 plus the offsets of s
-  // (with (r + s_d* - 1)/2 along d*).
-  int fc[3] = {ci[0], ci[1], ci[2]};
-  fc[ds] = fb;
-  const long long f0 = fc[0] + (long long)d.n[0] * (fc[1] + (long long)d.n[1] * fc[2]);
-  const long long h0 = ci[0] + (long long)d.fn[0] * (ci[1] + (long long)d.fn[1] * ci[2]);
-  double acc = 0.0;
-  int e = 0;
-  int next = s_start[1];
-  for (int qb = 0; qb < ntab; qb += kRapBatch) {
-    double av[kRapBatch], wv[kRapBatch], rv[kRapBatch];
-#pragma unroll
-    for (int u = 0; u < kRapBatch; ++u) {
-      const int q = qb + u;
-      av[u] = 0.0;
-      wv[u] = 1.0;
-      rv[u] = 0.0;
-      if (q >= ntab) continue;                       // block-uniform
-      const int w = s_w[q];
-      const int r = (w & 3) - 1, gsel = (w >> 2) & 3, cs = w >> 4;
-      bool in = row_ok[r + 1] && (unsigned)(fb + r + off_comp(cs, ds)) < (unsigned)nd;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        if (a != ds) in = in && (unsigned)(ci[a] + off_comp(cs, a)) < (unsigned)d.n[a];
-      if (!in) continue;
-      av[u] = coef[s_cof[q] + f0];
-      rv[u] = rho[r + 1];
-      if (gsel != 0) wv[u] = gsel == 1 ? wm[h0 + s_dh[q]] : wp[h0 + s_dh[q]];
-    }
-#pragma unroll
-    for (int u = 0; u < kRapBatch; ++u) {
-      const int q = qb + u;
-      if (q >= ntab) break;                          // block-uniform
-      while (q == next) {                            // entry e complete (block-uniform)
-        out[(long long)e * d.cncell + cidx] = acc;
-        if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)acc;
-        acc = 0.0;
-        ++e;
-        next = s_start[e + 1];
+  const long long cidx = (long long)dev::chunk_index() * kBlock + threadIdx.x;
+  if (cidx >= d.cncell) return;
+  switch (d.dstar) {
+    case 0: rap_cell<0>(d, t, cidx); break;
+    case 1: rap_cell<1>(d, t, cidx); break;
+    case 2: rap_cell<2>(d, t, cidx); break;
+    default: {   // identity transfer
+      double l1 = 0.0;
+      for (int e = 0; e < t.nent; ++e) {
+        const int fe = t.fmap[t.cofs[e]];
+        const double v = dev::G(d.coef)[(long long)fe * d.ncell + cidx];
+        dev::Gw(t.out)[(long long)e * d.cncell + cidx] = v;
+        if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)v;
+        if (t.fine32) dev::Gw(t.fine32)[(long long)fe * d.ncell + cidx] = (float)v;
+        l1 += fabs(v);
       }
-      acc = fma(rv[u] * av[u], wv[u], acc);
+      if (t.l1) dev::Gw(t.l1)[cidx] = l1;
     }
-  }
-  for (; e < nent; ++e) {                            // the last entry, and any empty ones after it
-    out[(long long)e * d.cncell + cidx] = acc;
-    if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)acc;
-    acc = 0.0;
   }
 }
 
@@ -599,9 +626,9 @@ void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *
 void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
                            int nrow, const int *urow, const int *uptr, const double *uval,
                            double factor, double *rs, float *rs32, int *flag, hipStream_t st,
-                           const PartDesc<float> *cast32) {
+                           const PartDesc<float> *cast32, bool stencil_sums_done) {
   if (l1) {
-    k_l1_cells<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, cast32, rs);
+    if (!stencil_sums_done) k_l1_cells<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, cast32, rs);
     if (nrow > 0) k_l1_urows<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, uval, rs);
     k_l1_finish<<<nblk(n), kBlock, 0, st>>>(n, factor, rs, rs32, flag);
   } else {
@@ -609,10 +636,15 @@ void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, in
   }
 }
 
+bool rap_per_cell(int nparts, int maxcoarse, int64_t cell_min) {
+  return (int64_t)maxcoarse * nparts >= cell_min;
+}
+
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
                 int maxent_c, int64_t cell_min, hipStream_t st) {
-  if ((int64_t)maxcoarse * nparts >= cell_min) {
-    k_rap<<<dim3(nblk(maxcoarse), nparts), kBlock, 0, st>>>(desc, rd);
+  if (rap_per_cell(nparts, maxcoarse, cell_min)) {
+    // 8-aligned grid so that the XCD-aware block order applies
+    k_rap<<<dim3((nblk(maxcoarse) + 7u) & ~7u, nparts), kBlock, 0, st>>>(desc, rd);
   } else {
     // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies
     const unsigned nb = (nblk(maxcoarse) * (unsigned)maxent_c + 7u) & ~7u;

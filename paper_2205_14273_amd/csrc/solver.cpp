@@ -96,43 +96,38 @@ int index_of(const std::vector<std::array<int, 3>> &pat, const std::array<int, 3
   return -1;
 }
 
-// Galerkin table of one part (see k_rap)
+// Entry maps of one part's Galerkin product over the 27 offsets (see k_rap):
+// fine entry and coarse entry of each offset, and the offset of each coarse
+// entry.  Every coarse entry a fine one reaches must be in the coarse pattern.
+int cube_index(const std::array<int, 3> &o) { return (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1); }
+
 void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) {
-  f.rap_start.assign(1, 0);
-  f.rap_code.clear();
+  f.rap_fmap.fill(-1);
+  f.rap_cmap.fill(-1);
+  f.rap_cofs.fill(0);
+  for (size_t e = 0; e < f.pat.size(); ++e) f.rap_fmap[cube_index(f.pat[e])] = (int)e;
+  for (size_t e = 0; e < cpat.size(); ++e) {
+    f.rap_cmap[cube_index(cpat[e])] = (int)e;
+    f.rap_cofs[e] = cube_index(cpat[e]);
+  }
+  f.rap_nent = (int)cpat.size();
   if (f.dstar < 0) {
-    for (size_t e = 0; e < cpat.size(); ++e) {
-      f.rap_code.push_back(index_of(f.pat, cpat[e]));
-      f.rap_start.push_back((int)f.rap_code.size());
-    }
+    for (const auto &t : cpat)
+      if (f.rap_fmap[cube_index(t)] < 0) throw Error(SSAMG_ERR_STATE, "internal: identity transfer changes the pattern");
     return;
   }
   const int ds = f.dstar;
-  std::vector<std::vector<int>> lists(cpat.size());
-  for (int r = -1; r <= 1; ++r)
-    for (size_t si = 0; si < f.pat.size(); ++si) {
-      const auto s = f.pat[si];
+  if (f.nf < 1) throw Error(SSAMG_ERR_STATE, "internal: coarsened part without F cells");
+  for (const auto &s : f.pat)
+    for (int r = -1; r <= 1; ++r) {
       const int q = r + s[ds];
-      auto push = [&](int td, int gsel) {
+      for (int td : {(q & 1) == 0 ? q / 2 : (q - 1) / 2, (q & 1) == 0 ? q / 2 : (q + 1) / 2}) {
         auto t = s;
         t[ds] = td;
-        const int e = index_of(cpat, t);
-        if (e < 0) throw Error(SSAMG_ERR_STATE, "internal: Galerkin target outside coarse pattern");
-        lists[e].push_back((r + 1) | ((int)si << 2) | (gsel << 7));
-      };
-      if ((q & 1) == 0) {
-        push(q / 2, 0);
-      } else {
-        push((q - 1) / 2, 1);
-        push((q + 1) / 2, 2);
+        if (td < -1 || td > 1 || f.rap_cmap[cube_index(t)] < 0)
+          throw Error(SSAMG_ERR_STATE, "internal: Galerkin target outside coarse pattern");
       }
     }
-  for (auto &l : lists) {
-    f.rap_code.insert(f.rap_code.end(), l.begin(), l.end());
-    f.rap_start.push_back((int)f.rap_code.size());
-  }
-  if (f.rap_code.size() > (size_t)kRapMaxTab)
-    throw Error(SSAMG_ERR_STATE, "internal: Galerkin table longer than kRapMaxTab");
 }
 
 // The FP64 product reads mirrored entries when the caller declares A symmetric
@@ -900,10 +895,6 @@ void carve(Solver &s, Carver &cv) {
     V.d_rapdesc = l < L - 1 ? cv.take<RapDesc>(V.parts.size()) : nullptr;
     V.d_tail = (char *)tail_all + (size_t)l * tail_size;
     V.d_ctail = (char *)ctail_all + (size_t)l * tail_size;
-    for (auto &q : V.parts) {
-      q.d_rap_start = l < L - 1 ? cv.take<int>(q.rap_start.size()) : nullptr;
-      q.d_rap_code = l < L - 1 ? cv.take<int>(q.rap_code.size()) : nullptr;
-    }
   }
   cv.off = align_up(cv.off);
   cv.tab_end = cv.off;
@@ -1036,14 +1027,22 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     for (size_t p = 0; p < V.parts.size(); ++p) {
       PartLevel &q = V.parts[p];
       if (l < L - 1) {
-        putv(q.d_rap_start, q.rap_start);
-        putv(q.d_rap_code, q.rap_code);
         RapDesc r{};
         r.out = s.lv[l + 1].parts[p].coef64;
         r.out32 = mixed && l + 1 < L - 1 ? s.lv[l + 1].parts[p].coef32 : nullptr;
-        r.start = q.d_rap_start;
-        r.code = q.d_rap_code;
-        r.nent = (int)q.rap_start.size() - 1;
+        // the one-thread-per-coarse-cell kernel reads every coefficient of the
+        // level: it also forms the L1 row sums and, on the finest level of a
+        // mixed-precision cycle, the FP32 copy
+        if (rap_per_cell((int)V.parts.size(), V.maxcoarse, s.rap_cell_min)) {
+          r.l1 = s.prm.relax == SSAMG_RELAX_L1_JACOBI ? V.d_rs64 + q.off : nullptr;
+          r.fine32 = l == 0 && mixed ? q.coef32 : nullptr;
+        }
+        r.nent = q.rap_nent;
+        for (int o = 0; o < 27; ++o) {
+          r.fmap[o] = q.rap_fmap[o];
+          r.cmap[o] = q.rap_cmap[o];
+          r.cofs[o] = q.rap_cofs[o];
+        }
         hr.push_back(r);
       }
     }
@@ -1103,9 +1102,15 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   // finest-level FP32 copies; coarser ones are written by the kernels below
   // per-cell smoother factors: omega_p / a_ii, or factor / sum_j |a_ij|
   const bool l1 = s.prm.relax == SSAMG_RELAX_L1_JACOBI;
+  // levels whose Galerkin product runs one thread per coarse cell: that kernel
+  // writes their L1 row sums (stencil part) and the finest FP32 copy
+  auto fused = [&](int l) {
+    return l < L - 1 && rap_per_cell((int)s.lv[l].parts.size(), s.lv[l].maxcoarse, s.rap_cell_min);
+  };
   if (mixed && L > 1) {
     Level &V = s.lv[0];
-    if (!l1)   // with L1-Jacobi the factor pass writes them as it reads the coefficients
+    // otherwise the L1 factor pass writes them as it reads the coefficients
+    if (!l1 && !fused(0))
       for (auto &q : V.parts) launch_cast_d2f(q.coef64, q.coef32, (int64_t)q.pat.size() * q.ncell, st);
     launch_cast_d2f(V.d_uval64, V.d_uval32, V.nnz, st);
   }
@@ -1115,7 +1120,7 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     float *rs32 = mixed && l < L - 1 ? V.d_rs32 : nullptr;
     launch_smoother_scale(l1, V.d_desc64, (int)V.parts.size(), V.maxcell, V.N, V.nrow, V.d_urow,
                           V.d_uptr, V.d_uval64, l1_factor, V.d_rs64, rs32, s.flag, st,
-                          l == 0 && mixed && L > 1 ? V.d_desc32 : nullptr);
+                          l == 0 && mixed && L > 1 && !fused(0) ? V.d_desc32 : nullptr, fused(l));
     // skipped parts: factor 0, so neither sweep changes their cells
     for (auto &q : V.parts) {
       if (!q.skip) continue;
@@ -1123,8 +1128,8 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
       if (rs32) SSAMG_HIP(hipMemsetAsync(rs32 + q.off, 0, (size_t)q.ncell * sizeof(float), st));
     }
   };
-  smoother_scale(0);
-  // level by level: weights, structured and unstructured Galerkin products
+  // level by level: weights, structured and unstructured Galerkin products,
+  // then the level's smoother factors
   for (int l = 0; l + 1 < L; ++l) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
@@ -1132,8 +1137,9 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, s.rap_cell_min, st);
     launch_uc_numeric(C.nnz, C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
-    smoother_scale(l + 1);
+    smoother_scale(l);
   }
+  smoother_scale(L - 1);
   // operator packs of the coarse-end kernel: levels l0 .. L-2 (consecutive
   // records; level sizes do not grow, so the packed levels are a suffix)
   {

@@ -68,9 +68,6 @@ constexpr int64_t kSplitCells = 1 << 20;
 constexpr int kDirectMax = 64;
 // largest switch level of the hybrid tail (dense FP64 inverse of at most 2 GiB)
 constexpr int64_t kDenseMax = 16384;
-// rows of one part's Galerkin table, staged in LDS by the kernel (3 fine rows x
-// 27 entries x at most 2 weights = 162)
-constexpr int kRapMaxTab = 256;
 // coarse levels of at least this many cells (over all parts) take the
 // one-thread-per-coarse-cell Galerkin kernel; smaller ones one thread per
 // (coarse cell, entry), whose shorter gather chains win when threads are few
@@ -215,9 +212,10 @@ struct PartLevel {
   double *coef64 = nullptr;
   float *coef32 = nullptr;
   int64_t wofs = 0;                  // offset of wm in the level weight buffer (wp at +nf)
-  // Galerkin table toward the next level (host + device)
-  std::vector<int> rap_start, rap_code;
-  int *d_rap_start = nullptr, *d_rap_code = nullptr;
+  // Galerkin product toward the next level: entry maps over the 27 offsets
+  // (see RapDesc)
+  std::array<int, 27> rap_fmap{}, rap_cmap{}, rap_cofs{};
+  int rap_nent = 0;
 };
 
 // Growable device buffer (kept across setups; reallocated only to grow).
@@ -425,14 +423,17 @@ struct TailPlan {
   int off_tab, off_vec, off_tv, off_acc, off_prod, bytes;
 };
 
-// per-part Galerkin table of one level (device array indexed by part)
+// per-part Galerkin product toward the next level (device array indexed by
+// part).  Offsets are cube indices (dx+1) + 3(dy+1) + 9(dz+1).
 struct RapDesc {
-  double *out;         // coarse coefficients [nent_c][cncell]
+  double *out;         // coarse coefficients [nent][cncell]
   float *out32;        // FP32 copy of them (mixed-precision cycle) or null
-  const int *start;    // [nent_c + 1] into code
-  const int *code;     // (r+1) | s << 2 | gsel << 7; identity parts: fine entry per coarse entry
+  double *l1;          // one-thread-per-coarse-cell kernel: sum_s |a_s(f)| of every fine cell (part slice) or null
+  float *fine32;       // that kernel: FP32 copy of the fine coefficients [nent_f][ncell] or null
   int nent;            // coarse entries
-  int pad;
+  int fmap[27];        // fine entry of each offset, -1: not in the fine stencil
+  int cmap[27];        // coarse entry of each offset, -1: not in the coarse stencil
+  int cofs[27];        // offset of each coarse entry
 };
 
 // finite-volume assembly arguments
@@ -550,16 +551,21 @@ void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *
 void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
                            int maxf, int *flag, hipStream_t st);
 // one thread per coarse cell when the level has at least cell_min coarse cells
-// (over all parts), else one thread per (coarse cell, entry); same sums in the
-// same order either way
+// (over all parts), else one thread per (coarse cell, entry); the same values
+// bit for bit either way
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
                 int maxent_c, int64_t cell_min, hipStream_t st);
+// whether launch_rap takes the one-thread-per-coarse-cell kernel (which also
+// writes the fine level's L1 row sums and FP32 copy when asked to)
+bool rap_per_cell(int nparts, int maxcoarse, int64_t cell_min);
 // weighted L1-Jacobi: cast32 (finest level, mixed precision) also receives
-// the FP32 copy of the coefficients the pass reads
+// the FP32 copy of the coefficients the pass reads; stencil_sums_done: rs
+// already holds the stencil part of the row sums (written by the Galerkin
+// kernel)
 void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, int maxcell, int64_t n,
                            int nrow, const int *urow, const int *uptr, const double *uval,
                            double factor, double *rs, float *rs32, int *flag, hipStream_t st,
-                           const PartDesc<float> *cast32 = nullptr);
+                           const PartDesc<float> *cast32 = nullptr, bool stencil_sums_done = false);
 template <typename T, typename TB>
 void launch_smooth_resid(int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell, int lg,
                          const TB *b, T *x, T *r, hipStream_t st, LaunchEvents ev = {});
