@@ -52,6 +52,22 @@ Readings where the paper is silent or garbled (all are listed in the design note
            (d*_l = d*_{l-n_d} >= 0); the coarsest level and parts that no
            longer coarsen always relax.  Not relaxing means a zero smoother
            factor: no pre-sweep contribution and no post-sweep change.
+  R-ng     the non-Galerkin coarse operator that Section 5 plans for isotropic
+           problems (option coarse_op="nongalerkin") is not specified there.
+           Reading: it applies to parts whose stencil is a star (every offset
+           has at most one nonzero component, e.g. 7-point), keeps the star
+           pattern on the coarse level, and starts from the Galerkin product.
+           Each same-part entry (I, J) whose offset (t, Q) has both a nonzero
+           component across d* (t) and along d* (Q) joins the corners of the
+           rectangle I, K1 = I + t, J, K2 = I + Q; it is removed and half of
+           its value is added to each of the four star entries (I, K1),
+           (I, K2), (K1, J), (K2, J) along the rectangle's sides, and the
+           diagonals of rows K1 and K2 lose half of it, so every row sum of
+           the Galerkin operator is kept.  Seen as a graph Laplacian, each
+           diagonal edge is replaced by the four sides of its rectangle at
+           half its weight; a symmetric operator stays symmetric.  For the
+           constant-coefficient Laplacian the result is the finite-volume
+           stencil of the coarsened cells.
 """
 from __future__ import annotations
 
@@ -335,6 +351,50 @@ def galerkin(A, P):
     return Ac
 
 
+def is_star(pattern):
+    """Every offset has at most one nonzero component (e.g. the 7-point stencil)."""
+    return all(int(np.count_nonzero(np.asarray(t))) <= 1 for t in pattern)
+
+
+def non_galerkin(Ac, cdims, coffs, p, dstar):
+    """Reading R-ng for part p of a coarse operator Ac (Section 5, future work):
+    every same-part entry v at (I, J) of offset (t, Q), t across d* and Q along
+    d* both nonzero, is removed and v/2 is added at (I, I+t), (I, I+Q),
+    (I+t, J) and (I+Q, J); the diagonals of I+t and I+Q lose v/2 each, which
+    keeps every row sum."""
+    A = Ac.tocoo()
+    o0, o1 = int(coffs[p]), int(coffs[p + 1])
+    nx, ny, nz = cdims[p]
+    stride = np.array([1, nx, nx * ny])
+    inp = (A.row >= o0) & (A.row < o1) & (A.col >= o0) & (A.col < o1)
+
+    def coord(g):
+        loc = g - o0
+        return np.stack([loc % nx, (loc // nx) % ny, loc // (nx * ny)], axis=1)
+
+    sel = np.nonzero(inp)[0]
+    off = coord(A.col[sel]) - coord(A.row[sel])
+    q = off[:, dstar]
+    t = off.copy()
+    t[:, dstar] = 0
+    move = sel[(q != 0) & np.any(t != 0, axis=1)]
+    qm = q[(q != 0) & np.any(t != 0, axis=1)]
+    keep = np.ones(A.nnz, dtype=bool)
+    keep[move] = False
+    I, J, v = A.row[move], A.col[move], A.data[move]
+    K1 = J - qm * stride[dstar]      # I + t
+    K2 = I + qm * stride[dstar]      # I + Q
+    for K in (K1, K2):
+        assert np.all((K >= o0) & (K < o1))
+    h = 0.5 * v
+    rows = np.concatenate([A.row[keep], I, I, K1, K2, K1, K2])
+    cols = np.concatenate([A.col[keep], K1, K2, J, J, K1, K2])
+    vals = np.concatenate([A.data[keep], h, h, h, h, -h, -h])
+    out = sp.coo_matrix((vals, (rows, cols)), shape=Ac.shape).tocsr()
+    out.sort_indices()
+    return out
+
+
 def _pattern_of(P):
     Q = P.copy()
     Q.data = np.ones_like(Q.data)
@@ -359,8 +419,12 @@ class Hierarchy:
 
 
 def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=64,
-          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False, pb="one", hybrid_level=0):
+          min_coarse_size=0, coarse="sweep", relax="jacobi", skip=False, pb="one", hybrid_level=0,
+          coarse_op="galerkin"):
     """Full SSAMG setup.  ``pattern0[p]`` is the input stencil of part p.
+
+    ``coarse_op="nongalerkin"``: parts with star stencils get the non-Galerkin
+    coarse operator of reading R-ng (the rest stay Galerkin).
 
     ``hybrid_level`` = k > 0: the hybrid scheme of Section 3.5 - SSAMG builds
     levels 0 .. k-1 and the problem left at level k is solved exactly (here by
@@ -404,6 +468,14 @@ def setup(A0, dims, faces, pattern0, ndim, ustruct0=None, omega=0.0, max_levels=
         lev.P = interpolation_matrix(lev, cdims, coffs)
         Ac = galerkin(lev.A, lev.P)
         pats = [coarse_pattern(lev.pattern[p], lev.dstar[p]) for p in range(len(dims))]
+        if coarse_op == "nongalerkin":
+            for p in range(len(dims)):
+                if lev.dstar[p] >= 0 and is_star(lev.pattern[p]):
+                    Ac = non_galerkin(Ac, cdims, coffs, p, lev.dstar[p])
+                    pats[p] = np.asarray([t for t in pats[p] if np.count_nonzero(t) <= 1],
+                                         dtype=np.int32)
+        elif coarse_op != "galerkin":
+            raise ValueError(f"unknown coarse_op {coarse_op!r}")
         Pb = _pattern_of(lev.P)
         ust = (Pb.T @ lev.ustruct @ Pb).tocsr()
         ust.data[:] = 1.0

@@ -965,3 +965,89 @@ def test_tc4_samr_invariants():
     ref = ssamg.solve(h, case.b, tol=1e-10)
     xd = np.linalg.solve(D, case.b)
     assert ref.converged and np.linalg.norm(ref.x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+# ---------------------------------------------------------------------------
+# non-Galerkin coarse operator for star stencils (Section 5, reading R-ng)
+
+
+def _interior_stencil(lev, p=0):
+    vals = ssamg.stencil_values_fast(lev, p)
+    nx, ny, nz = lev.dims[p]
+    c = nx // 2 + nx * (ny // 2 + ny * (nz // 2))
+    return {tuple(int(a) for a in t): vals[e, c] for e, t in enumerate(lev.pattern[p])}
+
+
+def test_nongalerkin_constant_laplacian_is_the_coarse_cell_discretisation():
+    """On the constant 7-point Laplacian (conductance 1 per face) the
+    non-Galerkin operator of a level is the finite-volume stencil of the
+    coarsened cells: a face of area A between centers a distance h apart
+    conducts A/h.  Level 1 (cells 2x1x1): x 1/2, y and z 2, center 9; level 2
+    (2x2x1): x and y 1, z 4, center 12.  A missing half, a rerouting to one
+    side of the rectangle only or a wrong diagonal all change these numbers
+    (the Galerkin level 1 has +1/2 along x and -1/4 on the diagonals)."""
+    _, h = fv_hierarchy(W.c1(16), coarse_op="nongalerkin")
+    assert [lev.dstar[0] for lev in h.levels[:2]] == [0, 1]
+    want1 = {(0, 0, 0): 9.0, (-1, 0, 0): -0.5, (1, 0, 0): -0.5, (0, -1, 0): -2.0, (0, 1, 0): -2.0,
+             (0, 0, -1): -2.0, (0, 0, 1): -2.0}
+    want2 = {(0, 0, 0): 12.0, (-1, 0, 0): -1.0, (1, 0, 0): -1.0, (0, -1, 0): -1.0, (0, 1, 0): -1.0,
+             (0, 0, -1): -4.0, (0, 0, 1): -4.0}
+    for lev, want in ((h.levels[1], want1), (h.levels[2], want2)):
+        got = _interior_stencil(lev)
+        assert set(got) == set(want)
+        for k, v in want.items():
+            assert abs(got[k] - v) < 1e-13, (k, got[k], v)
+    _, hg = fv_hierarchy(W.c1(16))
+    g1 = _interior_stencil(hg.levels[1])
+    assert abs(g1[(1, 0, 0)] - 0.5) < 1e-13 and abs(g1[(1, 1, 0)] + 0.25) < 1e-13
+
+
+def _ng_cases():
+    g = W.Geometry(3, [(8, 7, 6), (6, 7, 6), (5, 4, 6)], [(0, 0, 0), (8, 0, 0), (8, 7, 0)])
+    raw = W.random_link_case(11, g, 7)
+    A, _ = assemble.assemble_raw(g.dims, raw.stencils, raw.coeffs, raw.urow, raw.ucol, raw.uval)
+    hraw = ssamg.setup(A, g.dims, raw.faces, raw.stencils, 3, coarse_op="nongalerkin",
+                       ustruct0=assemble.u_structure(raw.urow, raw.ucol, A.shape[0]))
+    return [("raw", hraw), ("c5", fv_hierarchy(W.c5(8), coarse_op="nongalerkin")[1]),
+            ("c2", fv_hierarchy(W.c2(6), coarse_op="nongalerkin")[1])]
+
+
+@pytest.mark.parametrize("name", ["raw", "c5", "c2"])
+def test_nongalerkin_invariants(name):
+    """Every level of a non-Galerkin hierarchy on variable coefficients: star
+    patterns only; symmetric (a rerouting to the wrong neighbour breaks this
+    once coefficients vary); every row sum equal to that of the Galerkin
+    product of the level above (pins the diagonal); the cross-part entries
+    and the entries of parts that did not coarsen untouched; positive
+    definite; and PCG converges."""
+    h = dict(_ng_cases())[name]
+    for l in range(1, h.nlevels):
+        lev, up = h.levels[l], h.levels[l - 1]
+        for p in range(len(lev.dims)):
+            assert all(np.count_nonzero(t) <= 1 for t in lev.pattern[p])
+        A = lev.A
+        assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+        G = ssamg.galerkin(up.A, up.P)
+        assert np.allclose(np.asarray(A.sum(axis=1)).ravel(), np.asarray(G.sum(axis=1)).ravel(),
+                           rtol=0, atol=1e-12 * abs(A).max())
+        part = assemble.cell_coords(lev.dims, lev.offsets)[0]
+        D = (A - G).tocoo()
+        D.data[abs(D.data) <= 1e-13 * abs(A).max()] = 0
+        D.eliminate_zeros()
+        assert np.all(part[D.row] == part[D.col])
+        moved = {p for p in range(len(lev.dims)) if up.dstar[p] >= 0}
+        assert set(np.unique(part[D.row]).tolist()) <= moved
+        if A.shape[0] <= 1500:
+            assert np.linalg.eigvalsh(A.toarray()).min() > 0
+    r = np.random.default_rng(4).uniform(-1, 1, h.levels[0].n)
+    res = ssamg.solve(h, r)
+    assert res.converged and res.iters <= 30
+
+
+def test_nongalerkin_leaves_other_stencils_galerkin():
+    """A 27-point part is not a star: the option changes nothing there."""
+    case = W.c3(4)
+    _, h = fv_hierarchy(case, coarse_op="nongalerkin")
+    _, hg = fv_hierarchy(case)
+    for a, b in zip(h.levels, hg.levels):
+        assert (a.A != b.A).nnz == 0
