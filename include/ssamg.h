@@ -58,6 +58,7 @@ enum { SSAMG_RELAX_JACOBI = 0, SSAMG_RELAX_L1_JACOBI = 1 };
 enum { SSAMG_COARSE_SWEEP = 0, SSAMG_COARSE_DIRECT = 1 };
 enum { SSAMG_FP64 = 0, SSAMG_FP32 = 1 };
 enum { SSAMG_PB_ONE = 0, SSAMG_PB_LUMP = 1 };
+enum { SSAMG_COARSE_OP_GALERKIN = 0, SSAMG_COARSE_OP_NONGALERKIN = 1 };
 enum { SSAMG_LAYOUT_CELL_MAJOR = 0, SSAMG_LAYOUT_RHS_MAJOR = 1 };
 
 typedef struct ssamg_problem_s *ssamg_problem;
@@ -235,6 +236,19 @@ typedef struct {
                                 have at most 16384 unknowns (SSAMG_ERR_UNSUPPORTED from
                                 setup_symbolic otherwise); SSAMG_ERR_NUMERIC when its
                                 operator is not positive definite.  Overrides coarse */
+  int coarse_op;             /* coarse stencils (Section 3.3; Section 5 plans the
+                                second for isotropic problems):
+                                SSAMG_COARSE_OP_GALERKIN (default): P^T S P;
+                                SSAMG_COARSE_OP_NONGALERKIN: on parts whose stencil is a
+                                star (every offset has at most one nonzero component,
+                                e.g. 7-point) the coarse stencil keeps that pattern:
+                                each Galerkin entry with components both across and
+                                along d* is replaced by the four star entries along
+                                the sides of the rectangle it spans, at half its
+                                value, the diagonals keeping every row sum.  For the
+                                constant-coefficient Laplacian this is the
+                                finite-volume stencil of the coarsened cells.  Other
+                                parts and the couplings P^T U P stay Galerkin */
 } ssamg_params;
 
 typedef struct {

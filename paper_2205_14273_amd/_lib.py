@@ -53,7 +53,7 @@ class ssamg_params(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_nrhs", C.c_int),
                 ("use_graph", C.c_int), ("skip", C.c_int), ("autotune", C.c_int),
                 ("symmetric", C.c_int), ("pb_interp", C.c_int),
-                ("hybrid_level", C.c_int)]
+                ("hybrid_level", C.c_int), ("coarse_op", C.c_int)]
 
 
 class ssamg_info(C.Structure):

@@ -118,6 +118,7 @@ ssamg_status ssamg_params_default(ssamg_params *p) {
   p->symmetric = 1;
   p->pb_interp = SSAMG_PB_ONE;
   p->hybrid_level = 0;
+  p->coarse_op = SSAMG_COARSE_OP_GALERKIN;
   API_END
 }
 
@@ -140,6 +141,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (p.autotune != 0 && p.autotune != 1) throw Error(SSAMG_ERR_ARG, "autotune must be 0 or 1");
   if (p.symmetric != 0 && p.symmetric != 1) throw Error(SSAMG_ERR_ARG, "symmetric must be 0 or 1");
   if (p.hybrid_level < 0) throw Error(SSAMG_ERR_ARG, "hybrid_level must be >= 0");
+  if (p.coarse_op != SSAMG_COARSE_OP_GALERKIN && p.coarse_op != SSAMG_COARSE_OP_NONGALERKIN)
+    throw Error(SSAMG_ERR_ARG, "coarse_op must be SSAMG_COARSE_OP_GALERKIN or SSAMG_COARSE_OP_NONGALERKIN");
   if (p.pb_interp != SSAMG_PB_ONE && p.pb_interp != SSAMG_PB_LUMP)
     throw Error(SSAMG_ERR_ARG, "pb_interp must be SSAMG_PB_ONE or SSAMG_PB_LUMP");
   if (p.cycle_precision != SSAMG_FP64 && p.cycle_precision != SSAMG_FP32)

@@ -385,6 +385,96 @@ __device__ __forceinline__ double rap_entry_value(const PartDesc<double> &d, con
                      wp[gp], false, 0.0, 0.0);
 }
 
+// Non-Galerkin coarse stencil of a star part (SSAMG_COARSE_OP_NONGALERKIN;
+// Section 5 plans it for isotropic problems).  From the Galerkin entries G,
+// each entry of offset (t, Q) with t != 0 across d* and Q != 0 along d* is
+// replaced by its rectangle's four sides (I, I+t), (I, I+Q), (I+t, J),
+// (I+Q, J) at half its value, and the diagonals of I+t and I+Q lose half of
+// it (row sums kept).  Gathered per coarse entry of cell I, over the four
+// unit offsets t across d* and Q = -1, 1:
+//   C_(t,0)(I) = G_(t,0)(I) + 1/2 sum_Q [G_(t,Q)(I) + G_(t,Q)(I - Q)]
+//   C_(0,Q)(I) = G_(0,Q)(I) + 1/2 sum_t [G_(t,Q)(I) + G_(t,Q)(I - t)]
+//   C_0(I)     = G_0(I)     - 1/2 sum_t sum_Q [G_(t,Q)(I - t) + G_(t,Q)(I - Q)]
+// with the terms of cells outside the coarse box left out.
+template <int DS>
+__device__ __forceinline__ double rap_ng_value(const PartDesc<double> &d, const RapDesc &t, long long cidx,
+                                               int o) {
+  constexpr int AX = (DS + 1) % 3, BX = (DS + 2) % 3;
+  int ci[3];
+  cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
+  // Galerkin entry of offset (u across, q along d*) at coarse cell ci - shift;
+  // 0 if that cell is outside the coarse box
+  auto G = [&](int ua, int ub, int q, int sa, int sb, int sd) -> double {
+    int c[3] = {ci[0], ci[1], ci[2]};
+    c[AX] -= sa;
+    c[BX] -= sb;
+    c[DS] -= sd;
+    if ((unsigned)c[0] >= (unsigned)d.cn[0] || (unsigned)c[1] >= (unsigned)d.cn[1] ||
+        (unsigned)c[2] >= (unsigned)d.cn[2])
+      return 0.0;
+    const long long cc = c[0] + (long long)d.cn[0] * (c[1] + (long long)d.cn[1] * c[2]);
+    return rap_entry_value<DS>(d, t, cc,
+                               (ua + 1) * cube_stride(AX) + (ub + 1) * cube_stride(BX) + (q + 1) * cube_stride(DS));
+  };
+  const int ta = cube_comp(o, AX), tb = cube_comp(o, BX), Q = cube_comp(o, DS);
+  const int tu[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+  double sum = 0.0;
+  if (ta == 0 && tb == 0 && Q == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = -1; q <= 1; q += 2) {
+        sum += G(tu[k][0], tu[k][1], q, tu[k][0], tu[k][1], 0);
+        sum += G(tu[k][0], tu[k][1], q, 0, 0, q);
+      }
+    return G(0, 0, 0, 0, 0, 0) - 0.5 * sum;
+  }
+  if (ta == 0 && tb == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sum += G(tu[k][0], tu[k][1], Q, 0, 0, 0);
+      sum += G(tu[k][0], tu[k][1], Q, tu[k][0], tu[k][1], 0);
+    }
+    return G(0, 0, Q, 0, 0, 0) + 0.5 * sum;
+  }
+#pragma unroll
+  for (int q = -1; q <= 1; q += 2) {
+    sum += G(ta, tb, q, 0, 0, 0);
+    sum += G(ta, tb, q, 0, 0, q);
+  }
+  return G(ta, tb, 0, 0, 0, 0) + 0.5 * sum;
+}
+
+// one coarse cell of a non-Galerkin part, every entry; the L1 row sums and
+// FP32 copy of rows 2I and 2I+1 in entry order
+template <int DS>
+__device__ __forceinline__ void rap_cell_ng(const PartDesc<double> &d, const RapDesc &t, long long cidx) {
+  for (int e = 0; e < t.nent; ++e) {
+    const double v = rap_ng_value<DS>(d, t, cidx, t.cofs[e]);
+    dev::Gw(t.out)[(long long)e * d.cncell + cidx] = v;
+    if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)v;
+  }
+  if (!t.l1 && !t.fine32) return;
+  RapGeo g;
+  rap_geo<DS>(d, cidx, g);
+  const bool okp = g.row_ok[2];
+  double l1c = 0.0, l1f = 0.0;
+  for (int e = 0; e < d.nent; ++e) {
+    const double a0 = dev::G(d.coef)[(long long)e * d.ncell + g.fr[1]];
+    const double a1 = dev::G(d.coef)[(long long)e * d.ncell + g.fr[2]];
+    l1c += fabs(a0);
+    l1f += fabs(a1);
+    if (t.fine32) {
+      dev::Gw(t.fine32)[(long long)e * d.ncell + g.fr[1]] = (float)a0;
+      if (okp) dev::Gw(t.fine32)[(long long)e * d.ncell + g.fr[2]] = (float)a1;
+    }
+  }
+  if (t.l1) {
+    dev::Gw(t.l1)[g.fr[1]] = l1c;
+    if (okp) dev::Gw(t.l1)[g.fr[2]] = l1f;
+  }
+}
+
 // Small coarse levels: one thread per (coarse cell, coarse entry); a block
 // covers one entry of a tile of kBlock coarse cells, and the blocks of one
 // tile are consecutive in the XCD-aware order, so they read the tile's fine
@@ -399,10 +489,13 @@ __global__ __launch_bounds__(kBlock) void k_rap_entry(const PartDesc<double> *__
   if (e >= t.nent || cidx >= d.cncell) return;
   const int o = t.cofs[e];
   double v;
-  switch (d.dstar) {
+  switch (d.dstar + (t.ng ? 3 : 0)) {
     case 0: v = rap_entry_value<0>(d, t, cidx, o); break;
     case 1: v = rap_entry_value<1>(d, t, cidx, o); break;
     case 2: v = rap_entry_value<2>(d, t, cidx, o); break;
+    case 3: v = rap_ng_value<0>(d, t, cidx, o); break;
+    case 4: v = rap_ng_value<1>(d, t, cidx, o); break;
+    case 5: v = rap_ng_value<2>(d, t, cidx, o); break;
     default:   // identity transfer: the same operator, entries in the coarse order
       v = dev::G(d.coef)[(long long)t.fmap[o] * d.ncell + cidx];
   }
@@ -417,6 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
   const RapDesc &t = rd[blockIdx.y];
   const long long cidx = (long long)dev::chunk_index() * kBlock + threadIdx.x;
   if (cidx >= d.cncell) return;
+  if (t.ng) return;                                   // k_rap_ng's parts
   switch (d.dstar) {
     case 0: rap_cell<0>(d, t, cidx); break;
     case 1: rap_cell<1>(d, t, cidx); break;
@@ -433,6 +527,21 @@ __global__ __launch_bounds__(kBlock) void k_rap(const PartDesc<double> *__restri
       }
       if (t.l1) dev::Gw(t.l1)[cidx] = l1;
     }
+  }
+}
+
+// The non-Galerkin parts of a large level (a kernel of its own: its register
+// demand would otherwise lower the occupancy of k_rap)
+__global__ __launch_bounds__(kBlock) void k_rap_ng(const PartDesc<double> *__restrict__ desc,
+                                                   const RapDesc *__restrict__ rd) {
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const RapDesc &t = rd[blockIdx.y];
+  const long long cidx = (long long)dev::chunk_index() * kBlock + threadIdx.x;
+  if (!t.ng || cidx >= d.cncell) return;
+  switch (d.dstar) {
+    case 0: rap_cell_ng<0>(d, t, cidx); break;
+    case 1: rap_cell_ng<1>(d, t, cidx); break;
+    default: rap_cell_ng<2>(d, t, cidx); break;
   }
 }
 
@@ -641,10 +750,12 @@ bool rap_per_cell(int nparts, int maxcoarse, int64_t cell_min) {
 }
 
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
-                int maxent_c, int64_t cell_min, hipStream_t st) {
+                int maxent_c, int64_t cell_min, bool any_ng, hipStream_t st) {
   if (rap_per_cell(nparts, maxcoarse, cell_min)) {
     // 8-aligned grid so that the XCD-aware block order applies
-    k_rap<<<dim3((nblk(maxcoarse) + 7u) & ~7u, nparts), kBlock, 0, st>>>(desc, rd);
+    const dim3 grid((nblk(maxcoarse) + 7u) & ~7u, nparts);
+    k_rap<<<grid, kBlock, 0, st>>>(desc, rd);
+    if (any_ng) k_rap_ng<<<grid, kBlock, 0, st>>>(desc, rd);
   } else {
     // tiles x entries, rounded up to a multiple of 8 so that the XCD-aware order applies
     const unsigned nb = (nblk(maxcoarse) * (unsigned)maxent_c + 7u) & ~7u;

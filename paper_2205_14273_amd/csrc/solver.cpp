@@ -96,12 +96,21 @@ int index_of(const std::vector<std::array<int, 3>> &pat, const std::array<int, 3
   return -1;
 }
 
+// whether a part's coarse stencil is the non-Galerkin one (SSAMG_COARSE_OP_NONGALERKIN
+// and a coarsened star stencil)
+bool nongalerkin(const Solver &s, const PartLevel &q) {
+  if (s.prm.coarse_op != SSAMG_COARSE_OP_NONGALERKIN || q.dstar < 0) return false;
+  for (const auto &t : q.pat)
+    if ((t[0] != 0) + (t[1] != 0) + (t[2] != 0) > 1) return false;
+  return true;
+}
+
 // Entry maps of one part's Galerkin product over the 27 offsets (see k_rap):
 // fine entry and coarse entry of each offset, and the offset of each coarse
 // entry.  Every coarse entry a fine one reaches must be in the coarse pattern.
 int cube_index(const std::array<int, 3> &o) { return (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1); }
 
-void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) {
+void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat, bool ng) {
   f.rap_fmap.fill(-1);
   f.rap_cmap.fill(-1);
   f.rap_cofs.fill(0);
@@ -111,6 +120,7 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
     f.rap_cofs[e] = cube_index(cpat[e]);
   }
   f.rap_nent = (int)cpat.size();
+  f.rap_ng = ng;
   if (f.dstar < 0) {
     for (const auto &t : cpat)
       if (f.rap_fmap[cube_index(t)] < 0) throw Error(SSAMG_ERR_STATE, "internal: identity transfer changes the pattern");
@@ -124,7 +134,8 @@ void build_rap_table(PartLevel &f, const std::vector<std::array<int, 3>> &cpat) 
       for (int td : {(q & 1) == 0 ? q / 2 : (q - 1) / 2, (q & 1) == 0 ? q / 2 : (q + 1) / 2}) {
         auto t = s;
         t[ds] = td;
-        if (td < -1 || td > 1 || f.rap_cmap[cube_index(t)] < 0)
+        const bool rerouted = ng && t[ds] != 0 && (t[0] != 0) + (t[1] != 0) + (t[2] != 0) > 1;
+        if (td < -1 || td > 1 || (f.rap_cmap[cube_index(t)] < 0 && !rerouted))
           throw Error(SSAMG_ERR_STATE, "internal: Galerkin target outside coarse pattern");
       }
     }
@@ -500,7 +511,9 @@ void symbolic_couplings(Solver &s, int lgmax) {
   int next_tab = 0;
   auto tables = [&](int nlev) {
     for (; nlev > 0 && next_tab < L - 1; --nlev, ++next_tab)
-      for (int p = 0; p < np; ++p) build_rap_table(s.lv[next_tab].parts[p], s.lv[next_tab + 1].parts[p].pat);
+      for (int p = 0; p < np; ++p)
+        build_rap_table(s.lv[next_tab].parts[p], s.lv[next_tab + 1].parts[p].pat,
+                        nongalerkin(s, s.lv[next_tab].parts[p]));
   };
   while ((int)s.store.size() < L) s.store.emplace_back(new LevelStore());
   // one upload: SymPart tables of all levels and the block offsets of ublk
@@ -798,6 +811,13 @@ void setup_symbolic(Solver &s) {
         c.ncell = q.cncell;
         c.faces = q.faces;
         c.pat = coarse_pattern(q.pat, ds);
+        // non-Galerkin option: a star stencil keeps its star pattern
+        if (nongalerkin(s, q)) {
+          std::vector<std::array<int, 3>> star;
+          for (const auto &t : c.pat)
+            if ((t[0] != 0) + (t[1] != 0) + (t[2] != 0) <= 1) star.push_back(t);
+          c.pat = std::move(star);
+        }
         c.center = index_of(c.pat, {0, 0, 0});
         C.parts.push_back(std::move(c));   // Galerkin table: built in symbolic_couplings
       }
@@ -1038,6 +1058,7 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
           r.fine32 = l == 0 && mixed ? q.coef32 : nullptr;
         }
         r.nent = q.rap_nent;
+        r.ng = q.rap_ng ? 1 : 0;
         for (int o = 0; o < 27; ++o) {
           r.fmap[o] = q.rap_fmap[o];
           r.cmap[o] = q.rap_cmap[o];
@@ -1134,7 +1155,9 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
     launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
-    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, s.rap_cell_min, st);
+    bool any_ng = false;
+    for (const auto &q : V.parts) any_ng = any_ng || q.rap_ng;
+    launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, s.rap_cell_min, any_ng, st);
     launch_uc_numeric(C.nnz, C.d_uc_start, C.d_uc_k, C.d_uc_a, C.d_uc_b, V.d_uval64,
                       V.d_w64, C.d_uval64, mixed && l + 1 < L - 1 ? C.d_uval32 : nullptr, st);
     smoother_scale(l);

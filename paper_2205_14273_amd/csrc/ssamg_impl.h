@@ -216,6 +216,7 @@ struct PartLevel {
   // (see RapDesc)
   std::array<int, 27> rap_fmap{}, rap_cmap{}, rap_cofs{};
   int rap_nent = 0;
+  bool rap_ng = false;               // non-Galerkin coarse stencil (SSAMG_COARSE_OP_NONGALERKIN)
 };
 
 // Growable device buffer (kept across setups; reallocated only to grow).
@@ -431,6 +432,7 @@ struct RapDesc {
   double *l1;          // one-thread-per-coarse-cell kernel: sum_s |a_s(f)| of every fine cell (part slice) or null
   float *fine32;       // that kernel: FP32 copy of the fine coefficients [nent_f][ncell] or null
   int nent;            // coarse entries
+  int ng;              // 1: non-Galerkin coarse stencil of a star part (see rap_ng_value)
   int fmap[27];        // fine entry of each offset, -1: not in the fine stencil
   int cmap[27];        // coarse entry of each offset, -1: not in the coarse stencil
   int cofs[27];        // offset of each coarse entry
@@ -554,7 +556,7 @@ void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *
 // (over all parts), else one thread per (coarse cell, entry); the same values
 // bit for bit either way
 void launch_rap(const PartDesc<double> *desc, const RapDesc *rd, int nparts, int maxcoarse,
-                int maxent_c, int64_t cell_min, hipStream_t st);
+                int maxent_c, int64_t cell_min, bool any_ng, hipStream_t st);
 // whether launch_rap takes the one-thread-per-coarse-cell kernel (which also
 // writes the fine level's L1 row sums and FP32 copy when asked to)
 bool rap_per_cell(int nparts, int maxcoarse, int64_t cell_min);

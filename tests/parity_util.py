@@ -14,7 +14,8 @@ def oracle_fv(case, **kw):
                    max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
                    relax=kw.get("relax", case.relax), coarse=kw.get("coarse", "sweep"),
                    skip=kw.get("skip", False), pb=kw.get("pb", "one"),
-                   hybrid_level=kw.get("hybrid_level", 0))
+                   hybrid_level=kw.get("hybrid_level", 0),
+                   coarse_op=kw.get("coarse_op", "galerkin"))
 
 
 def oracle_raw(case, **kw):
@@ -23,7 +24,7 @@ def oracle_raw(case, **kw):
     return O.setup(A, g.dims, case.faces, case.stencils, g.ndim, omega=kw.get("omega", 0.0),
                    ustruct0=assemble.u_structure(case.urow, case.ucol, A.shape[0]),
                    max_levels=kw.get("max_levels", 64), min_coarse_size=kw.get("min_coarse_size", 0),
-                   pb=kw.get("pb", "one"))
+                   pb=kw.get("pb", "one"), coarse_op=kw.get("coarse_op", "galerkin"))
 
 
 def gpu_fv(case, **params):
