@@ -32,6 +32,8 @@ FP64 = 0
 FP32 = 1
 PB_ONE = 0
 PB_LUMP = 1
+COARSE_OP_GALERKIN = 0
+COARSE_OP_NONGALERKIN = 1
 LAYOUT_CELL_MAJOR = 0
 LAYOUT_RHS_MAJOR = 1
 NOALLOC_SCRATCH_BYTES = 64 << 20

@@ -396,63 +396,120 @@ __device__ __forceinline__ double rap_entry_value(const PartDesc<double> &d, con
 //   C_(0,Q)(I) = G_(0,Q)(I) + 1/2 sum_t [G_(t,Q)(I) + G_(t,Q)(I - t)]
 //   C_0(I)     = G_0(I)     - 1/2 sum_t sum_Q [G_(t,Q)(I - t) + G_(t,Q)(I - Q)]
 // with the terms of cells outside the coarse box left out.
+// Galerkin entry of offset (ua, ub across d*, q along d*) at coarse cell
+// ci - (sa, sb, sd); 0 if that cell is outside the coarse box
+template <int DS>
+__device__ __forceinline__ double ng_g(const PartDesc<double> &d, const RapDesc &t, const int (&ci)[3], int ua,
+                                       int ub, int q, int sa, int sb, int sd) {
+  constexpr int AX = (DS + 1) % 3, BX = (DS + 2) % 3;
+  int c[3] = {ci[0], ci[1], ci[2]};
+  c[AX] -= sa;
+  c[BX] -= sb;
+  c[DS] -= sd;
+  if ((unsigned)c[0] >= (unsigned)d.cn[0] || (unsigned)c[1] >= (unsigned)d.cn[1] ||
+      (unsigned)c[2] >= (unsigned)d.cn[2])
+    return 0.0;
+  const long long cc = c[0] + (long long)d.cn[0] * (c[1] + (long long)d.cn[1] * c[2]);
+  return rap_entry_value<DS>(d, t, cc,
+                             (ua + 1) * cube_stride(AX) + (ub + 1) * cube_stride(BX) + (q + 1) * cube_stride(DS));
+}
+
+// the four unit offsets across d* (components along AX, BX), in summation order
+__constant__ const int kNgT[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+
 template <int DS>
 __device__ __forceinline__ double rap_ng_value(const PartDesc<double> &d, const RapDesc &t, long long cidx,
                                                int o) {
   constexpr int AX = (DS + 1) % 3, BX = (DS + 2) % 3;
   int ci[3];
   cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
-  // Galerkin entry of offset (u across, q along d*) at coarse cell ci - shift;
-  // 0 if that cell is outside the coarse box
-  auto G = [&](int ua, int ub, int q, int sa, int sb, int sd) -> double {
-    int c[3] = {ci[0], ci[1], ci[2]};
-    c[AX] -= sa;
-    c[BX] -= sb;
-    c[DS] -= sd;
-    if ((unsigned)c[0] >= (unsigned)d.cn[0] || (unsigned)c[1] >= (unsigned)d.cn[1] ||
-        (unsigned)c[2] >= (unsigned)d.cn[2])
-      return 0.0;
-    const long long cc = c[0] + (long long)d.cn[0] * (c[1] + (long long)d.cn[1] * c[2]);
-    return rap_entry_value<DS>(d, t, cc,
-                               (ua + 1) * cube_stride(AX) + (ub + 1) * cube_stride(BX) + (q + 1) * cube_stride(DS));
-  };
   const int ta = cube_comp(o, AX), tb = cube_comp(o, BX), Q = cube_comp(o, DS);
-  const int tu[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
   double sum = 0.0;
   if (ta == 0 && tb == 0 && Q == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int q = -1; q <= 1; q += 2) {
-        sum += G(tu[k][0], tu[k][1], q, tu[k][0], tu[k][1], 0);
-        sum += G(tu[k][0], tu[k][1], q, 0, 0, q);
+        sum += ng_g<DS>(d, t, ci, kNgT[k][0], kNgT[k][1], q, kNgT[k][0], kNgT[k][1], 0);
+        sum += ng_g<DS>(d, t, ci, kNgT[k][0], kNgT[k][1], q, 0, 0, q);
       }
-    return G(0, 0, 0, 0, 0, 0) - 0.5 * sum;
+    return ng_g<DS>(d, t, ci, 0, 0, 0, 0, 0, 0) - 0.5 * sum;
   }
   if (ta == 0 && tb == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      sum += G(tu[k][0], tu[k][1], Q, 0, 0, 0);
-      sum += G(tu[k][0], tu[k][1], Q, tu[k][0], tu[k][1], 0);
+      sum += ng_g<DS>(d, t, ci, kNgT[k][0], kNgT[k][1], Q, 0, 0, 0);
+      sum += ng_g<DS>(d, t, ci, kNgT[k][0], kNgT[k][1], Q, kNgT[k][0], kNgT[k][1], 0);
     }
-    return G(0, 0, Q, 0, 0, 0) + 0.5 * sum;
+    return ng_g<DS>(d, t, ci, 0, 0, Q, 0, 0, 0) + 0.5 * sum;
   }
 #pragma unroll
   for (int q = -1; q <= 1; q += 2) {
-    sum += G(ta, tb, q, 0, 0, 0);
-    sum += G(ta, tb, q, 0, 0, q);
+    sum += ng_g<DS>(d, t, ci, ta, tb, q, 0, 0, 0);
+    sum += ng_g<DS>(d, t, ci, ta, tb, q, 0, 0, q);
   }
-  return G(ta, tb, 0, 0, 0, 0) + 0.5 * sum;
+  return ng_g<DS>(d, t, ci, ta, tb, 0, 0, 0, 0) + 0.5 * sum;
 }
 
-// one coarse cell of a non-Galerkin part, every entry; the L1 row sums and
-// FP32 copy of rows 2I and 2I+1 in entry order
+// one coarse cell of a non-Galerkin part, every entry: each of the 31
+// Galerkin values once, combined in rap_ng_value's order (so the same bits);
+// then the L1 row sums and FP32 copy of rows 2I and 2I+1 in entry order
 template <int DS>
 __device__ __forceinline__ void rap_cell_ng(const PartDesc<double> &d, const RapDesc &t, long long cidx) {
-  for (int e = 0; e < t.nent; ++e) {
-    const double v = rap_ng_value<DS>(d, t, cidx, t.cofs[e]);
+  constexpr int AX = (DS + 1) % 3, BX = (DS + 2) % 3;
+  int ci[3];
+  cell_ijk((int)cidx, d.cn[0], d.cn[1], ci[0], ci[1], ci[2]);
+  double own[4][2], sht[4][2], shq[4][2], gt0[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int ua = kNgT[k][0], ub = kNgT[k][1];
+    gt0[k] = ng_g<DS>(d, t, ci, ua, ub, 0, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int q = 2 * j - 1;
+      own[k][j] = ng_g<DS>(d, t, ci, ua, ub, q, 0, 0, 0);
+      sht[k][j] = ng_g<DS>(d, t, ci, ua, ub, q, ua, ub, 0);
+      shq[k][j] = ng_g<DS>(d, t, ci, ua, ub, q, 0, 0, q);
+    }
+  }
+  const double g0 = ng_g<DS>(d, t, ci, 0, 0, 0, 0, 0, 0);
+  // the coarse pattern is the star: every entry is one of the seven below
+  auto put = [&](int o, double v) {
+    const int e = t.cmap[o];
+    if (e < 0) return;
     dev::Gw(t.out)[(long long)e * d.cncell + cidx] = v;
     if (t.out32) dev::Gw(t.out32)[(long long)e * d.cncell + cidx] = (float)v;
+  };
+  {
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        sum += sht[k][j];
+        sum += shq[k][j];
+      }
+    put(13, g0 - 0.5 * sum);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sum += own[k][j];
+      sum += sht[k][j];
+    }
+    put(13 + (2 * j - 1) * cube_stride(DS), ng_g<DS>(d, t, ci, 0, 0, 2 * j - 1, 0, 0, 0) + 0.5 * sum);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      sum += own[k][j];
+      sum += shq[k][j];
+    }
+    put(13 + kNgT[k][0] * cube_stride(AX) + kNgT[k][1] * cube_stride(BX), gt0[k] + 0.5 * sum);
   }
   if (!t.l1 && !t.fine32) return;
   RapGeo g;

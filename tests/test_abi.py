@@ -115,3 +115,17 @@ def test_new_entry_points_validate_without_gpu(libpath):
     assert lib.ssamg_solver_create(prob, C.byref(p), None, C.byref(s)) == _lib.ERR_ARG
     assert b"pb_interp" in lib.ssamg_last_error()
     assert lib.ssamg_problem_destroy(prob) == _lib.OK
+
+
+def test_binding_constants_match_the_header():
+    """Every enumerator and every ssamg_params field of the header has its
+    twin in the binding, with the same value and in the same order."""
+    from paper_2205_14273_amd import _lib
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    enums = re.findall(r"\bSSAMG_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)
+    assert len(enums) > 20
+    for name, val in enums:
+        assert getattr(_lib, name) == int(val), name
+    body = re.search(r"typedef struct \{([^}]*)\} ssamg_params;", text, flags=re.S).group(1)
+    fields = re.findall(r"\b([a-z_0-9]+)\s*;", body)
+    assert [f[0] for f in _lib.ssamg_params._fields_] == fields
