@@ -1390,6 +1390,185 @@ __global__ __launch_bounds__(kBlock) void k_dot_groups(const double *__restrict_
   if ((int)threadIdx.x < nr) out[blockIdx.x * kMaxRhs + threadIdx.x] = sh[threadIdx.x];
 }
 
+// ---------------------------------------------------------------- FP64 product, two cells per thread
+
+// The U part of A x for two cells per thread (one right-hand side): the block
+// covers the 256-cell chunks 2 b and 2 b + 1, whose rows and entries are
+// contiguous; products staged in LDS as in block_coupling, each row summed in
+// entry order by one thread (the same sums, bit for bit, as there).  Must be
+// called by every thread of the block.
+__device__ __forceinline__ void block_coupling_pair(const PartDesc<double> &d, int b2, const double *x,
+                                                    double *__restrict__ prod, double *__restrict__ rsum,
+                                                    double &out0, double &out1) {
+  out0 = out1 = 0.0;
+  const long long nch = (d.ncell + kBlock - 1) / kBlock;   // the table holds nch + 1 entries
+  const long long ca = min(2LL * b2, nch), cb = min(2LL * b2 + 2, nch);
+  const auto ub = G(d.ublk[0]);
+  const int u0 = ub[2 * ca], e0 = ub[2 * ca + 1], u1 = ub[2 * cb], e1 = ub[2 * cb + 1];
+  if (u0 == u1) return;                                    // block-uniform
+  const int tid = threadIdx.x;
+  const int cell0 = (int)d.off + b2 * 2 * kBlock;
+  const int nrt = u1 - u0;                                 // rows of the block, at most 512
+  int rq0[2] = {0, 0}, rq1[2] = {0, 0}, rslot[2] = {0, 0};
+  double racc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = tid + h * kBlock;
+    if (r < nrt) {
+      rq0[h] = G(d.uptr)[u0 + r];
+      rq1[h] = G(d.uptr)[u0 + r + 1];
+      rslot[h] = G(d.urow)[u0 + r] - cell0;
+    }
+  }
+  rsum[tid] = 0.0;
+  rsum[tid + kBlock] = 0.0;
+  constexpr int per = kUChunkBig;
+  for (int ec = e0; ec < e1; ec += per) {
+    const int np = min(per, e1 - ec);
+    int cc[per / kBlock];
+    double vv[per / kBlock], xx[per / kBlock];
+#pragma unroll
+    for (int t = 0; t < per / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      const int qe = ec + (q < np ? q : 0);
+      cc[t] = gload(d.ucol + qe);
+      vv[t] = gload(d.uval + qe);
+    }
+#pragma unroll
+    for (int t = 0; t < per / kBlock; ++t) xx[t] = t * kBlock < np ? x[cc[t]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < per / kBlock; ++t) {
+      const int q = tid + t * kBlock;
+      if (q < np) prod[q] = vv[t] * xx[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (tid + h * kBlock < nrt) {
+        const int qa = max(rq0[h], ec), qb = min(rq1[h], ec + np);
+        racc[h] = row_sum(prod, qa - ec, qb - ec, 0, 0, racc[h]);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (tid + h * kBlock < nrt) rsum[rslot[h]] = racc[h];
+  __syncthreads();
+  out0 = rsum[2 * tid];
+  out1 = rsum[2 * tid + 1];
+}
+
+// q = A p and the per-256-cell partial sums of p.q (Section 2 product; the
+// PCG product of Section 4) on the finest level when every part has the full
+// 27-point stencil and an even number of cells along x: two cells (c, c + 1)
+// of a row per thread, so every coefficient and vector value comes in a
+// 16-byte pair - half the load instructions of the one-cell kernel, which
+// bound that kernel (its address and data traffic between L1 and registers,
+// not HBM).  With MIR the entries of negative offset are read as the
+// neighbour's mirrored entry (a_s(c) = a_{-s}(c+s)); their pairs start at an
+// odd cell and are assembled from two aligned pairs.  Vector values come as
+// the three aligned pairs (c-2, c-1), (c, c+1), (c+2, c+3) of each of the
+// nine rows.  A neighbour outside the box reads an in-bounds address and is
+// zeroed.  The stencil sums run in (dz, dy, dx) order; the coupling sums and
+// the partial slots are those of the one-cell kernel.
+// 16-byte load at a uniform base plus a 32-bit byte offset (one offset
+// register per load, the base in scalar registers)
+typedef double dpair __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ dpair ld2(const double *base, unsigned byteoff) {
+  return *(dev::gptr<dpair>)((dev::gptr<char>)G(base) + byteoff);
+}
+
+template <bool MIR>
+__global__ __launch_bounds__(kBlock) void k_product2(const PartDesc<double> *__restrict__ desc, int nb1,
+                                                     const double *__restrict__ x, double *__restrict__ y,
+                                                     double *__restrict__ dotp) {
+  __shared__ double prod[kUChunkBig];
+  __shared__ double sh[2 * kBlock];
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const int b2 = chunk_index();
+  const int tid = threadIdx.x;
+  const long long c = (long long)b2 * (2 * kBlock) + 2 * tid;
+  const bool valid = c < d.ncell;
+  const int cc = valid ? (int)c : 0;
+  int i, j, k;
+  cell_ijk(cc, d.n[0], d.n[1], i, j, k);
+  const unsigned my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
+  const bool xl = i > 0;                   // cell c has its -x neighbour
+  const bool xr = i + 2 < d.n[0];          // cell c + 1 has its +x neighbour
+  const int nx = d.n[0], nxy = d.n[0] * d.n[1];
+  const double *xb = x + d.off;
+  const unsigned c8 = 8u * (unsigned)cc;
+  double acc0 = 0.0, acc1 = 0.0, xc0 = 0.0, xc1 = 0.0;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const bool row = ((my >> (dy + 1)) & (mz >> (dz + 1)) & 1u) != 0;
+      const unsigned r8 = c8 + 8u * (unsigned)(row ? dy * nx + dz * nxy : 0);   // byte offset of (c + row)
+      const bool okm = row && xl, okp = row && xr;
+      const dpair xm = ld2(xb, okm ? r8 - 16u : r8);
+      const dpair xz = ld2(xb, r8);
+      const dpair xp = ld2(xb, okp ? r8 + 16u : r8);
+      const double xv0[3] = {okm ? xm.y : 0.0, row ? xz.x : 0.0, row ? xz.y : 0.0};
+      const double xv1[3] = {row ? xz.x : 0.0, row ? xz.y : 0.0, okp ? xp.x : 0.0};
+      if (dz == 0 && dy == 0) {
+        xc0 = xz.x;
+        xc1 = xz.y;
+      }
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+        const bool neg = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+        double a0, a1;
+        if (MIR && neg) {
+          // a_s(c) = a_{-s}(c + s): entry -s at the neighbour c + s (row r8 + dx)
+          const double *arr = d.coef + (long long)d.cube[26 - o] * d.ncell;
+          if (dx == 0) {
+            const dpair v = ld2(arr, r8);
+            a0 = v.x;
+            a1 = v.y;
+          } else {
+            const bool ok0 = row && (dx > 0 || xl), ok1 = row && (dx < 0 || xr);
+            const dpair u = ld2(arr, ok0 ? r8 + 8u * (unsigned)(dx - 1) : c8);
+            const dpair w = ld2(arr, ok1 ? r8 + 8u * (unsigned)(dx + 1) : c8);
+            a0 = u.y;
+            a1 = w.x;
+          }
+        } else {
+          const dpair v = ld2(d.coef + (long long)d.cube[o] * d.ncell, c8);
+          a0 = v.x;
+          a1 = v.y;
+        }
+        acc0 = fma(a0, xv0[dx + 1], acc0);
+        acc1 = fma(a1, xv1[dx + 1], acc1);
+      }
+    }
+  }
+  double u0, u1;
+  block_coupling_pair(d, b2, xb - d.off, prod, sh, u0, u1);
+  acc0 += u0;
+  acc1 += u1;
+  if (valid) *(double2 *)(y + d.off + cc) = make_double2(acc0, acc1);
+  // p.q per 256-cell chunk 2 b2 and 2 b2 + 1 (the one-cell kernel's tree)
+  __syncthreads();
+  sh[2 * tid] = valid ? xc0 * acc0 : 0.0;
+  sh[2 * tid + 1] = valid ? xc1 * acc1 : 0.0;
+  const int half = tid >> 7, t = tid & 127;   // threads 0..127 reduce chunk 2 b2, 128..255 the next
+  for (int s = kBlock / 2; s >= 1; s >>= 1) {
+    __syncthreads();
+    if (t < s) sh[half * kBlock + t] += sh[half * kBlock + t + s];
+  }
+  __syncthreads();
+  const long long slots = 4LL * ((nb1 + 3) / 4);
+  double *dslot = dotp + (long long)blockIdx.y * slots;
+  if (tid < 2) {
+    const long long ch = 2LL * b2 + tid;
+    if (ch < nb1) dslot[ch] = sh[tid * kBlock];
+  }
+  // the block holding the one-cell grid's last chunk clears the rounding slots
+  if ((nb1 - 1) / 2 == b2 && tid < slots - nb1) dslot[nb1 + tid] = 0.0;
+}
+
 // kernel<<<grid, kBlock>>>(args...) on st, timed by ev when ev.start is set
 template <typename K, typename... A>
 inline void dispatch(K kernel, dim3 grid, hipStream_t st, const LaunchEvents &ev, A... args) {
@@ -1453,6 +1632,16 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+
+void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, const double *x,
+                     double *y, double *dotp, hipStream_t st, LaunchEvents ev) {
+  const int nb1 = (int)grid_cells(maxcell, 0);
+  dim3 grid((unsigned)((nb1 + 1) / 2), nparts);
+  if (mir)
+    dispatch(k_product2<true>, grid, st, ev, desc, nb1, x, y, dotp);
+  else
+    dispatch(k_product2<false>, grid, st, ev, desc, nb1, x, y, dotp);
+}
 
 template <typename T, typename TB, typename TO>
 void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int nparts, int maxcell,

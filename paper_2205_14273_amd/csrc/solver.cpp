@@ -208,8 +208,10 @@ PartDesc<T> make_desc(const Level &V, const PartLevel &q, size_t p, const T *coe
     d.tbp[lg] = (plane % cpb == 0) ? (int)(plane / cpb) : 0;
     d.tsb[lg] = (d.tbp[lg] > 0 && strips[lg] > 1) ? (d.tbp[lg] + strips[lg] - 1) / strips[lg] : 0;
   }
+  for (int o = 0; o < 27; ++o) d.cube[o] = -1;
   for (size_t e = 0; e < q.pat.size(); ++e) {
     const auto &o = q.pat[e];
+    d.cube[cube_index(o)] = (int)e;
     d.lin[e] = o[0] + q.n[0] * (o[1] + q.n[1] * o[2]);
     d.code[e] = pack_off(o[0], o[1], o[2]);
     d.lc[e] = d.lin[e] * 64 + d.code[e];
@@ -1467,6 +1469,16 @@ void precond(Solver &s, int lg, bool dots = false) {
     precond_t<double>(s, lg, dots);
 }
 
+// whether the finest level takes the two-cells-per-thread FP64 product: every
+// part has the full 27-point stencil and an even number of cells along x (so
+// a cell pair never straddles a row and every part starts at an even cell)
+bool product2_ok(const Solver &s) {
+  if (s.product2 == 0) return false;
+  for (const auto &q : s.lv[0].parts)
+    if (q.pat.size() != 27 || (q.n[0] & 1) || (q.off & 1)) return false;
+  return true;
+}
+
 // y = A x on level 0 in FP64; with dot_slot >= 0 the product also forms x.y
 // per right-hand side into that scalar slot (two small reduction launches)
 void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) {
@@ -1478,9 +1490,12 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
   if (dot && !s.dotp) throw Error(SSAMG_ERR_STATE, "internal: fused product dot needs a batch of 4+");
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
-    launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
-                                           V.maxcell, lg, x, nullptr, y, s.stream, pr.e, cols4,
-                                           dot ? s.dotp : nullptr, nullptr, mirrored(s));
+    if (dot && lg == 0 && product2_ok(s))
+      launch_product2(V.d_desc64, np, V.maxcell, mirrored(s), x, y, s.dotp, s.stream, pr.e);
+    else
+      launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
+                                             V.maxcell, lg, x, nullptr, y, s.stream, pr.e, cols4,
+                                             dot ? s.dotp : nullptr, nullptr, mirrored(s));
   }
   if (dot) {
     const bool c4 = cols4 != 0 && stencil_cols4_ok<double>(lg, V.maxent);

@@ -142,6 +142,8 @@ struct PartDesc {
   // lin[s] * 64 + code[s] (code < 64): the small-level sweeps read one scalar
   // per entry, which keeps the 27-point tables within the scalar registers
   int lc[kMaxEnt];
+  // entry of each offset, cube index (dx+1) + 3(dy+1) + 9(dz+1); -1: none
+  int cube[27];
 };
 
 // ------------------------------------------------------------------ problem
@@ -309,6 +311,7 @@ struct Solver {
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
   int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
+  int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell FP64 product everywhere
   int lk = -1;                       // collapse level (-1: none)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
   hipEvent_t ev_scal = nullptr;      // PCG: the scalars of an iteration have reached the host
@@ -483,6 +486,13 @@ void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int
                     int lg, const T *x, const TB *b, TO *y, hipStream_t st, LaunchEvents ev = {},
                     int cols4 = -1, double *dotp = nullptr, const double *aux = nullptr,
                     bool mir = false);
+// The FP64 product of PCG with its p.q partials (MODE_APPLY_DOT, one
+// right-hand side) on a finest level whose parts all have the full 27-point
+// stencil and an even number of cells along x, two cells per thread
+// (k_product2); same partial slots as the one-column kernel.  nb1: that
+// kernel's blocks per part.
+void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, const double *x,
+                     double *y, double *dotp, hipStream_t st, LaunchEvents ev = {});
 // First pass of the fused product dot: kDotGroupBlocks partial sums per
 // right-hand side into partial[b][k] (row stride kMaxRhs) from ngroups groups
 // of dotp (per = 4 one-column slots each, or per = 1 group sum); k_dot_final
