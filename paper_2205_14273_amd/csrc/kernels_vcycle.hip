@@ -1392,41 +1392,44 @@ __global__ __launch_bounds__(kBlock) void k_dot_groups(const double *__restrict_
 
 // ---------------------------------------------------------------- FP64 product, two cells per thread
 
-// The U part of A x for two cells per thread (one right-hand side): the block
-// covers the 256-cell chunks 2 b and 2 b + 1, whose rows and entries are
-// contiguous; products staged in LDS as in block_coupling, each row summed in
-// entry order by one thread (the same sums, bit for bit, as there).  Must be
+// The U part of A x for CPT consecutive cells per thread (one right-hand
+// side): the block covers the 256-cell chunks CPT b .. CPT b + CPT - 1, whose
+// rows and entries are contiguous; products staged in LDS as in
+// block_coupling, each row summed in entry order by one thread (the same sums,
+// bit for bit, as there).  out[k] is cell CPT tid + k of the block.  Must be
 // called by every thread of the block.
-__device__ __forceinline__ void block_coupling_pair(const PartDesc<double> &d, int b2, const double *x,
-                                                    double *__restrict__ prod, double *__restrict__ rsum,
-                                                    double &out0, double &out1) {
-  out0 = out1 = 0.0;
+template <int CPT, typename T>
+__device__ __forceinline__ void block_coupling_multi(const PartDesc<T> &d, int bk, const T *x,
+                                                     T *__restrict__ prod, T *__restrict__ rsum, T (&out)[CPT]) {
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) out[k] = T(0);
   const long long nch = (d.ncell + kBlock - 1) / kBlock;   // the table holds nch + 1 entries
-  const long long ca = min(2LL * b2, nch), cb = min(2LL * b2 + 2, nch);
+  const long long ca = min((long long)CPT * bk, nch), cb = min((long long)CPT * bk + CPT, nch);
   const auto ub = G(d.ublk[0]);
   const int u0 = ub[2 * ca], e0 = ub[2 * ca + 1], u1 = ub[2 * cb], e1 = ub[2 * cb + 1];
   if (u0 == u1) return;                                    // block-uniform
   const int tid = threadIdx.x;
-  const int cell0 = (int)d.off + b2 * 2 * kBlock;
-  const int nrt = u1 - u0;                                 // rows of the block, at most 512
-  int rq0[2] = {0, 0}, rq1[2] = {0, 0}, rslot[2] = {0, 0};
-  double racc[2] = {0.0, 0.0};
+  const int cell0 = (int)d.off + bk * CPT * kBlock;
+  const int nrt = u1 - u0;                                 // rows of the block, at most CPT * 256
+  int rq0[CPT], rq1[CPT], rslot[CPT];
+  T racc[CPT];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < CPT; ++h) {
     const int r = tid + h * kBlock;
+    rq0[h] = rq1[h] = rslot[h] = 0;
+    racc[h] = T(0);
     if (r < nrt) {
       rq0[h] = G(d.uptr)[u0 + r];
       rq1[h] = G(d.uptr)[u0 + r + 1];
       rslot[h] = G(d.urow)[u0 + r] - cell0;
     }
+    rsum[tid + h * kBlock] = T(0);
   }
-  rsum[tid] = 0.0;
-  rsum[tid + kBlock] = 0.0;
   constexpr int per = kUChunkBig;
   for (int ec = e0; ec < e1; ec += per) {
     const int np = min(per, e1 - ec);
     int cc[per / kBlock];
-    double vv[per / kBlock], xx[per / kBlock];
+    T vv[per / kBlock], xx[per / kBlock];
 #pragma unroll
     for (int t = 0; t < per / kBlock; ++t) {
       const int q = tid + t * kBlock;
@@ -1435,7 +1438,7 @@ __device__ __forceinline__ void block_coupling_pair(const PartDesc<double> &d, i
       vv[t] = gload(d.uval + qe);
     }
 #pragma unroll
-    for (int t = 0; t < per / kBlock; ++t) xx[t] = t * kBlock < np ? x[cc[t]] : 0.0;
+    for (int t = 0; t < per / kBlock; ++t) xx[t] = t * kBlock < np ? x[cc[t]] : T(0);
 #pragma unroll
     for (int t = 0; t < per / kBlock; ++t) {
       const int q = tid + t * kBlock;
@@ -1443,7 +1446,7 @@ __device__ __forceinline__ void block_coupling_pair(const PartDesc<double> &d, i
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < CPT; ++h)
       if (tid + h * kBlock < nrt) {
         const int qa = max(rq0[h], ec), qb = min(rq1[h], ec + np);
         racc[h] = row_sum(prod, qa - ec, qb - ec, 0, 0, racc[h]);
@@ -1451,11 +1454,11 @@ __device__ __forceinline__ void block_coupling_pair(const PartDesc<double> &d, i
     __syncthreads();
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < CPT; ++h)
     if (tid + h * kBlock < nrt) rsum[rslot[h]] = racc[h];
   __syncthreads();
-  out0 = rsum[2 * tid];
-  out1 = rsum[2 * tid + 1];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) out[k] = rsum[CPT * tid + k];
 }
 
 // q = A p and the per-256-cell partial sums of p.q (Section 2 product; the
@@ -1544,10 +1547,10 @@ __global__ __launch_bounds__(kBlock) void k_product2(const PartDesc<double> *__r
       }
     }
   }
-  double u0, u1;
-  block_coupling_pair(d, b2, xb - d.off, prod, sh, u0, u1);
-  acc0 += u0;
-  acc1 += u1;
+  double u[2];
+  block_coupling_multi<2>(d, b2, xb - d.off, prod, sh, u);
+  acc0 += u[0];
+  acc1 += u[1];
   if (valid) *(double2 *)(y + d.off + cc) = make_double2(acc0, acc1);
   // p.q per 256-cell chunk 2 b2 and 2 b2 + 1 (the one-cell kernel's tree)
   __syncthreads();
@@ -1567,6 +1570,92 @@ __global__ __launch_bounds__(kBlock) void k_product2(const PartDesc<double> *__r
   }
   // the block holding the one-cell grid's last chunk clears the rounding slots
   if ((nb1 - 1) / 2 == b2 && tid < slots - nb1) dslot[nb1 + tid] = 0.0;
+}
+
+// CPT consecutive values of type T at a uniform base plus a 32-bit byte offset
+template <typename T, int CPT>
+struct VecOf {
+  typedef T type __attribute__((ext_vector_type(CPT)));
+};
+template <typename T, int CPT>
+__device__ __forceinline__ typename VecOf<T, CPT>::type ldv(const T *base, unsigned byteoff) {
+  return *(dev::gptr<typename VecOf<T, CPT>::type>)((dev::gptr<char>)G(base) + byteoff);
+}
+
+// The finest level's residual t = b - A x (MODE_RESID) and post-smoothing
+// sweep z = x + w (b - A x) (MODE_JACOBI) of the V-cycle (Section 3.4,
+// eq:relax0; one right-hand side, b in FP64) on a level whose parts all have
+// the full 27-point stencil and a multiple of CPT cells along x: CPT cells of
+// a row per thread (16-byte vectors: 2 FP64 or 4 FP32 values), every entry
+// read (no mirror), vector values as the three aligned vectors before, at and
+// after the thread's cells in each of the nine rows; stencil sums in
+// (dz, dy, dx) order, couplings as in the one-cell kernel.
+template <typename T, int MODE, typename TO, int CPT>
+__global__ __launch_bounds__(kBlock) void k_sweepN(const PartDesc<T> *__restrict__ desc, const T *__restrict__ x,
+                                                   const double *__restrict__ b, TO *__restrict__ y) {
+  __shared__ T prod[kUChunkBig];
+  __shared__ T sh[CPT * kBlock];
+  const PartDesc<T> &d = desc[blockIdx.y];
+  const int bk = chunk_index();
+  const int tid = threadIdx.x;
+  const long long c = (long long)bk * (CPT * kBlock) + CPT * tid;
+  const bool valid = c < d.ncell;
+  const int cc = valid ? (int)c : 0;
+  int i, j, k;
+  cell_ijk(cc, d.n[0], d.n[1], i, j, k);
+  const unsigned my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
+  const bool xl = i > 0, xr = i + CPT < d.n[0];   // first cell's -x, last cell's +x neighbour
+  const int nx = d.n[0], nxy = d.n[0] * d.n[1];
+  const T *xb = x + d.off;
+  constexpr unsigned ts = sizeof(T);
+  const unsigned ct = ts * (unsigned)cc;
+  T acc[CPT], xc[CPT], ac[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) acc[q] = xc[q] = ac[q] = T(0);
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const bool row = ((my >> (dy + 1)) & (mz >> (dz + 1)) & 1u) != 0;
+      const unsigned rt = ct + ts * (unsigned)(row ? dy * nx + dz * nxy : 0);
+      const bool okm = row && xl, okp = row && xr;
+      const auto xm = ldv<T, CPT>(xb, okm ? rt - CPT * ts : rt);
+      const auto xz = ldv<T, CPT>(xb, rt);
+      const auto xp = ldv<T, CPT>(xb, okp ? rt + CPT * ts : rt);
+      T xv[CPT + 2];   // values at cells c - 1 .. c + CPT of the row
+      xv[0] = okm ? xm[CPT - 1] : T(0);
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) xv[q + 1] = row ? xz[q] : T(0);
+      xv[CPT + 1] = okp ? xp[0] : T(0);
+      if (dz == 0 && dy == 0)
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) xc[q] = xz[q];
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+        const auto v = ldv<T, CPT>(d.coef + (long long)d.cube[o] * d.ncell, ct);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          if (o == 13) ac[q] = v[q];
+          acc[q] = fma(v[q], xv[q + 1 + dx], acc[q]);
+        }
+      }
+    }
+  }
+  T u[CPT];
+  block_coupling_multi<CPT>(d, bk, xb - d.off, prod, sh, u);
+  if (!valid) return;
+  const long long o = d.off + cc;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const T r = (T)b[o + q] - (acc[q] + u[q]);
+    if constexpr (MODE == MODE_RESID) {
+      y[o + q] = (TO)r;
+    } else {
+      const T w = d.rs ? G(d.rs)[cc + q] : d.omega / ac[q];
+      y[o + q] = (TO)(xc[q] + w * r);
+    }
+  }
 }
 
 // kernel<<<grid, kBlock>>>(args...) on st, timed by ev when ev.start is set
@@ -1632,6 +1721,25 @@ void stencil_mode(int mode, dim3 grid, const PartDesc<T> *desc, int lg, const T 
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+
+template <typename T, typename TO>
+void launch_sweep2(int mode, const PartDesc<T> *desc, int nparts, int maxcell, const T *x, const double *b, TO *y,
+                   hipStream_t st, LaunchEvents ev) {
+  constexpr int cpt = 16 / sizeof(T);
+  dim3 grid((unsigned)((grid_cells(maxcell, 0) + cpt - 1) / cpt), nparts);
+  if (mode == MODE_RESID)
+    dispatch(k_sweepN<T, MODE_RESID, TO, cpt>, grid, st, ev, desc, x, b, y);
+  else if (mode == MODE_JACOBI)
+    dispatch(k_sweepN<T, MODE_JACOBI, TO, cpt>, grid, st, ev, desc, x, b, y);
+  else
+    throw Error(SSAMG_ERR_STATE, "internal: multi-cell sweep mode");
+}
+template void launch_sweep2<float, float>(int, const PartDesc<float> *, int, int, const float *, const double *,
+                                          float *, hipStream_t, LaunchEvents);
+template void launch_sweep2<float, double>(int, const PartDesc<float> *, int, int, const float *, const double *,
+                                           double *, hipStream_t, LaunchEvents);
+template void launch_sweep2<double, double>(int, const PartDesc<double> *, int, int, const double *,
+                                            const double *, double *, hipStream_t, LaunchEvents);
 
 void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, const double *x,
                      double *y, double *dotp, hipStream_t st, LaunchEvents ev) {

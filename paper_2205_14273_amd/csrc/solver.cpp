@@ -8,6 +8,7 @@
 #include <functional>
 #include <limits>
 #include <numeric>
+#include <type_traits>
 
 #include "capi_common.h"
 #include "ssamg_impl.h"
@@ -1268,6 +1269,17 @@ struct Probe {
 // with four or more right-hand sides (then run four columns per thread), where
 // the fused kernel's neighbour streams (coefficients, b, w) cost more than
 // writing x and running the plain residual sweep.
+// whether the finest level's one-column product and sweeps run two cells per
+// thread (k_product2, k_sweep2): every part has the full 27-point stencil and
+// an even number of cells along x (so a cell pair never straddles a row and
+// every part starts at an even cell)
+bool product2_ok(const Solver &s, int cpt = 2) {
+  if (s.product2 == 0) return false;
+  for (const auto &q : s.lv[0].parts)
+    if (q.pat.size() != 27 || q.n[0] % cpt != 0 || q.off % cpt != 0) return false;
+  return true;
+}
+
 template <typename T, typename TB>
 void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int lg, const TB *b, T *x, T *t,
                 const TuneRec &o, LaunchEvents ev = {}) {
@@ -1277,6 +1289,12 @@ void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int l
                                              : (V.maxent > 15 && V.N >= s.split_cells));
   if (split) {
     launch_smooth_zero<T, TB>(fine, d, np, V.maxcell, lg, b, x, s.stream);
+    if constexpr (std::is_same<TB, double>::value) {
+      if (sizeof(T) == 8 && fine && lg == 0 && s.sweepn && product2_ok(s, 16 / sizeof(T))) {
+        launch_sweep2<T, T>(MODE_RESID, d, np, V.maxcell, x, b, t, s.stream, ev);
+        return;
+      }
+    }
     launch_stencil<T, TB, T>(MODE_RESID, fine, V.maxent, d, np, V.maxcell, lg, x, b, t, s.stream, ev, o.cols4);
   } else {
     launch_smooth_resid<T, TB>(fine, V.maxent, d, np, V.maxcell, lg, b, x, t, s.stream, ev);
@@ -1450,9 +1468,12 @@ void precond_t(Solver &s, int lg, bool dots) {
   {
     // with dots the sweep also reads q (flexible CG)
     Probe pr(s, SSAMG_PROBE_JACOBI0, level0_bytes(s, SSAMG_PROBE_JACOBI0, lg, tc, tx, dots && flexible ? 16 : 8, 8));
-    launch_stencil<T, double, double>(dots ? MODE_JACOBI_DOT : MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg, x,
-                                      s.r, s.z, st, pr.e, o.cols4, dots ? s.dotp : nullptr,
-                                      dots && flexible ? s.q : nullptr);
+    if (sizeof(T) == 8 && !dots && lg == 0 && s.sweepn && product2_ok(s, 16 / sizeof(T)))
+      launch_sweep2<T, double>(MODE_JACOBI, d, np, V.maxcell, x, s.r, s.z, st, pr.e);
+    else
+      launch_stencil<T, double, double>(dots ? MODE_JACOBI_DOT : MODE_JACOBI, 1, V.maxent, d, np, V.maxcell, lg,
+                                        x, s.r, s.z, st, pr.e, o.cols4, dots ? s.dotp : nullptr,
+                                        dots && flexible ? s.q : nullptr);
   }
   if (dots) {
     const bool c4 = o.cols4 != 0 && stencil_cols4_ok<T>(lg, V.maxent);
@@ -1467,16 +1488,6 @@ void precond(Solver &s, int lg, bool dots = false) {
     precond_t<float>(s, lg, dots);
   else
     precond_t<double>(s, lg, dots);
-}
-
-// whether the finest level takes the two-cells-per-thread FP64 product: every
-// part has the full 27-point stencil and an even number of cells along x (so
-// a cell pair never straddles a row and every part starts at an even cell)
-bool product2_ok(const Solver &s) {
-  if (s.product2 == 0) return false;
-  for (const auto &q : s.lv[0].parts)
-    if (q.pat.size() != 27 || (q.n[0] & 1) || (q.off & 1)) return false;
-  return true;
 }
 
 // y = A x on level 0 in FP64; with dot_slot >= 0 the product also forms x.y

@@ -311,7 +311,8 @@ struct Solver {
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
   int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
-  int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell FP64 product everywhere
+  int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere
+  int sweepn = 1;                            // SSAMG_SWEEPN=0: the one-cell finest sweeps
   int lk = -1;                       // collapse level (-1: none)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
   hipEvent_t ev_scal = nullptr;      // PCG: the scalars of an iteration have reached the host
@@ -493,6 +494,15 @@ void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int
 // kernel's blocks per part.
 void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, const double *x,
                      double *y, double *dotp, hipStream_t st, LaunchEvents ev = {});
+// The finest level's residual (MODE_RESID) or post-smoothing sweep
+// (MODE_JACOBI) for one right-hand side with b in FP64, 16 / sizeof(T) cells
+// per thread (k_sweepN): every part has the full 27-point stencil and a
+// multiple of that many cells along x.  Taken by the FP64 cycle only: in
+// FP32 the four-cell form measured slower than one cell per thread (C3
+// post-sweep 491 against 434 us; two waves per SIMD instead of four).
+template <typename T, typename TO>
+void launch_sweep2(int mode, const PartDesc<T> *desc, int nparts, int maxcell, const T *x, const double *b, TO *y,
+                   hipStream_t st, LaunchEvents ev = {});
 // First pass of the fused product dot: kDotGroupBlocks partial sums per
 // right-hand side into partial[b][k] (row stride kMaxRhs) from ngroups groups
 // of dotp (per = 4 one-column slots each, or per = 1 group sum); k_dot_final

@@ -266,3 +266,30 @@ def test_binding_rejects_bad_vectors():
         s.apply_A(1, good)
     with pytest.raises(TypeError):
         s.apply_precond(good.float())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_cell_product_and_sweeps(monkeypatch, precision):
+    """Full 27-point levels with even rows run the PCG product two cells per
+    thread and, in the FP64 cycle, the finest residual and post-sweep two cells
+    per thread: the cycle matches the oracle entry by entry, the solve reaches
+    the tolerance with the oracle's iterations (the true residual is formed by
+    the one-cell product), and it equals the one-cell kernels' solve to
+    rounding."""
+    _print_case(f"multi-cell kernels c3_10 precision={precision}")
+    case = W.c3(10)
+    h = oracle_fv(case)
+    b = case.b
+    ref = O.solve(h, b, tol=1e-8, flexible=(precision == 1))
+    out = {}
+    for v in ("1", "0"):
+        monkeypatch.setenv("SSAMG_PRODUCT2", v)
+        _, s = gpu_fv(case, cycle_precision=precision)
+        r = np.random.default_rng(31).uniform(-1, 1, h.levels[0].n)
+        z = s.apply_precond(_cuda(r)).cpu().numpy()
+        assert_cycle_close(z, O.vcycle(h, r), vcycle_scale(h, r), CYCLE_RTOL[precision], f"product2={v}")
+        x, st, info = s.solve(_cuda(b))
+        assert st == 0 and info.true_relres[0] < 1e-8 and abs(info.iters[0] - ref.iters) <= 1
+        out[v] = (x.cpu().numpy(), info.iters[0])
+    assert out["1"][1] == out["0"][1]
+    assert np.linalg.norm(out["1"][0] - out["0"][0]) <= 1e-9 * np.linalg.norm(out["0"][0])
