@@ -73,7 +73,14 @@ __device__ int find_part(const int *geom, int nparts, int p, const int G[3], int
 __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *__restrict__ kappa,
                                                        const double *__restrict__ aniso,
                                                        double *const *__restrict__ coef) {
+  // the part's link factors and geometric weights, once per block
+  __shared__ double s_as[kMaxEnt], s_gw[kMaxEnt];
   const int p = blockIdx.y;
+  if ((int)threadIdx.x < fa.nent) {
+    s_as[threadIdx.x] = link_factor(aniso, p, fa.code[threadIdx.x]);
+    s_gw[threadIdx.x] = geom_weight(fa.code[threadIdx.x]);
+  }
+  __syncthreads();
   const Geo me = geo_of(fa.geom, p);
   const long long ncell = (long long)me.n[0] * me.n[1] * me.n[2];
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -84,21 +91,24 @@ __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *
   const int loc[3] = {i, j, k};
   const double kc = kappa[me.off + c];
   const auto cf = dev::Gw(coef[p]);
+  const auto kp = dev::G(kappa) + me.off;
+  const long long sy = me.n[0], sz = (long long)me.n[0] * me.n[1];
   double diag = 0.0;
   for (int s = 1; s < fa.nent; ++s) {
     const int code = fa.code[s];
-    const double as = link_factor(aniso, p, code);
+    const double as = s_as[s];
     const double xi = as * kc;
-    const double gw = geom_weight(code);
+    const double gw = s_gw[s];
     int nb[3];
     bool in = true;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       nb[d] = loc[d] + oc(code, d);
-      in = in && nb[d] >= 0 && nb[d] < me.n[d];
+      in = in && (unsigned)nb[d] < (unsigned)me.n[d];
     }
     double t, v = 0.0;
     if (in) {
-      const double xj = as * kappa[me.off + nb[0] + (long long)me.n[0] * (nb[1] + (long long)me.n[1] * nb[2])];
+      const double xj = as * kp[c + oc(code, 0) + sy * oc(code, 1) + sz * oc(code, 2)];
       t = gw * 2.0 * xi * xj / (xi + xj);
       v = -t;
     } else {
