@@ -5,12 +5,12 @@
 //
 // Every U_l entry (f, g) meets at most two nonzeros in row f and two in row
 // g of P (two-point interpolation), so it emits up to four records keyed by
-// the coarse pair (I, J).  A stable radix sort on the key groups the records
-// by coarse entry while keeping the emission order (row-major over U_l), so
-// the numeric pass sums each entry in a fixed order.  Runs of equal keys are
-// the coarse entries; runs of equal I are the stored rows.
-#include <hipcub/hipcub.hpp>
-
+// the coarse pair (I, J).  The records are put in key order with ties in
+// emission order (row-major over U_l, the order of a stable sort), so the
+// numeric pass sums each entry in a fixed order: counted into coarse-row
+// buckets, scattered, and ranked inside each row.  Runs of equal keys are the
+// coarse entries; runs of equal I are the stored rows.  All scans are the
+// three-pass block scans below.
 #include "ssamg_impl.h"
 
 namespace ssamg {
@@ -103,56 +103,61 @@ __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp,
 // offsets, scatter every valid record into its row's range (any order), then
 // place each at its row offset plus its rank among the row's records by
 // (key, record index).  Positions past the valid records get the invalid key.
+// A wave's 64 records fall in few coarse rows (those of a handful of fine
+// rows), though not in runs (the two coarse rows of an F row alternate), so
+// the wave groups its lanes by row: one lane per distinct row touches that
+// row's counter, with the group's size, and each lane gets its rank in its
+// group.
+__device__ __forceinline__ int rec_row(const unsigned long long *__restrict__ key, long long n,
+                                       unsigned long long nc, unsigned long long invalid) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const unsigned long long k = i < n ? key[i] : invalid;
+  return k != invalid ? (int)(k / nc) : -1;
+}
+
 __global__ __launch_bounds__(kBlock) void k_row_count(const unsigned long long *__restrict__ key, long long n,
                                                       unsigned long long nc, unsigned long long invalid,
                                                       int *__restrict__ cnt) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const unsigned long long k = key[i];
-  if (k != invalid) atomicAdd(&cnt[k / nc], 1);
+  const int r = rec_row(key, n, nc, invalid);
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(r >= 0);
+  while (pending) {                                        // wave-uniform
+    const int leader = __ffsll((long long)pending) - 1;
+    const int val = __shfl(r, leader, 64);
+    const unsigned long long same = __ballot(r == val) & pending;
+    if (lane == leader) atomicAdd(&cnt[val], __popcll(same));
+    pending &= ~same;
+  }
 }
 
-// cnt holds the row counts on entry and zeros on exit
+// cnt holds the row counts on entry and zeros on exit; a group takes
+// consecutive slots of its row's range
 __global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long *__restrict__ key,
                                                         const unsigned *__restrict__ idx, long long n,
                                                         unsigned long long nc, unsigned long long invalid,
                                                         const int *__restrict__ roff, int *__restrict__ cnt,
                                                         unsigned long long *__restrict__ tk,
                                                         unsigned *__restrict__ ti) {
+  const int r = rec_row(key, n, nc, invalid);
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ULL << lane) - 1;
+  int pos = 0;
+  unsigned long long pending = __ballot(r >= 0);
+  while (pending) {                                        // wave-uniform
+    const int leader = __ffsll((long long)pending) - 1;
+    const int val = __shfl(r, leader, 64);
+    const unsigned long long same = __ballot(r == val) & pending;
+    const int m = __popcll(same);
+    int base = 0;
+    if (lane == leader) base = roff[val] + atomicSub(&cnt[val], m) - m;
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1) pos = base + __popcll(same & below);
+    pending &= ~same;
+  }
+  if (r < 0) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const unsigned long long k = key[i];
-  if (k == invalid) return;
-  const long long r = (long long)(k / nc);
-  const int pos = roff[r] + atomicSub(&cnt[r], 1) - 1;
-  tk[pos] = k;
+  tk[pos] = key[i];
   ti[pos] = idx[i];
-}
-
-__global__ __launch_bounds__(kBlock) void k_row_rank(const unsigned long long *__restrict__ tk,
-                                                     const unsigned *__restrict__ ti, long long n,
-                                                     unsigned long long nc, unsigned long long invalid,
-                                                     const int *__restrict__ roff,
-                                                     unsigned long long *__restrict__ key,
-                                                     unsigned *__restrict__ idx) {
-  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n) return;
-  if (p >= roff[nc]) {
-    key[p] = invalid;
-    return;
-  }
-  const unsigned long long k = tk[p];
-  const unsigned s = ti[p];
-  const long long r = (long long)(k / nc);
-  const int b = roff[r], e = roff[r + 1];
-  int rank = 0;
-  for (int j = b; j < e; ++j) {
-    const unsigned long long kj = tk[j];
-    const unsigned sj = ti[j];
-    rank += (kj < k || (kj == k && sj < s)) ? 1 : 0;
-  }
-  key[b + rank] = k;
-  idx[b + rank] = s;
 }
 
 // after the sort: flags of records that open a coarse entry / a coarse row,
@@ -249,9 +254,157 @@ __global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp,
   out[2 * (boff[p] + b) + 1] = nrow > 0 ? uptr[lo] : 0;
 }
 
+// Rank of every record inside its row by (key, record index), one wave per
+// chunk of 64 sorted positions: the wave takes each row that starts in its
+// chunk and every lane counts, for its records, the smaller ones.  Inside a
+// row every key has the same coarse row, so (column, record index) packed in
+// 64 bits orders it; rows of at most cap records are staged in LDS that way
+// (else read from memory).  The same positions as a stable sort.
+constexpr int kRankCap = 512;
+__global__ __launch_bounds__(64) void k_row_rank_lds(const unsigned long long *__restrict__ tk,
+                                                     const unsigned *__restrict__ ti, long long n,
+                                                     unsigned long long nc, unsigned long long invalid,
+                                                     const int *__restrict__ roff, int cap,
+                                                     unsigned long long *__restrict__ key,
+                                                     unsigned *__restrict__ idx) {
+  __shared__ unsigned long long sv[kRankCap];
+  const int lane = threadIdx.x;
+  const long long p = (long long)blockIdx.x * 64 + lane;
+  const long long total = roff[nc];
+  if (p < n && p >= total) key[p] = invalid;
+  bool start = false;
+  if (p < total) {
+    const long long r = (long long)(tk[p] / nc);
+    start = roff[r] == p;
+  }
+  unsigned long long starts = __ballot(start);
+  while (starts) {                                         // wave-uniform
+    const int l = __ffsll((long long)starts) - 1;
+    starts &= starts - 1;
+    const long long p0 = (long long)blockIdx.x * 64 + l;
+    const long long r = (long long)(tk[p0] / nc);
+    const int b = roff[r], e = roff[r + 1], len = e - b;
+    const unsigned long long rbase = (unsigned long long)r * nc;
+    auto packed = [&](int q) { return ((tk[q] - rbase) << 32) | ti[q]; };
+    if (len <= cap) {
+      for (int q = lane; q < len; q += 64) sv[q] = packed(b + q);
+      __syncthreads();
+      for (int q = lane; q < len; q += 64) {
+        const unsigned long long v = sv[q];
+        int rank = 0;
+        int j = 0;
+        for (; j + 4 <= len; j += 4) {
+          const unsigned long long w0 = sv[j], w1 = sv[j + 1], w2 = sv[j + 2], w3 = sv[j + 3];
+          rank += (w0 < v) + (w1 < v) + (w2 < v) + (w3 < v);
+        }
+        for (; j < len; ++j) rank += sv[j] < v;
+        key[b + rank] = rbase + (v >> 32);
+        idx[b + rank] = (unsigned)v;
+      }
+      __syncthreads();
+    } else {
+      for (int q = lane; q < len; q += 64) {
+        const unsigned long long v = packed(b + q);
+        int rank = 0;
+        for (int j = b; j < e; ++j) rank += packed(j) < v;
+        key[b + rank] = rbase + (v >> 32);
+        idx[b + rank] = (unsigned)v;
+      }
+    }
+  }
+}
+
+// Three-pass scans over blocks of kScanItems elements (kBlock threads of
+// kScanPer consecutive items): per-block sums, an exclusive scan of those sums
+// in one block, then each block's scan plus its offset.
+constexpr int kScanPer = 8;
+constexpr int kScanItems = kBlock * kScanPer;
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive(T v, T *sh, T &total) {
+  // exclusive prefix of v over the block's threads (Hillis-Steele in LDS)
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    const T add = tid >= o ? sh[tid - o] : T(0);
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  total = sh[kBlock - 1];
+  const T incl = sh[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T *__restrict__ in, long long n,
+                                                        T *__restrict__ bsum) {
+  __shared__ T sh[kBlock];
+  const long long base = (long long)blockIdx.x * kScanItems + (long long)threadIdx.x * kScanPer;
+  T v = T(0);
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q)
+    if (base + q < n) v += in[base + q];
+  T total;
+  (void)block_exclusive(v, sh, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// in place: bsum[b] <- sum of bsum[0 .. b-1]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_sums(T *__restrict__ bsum, int nb) {
+  __shared__ T sh[kBlock];
+  T carry = T(0);
+  for (int c0 = 0; c0 < nb; c0 += kBlock) {
+    const int i = c0 + (int)threadIdx.x;
+    const T v = i < nb ? bsum[i] : T(0);
+    T total;
+    const T ex = block_exclusive(v, sh, total);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += total;
+  }
+}
+
+template <typename T, bool INCLUSIVE>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const T *__restrict__ in, long long n,
+                                                      const T *__restrict__ bsum, T *__restrict__ out) {
+  __shared__ T sh[kBlock];
+  const long long base = (long long)blockIdx.x * kScanItems + (long long)threadIdx.x * kScanPer;
+  T v[kScanPer];
+  T tsum = T(0);
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = base + q < n ? in[base + q] : T(0);
+    tsum += v[q];
+  }
+  T total;
+  T run = bsum[blockIdx.x] + block_exclusive(tsum, sh, total);
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    if (INCLUSIVE) run += v[q];
+    if (base + q < n) out[base + q] = run;
+    if (!INCLUSIVE) run += v[q];
+  }
+}
+
 inline unsigned nblk(long long n) {
   long long b = (n + kBlock - 1) / kBlock;
   return (unsigned)(b > 0 ? b : 1);
+}
+
+// out = scan of in[0 .. n) (exclusive or inclusive); bs: scratch for the
+// block sums
+template <typename T, bool INCLUSIVE>
+void device_scan(const T *in, T *out, long long n, DevBuf &bs, hipStream_t st) {
+  if (n <= 0) return;
+  const long long nb = (n + kScanItems - 1) / kScanItems;
+  bs.reserve((size_t)(nb + 1) * sizeof(T));
+  T *b = (T *)bs.p;
+  k_scan_reduce<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, b);
+  k_scan_sums<T><<<1, kBlock, 0, st>>>(b, (int)nb);
+  k_scan_down<T, INCLUSIVE><<<(unsigned)nb, kBlock, 0, st>>>(in, n, b, out);
 }
 
 }  // namespace
@@ -308,34 +461,21 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   int *small = (int *)w.small.p;
   k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
                                        rk, ra, rb, small);
-  // key order, ties in record order.  Up to w.row_sort records: k0/i0 ->
-  // row buckets in k1/i1 -> ranked in k0/i0 (five launches); above, a stable
-  // radix sort k0/i0 -> k1/i1 (its passes pay off on large levels)
-  if (n > w.row_sort) {
-    size_t rbytes = 0;
-    SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, rbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
-    w.temp.reserve(rbytes);
-    SSAMG_HIP(hipcub::DeviceRadixSort::SortPairs(w.temp.p, rbytes, k0, k1, i0, i1, (int)n, 0, end_bit, st));
-  } else {
-    w.rcnt.reserve((size_t)(nc + 1) * 4);
-    w.roff.reserve((size_t)(nc + 1) * 4);
-    int *rcnt = (int *)w.rcnt.p, *roff = (int *)w.roff.p;
-    SSAMG_HIP(hipMemsetAsync(rcnt, 0, (size_t)(nc + 1) * 4, st));
-    k_row_count<<<nblk(n), kBlock, 0, st>>>(k0, n, (unsigned long long)nc, invalid, rcnt);
-    size_t tbytes = 0;
-    SSAMG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tbytes, rcnt, roff, (int)(nc + 1), st));
-    w.temp.reserve(tbytes);
-    SSAMG_HIP(hipcub::DeviceScan::ExclusiveSum(w.temp.p, tbytes, rcnt, roff, (int)(nc + 1), st));
-    k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, i0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
-    k_row_rank<<<nblk(n), kBlock, 0, st>>>(k1, i1, n, (unsigned long long)nc, invalid, roff, k0, i0);
-    std::swap(k0, k1);
-    std::swap(i0, i1);
-  }
+  // key order, ties in record order: k0/i0 -> row buckets in k1/i1 -> ranked
+  // inside each row into k0/i0 (rows of at most w.row_sort records in LDS)
+  w.rcnt.reserve((size_t)(nc + 1) * 4);
+  w.roff.reserve((size_t)(nc + 1) * 4);
+  int *rcnt = (int *)w.rcnt.p, *roff = (int *)w.roff.p;
+  SSAMG_HIP(hipMemsetAsync(rcnt, 0, (size_t)(nc + 1) * 4, st));
+  k_row_count<<<nblk(n), kBlock, 0, st>>>(k0, n, (unsigned long long)nc, invalid, rcnt);
+  device_scan<int, false>(rcnt, roff, nc + 1, w.temp, st);
+  k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, i0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
+  k_row_rank_lds<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(k1, i1, n, (unsigned long long)nc, invalid, roff,
+                                                            (int)std::min<int64_t>(w.row_sort, kRankCap), k0, i0);
+  std::swap(k0, k1);
+  std::swap(i0, i1);
   k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, flags, small);
-  size_t tbytes = 0;
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tbytes, flags, scan, (int)n, st));
-  w.temp.reserve(tbytes);
-  SSAMG_HIP(hipcub::DeviceScan::InclusiveSum(w.temp.p, tbytes, flags, scan, (int)n, st));
+  device_scan<long long, true>(flags, scan, n, w.temp, st);
   k_counts<<<1, 1, 0, st>>>(scan, small);
   SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   if (before_sync) before_sync();   // host work that overlaps the device's

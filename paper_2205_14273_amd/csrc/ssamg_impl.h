@@ -60,7 +60,9 @@ constexpr int64_t kCollapseCells = 128;
 // microseconds of host work beats the ten launches and the synchronisation
 // of the device sort
 constexpr int64_t kHostSymRecords = 16384;
-constexpr int64_t kRowSortRecords = int64_t(1) << 20;   // larger coupling products use a radix sort
+// coupling-product records of a coarse row ranked in LDS (rows with more are
+// ranked from memory); SSAMG_ROW_SORT lowers it (0: every row from memory)
+constexpr int64_t kRowSortRecords = 512;
 // levels with more than 15-point stencils and at least this many cells run the
 // first smoothing sweep and the residual as two kernels instead of one
 constexpr int64_t kSplitCells = 1 << 20;
@@ -254,7 +256,7 @@ struct LevelStore {
 struct SymScratch {
   DevBuf key0, key1, idx0, idx1, rk, ra, rb, flags, scan, small, temp, rcnt, roff;
   int *host_small = nullptr;         // pinned
-  int64_t row_sort = kRowSortRecords; // record counts up to this are ordered by row buckets
+  int64_t row_sort = kRowSortRecords; // rows of at most this many records are ranked in LDS
   ~SymScratch() {
     if (host_small) (void)hipHostFree(host_small);
   }

@@ -325,9 +325,9 @@ def test_host_formed_couplings_match_device(monkeypatch, name):
     """The coupling products of the small coarse levels are formed on the host
     (SSAMG_HOST_SYM records and below): with every level on the device, every
     level on the host and the default split, the hierarchies match the oracle
-    and the cycles are bitwise equal.  On the device the records are ordered
-    by row buckets (SSAMG_ROW_SORT records and below) or by a radix sort; both
-    give the same order."""
+    and the cycles are bitwise equal.  On the device the records of each
+    coarse row are ranked in LDS (rows of at most SSAMG_ROW_SORT records) or
+    from memory (SSAMG_ROW_SORT=0: every row); both give the same order."""
     _print_case(f"host couplings {name}")
     case = {"c2_12": lambda: W.c2(12), "c3_8": lambda: W.c3(8)}[name]()
     h = oracle_fv(case)
