@@ -432,8 +432,25 @@ class Solver:
             if not hasattr(self.params, k):
                 raise TypeError(f"unknown parameter {k}")
             setattr(self.params, k, v)
+        # the library orders its work on the stream current at creation; calls
+        # made under another stream are ordered against it both ways (_enter
+        # and _leave), so inputs produced there (fv_assemble, b) are complete
+        # before the solver reads them and outputs are ready when it resumes
+        self.stream = torch.cuda.current_stream()
         self.h = ssamg_solver_create(problem.h, self.params)
         self.ws = None
+
+    def _enter(self):
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _leave(self, cur, *outs):
+        if cur != self.stream:
+            for t in outs:
+                t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -443,25 +460,25 @@ class Solver:
 
     def setup(self):
         """Symbolic + numeric setup; the workspace is a torch uint8 tensor."""
-        ssamg_setup_symbolic(self.h)
-        nbytes = ssamg_workspace_bytes(self.h)
-        if self.ws is None or self.ws.numel() < nbytes:
-            self.ws = None
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        ssamg_setup_numeric(self.h, self.ws)
-        self.nlevels = ssamg_num_levels(self.h)
+        self.setup_symbolic()
+        self.setup_numeric()
         return self
 
     def setup_symbolic(self):
+        cur = self._enter()
         ssamg_setup_symbolic(self.h)
+        self._leave(cur)
         self.nlevels = ssamg_num_levels(self.h)
 
     def setup_numeric(self):
         nbytes = ssamg_workspace_bytes(self.h)
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = None
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            with torch.cuda.stream(self.stream):
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        cur = self._enter()
         ssamg_setup_numeric(self.h, self.ws)
+        self._leave(cur)
 
     def solve(self, b, x=None, layout=L.LAYOUT_CELL_MAJOR):
         """b: float64 device tensor, [N] or [N, nrhs] (rhs fastest) in the
@@ -474,17 +491,23 @@ class Solver:
             nrhs = int(b.shape[0] if layout == L.LAYOUT_RHS_MAJOR else b.shape[1])
         if x is None:
             x = torch.empty_like(b)
+        cur = self._enter()
         st, info = ssamg_solve(self.h, nrhs, b, x, layout)
+        self._leave(cur, b, x)
         return x, st, info
 
     def update_coeffs(self, part, vals):
         """New stencil values of one part ([nent][nz][ny][nx], same pattern: a
         CUDA float64 tensor or a host array); run setup() again before solving."""
         nent, ncell = ssamg_problem_part_size(self.problem.h, part)
+        cur = self._enter()
         if isinstance(vals, torch.Tensor) and vals.is_cuda:
-            ssamg_update_coeffs(self.h, part, vals.contiguous().reshape(-1), L.MEM_DEVICE, nent * ncell)
+            v = vals.contiguous().reshape(-1)
+            ssamg_update_coeffs(self.h, part, v, L.MEM_DEVICE, nent * ncell)
+            self._leave(cur, v)
         else:
             ssamg_update_coeffs(self.h, part, vals, L.MEM_HOST, nent * ncell)
+            self._leave(cur)
 
     def autotune(self, nrhs, cache_path=None):
         """Time and keep the fastest launch options of the batched cycle for
@@ -504,12 +527,18 @@ class Solver:
 
     def apply_A(self, level, x):
         y = torch.empty_like(x)
-        ssamg_apply_A(self.h, level, x.contiguous(), y)
+        x = x.contiguous()
+        cur = self._enter()
+        ssamg_apply_A(self.h, level, x, y)
+        self._leave(cur, x, y)
         return y
 
     def apply_precond(self, r):
         z = torch.empty_like(r)
-        ssamg_apply_precond(self.h, r.contiguous(), z)
+        r = r.contiguous()
+        cur = self._enter()
+        ssamg_apply_precond(self.h, r, z)
+        self._leave(cur, r, z)
         return z
 
     def level_info(self, level, part):

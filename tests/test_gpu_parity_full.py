@@ -293,3 +293,30 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision):
         out[v] = (x.cpu().numpy(), info.iters[0])
     assert out["1"][1] == out["0"][1]
     assert np.linalg.norm(out["1"][0] - out["0"][0]) <= 1e-9 * np.linalg.norm(out["0"][0])
+
+
+def test_calls_under_another_stream():
+    """A solver orders its work on the stream current at its creation; inputs
+    made under another stream (the assembled coefficients, b) are waited for
+    and its outputs are ready on the caller's stream: the solve equals the one
+    made on a single stream, bit for bit."""
+    from paper_2205_14273_amd.ssamg import Problem, Solver
+    _print_case("calls under another stream")
+    case = W.c2(12)
+    _, s0 = gpu_fv(case)
+    x0, st0, _ = s0.solve(_cuda(case.b))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        kappa = torch.as_tensor(case.kappa, device="cuda")
+        pr = Problem.from_fv(case.geometry, case.stencil, kappa, case.aniso)
+    s = Solver(pr)
+    with torch.cuda.stream(side):
+        s.setup()
+        b = torch.as_tensor(case.b, device="cuda")
+        x, st, _ = s.solve(b)
+        y = x * 1.0
+        z = s.apply_precond(b) * 1.0
+    torch.cuda.synchronize()
+    assert st == st0 == 0
+    assert torch.equal(y, x0)
+    assert torch.equal(z, s0.apply_precond(_cuda(case.b)))
