@@ -279,6 +279,26 @@ def main():
     if not args.no_fp64:
         log("comparison run: FP64 V-cycle (same steps)")
         fp64, x64, _, _ = run(B.L.FP64, args.steps, args.warmup)
+    per_rhs = None
+    if nrhs > 1:
+        # the same right-hand sides solved one at a time on the same hierarchy
+        # (solve only: setup is shared), against the batched solve per column
+        log(f"sequential run: the {nrhs} right-hand sides one by one (FP32 cycle)")
+        cols = [b[:, k].contiguous() for k in range(nrhs)]
+        xs = torch.empty_like(cols[0])
+        s32.solve(cols[0], xs)                      # captures the one-column graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for col in cols:
+            _, st1, inf1 = s32.solve(col, xs)
+            its.append(inf1.iters[0])
+        torch.cuda.synchronize()
+        seq = (time.perf_counter() - t0) * 1e3
+        per_rhs = {"batched_solve_ms_per_rhs": round(mixed["solve_s"] * 1e3 / nrhs, 4),
+                   "sequential_solve_ms_per_rhs": round(seq / nrhs, 4),
+                   "sequential_iters_min_max": [min(its), max(its)]}
+        log(f"  sequential: {seq:.1f} ms for {nrhs} solves ({seq / nrhs:.2f} ms each), iters {min(its)}-{max(its)}")
     roof = roofline(args.probe, probe)
     roof2 = None
     if args.probe2 != "none" and args.probe2 != args.probe:
@@ -369,6 +389,7 @@ def main():
                    "solve_s": round(mixed["solve_s"], 6), "true_relres": mixed["true_relres"],
                    "autotune_s": round(tune_s[1], 4) if 1 in tune_s else None},
         "roofline_cycle_sweep": roof2,
+        "per_rhs": per_rhs,
         "fp64_cycle": None if fp64 is None else {
             "ms_per_step": round(fp64["ms_per_step"], 4), "setup_s": round(fp64["setup_s"], 6),
             "solve_s": round(fp64["solve_s"], 6), "iters": fp64["iters"],
