@@ -70,21 +70,12 @@ __device__ int find_part(const int *geom, int nparts, int p, const int G[3], int
   return -1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *__restrict__ kappa,
-                                                       const double *__restrict__ aniso,
-                                                       double *const *__restrict__ coef) {
-  // the part's link factors and geometric weights, once per block
-  __shared__ double s_as[kMaxEnt], s_gw[kMaxEnt];
-  const int p = blockIdx.y;
-  if ((int)threadIdx.x < fa.nent) {
-    s_as[threadIdx.x] = link_factor(aniso, p, fa.code[threadIdx.x]);
-    s_gw[threadIdx.x] = geom_weight(fa.code[threadIdx.x]);
-  }
-  __syncthreads();
-  const Geo me = geo_of(fa.geom, p);
+// one cell of k_fv_stencil: its stencil row and its links' metric terms
+__device__ __forceinline__ void fv_cell(const FvArgs &fa, const double *__restrict__ kappa,
+                                        const double *__restrict__ aniso, double *const *__restrict__ coef,
+                                        const Geo &me, int p, long long c, const double *s_as,
+                                        const double *s_gw, double (&md)[3]) {
   const long long ncell = (long long)me.n[0] * me.n[1] * me.n[2];
-  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= ncell) return;
   const int i = (int)(c % me.n[0]);
   const int j = (int)((c / me.n[0]) % me.n[1]);
   const int k = (int)(c / ((long long)me.n[0] * me.n[1]));
@@ -111,6 +102,9 @@ __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *
       const double xj = as * kp[c + oc(code, 0) + sy * oc(code, 1) + sz * oc(code, 2)];
       t = gw * 2.0 * xi * xj / (xi + xj);
       v = -t;
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (oc(code, q) != 0) md[q] += t;
     } else {
       const int G[3] = {me.o[0] + nb[0], me.o[1] + nb[1], me.o[2] + nb[2]};
       int cell = 0;
@@ -126,6 +120,38 @@ __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *
     cf[(long long)s * ncell + c] = v;
   }
   cf[c] = diag;   // entry 0 is the center
+}
+
+// Also the block's partial sums of the direction metric c_d of Section 3.1
+// (minus the off-diagonal same-part coefficients with a nonzero d component,
+// the center being positive): the conductance of every same-part link, per
+// direction its offset has; [part][block][3], reduced as k_wsum_partial's.
+__global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *__restrict__ kappa,
+                                                       const double *__restrict__ aniso,
+                                                       double *const *__restrict__ coef,
+                                                       double *__restrict__ mpart) {
+  // the part's link factors and geometric weights, once per block
+  __shared__ double s_as[kMaxEnt], s_gw[kMaxEnt];
+  __shared__ double sh[3][kBlock];
+  const int p = blockIdx.y;
+  if ((int)threadIdx.x < fa.nent) {
+    s_as[threadIdx.x] = link_factor(aniso, p, fa.code[threadIdx.x]);
+    s_gw[threadIdx.x] = geom_weight(fa.code[threadIdx.x]);
+  }
+  __syncthreads();
+  const Geo me = geo_of(fa.geom, p);
+  const long long ncell = (long long)me.n[0] * me.n[1] * me.n[2];
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double md[3] = {0.0, 0.0, 0.0};
+  if (c < ncell) fv_cell(fa, kappa, aniso, coef, me, p, c, s_as, s_gw, md);
+  for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = md[q];
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) mpart[((long long)p * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(kBlock) void k_fv_coupling(int nrow, const int *__restrict__ urow,
@@ -238,8 +264,8 @@ inline unsigned nblk(long long n) {
 }  // namespace
 
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
-                       double *const *coef, hipStream_t st) {
-  k_fv_stencil<<<dim3(nblk(maxcell), fa.nparts), kBlock, 0, st>>>(fa, kappa, aniso, coef);
+                       double *const *coef, double *mpart, hipStream_t st) {
+  k_fv_stencil<<<dim3(fv_blocks(maxcell), fa.nparts), kBlock, 0, st>>>(fa, kappa, aniso, coef, mpart);
 }
 
 void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *ucol,

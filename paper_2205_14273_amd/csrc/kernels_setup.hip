@@ -784,6 +784,10 @@ void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *
   k_wsum_final<<<nparts, kBlock, 0, st>>>(partial, (int)nb, out);
 }
 
+void launch_wsum_final(const double *partial, int nparts, int nblk, double *out, hipStream_t st) {
+  k_wsum_final<<<nparts, kBlock, 0, st>>>(partial, nblk, out);
+}
+
 void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
                            int maxf, int *flag, hipStream_t st) {
   k_interp_weights<<<dim3(nblk(maxf), nparts), kBlock, 0, st>>>(desc, desc32, flag);

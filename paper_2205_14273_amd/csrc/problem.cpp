@@ -37,8 +37,11 @@ void Problem::free_device() {
     c = nullptr;
   }
   for (void *p : {(void *)d_urow, (void *)d_uptr, (void *)d_ucol, (void *)d_uval, (void *)d_kappa,
-                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom, (void *)d_cptr})
+                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom, (void *)d_cptr, (void *)d_mpart})
     if (p) (void)hipFree(p);
+  d_mpart = nullptr;
+  mpart_cap = 0;
+  metric_version = 0;
   d_urow = d_uptr = d_ucol = d_ucode = d_geom = nullptr;
   d_cptr = nullptr;
   fv_structure_ready = false;
@@ -317,6 +320,7 @@ ssamg_status ssamg_problem_set_box(ssamg_problem prob, int part, const int lo[3]
     if (pr->coef[part]) (void)hipFree(pr->coef[part]);
     pr->coef[part] = nullptr;
     pr->coef_set[part] = 0;
+    pr->coef_version++;
     pr->fv_structure_ready = false;
   }
   API_END
@@ -348,6 +352,7 @@ ssamg_status ssamg_problem_set_face(ssamg_problem prob, int part, int face, int 
 // they reach: topology changes ask for the coefficients again
 static void topology_changed(Problem *pr) {
   for (int p = 0; p < pr->nparts; ++p) pr->coef_set[p] = 0;
+  pr->coef_version++;
   pr->fv_structure_ready = false;
 }
 
@@ -427,6 +432,7 @@ ssamg_status ssamg_problem_set_stencil(ssamg_problem prob, int part, int nent, c
     if (pr->coef[part]) (void)hipFree(pr->coef[part]);
     pr->coef[part] = nullptr;
     pr->coef_set[part] = 0;
+    pr->coef_version++;
     pr->fv_structure_ready = false;
   }
   API_END
@@ -508,6 +514,7 @@ ssamg_status ssamg_problem_set_coeffs(ssamg_problem prob, int part, const double
   (void)hipFree(flag);
   SSAMG_HIP(hipGetLastError());
   pr->coef_set[part] = 1;
+  pr->coef_version++;
   pr->sym_ok[part] = hflag[1] == 0;
   pr->fv_structure_ready = false;
   if (hflag[0]) throw Error(SSAMG_ERR_NUMERIC, "nonpositive diagonal or non-finite coefficient");
@@ -734,11 +741,22 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
   fa.nparts = pr->nparts;
   fa.nent = nent;
   for (int e = 0; e < nent; ++e) fa.code[e] = pack_off(st_off[e][0], st_off[e][1], st_off[e][2]);
-  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, pr->d_cptr, st);
+  const size_t mbytes = (size_t)pr->nparts * fv_blocks((int)maxcell) * 3 * sizeof(double);
+  if (pr->mpart_cap < mbytes) {
+    if (pr->d_mpart) (void)hipFree(pr->d_mpart);
+    pr->d_mpart = nullptr;
+    pr->mpart_cap = 0;
+    pr->d_mpart = dev_alloc<double>(mbytes / sizeof(double));
+    pr->mpart_cap = mbytes;
+  }
+  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, pr->d_cptr, pr->d_mpart, st);
   launch_fv_coupling((int)pr->urow.size(), pr->d_urow, pr->d_uptr, pr->d_ucol, pr->d_ucode,
                      pr->d_kappa, pr->d_aniso, pr->d_uval, st);
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(st));
+  pr->coef_version++;
+  pr->metric_version = pr->coef_version;
+  pr->mpart_nb = fv_blocks((int)maxcell);
   API_END
 }
 

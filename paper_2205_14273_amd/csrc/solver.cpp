@@ -743,8 +743,13 @@ void setup_symbolic(Solver &s) {
     PartDesc<double> *dd = (PartDesc<double> *)base;
     double *part = (double *)(base + align_up(np * sizeof(PartDesc<double>)));
     double *out = part + (size_t)np * 256 * 3;
-    SSAMG_HIP(hipMemcpyAsync(dd, hd.data(), np * sizeof(PartDesc<double>), hipMemcpyHostToDevice, s.stream));
-    launch_wsum(dd, np, maxcell, part, out, s.stream);
+    if (pr.d_mpart && pr.metric_version == pr.coef_version) {
+      // the finite-volume assembly formed the partial sums with the coefficients
+      launch_wsum_final(pr.d_mpart, np, pr.mpart_nb, out, s.stream);
+    } else {
+      SSAMG_HIP(hipMemcpyAsync(dd, hd.data(), np * sizeof(PartDesc<double>), hipMemcpyHostToDevice, s.stream));
+      launch_wsum(dd, np, maxcell, part, out, s.stream);
+    }
     SSAMG_HIP(hipGetLastError());
     s.cd.assign((size_t)np * 3, 0.0);
     SSAMG_HIP(hipMemcpyAsync(s.cd.data(), out, np * 3 * sizeof(double), hipMemcpyDeviceToHost, s.stream));

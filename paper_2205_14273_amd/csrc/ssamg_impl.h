@@ -160,6 +160,14 @@ struct Problem {
   std::vector<int> center;
   std::vector<double *> coef;        // device [nent][ncell] per part, problem-owned
   std::vector<int> coef_set;
+  // every change of coefficients bumps coef_version; finite-volume assembly
+  // also leaves the per-block partial sums of the direction metric c_d
+  // (Section 3.1; [part][block][3], mpart_nb blocks per part), valid while
+  // metric_version == coef_version
+  uint64_t coef_version = 1, metric_version = 0;
+  double *d_mpart = nullptr;
+  size_t mpart_cap = 0;
+  int mpart_nb = 0;
   // 1: the part's given coefficients satisfy a_s(c) = a_{-s}(c+s) to a relative
   // 1e-12 (checked by set_coeffs; finite-volume assembly is symmetric)
   std::vector<int> sym_ok;
@@ -444,6 +452,9 @@ struct RapDesc {
   int cofs[27];        // offset of each coarse entry
 };
 
+// blocks per part of the finite-volume stencil kernel (its metric partials)
+inline int fv_blocks(int maxcell) { return (maxcell + kBlock - 1) / kBlock > 0 ? (maxcell + kBlock - 1) / kBlock : 1; }
+
 // finite-volume assembly arguments
 struct FvArgs {
   const int *geom;     // per part: origin[3], dims[3], cell offset
@@ -572,6 +583,8 @@ void launch_resid_norm(const double *b, const double *ax, int64_t nel, int lg, d
 void launch_normalise(const BoxStencil &bs, int *flag, hipStream_t st);
 void launch_wsum(const PartDesc<double> *desc, int nparts, int maxcell, double *partial, double *out,
                  hipStream_t st);
+// c_d from per-block partial sums [part][nblk][3] (those of fv_assemble)
+void launch_wsum_final(const double *partial, int nparts, int nblk, double *out, hipStream_t st);
 void launch_interp_weights(const PartDesc<double> *desc, const PartDesc<float> *desc32, int nparts,
                            int maxf, int *flag, hipStream_t st);
 // one thread per coarse cell when the level has at least cell_min coarse cells
@@ -625,7 +638,7 @@ void launch_dense_apply(const double *m, int64_t n, int lg, const T *vb, T *vt, 
 
 // kernels_fv.hip
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
-                       double *const *coef, hipStream_t st);
+                       double *const *coef, double *mpart, hipStream_t st);
 void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *ucol,
                         const int *ucode, const double *kappa, const double *aniso, double *uval,
                         hipStream_t st);
