@@ -165,8 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_fv_coupling(int nrow, const int *__r
   if (r >= nrow) return;
   const int i = urow[r];
   for (int q = uptr[r]; q < uptr[r + 1]; ++q) {
-    const int w = ucode[q];
-    const int code = w & 31, pi = (w >> 5) & 8191, pj = (w >> 18) & 8191;
+    const unsigned w = (unsigned)ucode[q];   // offset (6 bits), row part, column part (13 bits each)
+    const int code = (int)(w & 63u), pi = (int)((w >> 6) & 8191u), pj = (int)((w >> 19) & 8191u);
     const double xi = link_factor(aniso, pi, code) * kappa[i];
     const double xj = link_factor(aniso, pj, code) * kappa[ucol[q]];
     uval[q] = -geom_weight(code) * 2.0 * xi * xj / (xi + xj);
@@ -244,8 +244,8 @@ __global__ __launch_bounds__(kBlock) void k_fv_grad_u(int nrow, const int *__res
   const int i = urow[r];
   double acc = 0.0;
   for (int q = uptr[r]; q < uptr[r + 1]; ++q) {
-    const int w = ucode[q];
-    const int code = w & 31, pi = (w >> 5) & 8191, pj = (w >> 18) & 8191;
+    const unsigned w = (unsigned)ucode[q];   // offset (6 bits), row part, column part (13 bits each)
+    const int code = (int)(w & 63u), pi = (int)((w >> 6) & 8191u), pj = (int)((w >> 19) & 8191u);
     const int j = ucol[q];
     const double ai = link_factor(aniso, pi, code);
     const double xi = ai * kappa[i];

@@ -686,7 +686,9 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
                 const int64_t jid = off[q] + (G[0] - h[0]) + (int64_t)m[0] * ((G[1] - h[1]) + (int64_t)m[1] * (G[2] - h[2]));
                 crow.push_back(off[p] + i + (int64_t)n[0] * (j + (int64_t)n[1] * k));
                 ccol.push_back(jid);
-                ccode_raw.push_back(pack_off(st_off[e][0], st_off[e][1], st_off[e][2]) | (p << 5) | (q << 18));
+                // link code: offset (6 bits), row part, column part (13 bits each)
+                ccode_raw.push_back((int)((unsigned)pack_off(st_off[e][0], st_off[e][1], st_off[e][2]) |
+                                          ((unsigned)p << 6) | ((unsigned)q << 19)));
                 break;
               }
             }

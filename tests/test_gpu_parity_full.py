@@ -268,17 +268,34 @@ def test_binding_rejects_bad_vectors():
         s.apply_precond(good.float())
 
 
+def _odd_chunks_case():
+    """27-point, two parts of 10 x 10 x 6 (600 cells: three 256-cell chunks, so
+    the two-cell kernels' last block holds a chunk the one-cell grid lacks)
+    and one of 6 x 10 x 6, heterogeneous kappa and a different anisotropy per
+    part (which the cross-part conductances of the 27-point stencil read by
+    part index: an odd number of parts and links with dz = +1 once decoded a
+    wrong part there)."""
+    g = W.Geometry(3, [(10, 10, 6), (10, 10, 6), (6, 10, 6)], [(0, 0, 0), (10, 0, 0), (20, 0, 0)])
+    rng = np.random.default_rng(77)
+    kappa = np.exp(rng.standard_normal(g.n))
+    b = rng.uniform(-1, 1, g.n)
+    aniso = np.array([[1.0, 2.0, 3.0], [2.0, 1.0, 1.0], [1.0, 1.0, 4.0]])
+    return W.FVCase("odd", g, 27, kappa, aniso, b, relax="l1")
+
+
 @pytest.mark.parametrize("precision", [0, 1])
-def test_multi_cell_product_and_sweeps(monkeypatch, precision):
+@pytest.mark.parametrize("name", ["c3_10", "odd"])
+def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
     """Full 27-point levels with even rows run the PCG product two cells per
     thread and, in the FP64 cycle, the finest residual and post-sweep two cells
     per thread: the cycle matches the oracle entry by entry, the solve reaches
     the tolerance with the oracle's iterations (the true residual is formed by
     the one-cell product), and it equals the one-cell kernels' solve to
     rounding."""
-    _print_case(f"multi-cell kernels c3_10 precision={precision}")
-    case = W.c3(10)
+    _print_case(f"multi-cell kernels {name} precision={precision}")
+    case = W.c3(10) if name == "c3_10" else _odd_chunks_case()
     h = oracle_fv(case)
+    compare_hierarchy(h, gpu_fv(case)[1], case.geometry.nparts)
     b = case.b
     ref = O.solve(h, b, tol=1e-8, flexible=(precision == 1))
     out = {}
