@@ -1,7 +1,8 @@
 """Adjoint gradient of L(x(kappa)) = 1/2 ||x - x_t||^2 with x = A(kappa)^{-1} b.
 
 * the library's fv_grad kernels against the oracle's gradient formula on the
-  same seeded (lambda, x) - 7- and 27-point, several parts, 2D;
+  same seeded (lambda, x) - 7- and 27-point, several parts, a different
+  anisotropy per part, 2D;
 * the autograd function end to end against the oracle (exact sparse solves,
   oracle assembly and gradient) on small problems;
 * the adjoint gradient against central finite differences of L on sampled
@@ -33,7 +34,17 @@ def _fv_case(name):
         "c3_6": lambda: W.c3(6),
         "c2_9": lambda: W.c2(9),
         "2d": _case_2d,
+        "odd27": _case_odd27,
     }[name]()
+
+
+def _case_odd27():
+    """27-point, three parts of different sizes along x, a different
+    anisotropy per part (cross-part conductances read it by part index)."""
+    g = W.geometry_along_x(3, [(5, 4, 3), (5, 4, 3), (3, 4, 3)])
+    kappa = np.exp(np.random.default_rng(78).standard_normal(g.n))
+    aniso = np.array([[1.0, 2.0, 3.0], [2.0, 1.0, 1.0], [1.0, 1.0, 4.0]])
+    return W.FVCase("odd27", g, 27, kappa, aniso, np.zeros(g.n))
 
 
 def _case_2d():
@@ -43,7 +54,7 @@ def _case_2d():
                     np.zeros(g.n))
 
 
-@pytest.mark.parametrize("name", ["c5_7", "c3_6", "c2_9", "2d"])
+@pytest.mark.parametrize("name", ["c5_7", "c3_6", "c2_9", "2d", "odd27"])
 def test_fv_grad_kernel_parity(name):
     _print_case(name)
     from paper_2205_14273_amd.ssamg import Problem
