@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--coarse-op", default="galerkin", choices=["galerkin", "nongalerkin"],
                     help="coarse stencils of 7-point parts: Galerkin (default) or the non-Galerkin "
                          "option for isotropic problems")
+    ap.add_argument("--skip", action="store_true",
+                    help="the skip option of Section 3.4 (no relaxation where a part coarsens along the "
+                         "same direction as ndim levels above)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -168,6 +171,8 @@ def main():
             params["hybrid_level"] = args.hybrid_level
         if args.coarse_op == "nongalerkin":
             params["coarse_op"] = B.L.COARSE_OP_NONGALERKIN
+        if args.skip:
+            params["skip"] = 1
         pr.fv_assemble(kappa, aniso, case.stencil)
         s = B.Solver(pr, **params)
         return pr, s
@@ -332,7 +337,7 @@ def main():
         A, _ = assemble.assemble_fv(sg, sample_case.stencil, sample_case.kappa, sample_case.aniso)
         h = O.setup(A, sg.dims, sg.face_kinds(), [W.stencil_offsets(sample_case.stencil, sg.ndim)]
                     * sg.nparts, sg.ndim, omega=sample_case.omega, relax=sample_case.relax,
-                    hybrid_level=args.hybrid_level, coarse_op=args.coarse_op)
+                    hybrid_level=args.hybrid_level, coarse_op=args.coarse_op, skip=args.skip)
         ts = time.perf_counter()
         bb = sample_case.b if sample_case.b.ndim == 1 else sample_case.b[0]
         ref = O.solve(h, bb, tol=sample_case.tol, max_iter=sample_case.max_iter)
@@ -380,7 +385,8 @@ def main():
         "config": {"workload": f"{args.config}: {DESCR[args.config]}; FP32 V(1,1) cycle in FP64 PCG, "
                                f"tol {case.tol}"
                                + (f"; hybrid tail at level {args.hybrid_level}" if args.hybrid_level else "")
-                               + ("; non-Galerkin coarse stencils" if args.coarse_op == "nongalerkin" else ""),
+                               + ("; non-Galerkin coarse stencils" if args.coarse_op == "nongalerkin" else "")
+                               + ("; skip option" if args.skip else ""),
                    "cells": N, "nrhs": nrhs,
                    "levels": mixed["levels"], "iters": mixed["iters"],
                    "assemble_s": round(mixed["assemble_s"], 6), "setup_s": round(mixed["setup_s"], 6),
