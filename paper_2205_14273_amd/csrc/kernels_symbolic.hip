@@ -73,10 +73,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp,
                                                  unsigned long long nc, unsigned long long invalid,
                                                  unsigned long long *__restrict__ key,
                                                  unsigned *__restrict__ idx, int *__restrict__ rk,
-                                                 int *__restrict__ ra, int *__restrict__ rb,
-                                                 int *__restrict__ small) {
+                                                 int *__restrict__ ra, int *__restrict__ rb) {
   const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (q < 4) small[q] = 0;   // counts of k_flags / k_counts start at zero
   if (q >= nnz) return;
   int cf[2], sf[2], cg[2], sg[2];
   const int nf = prow(sp, np, erow[q], cf, sf);
@@ -160,36 +158,23 @@ __global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long
   ti[pos] = idx[i];
 }
 
-// after the sort: flags of records that open a coarse entry / a coarse row,
-// and the count of valid records (invalid keys sort last)
-// packed flags: bit 0 a record that opens a coarse entry, bit 32 one that
-// opens a coarse row (one 64-bit scan then counts both)
-__global__ __launch_bounds__(kBlock) void k_flags(const unsigned long long *__restrict__ key,
-                                                  long long n, unsigned long long nc,
-                                                  unsigned long long invalid,
-                                                  long long *__restrict__ flags, int *__restrict__ small) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const bool v = key[i] != invalid;
-  const long long fnew = v && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
-  const long long frow = v && (i == 0 || key[i] / nc != key[i - 1] / nc) ? 1 : 0;
-  flags[i] = fnew | (frow << 32);
-  if (v && (i == n - 1 || key[i + 1] == invalid)) small[0] = (int)(i + 1);
-}
-
-// entry and row counts from the inclusive scan of the packed flags
-__global__ void k_counts(const long long *__restrict__ scan, int *__restrict__ small) {
-  const int nvalid = small[0];
-  small[1] = nvalid > 0 ? (int)(scan[nvalid - 1] & 0xffffffffLL) : 0;
-  small[2] = nvalid > 0 ? (int)(scan[nvalid - 1] >> 32) : 0;
+// sizes after the row scan (exclusive over nc + 1 rows): valid records,
+// coarse entries, coarse rows
+__global__ void k_counts(const int *__restrict__ roff, const long long *__restrict__ rscan,
+                         unsigned long long nc, int *__restrict__ small) {
+  small[0] = roff[nc];
+  small[1] = (int)(rscan[nc] & 0xffffffffLL);
+  small[2] = (int)(rscan[nc] >> 32);
 }
 
 // coarse entries (column, row), rows (cell, first entry) and the
-// contributions in sorted order
+// contributions in sorted order; rscan[r] = first entry | row number << 32
 __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__restrict__ key,
                                                  const unsigned *__restrict__ idx,
-                                                 const long long *__restrict__ flags,
-                                                 const long long *__restrict__ scan, long long nvalid,
+                                                 const int *__restrict__ ent,
+                                                 const int *__restrict__ roff,
+                                                 const long long *__restrict__ rscan, long long nvalid,
+                                                 long long nent, long long nrow,
                                                  unsigned long long nc, const int *__restrict__ rk,
                                                  const int *__restrict__ ra,
                                                  const int *__restrict__ rb, int *__restrict__ ucol,
@@ -203,20 +188,24 @@ __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__res
   ck[i] = rk[s];
   ca[i] = ra[s];
   cb[i] = rb[s];
-  const long long f = flags[i], sc = scan[i];
-  const int e = (int)(sc & 0xffffffffLL) - 1, rid = (int)(sc >> 32);
-  if (f & 1) {
-    ucol[e] = (int)(key[i] % nc);
-    erow[e] = (int)(key[i] / nc);
-    start[e] = (int)i;
+  const unsigned long long k = key[i];
+  const long long r = (long long)(k / nc);
+  const long long rs = rscan[r];
+  const int e0 = (int)(rs & 0xffffffffLL), rid = (int)(rs >> 32);
+  const int en = ent[i];
+  const bool rowstart = roff[r] == i;
+  if (rowstart || ent[i - 1] != en) {                     // first record of a coarse entry
+    ucol[e0 + en] = (int)(k % nc);
+    erow[e0 + en] = (int)r;
+    start[e0 + en] = (int)i;
   }
-  if (f >> 32) {
-    urow[rid - 1] = (int)(key[i] / nc);
-    uptr[rid - 1] = e;
+  if (rowstart) {
+    urow[rid] = (int)r;
+    uptr[rid] = e0;
   }
   if (i == nvalid - 1) {
-    start[e + 1] = (int)nvalid;
-    uptr[rid] = e + 1;
+    start[nent] = (int)nvalid;
+    uptr[nrow] = (int)nent;
   }
 }
 
@@ -258,16 +247,22 @@ __global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp,
 // chunk of 64 sorted positions: the wave takes each row that starts in its
 // chunk and every lane counts, for its records, the smaller ones.  Inside a
 // row every key has the same coarse row, so (column, record index) packed in
-// 64 bits orders it; rows of at most cap records are staged in LDS that way
-// (else read from memory).  The same positions as a stable sort.
+// 64 bits orders it; rows of at most cap records are staged and ordered in
+// LDS that way (else read from and ordered in memory).  The same positions as
+// a stable sort.  A scan over the ordered row then numbers its distinct
+// columns (the coarse entries): ent[i] is record i's entry inside its row, and
+// rowinfo[r] = entry count | 1 << 32 for a row with records, whose scan over
+// the rows gives every row's first entry and its row number.
 constexpr int kRankCap = 512;
 __global__ __launch_bounds__(64) void k_row_rank_lds(const unsigned long long *__restrict__ tk,
                                                      const unsigned *__restrict__ ti, long long n,
                                                      unsigned long long nc, unsigned long long invalid,
                                                      const int *__restrict__ roff, int cap,
                                                      unsigned long long *__restrict__ key,
-                                                     unsigned *__restrict__ idx) {
+                                                     unsigned *__restrict__ idx, int *__restrict__ ent,
+                                                     long long *__restrict__ rowinfo) {
   __shared__ unsigned long long sv[kRankCap];
+  __shared__ unsigned long long ss[kRankCap];
   const int lane = threadIdx.x;
   const long long p = (long long)blockIdx.x * 64 + lane;
   const long long total = roff[nc];
@@ -286,22 +281,19 @@ __global__ __launch_bounds__(64) void k_row_rank_lds(const unsigned long long *_
     const int b = roff[r], e = roff[r + 1], len = e - b;
     const unsigned long long rbase = (unsigned long long)r * nc;
     auto packed = [&](int q) { return ((tk[q] - rbase) << 32) | ti[q]; };
-    if (len <= cap) {
+    const bool lds = len <= cap;
+    if (lds) {
       for (int q = lane; q < len; q += 64) sv[q] = packed(b + q);
       __syncthreads();
       for (int q = lane; q < len; q += 64) {
         const unsigned long long v = sv[q];
         int rank = 0;
         int j = 0;
-        for (; j + 4 <= len; j += 4) {
-          const unsigned long long w0 = sv[j], w1 = sv[j + 1], w2 = sv[j + 2], w3 = sv[j + 3];
-          rank += (w0 < v) + (w1 < v) + (w2 < v) + (w3 < v);
-        }
+        for (; j + 4 <= len; j += 4)
+          rank += (sv[j] < v) + (sv[j + 1] < v) + (sv[j + 2] < v) + (sv[j + 3] < v);
         for (; j < len; ++j) rank += sv[j] < v;
-        key[b + rank] = rbase + (v >> 32);
-        idx[b + rank] = (unsigned)v;
+        ss[rank] = v;
       }
-      __syncthreads();
     } else {
       for (int q = lane; q < len; q += 64) {
         const unsigned long long v = packed(b + q);
@@ -311,6 +303,30 @@ __global__ __launch_bounds__(64) void k_row_rank_lds(const unsigned long long *_
         idx[b + rank] = (unsigned)v;
       }
     }
+    __syncthreads();
+    // number the distinct columns in order (a wave scan per 64 positions)
+    auto col = [&](int q) { return lds ? ss[q] >> 32 : key[b + q] - rbase; };
+    int carry = 0;
+    for (int q0 = 0; q0 < len; q0 += 64) {                 // wave-uniform
+      const int q = q0 + lane;
+      int f = 0;
+      if (q < len) f = q == 0 || col(q) != col(q - 1);
+      int sc = f;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(sc, o, 64);
+        if (lane >= o) sc += t;
+      }
+      if (q < len) {
+        if (lds) {
+          key[b + q] = rbase + (ss[q] >> 32);
+          idx[b + q] = (unsigned)ss[q];
+        }
+        ent[b + q] = carry + sc - 1;
+      }
+      carry += __shfl(sc, 63, 64);
+    }
+    if (lane == 0) rowinfo[r] = (long long)carry | (1LL << 32);
+    __syncthreads();
   }
 }
 
@@ -446,8 +462,7 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   w.rk.reserve(n * 4);
   w.ra.reserve(n * 4);
   w.rb.reserve(n * 4);
-  w.flags.reserve(n * 8);
-  w.scan.reserve(n * 8);
+  w.ent.reserve(n * 4);
   w.small.reserve(64);
   if (!w.host_small) {
     void *h = nullptr;
@@ -457,10 +472,10 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   auto *k0 = (unsigned long long *)w.key0.p, *k1 = (unsigned long long *)w.key1.p;
   auto *i0 = (unsigned *)w.idx0.p, *i1 = (unsigned *)w.idx1.p;
   int *rk = (int *)w.rk.p, *ra = (int *)w.ra.p, *rb = (int *)w.rb.p;
-  long long *flags = (long long *)w.flags.p, *scan = (long long *)w.scan.p;
+  int *ent = (int *)w.ent.p;
   int *small = (int *)w.small.p;
   k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
-                                       rk, ra, rb, small);
+                                       rk, ra, rb);
   // key order, ties in record order: k0/i0 -> row buckets in k1/i1 -> ranked
   // inside each row into k0/i0 (rows of at most w.row_sort records in LDS)
   w.rcnt.reserve((size_t)(nc + 1) * 4);
@@ -470,13 +485,17 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   k_row_count<<<nblk(n), kBlock, 0, st>>>(k0, n, (unsigned long long)nc, invalid, rcnt);
   device_scan<int, false>(rcnt, roff, nc + 1, w.temp, st);
   k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, i0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
+  w.rinfo.reserve((size_t)(nc + 1) * 8);
+  w.rscan.reserve((size_t)(nc + 1) * 8);
+  long long *rinfo = (long long *)w.rinfo.p, *rscan = (long long *)w.rscan.p;
+  SSAMG_HIP(hipMemsetAsync(rinfo, 0, (size_t)(nc + 1) * 8, st));
   k_row_rank_lds<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(k1, i1, n, (unsigned long long)nc, invalid, roff,
-                                                            (int)std::min<int64_t>(w.row_sort, kRankCap), k0, i0);
+                                                            (int)std::min<int64_t>(w.row_sort, kRankCap), k0, i0,
+                                                            ent, rinfo);
   std::swap(k0, k1);
   std::swap(i0, i1);
-  k_flags<<<nblk(n), kBlock, 0, st>>>(k1, n, (unsigned long long)nc, invalid, flags, small);
-  device_scan<long long, true>(flags, scan, n, w.temp, st);
-  k_counts<<<1, 1, 0, st>>>(scan, small);
+  device_scan<long long, false>(rinfo, rscan, nc + 1, w.temp, st);
+  k_counts<<<1, 1, 0, st>>>(roff, rscan, (unsigned long long)nc, small);
   SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   if (before_sync) before_sync();   // host work that overlaps the device's
   SSAMG_HIP(hipStreamSynchronize(st));
@@ -490,7 +509,7 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   out.ck.reserve((size_t)nvalid * 4);
   out.ca.reserve((size_t)nvalid * 4);
   out.cb.reserve((size_t)nvalid * 4);
-  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, flags, scan, nvalid, (unsigned long long)nc,
+  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, ent, roff, rscan, nvalid, nent, nr, (unsigned long long)nc,
                                           rk, ra, rb, (int *)out.ucol.p, (int *)out.erow.p,
                                           (int *)out.start.p, (int *)out.urow.p, (int *)out.uptr.p,
                                           (int *)out.ck.p, (int *)out.ca.p, (int *)out.cb.p);

@@ -262,7 +262,7 @@ struct LevelStore {
 
 // Scratch of the device sort.
 struct SymScratch {
-  DevBuf key0, key1, idx0, idx1, rk, ra, rb, flags, scan, small, temp, rcnt, roff;
+  DevBuf key0, key1, idx0, idx1, rk, ra, rb, ent, small, temp, rcnt, roff, rinfo, rscan;
   int *host_small = nullptr;         // pinned
   int64_t row_sort = kRowSortRecords; // rows of at most this many records are ranked in LDS
   ~SymScratch() {
