@@ -8,9 +8,9 @@
 // the coarse pair (I, J).  The records are put in key order with ties in
 // emission order (row-major over U_l, the order of a stable sort), so the
 // numeric pass sums each entry in a fixed order: counted into coarse-row
-// buckets, scattered, and ranked inside each row.  Runs of equal keys are the
-// coarse entries; runs of equal I are the stored rows.  All scans are the
-// three-pass block scans below.
+// buckets (as they are emitted), scattered, and ranked inside each row, which
+// also numbers the row's entries.  Runs of equal keys are the coarse entries;
+// runs of equal I are the stored rows.  All scans are the block scans below.
 #include "ssamg_impl.h"
 
 namespace ssamg {
@@ -66,38 +66,67 @@ __device__ int prow(const SymPart *sp, int np, long long cell, int col[2], int s
   return 1;
 }
 
-// one thread per entry q of U_l (row cell erow[q]); its records sit at 4q .. 4q+3
+// The lanes of a wave with the same coarse row r >= 0 form a group: one lane
+// of each group calls f(r, group mask, leader lane); wave-uniform loop
+template <typename F>
+__device__ __forceinline__ void wave_groups(int r, F &&f) {
+  unsigned long long pending = __ballot(r >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int val = __shfl(r, leader, 64);
+    const unsigned long long same = __ballot(r == val) & pending;
+    f(val, same, leader);
+    pending &= ~same;
+  }
+}
+
+// one thread per entry q of U_l (row cell erow[q]); its records sit at
+// 4q .. 4q+3.  The valid records are counted into their coarse rows' buckets
+// (cnt, zero on entry), a wave's records with the same row with one atomic.
 __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp, int np, long long nnz,
                                                  const int *__restrict__ erow,
                                                  const int *__restrict__ ucol,
                                                  unsigned long long nc, unsigned long long invalid,
                                                  unsigned long long *__restrict__ key,
                                                  unsigned *__restrict__ idx, int *__restrict__ rk,
-                                                 int *__restrict__ ra, int *__restrict__ rb) {
+                                                 int *__restrict__ ra, int *__restrict__ rb,
+                                                 int *__restrict__ cnt) {
   const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (q >= nnz) return;
-  int cf[2], sf[2], cg[2], sg[2];
-  const int nf = prow(sp, np, erow[q], cf, sf);
-  const int ng = prow(sp, np, ucol[q], cg, sg);
+  const int lane = threadIdx.x & 63;
+  int cf[2] = {-1, -1}, sf[2], cg[2], sg[2];
+  int nf = 0, ng = 0;
+  if (q < nnz) {
+    nf = prow(sp, np, erow[q], cf, sf);
+    ng = prow(sp, np, ucol[q], cg, sg);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const long long i = 4LL * q + t;
-    const int a = t >> 1, b = t & 1;
-    idx[i] = (unsigned)i;
-    if (a < nf && b < ng) {
-      key[i] = (unsigned long long)cf[a] * nc + (unsigned long long)cg[b];
-      rk[i] = (int)q;
-      ra[i] = sf[a];
-      rb[i] = sg[b];
-    } else {
-      key[i] = invalid;
-      rk[i] = ra[i] = rb[i] = 0;
+    for (int t = 0; t < 4; ++t) {
+      const long long i = 4LL * q + t;
+      const int a = t >> 1, b = t & 1;
+      idx[i] = (unsigned)i;
+      if (a < nf && b < ng) {
+        key[i] = (unsigned long long)cf[a] * nc + (unsigned long long)cg[b];
+        rk[i] = (int)q;
+        ra[i] = sf[a];
+        rb[i] = sg[b];
+      } else {
+        key[i] = invalid;
+        rk[i] = ra[i] = rb[i] = 0;
+      }
     }
+  }
+  // coarse row cf[a] takes ng valid records of this entry (one or two)
+  const unsigned long long two = __ballot(ng == 2);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int r = a < nf && ng > 0 ? cf[a] : -1;
+    wave_groups(r, [&](int val, unsigned long long same, int leader) {
+      if (lane == leader) atomicAdd(&cnt[val], __popcll(same) + __popcll(same & two));
+    });
   }
 }
 
 // The records in key order, ties in record order (the order of a stable sort):
-// count the valid records of every coarse row, scan the counts into row
+// count the valid records of every coarse row (k_emit), scan the counts into row
 // offsets, scatter every valid record into its row's range (any order), then
 // place each at its row offset plus its rank among the row's records by
 // (key, record index).  Positions past the valid records get the invalid key.
@@ -113,21 +142,6 @@ __device__ __forceinline__ int rec_row(const unsigned long long *__restrict__ ke
   return k != invalid ? (int)(k / nc) : -1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_row_count(const unsigned long long *__restrict__ key, long long n,
-                                                      unsigned long long nc, unsigned long long invalid,
-                                                      int *__restrict__ cnt) {
-  const int r = rec_row(key, n, nc, invalid);
-  const int lane = threadIdx.x & 63;
-  unsigned long long pending = __ballot(r >= 0);
-  while (pending) {                                        // wave-uniform
-    const int leader = __ffsll((long long)pending) - 1;
-    const int val = __shfl(r, leader, 64);
-    const unsigned long long same = __ballot(r == val) & pending;
-    if (lane == leader) atomicAdd(&cnt[val], __popcll(same));
-    pending &= ~same;
-  }
-}
-
 // cnt holds the row counts on entry and zeros on exit; a group takes
 // consecutive slots of its row's range
 __global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long *__restrict__ key,
@@ -140,31 +154,17 @@ __global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ULL << lane) - 1;
   int pos = 0;
-  unsigned long long pending = __ballot(r >= 0);
-  while (pending) {                                        // wave-uniform
-    const int leader = __ffsll((long long)pending) - 1;
-    const int val = __shfl(r, leader, 64);
-    const unsigned long long same = __ballot(r == val) & pending;
+  wave_groups(r, [&](int val, unsigned long long same, int leader) {
     const int m = __popcll(same);
     int base = 0;
     if (lane == leader) base = roff[val] + atomicSub(&cnt[val], m) - m;
     base = __shfl(base, leader, 64);
     if ((same >> lane) & 1) pos = base + __popcll(same & below);
-    pending &= ~same;
-  }
+  });
   if (r < 0) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   tk[pos] = key[i];
   ti[pos] = idx[i];
-}
-
-// sizes after the row scan (exclusive over nc + 1 rows): valid records,
-// coarse entries, coarse rows
-__global__ void k_counts(const int *__restrict__ roff, const long long *__restrict__ rscan,
-                         unsigned long long nc, int *__restrict__ small) {
-  small[0] = roff[nc];
-  small[1] = (int)(rscan[nc] & 0xffffffffLL);
-  small[2] = (int)(rscan[nc] >> 32);
 }
 
 // coarse entries (column, row), rows (cell, first entry) and the
@@ -173,7 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__res
                                                  const unsigned *__restrict__ idx,
                                                  const int *__restrict__ ent,
                                                  const int *__restrict__ roff,
-                                                 const long long *__restrict__ rscan, long long nvalid,
+                                                 const long long *__restrict__ rscan,
+                                                 long long *__restrict__ rinfo, long long nvalid,
                                                  long long nent, long long nrow,
                                                  unsigned long long nc, const int *__restrict__ rk,
                                                  const int *__restrict__ ra,
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(const unsigned long long *__res
   if (rowstart) {
     urow[rid] = (int)r;
     uptr[rid] = e0;
+    rinfo[r] = 0;                                          // zero again for the next call
   }
   if (i == nvalid - 1) {
     start[nent] = (int)nvalid;
@@ -383,9 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_sums(T *__restrict__ bsum, int 
   }
 }
 
+// bsum null: a single block (offset 0).  sizes non-null: the thread that
+// writes out[n-1] of the row scan also stores the sizes for the host:
+// sizes[0] = *nvalid, sizes[1] = out[n-1] & 0xffffffff, sizes[2] = out[n-1] >> 32
 template <typename T, bool INCLUSIVE>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const T *__restrict__ in, long long n,
-                                                      const T *__restrict__ bsum, T *__restrict__ out) {
+                                                      const T *__restrict__ bsum, T *__restrict__ out,
+                                                      const int *__restrict__ nvalid,
+                                                      int *__restrict__ sizes) {
   __shared__ T sh[kBlock];
   const long long base = (long long)blockIdx.x * kScanItems + (long long)threadIdx.x * kScanPer;
   T v[kScanPer];
@@ -396,11 +403,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T *__restrict__ in, 
     tsum += v[q];
   }
   T total;
-  T run = bsum[blockIdx.x] + block_exclusive(tsum, sh, total);
+  T run = (bsum ? bsum[blockIdx.x] : T(0)) + block_exclusive(tsum, sh, total);
 #pragma unroll
   for (int q = 0; q < kScanPer; ++q) {
     if (INCLUSIVE) run += v[q];
     if (base + q < n) out[base + q] = run;
+    if (sizes && base + q == n - 1) {
+      const long long w = (long long)run;
+      sizes[0] = *nvalid;
+      sizes[1] = (int)(w & 0xffffffffLL);
+      sizes[2] = (int)(w >> 32);
+    }
     if (!INCLUSIVE) run += v[q];
   }
 }
@@ -411,16 +424,32 @@ inline unsigned nblk(long long n) {
 }
 
 // out = scan of in[0 .. n) (exclusive or inclusive); bs: scratch for the
-// block sums
+// block sums (one launch when a block covers n); nvalid, sizes: see k_scan_down
 template <typename T, bool INCLUSIVE>
-void device_scan(const T *in, T *out, long long n, DevBuf &bs, hipStream_t st) {
+void device_scan(const T *in, T *out, long long n, DevBuf &bs, hipStream_t st, const int *nvalid = nullptr,
+                 int *sizes = nullptr) {
   if (n <= 0) return;
   const long long nb = (n + kScanItems - 1) / kScanItems;
-  bs.reserve((size_t)(nb + 1) * sizeof(T));
-  T *b = (T *)bs.p;
-  k_scan_reduce<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, b);
-  k_scan_sums<T><<<1, kBlock, 0, st>>>(b, (int)nb);
-  k_scan_down<T, INCLUSIVE><<<(unsigned)nb, kBlock, 0, st>>>(in, n, b, out);
+  T *b = nullptr;
+  if (nb > 1) {
+    bs.reserve((size_t)(nb + 1) * sizeof(T));
+    b = (T *)bs.p;
+    k_scan_reduce<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, b);
+    k_scan_sums<T><<<1, kBlock, 0, st>>>(b, (int)nb);
+  }
+  k_scan_down<T, INCLUSIVE><<<(unsigned)nb, kBlock, 0, st>>>(in, n, b, out, nvalid, sizes);
+}
+
+// reserve a buffer that the caller keeps all zero between calls: cleared
+// here only when its allocation is new
+void zero_reserve(DevBuf &b, size_t bytes, const void *&zp, size_t &zcap, hipStream_t st) {
+  b.reserve(bytes);
+  if (b.p != zp || b.cap != zcap) {
+    zp = nullptr;
+    SSAMG_HIP(hipMemsetAsync(b.p, 0, b.cap, st));
+    zp = b.p;
+    zcap = b.cap;
+  }
 }
 
 }  // namespace
@@ -455,6 +484,8 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   int end_bit = 1;
   while (end_bit < 64 && ((unsigned long long)1 << end_bit) <= (unsigned long long)nc * nc) ++end_bit;
   const unsigned long long invalid = end_bit >= 64 ? ~0ULL : (((unsigned long long)1 << end_bit) - 1);
+  // every buffer first: nothing below throws before the two zero-kept
+  // buffers are zero again, except a device error (which clears the record)
   w.key0.reserve(n * 8);
   w.key1.reserve(n * 8);
   w.idx0.reserve(n * 4);
@@ -464,6 +495,11 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   w.rb.reserve(n * 4);
   w.ent.reserve(n * 4);
   w.small.reserve(64);
+  w.roff.reserve((size_t)(nc + 1) * 4);
+  w.rscan.reserve((size_t)(nc + 1) * 8);
+  w.temp.reserve((size_t)((nc + 1 + kScanItems - 1) / kScanItems + 1) * 8);
+  zero_reserve(w.rcnt, (size_t)(nc + 1) * 4, w.rcnt_zero, w.rcnt_zcap, st);
+  zero_reserve(w.rinfo, (size_t)(nc + 1) * 8, w.rinfo_zero, w.rinfo_zcap, st);
   if (!w.host_small) {
     void *h = nullptr;
     SSAMG_HIP(hipHostMalloc(&h, 64));
@@ -474,33 +510,37 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   int *rk = (int *)w.rk.p, *ra = (int *)w.ra.p, *rb = (int *)w.rb.p;
   int *ent = (int *)w.ent.p;
   int *small = (int *)w.small.p;
-  k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
-                                       rk, ra, rb);
-  // key order, ties in record order: k0/i0 -> row buckets in k1/i1 -> ranked
-  // inside each row into k0/i0 (rows of at most w.row_sort records in LDS)
-  w.rcnt.reserve((size_t)(nc + 1) * 4);
-  w.roff.reserve((size_t)(nc + 1) * 4);
   int *rcnt = (int *)w.rcnt.p, *roff = (int *)w.roff.p;
-  SSAMG_HIP(hipMemsetAsync(rcnt, 0, (size_t)(nc + 1) * 4, st));
-  k_row_count<<<nblk(n), kBlock, 0, st>>>(k0, n, (unsigned long long)nc, invalid, rcnt);
+  long long *rinfo = (long long *)w.rinfo.p, *rscan = (long long *)w.rscan.p;
+  // a device error leaves the zero-kept buffers unknown
+  struct Guard {
+    SymScratch &w;
+    bool armed = true;
+    ~Guard() {
+      if (armed) w.rcnt_zero = w.rinfo_zero = nullptr;
+    }
+  } guard{w};
+  // records and row counts (rcnt) -> row offsets -> row buckets in k1/i1
+  // (rcnt back to zero) -> ranked inside each row into k0/i0 with entry
+  // numbers and row counts (rinfo) -> row scan and the sizes
+  k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
+                                       rk, ra, rb, rcnt);
   device_scan<int, false>(rcnt, roff, nc + 1, w.temp, st);
   k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, i0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
-  w.rinfo.reserve((size_t)(nc + 1) * 8);
-  w.rscan.reserve((size_t)(nc + 1) * 8);
-  long long *rinfo = (long long *)w.rinfo.p, *rscan = (long long *)w.rscan.p;
-  SSAMG_HIP(hipMemsetAsync(rinfo, 0, (size_t)(nc + 1) * 8, st));
   k_row_rank_lds<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(k1, i1, n, (unsigned long long)nc, invalid, roff,
                                                             (int)std::min<int64_t>(w.row_sort, kRankCap), k0, i0,
                                                             ent, rinfo);
   std::swap(k0, k1);
   std::swap(i0, i1);
-  device_scan<long long, false>(rinfo, rscan, nc + 1, w.temp, st);
-  k_counts<<<1, 1, 0, st>>>(roff, rscan, (unsigned long long)nc, small);
+  device_scan<long long, false>(rinfo, rscan, nc + 1, w.temp, st, roff + nc, small);
   SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   if (before_sync) before_sync();   // host work that overlaps the device's
   SSAMG_HIP(hipStreamSynchronize(st));
   const int nvalid = w.host_small[0], nent = w.host_small[1], nr = w.host_small[2];
-  if (nvalid == 0) return;
+  if (nvalid == 0) {
+    guard.armed = false;                  // no row written, rcnt back to zero
+    return;
+  }
   out.ucol.reserve((size_t)nent * 4);
   out.erow.reserve((size_t)nent * 4);
   out.start.reserve((size_t)(nent + 1) * 4);
@@ -509,11 +549,12 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   out.ck.reserve((size_t)nvalid * 4);
   out.ca.reserve((size_t)nvalid * 4);
   out.cb.reserve((size_t)nvalid * 4);
-  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, ent, roff, rscan, nvalid, nent, nr, (unsigned long long)nc,
+  k_fill<<<nblk(nvalid), kBlock, 0, st>>>(k1, i1, ent, roff, rscan, rinfo, nvalid, nent, nr, (unsigned long long)nc,
                                           rk, ra, rb, (int *)out.ucol.p, (int *)out.erow.p,
                                           (int *)out.start.p, (int *)out.urow.p, (int *)out.uptr.p,
                                           (int *)out.ck.p, (int *)out.ca.p, (int *)out.cb.p);
   SSAMG_HIP(hipGetLastError());
+  guard.armed = false;
   out_nnz = nent;
   out_nrow = nr;
   out.ncontrib = nvalid;

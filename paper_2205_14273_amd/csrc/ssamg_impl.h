@@ -265,6 +265,10 @@ struct SymScratch {
   DevBuf key0, key1, idx0, idx1, rk, ra, rb, ent, small, temp, rcnt, roff, rinfo, rscan;
   int *host_small = nullptr;         // pinned
   int64_t row_sort = kRowSortRecords; // rows of at most this many records are ranked in LDS
+  // rcnt and rinfo are all zero between calls (each call leaves them so); the
+  // allocation (pointer, capacity) that was last cleared, null when unknown
+  const void *rcnt_zero = nullptr, *rinfo_zero = nullptr;
+  size_t rcnt_zcap = 0, rinfo_zcap = 0;
   ~SymScratch() {
     if (host_small) (void)hipHostFree(host_small);
   }
