@@ -110,37 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_wsum_final(const double *__restrict_
 // strongly heterogeneous problems) the two off-plane sums are normalised by
 // their total so constants are interpolated, or 1/2 each if that total is not
 // negative.
-__global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double> *__restrict__ desc,
-                                                           const PartDesc<float> *__restrict__ desc32,
-                                                           int *__restrict__ flag) {
-  const PartDesc<double> &d = desc[blockIdx.y];
-  const long long fidx = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (d.dstar < 0 || fidx >= d.nf) return;
-  const int ds = d.dstar;
-  int g[3];
-  cell_ijk((int)fidx, d.fn[0], d.fn[1], g[0], g[1], g[2]);
-  int f[3] = {g[0], g[1], g[2]};
-  f[ds] = 2 * g[ds] + 1;
-  const long long c = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
-  // all coefficient loads first (entries past nent read entry 0 and are
-  // skipped), then the sums in entry order
-  double cv[kMaxEnt];
-#pragma unroll
-  for (int s = 0; s < kMaxEnt; ++s) cv[s] = dev::G(d.coef)[(long long)(s < d.nent ? s : 0) * d.ncell + c];
-  double den = 0.0, sm = 0.0, sp = 0.0;
-#pragma unroll
-  for (int s = 0; s < kMaxEnt; ++s) {
-    if (s >= d.nent) break;
-    const double v = cv[s];
-    const int o = off_comp(d.code[s], ds);
-    if (o == 0)
-      den += v;
-    else if (o < 0)
-      sm += v;
-    else
-      sp += v;
-  }
-  double wm, wp;
+// weights from the collapse sums (den: zero d* component, sm / sp: -1 / +1)
+__device__ __forceinline__ void collapse_weights(double den, double sm, double sp, double &wm, double &wp) {
   if (den > 0.0) {
     wm = -sm / den;
     wp = -sp / den;
@@ -152,6 +123,41 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
     wm = 0.5;
     wp = 0.5;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double> *__restrict__ desc,
+                                                           const PartDesc<float> *__restrict__ desc32,
+                                                           int *__restrict__ flag) {
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const long long fidx = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (d.dstar < 0 || d.wfused || fidx >= d.nf) return;
+  const int ds = d.dstar;
+  int g[3];
+  cell_ijk((int)fidx, d.fn[0], d.fn[1], g[0], g[1], g[2]);
+  int f[3] = {g[0], g[1], g[2]};
+  f[ds] = 2 * g[ds] + 1;
+  const long long c = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
+  // all coefficient loads first (in summation order; slots past nent read the
+  // first entry and are skipped), then the sums
+  double cv[kMaxEnt];
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s)
+    cv[s] = dev::G(d.coef)[(long long)d.wsum[s < d.nent ? s : 0] * d.ncell + c];
+  double den = 0.0, sm = 0.0, sp = 0.0;
+#pragma unroll
+  for (int s = 0; s < kMaxEnt; ++s) {
+    if (s >= d.nent) break;
+    const double v = cv[s];
+    const int o = off_comp(d.code[d.wsum[s]], ds);
+    if (o == 0)
+      den += v;
+    else if (o < 0)
+      sm += v;
+    else
+      sp += v;
+  }
+  double wm, wp;
+  collapse_weights(den, sm, sp, wm, wp);
   const bool hi_out = f[ds] + 1 > d.n[ds] - 1;   // lower corner 0: f-1 >= 0 always
   if (hi_out) {
     wp = 0.0;
@@ -308,6 +314,7 @@ __device__ __forceinline__ void rap_cell(const PartDesc<double> &d, const RapDes
   const bool okm = g.row_ok[0], okp = g.row_ok[2];
   const bool ok2m = g.fb - 2 >= 0, ok2p = g.fb + 2 <= g.nd - 1;
   double l1c = 0.0, l1f = 0.0;
+  double wden = 0.0, wsm = 0.0, wsp = 0.0;
 #pragma unroll
   for (int tb = -1; tb <= 1; ++tb) {
 #pragma unroll
@@ -344,6 +351,15 @@ __device__ __forceinline__ void rap_cell(const PartDesc<double> &d, const RapDes
         if (e < 0) continue;
         out[(long long)e * d.cncell + cidx] = v[Q];
         if (t.out32) out32[(long long)e * d.cncell + cidx] = (float)v[Q];
+        // the coarse row's collapse sums along its own direction, in the
+        // order of formation (the order of the descriptor's wsum)
+        const int comp = t.wdir == DS ? Q - 1 : t.wdir == AX ? ta : tb;
+        if (comp == 0)
+          wden += v[Q];
+        else if (comp < 0)
+          wsm += v[Q];
+        else
+          wsp += v[Q];
       }
     }
   }
@@ -351,6 +367,29 @@ __device__ __forceinline__ void rap_cell(const PartDesc<double> &d, const RapDes
     const auto l1 = dev::Gw(t.l1);
     l1[g.fr[1]] = l1c;
     if (okp) l1[g.fr[2]] = l1f;
+  }
+  // the coarse cell's own interpolation weights if it is an F cell of its level
+  // (selects, not a runtime index into the coordinate registers)
+  const int wd = t.wdir;
+  const int cw = wd == 0 ? g.ci[0] : wd == 1 ? g.ci[1] : g.ci[2];
+  if (wd >= 0 && (cw & 1)) {
+    const int f0 = wd == 0 ? (cw - 1) >> 1 : g.ci[0];
+    const int f1 = wd == 1 ? (cw - 1) >> 1 : g.ci[1];
+    const int f2 = wd == 2 ? (cw - 1) >> 1 : g.ci[2];
+    const long long fidx = f0 + (long long)t.wfn[0] * (f1 + (long long)t.wfn[1] * f2);
+    double wmv, wpv;
+    collapse_weights(wden, wsm, wsp, wmv, wpv);
+    if (cw + 1 > d.cn[wd] - 1) {
+      wpv = 0.0;
+      if ((t.wfaces >> (2 * wd + 1)) & 1) wmv = 1.0;
+    }
+    if (!isfinite(wmv) || !isfinite(wpv)) t.wflag[0] = 1;
+    dev::Gw(t.wm)[fidx] = wmv;
+    dev::Gw(t.wp)[fidx] = wpv;
+    if (t.wm32) {
+      dev::Gw(t.wm32)[fidx] = (float)wmv;
+      dev::Gw(t.wp32)[fidx] = (float)wpv;
+    }
   }
 }
 

@@ -250,6 +250,41 @@ void upload(T *dst, const std::vector<T> &src, hipStream_t st) {
 // the block order of the stored launch options: the cycle's descriptors take
 // the cycle's strips; in a mixed-precision cycle the FP64 ones of level 0 serve
 // the FP64 product of PCG and take its strips.
+// Part p of level l gets its interpolation weights from the one-thread-per-
+// coarse-cell Galerkin product that forms it (not for the lumped part-face
+// reading, which needs the level's couplings, formed after that product).
+bool weights_fused(const Solver &s, int l, size_t p) {
+  const int L = (int)s.lv.size();
+  if (l < 1 || l >= L - 1) return false;
+  const Level &F = s.lv[l - 1];
+  if (!rap_per_cell((int)F.parts.size(), F.maxcoarse, s.rap_cell_min)) return false;
+  const PartLevel &pf = F.parts[p], &q = s.lv[l].parts[p];
+  return pf.dstar >= 0 && !pf.rap_ng && q.dstar >= 0 && s.prm.pb_interp != SSAMG_PB_LUMP;
+}
+
+// Order in which the collapse sums of level l's part p take its entries: the
+// order in which the Galerkin product forms a coarse row (perpendicular
+// offsets (tb, ta) in the two other axes after the previous direction, then
+// that direction's component), entry order where no product forms the level.
+void weight_order(const Solver &s, int l, size_t p, int (&ord)[kMaxEnt]) {
+  const PartLevel &q = s.lv[l].parts[p];
+  const int nent = (int)q.pat.size();
+  for (int e = 0; e < kMaxEnt; ++e) ord[e] = e < nent ? e : 0;
+  if (l < 1) return;
+  const PartLevel &pf = s.lv[l - 1].parts[p];
+  if (pf.dstar < 0 || pf.rap_ng) return;
+  const int ds = pf.dstar, ax = (ds + 1) % 3, bx = (ds + 2) % 3;
+  auto stride = [](int a) { return a == 0 ? 1 : a == 1 ? 3 : 9; };
+  int k = 0;
+  for (int tb = -1; tb <= 1; ++tb)
+    for (int ta = -1; ta <= 1; ++ta)
+      for (int qd = -1; qd <= 1; ++qd) {
+        const int e = pf.rap_cmap[(ta + 1) * stride(ax) + (tb + 1) * stride(bx) + (qd + 1) * stride(ds)];
+        if (e >= 0) ord[k++] = e;
+      }
+  if (k != nent) throw Error(SSAMG_ERR_STATE, "internal: coarse stencil not covered by its Galerkin table");
+}
+
 void build_descs(const Solver &s, int l, std::vector<PartDesc<double>> &h64,
                  std::vector<PartDesc<float>> &h32) {
   const Level &V = s.lv[l];
@@ -268,6 +303,8 @@ void build_descs(const Solver &s, int l, std::vector<PartDesc<double>> &h64,
     const bool sym = mirrored(s);
     h64.push_back(make_desc<double>(V, q, p, q.coef64, V.d_w64, V.d_uval64, V.d_rs64, mv, sym));
     h64.back().pblump = s.prm.pb_interp == SSAMG_PB_LUMP;
+    weight_order(s, l, p, h64.back().wsum);
+    h64.back().wfused = weights_fused(s, l, p) ? 1 : 0;
     if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32, cyc, false));
   }
 }
@@ -1067,6 +1104,19 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
         }
         r.nent = q.rap_nent;
         r.ng = q.rap_ng ? 1 : 0;
+        r.wdir = -1;
+        if (weights_fused(s, l + 1, p)) {
+          const Level &C = s.lv[l + 1];
+          const PartLevel &qc = C.parts[p];
+          r.wdir = qc.dstar;
+          r.wfaces = qc.faces;
+          for (int a = 0; a < 3; ++a) r.wfn[a] = qc.fn[a];
+          r.wm = C.d_w64 + qc.wofs;
+          r.wp = C.d_w64 + qc.wofs + qc.nf;
+          r.wm32 = mixed && C.d_w32 ? C.d_w32 + qc.wofs : nullptr;
+          r.wp32 = mixed && C.d_w32 ? C.d_w32 + qc.wofs + qc.nf : nullptr;
+          r.wflag = s.flag;
+        }
         for (int o = 0; o < 27; ++o) {
           r.fmap[o] = q.rap_fmap[o];
           r.cmap[o] = q.rap_cmap[o];
@@ -1162,7 +1212,9 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   for (int l = 0; l + 1 < L; ++l) {
     Level &V = s.lv[l], &C = s.lv[l + 1];
     const int np = (int)V.parts.size();
-    launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
+    bool all_fused = true;
+    for (int p = 0; p < np; ++p) all_fused = all_fused && (V.parts[p].dstar < 0 || weights_fused(s, l, p));
+    if (!all_fused) launch_interp_weights(V.d_desc64, mixed ? V.d_desc32 : nullptr, np, V.maxf, s.flag, st);
     bool any_ng = false;
     for (const auto &q : V.parts) any_ng = any_ng || q.rap_ng;
     launch_rap(V.d_desc64, V.d_rapdesc, np, V.maxcoarse, C.maxent, s.rap_cell_min, any_ng, st);

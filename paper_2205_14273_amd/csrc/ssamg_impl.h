@@ -141,6 +141,12 @@ struct PartDesc {
   // s, mlin[s] = 0.
   int mir[kMaxEnt];
   int mlin[kMaxEnt];
+  // interpolation weights (FP64 descriptors only): the collapse sums take the
+  // entries in the order wsum[0 .. nent) (the order in which the Galerkin
+  // product forms a coarse row, so both kernels round alike); wfused: that
+  // product has already written this part's weights
+  int wsum[kMaxEnt];
+  int wfused;
   // lin[s] * 64 + code[s] (code < 64): the small-level sweeps read one scalar
   // per entry, which keeps the 27-point tables within the scalar registers
   int lc[kMaxEnt];
@@ -199,7 +205,7 @@ struct Problem {
   int fv_stencil = 0;
   double *d_kappa = nullptr;
   double *d_aniso = nullptr;
-  int *d_ucode = nullptr;            // per coupling entry: offset code | p_i << 5 | p_j << 18
+  int *d_ucode = nullptr;            // per coupling entry: offset code | p_i << 6 | p_j << 19
   int *d_geom = nullptr;             // per part: origin[3], dims[3], offset
   double **d_cptr = nullptr;         // device copy of coef[]
   std::vector<int> fv_signature;     // placement + stencil the FV structure was built for
@@ -454,6 +460,16 @@ struct RapDesc {
   int fmap[27];        // fine entry of each offset, -1: not in the fine stencil
   int cmap[27];        // coarse entry of each offset, -1: not in the coarse stencil
   int cofs[27];        // offset of each coarse entry
+  // one-thread-per-coarse-cell kernel: the coarse part's own interpolation
+  // weights (toward the level after) from each coarse row as it is formed:
+  // its coarsening direction (-1: not formed here), faces, F-box extents,
+  // the weight arrays (FP32 copies or null) and the error flag
+  int wdir;
+  int wfaces;
+  int wfn[3];
+  double *wm, *wp;
+  float *wm32, *wp32;
+  int *wflag;
 };
 
 // blocks per part of the finite-volume stencil kernel (its metric partials)

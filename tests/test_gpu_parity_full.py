@@ -40,8 +40,9 @@ SMALL = {"c2_20": lambda: W.c2(20), "c3_9": lambda: W.c3(9), "c5_11": lambda: W.
 def test_rap_per_cell_kernel_parity(monkeypatch, name):
     """Levels of at least SSAMG_RAP_CELL_MIN coarse cells take the per-cell
     Galerkin kernel (the one that forms every large coarse operator at full
-    size); forced on every level it matches the oracle and gives the per-entry
-    kernel's operators bit for bit."""
+    size, and the interpolation weights of the levels it forms); forced on
+    every level it matches the oracle and gives the per-entry kernel's
+    operators and the separate weight kernel's weights bit for bit."""
     _print_case(f"rap per cell {name}")
     case = SMALL[name]()
     h = oracle_fv(case)
@@ -53,6 +54,9 @@ def test_rap_per_cell_kernel_parity(monkeypatch, name):
     for l in range(1, h.nlevels):
         for p in range(case.geometry.nparts):
             assert np.array_equal(s_cell.copy_stencil(l, p), s_ent.copy_stencil(l, p)), (l, p)
+            if l < h.nlevels - 1:
+                for wc, we in zip(s_cell.copy_interp(l, p), s_ent.copy_interp(l, p)):
+                    assert np.array_equal(wc, we), ("weights", l, p)
     r = np.random.default_rng(5).uniform(-1, 1, h.levels[0].n)
     z = s_cell.apply_precond(_cuda(r)).cpu().numpy()
     assert_cycle_close(z, O.vcycle(h, r), vcycle_scale(h, r), CYCLE_RTOL[0], name)
