@@ -70,11 +70,15 @@ __device__ int find_part(const int *geom, int nparts, int p, const int G[3], int
   return -1;
 }
 
-// one cell of k_fv_stencil: its stencil row and its links' metric terms
+// one cell of k_fv_stencil: its stencil row, its links' metric terms and,
+// along every direction d in which the cell is odd, its collapse sums: den
+// (the coefficients with zero d component), sm / sp (those at -1 / +1), the
+// off-center entries in entry order and then the center
 __device__ __forceinline__ void fv_cell(const FvArgs &fa, const double *__restrict__ kappa,
                                         const double *__restrict__ aniso, double *const *__restrict__ coef,
                                         const Geo &me, int p, long long c, const double *s_as,
-                                        const double *s_gw, double (&md)[3]) {
+                                        const double *s_gw, double (&md)[3], double *__restrict__ csum,
+                                        const long long *__restrict__ csoff) {
   const long long ncell = (long long)me.n[0] * me.n[1] * me.n[2];
   const int i = (int)(c % me.n[0]);
   const int j = (int)((c / me.n[0]) % me.n[1]);
@@ -85,6 +89,7 @@ __device__ __forceinline__ void fv_cell(const FvArgs &fa, const double *__restri
   const auto kp = dev::G(kappa) + me.off;
   const long long sy = me.n[0], sz = (long long)me.n[0] * me.n[1];
   double diag = 0.0;
+  double cd[3] = {0.0, 0.0, 0.0}, cm[3] = {0.0, 0.0, 0.0}, cp[3] = {0.0, 0.0, 0.0};
   for (int s = 1; s < fa.nent; ++s) {
     const int code = fa.code[s];
     const double as = s_as[s];
@@ -118,8 +123,35 @@ __device__ __forceinline__ void fv_cell(const FvArgs &fa, const double *__restri
     }
     diag += t;
     cf[(long long)s * ncell + c] = v;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int o = oc(code, d);
+      if (o == 0)
+        cd[d] += v;
+      else if (o < 0)
+        cm[d] += v;
+      else
+        cp[d] += v;
+    }
   }
   cf[c] = diag;   // entry 0 is the center
+  if (!csum) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!(loc[d] & 1)) continue;
+    const int a = (d + 1) % 3, b = (d + 2) % 3;
+    const long long h = me.n[d] >> 1;
+    const long long nf = h * me.n[a] * me.n[b];
+    // F-box index: the coordinates with loc[d] -> (loc[d]-1)/2 in the extents with n[d] -> n[d]/2
+    const int g[3] = {d == 0 ? (loc[0] - 1) >> 1 : loc[0], d == 1 ? (loc[1] - 1) >> 1 : loc[1],
+                      d == 2 ? (loc[2] - 1) >> 1 : loc[2]};
+    const long long e0 = d == 0 ? h : me.n[0], e1 = d == 1 ? h : me.n[1];
+    const long long fi = g[0] + e0 * (g[1] + e1 * g[2]);
+    const auto out = dev::Gw(csum) + csoff[3 * p + d];
+    out[fi] = cd[d] + diag;
+    out[nf + fi] = cm[d];
+    out[2 * nf + fi] = cp[d];
+  }
 }
 
 // Also the block's partial sums of the direction metric c_d of Section 3.1
@@ -129,7 +161,8 @@ __device__ __forceinline__ void fv_cell(const FvArgs &fa, const double *__restri
 __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *__restrict__ kappa,
                                                        const double *__restrict__ aniso,
                                                        double *const *__restrict__ coef,
-                                                       double *__restrict__ mpart) {
+                                                       double *__restrict__ mpart, double *__restrict__ csum,
+                                                       const long long *__restrict__ csoff) {
   // the part's link factors and geometric weights, once per block
   __shared__ double s_as[kMaxEnt], s_gw[kMaxEnt];
   __shared__ double sh[3][kBlock];
@@ -143,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_fv_stencil(FvArgs fa, const double *
   const long long ncell = (long long)me.n[0] * me.n[1] * me.n[2];
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   double md[3] = {0.0, 0.0, 0.0};
-  if (c < ncell) fv_cell(fa, kappa, aniso, coef, me, p, c, s_as, s_gw, md);
+  if (c < ncell) fv_cell(fa, kappa, aniso, coef, me, p, c, s_as, s_gw, md, csum, csoff);
   for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = md[q];
   for (int s = kBlock / 2; s > 0; s >>= 1) {
     __syncthreads();
@@ -264,8 +297,10 @@ inline unsigned nblk(long long n) {
 }  // namespace
 
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
-                       double *const *coef, double *mpart, hipStream_t st) {
-  k_fv_stencil<<<dim3(fv_blocks(maxcell), fa.nparts), kBlock, 0, st>>>(fa, kappa, aniso, coef, mpart);
+                       double *const *coef, double *mpart, double *csum, const long long *csoff,
+                       hipStream_t st) {
+  k_fv_stencil<<<dim3(fv_blocks(maxcell), fa.nparts), kBlock, 0, st>>>(fa, kappa, aniso, coef, mpart, csum,
+                                                                       csoff);
 }
 
 void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *ucol,

@@ -137,24 +137,32 @@ __global__ __launch_bounds__(kBlock) void k_interp_weights(const PartDesc<double
   int f[3] = {g[0], g[1], g[2]};
   f[ds] = 2 * g[ds] + 1;
   const long long c = f[0] + (long long)d.n[0] * (f[1] + (long long)d.n[1] * f[2]);
-  // all coefficient loads first (in summation order; slots past nent read the
-  // first entry and are skipped), then the sums
-  double cv[kMaxEnt];
-#pragma unroll
-  for (int s = 0; s < kMaxEnt; ++s)
-    cv[s] = dev::G(d.coef)[(long long)d.wsum[s < d.nent ? s : 0] * d.ncell + c];
   double den = 0.0, sm = 0.0, sp = 0.0;
+  if (d.csum) {
+    // formed by the assembly in the same order
+    const auto cs = dev::G(d.csum);
+    den = cs[fidx];
+    sm = cs[d.nf + fidx];
+    sp = cs[2 * d.nf + fidx];
+  } else {
+    // all coefficient loads first (in summation order; slots past nent read
+    // the first entry and are skipped), then the sums
+    double cv[kMaxEnt];
 #pragma unroll
-  for (int s = 0; s < kMaxEnt; ++s) {
-    if (s >= d.nent) break;
-    const double v = cv[s];
-    const int o = off_comp(d.code[d.wsum[s]], ds);
-    if (o == 0)
-      den += v;
-    else if (o < 0)
-      sm += v;
-    else
-      sp += v;
+    for (int s = 0; s < kMaxEnt; ++s)
+      cv[s] = dev::G(d.coef)[(long long)d.wsum[s < d.nent ? s : 0] * d.ncell + c];
+#pragma unroll
+    for (int s = 0; s < kMaxEnt; ++s) {
+      if (s >= d.nent) break;
+      const double v = cv[s];
+      const int o = off_comp(d.code[d.wsum[s]], ds);
+      if (o == 0)
+        den += v;
+      else if (o < 0)
+        sm += v;
+      else
+        sp += v;
+    }
   }
   double wm, wp;
   collapse_weights(den, sm, sp, wm, wp);

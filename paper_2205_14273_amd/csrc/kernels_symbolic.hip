@@ -222,27 +222,28 @@ __global__ __launch_bounds__(kBlock) void k_entry_rows(int nrow, const int *__re
 
 // first stored row of every block of a grid-over-cells launch (1 << lg rhs)
 // and that row's first entry: out[2b] = row, out[2b + 1] = uptr[row]
-__global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp, int np, int lg,
-                                                 const long long *__restrict__ boff, int nrow,
-                                                 const int *__restrict__ urow,
-                                                 const int *__restrict__ uptr, int *__restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_ublk(const SymPart *__restrict__ sp_all, int np,
+                                                 const long long *__restrict__ boff_all, UblkJobs jobs) {
+  const UblkJob &jb = jobs.j[blockIdx.z];
   const int p = blockIdx.y;
-  const SymPart &q = sp[p];
-  const long long cpb = kBlock >> lg;
+  const SymPart &q = sp_all[jb.spat + p];
+  const long long *boff = boff_all + jb.boffat;
+  const long long cpb = kBlock >> jb.lg;
   const long long nchunk = (q.ncell + cpb - 1) / cpb;
   const long long b = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (b > nchunk) return;
   const long long first = q.off + (b * cpb < q.ncell ? b * cpb : q.ncell);
+  const int nrow = jb.nrow;
   int lo = 0, hi = nrow;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (urow[mid] < first)
+    if (jb.urow[mid] < first)
       lo = mid + 1;
     else
       hi = mid;
   }
-  out[2 * (boff[p] + b)] = lo;
-  out[2 * (boff[p] + b) + 1] = nrow > 0 ? uptr[lo] : 0;
+  jb.out[2 * (boff[p] + b)] = lo;
+  jb.out[2 * (boff[p] + b) + 1] = nrow > 0 ? jb.uptr[lo] : 0;
 }
 
 // Rank of every record inside its row by (key, record index), one wave per
@@ -564,9 +565,9 @@ void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hi
   if (nrow > 0) k_entry_rows<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, erow);
 }
 
-void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
-                 const int *urow, const int *uptr, int *out, hipStream_t st) {
-  k_ublk<<<dim3(nblk(maxchunk + 1), np), kBlock, 0, st>>>(sp, np, lg, boff, nrow, urow, uptr, out);
+void launch_ublk(const SymPart *sp, int np, const long long *boff, const UblkJobs &jobs, int64_t nbx,
+                 hipStream_t st) {
+  if (jobs.n > 0) k_ublk<<<dim3((unsigned)nbx, np, jobs.n), kBlock, 0, st>>>(sp, np, boff, jobs);
 }
 
 }  // namespace ssamg

@@ -37,10 +37,15 @@ void Problem::free_device() {
     c = nullptr;
   }
   for (void *p : {(void *)d_urow, (void *)d_uptr, (void *)d_ucol, (void *)d_uval, (void *)d_kappa,
-                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom, (void *)d_cptr, (void *)d_mpart})
+                  (void *)d_aniso, (void *)d_ucode, (void *)d_geom, (void *)d_cptr, (void *)d_mpart,
+                  (void *)d_csum, (void *)d_csoff})
     if (p) (void)hipFree(p);
   d_mpart = nullptr;
   mpart_cap = 0;
+  d_csum = nullptr;
+  csum_cap = 0;
+  d_csoff = nullptr;
+  csum_off.clear();
   metric_version = 0;
   d_urow = d_uptr = d_ucol = d_ucode = d_geom = nullptr;
   d_cptr = nullptr;
@@ -751,7 +756,32 @@ ssamg_status ssamg_problem_fv_assemble(ssamg_problem prob, const double *kappa, 
     pr->d_mpart = dev_alloc<double>(mbytes / sizeof(double));
     pr->mpart_cap = mbytes;
   }
-  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, pr->d_cptr, pr->d_mpart, st);
+  // collapse sums: per part and direction d, three blocks of the cells odd along d
+  {
+    std::vector<long long> off((size_t)3 * pr->nparts);
+    long long tot = 0;
+    for (int p = 0; p < pr->nparts; ++p) {
+      const auto &n = pr->dims[p];
+      for (int d = 0; d < 3; ++d) {
+        off[3 * p + d] = tot;
+        tot += 3LL * (n[d] / 2) * n[(d + 1) % 3] * n[(d + 2) % 3];
+      }
+    }
+    const size_t cbytes = (size_t)std::max<long long>(tot, 1) * sizeof(double);
+    if (pr->csum_cap < cbytes) {
+      if (pr->d_csum) (void)hipFree(pr->d_csum);
+      pr->d_csum = nullptr;
+      pr->csum_cap = 0;
+      pr->d_csum = dev_alloc<double>(cbytes / sizeof(double));
+      pr->csum_cap = cbytes;
+    }
+    if (off != pr->csum_off || !pr->d_csoff) {
+      dev_upload(pr->d_csoff, off);
+      pr->csum_off = off;
+    }
+  }
+  launch_fv_stencil(fa, maxcell, pr->d_kappa, pr->d_aniso, pr->d_cptr, pr->d_mpart, pr->d_csum, pr->d_csoff,
+                    st);
   launch_fv_coupling((int)pr->urow.size(), pr->d_urow, pr->d_uptr, pr->d_ucol, pr->d_ucode,
                      pr->d_kappa, pr->d_aniso, pr->d_uval, st);
   SSAMG_HIP(hipGetLastError());

@@ -270,7 +270,15 @@ void weight_order(const Solver &s, int l, size_t p, int (&ord)[kMaxEnt]) {
   const PartLevel &q = s.lv[l].parts[p];
   const int nent = (int)q.pat.size();
   for (int e = 0; e < kMaxEnt; ++e) ord[e] = e < nent ? e : 0;
-  if (l < 1) return;
+  if (l < 1) {
+    // finest level: the off-center entries in entry order, then the center
+    // (the order in which the finite-volume assembly forms a row)
+    int k = 0;
+    for (int e = 0; e < nent; ++e)
+      if (e != q.center) ord[k++] = e;
+    ord[k++] = q.center;
+    return;
+  }
   const PartLevel &pf = s.lv[l - 1].parts[p];
   if (pf.dstar < 0 || pf.rap_ng) return;
   const int ds = pf.dstar, ax = (ds + 1) % 3, bx = (ds + 2) % 3;
@@ -305,6 +313,11 @@ void build_descs(const Solver &s, int l, std::vector<PartDesc<double>> &h64,
     h64.back().pblump = s.prm.pb_interp == SSAMG_PB_LUMP;
     weight_order(s, l, p, h64.back().wsum);
     h64.back().wfused = weights_fused(s, l, p) ? 1 : 0;
+    const Problem &pr = *s.prob;
+    h64.back().csum = l == 0 && q.dstar >= 0 && pr.fv_stencil && pr.d_csum &&
+                              pr.metric_version == pr.coef_version && (int)pr.csum_off.size() == 3 * pr.nparts
+                          ? pr.d_csum + pr.csum_off[3 * p + q.dstar]
+                          : nullptr;
     if (mixed) h32.push_back(make_desc<float>(V, q, p, q.coef32, V.d_w32, V.d_uval32, V.d_rs32, cyc, false));
   }
 }
@@ -697,19 +710,39 @@ void symbolic_couplings(Solver &s, int lgmax) {
     // the host vectors must outlive the asynchronous copy
     SSAMG_HIP(hipStreamSynchronize(st));
   }
-  for (int l = 0; l < lh; ++l) {
-    Level &V = s.lv[l];
-    int64_t maxchunk = 0;
-    for (auto &q : V.parts) maxchunk = std::max<int64_t>(maxchunk, q.ncell);
-    for (int lg = 0; lg <= kMaxLg; ++lg) {
-      V.d_ublk[lg] = nullptr;
-      if (lg > lgmax) continue;
-      DevBuf &ub = s.store[l]->ublk[lg];
-      ub.reserve((size_t)V.ublk_len[lg] * 2 * sizeof(int));
-      launch_ublk(d_sp + sp_at[l], np, lg, (maxchunk + (kBlock >> lg) - 1) / (kBlock >> lg),
-                  d_boff + boff_at[l * (kMaxLg + 1) + lg], V.nrow, V.d_urow, V.d_uptr, (int *)ub.p, st);
-      V.d_ublk[lg] = (int *)ub.p;
+  // block tables of the device-formed levels, all (level, lg) pairs in few launches
+  {
+    UblkJobs jobs{};
+    int64_t nbx = 1;
+    auto flush = [&] {
+      launch_ublk(d_sp, np, d_boff, jobs, nbx, st);
+      jobs.n = 0;
+      nbx = 1;
+    };
+    for (int l = 0; l < lh; ++l) {
+      Level &V = s.lv[l];
+      int64_t maxchunk = 0;
+      for (auto &q : V.parts) maxchunk = std::max<int64_t>(maxchunk, q.ncell);
+      for (int lg = 0; lg <= kMaxLg; ++lg) {
+        V.d_ublk[lg] = nullptr;
+        if (lg > lgmax) continue;
+        DevBuf &ub = s.store[l]->ublk[lg];
+        ub.reserve((size_t)V.ublk_len[lg] * 2 * sizeof(int));
+        V.d_ublk[lg] = (int *)ub.p;
+        const int64_t chunks = (maxchunk + (kBlock >> lg) - 1) / (kBlock >> lg);
+        nbx = std::max<int64_t>(nbx, (chunks + 1 + kBlock - 1) / kBlock);
+        UblkJob &j = jobs.j[jobs.n++];
+        j.urow = V.d_urow;
+        j.uptr = V.d_uptr;
+        j.out = (int *)ub.p;
+        j.nrow = V.nrow;
+        j.lg = lg;
+        j.spat = (int)sp_at[l];
+        j.boffat = (int)boff_at[l * (kMaxLg + 1) + lg];
+        if (jobs.n == kUblkJobs) flush();
+      }
     }
+    flush();
   }
   SSAMG_HIP(hipGetLastError());
   SSAMG_HIP(hipStreamSynchronize(st));

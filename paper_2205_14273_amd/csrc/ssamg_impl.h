@@ -147,6 +147,10 @@ struct PartDesc {
   // product has already written this part's weights
   int wsum[kMaxEnt];
   int wfused;
+  // finest level of an assembled problem: the collapse sums along dstar
+  // (den, sm, sp blocks of nf) that the assembly formed in the order of wsum,
+  // or null
+  const double *csum;
   // lin[s] * 64 + code[s] (code < 64): the small-level sweeps read one scalar
   // per entry, which keeps the 27-point tables within the scalar registers
   int lc[kMaxEnt];
@@ -174,6 +178,14 @@ struct Problem {
   double *d_mpart = nullptr;
   size_t mpart_cap = 0;
   int mpart_nb = 0;
+  // the same assembly's collapse sums of every cell odd along a direction d,
+  // per part and direction in that direction's F-box order: den, sm and sp
+  // (as the interpolation weights take them), each of nf_d doubles, from
+  // d_csum + csum_off[3 p + d]; valid with the metric
+  double *d_csum = nullptr;
+  size_t csum_cap = 0;
+  long long *d_csoff = nullptr;
+  std::vector<long long> csum_off;
   // 1: the part's given coefficients satisfy a_s(c) = a_{-s}(c+s) to a relative
   // 1e-12 (checked by set_coeffs; finite-volume assembly is symmetric)
   std::vector<int> sym_ok;
@@ -639,8 +651,21 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
                             int &out_nrow, hipStream_t st,
                             const std::function<void()> &before_sync = {});
 void launch_entry_rows(int nrow, const int *urow, const int *uptr, int *erow, hipStream_t st);
-void launch_ublk(const SymPart *sp, int np, int lg, int64_t maxchunk, const long long *boff, int nrow,
-                 const int *urow, const int *uptr, int *out, hipStream_t st);
+// block tables of several (level, lg) pairs in one launch: the level's part
+// records start at sp + spat, its block offsets at boff + boffat; nbx: blocks
+// of kBlock chunks that cover the largest part
+struct UblkJob {
+  const int *urow, *uptr;
+  int *out;
+  int nrow, lg, spat, boffat;
+};
+constexpr int kUblkJobs = 48;
+struct UblkJobs {
+  int n;
+  UblkJob j[kUblkJobs];
+};
+void launch_ublk(const SymPart *sp, int np, const long long *boff, const UblkJobs &jobs, int64_t nbx,
+                 hipStream_t st);
 
 // kernels_dense.hip: exact solve of the hybrid tail's switch level
 int64_t dense_pad(int64_t n);            // order of the padded dense matrix
@@ -658,7 +683,8 @@ void launch_dense_apply(const double *m, int64_t n, int lg, const T *vb, T *vt, 
 
 // kernels_fv.hip
 void launch_fv_stencil(const FvArgs &fa, int maxcell, const double *kappa, const double *aniso,
-                       double *const *coef, double *mpart, hipStream_t st);
+                       double *const *coef, double *mpart, double *csum, const long long *csoff,
+                       hipStream_t st);
 void launch_fv_coupling(int nrow, const int *urow, const int *uptr, const int *ucol,
                         const int *ucode, const double *kappa, const double *aniso, double *uval,
                         hipStream_t st);
