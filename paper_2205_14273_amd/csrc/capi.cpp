@@ -176,7 +176,7 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   const char *rapmin = std::getenv("SSAMG_RAP_CELL_MIN");
   if (rapmin && rapmin[0]) s->rap_cell_min = std::max<int64_t>(0, std::atoll(rapmin));
   const char *prod2 = std::getenv("SSAMG_PRODUCT2");
-  if (prod2 && prod2[0]) s->product2 = std::atoi(prod2) != 0;
+  if (prod2 && prod2[0]) s->product2 = std::max(0, std::min(2, std::atoi(prod2)));
   const char *sweepn = std::getenv("SSAMG_SWEEPN");
   if (sweepn && sweepn[0]) s->sweepn = std::atoi(sweepn) != 0;
   const char *rsort = std::getenv("SSAMG_ROW_SORT");

@@ -1481,6 +1481,21 @@ __device__ __forceinline__ dpair ld2(const double *base, unsigned byteoff) {
   return *(dev::gptr<dpair>)((dev::gptr<char>)G(base) + byteoff);
 }
 
+__device__ __forceinline__ double ld1(const double *base, unsigned byteoff) {
+  return *(dev::gptr<double>)((dev::gptr<char>)G(base) + byteoff);
+}
+
+// a double from another lane of the wave by a whole-wave DPP shift (CTRL
+// 0x138: from lane - 1; 0x130: from lane + 1; 0 where there is none); every
+// lane of the wave must execute it
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <bool MIR>
 __global__ __launch_bounds__(kBlock) void k_product2(const PartDesc<double> *__restrict__ desc, int nb1,
                                                      const double *__restrict__ x, double *__restrict__ y,
@@ -1569,6 +1584,131 @@ __global__ __launch_bounds__(kBlock) void k_product2(const PartDesc<double> *__r
     if (ch < nb1) dslot[ch] = sh[tid * kBlock];
   }
   // the block holding the one-cell grid's last chunk clears the rounding slots
+  if ((nb1 - 1) / 2 == b2 && tid < slots - nb1) dslot[nb1 + tid] = 0.0;
+}
+
+// k_product2 with the x values at c - 1 and c + 2 of each row taken from the
+// lanes before and after (they hold them as their own pairs; a lane whose
+// neighbour in the row lies in another wave loads it): one pair load per row
+// instead of three.  Every load is issued first (the rows' own pairs, then
+// the coefficients), the few loads of the waves' edge lanes after them in one
+// branch, then the shifts and the sums in the same order as k_product2 (the
+// same bits).
+template <bool MIR>
+__global__ __launch_bounds__(kBlock) void k_product2s(const PartDesc<double> *__restrict__ desc, int nb1,
+                                                      const double *__restrict__ x, double *__restrict__ y,
+                                                      double *__restrict__ dotp) {
+  __shared__ double prod[kUChunkBig];
+  __shared__ double sh[2 * kBlock];
+  const PartDesc<double> &d = desc[blockIdx.y];
+  const int b2 = chunk_index();
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const long long c = (long long)b2 * (2 * kBlock) + 2 * tid;
+  const bool valid = c < d.ncell;
+  const int cc = valid ? (int)c : 0;
+  int i, j, k;
+  cell_ijk(cc, d.n[0], d.n[1], i, j, k);
+  const unsigned my = nb_mask(j, d.n[1]), mz = nb_mask(k, d.n[2]);
+  const bool xl = i > 0;                   // cell c has its -x neighbour
+  const bool xr = i + 2 < d.n[0];          // cell c + 1 has its +x neighbour
+  const int nx = d.n[0], nxy = d.n[0] * d.n[1];
+  const double *xb = x + d.off;
+  const unsigned c8 = 8u * (unsigned)cc;
+  bool row[9];
+  unsigned r8[9];
+  dpair xz[9];
+  double a0[27], a1[27];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int ri = (dy + 1) + 3 * (dz + 1);
+      row[ri] = ((my >> (dy + 1)) & (mz >> (dz + 1)) & 1u) != 0;
+      r8[ri] = c8 + 8u * (unsigned)(row[ri] ? dy * nx + dz * nxy : 0);
+      xz[ri] = ld2(xb, r8[ri]);
+    }
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int ri = (dy + 1) + 3 * (dz + 1);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+        const bool neg = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+        if (MIR && neg) {
+          const double *arr = d.coef + (long long)d.cube[26 - o] * d.ncell;
+          if (dx == 0) {
+            const dpair v = ld2(arr, r8[ri]);
+            a0[o] = v.x;
+            a1[o] = v.y;
+          } else {
+            const bool ok0 = row[ri] && (dx > 0 || xl), ok1 = row[ri] && (dx < 0 || xr);
+            const dpair u = ld2(arr, ok0 ? r8[ri] + 8u * (unsigned)(dx - 1) : c8);
+            const dpair w = ld2(arr, ok1 ? r8[ri] + 8u * (unsigned)(dx + 1) : c8);
+            a0[o] = u.y;
+            a1[o] = w.x;
+          }
+        } else {
+          const dpair v = ld2(d.coef + (long long)d.cube[o] * d.ncell, c8);
+          a0[o] = v.x;
+          a1[o] = v.y;
+        }
+      }
+    }
+  // x at c - 1 and c + 2 of every row: from the lanes before and after
+  double xlo[9], xhi[9];
+#pragma unroll
+  for (int ri = 0; ri < 9; ++ri) {
+    xlo[ri] = wave_shift<0x138>(xz[ri].y);
+    xhi[ri] = wave_shift<0x130>(xz[ri].x);
+  }
+  if (lane == 0 && xl) {
+#pragma unroll
+    for (int ri = 0; ri < 9; ++ri)
+      if (row[ri]) xlo[ri] = ld1(xb, r8[ri] - 8u);
+  }
+  if (lane == 63 && xr) {
+#pragma unroll
+    for (int ri = 0; ri < 9; ++ri)
+      if (row[ri]) xhi[ri] = ld1(xb, r8[ri] + 16u);
+  }
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+  for (int ri = 0; ri < 9; ++ri) {
+    const bool okm = row[ri] && xl, okp = row[ri] && xr;
+    const double xv0[3] = {okm ? xlo[ri] : 0.0, row[ri] ? xz[ri].x : 0.0, row[ri] ? xz[ri].y : 0.0};
+    const double xv1[3] = {row[ri] ? xz[ri].x : 0.0, row[ri] ? xz[ri].y : 0.0, okp ? xhi[ri] : 0.0};
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int o = (dx + 1) + 3 * ri;
+      acc0 = fma(a0[o], xv0[dx + 1], acc0);
+      acc1 = fma(a1[o], xv1[dx + 1], acc1);
+    }
+  }
+  const double xc0 = xz[4].x, xc1 = xz[4].y;
+  double u[2];
+  block_coupling_multi<2>(d, b2, xb - d.off, prod, sh, u);
+  acc0 += u[0];
+  acc1 += u[1];
+  if (valid) *(double2 *)(y + d.off + cc) = make_double2(acc0, acc1);
+  // p.q per 256-cell chunk 2 b2 and 2 b2 + 1 (the one-cell kernel's tree)
+  __syncthreads();
+  sh[2 * tid] = valid ? xc0 * acc0 : 0.0;
+  sh[2 * tid + 1] = valid ? xc1 * acc1 : 0.0;
+  const int half = tid >> 7, t = tid & 127;
+  for (int s = kBlock / 2; s >= 1; s >>= 1) {
+    __syncthreads();
+    if (t < s) sh[half * kBlock + t] += sh[half * kBlock + t + s];
+  }
+  __syncthreads();
+  const long long slots = 4LL * ((nb1 + 3) / 4);
+  double *dslot = dotp + (long long)blockIdx.y * slots;
+  if (tid < 2) {
+    const long long ch = 2LL * b2 + tid;
+    if (ch < nb1) dslot[ch] = sh[tid * kBlock];
+  }
   if ((nb1 - 1) / 2 == b2 && tid < slots - nb1) dslot[nb1 + tid] = 0.0;
 }
 
@@ -1741,12 +1881,16 @@ template void launch_sweep2<float, double>(int, const PartDesc<float> *, int, in
 template void launch_sweep2<double, double>(int, const PartDesc<double> *, int, int, const double *,
                                             const double *, double *, hipStream_t, LaunchEvents);
 
-void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, const double *x,
-                     double *y, double *dotp, hipStream_t st, LaunchEvents ev) {
+void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, bool share,
+                     const double *x, double *y, double *dotp, hipStream_t st, LaunchEvents ev) {
   const int nb1 = (int)grid_cells(maxcell, 0);
   dim3 grid((unsigned)((nb1 + 1) / 2), nparts);
-  if (mir)
+  if (mir && share)
+    dispatch(k_product2s<true>, grid, st, ev, desc, nb1, x, y, dotp);
+  else if (mir)
     dispatch(k_product2<true>, grid, st, ev, desc, nb1, x, y, dotp);
+  else if (share)
+    dispatch(k_product2s<false>, grid, st, ev, desc, nb1, x, y, dotp);
   else
     dispatch(k_product2<false>, grid, st, ev, desc, nb1, x, y, dotp);
 }

@@ -1592,7 +1592,7 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
     if (dot && lg == 0 && product2_ok(s))
-      launch_product2(V.d_desc64, np, V.maxcell, mirrored(s), x, y, s.dotp, s.stream, pr.e);
+      launch_product2(V.d_desc64, np, V.maxcell, mirrored(s), s.product2 == 2, x, y, s.dotp, s.stream, pr.e);
     else
       launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,
                                              V.maxcell, lg, x, nullptr, y, s.stream, pr.e, cols4,

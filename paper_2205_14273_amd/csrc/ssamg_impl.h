@@ -343,7 +343,9 @@ struct Solver {
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
   int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
-  int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere
+  int product2 = 2;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere;
+                                             // 1: two-cell product loading its row neighbours;
+                                             // 2: ... taking them from the adjacent lanes
   int sweepn = 1;                            // SSAMG_SWEEPN=0: the one-cell finest sweeps
   int lk = -1;                       // collapse level (-1: none)
   DevBuf host_cpl;                   // couplings and block tables of the host-formed levels
@@ -537,8 +539,8 @@ void launch_stencil(int mode, int fine, int maxent, const PartDesc<T> *desc, int
 // stencil and an even number of cells along x, two cells per thread
 // (k_product2); same partial slots as the one-column kernel.  nb1: that
 // kernel's blocks per part.
-void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, const double *x,
-                     double *y, double *dotp, hipStream_t st, LaunchEvents ev = {});
+void launch_product2(const PartDesc<double> *desc, int nparts, int maxcell, bool mir, bool share,
+                     const double *x, double *y, double *dotp, hipStream_t st, LaunchEvents ev = {});
 // The finest level's residual (MODE_RESID) or post-smoothing sweep
 // (MODE_JACOBI) for one right-hand side with b in FP64, 16 / sizeof(T) cells
 // per thread (k_sweepN): every part has the full 27-point stencil and a

@@ -295,7 +295,9 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
     per thread: the cycle matches the oracle entry by entry, the solve reaches
     the tolerance with the oracle's iterations (the true residual is formed by
     the one-cell product), and it equals the one-cell kernels' solve to
-    rounding."""
+    rounding.  The product that takes the row neighbours from the adjacent
+    lanes (SSAMG_PRODUCT2=2; the odd case's rows cross wave boundaries, so its
+    edge lanes load theirs) gives the same solve bit for bit."""
     _print_case(f"multi-cell kernels {name} precision={precision}")
     case = W.c3(10) if name == "c3_10" else _odd_chunks_case()
     h = oracle_fv(case)
@@ -303,7 +305,7 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
     b = case.b
     ref = O.solve(h, b, tol=1e-8, flexible=(precision == 1))
     out = {}
-    for v in ("1", "0"):
+    for v in ("2", "1", "0"):
         monkeypatch.setenv("SSAMG_PRODUCT2", v)
         _, s = gpu_fv(case, cycle_precision=precision)
         r = np.random.default_rng(31).uniform(-1, 1, h.levels[0].n)
@@ -314,6 +316,7 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
         out[v] = (x.cpu().numpy(), info.iters[0])
     assert out["1"][1] == out["0"][1]
     assert np.linalg.norm(out["1"][0] - out["0"][0]) <= 1e-9 * np.linalg.norm(out["0"][0])
+    assert out["2"][1] == out["1"][1] and np.array_equal(out["2"][0], out["1"][0])
 
 
 def test_calls_under_another_stream():
