@@ -241,12 +241,12 @@ def main():
         name = name.format(n=nent)
         if probe == "matvec" and nent > 7:
             name = name[:-1] + ", true>"       # mirrored reads of a symmetric stencil
-        p2 = os.environ.get("SSAMG_PRODUCT2", "2")
+        p2 = os.environ.get("SSAMG_PRODUCT2", "1")
         if (probe == "matvec" and nrhs == 1 and nent == 27 and p2 != "0"
                 and all(dd[0] % 2 == 0 for dd in g.dims)):
-            # two cells per thread (full 27-point, even rows); by default the
-            # row neighbours come from the adjacent lanes
-            name = "k_product2<true>" if p2 == "1" else "k_product2s<true>"
+            # two cells per thread (full 27-point, even rows); 2: the row
+            # neighbours come from the adjacent lanes
+            name = "k_product2s<true>" if p2 == "2" else "k_product2<true>"
         if nrhs >= 4 and not (name.startswith("k_stencil<double") and nent == 27):
             # four right-hand-side columns per thread on batched levels
             name = name.replace("k_stencil<", "k_stencil4<")

@@ -343,7 +343,7 @@ struct Solver {
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
   int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
-  int product2 = 2;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere;
+  int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere;
                                              // 1: two-cell product loading its row neighbours;
                                              // 2: ... taking them from the adjacent lanes
   int sweepn = 1;                            // SSAMG_SWEEPN=0: the one-cell finest sweeps
