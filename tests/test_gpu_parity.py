@@ -345,6 +345,35 @@ def test_host_formed_couplings_match_device(monkeypatch, name):
     assert all(torch.equal(out[0], o) for o in out[1:])
 
 
+@pytest.mark.parametrize("row_sort", [None, "0"])
+def test_repeated_device_setups_are_identical(monkeypatch, row_sort):
+    """The device coupling product keeps two count buffers at zero between
+    calls (each call leaves them so; they are cleared only when allocated):
+    three setups of one solver, every level on the device, give the same
+    couplings on every level and the same solve bit for bit, with rows
+    ranked in LDS or from memory."""
+    _print_case(f"repeated device setups row_sort={row_sort}")
+    monkeypatch.setenv("SSAMG_HOST_SYM", "0")
+    if row_sort is None:
+        monkeypatch.delenv("SSAMG_ROW_SORT", raising=False)
+    else:
+        monkeypatch.setenv("SSAMG_ROW_SORT", row_sort)
+    case = W.c3(8)
+    _, s = gpu_fv(case)
+    b = _cuda(case.b)
+    ref_c = [s.copy_coupling(l) for l in range(s.nlevels)]
+    ref_x, st, _ = s.solve(b)
+    assert st == 0
+    for _ in range(2):
+        s.setup()
+        for l in range(s.nlevels):
+            got = s.copy_coupling(l)
+            for a, e in zip(got, ref_c[l]):
+                assert np.array_equal(a, e), l
+        x, st, _ = s.solve(b)
+        assert st == 0 and torch.equal(x, ref_x)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_split_down_sweep_matches_fused(monkeypatch, precision):
     """On large 27-point levels the first sweep and the residual run as two
