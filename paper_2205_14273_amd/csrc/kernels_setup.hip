@@ -751,15 +751,23 @@ __global__ __launch_bounds__(kBlock) void k_uc_numeric(long long nnz, const int 
 // of A = S + U; the smoother factor of cell i is factor / M_ii.
 // desc32 (finest level of a mixed-precision cycle, else null): the pass also
 // writes the FP32 copy of the coefficients it reads.
-__global__ __launch_bounds__(kBlock) void k_l1_cells(const PartDesc<double> *__restrict__ desc,
-                                                     const PartDesc<float> *__restrict__ desc32,
-                                                     double *__restrict__ l1) {
+// The weighted L1-Jacobi factor of a part's cells in one pass, on levels
+// whose stencil sums no Galerkin kernel has formed (small levels: one launch
+// instead of three): the stencil sum in entry order (with the FP32 copy when
+// desc32 is given) plus the sum of |u| over the cell's coupling row in entry
+// order (found among the stored rows of its 256-cell block), then factor /
+// sum.  On large levels the per-cell searches cost more than the launches
+// they save, so there the rows add their sums in a row-parallel pass.
+__global__ __launch_bounds__(kBlock) void k_l1_fused(const PartDesc<double> *__restrict__ desc,
+                                                     const PartDesc<float> *__restrict__ desc32, double factor,
+                                                     double *__restrict__ rs, float *__restrict__ rs32,
+                                                     int *__restrict__ flag) {
   const PartDesc<double> &d = desc[blockIdx.y];
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.ncell) return;
   const auto cf = dev::G(d.coef);
   const auto c32 = desc32 ? dev::Gw(const_cast<float *>(desc32[blockIdx.y].coef)) : nullptr;
-  double cv[kMaxEnt];   // all loads first, as in k_interp_weights
+  double cv[kMaxEnt];
 #pragma unroll
   for (int s = 0; s < kMaxEnt; ++s) cv[s] = cf[(long long)(s < d.nent ? s : 0) * d.ncell + c];
   double acc = 0.0;
@@ -769,7 +777,29 @@ __global__ __launch_bounds__(kBlock) void k_l1_cells(const PartDesc<double> *__r
     acc += fabs(cv[s]);
     if (desc32) c32[(long long)s * d.ncell + c] = (float)cv[s];
   }
-  l1[d.off + c] = acc;
+  if (d.urow) {
+    // the block's stored rows are ascending: binary search for the cell's
+    const auto ub = dev::G(d.ublk[0]) + 2 * (c / kBlock);
+    int lo = ub[0], hi = ub[2];
+    const int cell = (int)(d.off + c);
+    const auto urow = dev::G(d.urow);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (urow[mid] < cell)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < ub[2] && urow[lo] == cell) {
+      double us = 0.0;
+      for (int q = dev::G(d.uptr)[lo]; q < dev::G(d.uptr)[lo + 1]; ++q) us += fabs(dev::G(d.uval)[q]);
+      acc += us;
+    }
+  }
+  const double v = factor / acc;
+  if (!(acc > 0.0) || !isfinite(v)) flag[0] = 1;
+  rs[d.off + c] = v;
+  if (rs32) rs32[d.off + c] = (float)v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_l1_urows(int nrow, const int *__restrict__ urow,
@@ -844,8 +874,10 @@ void launch_smoother_scale(bool l1, const PartDesc<double> *desc, int nparts, in
                            int nrow, const int *urow, const int *uptr, const double *uval,
                            double factor, double *rs, float *rs32, int *flag, hipStream_t st,
                            const PartDesc<float> *cast32, bool stencil_sums_done) {
-  if (l1) {
-    if (!stencil_sums_done) k_l1_cells<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, cast32, rs);
+  if (l1 && !stencil_sums_done) {
+    k_l1_fused<<<dim3(nblk(maxcell), nparts), kBlock, 0, st>>>(desc, cast32, factor, rs, rs32, flag);
+  } else if (l1) {
+    // the per-cell Galerkin kernel has written the stencil sums into rs
     if (nrow > 0) k_l1_urows<<<nblk(nrow), kBlock, 0, st>>>(nrow, urow, uptr, uval, rs);
     k_l1_finish<<<nblk(n), kBlock, 0, st>>>(n, factor, rs, rs32, flag);
   } else {
