@@ -1591,7 +1591,9 @@ void apply_A0(Solver &s, int lg, const double *x, double *y, int dot_slot = -1) 
   if (dot && !s.dotp) throw Error(SSAMG_ERR_STATE, "internal: fused product dot needs a batch of 4+");
   {
     Probe pr(s, SSAMG_PROBE_MATVEC, level0_bytes(s, SSAMG_PROBE_MATVEC, lg, 8, 8, 8, 8));
-    if (dot && lg == 0 && product2_ok(s))
+    // the two-cell product always forms its p.q partials; without a dot they
+    // go to the partial buffer unread (the true residual's product)
+    if (lg == 0 && product2_ok(s) && s.dotp)
       launch_product2(V.d_desc64, np, V.maxcell, mirrored(s), s.product2 == 2, x, y, s.dotp, s.stream, pr.e);
     else
       launch_stencil<double, double, double>(dot ? MODE_APPLY_DOT : MODE_APPLY, 1, V.maxent, V.d_desc64, np,

@@ -294,7 +294,7 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
     thread and, in the FP64 cycle, the finest residual and post-sweep two cells
     per thread: the cycle matches the oracle entry by entry, the solve reaches
     the tolerance with the oracle's iterations (the true residual is formed by
-    the one-cell product), and it equals the one-cell kernels' solve to
+    the same product), and it equals the one-cell kernels' solve to
     rounding.  The product that takes the row neighbours from the adjacent
     lanes (SSAMG_PRODUCT2=2; the odd case's rows cross wave boundaries, so its
     edge lanes load theirs) gives the same solve bit for bit."""
