@@ -156,10 +156,15 @@ __global__ __launch_bounds__(kFinalThreads) void k_dot_final(const double *__res
 // the partial sums of r.r; alpha is kept in S_ALPHA for the x update, which
 // waits for the next p update (k_pcg_xp) or the end of the solve (k_pcg_x), so
 // that p is read once per iteration
+// TX (one column only): also the finest level's first sweep from zero of the
+// next cycle, x0 = w r with the level's smoother factors w (k_smooth_zero's
+// arithmetic), so that the cycle need not read r again for it
+template <typename TX>
 __global__ __launch_bounds__(kBlock) void k_pcg_r(long long nel, int lg, double *__restrict__ scal,
                                                   const int *__restrict__ active, double *__restrict__ r,
                                                   const double *__restrict__ q,
-                                                  double *__restrict__ partial) {
+                                                  double *__restrict__ partial, const TX *__restrict__ w,
+                                                  TX *__restrict__ x0) {
   __shared__ double sh[kBlock];
   const int nr = 1 << lg;
   const int kr = threadIdx.x & (nr - 1);
@@ -175,6 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_r(long long nel, int lg, double 
       r[i] = ri;
     }
     acc = fma(ri, ri, acc);
+    if (x0) x0[i] = w[i] * (TX)ri;
   }
   sh[threadIdx.x] = acc;
   block_tree(sh, nr);
@@ -325,9 +331,12 @@ void launch_dot2(const double *a, const double *b, const double *c, int64_t nel,
 }
 
 void launch_pcg_r(int64_t nel, int lg, double *scal, const int *active, double *r, const double *q,
-                  double *partial, hipStream_t st) {
+                  double *partial, hipStream_t st, const float *w32, float *x32, const double *w64, double *x64) {
   const unsigned nb = red_blocks(nel);
-  k_pcg_r<<<nb, kBlock, 0, st>>>(nel, lg, scal, active, r, q, partial);
+  if (x64)
+    k_pcg_r<double><<<nb, kBlock, 0, st>>>(nel, lg, scal, active, r, q, partial, w64, x64);
+  else
+    k_pcg_r<float><<<nb, kBlock, 0, st>>>(nel, lg, scal, active, r, q, partial, w32, x32);
   k_dot_final<<<1, kFinalThreads, 0, st>>>(partial, (int)nb, lg, scal, S_RR, 0, S_RR);
 }
 

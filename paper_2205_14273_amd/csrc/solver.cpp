@@ -1370,15 +1370,19 @@ bool product2_ok(const Solver &s, int cpt = 2) {
   return true;
 }
 
+bool first_sweep_split(const Solver &s, const Level &V, int lg, const TuneRec &o) {
+  return o.split >= 0 ? o.split == 1
+                      : (lg >= 2 ? (V.N << lg) >= s.split_cells : (V.maxent > 15 && V.N >= s.split_cells));
+}
+
+// x_ready: x = w b is already formed (by the residual update of PCG)
 template <typename T, typename TB>
 void down_sweep(Solver &s, const Level &V, const PartDesc<T> *d, int fine, int lg, const TB *b, T *x, T *t,
-                const TuneRec &o, LaunchEvents ev = {}) {
+                const TuneRec &o, LaunchEvents ev = {}, bool x_ready = false) {
   const int np = (int)V.parts.size();
-  const bool split = o.split >= 0 ? o.split == 1
-                                  : (lg >= 2 ? (V.N << lg) >= s.split_cells
-                                             : (V.maxent > 15 && V.N >= s.split_cells));
+  const bool split = first_sweep_split(s, V, lg, o);
   if (split) {
-    launch_smooth_zero<T, TB>(fine, d, np, V.maxcell, lg, b, x, s.stream);
+    if (!x_ready) launch_smooth_zero<T, TB>(fine, d, np, V.maxcell, lg, b, x, s.stream);
     if constexpr (std::is_same<TB, double>::value) {
       if (sizeof(T) == 8 && fine && lg == 0 && s.sweepn && product2_ok(s, 16 / sizeof(T))) {
         launch_sweep2<T, T>(MODE_RESID, d, np, V.maxcell, x, b, t, s.stream, ev);
@@ -1543,7 +1547,9 @@ void precond_t(Solver &s, int lg, bool dots) {
   const TuneRec o = tune_rec(s, 0, lg);
   {
     Probe pr(s, SSAMG_PROBE_RESID0, level0_bytes(s, SSAMG_PROBE_RESID0, lg, tc, tx, 8, tx));
-    down_sweep<T, double>(s, V, d, 1, lg, s.r, x, t, o, pr.e);
+    const bool ready = s.x0_ready && lg == 0 && first_sweep_split(s, V, lg, o);
+    s.x0_ready = false;
+    down_sweep<T, double>(s, V, d, 1, lg, s.r, x, t, o, pr.e, ready);
   }
   {
     Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
@@ -1825,6 +1831,7 @@ void probe_read(Solver &s, int64_t *launches, double *ms, double *bytes) {
 
 void apply_precond(Solver &s, const double *r, double *z) {
   const int64_t N = s.lv[0].N;
+  s.x0_ready = false;
   launch_copy(r, s.r, N, s.stream);
   precond(s, 0);
   launch_copy(s.z, z, N, s.stream);
@@ -1846,6 +1853,13 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   std::vector<int> act(kMaxRhs, 0), iters(nrhs, 0), conv(nrhs, 0);
   std::vector<double> bb(nrhs), relres(nrhs, 0.0);
 
+  s.x0_ready = false;
+  // one column with a split finest down-sweep: the residual update also forms
+  // that sweep's x = w r for the next cycle
+  const Level &V0 = s.lv[0];
+  const bool fuse0 = s.pcg_fuse && lg == 0 && s.lv.size() > 1 && V0.d_rs64 &&
+                     first_sweep_split(s, V0, 0, tune_rec(s, 0, 0)) &&
+                     (s.prm.cycle_precision == SSAMG_FP32 ? V0.d_rs32 != nullptr : true);
   launch_fill(x, 0.0, nel, st);
   launch_copy(b, s.r, nel, st);
   launch_dot(b, b, nel, lg, s.partial, s.scal, S_BB, 0, st);
@@ -1887,7 +1901,14 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   std::vector<double> rel1(nrhs, 1.0), rel2(nrhs, 1.0);   // x0 = 0: the initial relative residual is 1
   for (int it = 1; it <= s.prm.max_iter && nact > 0; ++it) {
     apply_A0(s, lg, s.p, s.q, S_PQ);        // p.q formed by the product itself
-    launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st);
+    if (fuse0 && s.prm.cycle_precision == SSAMG_FP32)
+      launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st, V0.d_rs32, (float *)V0.vx);
+    else if (fuse0)
+      launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st, nullptr, nullptr, V0.d_rs64,
+                   (double *)V0.vx);
+    else
+      launch_pcg_r(nel, lg, s.scal, s.active, s.r, s.q, s.partial, st);
+    s.x0_ready = fuse0;
     pending_x = true;
     SSAMG_HIP(hipMemcpyAsync(h, s.scal, kScalSlots * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost, st));
     SSAMG_HIP(hipEventRecord(s.ev_scal, st));
@@ -1929,6 +1950,7 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
     if (nact == 0 || it == s.prm.max_iter) break;
     if (!spec) next_direction();
   }
+  s.x0_ready = false;
   if (pending_x) launch_pcg_x(nel, lg, s.scal, s.p, x, st);
   // true residual
   apply_A0(s, lg, x, s.q);

@@ -343,6 +343,8 @@ struct Solver {
   int64_t host_sym = kHostSymRecords; // SSAMG_HOST_SYM overrides (0: device only)
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
   int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
+  bool x0_ready = false;                     // the finest level's x = w r is formed (next cycle skips it)
+  bool pcg_fuse = true;                      // SSAMG_PCG_FUSE=0: the residual update does not form it
   int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere;
                                              // 1: two-cell product loading its row neighbours;
                                              // 2: ... taking them from the adjacent lanes
@@ -603,8 +605,11 @@ void launch_dot(const double *a, const double *b, int64_t nel, int lg, double *p
 // partial holds 2 * kRedBlocks * kMaxRhs doubles
 void launch_dot2(const double *a, const double *b, const double *c, int64_t nel, int lg, double *partial,
                  double *scal, int slot_ab, int shift_rz, int slot_bc, hipStream_t st);
+// x32 / x64 (one column): also x0 = w r, the finest level's first sweep from
+// zero of the next cycle, with the level's smoother factors w32 / w64
 void launch_pcg_r(int64_t nel, int lg, double *scal, const int *active, double *r, const double *q,
-                  double *partial, hipStream_t st);
+                  double *partial, hipStream_t st, const float *w32 = nullptr, float *x32 = nullptr,
+                  const double *w64 = nullptr, double *x64 = nullptr);
 void launch_pcg_xp(int64_t nel, int lg, const double *scal, const int *active, int flexible,
                    const double *z, double *p, double *x, hipStream_t st);
 void launch_pcg_x(int64_t nel, int lg, const double *scal, const double *p, double *x, hipStream_t st);

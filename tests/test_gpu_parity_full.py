@@ -319,6 +319,32 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
     assert out["2"][1] == out["1"][1] and np.array_equal(out["2"][0], out["1"][0])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_residual_update_forms_first_sweep(monkeypatch, precision):
+    """One-column solves whose finest down-sweep is split let PCG's residual
+    update also form that sweep's x = w r (SSAMG_PCG_FUSE, on by default): the
+    solve equals the one with the separate sweep bit for bit, and the oracle's
+    iterations.  SSAMG_SPLIT_CELLS=0 splits every level, so the small case
+    takes that path."""
+    _print_case(f"fused first sweep precision={precision}")
+    case = W.c3(10)
+    h = oracle_fv(case)
+    ref = O.solve(h, case.b, tol=1e-8, flexible=(precision == 1))
+    monkeypatch.setenv("SSAMG_SPLIT_CELLS", "0")
+    out = {}
+    for v in ("1", "0"):
+        monkeypatch.setenv("SSAMG_PCG_FUSE", v)
+        _, s = gpu_fv(case, cycle_precision=precision)
+        x, st, info = s.solve(_cuda(case.b))
+        assert st == 0 and info.true_relres[0] < 1e-8 and abs(info.iters[0] - ref.iters) <= 1
+        out[v] = (x, info.iters[0])
+        # a preconditioner application right after a solve starts from zero
+        r = _cuda(np.random.default_rng(4).uniform(-1, 1, h.levels[0].n))
+        out[v + "z"] = s.apply_precond(r)
+    assert out["1"][1] == out["0"][1] and torch.equal(out["1"][0], out["0"][0])
+    assert torch.equal(out["1z"], out["0z"])
+
+
 def test_calls_under_another_stream():
     """A solver orders its work on the stream current at its creation; inputs
     made under another stream (the assembled coefficients, b) are waited for
