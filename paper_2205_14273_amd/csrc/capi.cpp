@@ -179,8 +179,8 @@ ssamg_status ssamg_solver_create(ssamg_problem prob, const ssamg_params *params,
   if (prod2 && prod2[0]) s->product2 = std::max(0, std::min(2, std::atoi(prod2)));
   const char *sweepn = std::getenv("SSAMG_SWEEPN");
   if (sweepn && sweepn[0]) s->sweepn = std::atoi(sweepn) != 0;
-  const char *fuse = std::getenv("SSAMG_PCG_FUSE");
-  if (fuse && fuse[0]) s->pcg_fuse = std::atoi(fuse) != 0;
+  const char *fuse = std::getenv("SSAMG_FUSE_ZERO");
+  if (fuse && fuse[0]) s->fuse_zero = std::atoi(fuse) != 0;
   const char *rsort = std::getenv("SSAMG_ROW_SORT");
   if (rsort && rsort[0]) s->scratch.row_sort = std::max<int64_t>(0, std::atoll(rsort));
   const char *hsym = std::getenv("SSAMG_HOST_SYM");

@@ -341,10 +341,13 @@ __device__ __forceinline__ T upre_apply(const PartDesc<T> &d, int lg, const UPre
 // b_c = P^T r for coarse cell cc: r(2I) + wp(2I-1) r(2I-1) + wm(2I+1) r(2I+1)
 template <typename T>
 __device__ __forceinline__ void restrict_one(const PartDesc<T> &d, int cc, int kr, int lg,
-                                             const T *__restrict__ r, T *__restrict__ bc) {
+                                             const T *__restrict__ r, T *__restrict__ bc,
+                                             const T *__restrict__ wn = nullptr, T *__restrict__ xn = nullptr) {
   const long long oc = ((d.coff + cc) << lg) + kr;
   if (d.dstar < 0) {
-    bc[oc] = r[((d.off + cc) << lg) + kr];
+    const T v = r[((d.off + cc) << lg) + kr];
+    bc[oc] = v;
+    if (xn) xn[oc] = wn[d.coff + cc] * v;
     return;
   }
   int ci[3];
@@ -368,6 +371,8 @@ __device__ __forceinline__ void restrict_one(const PartDesc<T> &d, int cc, int k
     v = fma(G(d.wm)[fl], rp[(long long)stride << lg], v);
   }
   bc[oc] = v;
+  // the next level's first sweep from zero, x = w b (k_smooth_zero's arithmetic)
+  if (xn) xn[oc] = wn[d.coff + cc] * v;
 }
 
 // x(c) += (P x_c)(c): even cells along d* take their coarse value, odd cells
@@ -946,13 +951,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_mixed(const PartDesc<double> 
   x[o] = (float)(smooth_factor(d, c) * (double)b[o]);
 }
 
+// wn, xn: also the next level's first sweep from zero, xn = wn b_c (wn: that
+// level's smoother factors)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const PartDesc<T> *__restrict__ desc, int lg,
-                                                     const T *__restrict__ r, T *__restrict__ bc) {
+                                                     const T *__restrict__ r, T *__restrict__ bc,
+                                                     const T *__restrict__ wn, T *__restrict__ xn) {
   const PartDesc<T> &d = desc[blockIdx.y];
   const long long e = (long long)chunk_index() * kBlock + threadIdx.x;
   if (e >= (d.cncell << lg)) return;
-  restrict_one(d, (int)(e >> lg), (int)(e & ((1 << lg) - 1)), lg, r, bc);
+  restrict_one(d, (int)(e >> lg), (int)(e & ((1 << lg) - 1)), lg, r, bc, wn, xn);
 }
 
 template <typename T>
@@ -1935,11 +1943,13 @@ void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxce
 
 template <typename T>
 void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
-                     hipStream_t st, LaunchEvents ev) {
-  if (lg >= 2)
+                     hipStream_t st, LaunchEvents ev, const T *wn, T *xn) {
+  if (lg >= 2) {
+    if (xn) throw Error(SSAMG_ERR_STATE, "internal: the four-column restriction forms no first sweep");
     dispatch(k_restrict4<T>, dim3(grid_cells(maxcoarse, lg - 2), nparts), st, ev, desc, lg, r, bc);
-  else
-    dispatch(k_restrict<T>, dim3(grid_cells(maxcoarse, lg), nparts), st, ev, desc, lg, r, bc);
+  } else {
+    dispatch(k_restrict<T>, dim3(grid_cells(maxcoarse, lg), nparts), st, ev, desc, lg, r, bc, wn, xn);
+  }
 }
 
 template <typename T>
@@ -2010,9 +2020,9 @@ template void launch_smooth_zero<float, float>(int, const PartDesc<float> *, int
 template void launch_smooth_zero<float, double>(int, const PartDesc<float> *, int, int, int,
                                                 const double *, float *, hipStream_t);
 template void launch_restrict<double>(const PartDesc<double> *, int, int, int, const double *, double *,
-                                      hipStream_t, LaunchEvents);
+                                      hipStream_t, LaunchEvents, const double *, double *);
 template void launch_restrict<float>(const PartDesc<float> *, int, int, int, const float *, float *,
-                                     hipStream_t, LaunchEvents);
+                                     hipStream_t, LaunchEvents, const float *, float *);
 template void launch_interp_add<double>(const PartDesc<double> *, int, int, int, const double *, double *,
                                         hipStream_t, LaunchEvents);
 template void launch_interp_add<float>(const PartDesc<float> *, int, int, int, const float *, float *,

@@ -1448,6 +1448,31 @@ int tail_start(const Solver &s, int lg) {
   return L - 1;
 }
 
+// first level handled by the coarse end (or a grid collapse); levels 1 .. end-1
+// are grid levels.  With a collapse level above the coarse end's first level
+// (wide batches), the grid levels stop there and its operator is applied as a
+// grid kernel.
+int grid_end(const Solver &s, int lg) {
+  const int lt0 = tail_start(s, lg);
+  return s.lk >= 1 && s.lk < lt0 ? s.lk : lt0;
+}
+
+// whether grid level l >= 1 takes its first sweep from zero from the
+// restriction that forms its right-hand side (split down-sweep, one or two
+// columns)
+bool zero_in_restrict(const Solver &s, int l, int lg) {
+  return s.fuse_zero && lg < 2 && l >= 1 && l < grid_end(s, lg) &&
+         first_sweep_split(s, s.lv[l], lg, tune_rec(s, l, lg));
+}
+
+template <typename T>
+const T *level_rs(const Level &V) {
+  if constexpr (sizeof(T) == 4)
+    return (const T *)V.d_rs32;
+  else
+    return (const T *)V.d_rs64;
+}
+
 // Levels l >= 1 of one V(1,1) cycle: from lv[1].vb into lv[1].vt (all in T,
 // the coarsest level in FP64).  Captured in a HIP graph when use_graph is set.
 template <typename T>
@@ -1455,17 +1480,18 @@ void run_tail(Solver &s, int lg) {
   hipStream_t st = s.stream;
   const int L = (int)s.lv.size();
   const int np = (int)s.lv[0].parts.size();
-  // with a collapse level above the coarse end's first level (wide batches),
-  // the grid levels stop there and its operator is applied as a grid kernel
   const int lt0 = tail_start(s, lg);
   const bool grid_collapse = s.lk >= 1 && s.lk < lt0;
-  const int lt = grid_collapse ? s.lk : lt0;
+  const int lt = grid_end(s, lg);
   for (int l = 1; l < lt; ++l) {
     Level &V = s.lv[l];
     const PartDesc<T> *d = desc_of<T>(V);
     T *b = (T *)V.vb, *x = (T *)V.vx, *t = (T *)V.vt;
-    down_sweep<T, T>(s, V, d, 0, lg, b, x, t, tune_rec(s, l, lg));
-    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[l + 1].vb, st);
+    down_sweep<T, T>(s, V, d, 0, lg, b, x, t, tune_rec(s, l, lg), {}, zero_in_restrict(s, l, lg));
+    Level &C = s.lv[l + 1];
+    const bool zn = zero_in_restrict(s, l + 1, lg);
+    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)C.vb, st, {}, zn ? level_rs<T>(C) : nullptr,
+                       zn ? (T *)C.vx : nullptr);
   }
   TailPlan pl;
   if (s.d_hyb)   // hybrid tail: the exact solve of the switch level, FP64 inverse
@@ -1553,7 +1579,10 @@ void precond_t(Solver &s, int lg, bool dots) {
   }
   {
     Probe pr(s, SSAMG_PROBE_RESTRICT0, level0_bytes(s, SSAMG_PROBE_RESTRICT0, lg, tc, tx, tx, tx));
-    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)s.lv[1].vb, st, pr.e);
+    Level &C = s.lv[1];
+    const bool zn = zero_in_restrict(s, 1, lg);
+    launch_restrict<T>(d, np, V.maxcoarse, lg, t, (T *)C.vb, st, pr.e, zn ? level_rs<T>(C) : nullptr,
+                       zn ? (T *)C.vx : nullptr);
   }
   tail<T>(s, lg);
   {
@@ -1857,7 +1886,7 @@ ssamg_status pcg_solve(Solver &s, int nrhs, const double *b, double *x, ssamg_in
   // one column with a split finest down-sweep: the residual update also forms
   // that sweep's x = w r for the next cycle
   const Level &V0 = s.lv[0];
-  const bool fuse0 = s.pcg_fuse && lg == 0 && s.lv.size() > 1 && V0.d_rs64 &&
+  const bool fuse0 = s.fuse_zero && lg == 0 && s.lv.size() > 1 && V0.d_rs64 &&
                      first_sweep_split(s, V0, 0, tune_rec(s, 0, 0)) &&
                      (s.prm.cycle_precision == SSAMG_FP32 ? V0.d_rs32 != nullptr : true);
   launch_fill(x, 0.0, nel, st);

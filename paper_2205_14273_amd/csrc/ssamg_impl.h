@@ -344,7 +344,8 @@ struct Solver {
   int64_t collapse_cells = kCollapseCells;   // SSAMG_COLLAPSE_CELLS overrides (0: off)
   int64_t rap_cell_min = kRapCellMin;        // SSAMG_RAP_CELL_MIN overrides (0: per-cell kernel always)
   bool x0_ready = false;                     // the finest level's x = w r is formed (next cycle skips it)
-  bool pcg_fuse = true;                      // SSAMG_PCG_FUSE=0: the residual update does not form it
+  bool fuse_zero = true;                     // SSAMG_FUSE_ZERO=0: first sweeps from zero run on their own
+                                             // (not formed by PCG's residual update or the restriction)
   int product2 = 1;                          // SSAMG_PRODUCT2=0: the one-cell product and sweeps everywhere;
                                              // 1: two-cell product loading its row neighbours;
                                              // 2: ... taking them from the adjacent lanes
@@ -586,8 +587,10 @@ template <typename T, typename TB>
 void launch_smooth_zero(int fine, const PartDesc<T> *desc, int nparts, int maxcell, int lg, const TB *b,
                         T *x, hipStream_t st);
 template <typename T>
+// wn, xn (one or two columns): also the next level's first sweep from zero,
+// xn = wn b_c, with that level's smoother factors wn (level vector)
 void launch_restrict(const PartDesc<T> *desc, int nparts, int maxcoarse, int lg, const T *r, T *bc,
-                     hipStream_t st, LaunchEvents ev = {});
+                     hipStream_t st, LaunchEvents ev = {}, const T *wn = nullptr, T *xn = nullptr);
 template <typename T>
 void launch_interp_add(const PartDesc<T> *desc, int nparts, int maxcell, int lg, const T *xc, T *x,
                        hipStream_t st, LaunchEvents ev = {});

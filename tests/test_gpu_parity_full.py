@@ -321,11 +321,12 @@ def test_multi_cell_product_and_sweeps(monkeypatch, precision, name):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_residual_update_forms_first_sweep(monkeypatch, precision):
-    """One-column solves whose finest down-sweep is split let PCG's residual
-    update also form that sweep's x = w r (SSAMG_PCG_FUSE, on by default): the
-    solve equals the one with the separate sweep bit for bit, and the oracle's
-    iterations.  SSAMG_SPLIT_CELLS=0 splits every level, so the small case
-    takes that path."""
+    """One-column solves whose down-sweeps are split let PCG's residual update
+    form the finest level's first sweep from zero, x = w r, and each
+    restriction form the next grid level's, x = w b (SSAMG_FUSE_ZERO, on by
+    default): the solve equals the one with the separate sweeps bit for bit,
+    and the oracle's iterations.  SSAMG_SPLIT_CELLS=0 splits every level, so
+    the small case takes those paths."""
     _print_case(f"fused first sweep precision={precision}")
     case = W.c3(10)
     h = oracle_fv(case)
@@ -333,7 +334,7 @@ def test_residual_update_forms_first_sweep(monkeypatch, precision):
     monkeypatch.setenv("SSAMG_SPLIT_CELLS", "0")
     out = {}
     for v in ("1", "0"):
-        monkeypatch.setenv("SSAMG_PCG_FUSE", v)
+        monkeypatch.setenv("SSAMG_FUSE_ZERO", v)
         _, s = gpu_fv(case, cycle_precision=precision)
         x, st, info = s.solve(_cuda(case.b))
         assert st == 0 and info.true_relres[0] < 1e-8 and abs(info.iters[0] - ref.iters) <= 1
