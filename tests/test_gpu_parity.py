@@ -345,6 +345,31 @@ def test_host_formed_couplings_match_device(monkeypatch, name):
     assert all(torch.equal(out[0], o) for o in out[1:])
 
 
+def test_update_after_assembly_uses_the_new_values():
+    """After ssamg_update_coeffs on an assembled problem, the assembly's
+    direction-metric partials and collapse sums no longer describe the
+    coefficients: the new setup forms them from the coefficients and matches
+    the oracle on the updated operator (part 0's stencil doubled, which keeps
+    it symmetric and diagonally dominant)."""
+    _print_case("update after assembly")
+    case = W.c3(8)
+    g = case.geometry
+    _, s = gpu_fv(case)
+    new0 = s.copy_stencil(0, 0) * 2.0
+    s.update_coeffs(0, new0)
+    s.setup()
+    A, _ = assemble.assemble_fv(g, case.stencil, case.kappa, case.aniso)
+    A = A.tocoo()
+    n0 = int(np.prod(g.dims[0]))
+    inside = (A.row < n0) & (A.col < n0)
+    data = np.where(inside, 2.0 * A.data, A.data)
+    A2 = type(A)((data, (A.row, A.col)), shape=A.shape).tocsr()
+    pat = [W.stencil_offsets(case.stencil, g.ndim)] * g.nparts
+    h = O.setup(A2, g.dims, g.face_kinds(), pat, g.ndim, omega=case.omega, max_levels=64, min_coarse_size=0,
+                relax=case.relax, coarse="sweep", skip=False, pb="one", hybrid_level=0, coarse_op="galerkin")
+    compare_hierarchy(h, s, g.nparts)
+
+
 @pytest.mark.parametrize("row_sort", [None, "0"])
 def test_repeated_device_setups_are_identical(monkeypatch, row_sort):
     """The device coupling product keeps two count buffers at zero between
