@@ -495,22 +495,23 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   w.ra.reserve(n * 4);
   w.rb.reserve(n * 4);
   w.ent.reserve(n * 4);
-  w.small.reserve(64);
   w.roff.reserve((size_t)(nc + 1) * 4);
   w.rscan.reserve((size_t)(nc + 1) * 8);
   w.temp.reserve((size_t)((nc + 1 + kScanItems - 1) / kScanItems + 1) * 8);
   zero_reserve(w.rcnt, (size_t)(nc + 1) * 4, w.rcnt_zero, w.rcnt_zcap, st);
   zero_reserve(w.rinfo, (size_t)(nc + 1) * 8, w.rinfo_zero, w.rinfo_zcap, st);
   if (!w.host_small) {
-    void *h = nullptr;
-    SSAMG_HIP(hipHostMalloc(&h, 64));
+    // coherent pinned memory the scan kernel writes the sizes into
+    void *h = nullptr, *dv = nullptr;
+    SSAMG_HIP(hipHostMalloc(&h, 64, hipHostMallocCoherent | hipHostMallocMapped));
     w.host_small = (int *)h;
+    SSAMG_HIP(hipHostGetDevicePointer(&dv, h, 0));
+    w.dev_small = (int *)dv;
   }
   auto *k0 = (unsigned long long *)w.key0.p, *k1 = (unsigned long long *)w.key1.p;
   auto *i0 = (unsigned *)w.idx0.p, *i1 = (unsigned *)w.idx1.p;
   int *rk = (int *)w.rk.p, *ra = (int *)w.ra.p, *rb = (int *)w.rb.p;
   int *ent = (int *)w.ent.p;
-  int *small = (int *)w.small.p;
   int *rcnt = (int *)w.rcnt.p, *roff = (int *)w.roff.p;
   long long *rinfo = (long long *)w.rinfo.p, *rscan = (long long *)w.rscan.p;
   // a device error leaves the zero-kept buffers unknown
@@ -533,8 +534,8 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
                                                             ent, rinfo);
   std::swap(k0, k1);
   std::swap(i0, i1);
-  device_scan<long long, false>(rinfo, rscan, nc + 1, w.temp, st, roff + nc, small);
-  SSAMG_HIP(hipMemcpyAsync(w.host_small, small, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+  // the sizes go straight to the host's pinned buffer (read after the sync)
+  device_scan<long long, false>(rinfo, rscan, nc + 1, w.temp, st, roff + nc, w.dev_small);
   if (before_sync) before_sync();   // host work that overlaps the device's
   SSAMG_HIP(hipStreamSynchronize(st));
   const int nvalid = w.host_small[0], nent = w.host_small[1], nr = w.host_small[2];

@@ -280,8 +280,9 @@ struct LevelStore {
 
 // Scratch of the device sort.
 struct SymScratch {
-  DevBuf key0, key1, idx0, idx1, rk, ra, rb, ent, small, temp, rcnt, roff, rinfo, rscan;
-  int *host_small = nullptr;         // pinned
+  DevBuf key0, key1, idx0, idx1, rk, ra, rb, ent, temp, rcnt, roff, rinfo, rscan;
+  int *host_small = nullptr;         // pinned, coherent: the three sizes of the last call
+  int *dev_small = nullptr;          // its device address
   int64_t row_sort = kRowSortRecords; // rows of at most this many records are ranked in LDS
   // rcnt and rinfo are all zero between calls (each call leaves them so); the
   // allocation (pointer, capacity) that was last cleared, null when unknown
