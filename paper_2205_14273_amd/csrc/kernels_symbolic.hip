@@ -81,16 +81,15 @@ __device__ __forceinline__ void wave_groups(int r, F &&f) {
 }
 
 // one thread per entry q of U_l (row cell erow[q]); its records sit at
-// 4q .. 4q+3.  The valid records are counted into their coarse rows' buckets
+// 4q .. 4q+3 (a record's index is its position).  The valid records are counted into their coarse rows' buckets
 // (cnt, zero on entry), a wave's records with the same row with one atomic.
 __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp, int np, long long nnz,
                                                  const int *__restrict__ erow,
                                                  const int *__restrict__ ucol,
                                                  unsigned long long nc, unsigned long long invalid,
                                                  unsigned long long *__restrict__ key,
-                                                 unsigned *__restrict__ idx, int *__restrict__ rk,
-                                                 int *__restrict__ ra, int *__restrict__ rb,
-                                                 int *__restrict__ cnt) {
+                                                 int *__restrict__ rk, int *__restrict__ ra,
+                                                 int *__restrict__ rb, int *__restrict__ cnt) {
   const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   int cf[2] = {-1, -1}, sf[2], cg[2], sg[2];
@@ -102,15 +101,13 @@ __global__ __launch_bounds__(kBlock) void k_emit(const SymPart *__restrict__ sp,
     for (int t = 0; t < 4; ++t) {
       const long long i = 4LL * q + t;
       const int a = t >> 1, b = t & 1;
-      idx[i] = (unsigned)i;
       if (a < nf && b < ng) {
         key[i] = (unsigned long long)cf[a] * nc + (unsigned long long)cg[b];
         rk[i] = (int)q;
         ra[i] = sf[a];
         rb[i] = sg[b];
       } else {
-        key[i] = invalid;
-        rk[i] = ra[i] = rb[i] = 0;
+        key[i] = invalid;   // never ranked or read again
       }
     }
   }
@@ -144,8 +141,7 @@ __device__ __forceinline__ int rec_row(const unsigned long long *__restrict__ ke
 
 // cnt holds the row counts on entry and zeros on exit; a group takes
 // consecutive slots of its row's range
-__global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long *__restrict__ key,
-                                                        const unsigned *__restrict__ idx, long long n,
+__global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long *__restrict__ key, long long n,
                                                         unsigned long long nc, unsigned long long invalid,
                                                         const int *__restrict__ roff, int *__restrict__ cnt,
                                                         unsigned long long *__restrict__ tk,
@@ -164,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_row_scatter(const unsigned long long
   if (r < 0) return;
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
   tk[pos] = key[i];
-  ti[pos] = idx[i];
+  ti[pos] = (unsigned)i;
 }
 
 // coarse entries (column, row), rows (cell, first entry) and the
@@ -525,10 +521,10 @@ void coarse_coupling_device(SymScratch &w, const SymPart *sp, int np, int64_t nn
   // records and row counts (rcnt) -> row offsets -> row buckets in k1/i1
   // (rcnt back to zero) -> ranked inside each row into k0/i0 with entry
   // numbers and row counts (rinfo) -> row scan and the sizes
-  k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, i0,
-                                       rk, ra, rb, rcnt);
+  k_emit<<<nblk(nnz), kBlock, 0, st>>>(sp, np, nnz, erow, ucol, (unsigned long long)nc, invalid, k0, rk, ra,
+                                       rb, rcnt);
   device_scan<int, false>(rcnt, roff, nc + 1, w.temp, st);
-  k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, i0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
+  k_row_scatter<<<nblk(n), kBlock, 0, st>>>(k0, n, (unsigned long long)nc, invalid, roff, rcnt, k1, i1);
   k_row_rank_lds<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(k1, i1, n, (unsigned long long)nc, invalid, roff,
                                                             (int)std::min<int64_t>(w.row_sort, kRankCap), k0, i0,
                                                             ent, rinfo);
