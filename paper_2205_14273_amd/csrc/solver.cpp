@@ -473,7 +473,6 @@ void host_coarse_coupling(const SymPart *sp, int np, const std::vector<int> &ero
   ra.reserve(4 * nnz);
   rb.reserve(4 * nnz);
   const uint64_t ncu = (uint64_t)nc;
-  uint64_t kmax = 0;
   for (size_t q = 0; q < nnz; ++q) {
     int cf[2], sf[2], cg[2], sg[2];
     const int nf = host_prow(sp, np, erow[q], cf, sf);
@@ -482,7 +481,6 @@ void host_coarse_coupling(const SymPart *sp, int np, const std::vector<int> &ero
       const int a = t >> 1, b = t & 1;
       if (a < nf && b < ng) {
         const uint64_t k = (uint64_t)cf[a] * ncu + (uint64_t)cg[b];
-        kmax = std::max(kmax, k);
         idx.push_back((uint32_t)rk.size());
         key.push_back(k);
         rk.push_back((int)q);
@@ -493,20 +491,34 @@ void host_coarse_coupling(const SymPart *sp, int np, const std::vector<int> &ero
   }
   const size_t nvalid = key.size();
   if (nvalid == 0) return;
-  // stable LSD radix sort of (key, idx), eight bits a pass
-  key2.resize(nvalid);
-  idx2.resize(nvalid);
-  int bits = 1;
-  while (bits < 64 && (kmax >> bits) != 0) ++bits;
-  for (int shift = 0; shift < bits; shift += 8) {
-    size_t cnt[257] = {0};
-    for (size_t i = 0; i < nvalid; ++i) ++cnt[((key[i] >> shift) & 255) + 1];
-    for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
+  // key order, ties in emission order (a stable sort), as the device forms
+  // it: count the records of every coarse row, place them row by row in
+  // emission order, then order each row by key with a stable insertion sort
+  // (rows hold few records)
+  {
+    std::vector<int> rpos((size_t)nc + 1, 0);
+    for (size_t i = 0; i < nvalid; ++i) ++rpos[(size_t)(key[i] / ncu) + 1];
+    for (int64_t r = 0; r < nc; ++r) rpos[r + 1] += rpos[r];
+    key2.resize(nvalid);
+    idx2.resize(nvalid);
+    std::vector<int> fillp(rpos.begin(), rpos.end() - 1);
     for (size_t i = 0; i < nvalid; ++i) {
-      const size_t at = cnt[(key[i] >> shift) & 255]++;
+      const size_t at = (size_t)fillp[(size_t)(key[i] / ncu)]++;
       key2[at] = key[i];
       idx2[at] = idx[i];
     }
+    for (int64_t r = 0; r < nc; ++r)
+      for (int64_t j = rpos[r] + 1; j < rpos[r + 1]; ++j) {
+        const uint64_t k = key2[j];
+        const uint32_t v = idx2[j];
+        int64_t m = j - 1;
+        for (; m >= rpos[r] && key2[m] > k; --m) {
+          key2[m + 1] = key2[m];
+          idx2[m + 1] = idx2[m];
+        }
+        key2[m + 1] = k;
+        idx2[m + 1] = v;
+      }
     key.swap(key2);
     idx.swap(idx2);
   }
