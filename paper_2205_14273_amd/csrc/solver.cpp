@@ -391,6 +391,7 @@ Solver::~Solver() {
   if (graph) (void)hipGraphDestroy(graph);
   if (ws_owned && ws) (void)hipFree(ws);
   if (h_pin) (void)hipHostFree(h_pin);
+  if (h_tab) (void)hipHostFree(h_tab);
   for (auto e : pev) (void)hipEventDestroy(e);
   if (ev_scal) (void)hipEventDestroy(ev_scal);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -1120,12 +1121,27 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   const int L = (int)s.lv.size();
   const bool mixed = s.prm.cycle_precision == SSAMG_FP32;
   // every host-built table goes up in one copy
-  std::vector<char> stage(cv.tab_end - cv.tab_begin);
+  // staged in pinned memory, so that the copy runs asynchronously; a copy of
+  // an earlier call that did not end normally is waited for first
+  const size_t tab_bytes = cv.tab_end - cv.tab_begin;
+  if (s.h_tab_busy) {
+    SSAMG_HIP(hipStreamSynchronize(st));
+    s.h_tab_busy = false;
+  }
+  if (s.h_tab_cap < tab_bytes) {
+    if (s.h_tab) (void)hipHostFree(s.h_tab);
+    s.h_tab = nullptr;
+    s.h_tab_cap = 0;
+    SSAMG_HIP(hipHostMalloc(&s.h_tab, tab_bytes + 4096));
+    s.h_tab_cap = tab_bytes + 4096;
+  }
+  char *stage = (char *)s.h_tab;
+  std::memset(stage, 0, tab_bytes);
   auto put = [&](const void *dst, const void *src, size_t nbytes) {
     if (!nbytes) return;
     const size_t at = (size_t)((const char *)dst - cv.base) - cv.tab_begin;
-    if (at + nbytes > stage.size()) throw Error(SSAMG_ERR_STATE, "internal: table outside its segment");
-    std::memcpy(stage.data() + at, src, nbytes);
+    if (at + nbytes > tab_bytes) throw Error(SSAMG_ERR_STATE, "internal: table outside its segment");
+    std::memcpy(stage + at, src, nbytes);
   };
   auto putv = [&](const void *dst, const auto &v) { put(dst, v.data(), v.size() * sizeof(v[0])); };
   for (int l = 0; l < L; ++l) {
@@ -1219,8 +1235,10 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
         rec((double *)nullptr);
     }
   }
-  if (!stage.empty())
-    SSAMG_HIP(hipMemcpyAsync(cv.base + cv.tab_begin, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
+  if (tab_bytes) {
+    s.h_tab_busy = true;
+    SSAMG_HIP(hipMemcpyAsync(cv.base + cv.tab_begin, stage, tab_bytes, hipMemcpyHostToDevice, st));
+  }
   SSAMG_HIP(hipMemsetAsync(s.flag, 0, sizeof(int), st));
   const auto t1 = std::chrono::steady_clock::now();
   // finest-level FP32 copies; coarser ones are written by the kernels below
@@ -1304,10 +1322,11 @@ void setup_numeric(Solver &s, void *ws, size_t bytes) {
   int hflag = 0;
   SSAMG_HIP(hipMemcpyAsync(&hflag, s.flag, sizeof(int), hipMemcpyDeviceToHost, st));
   SSAMG_HIP(hipStreamSynchronize(st));
+  s.h_tab_busy = false;
   const auto t2 = std::chrono::steady_clock::now();
   if (s.verbose)
     fprintf(stderr, "[ssamg] numeric setup: tables %.3f ms (%zu bytes), kernels %.3f ms\n",
-            std::chrono::duration<double, std::milli>(t1 - t0).count(), stage.size(),
+            std::chrono::duration<double, std::milli>(t1 - t0).count(), tab_bytes,
             std::chrono::duration<double, std::milli>(t2 - t1).count());
   if (hflag == 2) throw Error(SSAMG_ERR_NUMERIC, "coarsest operator is not positive definite (direct solve)");
   if (hflag) throw Error(SSAMG_ERR_NUMERIC, "non-finite interpolation weight");

@@ -376,6 +376,11 @@ struct Solver {
   int *active = nullptr;             // [kMaxRhs]
   int *flag = nullptr;               // device error flag
   double *h_pin = nullptr;           // pinned host mirror of a few scalar slots
+  // pinned staging of the numeric setup's host-built tables (one asynchronous
+  // copy); busy while a copy from it may still be in flight
+  void *h_tab = nullptr;
+  size_t h_tab_cap = 0;
+  bool h_tab_busy = false;
   // hybrid tail (hybrid_level > 0): dense inverse of the coarsest level, padded
   // to a multiple of 64 (row-major, symmetric), and its scratch
   double *d_hyb = nullptr, *d_hyb_pt = nullptr, *d_hyb_dinv = nullptr, *d_hyb_part = nullptr;
